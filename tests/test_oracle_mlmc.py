@@ -1,0 +1,140 @@
+"""Pins of the oracle's QoI samples and the MLMC / CGV estimators.
+
+* Two-layer piecewise constant model with a horizontal interface: the layers
+  are parallel to the flow, so every sample has the closed form
+  Q = f k_0 + (1 - f) k_1, f = (rows below the interface)/m.
+* Its moments follow from that closed form: E[Q] = E[k] = e^(1/2),
+  V[Q] = E[f^2 + (1-f)^2] V[k], V[Y] = E[(f_m - f_(m/2))^2] 2 V[k], with
+  V[k] = (e - 1) e and the f-moments integrated exactly over y0 ~ U(0.3, 0.7).
+  Sampled moments must fall within 5 standard errors.
+* Coarse Grid Variates on a field that is constant along x1 rows: the 2^d
+  sub-lattice QoIs average to the fine QoI exactly (Section 4.1).
+* CGV unbiasedness (Section 4.1: each sub-lattice is a valid coarse sample of
+  a stationary field): mean of the CGV coarse QoI vs independently sampled
+  coarse QoIs, two-sample test.
+* Estimator arithmetic eq. (3.6)/(3.7) against numpy mean/var.
+"""
+import numpy as np
+
+import workloads as W
+from oracle import field, geometry, mlmc
+
+VK = (np.e - 1.0) * np.e
+
+
+def _f_moments(m_f, m_c=None, lo=0.3, hi=0.7):
+    """Exact E[f^2 + (1-f)^2] (and E[(f_f - f_c)^2]) over y0 ~ U(lo, hi)."""
+    def f(m, y0):
+        return np.ceil(m * y0 - 0.5) / m
+    mm = [m_f] + ([m_c] if m_c else [])
+    pts = {lo, hi}
+    for m in mm:
+        for j in range(m + 1):
+            y = (j + 0.5) / m
+            if lo < y < hi:
+                pts.add(y)
+    pts = sorted(pts)
+    e1 = e2 = 0.0
+    for a, b in zip(pts[:-1], pts[1:]):
+        y = 0.5 * (a + b)
+        w = (b - a) / (hi - lo)
+        ff = f(m_f, y)
+        e1 += w * (ff ** 2 + (1 - ff) ** 2)
+        if m_c:
+            e2 += w * (ff - f(m_c, y)) ** 2
+    return e1, e2
+
+
+def test_piecewise_constant_closed_form_per_sample():
+    model = W.PC2
+    for m in (16, 32):
+        for s in range(12):
+            k = field.sample_k(model, 0, s, m)
+            qf, qi = mlmc.solve_qoi(k)
+            lid = geometry.layer_ids(model, 0, s, m)
+            f = np.sum(lid[:, 0] == 0) / m
+            kl = np.exp(field.layer_constants(model, 0, s))
+            ref = f * kl[0] + (1 - f) * kl[1]
+            assert abs(qf - ref) < 1e-12 * ref
+            assert abs(qi - ref) < 1e-12 * ref
+
+
+def test_analytic_moments_known_values():
+    e16, _ = _f_moments(16)
+    e32, ey = _f_moments(32, 16)
+    assert abs(e16 * VK - 2.464244) < 2e-6
+    assert abs(e32 * VK - 2.459968) < 2e-6
+    assert abs(ey * 2 * VK - 4.27622e-3) < 2e-8
+
+
+def test_sampled_moments_match_analytic():
+    model = W.PC2
+    N = 20000
+    for level, m in ((0, 16), (1, 32)):
+        Q, Y = np.empty(N), np.empty(N)
+        for s in range(N):
+            z = field.layer_constants(model, level, s)
+            y0 = geometry.interface_params(model, level, s)["y0"]
+            kl = np.exp(z)
+            ff = np.ceil(m * y0 - 0.5) / m
+            fc = np.ceil(m // 2 * y0 - 0.5) / (m // 2)
+            Q[s] = ff * kl[0] + (1 - ff) * kl[1]
+            Y[s] = (ff - fc) * (kl[0] - kl[1])
+        e1, e2 = _f_moments(m, m // 2)
+        se_mean = np.sqrt(Q.var() / N)
+        assert abs(Q.mean() - np.exp(0.5)) < 5 * se_mean
+        vq = e1 * VK
+        # variance of the sample variance of a heavy-tailed variable: use the 4th moment
+        se_var = np.sqrt((np.mean((Q - Q.mean()) ** 4) - Q.var() ** 2) / N)
+        assert abs(Q.var() - vq) < 5 * se_var
+        vy = e2 * 2 * VK
+        se_vy = np.sqrt((np.mean(Y ** 4) - np.mean(Y ** 2) ** 2) / N)
+        assert abs(np.mean(Y ** 2) - vy) < 5 * se_vy
+
+
+def test_level_sample_plain_matches_closed_form_difference():
+    model = W.PC2
+    for s in range(5):
+        r = mlmc.level_sample(model, 1, s, 32)
+        y0 = geometry.interface_params(model, 1, s)["y0"]
+        kl = np.exp(field.layer_constants(model, 1, s))
+        ff = np.ceil(32 * y0 - 0.5) / 32
+        fc = np.ceil(16 * y0 - 0.5) / 16
+        assert abs(r["Y"] - (ff - fc) * (kl[0] - kl[1])) < 1e-12 * abs(r["Q_f"])
+
+
+def test_cgv_row_constant_field_is_exact():
+    rng = np.random.default_rng(7)
+    m = 16
+    k = np.repeat(np.exp(rng.standard_normal(m))[:, None], m, axis=1)
+    qf, _ = mlmc.solve_qoi(k)
+    qc = np.mean([mlmc.solve_qoi(kc)[0] for kc in field.cgv_sublattices(k)])
+    assert abs(qf - qc) < 1e-12 * qf
+    r = mlmc.level_sample(W.PC2, 1, 0, 32, cgv=True)
+    assert abs(r["Y"]) < 1e-12 * r["Q_f"]
+
+
+def test_cgv_coarse_mean_is_unbiased():
+    model = W.STATIONARY_1NORM
+    N = 300
+    qcgv = np.array([mlmc.level_sample(model, 1, s, 8, cgv=True)["Q_c"] for s in range(N)])
+    qind = np.array([mlmc.solve_qoi(field.sample_k(model, 0, s, 4))[0] for s in range(N)])
+    diff = qcgv.mean() - qind.mean()
+    se = np.sqrt(qcgv.var() / N + qind.var() / N)
+    assert abs(diff) < 4 * se
+    # and averaging over the four sub-lattices lowers the variance of Y
+    yc = np.array([mlmc.level_sample(model, 1, s, 8, cgv=True)["Y"] for s in range(100)])
+    yp = np.array([mlmc.level_sample(model, 1, s, 8, cgv=False)["Y"] for s in range(100)])
+    assert yc.var() < yp.var()
+
+
+def test_estimator_arithmetic():
+    rng = np.random.default_rng(8)
+    ys = [rng.standard_normal(n) + mu for n, mu in ((50, 1.0), (20, 0.1), (10, 0.01))]
+    sums = [mlmc.level_sums(y, y, np.zeros_like(y)) for y in ys]
+    est = mlmc.estimate(sums)
+    assert abs(est["estimate"] - sum(y.mean() for y in ys)) < 1e-13
+    v = sum(y.var(ddof=1) / y.size for y in ys)
+    assert abs(est["variance_of_estimate"] - v) < 1e-13
+    for lv, y in zip(est["levels"], ys):
+        assert abs(lv["var_y"] - y.var(ddof=1)) < 1e-12

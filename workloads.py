@@ -1,0 +1,85 @@
+"""Seeded synthetic workloads shared by the tests, the oracle checks and the bench.
+
+This module holds only parameter records: which random layer model, which
+grids, how many samples and which seed.  It contains none of the method's
+arithmetic; the oracle and the GPU library each turn these parameters into
+samples with their own code.
+
+Model records follow the layered permeability models of Section 2
+(Example 1: piecewise constant log-normal; Example 2: piecewise log-normal
+field with the exponential covariance eq. (2.3)) and the random layer
+shapes of Section 3.4.
+"""
+from dataclasses import dataclass, field, replace
+from typing import List, Tuple
+
+# interface_kind
+HORIZONTAL = 0        # one horizontal interface at height y0 ~ U(y_lo, y_hi)
+PIECEWISE_LINEAR = 1  # n_nodes equispaced nodes (x_q = q/(n-1)), heights ~ U(y_lo, y_hi)
+PAPER_TWO_LINES = 2   # Section 3.4: lines (0,y1)-(1,y2) and (0,y3)-(1,y4), three layers
+NO_INTERFACE = 4      # a single layer (stationary field, Section 4.2)
+
+# field_kind
+PIECEWISE_CONSTANT = 0  # Example 1
+CORRELATED_CE = 1       # Example 2, sampled by circulant embedding
+
+
+@dataclass
+class Model:
+    dim: int = 2
+    interface_kind: int = HORIZONTAL
+    n_nodes: int = 2
+    n_layers: int = 2
+    field_kind: int = PIECEWISE_CONSTANT
+    norm_r: int = 2
+    y_lo: float = 0.3
+    y_hi: float = 0.7
+    mu: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0)
+    sigma2: Tuple[float, ...] = (1.0, 1.0, 1.0, 1.0)
+    lam: Tuple[float, ...] = (0.3, 0.3, 0.3, 0.3)
+    seed: int = 0
+    # circulant-embedding length per direction, one per MLMC grid size m
+    n_ce: dict = field(default_factory=dict)
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+@dataclass
+class Workload:
+    name: str
+    model: Model
+    m_levels: List[int]
+    n_samples: List[int]
+    cgv: bool = False
+
+
+# Two-layer piecewise constant model on 16^2 and 32^2 grids, 200 samples each.
+PC2 = Model(interface_kind=HORIZONTAL, n_layers=2, field_kind=PIECEWISE_CONSTANT,
+            mu=(0.0, 0.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0), seed=0)
+SMALL_PC = Workload("2d-pc-2layer-16-32", PC2, [16, 32], [200, 200])
+
+# Two-layer log-normal correlated model: 8-node piecewise-linear interface,
+# exponential covariance (2-norm), sigma^2 = 1, lambda = 0.3, means 0 (bottom), 2 (top).
+CE2 = Model(interface_kind=PIECEWISE_LINEAR, n_nodes=8, n_layers=2,
+            field_kind=CORRELATED_CE, norm_r=2, mu=(0.0, 2.0, 0.0, 0.0),
+            sigma2=(1.0, 1.0, 1.0, 1.0), lam=(0.3, 0.3, 0.3, 0.3), seed=0,
+            n_ce={16: 32, 32: 72, 64: 135, 128: 375, 256: 960, 512: 1875})
+LAYERED_CE = Workload("2d-ce-8node-64-512", CE2, [64, 128, 256, 512], [4096, 1024, 256, 64])
+
+# The same piecewise constant model on 64^2..512^2 with Coarse Grid Variates.
+CGV_PC = Workload("2d-pc-cgv-64-512", PC2, [64, 128, 256, 512], [4096, 1024, 256, 64], cgv=True)
+
+# High-contrast correlated model on a 1024^2 grid.
+CE_HC = Model(interface_kind=PIECEWISE_LINEAR, n_nodes=8, n_layers=2,
+              field_kind=CORRELATED_CE, norm_r=2, mu=(-2.0, 2.0, 0.0, 0.0),
+              sigma2=(3.0, 3.0, 3.0, 3.0), lam=(0.1, 0.1, 0.1, 0.1), seed=0,
+              n_ce={512: 1024, 1024: 2048})
+HIGH_CONTRAST = Workload("2d-ce-hc-1024", CE_HC, [1024], [256])
+
+# Continuous stationary log-normal field (no layers), 1-norm covariance,
+# lambda = 0.3, sigma^2 = 1, as in the CGV experiment of Section 4.2.
+STATIONARY_1NORM = Model(interface_kind=NO_INTERFACE, n_layers=1, field_kind=CORRELATED_CE,
+                         norm_r=1, mu=(0.0, 0.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0),
+                         lam=(0.3, 0.3, 0.3, 0.3), seed=0,
+                         n_ce={4: 8, 8: 16, 16: 32, 32: 64, 64: 128, 128: 256, 256: 512})
