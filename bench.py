@@ -1,0 +1,160 @@
+#!/usr/bin/env python
+"""Throughput of the MLMC hot path on one MI355X.
+
+One step = one pass of the whole path over the layered correlated workload:
+for each level l (grids 64^2, 128^2, 256^2, 512^2 with 4096/1024/256/64
+samples) sample k by circulant embedding, assemble the finite volume system,
+solve it by multigrid-preconditioned CG to relative residual 1e-13, take the
+outflow QoI, do the same for the plain coarse companion (levels >= 1), and
+reduce Y = Q_f - Q_c into the level sums.  Every step draws fresh samples.
+
+Prints one JSON line: value = Y-samples per second over all levels (the
+per-level rates are in "per_level"), a roofline entry for the dominant
+kernel timed live with HIP events, and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "MLMC samples solved/s per level at 1e-10 QoI rel-err; HBM GB/s; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+DOMINANT = "rbgs_l0"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--kernel", default=DOMINANT, help="kernel label timed for the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, budget_s):
+    """The oracle (as it is) on the first samples of each level, one thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    from oracle import field as ofield
+    from oracle import mlmc as omlmc
+    per_level = []
+    spent = 0.0
+    share = budget_s / len(wl.m_levels)
+    for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+        lam = ofield.ce_eigenvalues(wl.model.n_ce[m], m, wl.model.sigma2[0], wl.model.lam[0],
+                                    wl.model.norm_r)
+        done, t0 = 0, time.perf_counter()
+        while True:
+            omlmc.level_sample(wl.model, level, done, m, cgv=wl.cgv, lam_eig=lam)
+            done += 1
+            el = time.perf_counter() - t0
+            if el >= share or done >= n:
+                break
+        spent += el
+        per_level.append({"m": m, "samples": done, "s_per_sample": el / done})
+    total_s = sum(p["s_per_sample"] * n for p, n in zip(per_level, wl.n_samples))
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": sum(wl.n_samples) / total_s, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": "first %s samples of levels %s (of %s), Y-samples incl. coarse companion, "
+                      "1 thread, %.1f s of CPU work; rate extrapolated to the full level sizes"
+                      % ("/".join(str(p["samples"]) for p in per_level),
+                         "/".join("%d^2" % m for m in wl.m_levels),
+                         "/".join(str(n) for n in wl.n_samples), spent),
+            "per_level_s_per_sample": [p["s_per_sample"] for p in per_level]}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the sample-parallel path on a single "
+              "MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        return 2
+    import torch
+
+    import paper_1506_04694_amd as lib
+
+    wl = W.LAYERED_CE
+    dev = 0
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = lib.mlmc_ctx_create(dev, stream)
+    opts = lib.mlmc_solver_opts_default()
+    nlev = len(wl.m_levels)
+    level_times = [[] for _ in range(nlev)]
+    iters = [[] for _ in range(nlev)]
+
+    def step(idx, record):
+        sums = []
+        for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+            t0 = time.perf_counter()
+            s = lib.mlmc_level_run(ctx, wl.model, level, m, idx * n, n, wl.cgv, opts)
+            dt = time.perf_counter() - t0
+            if record:
+                level_times[level].append(dt)
+                iters[level].append((s.iters_fine / n, s.iters_coarse / max(n, 1)))
+            sums.append(s)
+        return sums
+
+    for w in range(args.warmup):
+        step(w, False)
+    torch.cuda.synchronize()
+    lib.mlmc_profile_enable(ctx, args.kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sums = step(args.warmup + k, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = lib.mlmc_profile_read(ctx)
+    lib.mlmc_profile_enable(ctx, None)
+    est = lib.mlmc_estimate(sums)
+    lib.mlmc_ctx_destroy(ctx)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    total = sum(wl.n_samples)
+    per_level = []
+    for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+        t = sorted(level_times[level])[len(level_times[level]) // 2]
+        per_level.append({"level": level, "m": m, "samples": n, "ms": 1e3 * t,
+                          "samples_per_s": n / t,
+                          "mean_iters_fine": sum(a for a, _ in iters[level]) / len(iters[level]),
+                          "mean_iters_coarse": sum(b for _, b in iters[level]) / len(iters[level])})
+    roof = None
+    if prof["launches"] > 0 and prof["total_ms"] > 0:
+        avg_ms = prof["total_ms"] / prof["launches"]
+        achieved = prof["algorithmic_bytes"] / (prof["total_ms"] * 1e-3) / 1e9
+        roof = {"kernel": args.kernel, "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "launches": prof["launches"], "avg_launch_ms": avg_ms,
+                "algorithmic_bytes_per_launch": prof["algorithmic_bytes"] / prof["launches"]}
+    out = {"metric": METRIC, "value": total / (elapsed / args.steps), "unit": "samples/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": wl.name, "levels_m": wl.m_levels, "samples": wl.n_samples,
+                      "estimator": "cgv" if wl.cgv else "plain", "tol_relres": opts.tol,
+                      "n_ce": [wl.model.n_ce[m] for m in wl.m_levels],
+                      "model": "2 layers, 8-node interface, exp. covariance r=2, sigma2=1, "
+                               "lambda=0.3, means 0/2"},
+           "per_level": per_level, "estimate": est, "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

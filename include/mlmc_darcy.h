@@ -1,0 +1,251 @@
+/*
+ * mlmc_darcy.h -- C ABI of the MI355X (gfx950) library for multilevel Monte
+ * Carlo estimation of Darcy flow in randomly layered media.
+ *
+ * Method: Park & Teckentrup, "Improved Multilevel Monte Carlo Methods for
+ * Finite Volume Discretisations of Darcy Flow in Randomly Layered Media"
+ * (arXiv 1506.04694).  For each sample omega the library
+ *   1. samples the layered permeability k(x, omega) at the cell centres
+ *      (Section 2, Examples 1 and 2, eq. (2.3); layer shapes of Section 3.4;
+ *      circulant embedding of Section 3.4),
+ *   2. assembles the cell-centred finite volume system eq. (3.3) with
+ *      harmonic-mean faces (Sections 3.1 and 3.4) for Model Problem 2,
+ *      eq. (3.11),
+ *   3. solves it with a multigrid-preconditioned conjugate gradient method
+ *      stopped on ||r_m|| / ||r_0|| (Section 3.5),
+ *   4. evaluates the outflow M^(2) through x1 = 1 (Section 3.4), and
+ *   5. reduces the samples into the MLMC estimator eq. (3.6)/(3.7) or the
+ *      Coarse Grid Variates estimator eq. (4.1)/(4.2) (Section 4.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Grids are uniform m^d boxes on (0,1)^d, h = 1/m; cell (i, j) has centre
+ *   ((i + 1/2) h, (j + 1/2) h); i runs along x1 (the flow direction).
+ *   A per-sample field is stored row-major [j][i] (x1 fastest), and batches
+ *   are sample-major: element (s, j, i) sits at s*m*m + j*m + i.
+ * - Only d = 2 is implemented; other values return MLMC_EINVAL.
+ * - Every pointer argument named as "device" is device memory owned by the
+ *   caller, sized as documented, on the context's device.  Input and output
+ *   buffers must not overlap.  Host pointers are marked "host".
+ * - Calls enqueue work on the context's stream and return without waiting,
+ *   except where documented (mlmc_ce_min_embedding, mlmc_solve's convergence
+ *   polling, mlmc_level_run).  Device errors may surface at a later call.
+ * - No call throws; every call returns an mlmc_status and, on failure,
+ *   leaves a message for mlmc_last_error.
+ * - Sample s of a batch is Monte Carlo sample number first_sample + s.  Its
+ *   random numbers are a pure function of (seed, level, sample number), so
+ *   results do not depend on how samples are batched.
+ */
+#ifndef MLMC_DARCY_H
+#define MLMC_DARCY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mlmc_status {
+  MLMC_OK = 0,
+  MLMC_EINVAL = 1,   /* invalid argument or unsupported configuration        */
+  MLMC_ENOMEM = 2,   /* device allocation failed                              */
+  MLMC_EDEVICE = 3,  /* HIP runtime error                                     */
+  MLMC_EBUSY = 4,    /* resource limit reached; retry later                   */
+  MLMC_ENOCONV = 5,  /* at least one sample did not converge (mlmc_level_run) */
+  MLMC_EEMBED = 6    /* circulant embedding has negative eigenvalues          */
+} mlmc_status;
+
+/* Per-sample solver outcome written to the status[] array of mlmc_solve. */
+enum {
+  MLMC_SAMPLE_OK = 0,        /* relative residual below tol                    */
+  MLMC_SAMPLE_NOCONV = 1,    /* maxit iterations without reaching tol          */
+  MLMC_SAMPLE_BREAKDOWN = 2  /* non-finite value or non-positive p^T A p       */
+};
+
+/* Layer geometry (Section 2: random partition independent of k; Section 3.4). */
+enum {
+  MLMC_IFACE_HORIZONTAL = 0,       /* x2 = y0, y0 ~ U(y_lo, y_hi); 2 layers            */
+  MLMC_IFACE_PIECEWISE_LINEAR = 1, /* n_nodes equispaced nodes x = q/(n_nodes-1),
+                                      heights ~ U(y_lo, y_hi); 2 layers               */
+  MLMC_IFACE_PAPER_TWO_LINES = 2,  /* Section 3.4: lines (0,y1)-(1,y2), (0,y3)-(1,y4),
+                                      y1~U(.8,.9) y2~U(.6,.7) y3~U(.2,.3) y4~U(.4,.5);
+                                      3 layers                                        */
+  MLMC_IFACE_NONE = 4              /* one layer (stationary field)                    */
+};
+
+/* Per-layer law (Section 2). */
+enum {
+  MLMC_FIELD_PIECEWISE_CONSTANT = 0, /* Example 1: k_l = exp(mu_l + sqrt(sigma2_l) z_l) */
+  MLMC_FIELD_CORRELATED = 1          /* Example 2: k = exp(mu_l + g_l(x)), g_l Gaussian
+                                        with covariance eq. (2.3), sampled by circulant
+                                        embedding; all layers share sigma2, lambda, r;
+                                        at most 2 layers                               */
+};
+
+/*
+ * Random layered permeability model.  Layer 0 is the bottom layer; a cell
+ * centre exactly on an interface belongs to the upper layer.
+ * Random streams (Philox4x32-10, key = seed, counter = (block, sample number,
+ * level, tag)): tag 0 geometry uniforms (uniform q = word q%4 of block q/4),
+ * tag 1 layer constants (normals z0..z3 of block 0 by Box-Muller), tag 2
+ * circulant-embedding noise (noise point q = k2*n_ce + k1 takes (z0, z1) of
+ * block q/2 for even q and (z2, z3) for odd q; real part -> layer 0, imaginary
+ * part -> layer 1).
+ */
+typedef struct mlmc_model {
+  int32_t dim;            /* 2                                                  */
+  int32_t interface_kind; /* MLMC_IFACE_*                                       */
+  int32_t n_nodes;        /* nodes of a piecewise-linear interface (2..8)       */
+  int32_t n_layers;       /* layers actually used (1..3)                        */
+  int32_t field_kind;     /* MLMC_FIELD_*                                       */
+  int32_t norm_r;         /* 1 or 2: the l_r norm of eq. (2.3)                  */
+  int32_t n_ce;           /* circulant-embedding points per direction for the grid
+                             being sampled (>= 2m, factors 2, 3, 5 only, <= 4096) */
+  int32_t reserved;
+  double y_lo, y_hi;      /* range of interface heights                         */
+  double mu[4];           /* layer means of log k                               */
+  double sigma2[4];       /* layer variances of log k                           */
+  double lambda[4];       /* correlation lengths (correlated layers)            */
+  uint64_t seed;
+} mlmc_model;
+
+/* Multigrid-preconditioned CG options (Section 3.5 uses ||r_m||/||r_0|| < 1e-10). */
+typedef struct mlmc_solver_opts {
+  double tol;           /* relative residual tolerance in the 2-norm; x0 = 0        */
+  double omega;         /* scaling of the coarse-grid correction (default 2)        */
+  int32_t maxit;        /* iteration cap (default 200)                              */
+  int32_t nu1, nu2;     /* red-black Gauss-Seidel sweeps before / after (default 1) */
+  int32_t coarse_max;   /* coarsen while the grid is even and larger than this
+                           (default 4); the coarsest grid (<= 8 x 8) is solved by
+                           dense Cholesky                                           */
+  int32_t check_every;  /* iterations between host checks of the active count      */
+  int32_t reserved;
+} mlmc_solver_opts;
+
+/* Per-level sums of the estimator (host struct; accumulates across calls). */
+typedef struct mlmc_level_sums {
+  int64_t n;            /* samples added                                            */
+  int64_t n_failed;     /* samples whose fine or coarse solve did not reach tol     */
+  double sum_y;         /* sum of Y = Q_f - Q_c  (Q_c = 0 on level 0)               */
+  double sum_y2;        /* sum of Y^2                                               */
+  double sum_qf;        /* sum of Q_f                                               */
+  double sum_qc;        /* sum of Q_c                                               */
+  int64_t iters_fine;   /* total CG iterations of the fine solves                   */
+  int64_t iters_coarse; /* total CG iterations of the coarse solves                 */
+} mlmc_level_sums;
+
+typedef struct mlmc_estimate_t {
+  double estimate;            /* eq. (3.6): sum over levels of mean Y               */
+  double variance;            /* statistical part of eq. (3.7): sum V_l / N_l        */
+  double std_error;           /* sqrt(variance)                                     */
+} mlmc_estimate_t;
+
+typedef struct mlmc_ctx mlmc_ctx;
+
+/* Create a context on `device`.  `hip_stream` (a hipStream_t, may be NULL for
+ * the default stream) is the stream every call enqueues on.  The context owns
+ * its workspaces (embedding eigenvalues, multigrid hierarchies, scratch
+ * vectors) until mlmc_ctx_destroy.  A context is not thread-safe. */
+mlmc_status mlmc_ctx_create(int device, void* hip_stream, mlmc_ctx** out);
+mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx);
+mlmc_status mlmc_ctx_set_stream(mlmc_ctx* ctx, void* hip_stream);
+/* Message of the last failed call on ctx (never NULL; "" when none). */
+const char* mlmc_last_error(const mlmc_ctx* ctx);
+
+/* Fill `opts` with the defaults: tol 1e-13, omega 2, maxit 200, nu1 = nu2 = 1,
+ * coarse_max 4, check_every 4. */
+mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* opts);
+
+/* Circulant embedding (Section 3.4, exact sampling of eq. (2.3) on a grid):
+ * smallest n_ce >= 2m with prime factors in {2,3,5} whose embedding
+ * eigenvalues satisfy min >= -1e-12 max.  Synchronises the stream.
+ * n_ce_out: host. */
+mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m, int* n_ce_out);
+
+/* Sample k at the cell centres of an m x m grid for samples first_sample ..
+ * first_sample + batch - 1 of `level` (Section 2, Examples 1-2, Section 3.4).
+ *   k        device, [batch][m][m], written.
+ *   k_coarse device, [batch][m/2][m/2] or NULL.  When given (m even), also
+ *            writes the plain MLMC coarse sample of the same omega (eq. (3.6)):
+ *            layers re-evaluated at the coarse centres; piecewise constant
+ *            layers keep their value; correlated layers take the Gaussian
+ *            value of fine cell (2I, 2J).
+ * Correlated fields need model->n_ce valid for m (else MLMC_EEMBED); the
+ * embedding eigenvalues are computed once per (m, n_ce, sigma2, lambda, r)
+ * and cached in the context. */
+mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
+                              uint64_t first_sample, int batch, double* k, double* k_coarse);
+
+/* Coarse Grid Variates sub-samples (Section 4.1, eq. (4.1)): the 2^d coarse
+ * samples k^(a)(I, J) = k(2I + a1, 2J + a2), a = a1 + 2 a2.
+ *   k_fine device [batch][m][m] (m even); k_sub device [batch][4][m/2][m/2]. */
+mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch,
+                             const double* k_fine, double* k_sub);
+
+/* Finite volume system eq. (3.3), harmonic-mean faces, Model Problem 2
+ * (p = 1 on x1 = 0, p = 0 on x1 = 1, no flow on x2 = 0, 1; f = 0).
+ * Dirichlet faces use the half-cell distance: T = 2 k_P h^(d-2).
+ *   k   device [batch][m][m]            (input, positive)
+ *   T   device [batch][2][m][m]: T[s][0][j][i] = transmissibility of the face
+ *       x1 = (i+1)h of cell (i,j) (for i = m-1: the outflow boundary face);
+ *       T[s][1][j][i] = face x2 = (j+1)h (0 for j = m-1, no flow).
+ *   tb  device [batch][2][m]: tb[s][0][j] = face x1 = 0 of cell (0,j) (inflow
+ *       boundary); tb[s][1][i] = face x2 = 0 of cell (i,0) (0, no flow).
+ *   b   device [batch][m][m]: right-hand side (tb[s][0][j] in column i = 0).
+ * Row P of the system: sum over faces T_f (p_P - p_nb) = b_P, where boundary
+ * faces have p_nb = 0 after moving the Dirichlet data to b. */
+mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
+                          double* T, double* tb, double* b);
+
+/* Solve A p = b for each sample of the batch (operator as produced by
+ * mlmc_assemble) with conjugate gradients preconditioned by one symmetric
+ * geometric multigrid V-cycle (Section 3.5; aggregation coarsening with
+ * Galerkin coarse operators, red-black Gauss-Seidel smoothing).
+ *   p       device [batch][m][m], written (initial guess 0).
+ *   status  device int32 [batch], iters device int32 [batch],
+ *   relres  device double [batch] = ||b - A p|| / ||b|| recomputed at exit.
+ * A sample that fails is reported in status[]; it never stops the batch.
+ * Polls a device counter every opts->check_every iterations (stream sync). */
+mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T,
+                       const double* tb, const double* b, double* p,
+                       const mlmc_solver_opts* opts, int32_t* status, int32_t* iters,
+                       double* relres);
+
+/* Outflow M^(2) through x1 = 1 (Section 3.4) of the discrete solution:
+ * q_out[s] = sum_j 2 k(m-1, j) h^(d-2) p(m-1, j); q_in[s] (optional, may be
+ * NULL) = sum_j 2 k(0, j) h^(d-2) (1 - p(0, j)) (equal to q_out for the exact
+ * solution: local conservation).  k, p device [batch][m][m]; q_out, q_in
+ * device [batch]. */
+mlmc_status mlmc_qoi_outflow(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
+                             const double* p, double* q_out, double* q_in);
+
+/* One level of the estimator for samples first_sample .. first_sample + n - 1:
+ * sample (fine grid m_fine), assemble, solve, QoI; for level >= 1 also the
+ * coarse companions on the m_fine/2 grid -- the plain coarse sample of the
+ * same omega (eq. (3.6)), or with cgv != 0 the 2^d sub-lattices averaged as in
+ * eq. (4.1) -- and Y = Q_f - Q_c (eq. (4.2)); on level 0, Y = Q_f.
+ * Adds the level's sums to *sums (host).  q_f, q_c, y: device [n] or NULL.
+ * Synchronises the stream before returning.  Returns MLMC_ENOCONV when any
+ * solve failed (the sums are still updated, n_failed counts them). */
+mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
+                           uint64_t first_sample, int n, int cgv,
+                           const mlmc_solver_opts* opts, mlmc_level_sums* sums,
+                           double* q_f, double* q_c, double* y);
+
+/* Estimator eq. (3.6) and the statistical part of eq. (3.7) from per-level
+ * sums (host arithmetic only).  levels: host [n_levels]; out: host. */
+mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_estimate_t* out);
+
+/* Kernel timing: when enabled, every launch of the named kernel is bracketed
+ * by HIP events on the context's stream; mlmc_profile_read returns the launch
+ * count, the summed event time and the algorithmic bytes the library counts
+ * for those launches.  kernel_name NULL disables.  Host outputs. */
+mlmc_status mlmc_profile_enable(mlmc_ctx* ctx, const char* kernel_name);
+mlmc_status mlmc_profile_read(mlmc_ctx* ctx, int64_t* launches, double* total_ms,
+                              double* algorithmic_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLMC_DARCY_H */

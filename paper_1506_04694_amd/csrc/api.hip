@@ -1,0 +1,681 @@
+// Host side of the C ABI declared in include/mlmc_darcy.h: context, device
+// workspaces, the circulant-embedding cache, multigrid-PCG orchestration and
+// the per-level estimator driver.  All arithmetic of the method runs in the
+// kernels of field.hip, fv.hip and mg_pcg.hip; this file only validates
+// arguments, sizes buffers and enqueues launches on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mlmc_darcy.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace mlmc;
+
+namespace {
+
+struct CeEntry {
+  int n = 0;
+  FftPlan plan{};
+  double2* tw = nullptr;
+  double* sqT = nullptr;
+};
+
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct ProfEvent {
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace
+
+struct mlmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::string, Buffer> ws;
+  std::map<std::tuple<int, int, double, double, int>, CeEntry> ce;
+  void* host_pinned = nullptr;  // small pinned staging buffer
+  std::string prof_name;
+  std::vector<ProfEvent> prof;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+mlmc_status fail(mlmc_ctx* ctx, mlmc_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, MLMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)                          \
+  do {                                     \
+    mlmc_status s_ = (expr);               \
+    if (s_ != MLMC_OK) return s_;          \
+  } while (0)
+
+#define CHECK_LAUNCH()                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, MLMC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Grow-only named device workspace.
+mlmc_status ws_get(mlmc_ctx* ctx, const std::string& name, size_t bytes, void** out) {
+  Buffer& b = ctx->ws[name];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      HIP_TRY(hipStreamSynchronize(ctx->stream));  // earlier launches may still use it
+      HIP_TRY(hipFree(b.ptr));
+    }
+    b.ptr = nullptr;
+    b.bytes = 0;
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, MLMC_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                        " bytes for workspace '" + name + "' failed");
+    }
+    b.ptr = p;
+    b.bytes = bytes;
+  }
+  *out = b.ptr;
+  return MLMC_OK;
+}
+
+template <class T>
+mlmc_status ws(mlmc_ctx* ctx, const std::string& name, size_t count, T** out) {
+  void* p = nullptr;
+  TRY(ws_get(ctx, name, count * sizeof(T) + 256, &p));
+  *out = static_cast<T*>(p);
+  return MLMC_OK;
+}
+
+hipEvent_t pool_event(mlmc_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Brackets a launch with events when `name` is the profiled kernel.
+template <class F>
+void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch) {
+  if (!ctx->prof_name.empty() && ctx->prof_name == name) {
+    ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes};
+    (void)hipEventRecord(pe.a, ctx->stream);
+    launch();
+    (void)hipEventRecord(pe.b, ctx->stream);
+    ctx->prof.push_back(pe);
+  } else {
+    launch();
+  }
+}
+
+bool five_smooth(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+FftPlan make_plan(int n) {
+  FftPlan pl{};
+  pl.n = n;
+  int r = n;
+  auto push = [&](int R) { pl.radix[pl.nstages++] = R; r /= R; };
+  while (r % 4 == 0) push(4);
+  while (r % 2 == 0) push(2);
+  while (r % 3 == 0) push(3);
+  while (r % 5 == 0) push(5);
+  return pl;
+}
+
+mlmc_status check_model(mlmc_ctx* ctx, const mlmc_model* mdl) {
+  if (!mdl) return fail(ctx, MLMC_EINVAL, "model is NULL");
+  if (mdl->dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  const int k = mdl->interface_kind;
+  if (k != MLMC_IFACE_HORIZONTAL && k != MLMC_IFACE_PIECEWISE_LINEAR &&
+      k != MLMC_IFACE_PAPER_TWO_LINES && k != MLMC_IFACE_NONE)
+    return fail(ctx, MLMC_EINVAL, "unknown interface_kind");
+  if (k == MLMC_IFACE_PIECEWISE_LINEAR && (mdl->n_nodes < 2 || mdl->n_nodes > 8))
+    return fail(ctx, MLMC_EINVAL, "n_nodes must be in [2, 8]");
+  const int need = k == MLMC_IFACE_NONE ? 1 : (k == MLMC_IFACE_PAPER_TWO_LINES ? 3 : 2);
+  if (mdl->n_layers != need)
+    return fail(ctx, MLMC_EINVAL, "n_layers does not match the interface kind");
+  for (int l = 0; l < mdl->n_layers; ++l)
+    if (!(mdl->sigma2[l] >= 0.0) || !std::isfinite(mdl->mu[l]))
+      return fail(ctx, MLMC_EINVAL, "layer parameters must be finite with sigma2 >= 0");
+  if (mdl->field_kind == MLMC_FIELD_CORRELATED) {
+    if (mdl->n_layers > 2)
+      return fail(ctx, MLMC_EINVAL, "correlated fields support at most 2 layers");
+    for (int l = 1; l < mdl->n_layers; ++l)
+      if (mdl->sigma2[l] != mdl->sigma2[0] || mdl->lambda[l] != mdl->lambda[0])
+        return fail(ctx, MLMC_EINVAL, "correlated layers must share sigma2 and lambda");
+    if (!(mdl->lambda[0] > 0.0)) return fail(ctx, MLMC_EINVAL, "lambda must be positive");
+    if (mdl->norm_r != 1 && mdl->norm_r != 2) return fail(ctx, MLMC_EINVAL, "norm_r must be 1 or 2");
+  } else if (mdl->field_kind != MLMC_FIELD_PIECEWISE_CONSTANT) {
+    return fail(ctx, MLMC_EINVAL, "unknown field_kind");
+  }
+  if (!(mdl->y_lo <= mdl->y_hi)) return fail(ctx, MLMC_EINVAL, "y_lo > y_hi");
+  return MLMC_OK;
+}
+
+// Embedding eigenvalues for (m, n, sigma2, lambda, r); computed once, cached.
+// With `check_only`, a failing embedding is reported but not cached.
+mlmc_status ce_get(mlmc_ctx* ctx, int m, int n, double sigma2, double lambda, int r,
+                   CeEntry** out) {
+  auto key = std::make_tuple(m, n, sigma2, lambda, r);
+  auto it = ctx->ce.find(key);
+  if (it != ctx->ce.end()) {
+    *out = &it->second;
+    return MLMC_OK;
+  }
+  if (n < 2 * m || n > kFftMax || !five_smooth(n))
+    return fail(ctx, MLMC_EINVAL, "n_ce must satisfy 2m <= n_ce <= 4096 with factors 2, 3, 5");
+  CeEntry e;
+  e.n = n;
+  e.plan = make_plan(n);
+  HIP_TRY(hipMalloc(&e.tw, sizeof(double2) * n));
+  HIP_TRY(hipMalloc(&e.sqT, sizeof(double) * (size_t)n * n));
+  double2* c = nullptr;
+  TRY(ws(ctx, "ce_setup", (size_t)n * n, &c));
+  hipStream_t st = ctx->stream;
+  launch_ce_twiddles(st, n, e.tw);
+  launch_ce_first_row(st, n, m, sigma2, lambda, r, c);
+  launch_fft_lines(st, c, n, n, n, 1, e.tw, e.plan);   // along x1 (rows)
+  launch_fft_lines(st, c, n, n, 1, n, e.tw, e.plan);   // along x2 (columns)
+  const int nb = 256;
+  double* part = nullptr;
+  TRY(ws(ctx, "ce_minmax", 2 * nb, &part));
+  launch_ce_minmax(st, c, (long long)n * n, part, nb);
+  CHECK_LAUNCH();
+  std::vector<double> h(2 * nb);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double lo = h[0], hi = h[1];
+  for (int b = 1; b < nb; ++b) {
+    lo = std::fmin(lo, h[2 * b]);
+    hi = std::fmax(hi, h[2 * b + 1]);
+  }
+  if (!(hi > 0.0) || lo < -1e-12 * hi) {
+    (void)hipFree(e.tw);
+    (void)hipFree(e.sqT);
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "circulant embedding n_ce = %d for m = %d is not non-negative (min/max = %.3e)", n, m,
+             hi > 0 ? lo / hi : 0.0);
+    return fail(ctx, MLMC_EEMBED, buf);
+  }
+  launch_ce_sqrt_transpose(st, c, n, e.sqT);
+  CHECK_LAUNCH();
+  auto res = ctx->ce.emplace(key, e);
+  *out = &res.first->second;
+  return MLMC_OK;
+}
+
+mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
+  if (!o) return fail(ctx, MLMC_EINVAL, "opts is NULL");
+  if (!(o->tol > 0.0)) return fail(ctx, MLMC_EINVAL, "tol must be positive");
+  if (o->maxit < 1) return fail(ctx, MLMC_EINVAL, "maxit must be >= 1");
+  if (o->nu1 < 1 || o->nu1 != o->nu2)
+    return fail(ctx, MLMC_EINVAL, "nu1 == nu2 >= 1 is required for a symmetric preconditioner");
+  if (o->coarse_max < 1) return fail(ctx, MLMC_EINVAL, "coarse_max must be >= 1");
+  if (!(o->omega > 0.0)) return fail(ctx, MLMC_EINVAL, "omega must be positive");
+  return MLMC_OK;
+}
+
+std::string lv(const char* base, int l) { return std::string(base) + std::to_string(l); }
+
+// Algorithmic bytes (FP64) per cell for the launches timed by mlmc_profile_*.
+constexpr double kBytesRbgs = 28.0;       // T (16) + own r (4) + other-colour z (4) + own z (4)
+constexpr double kBytesRbgsZero = 24.0;   // T (16) + own r (4) + own z write (4)
+constexpr double kBytesSpmv = 32.0;       // T (16) + p (8) + q write (8)
+constexpr double kBytesAxpy = 48.0;       // x, r, p, q read + x, r write
+constexpr double kBytesResRes = 34.0;     // T 16 + z 8 + r 8 + rc write 2
+constexpr double kBytesProlong = 18.0;    // z read + write 16 + zc 2
+
+}  // namespace
+
+// =================================================================== public ABI
+extern "C" {
+
+mlmc_status mlmc_ctx_create(int device, void* hip_stream, mlmc_ctx** out) {
+  mlmc_ctx* ctx = nullptr;
+  if (!out) return MLMC_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MLMC_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return MLMC_EDEVICE;
+  ctx = new mlmc_ctx();
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipHostMalloc(&ctx->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return MLMC_ENOMEM;
+  }
+  *out = ctx;
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx) {
+  if (!ctx) return MLMC_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->ws)
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  for (auto& kv : ctx->ce) {
+    (void)hipFree(kv.second.tw);
+    (void)hipFree(kv.second.sqT);
+  }
+  for (auto& pe : ctx->prof) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  delete ctx;
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_ctx_set_stream(mlmc_ctx* ctx, void* hip_stream) {
+  if (!ctx) return MLMC_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return MLMC_OK;
+}
+
+const char* mlmc_last_error(const mlmc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* o) {
+  if (!o) return MLMC_EINVAL;
+  std::memset(o, 0, sizeof *o);
+  o->tol = 1e-13;
+  o->omega = 2.0;
+  o->maxit = 200;
+  o->nu1 = 1;
+  o->nu2 = 1;
+  o->coarse_max = 4;
+  o->check_every = 4;
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m, int* n_ce_out) {
+  if (!ctx || !n_ce_out) return MLMC_EINVAL;
+  TRY(check_model(ctx, model));
+  if (m < 1) return fail(ctx, MLMC_EINVAL, "m must be positive");
+  (void)hipSetDevice(ctx->device);
+  for (int n = 2 * m; n <= kFftMax; ++n) {
+    if (!five_smooth(n)) continue;
+    CeEntry* e = nullptr;
+    mlmc_status s = ce_get(ctx, m, n, model->sigma2[0], model->lambda[0], model->norm_r, &e);
+    if (s == MLMC_OK) {
+      *n_ce_out = n;
+      ctx->err.clear();
+      return MLMC_OK;
+    }
+    if (s != MLMC_EEMBED) return s;
+  }
+  return fail(ctx, MLMC_EEMBED, "no valid circulant embedding with n_ce <= 4096");
+}
+
+mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
+                              uint64_t first_sample, int batch, double* k, double* k_coarse) {
+  if (!ctx) return MLMC_EINVAL;
+  TRY(check_model(ctx, model));
+  if (m < 1 || batch < 0 || level < 0 || !k) return fail(ctx, MLMC_EINVAL, "bad m/batch/level/k");
+  if (k_coarse && (m % 2)) return fail(ctx, MLMC_EINVAL, "k_coarse needs an even m");
+  if (first_sample + (uint64_t)batch > (1ull << 32))
+    return fail(ctx, MLMC_EINVAL, "sample numbers must fit in 32 bits");
+  if (batch == 0) return MLMC_OK;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  double* params = nullptr;
+  TRY(ws(ctx, "params", (size_t)batch * kParamStride, &params));
+  launch_sample_params(st, *model, level, first_sample, batch, params);
+  if (model->field_kind == MLMC_FIELD_PIECEWISE_CONSTANT) {
+    launch_field_pc(st, *model, m, batch, params, k);
+    if (k_coarse) launch_field_pc(st, *model, m / 2, batch, params, k_coarse);
+    CHECK_LAUNCH();
+    return MLMC_OK;
+  }
+  CeEntry* e = nullptr;
+  TRY(ce_get(ctx, m, model->n_ce, model->sigma2[0], model->lambda[0], model->norm_r, &e));
+  double2* uT = nullptr;
+  TRY(ws(ctx, "ce_uT", (size_t)batch * m * e->n, &uT));
+  const double cells = (double)batch * m * m;
+  const double ratio = (double)e->n / m;
+  timed(ctx, "ce_pass_a", cells * (16.0 * ratio + 8.0 * ratio * ratio), [&] {
+    launch_ce_pass_a(st, *model, level, first_sample, batch, m, e->sqT, e->tw, e->plan, uT);
+  });
+  timed(ctx, "ce_pass_b", cells * (16.0 * ratio + 8.0 + (k_coarse ? 2.0 : 0.0)), [&] {
+    launch_ce_pass_b(st, *model, batch, m, uT, e->tw, e->plan, params, k, k_coarse);
+  });
+  CHECK_LAUNCH();
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch, const double* k_fine,
+                             double* k_sub) {
+  if (!ctx) return MLMC_EINVAL;
+  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (m < 2 || (m % 2) || batch < 0 || !k_fine || !k_sub)
+    return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_cgv_extract");
+  if (batch == 0) return MLMC_OK;
+  (void)hipSetDevice(ctx->device);
+  launch_cgv_extract(ctx->stream, m, batch, k_fine, k_sub);
+  CHECK_LAUNCH();
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double* k, double* T,
+                          double* tb, double* b) {
+  if (!ctx) return MLMC_EINVAL;
+  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (m < 1 || batch < 0 || !k || !T || !tb || !b)
+    return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_assemble");
+  if (batch == 0) return MLMC_OK;
+  (void)hipSetDevice(ctx->device);
+  timed(ctx, "assemble", (double)batch * m * m * 40.0,
+        [&] { launch_assemble(ctx->stream, m, batch, k, T, tb, b); });
+  CHECK_LAUNCH();
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_qoi_outflow(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
+                             const double* p, double* q_out, double* q_in) {
+  if (!ctx) return MLMC_EINVAL;
+  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (m < 1 || batch < 0 || !k || !p || !q_out)
+    return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_qoi_outflow");
+  if (batch == 0) return MLMC_OK;
+  (void)hipSetDevice(ctx->device);
+  launch_qoi(ctx->stream, m, batch, k, p, q_out, q_in);
+  CHECK_LAUNCH();
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T,
+                       const double* tb, const double* b, double* p,
+                       const mlmc_solver_opts* opts, int32_t* status, int32_t* iters,
+                       double* relres) {
+  if (!ctx) return MLMC_EINVAL;
+  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  TRY(check_opts(ctx, opts));
+  if (m < 1 || batch < 0 || !T || !tb || !b || !p || !status || !iters || !relres)
+    return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_solve");
+  if (batch == 0) return MLMC_OK;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+
+  // grid hierarchy: halve while even and above coarse_max
+  std::vector<int> ms{m};
+  while (ms.back() % 2 == 0 && ms.back() > opts->coarse_max) ms.push_back(ms.back() / 2);
+  const int L = (int)ms.size() - 1;
+  if (ms[L] > 8)
+    return fail(ctx, MLMC_EINVAL, "coarsest grid " + std::to_string(ms[L]) +
+                                      " > 8: m must be c * 2^k with c <= 8");
+  const long long n = (long long)m * m;
+  const int bps = blocks_per_sample(n);
+
+  std::vector<const double*> Tl(L + 1), tbl(L + 1);
+  std::vector<double*> zl(L + 1), rl(L + 1);
+  Tl[0] = T;
+  tbl[0] = tb;
+  double *r, *z, *pv, *q, *partial;
+  TRY(ws(ctx, "s_r", batch * n, &r));
+  TRY(ws(ctx, "s_z", batch * n, &z));
+  TRY(ws(ctx, "s_p", batch * n, &pv));
+  TRY(ws(ctx, "s_q", batch * n, &q));
+  TRY(ws(ctx, "s_partial", (size_t)batch * bps, &partial));
+  zl[0] = z;
+  rl[0] = r;
+  for (int l = 1; l <= L; ++l) {
+    const long long nl = (long long)ms[l] * ms[l];
+    double *Tc, *tbc, *zc, *rc;
+    TRY(ws(ctx, lv("s_T", l), batch * 2 * nl, &Tc));
+    TRY(ws(ctx, lv("s_tb", l), (size_t)batch * 2 * ms[l], &tbc));
+    TRY(ws(ctx, lv("s_zl", l), batch * nl, &zc));
+    TRY(ws(ctx, lv("s_rl", l), batch * nl, &rc));
+    Tl[l] = Tc;
+    tbl[l] = tbc;
+    zl[l] = zc;
+    rl[l] = rc;
+    launch_coarsen(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tc, tbc);
+  }
+  const long long nc = (long long)ms[L] * ms[L];
+  double* Lf = nullptr;
+  TRY(ws(ctx, "s_chol", batch * nc * nc, &Lf));
+  launch_dense_factor(st, ms[L], batch, Tl[L], tbl[L], Lf);
+
+  SolverState S;
+  TRY(ws(ctx, "s_r0", batch, &S.r0sq));
+  TRY(ws(ctx, "s_rho", batch, &S.rho));
+  TRY(ws(ctx, "s_alpha", batch, &S.alpha));
+  TRY(ws(ctx, "s_beta", batch, &S.beta));
+  TRY(ws(ctx, "s_active", batch, &S.active));
+  TRY(ws(ctx, "s_count", 1, &S.count));
+  CHECK_LAUNCH();
+
+  const int nu = opts->nu1;
+  const double omega = opts->omega;
+  const double cells0 = (double)batch * n;
+  // symmetric V-cycle on level l: z_l ~ A_l^{-1} r_l
+  std::function<void(int)> vcycle = [&](int l) {
+    if (l == L) {
+      launch_dense_solve(st, ms[L], batch, Lf, rl[L], zl[L], S.active);
+      return;
+    }
+    const int ml = ms[l];
+    const double cells = (double)batch * ml * ml;
+    const char* lab = l == 0 ? "rbgs_l0" : "rbgs_coarse";
+    for (int it = 0; it < nu; ++it) {
+      timed(ctx, lab, cells * (it == 0 ? kBytesRbgsZero : kBytesRbgs), [&] {
+        launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, it == 0);
+      });
+      timed(ctx, lab, cells * kBytesRbgs, [&] {
+        launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+      });
+    }
+    timed(ctx, l == 0 ? "resid_restrict_l0" : "resid_restrict_coarse", cells * kBytesResRes, [&] {
+      launch_resid_restrict(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], rl[l + 1], S.active);
+    });
+    vcycle(l + 1);
+    timed(ctx, l == 0 ? "prolong_l0" : "prolong_coarse", cells * kBytesProlong, [&] {
+      launch_prolong(st, ml, batch, zl[l + 1], zl[l], omega, S.active);
+    });
+    for (int it = 0; it < nu; ++it) {
+      timed(ctx, lab, cells * kBytesRbgs, [&] {
+        launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+      });
+      timed(ctx, lab, cells * kBytesRbgs, [&] {
+        launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
+      });
+    }
+  };
+
+  launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps);
+  launch_sc_init(st, batch, partial, bps, S, status, iters, relres);
+  vcycle(0);
+  launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
+  launch_sc_rho(st, batch, partial, bps, S, status, 1);
+  launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
+  CHECK_LAUNCH();
+
+  int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
+  const int check = opts->check_every > 0 ? opts->check_every : 1;
+  for (int it = 1;; ++it) {
+    timed(ctx, "spmv_dot", cells0 * kBytesSpmv, [&] {
+      launch_spmv_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
+    });
+    launch_sc_alpha(st, batch, partial, bps, S, status);
+    timed(ctx, "axpy_dot", cells0 * kBytesAxpy, [&] {
+      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active);
+    });
+    launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
+    CHECK_LAUNCH();
+    if (it % check == 0 || it >= opts->maxit) {
+      HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (*hcount == 0) break;
+    }
+    vcycle(0);
+    launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
+    launch_sc_rho(st, batch, partial, bps, S, status, 0);
+    launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
+  }
+  launch_true_residual(st, m, batch, T, tb, b, p, partial, bps);
+  launch_sc_final(st, batch, partial, bps, S, relres);
+  CHECK_LAUNCH();
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
+                           uint64_t first_sample, int n, int cgv, const mlmc_solver_opts* opts,
+                           mlmc_level_sums* sums, double* q_f, double* q_c, double* y) {
+  if (!ctx) return MLMC_EINVAL;
+  TRY(check_model(ctx, model));
+  TRY(check_opts(ctx, opts));
+  if (!sums || n < 0 || level < 0 || m_fine < 1)
+    return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_level_run");
+  if (level > 0 && (m_fine % 2)) return fail(ctx, MLMC_EINVAL, "level >= 1 needs an even m_fine");
+  if (n == 0) return MLMC_OK;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int m = m_fine, mc = m / 2;
+  const long long nf = (long long)m * m, ncl = (long long)mc * mc;
+  const int ncomp = level == 0 ? 0 : (cgv ? 4 : 1);
+
+  double *k, *T, *tb, *b, *p, *qf, *yv, *relres, *out;
+  int32_t *stf, *itf, *failed;
+  TRY(ws(ctx, "lr_k", n * nf, &k));
+  TRY(ws(ctx, "lr_T", n * 2 * nf, &T));
+  TRY(ws(ctx, "lr_tb", (size_t)n * 2 * m, &tb));
+  TRY(ws(ctx, "lr_b", n * nf, &b));
+  TRY(ws(ctx, "lr_p", n * nf, &p));
+  TRY(ws(ctx, "lr_qf", n, &qf));
+  TRY(ws(ctx, "lr_y", n, &yv));
+  TRY(ws(ctx, "lr_relres", (size_t)n * (ncomp > 0 ? ncomp : 1), &relres));
+  TRY(ws(ctx, "lr_stf", n, &stf));
+  TRY(ws(ctx, "lr_itf", n, &itf));
+  TRY(ws(ctx, "lr_failed", n, &failed));
+  TRY(ws(ctx, "lr_out", 8, &out));
+
+  double* kc = nullptr;
+  if (ncomp > 0) TRY(ws(ctx, "lr_kc", (size_t)n * ncomp * ncl, &kc));
+  TRY(mlmc_sample_field(ctx, model, m, level, first_sample, n, k, (ncomp == 1) ? kc : nullptr));
+  if (ncomp == 4) TRY(mlmc_cgv_extract(ctx, 2, m, n, k, kc));
+
+  TRY(mlmc_assemble(ctx, 2, m, n, k, T, tb, b));
+  TRY(mlmc_solve(ctx, 2, m, n, T, tb, b, p, opts, stf, itf, relres));
+  TRY(mlmc_qoi_outflow(ctx, 2, m, n, k, p, qf, nullptr));
+
+  double* qcv = nullptr;
+  int32_t *stc = nullptr, *itc = nullptr;
+  if (ncomp > 0) {
+    const int nb = n * ncomp;
+    double *Tc, *tbc, *bc, *pc, *qcomp;
+    TRY(ws(ctx, "lr_Tc", (size_t)nb * 2 * ncl, &Tc));
+    TRY(ws(ctx, "lr_tbc", (size_t)nb * 2 * mc, &tbc));
+    TRY(ws(ctx, "lr_bc", (size_t)nb * ncl, &bc));
+    TRY(ws(ctx, "lr_pc", (size_t)nb * ncl, &pc));
+    TRY(ws(ctx, "lr_qcomp", nb, &qcomp));
+    TRY(ws(ctx, "lr_qc", n, &qcv));
+    TRY(ws(ctx, "lr_stc", nb, &stc));
+    TRY(ws(ctx, "lr_itc", nb, &itc));
+    TRY(mlmc_assemble(ctx, 2, mc, nb, kc, Tc, tbc, bc));
+    TRY(mlmc_solve(ctx, 2, mc, nb, Tc, tbc, bc, pc, opts, stc, itc, relres));
+    TRY(mlmc_qoi_outflow(ctx, 2, mc, nb, kc, pc, qcomp, nullptr));
+    launch_cgv_average(st, n, ncomp, qcomp, qcv);
+  }
+  launch_y_and_fail(st, n, qf, qcv, stf, stc, ncomp, yv, failed);
+  launch_level_reduce(st, n, yv, qf, qcv, failed, itf, itc, ncomp, out);
+  if (q_f) HIP_TRY(hipMemcpyAsync(q_f, qf, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  if (q_c) {
+    if (qcv) HIP_TRY(hipMemcpyAsync(q_c, qcv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    else HIP_TRY(hipMemsetAsync(q_c, 0, sizeof(double) * n, st));
+  }
+  if (y) HIP_TRY(hipMemcpyAsync(y, yv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  CHECK_LAUNCH();
+  double* h = static_cast<double*>(ctx->host_pinned);
+  HIP_TRY(hipMemcpyAsync(h, out, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  sums->n += n;
+  sums->sum_y += h[0];
+  sums->sum_y2 += h[1];
+  sums->sum_qf += h[2];
+  sums->sum_qc += h[3];
+  sums->n_failed += (int64_t)llround(h[4]);
+  sums->iters_fine += (int64_t)llround(h[5]);
+  sums->iters_coarse += (int64_t)llround(h[6]);
+  if (h[4] > 0.5) return fail(ctx, MLMC_ENOCONV, "some solves did not reach the tolerance");
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_estimate_t* out) {
+  if (!levels || !out || n_levels < 1) return MLMC_EINVAL;
+  double est = 0.0, var = 0.0;
+  for (int l = 0; l < n_levels; ++l) {
+    const double nn = (double)levels[l].n;
+    if (nn < 2) return MLMC_EINVAL;
+    const double mean = levels[l].sum_y / nn;
+    const double v = (levels[l].sum_y2 - nn * mean * mean) / (nn - 1.0);
+    est += mean;
+    var += v / nn;
+  }
+  out->estimate = est;
+  out->variance = var;
+  out->std_error = std::sqrt(var);
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_profile_enable(mlmc_ctx* ctx, const char* kernel_name) {
+  if (!ctx) return MLMC_EINVAL;
+  ctx->prof_name = kernel_name ? kernel_name : "";
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_profile_read(mlmc_ctx* ctx, int64_t* launches, double* total_ms,
+                              double* algorithmic_bytes) {
+  if (!ctx || !launches || !total_ms || !algorithmic_bytes) return MLMC_EINVAL;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  double ms = 0.0, bytes = 0.0;
+  for (auto& pe : ctx->prof) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, pe.a, pe.b));
+    ms += t;
+    bytes += pe.bytes;
+    ctx->event_pool.push_back(pe.a);
+    ctx->event_pool.push_back(pe.b);
+  }
+  *launches = (int64_t)ctx->prof.size();
+  *total_ms = ms;
+  *algorithmic_bytes = bytes;
+  ctx->prof.clear();
+  return MLMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Host-side launch wrappers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mlmc_darcy.h"
+#include "fft.hpp"
+
+namespace mlmc {
+
+// ------------------------------------------------------------- field.hip
+void launch_sample_params(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
+                          int batch, double* params);
+void launch_field_pc(hipStream_t st, const mlmc_model& mdl, int m, int batch,
+                     const double* params, double* k);
+void launch_ce_twiddles(hipStream_t st, int n, double2* tw);
+void launch_ce_first_row(hipStream_t st, int n, int m, double sigma2, double lambda, int norm_r,
+                         double2* c);
+void launch_fft_lines(hipStream_t st, double2* data, int n, int nlines, long long line_stride,
+                      long long elem_stride, const double2* tw, const FftPlan& pl);
+void launch_ce_minmax(hipStream_t st, const double2* lam, long long count, double* partial,
+                      int nblocks);
+void launch_ce_sqrt_transpose(hipStream_t st, const double2* lam, int n, double* sqT);
+void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
+                      int batch, int m, const double* sqT, const double2* tw, const FftPlan& pl,
+                      double2* uT);
+void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, int batch, int m,
+                      const double2* uT, const double2* tw, const FftPlan& pl,
+                      const double* params, double* k, double* k_coarse);
+void launch_cgv_extract(hipStream_t st, int m, int batch, const double* kf, double* ksub);
+
+// ------------------------------------------------------------- fv.hip
+void launch_assemble(hipStream_t st, int m, int batch, const double* k, double* T, double* tb,
+                     double* b);
+void launch_qoi(hipStream_t st, int m, int batch, const double* k, const double* p, double* qout,
+                double* qin);
+void launch_cgv_average(hipStream_t st, int batch, int ncomp, const double* qcomp, double* qc);
+void launch_y_and_fail(hipStream_t st, int n, const double* qf, const double* qc,
+                       const int32_t* st_f, const int32_t* st_c, int ncomp, double* y,
+                       int32_t* failed);
+void launch_level_reduce(hipStream_t st, int n, const double* y, const double* qf,
+                         const double* qc, const int32_t* failed, const int32_t* it_f,
+                         const int32_t* it_c, int ncomp, double* out6);
+
+// ------------------------------------------------------------- mg_pcg.hip
+struct SolverState {          // per-sample scalars, device arrays of length batch
+  double* r0sq;
+  double* rho;
+  double* alpha;
+  double* beta;
+  int32_t* active;
+  int32_t* count;             // one int: active samples after the last convergence check
+};
+
+void launch_coarsen(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                    double* Tc, double* tbc);
+void launch_rbgs(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
+                 const double* r, const int32_t* active, int color, int zero_init);
+void launch_resid_restrict(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                           const double* z, const double* r, double* rc,
+                           const int32_t* active);
+void launch_prolong(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
+                    const int32_t* active);
+void launch_dense_factor(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                         double* L);
+void launch_dense_solve(hipStream_t st, int m, int batch, const double* L, const double* r,
+                        double* z, const int32_t* active);
+
+void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
+                     double* partial, int bps);
+void launch_spmv_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                     const double* p, double* q, double* partial, int bps,
+                     const int32_t* active);
+void launch_axpy_dot(hipStream_t st, int n, int batch, double* x, double* r, const double* p,
+                     const double* q, const double* alpha, double* partial, int bps,
+                     const int32_t* active);
+void launch_dot(hipStream_t st, int n, int batch, const double* a, const double* b,
+                double* partial, int bps, const int32_t* active);
+void launch_pupdate(hipStream_t st, int n, int batch, double* p, const double* z,
+                    const double* beta, int bps, const int32_t* active, int first);
+void launch_true_residual(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                          const double* b, const double* x, double* partial, int bps);
+
+void launch_sc_init(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                    int32_t* status, int32_t* iters, double* relres);
+void launch_sc_rho(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                   int32_t* status, int first);
+void launch_sc_alpha(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                     int32_t* status);
+void launch_sc_conv(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                    int32_t* status, int32_t* iters, double* relres, double tol, int maxit);
+void launch_sc_final(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                     double* relres);
+
+inline int blocks_per_sample(long long n) { return (int)((n + kCellsPerBlock - 1) / kCellsPerBlock); }
+
+}  // namespace mlmc

@@ -1,0 +1,540 @@
+// Batched multigrid-preconditioned conjugate gradients on gfx950.
+//
+// Section 3.5 solves each sample's symmetric positive definite system with
+// CG preconditioned by one multigrid cycle and stops when
+// ||r_m|| / ||r_0|| < tol.  Here the multigrid is geometric and per sample:
+//  * coarsening by 2 x 2 aggregation with piecewise-constant prolongation P
+//    and restriction P^T; the Galerkin operator P^T A P of a two-point-flux
+//    operator is again two-point-flux, with each coarse face carrying the sum
+//    of the two fine faces it covers (boundary faces likewise);
+//  * red-black Gauss-Seidel smoothing, red then black before the coarse
+//    correction and black then red after it, so the V-cycle is symmetric;
+//  * the coarse correction is scaled by omega (over-correction of the
+//    aggregation coarse space);
+//  * the coarsest grid (<= 8 x 8) is solved by a dense Cholesky factor.
+// Every kernel covers the whole batch; samples that have converged are
+// skipped through a per-sample active flag.  Per-sample dot products are
+// reduced in a fixed order (thread -> wave -> workgroup partial -> one thread
+// per sample), so a sample's iterates do not depend on the rest of the batch.
+//
+// Operator layout (per sample s, grid m x m, n = m*m):
+//   T[s][0][j][i] face x1 = (i+1)h of cell (i,j) (i = m-1: boundary face),
+//   T[s][1][j][i] face x2 = (j+1)h (j = m-1: boundary face),
+//   tb[s][0][j]   face x1 = 0 of cell (0,j), tb[s][1][i] face x2 = 0 of (i,0).
+//   (A x)_P = (sum of the four face T) x_P - sum over interior faces T x_nb.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mlmc {
+
+struct Faces {
+  double te, tw, tn, ts;
+};
+
+__device__ __forceinline__ Faces load_faces(const double* __restrict__ Ts,
+                                            const double* __restrict__ tbs, int m, int i, int j) {
+  const int c = j * m + i;
+  const int n = m * m;
+  Faces f;
+  f.te = Ts[c];
+  f.tw = i > 0 ? Ts[c - 1] : tbs[j];
+  f.tn = Ts[n + c];
+  f.ts = j > 0 ? Ts[n + c - m] : tbs[m + i];
+  return f;
+}
+
+__device__ __forceinline__ double neighbour_sum(const double* __restrict__ x, int m, int i, int j,
+                                                const Faces& f) {
+  const int c = j * m + i;
+  double o = 0.0;
+  if (i < m - 1) o += f.te * x[c + 1];
+  if (i > 0) o += f.tw * x[c - 1];
+  if (j < m - 1) o += f.tn * x[c + m];
+  if (j > 0) o += f.ts * x[c - m];
+  return o;
+}
+
+__device__ __forceinline__ double apply_at(const double* __restrict__ x, int m, int i, int j,
+                                           const Faces& f) {
+  const double d = f.te + f.tw + f.tn + f.ts;
+  return d * x[j * m + i] - neighbour_sum(x, m, i, j, f);
+}
+
+// ------------------------------------------------------------------ hierarchy
+__global__ void k_coarsen(int m, long long total, const double* __restrict__ T,
+                          const double* __restrict__ tb, double* __restrict__ Tc,
+                          double* __restrict__ tbc) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int mc = m / 2;
+  const long long nc = (long long)mc * mc, n = (long long)m * m;
+  const long long s = g / nc;
+  const int rem = (int)(g - s * nc);
+  const int J = rem / mc, I = rem - J * mc;
+  const double* Ts = T + s * 2 * n;
+  double* Tcs = Tc + s * 2 * nc;
+  const int i = 2 * I, j = 2 * J;
+  Tcs[rem] = Ts[j * m + i + 1] + Ts[(j + 1) * m + i + 1];
+  Tcs[nc + rem] = Ts[n + (j + 1) * m + i] + Ts[n + (j + 1) * m + i + 1];
+  const double* tbs = tb + s * 2 * m;
+  double* tbcs = tbc + s * 2 * mc;
+  if (I == 0) tbcs[J] = tbs[j] + tbs[j + 1];
+  if (J == 0) tbcs[mc + I] = tbs[m + i] + tbs[m + i + 1];
+}
+
+void launch_coarsen(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                    double* Tc, double* tbc) {
+  const long long total = (long long)batch * (m / 2) * (m / 2);
+  hipLaunchKernelGGL(k_coarsen, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T, tb,
+                     Tc, tbc);
+}
+
+// ------------------------------------------------------------------ smoother
+// One thread per cell of the given colour ((i + j) % 2 == color).
+__global__ void k_rbgs(int m, long long total, const double* __restrict__ T,
+                       const double* __restrict__ tb, double* __restrict__ z,
+                       const double* __restrict__ r, const int32_t* __restrict__ active,
+                       int color, int zero_init) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int half = m / 2;
+  const long long per = (long long)m * half;
+  const long long s = g / per;
+  if (!active[s]) return;
+  const int rem = (int)(g - s * per);
+  const int j = rem / half;
+  const int i = 2 * (rem - j * half) + ((j + color) & 1);
+  const long long n = (long long)m * m;
+  const Faces f = load_faces(T + s * 2 * n, tb + s * 2 * m, m, i, j);
+  const double d = f.te + f.tw + f.tn + f.ts;
+  double* zs = z + s * n;
+  const double rv = r[s * n + j * m + i];
+  zs[j * m + i] = zero_init ? rv / d : (rv + neighbour_sum(zs, m, i, j, f)) / d;
+}
+
+void launch_rbgs(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
+                 const double* r, const int32_t* active, int color, int zero_init) {
+  const long long total = (long long)batch * m * (m / 2);
+  hipLaunchKernelGGL(k_rbgs, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T, tb, z, r,
+                     active, color, zero_init);
+}
+
+// rc(I,J) = sum over the 2x2 fine cells of (r - A z)
+__global__ void k_resid_restrict(int m, long long total, const double* __restrict__ T,
+                                 const double* __restrict__ tb, const double* __restrict__ z,
+                                 const double* __restrict__ r, double* __restrict__ rc,
+                                 const int32_t* __restrict__ active) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int mc = m / 2;
+  const long long nc = (long long)mc * mc, n = (long long)m * m;
+  const long long s = g / nc;
+  if (!active[s]) return;
+  const int rem = (int)(g - s * nc);
+  const int J = rem / mc, I = rem - J * mc;
+  const double* Ts = T + s * 2 * n;
+  const double* tbs = tb + s * 2 * m;
+  const double* zs = z + s * n;
+  const double* rs = r + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = 2 * I + a, j = 2 * J + b;
+      const Faces f = load_faces(Ts, tbs, m, i, j);
+      acc += rs[j * m + i] - apply_at(zs, m, i, j, f);
+    }
+  rc[g] = acc;
+}
+
+void launch_resid_restrict(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                           const double* z, const double* r, double* rc,
+                           const int32_t* active) {
+  const long long total = (long long)batch * (m / 2) * (m / 2);
+  hipLaunchKernelGGL(k_resid_restrict, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T,
+                     tb, z, r, rc, active);
+}
+
+__global__ void k_prolong(int m, long long total, const double* __restrict__ zc,
+                          double* __restrict__ z, double omega,
+                          const int32_t* __restrict__ active) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long n = (long long)m * m;
+  const long long s = g / n;
+  if (!active[s]) return;
+  const int rem = (int)(g - s * n);
+  const int j = rem / m, i = rem - j * m;
+  const int mc = m / 2;
+  z[g] += omega * zc[s * mc * mc + (j / 2) * mc + (i / 2)];
+}
+
+void launch_prolong(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
+                    const int32_t* active) {
+  const long long total = (long long)batch * m * m;
+  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, zc, z,
+                     omega, active);
+}
+
+// ------------------------------------------------------------------ coarsest grid
+// Dense Cholesky A = L L^T per sample, one thread per sample (n = m*m <= 64).
+__global__ void k_dense_factor(int m, int batch, const double* __restrict__ T,
+                               const double* __restrict__ tb, double* __restrict__ L) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch) return;
+  const int n = m * m;
+  const double* Ts = T + (long long)s * 2 * n;
+  const double* tbs = tb + (long long)s * 2 * m;
+  double* A = L + (long long)s * n * n;
+  for (int q = 0; q < n * n; ++q) A[q] = 0.0;
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      const int c = j * m + i;
+      const Faces f = load_faces(Ts, tbs, m, i, j);
+      A[c * n + c] = f.te + f.tw + f.tn + f.ts;
+      if (i < m - 1) A[(c + 1) * n + c] = -f.te;
+      if (j < m - 1) A[(c + m) * n + c] = -f.tn;
+    }
+  // in-place lower Cholesky (column-oriented), only entries with row >= col used
+  for (int c = 0; c < n; ++c) {
+    double d = A[c * n + c];
+    for (int q = 0; q < c; ++q) d -= A[c * n + q] * A[c * n + q];
+    d = sqrt(d);
+    A[c * n + c] = d;
+    for (int rr = c + 1; rr < n; ++rr) {
+      double v = A[rr * n + c];
+      for (int q = 0; q < c; ++q) v -= A[rr * n + q] * A[c * n + q];
+      A[rr * n + c] = v / d;
+    }
+  }
+}
+
+void launch_dense_factor(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                         double* L) {
+  hipLaunchKernelGGL(k_dense_factor, dim3(blocks_for(batch, 64)), dim3(64), 0, st, m, batch, T,
+                     tb, L);
+}
+
+__global__ void k_dense_solve(int m, int batch, const double* __restrict__ L,
+                              const double* __restrict__ r, double* __restrict__ z,
+                              const int32_t* __restrict__ active) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch || !active[s]) return;
+  const int n = m * m;
+  const double* A = L + (long long)s * n * n;
+  const double* rs = r + (long long)s * n;
+  double* zs = z + (long long)s * n;
+  for (int i = 0; i < n; ++i) {
+    double v = rs[i];
+    for (int q = 0; q < i; ++q) v -= A[i * n + q] * zs[q];
+    zs[i] = v / A[i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double v = zs[i];
+    for (int q = i + 1; q < n; ++q) v -= A[q * n + i] * zs[q];
+    zs[i] = v / A[i * n + i];
+  }
+}
+
+void launch_dense_solve(hipStream_t st, int m, int batch, const double* L, const double* r,
+                        double* z, const int32_t* active) {
+  hipLaunchKernelGGL(k_dense_solve, dim3(blocks_for(batch, 64)), dim3(64), 0, st, m, batch, L, r,
+                     z, active);
+}
+
+// ------------------------------------------------------------------ PCG vector kernels
+// Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c.
+#define PCG_PROLOGUE                                        \
+  const int bps_ = bps;                                     \
+  const long long s = blockIdx.x / bps_;                    \
+  const int blk = blockIdx.x - (int)(s * bps_);             \
+  const int cell0 = blk * kCellsPerBlock + threadIdx.x;
+
+__global__ void __launch_bounds__(kBlock)
+k_pcg_init(int n, const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
+           double* __restrict__ partial, int bps) {
+  __shared__ double sh[kBlock / kWave];
+  PCG_PROLOGUE
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const int cell = cell0 + c * kBlock;
+    if (cell < n) {
+      const long long e = s * n + cell;
+      const double v = b[e];
+      x[e] = 0.0;
+      r[e] = v;
+      acc += v * v;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
+                     double* partial, int bps) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(batch * bps), dim3(kBlock), 0, st, n, b, x, r, partial, bps);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_spmv_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
+           const double* __restrict__ p, double* __restrict__ q, double* __restrict__ partial,
+           int bps, const int32_t* __restrict__ active) {
+  __shared__ double sh[kBlock / kWave];
+  PCG_PROLOGUE
+  if (!active[s]) return;
+  const int n = m * m;
+  const double* Ts = T + s * 2 * n;
+  const double* tbs = tb + s * 2 * m;
+  const double* ps = p + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const int cell = cell0 + c * kBlock;
+    if (cell < n) {
+      const int j = cell / m, i = cell - j * m;
+      const Faces f = load_faces(Ts, tbs, m, i, j);
+      const double v = apply_at(ps, m, i, j, f);
+      q[s * n + cell] = v;
+      acc += ps[cell] * v;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_spmv_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                     const double* p, double* q, double* partial, int bps,
+                     const int32_t* active) {
+  hipLaunchKernelGGL(k_spmv_dot, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q, partial,
+                     bps, active);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_axpy_dot(int n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+           const double* __restrict__ q, const double* __restrict__ alpha,
+           double* __restrict__ partial, int bps, const int32_t* __restrict__ active) {
+  __shared__ double sh[kBlock / kWave];
+  PCG_PROLOGUE
+  if (!active[s]) return;
+  const double a = alpha[s];
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const int cell = cell0 + c * kBlock;
+    if (cell < n) {
+      const long long e = s * n + cell;
+      x[e] += a * p[e];
+      const double rv = r[e] - a * q[e];
+      r[e] = rv;
+      acc += rv * rv;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_axpy_dot(hipStream_t st, int n, int batch, double* x, double* r, const double* p,
+                     const double* q, const double* alpha, double* partial, int bps,
+                     const int32_t* active) {
+  hipLaunchKernelGGL(k_axpy_dot, dim3(batch * bps), dim3(kBlock), 0, st, n, x, r, p, q, alpha,
+                     partial, bps, active);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+      double* __restrict__ partial, int bps, const int32_t* __restrict__ active) {
+  __shared__ double sh[kBlock / kWave];
+  PCG_PROLOGUE
+  if (!active[s]) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const int cell = cell0 + c * kBlock;
+    if (cell < n) {
+      const long long e = s * n + cell;
+      acc += a[e] * b[e];
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_dot(hipStream_t st, int n, int batch, const double* a, const double* b,
+                double* partial, int bps, const int32_t* active) {
+  hipLaunchKernelGGL(k_dot, dim3(batch * bps), dim3(kBlock), 0, st, n, a, b, partial, bps, active);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_pupdate(int n, double* __restrict__ p, const double* __restrict__ z,
+          const double* __restrict__ beta, int bps, const int32_t* __restrict__ active,
+          int first) {
+  PCG_PROLOGUE
+  if (!active[s]) return;
+  const double bt = first ? 0.0 : beta[s];
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const int cell = cell0 + c * kBlock;
+    if (cell < n) {
+      const long long e = s * n + cell;
+      p[e] = first ? z[e] : z[e] + bt * p[e];
+    }
+  }
+}
+
+void launch_pupdate(hipStream_t st, int n, int batch, double* p, const double* z,
+                    const double* beta, int bps, const int32_t* active, int first) {
+  hipLaunchKernelGGL(k_pupdate, dim3(batch * bps), dim3(kBlock), 0, st, n, p, z, beta, bps,
+                     active, first);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_true_residual(int m, const double* __restrict__ T, const double* __restrict__ tb,
+                const double* __restrict__ b, const double* __restrict__ x,
+                double* __restrict__ partial, int bps) {
+  __shared__ double sh[kBlock / kWave];
+  PCG_PROLOGUE
+  const int n = m * m;
+  const double* Ts = T + s * 2 * n;
+  const double* tbs = tb + s * 2 * m;
+  const double* xs = x + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const int cell = cell0 + c * kBlock;
+    if (cell < n) {
+      const int j = cell / m, i = cell - j * m;
+      const Faces f = load_faces(Ts, tbs, m, i, j);
+      const double rv = b[s * n + cell] - apply_at(xs, m, i, j, f);
+      acc += rv * rv;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_true_residual(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                          const double* b, const double* x, double* partial, int bps) {
+  hipLaunchKernelGGL(k_true_residual, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, b, x,
+                     partial, bps);
+}
+
+// ------------------------------------------------------------------ per-sample scalars
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int bps,
+                                               int s) {
+  double acc = 0.0;
+  for (int q = 0; q < bps; ++q) acc += partial[(long long)s * bps + q];
+  return acc;
+}
+
+__global__ void k_sc_init(int batch, const double* __restrict__ partial, int bps, SolverState S,
+                          int32_t* __restrict__ status, int32_t* __restrict__ iters,
+                          double* __restrict__ relres) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch) return;
+  const double v = sum_partials(partial, bps, s);
+  S.r0sq[s] = v;
+  iters[s] = 0;
+  relres[s] = 0.0;
+  status[s] = MLMC_SAMPLE_OK;
+  if (!(v > 0.0) || !isfinite(v)) {
+    S.active[s] = 0;
+    if (!isfinite(v)) status[s] = MLMC_SAMPLE_BREAKDOWN;
+  } else {
+    S.active[s] = 1;
+  }
+}
+
+void launch_sc_init(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                    int32_t* status, int32_t* iters, double* relres) {
+  hipLaunchKernelGGL(k_sc_init, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial, bps,
+                     s, status, iters, relres);
+}
+
+__global__ void k_sc_rho(int batch, const double* __restrict__ partial, int bps, SolverState S,
+                         int32_t* __restrict__ status, int first) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch || !S.active[s]) return;
+  const double v = sum_partials(partial, bps, s);
+  if (!(v > 0.0) || !isfinite(v)) {
+    S.active[s] = 0;
+    status[s] = MLMC_SAMPLE_BREAKDOWN;
+    return;
+  }
+  S.beta[s] = first ? 0.0 : v / S.rho[s];
+  S.rho[s] = v;
+}
+
+void launch_sc_rho(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                   int32_t* status, int first) {
+  hipLaunchKernelGGL(k_sc_rho, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial, bps,
+                     s, status, first);
+}
+
+__global__ void k_sc_alpha(int batch, const double* __restrict__ partial, int bps, SolverState S,
+                           int32_t* __restrict__ status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) *S.count = 0;
+  if (s >= batch || !S.active[s]) return;
+  const double v = sum_partials(partial, bps, s);
+  if (!(v > 0.0) || !isfinite(v)) {
+    S.active[s] = 0;
+    status[s] = MLMC_SAMPLE_BREAKDOWN;
+    return;
+  }
+  S.alpha[s] = S.rho[s] / v;
+}
+
+void launch_sc_alpha(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                     int32_t* status) {
+  hipLaunchKernelGGL(k_sc_alpha, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial,
+                     bps, s, status);
+}
+
+__global__ void k_sc_conv(int batch, const double* __restrict__ partial, int bps, SolverState S,
+                          int32_t* __restrict__ status, int32_t* __restrict__ iters,
+                          double* __restrict__ relres, double tol, int maxit) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch || !S.active[s]) return;
+  const double v = sum_partials(partial, bps, s);
+  const int it = iters[s] + 1;
+  iters[s] = it;
+  const double rr = sqrt(v / S.r0sq[s]);
+  relres[s] = rr;
+  if (!isfinite(v)) {
+    S.active[s] = 0;
+    status[s] = MLMC_SAMPLE_BREAKDOWN;
+  } else if (rr < tol) {
+    S.active[s] = 0;
+    status[s] = MLMC_SAMPLE_OK;
+  } else if (it >= maxit) {
+    S.active[s] = 0;
+    status[s] = MLMC_SAMPLE_NOCONV;
+  } else {
+    atomicAdd(S.count, 1);
+  }
+}
+
+void launch_sc_conv(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                    int32_t* status, int32_t* iters, double* relres, double tol, int maxit) {
+  hipLaunchKernelGGL(k_sc_conv, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial, bps,
+                     s, status, iters, relres, tol, maxit);
+}
+
+__global__ void k_sc_final(int batch, const double* __restrict__ partial, int bps, SolverState S,
+                           double* __restrict__ relres) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= batch) return;
+  const double v = sum_partials(partial, bps, s);
+  const double r0 = S.r0sq[s];
+  relres[s] = r0 > 0.0 ? sqrt(v / r0) : 0.0;
+}
+
+void launch_sc_final(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
+                     double* relres) {
+  hipLaunchKernelGGL(k_sc_final, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial,
+                     bps, s, relres);
+}
+
+}  // namespace mlmc

@@ -1,0 +1,111 @@
+"""The C-ABI library loads, exports every entry point its header declares,
+and the binding's struct layouts match the header (checked by compiling a C
+probe against include/mlmc_darcy.h).  Host-only entry points (defaults and
+the estimator arithmetic of eq. (3.6)/(3.7)) are checked against the oracle;
+no device call is made here."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlmc_darcy.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1506_04694_amd as lib
+    return lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\*|mlmc_status)\s+(mlmc_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib._lib, name), name
+    assert sorted(lib.EXPORTED) == names
+    out = subprocess.check_output(["nm", "-D", "--defined-only", lib.LIB_PATH]).decode()
+    for name in names:
+        assert re.search(r"\sT\s%s$" % name, out, re.M), name
+
+
+PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "mlmc_darcy.h"
+#define P(T, f) printf("%s.%s %zu\n", #T, #f, offsetof(T, f))
+int main(void) {
+  printf("mlmc_model %zu\nmlmc_solver_opts %zu\nmlmc_level_sums %zu\nmlmc_estimate_t %zu\n",
+         sizeof(mlmc_model), sizeof(mlmc_solver_opts), sizeof(mlmc_level_sums),
+         sizeof(mlmc_estimate_t));
+  P(mlmc_model, y_lo); P(mlmc_model, mu); P(mlmc_model, sigma2); P(mlmc_model, lambda);
+  P(mlmc_model, seed); P(mlmc_solver_opts, maxit); P(mlmc_solver_opts, check_every);
+  P(mlmc_level_sums, sum_y); P(mlmc_level_sums, iters_coarse);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header(lib, tmp_path):
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "probe.c"
+    src.write_text(PROBE)
+    exe = tmp_path / "probe"
+    subprocess.check_call([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    assert int(vals["mlmc_model"]) == ctypes.sizeof(lib.mlmc_model)
+    assert int(vals["mlmc_solver_opts"]) == ctypes.sizeof(lib.mlmc_solver_opts)
+    assert int(vals["mlmc_level_sums"]) == ctypes.sizeof(lib.mlmc_level_sums)
+    assert int(vals["mlmc_estimate_t"]) == ctypes.sizeof(lib.mlmc_estimate_t)
+    assert int(vals["mlmc_model.lambda"]) == lib.mlmc_model.lambda_.offset
+    assert int(vals["mlmc_model.seed"]) == lib.mlmc_model.seed.offset
+    assert int(vals["mlmc_model.y_lo"]) == lib.mlmc_model.y_lo.offset
+    assert int(vals["mlmc_solver_opts.check_every"]) == lib.mlmc_solver_opts.check_every.offset
+    assert int(vals["mlmc_level_sums.iters_coarse"]) == lib.mlmc_level_sums.iters_coarse.offset
+
+
+def test_solver_defaults(lib):
+    o = lib.mlmc_solver_opts_default()
+    assert o.tol == 1e-13 and o.omega == 2.0 and o.nu1 == o.nu2 == 1 and o.maxit == 200
+
+
+def test_estimate_matches_oracle(lib):
+    from oracle import mlmc as omlmc
+    rng = np.random.default_rng(3)
+    ys = [rng.standard_normal(n) * s + mu for n, s, mu in ((40, 1.0, 1.6), (25, 0.1, 0.01), (9, 0.02, 0.0))]
+    levels = []
+    for y in ys:
+        s = lib.mlmc_level_sums()
+        s.n = len(y)
+        s.sum_y = float(np.sum(y))
+        s.sum_y2 = float(np.sum(y * y))
+        levels.append(s)
+    got = lib.mlmc_estimate(levels)
+    ref = omlmc.estimate([omlmc.level_sums(y, y, np.zeros_like(y)) for y in ys])
+    assert abs(got["estimate"] - ref["estimate"]) < 1e-13
+    assert abs(got["variance"] - ref["variance_of_estimate"]) < 1e-13 * ref["variance_of_estimate"]
+    bad = lib.mlmc_level_sums()
+    bad.n = 1
+    with pytest.raises(lib.MlmcError):
+        lib.mlmc_estimate([bad])
+
+
+def test_product_path_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_1506_04694_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower() or f == "__init__.py" and \
+                    "import oracle" not in text, f

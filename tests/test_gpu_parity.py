@@ -1,0 +1,320 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, through the C ABI.
+
+Tolerances:
+* layer decisions and the CGV sub-lattice gather are exact;
+* k from Example 1 layers: 1e-14 relative (device exp/log/sincos may differ
+  from the host libm by an ulp);
+* k from circulant embedding: |log k_gpu - log k_oracle| <= 1e-11 (two
+  different FFTs of length n_ce <= 1875, errors ~ eps log n per value);
+* assembly: 1e-14 relative;
+* QoI: 1e-10 relative per sample -- the required parity; the solver
+  tolerance (relative residual 1e-13) is chosen so that this holds.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import workloads as W  # noqa: E402
+from oracle import field as ofield  # noqa: E402
+from oracle import fv as ofv  # noqa: E402
+from oracle import geometry as ogeom  # noqa: E402
+from oracle import mlmc as omlmc  # noqa: E402
+from oracle import qoi as oqoi  # noqa: E402
+from oracle import solve as osolve  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+QTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1506_04694_amd as lib
+    return lib
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
+    yield c
+    lib.mlmc_ctx_destroy(c)
+
+
+DEV = "cuda:0"
+
+
+def f64(*shape):
+    return torch.empty(*shape, dtype=torch.float64, device=DEV)
+
+
+def i32(*shape):
+    return torch.empty(*shape, dtype=torch.int32, device=DEV)
+
+
+def run_field(lib, ctx, model, m, level, first, batch, coarse=False):
+    k = f64(batch, m, m)
+    kc = f64(batch, m // 2, m // 2) if coarse else None
+    lib.mlmc_sample_field(ctx, model, m, level, first, batch, k, kc)
+    torch.cuda.synchronize()
+    return k.cpu().numpy(), (kc.cpu().numpy() if coarse else None)
+
+
+# ------------------------------------------------------------------ fields
+@pytest.mark.parametrize("m,level", [(16, 0), (32, 1), (24, 2)])
+def test_field_piecewise_constant(lib, ctx, m, level):
+    print("field pc m=%d level=%d" % (m, level), flush=True)
+    batch = 40
+    k, kc = run_field(lib, ctx, W.PC2, m, level, 5, batch, coarse=True)
+    for s in range(batch):
+        ref, refc = ofield.sample_k(W.PC2, level, 5 + s, m, with_coarse=True)
+        np.testing.assert_allclose(k[s], ref, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(kc[s], refc, rtol=1e-14, atol=0)
+
+
+def test_field_paper_two_lines_and_pw_linear(lib, ctx):
+    print("field geometry kinds", flush=True)
+    for model, m in ((W.PC2.with_(interface_kind=W.PAPER_TWO_LINES, n_layers=3), 24),
+                     (W.PC2.with_(interface_kind=W.PIECEWISE_LINEAR, n_nodes=8), 40),
+                     (W.PC2.with_(interface_kind=W.PIECEWISE_LINEAR, n_nodes=3), 16)):
+        k, _ = run_field(lib, ctx, model, m, 1, 0, 16)
+        for s in range(16):
+            lid = ogeom.layer_ids(model, 1, s, m)
+            z = ofield.layer_constants(model, 1, s)
+            np.testing.assert_allclose(k[s], np.exp(z[lid]), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("m,level", [(16, 0), (32, 1), (64, 2)])
+def test_field_circulant_embedding(lib, ctx, m, level):
+    print("field ce m=%d level=%d" % (m, level), flush=True)
+    batch = 6
+    k, kc = run_field(lib, ctx, W.CE2, m, level, 3, batch, coarse=True)
+    lam = ofield.ce_eigenvalues(W.CE2.n_ce[m], m, 1.0, 0.3, 2)
+    for s in range(batch):
+        ref, refc = ofield.sample_k(W.CE2, level, 3 + s, m, lam_eig=lam, with_coarse=True)
+        assert np.max(np.abs(np.log(k[s]) - np.log(ref))) < 1e-11
+        assert np.max(np.abs(np.log(kc[s]) - np.log(refc))) < 1e-11
+
+
+def test_field_ce_stationary_one_norm(lib, ctx):
+    print("field ce stationary 1-norm", flush=True)
+    model = W.STATIONARY_1NORM
+    m = 32
+    k, _ = run_field(lib, ctx, model, m, 0, 0, 4)
+    lam = ofield.ce_eigenvalues(model.n_ce[m], m, 1.0, 0.3, 1)
+    for s in range(4):
+        ref = ofield.sample_k(model, 0, s, m, lam_eig=lam)
+        assert np.max(np.abs(np.log(k[s]) - np.log(ref))) < 1e-11
+
+
+@pytest.mark.parametrize("m,sigma2,lam,r", [(16, 1.0, 0.3, 2), (64, 1.0, 0.3, 2), (32, 3.0, 0.1, 2),
+                                            (32, 1.0, 0.3, 1)])
+def test_min_embedding_matches_oracle(lib, ctx, m, sigma2, lam, r):
+    model = W.CE2.with_(sigma2=(sigma2,) * 4, lam=(lam,) * 4, norm_r=r)
+    got = lib.mlmc_ce_min_embedding(ctx, lib.make_model(model), m)
+    assert got == ofield.min_embedding(m, sigma2, lam, r)
+
+
+def test_embedding_refused(lib, ctx):
+    mm = lib.make_model(W.CE2, n_ce=128)
+    k = f64(1, 64, 64)
+    with pytest.raises(lib.MlmcError) as e:
+        lib.mlmc_sample_field(ctx, mm, 64, 0, 0, 1, k)
+    assert e.value.code == lib.MLMC_EEMBED
+
+
+def test_cgv_extract_exact(lib, ctx):
+    m, batch = 12, 3
+    kf = torch.arange(batch * m * m, dtype=torch.float64, device=DEV).reshape(batch, m, m)
+    ks = f64(batch, 4, m // 2, m // 2)
+    lib.mlmc_cgv_extract(ctx, 2, m, batch, kf, ks)
+    torch.cuda.synchronize()
+    kf_h = kf.cpu().numpy()
+    ks_h = ks.cpu().numpy()
+    for s in range(batch):
+        for a, sub in enumerate(ofield.cgv_sublattices(kf_h[s])):
+            assert np.array_equal(ks_h[s, a], sub)
+
+
+# ------------------------------------------------------------------ assembly
+def test_assemble_matches_oracle(lib, ctx):
+    rng = np.random.default_rng(11)
+    batch, m = 4, 10
+    kh = np.exp(1.5 * rng.standard_normal((batch, m, m)))
+    k = torch.from_numpy(kh).to(DEV)
+    T, tb, b = f64(batch, 2, m, m), f64(batch, 2, m), f64(batch, m, m)
+    lib.mlmc_assemble(ctx, 2, m, batch, k, T, tb, b)
+    torch.cuda.synchronize()
+    T, tb, b = T.cpu().numpy(), tb.cpu().numpy(), b.cpu().numpy()
+    for s in range(batch):
+        Tint, Tb = ofv.face_transmissibilities(kh[s])
+        np.testing.assert_allclose(T[s, 0, :, :-1], Tint[1], rtol=1e-14)   # x1 faces
+        np.testing.assert_allclose(T[s, 1, :-1, :], Tint[0], rtol=1e-14)   # x2 faces
+        np.testing.assert_allclose(T[s, 0, :, -1], Tb[:, -1], rtol=1e-15)
+        assert np.all(T[s, 1, -1, :] == 0) and np.all(tb[s, 1] == 0)
+        np.testing.assert_allclose(tb[s, 0], Tb[:, 0], rtol=1e-15)
+        _, bref = ofv.assemble(kh[s])
+        np.testing.assert_allclose(b[s].ravel(), bref, rtol=1e-15)
+
+
+# ------------------------------------------------------------------ solve + QoI
+def solve_batch(lib, ctx, kh, opts=None):
+    batch, m, _ = kh.shape
+    k = torch.from_numpy(np.ascontiguousarray(kh)).to(DEV)
+    T, tb, b = f64(batch, 2, m, m), f64(batch, 2, m), f64(batch, m, m)
+    p = f64(batch, m, m)
+    st, it, rr = i32(batch), i32(batch), f64(batch)
+    qo, qi = f64(batch), f64(batch)
+    opts = opts or lib.mlmc_solver_opts_default()
+    lib.mlmc_assemble(ctx, 2, m, batch, k, T, tb, b)
+    lib.mlmc_solve(ctx, 2, m, batch, T, tb, b, p, opts, st, it, rr)
+    lib.mlmc_qoi_outflow(ctx, 2, m, batch, k, p, qo, qi)
+    torch.cuda.synchronize()
+    return {"p": p.cpu().numpy(), "status": st.cpu().numpy(), "iters": it.cpu().numpy(),
+            "relres": rr.cpu().numpy(), "q_out": qo.cpu().numpy(), "q_in": qi.cpu().numpy()}
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 6, 8, 12, 16, 24, 40, 64, 96])
+def test_solve_qoi_random_lognormal(lib, ctx, m):
+    print("solve m=%d" % m, flush=True)
+    rng = np.random.default_rng(100 + m)
+    batch = 5
+    kh = np.exp(1.5 * rng.standard_normal((batch, m, m)))
+    out = solve_batch(lib, ctx, kh)
+    assert np.all(out["status"] == 0), out["status"]
+    assert np.all(out["relres"] < 1e-12), out["relres"]
+    for s in range(batch):
+        A, b = ofv.assemble(kh[s])
+        pr = osolve.direct_solve(A, b)
+        q = oqoi.outflow(kh[s], pr)
+        assert abs(out["q_out"][s] - q) <= QTOL * q, (s, out["q_out"][s], q)
+        assert abs(out["q_in"][s] - q) <= 1e-9 * q
+        assert np.max(np.abs(out["p"][s].ravel() - pr)) < 1e-8
+
+
+def test_solve_closed_forms(lib, ctx):
+    m = 32
+    rng = np.random.default_rng(5)
+    rows = np.exp(rng.standard_normal(m))
+    cols = np.exp(2.0 * rng.standard_normal(m))
+    kh = np.stack([np.full((m, m), 3.7), np.repeat(rows[:, None], m, 1), np.repeat(cols[None, :], m, 0)])
+    out = solve_batch(lib, ctx, kh)
+    assert abs(out["q_out"][0] - 3.7) < 1e-11 * 3.7
+    assert abs(out["q_out"][1] - rows.mean()) < 1e-11 * rows.mean()
+    hm = m / np.sum(1.0 / cols)
+    assert abs(out["q_out"][2] - hm) < 1e-11 * hm
+    x1 = (np.arange(m) + 0.5) / m
+    assert np.max(np.abs(out["p"][0] - (1 - x1)[None, :])) < 1e-11
+
+
+def test_solve_failure_paths(lib, ctx):
+    rng = np.random.default_rng(9)
+    m, batch = 32, 3
+    kh = np.exp(rng.standard_normal((batch, m, m)))
+    kh[1, 5, 7] = np.nan
+    out = solve_batch(lib, ctx, kh)
+    assert out["status"][0] == lib.MLMC_SAMPLE_OK and out["status"][2] == lib.MLMC_SAMPLE_OK
+    assert out["status"][1] == lib.MLMC_SAMPLE_BREAKDOWN
+    out = solve_batch(lib, ctx, kh[[0, 2]], lib.mlmc_solver_opts_default(maxit=1))
+    assert np.all(out["status"] == lib.MLMC_SAMPLE_NOCONV) and np.all(out["iters"] == 1)
+    with pytest.raises(lib.MlmcError) as e:
+        solve_batch(lib, ctx, kh[[0]], lib.mlmc_solver_opts_default(nu1=2, nu2=1))
+    assert e.value.code == lib.MLMC_EINVAL
+    with pytest.raises(lib.MlmcError):
+        solve_batch(lib, ctx, np.ones((1, 88, 88)))     # 88 = 11 * 8: coarsest 11 > 8
+
+
+# ------------------------------------------------------------------ level runs
+def level_run(lib, ctx, model, level, m, first, n, cgv, opts=None):
+    qf, qc, y = f64(n), f64(n), f64(n)
+    opts = opts or lib.mlmc_solver_opts_default()
+    sums = lib.mlmc_level_run(ctx, model, level, m, first, n, cgv, opts, q_f=qf, q_c=qc, y=y)
+    torch.cuda.synchronize()
+    return sums, qf.cpu().numpy(), qc.cpu().numpy(), y.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["pc2_16_32_plain.json", "pc2_16_32_cgv.json",
+                                  "ce2_16_32_plain.json", "ce2_16_32_cgv.json"])
+def test_level_run_matches_golden(lib, ctx, name):
+    print("level run golden %s" % name, flush=True)
+    rec = json.load(open(os.path.join(GOLDEN, name)))
+    model = {"pc2": W.PC2, "ce2": W.CE2}[name[:3]]
+    for lv in rec["levels"]:
+        rows = lv["samples"]
+        n = len(rows)
+        sums, qf, qc, y = level_run(lib, ctx, model, lv["level"], lv["m"], 0, n, rec["cgv"])
+        assert sums.n == n and sums.n_failed == 0
+        for s, row in enumerate(rows):
+            assert abs(qf[s] - row["Q_f"]) <= QTOL * abs(row["Q_f"])
+            if lv["level"] > 0:
+                assert abs(qc[s] - row["Q_c"]) <= QTOL * abs(row["Q_c"])
+                assert abs(y[s] - row["Y"]) <= QTOL * abs(row["Q_f"])
+        assert abs(sums.sum_y - y.sum()) <= 1e-12 * np.abs(y).sum()
+
+
+def test_level_run_config_small_estimator(lib, ctx):
+    """Two-level plain MLMC of the 16/32 piecewise constant workload (200 samples per
+    level): every sample against its closed form, and the estimate against e^(1/2)."""
+    wl = W.SMALL_PC
+    sums = []
+    for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+        s, qf, qc, y = level_run(lib, ctx, wl.model, level, m, 0, n, False)
+        sums.append(s)
+        for i in range(0, n, 7):
+            y0 = ogeom.interface_params(wl.model, level, i)["y0"]
+            kl = np.exp(ofield.layer_constants(wl.model, level, i))
+            ff = np.ceil(m * y0 - 0.5) / m
+            ref = ff * kl[0] + (1 - ff) * kl[1]
+            assert abs(qf[i] - ref) <= QTOL * ref
+    est = lib.mlmc_estimate(sums)
+    assert abs(est["estimate"] - np.exp(0.5)) < 5 * est["std_error"]
+
+
+def test_batch_invariance_bitwise(lib, ctx):
+    """A sample's result does not depend on the batch it is solved in."""
+    model, m = W.CE2, 64
+    _, qf_big, qc_big, _ = level_run(lib, ctx, model, 1, m, 10, 37, False)
+    for s in (0, 17, 36):
+        _, qf1, qc1, _ = level_run(lib, ctx, model, 1, m, 10 + s, 1, False)
+        assert qf1[0] == qf_big[s] and qc1[0] == qc_big[s]
+
+
+def test_level_run_noconv_is_reported(lib, ctx):
+    opts = lib.mlmc_solver_opts_default(maxit=2)
+    qf = f64(4)
+    sums = lib.mlmc_level_run(ctx, W.CE2, 1, 32, 0, 4, False, opts, q_f=qf, allow_noconv=True)
+    assert sums.n == 4 and sums.n_failed == 4
+    with pytest.raises(lib.MlmcError) as e:
+        lib.mlmc_level_run(ctx, W.CE2, 1, 32, 0, 4, False, opts)
+    assert e.value.code == lib.MLMC_ENOCONV
+
+
+# ------------------------------------------------------------------ full-size levels
+FULL = W.LAYERED_CE
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_layered_ce_full_level_sampled(lib, ctx, level):
+    """Each level of the layered correlated workload at its full size (the launch the
+    bench times), with sampled samples checked against the oracle one by one."""
+    m, n = FULL.m_levels[level], FULL.n_samples[level]
+    print("full level %d: %d x %d^2" % (level, n, m), flush=True)
+    sums, qf, qc, y = level_run(lib, ctx, FULL.model, level, m, 0, n, False)
+    assert sums.n == n and sums.n_failed == 0
+    assert np.all(np.isfinite(qf)) and np.all(qf > 0)
+    lam = ofield.ce_eigenvalues(FULL.model.n_ce[m], m, 1.0, 0.3, 2)
+    picks = [0, n // 3, n - 1] if m >= 512 else [0, n // 3, 2 * n // 3, n - 1]
+    for s in picks:
+        k = ofield.sample_k(FULL.model, level, s, m, lam_eig=lam, with_coarse=level > 0)
+        kf = k[0] if level > 0 else k
+        q_ref = omlmc.solve_qoi(kf)[0]
+        assert abs(qf[s] - q_ref) <= QTOL * q_ref, (s, qf[s], q_ref)
+        if level > 0:
+            qc_ref = omlmc.solve_qoi(k[1])[0]
+            assert abs(qc[s] - qc_ref) <= QTOL * qc_ref, (s, qc[s], qc_ref)
