@@ -119,7 +119,8 @@ typedef struct mlmc_solver_opts {
                            (default 4); the coarsest grid (<= 8 x 8) is solved by
                            dense Cholesky                                           */
   int32_t check_every;  /* iterations between host checks of the active count      */
-  int32_t reserved;
+  int32_t variant;      /* 0: fused LDS-tiled V-cycle kernels (needs nu1 = nu2 = 1,
+                           else falls back to 1); 1: one launch per sweep / step     */
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */

@@ -258,6 +258,8 @@ constexpr double kBytesSpmv = 32.0;       // T (16) + p (8) + q write (8)
 constexpr double kBytesAxpy = 48.0;       // x, r, p, q read + x, r write
 constexpr double kBytesResRes = 34.0;     // T 16 + z 8 + r 8 + rc write 2
 constexpr double kBytesProlong = 18.0;    // z read + write 16 + zc 2
+constexpr double kBytesDown = 34.0;       // T 16 + r 8 + z write 8 + coarse r write 2
+constexpr double kBytesUp = 42.0;         // T 16 + r 8 + z_pre 8 + z_c 2 + z write 8
 
 }  // namespace
 
@@ -368,10 +370,10 @@ mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int
   TRY(ws(ctx, "ce_uT", (size_t)batch * m * e->n, &uT));
   const double cells = (double)batch * m * m;
   const double ratio = (double)e->n / m;
-  timed(ctx, "ce_pass_a", cells * (16.0 * ratio + 8.0 * ratio * ratio), [&] {
+  timed(ctx, "k_ce_pass_a", cells * (16.0 * ratio + 8.0 * ratio * ratio), [&] {
     launch_ce_pass_a(st, *model, level, first_sample, batch, m, e->sqT, e->tw, e->plan, uT);
   });
-  timed(ctx, "ce_pass_b", cells * (16.0 * ratio + 8.0 + (k_coarse ? 2.0 : 0.0)), [&] {
+  timed(ctx, "k_ce_pass_b", cells * (16.0 * ratio + 8.0 + (k_coarse ? 2.0 : 0.0)), [&] {
     launch_ce_pass_b(st, *model, batch, m, uT, e->tw, e->plan, params, k, k_coarse);
   });
   CHECK_LAUNCH();
@@ -399,7 +401,7 @@ mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double
     return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_assemble");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
-  timed(ctx, "assemble", (double)batch * m * m * 40.0,
+  timed(ctx, "k_assemble", (double)batch * m * m * 40.0,
         [&] { launch_assemble(ctx->stream, m, batch, k, T, tb, b); });
   CHECK_LAUNCH();
   return MLMC_OK;
@@ -467,9 +469,10 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     launch_coarsen(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tc, tbc);
   }
   const long long nc = (long long)ms[L] * ms[L];
-  double* Lf = nullptr;
-  TRY(ws(ctx, "s_chol", batch * nc * nc, &Lf));
-  launch_dense_factor(st, ms[L], batch, Tl[L], tbl[L], Lf);
+  double *work = nullptr, *Ainv = nullptr;
+  TRY(ws(ctx, "s_chol", batch * nc * nc, &work));
+  TRY(ws(ctx, "s_ainv", batch * nc * nc, &Ainv));
+  launch_dense_factor(st, ms[L], batch, Tl[L], tbl[L], work, Ainv);
 
   SolverState S;
   TRY(ws(ctx, "s_r0", batch, &S.r0sq));
@@ -483,43 +486,85 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   const int nu = opts->nu1;
   const double omega = opts->omega;
   const double cells0 = (double)batch * n;
-  // symmetric V-cycle on level l: z_l ~ A_l^{-1} r_l
-  std::function<void(int)> vcycle = [&](int l) {
+  const bool fused = opts->variant == 0 && nu == 1;
+
+  // Fused V(1,1): tiled down/up kernels above level l0, one workgroup per
+  // sample for levels l0..L (sizes <= kCoarseCycleMax).
+  int l0 = L;
+  std::vector<double*> zpre(L + 1, nullptr);
+  CoarseDesc cdesc{};
+  if (fused) {
+    l0 = 0;
+    while (l0 < L && (ms[l0] > kCoarseCycleMax || L - l0 + 1 > kMaxCoarseLevels)) ++l0;
+    for (int l = 0; l < l0; ++l) TRY(ws(ctx, lv("s_zpre", l), batch * (long long)ms[l] * ms[l], &zpre[l]));
+    for (int q = 0; q + l0 <= L; ++q) {
+      cdesc.m[q] = ms[l0 + q];
+      cdesc.T[q] = Tl[l0 + q];
+      cdesc.tb[q] = tbl[l0 + q];
+    }
+  }
+  const int ncl = L - l0 + 1;
+  double coarse_bytes = 0.0;
+  for (int l = l0; l <= L; ++l) coarse_bytes += 16.0 * ms[l] * ms[l];
+  coarse_bytes = batch * (coarse_bytes + 16.0 * ms[l0] * ms[l0] + 8.0 * nc * nc);
+
+  std::function<void(int)> vcycle_unfused = [&](int l) {
     if (l == L) {
-      launch_dense_solve(st, ms[L], batch, Lf, rl[L], zl[L], S.active);
+      timed(ctx, "k_dense_apply", batch * (8.0 * nc * nc + 16.0 * nc),
+            [&] { launch_dense_apply(st, ms[L], batch, Ainv, rl[L], zl[L], S.active); });
       return;
     }
     const int ml = ms[l];
     const double cells = (double)batch * ml * ml;
-    const char* lab = l == 0 ? "rbgs_l0" : "rbgs_coarse";
     for (int it = 0; it < nu; ++it) {
-      timed(ctx, lab, cells * (it == 0 ? kBytesRbgsZero : kBytesRbgs), [&] {
+      timed(ctx, "k_rbgs", cells * (it == 0 ? kBytesRbgsZero : kBytesRbgs), [&] {
         launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, it == 0);
       });
-      timed(ctx, lab, cells * kBytesRbgs, [&] {
+      timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
         launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
       });
     }
-    timed(ctx, l == 0 ? "resid_restrict_l0" : "resid_restrict_coarse", cells * kBytesResRes, [&] {
+    timed(ctx, "k_resid_restrict", cells * kBytesResRes, [&] {
       launch_resid_restrict(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], rl[l + 1], S.active);
     });
-    vcycle(l + 1);
-    timed(ctx, l == 0 ? "prolong_l0" : "prolong_coarse", cells * kBytesProlong, [&] {
-      launch_prolong(st, ml, batch, zl[l + 1], zl[l], omega, S.active);
-    });
+    vcycle_unfused(l + 1);
+    timed(ctx, "k_prolong", cells * kBytesProlong,
+          [&] { launch_prolong(st, ml, batch, zl[l + 1], zl[l], omega, S.active); });
     for (int it = 0; it < nu; ++it) {
-      timed(ctx, lab, cells * kBytesRbgs, [&] {
+      timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
         launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
       });
-      timed(ctx, lab, cells * kBytesRbgs, [&] {
+      timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
         launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
+      });
+    }
+  };
+  auto vcycle = [&]() {
+    if (!fused) {
+      vcycle_unfused(0);
+      return;
+    }
+    for (int l = 0; l < l0; ++l) {
+      const double cells = (double)batch * ms[l] * ms[l];
+      timed(ctx, "k_mg_down", cells * kBytesDown, [&] {
+        launch_mg_down(st, ms[l], batch, Tl[l], tbl[l], rl[l], zpre[l], rl[l + 1], S.active);
+      });
+    }
+    timed(ctx, "k_mg_coarse_cycle", coarse_bytes, [&] {
+      launch_mg_coarse_cycle(st, batch, ncl, cdesc, rl[l0], zl[l0], Ainv, omega, S.active);
+    });
+    for (int l = l0 - 1; l >= 0; --l) {
+      const double cells = (double)batch * ms[l] * ms[l];
+      timed(ctx, "k_mg_up", cells * kBytesUp, [&] {
+        launch_mg_up(st, ms[l], batch, Tl[l], tbl[l], rl[l], zpre[l], zl[l], zl[l + 1], omega,
+                     S.active);
       });
     }
   };
 
   launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps);
   launch_sc_init(st, batch, partial, bps, S, status, iters, relres);
-  vcycle(0);
+  vcycle();
   launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
   launch_sc_rho(st, batch, partial, bps, S, status, 1);
   launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
@@ -528,11 +573,11 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
   const int check = opts->check_every > 0 ? opts->check_every : 1;
   for (int it = 1;; ++it) {
-    timed(ctx, "spmv_dot", cells0 * kBytesSpmv, [&] {
+    timed(ctx, "k_spmv_dot", cells0 * kBytesSpmv, [&] {
       launch_spmv_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
     });
     launch_sc_alpha(st, batch, partial, bps, S, status);
-    timed(ctx, "axpy_dot", cells0 * kBytesAxpy, [&] {
+    timed(ctx, "k_axpy_dot", cells0 * kBytesAxpy, [&] {
       launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active);
     });
     launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
@@ -542,7 +587,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       HIP_TRY(hipStreamSynchronize(st));
       if (*hcount == 0) break;
     }
-    vcycle(0);
+    vcycle();
     launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
     launch_sc_rho(st, batch, partial, bps, S, status, 0);
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);

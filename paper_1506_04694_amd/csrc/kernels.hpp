@@ -63,9 +63,31 @@ void launch_resid_restrict(hipStream_t st, int m, int batch, const double* T, co
 void launch_prolong(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
                     const int32_t* active);
 void launch_dense_factor(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                         double* L);
-void launch_dense_solve(hipStream_t st, int m, int batch, const double* L, const double* r,
+                         double* work, double* Ainv);
+void launch_dense_apply(hipStream_t st, int m, int batch, const double* Ainv, const double* r,
                         double* z, const int32_t* active);
+
+// ------------------------------------------------------------- mg_fused.hip
+constexpr int kTileX = 64;            // fused multigrid tile (cells along x1)
+constexpr int kTileY = 16;            // fused multigrid tile (cells along x2)
+constexpr int kCoarseCycleMax = 32;   // levels up to this size run in one workgroup per sample
+constexpr int kMaxCoarseLevels = 8;
+
+struct CoarseDesc {
+  int m[kMaxCoarseLevels];
+  const double* T[kMaxCoarseLevels];
+  const double* tb[kMaxCoarseLevels];
+};
+
+void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                    const double* r, double* z, double* rc, const int32_t* active);
+void launch_mg_up(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                  const double* r, const double* zpre, double* z, const double* zc, double omega,
+                  const int32_t* active);
+size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev);
+void launch_mg_coarse_cycle(hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
+                            const double* r0, double* z0, const double* Ainv, double omega,
+                            const int32_t* active);
 
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
                      double* partial, int bps);

@@ -178,15 +178,19 @@ void launch_prolong(hipStream_t st, int m, int batch, const double* zc, double* 
 }
 
 // ------------------------------------------------------------------ coarsest grid
-// Dense Cholesky A = L L^T per sample, one thread per sample (n = m*m <= 64).
+// Dense Cholesky A = L L^T per sample (one thread per sample, n = m*m <= 64),
+// then the explicit inverse A^-1 = L^-T L^-1 column by column, so that each
+// application on the coarsest grid is a matrix-vector product.
 __global__ void k_dense_factor(int m, int batch, const double* __restrict__ T,
-                               const double* __restrict__ tb, double* __restrict__ L) {
+                               const double* __restrict__ tb, double* __restrict__ work,
+                               double* __restrict__ Ainv) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= batch) return;
   const int n = m * m;
   const double* Ts = T + (long long)s * 2 * n;
   const double* tbs = tb + (long long)s * 2 * m;
-  double* A = L + (long long)s * n * n;
+  double* A = work + (long long)s * n * n;
+  double* X = Ainv + (long long)s * n * n;
   for (int q = 0; q < n * n; ++q) A[q] = 0.0;
   for (int j = 0; j < m; ++j)
     for (int i = 0; i < m; ++i) {
@@ -208,39 +212,48 @@ __global__ void k_dense_factor(int m, int batch, const double* __restrict__ T,
       A[rr * n + c] = v / d;
     }
   }
+  // columns of the inverse: L y = e_q, L^T x = y ; X is symmetric, stored row-major
+  for (int q = 0; q < n; ++q) {
+    for (int i = 0; i < n; ++i) {
+      double v = (i == q) ? 1.0 : 0.0;
+      for (int p = 0; p < i; ++p) v -= A[i * n + p] * X[p * n + q];
+      X[i * n + q] = v / A[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = X[i * n + q];
+      for (int p = i + 1; p < n; ++p) v -= A[p * n + i] * X[p * n + q];
+      X[i * n + q] = v / A[i * n + i];
+    }
+  }
 }
 
 void launch_dense_factor(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                         double* L) {
+                         double* work, double* Ainv) {
   hipLaunchKernelGGL(k_dense_factor, dim3(blocks_for(batch, 64)), dim3(64), 0, st, m, batch, T,
-                     tb, L);
+                     tb, work, Ainv);
 }
 
-__global__ void k_dense_solve(int m, int batch, const double* __restrict__ L,
+// z = A^-1 r, one thread per (sample, row).
+__global__ void k_dense_apply(int n, long long total, const double* __restrict__ Ainv,
                               const double* __restrict__ r, double* __restrict__ z,
                               const int32_t* __restrict__ active) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= batch || !active[s]) return;
-  const int n = m * m;
-  const double* A = L + (long long)s * n * n;
-  const double* rs = r + (long long)s * n;
-  double* zs = z + (long long)s * n;
-  for (int i = 0; i < n; ++i) {
-    double v = rs[i];
-    for (int q = 0; q < i; ++q) v -= A[i * n + q] * zs[q];
-    zs[i] = v / A[i * n + i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double v = zs[i];
-    for (int q = i + 1; q < n; ++q) v -= A[q * n + i] * zs[q];
-    zs[i] = v / A[i * n + i];
-  }
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long s = g / n;
+  if (!active[s]) return;
+  const int q = (int)(g - s * n);
+  const double* A = Ainv + s * n * n + (long long)q * n;
+  const double* rs = r + s * n;
+  double acc = 0.0;
+  for (int p = 0; p < n; ++p) acc += A[p] * rs[p];
+  z[g] = acc;
 }
 
-void launch_dense_solve(hipStream_t st, int m, int batch, const double* L, const double* r,
+void launch_dense_apply(hipStream_t st, int m, int batch, const double* Ainv, const double* r,
                         double* z, const int32_t* active) {
-  hipLaunchKernelGGL(k_dense_solve, dim3(blocks_for(batch, 64)), dim3(64), 0, st, m, batch, L, r,
-                     z, active);
+  const long long total = (long long)batch * m * m;
+  hipLaunchKernelGGL(k_dense_apply, dim3(blocks_for(total)), dim3(kBlock), 0, st, m * m, total,
+                     Ainv, r, z, active);
 }
 
 // ------------------------------------------------------------------ PCG vector kernels

@@ -318,3 +318,34 @@ def test_layered_ce_full_level_sampled(lib, ctx, level):
         if level > 0:
             qc_ref = omlmc.solve_qoi(k[1])[0]
             assert abs(qc[s] - qc_ref) <= QTOL * qc_ref, (s, qc[s], qc_ref)
+
+
+# ------------------------------------------------------------------ fused vs per-sweep V-cycle
+@pytest.mark.parametrize("m", [8, 24, 40, 64, 96, 128, 256])
+def test_fused_vcycle_matches_unfused(lib, ctx, m):
+    """The fused tiled V-cycle and the one-launch-per-sweep V-cycle are the same
+    preconditioner: equal iteration counts (+-1 from rounding) and QoIs, both at
+    the oracle's value."""
+    print("fused vs unfused m=%d" % m, flush=True)
+    rng = np.random.default_rng(300 + m)
+    batch = 3
+    kh = np.exp(1.5 * rng.standard_normal((batch, m, m)))
+    a = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=0))
+    b = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=1))
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+    assert np.all(np.abs(a["iters"] - b["iters"]) <= 1), (a["iters"], b["iters"])
+    for s in range(batch):
+        A, bb = ofv.assemble(kh[s])
+        q = oqoi.outflow(kh[s], osolve.direct_solve(A, bb))
+        assert abs(a["q_out"][s] - q) <= QTOL * q
+        assert abs(b["q_out"][s] - q) <= QTOL * q
+
+
+def test_iterations_flat_in_grid_size(lib, ctx):
+    """Multigrid-preconditioned CG needs a bounded number of iterations on the
+    layered correlated model from 64^2 to 512^2 (optimal solver, Section 3.5)."""
+    its = []
+    for level, m in enumerate([64, 128, 256, 512]):
+        sums = lib.mlmc_level_run(ctx, W.CE2, level, m, 0, 8, False, lib.mlmc_solver_opts_default())
+        its.append(sums.iters_fine / 8)
+    assert max(its) <= 25 and max(its) - min(its) <= 5, its
