@@ -203,6 +203,231 @@ k_mg_up(int m, int tx, int ty, int tiles_per_sample, const double* __restrict__ 
   }
 }
 
+// Branch-free load of one frame cell: every address is clamped into the
+// sample's arrays, so all loads of a thread are issued back to back and the
+// out-of-domain cases are resolved by selects afterwards.
+struct FrameLoad {
+  double te, tn;
+  int c, ic, jc;
+  bool in;
+};
+
+__device__ __forceinline__ FrameLoad frame_load(const double* __restrict__ Ts,
+                                                const double* __restrict__ tbs, int m, int i,
+                                                int j) {
+  FrameLoad v;
+  v.ic = min(max(i, 0), m - 1);
+  v.jc = min(max(j, 0), m - 1);
+  v.c = v.jc * m + v.ic;
+  const bool iin = i >= 0 && i < m, jin = j >= 0 && j < m;
+  v.in = iin && jin;
+  const double te = Ts[v.c];
+  const double tn = Ts[m * m + v.c];
+  const double tw = tbs[v.jc];
+  const double ts = tbs[m + v.ic];
+  v.te = v.in ? te : ((i == -1 && jin) ? tw : 0.0);
+  v.tn = v.in ? tn : ((j == -1 && iin) ? ts : 0.0);
+  return v;
+}
+
+// ------------------------------------------------------------------ fixed-tile variants
+// Same algorithm as k_mg_down / k_mg_up for tiles of compile-time size TX x TY
+// (used when TX divides m and TY divides m).  The frame width is a constant,
+// each thread owns the frame cells f = tid + 256 k in every phase, so its
+// right-hand side and diagonal stay in registers; LDS holds the faces and z.
+// Tiles of one sample are mapped to one XCD (shared L2 for the halos).
+template <int TX, int TY>
+struct Tile {
+  static constexpr int W = TX + 5, H = TY + 5, F = W * H;
+  static constexpr int K = (F + kBlock - 1) / kBlock;
+};
+
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int x = bid & 7, q = bid >> 3;
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+template <int TX, int TY>
+__global__ void __launch_bounds__(kBlock)
+k_mg_down_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
+            const double* __restrict__ r, double* __restrict__ z, double* __restrict__ rc,
+            const int32_t* __restrict__ active) {
+  using G = Tile<TX, TY>;
+  constexpr int W = G::W, F = G::F, K = G::K;
+  __shared__ double ste[F], stn[F], sz[F];
+  const int ntx = m / TX, tps = ntx * (m / TY);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
+  const long long s = bid / tps;
+  if (!active[s]) return;
+  const int tile = bid - (int)(s * tps);
+  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
+  const long long n = (long long)m * m;
+  const double* Ts = T + s * 2 * n;
+  const double* tbs = tb + s * 2 * m;
+  const double* rs = r + s * n;
+  double rv[K], dv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    rv[k] = 0.0;
+    if (f < F) {
+      const int fj = f / W, fi = f - fj * W;
+      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+      const FrameLoad v = frame_load(Ts, tbs, m, i, j);
+      const double rr = rs[v.c];
+      ste[f] = v.te;
+      stn[f] = v.tn;
+      rv[k] = v.in ? rr : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    dv[k] = 1.0;
+    if (f < F) {
+      const int fj = f / W, fi = f - fj * W;
+      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+      double v = 0.0;
+      if (fi >= 1 && fj >= 1) {
+        dv[k] = ste[f] + ste[f - 1] + stn[f] + stn[f - W];
+        if (i >= 0 && i < m && j >= 0 && j < m && ((i + j) & 1) == 0) v = rv[k] / dv[k];
+      }
+      sz[f] = v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    if (f < F) {
+      const int fj = f / W, fi = f - fj * W;
+      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+      if (fi >= 2 && fi < W - 1 && fj >= 2 && fj < G::H - 1 && i >= 0 && i < m && j >= 0 &&
+          j < m && ((i + j) & 1) == 1)
+        sz[f] = (rv[k] + ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
+                 stn[f - W] * sz[f - W]) / dv[k];
+    }
+  }
+  __syncthreads();
+  double* zs = z + s * n;
+#pragma unroll
+  for (int c0 = 0; c0 < TX * TY; c0 += kBlock) {
+    const int c = c0 + threadIdx.x;
+    const int cj = c / TX, ci = c - cj * TX;
+    zs[(Y0 + cj) * m + X0 + ci] = sz[(cj + 3) * W + ci + 3];
+  }
+  const int mc = m / 2;
+  double* rcs = rc + s * (long long)mc * mc;
+  constexpr int HX = TX / 2, HY = TY / 2;
+  // Residual of the tile's red cells (black residuals vanish), computed over
+  // each thread's own frame cells, parked in the face array once every thread
+  // is done reading faces, then summed per 2x2 block.
+  double res[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    res[k] = 0.0;
+    if (f < F) {
+      const int fj = f / W, fi = f - fj * W;
+      if (fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY && ((fi + fj) & 1) == 0)
+        res[k] = ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
+                 stn[f - W] * sz[f - W];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    if (f < F) ste[f] = res[k];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < HX * HY; c += kBlock) {
+    const int cj = c / HX, ci = c - cj * HX;
+    const int fa = (3 + 2 * cj) * W + 3 + 2 * ci;
+    rcs[(Y0 / 2 + cj) * mc + X0 / 2 + ci] = ste[fa] + ste[fa + W + 1];
+  }
+}
+
+template <int TX, int TY>
+__global__ void __launch_bounds__(kBlock)
+k_mg_up_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
+          const double* __restrict__ r, const double* __restrict__ zpre, double* __restrict__ z,
+          const double* __restrict__ zc, double omega, const int32_t* __restrict__ active) {
+  using G = Tile<TX, TY>;
+  constexpr int W = G::W, F = G::F, K = G::K;
+  __shared__ double ste[F], stn[F], sz[F];
+  const int ntx = m / TX, tps = ntx * (m / TY);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
+  const long long s = bid / tps;
+  if (!active[s]) return;
+  const int tile = bid - (int)(s * tps);
+  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
+  const long long n = (long long)m * m;
+  const int mc = m / 2;
+  const double* Ts = T + s * 2 * n;
+  const double* tbs = tb + s * 2 * m;
+  const double* rs = r + s * n;
+  const double* zps = zpre + s * n;
+  const double* zcs = zc + s * (long long)mc * mc;
+  double rv[K], dv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    rv[k] = 0.0;
+    if (f < F) {
+      const int fj = f / W, fi = f - fj * W;
+      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+      const FrameLoad v = frame_load(Ts, tbs, m, i, j);
+      const double rr = rs[v.c];
+      const double zp = zps[v.c];
+      const double zcv = zcs[(v.jc >> 1) * mc + (v.ic >> 1)];
+      ste[f] = v.te;
+      stn[f] = v.tn;
+      rv[k] = v.in ? rr : 0.0;
+      sz[f] = v.in ? zp + omega * zcv : 0.0;
+    }
+  }
+  __syncthreads();
+  // black sweep on R1
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    dv[k] = 1.0;
+    if (f < F) {
+      const int fj = f / W, fi = f - fj * W;
+      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+      if (fi >= 1 && fj >= 1) dv[k] = ste[f] + ste[f - 1] + stn[f] + stn[f - W];
+      if (fi >= 2 && fi < W - 1 && fj >= 2 && fj < G::H - 1 && i >= 0 && i < m && j >= 0 &&
+          j < m && ((i + j) & 1) == 1)
+        sz[f] = (rv[k] + ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
+                 stn[f - W] * sz[f - W]) / dv[k];
+    }
+  }
+  __syncthreads();
+  // red sweep on the tile
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kBlock;
+    if (f < F) {
+      const int fj = f / W, fi = f - fj * W;
+      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+      if (fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY && ((i + j) & 1) == 0)
+        sz[f] = (rv[k] + ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
+                 stn[f - W] * sz[f - W]) / dv[k];
+    }
+  }
+  __syncthreads();
+  double* zs = z + s * n;
+#pragma unroll
+  for (int c0 = 0; c0 < TX * TY; c0 += kBlock) {
+    const int c = c0 + threadIdx.x;
+    const int cj = c / TX, ci = c - cj * TX;
+    zs[(Y0 + cj) * m + X0 + ci] = sz[(cj + 3) * W + ci + 3];
+  }
+}
+
 // Largest even divisor of m that is <= cap.
 static int tile_dim(int m, int cap) {
   for (int t = cap < m ? cap : m; t >= 2; --t)
@@ -214,6 +439,12 @@ static size_t frame_bytes(int tx, int ty) { return (size_t)4 * (tx + 5) * (ty + 
 
 void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const double* tb,
                     const double* r, double* z, double* rc, const int32_t* active) {
+  if (m % kTileX == 0 && m % kTileY == 0) {
+    const int nb = batch * (m / kTileX) * (m / kTileY);
+    hipLaunchKernelGGL((k_mg_down_t<kTileX, kTileY>), dim3(nb), dim3(kBlock), 0, st, m, T, tb, r,
+                       z, rc, active);
+    return;
+  }
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
   const int tps = (m / tx) * (m / ty);
   hipLaunchKernelGGL(k_mg_down, dim3(batch * tps), dim3(kBlock), frame_bytes(tx, ty), st, m, tx,
@@ -223,6 +454,12 @@ void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const dou
 void launch_mg_up(hipStream_t st, int m, int batch, const double* T, const double* tb,
                   const double* r, const double* zpre, double* z, const double* zc, double omega,
                   const int32_t* active) {
+  if (m % kTileX == 0 && m % kTileY == 0) {
+    const int nb = batch * (m / kTileX) * (m / kTileY);
+    hipLaunchKernelGGL((k_mg_up_t<kTileX, kTileY>), dim3(nb), dim3(kBlock), 0, st, m, T, tb, r,
+                       zpre, z, zc, omega, active);
+    return;
+  }
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
   const int tps = (m / tx) * (m / ty);
   hipLaunchKernelGGL(k_mg_up, dim3(batch * tps), dim3(kBlock), frame_bytes(tx, ty), st, m, tx, ty,

@@ -178,59 +178,53 @@ void launch_prolong(hipStream_t st, int m, int batch, const double* zc, double* 
 }
 
 // ------------------------------------------------------------------ coarsest grid
-// Dense Cholesky A = L L^T per sample (one thread per sample, n = m*m <= 64),
-// then the explicit inverse A^-1 = L^-T L^-1 column by column, so that each
-// application on the coarsest grid is a matrix-vector product.
-__global__ void k_dense_factor(int m, int batch, const double* __restrict__ T,
-                               const double* __restrict__ tb, double* __restrict__ work,
-                               double* __restrict__ Ainv) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// Explicit inverse of each sample's coarsest matrix (n = m*m <= 64), so that
+// every application on the coarsest grid is a matrix-vector product.  One
+// 64-thread workgroup per sample builds A in LDS and inverts it in place by
+// Gauss-Jordan elimination without pivoting (A is symmetric positive
+// definite, so every pivot is positive):
+//   for each k: a_kk <- 1, row k /= pivot; for i != k: row i -= a_ik row k,
+//   with a_ik taken before the update and column k of row i ending at -a_ik/pivot.
+__global__ void __launch_bounds__(64)
+k_dense_factor(int m, int batch, const double* __restrict__ T, const double* __restrict__ tb,
+               double* __restrict__ work, double* __restrict__ Ainv) {
+  (void)work;
+  __shared__ double A[64 * 64];
+  __shared__ double col[64];
+  const int s = blockIdx.x;
   if (s >= batch) return;
   const int n = m * m;
   const double* Ts = T + (long long)s * 2 * n;
   const double* tbs = tb + (long long)s * 2 * m;
-  double* A = work + (long long)s * n * n;
+  for (int q = threadIdx.x; q < n * n; q += 64) A[q] = 0.0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += 64) {
+    const int j = c / m, i = c - j * m;
+    const Faces f = load_faces(Ts, tbs, m, i, j);
+    A[c * n + c] = f.te + f.tw + f.tn + f.ts;
+    if (i < m - 1) A[c * n + c + 1] = A[(c + 1) * n + c] = -f.te;
+    if (j < m - 1) A[c * n + c + m] = A[(c + m) * n + c] = -f.tn;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    for (int i = threadIdx.x; i < n; i += 64) col[i] = A[i * n + k];
+    __syncthreads();
+    const double piv = col[k];
+    for (int j = threadIdx.x; j < n; j += 64) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) / piv;
+    __syncthreads();
+    for (int q = threadIdx.x; q < n * n; q += 64) {
+      const int i = q / n, j = q - i * n;
+      if (i != k) A[q] = (j == k ? 0.0 : A[q]) - col[i] * A[k * n + j];
+    }
+    __syncthreads();
+  }
   double* X = Ainv + (long long)s * n * n;
-  for (int q = 0; q < n * n; ++q) A[q] = 0.0;
-  for (int j = 0; j < m; ++j)
-    for (int i = 0; i < m; ++i) {
-      const int c = j * m + i;
-      const Faces f = load_faces(Ts, tbs, m, i, j);
-      A[c * n + c] = f.te + f.tw + f.tn + f.ts;
-      if (i < m - 1) A[(c + 1) * n + c] = -f.te;
-      if (j < m - 1) A[(c + m) * n + c] = -f.tn;
-    }
-  // in-place lower Cholesky (column-oriented), only entries with row >= col used
-  for (int c = 0; c < n; ++c) {
-    double d = A[c * n + c];
-    for (int q = 0; q < c; ++q) d -= A[c * n + q] * A[c * n + q];
-    d = sqrt(d);
-    A[c * n + c] = d;
-    for (int rr = c + 1; rr < n; ++rr) {
-      double v = A[rr * n + c];
-      for (int q = 0; q < c; ++q) v -= A[rr * n + q] * A[c * n + q];
-      A[rr * n + c] = v / d;
-    }
-  }
-  // columns of the inverse: L y = e_q, L^T x = y ; X is symmetric, stored row-major
-  for (int q = 0; q < n; ++q) {
-    for (int i = 0; i < n; ++i) {
-      double v = (i == q) ? 1.0 : 0.0;
-      for (int p = 0; p < i; ++p) v -= A[i * n + p] * X[p * n + q];
-      X[i * n + q] = v / A[i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double v = X[i * n + q];
-      for (int p = i + 1; p < n; ++p) v -= A[p * n + i] * X[p * n + q];
-      X[i * n + q] = v / A[i * n + i];
-    }
-  }
+  for (int q = threadIdx.x; q < n * n; q += 64) X[q] = A[q];
 }
 
 void launch_dense_factor(hipStream_t st, int m, int batch, const double* T, const double* tb,
                          double* work, double* Ainv) {
-  hipLaunchKernelGGL(k_dense_factor, dim3(blocks_for(batch, 64)), dim3(64), 0, st, m, batch, T,
-                     tb, work, Ainv);
+  hipLaunchKernelGGL(k_dense_factor, dim3(batch), dim3(64), 0, st, m, batch, T, tb, work, Ainv);
 }
 
 // z = A^-1 r, one thread per (sample, row).
@@ -258,10 +252,21 @@ void launch_dense_apply(hipStream_t st, int m, int batch, const double* Ainv, co
 
 // ------------------------------------------------------------------ PCG vector kernels
 // Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c.
+// Logical block ids are remapped so that each XCD (with its own L2) runs a
+// contiguous range: the rows a block reads from its neighbours' cells are then
+// in the same L2.  Partials are indexed by the logical id, so the reduction
+// order does not depend on the remap.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  const int x = bid & 7, q = bid >> 3;
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
 #define PCG_PROLOGUE                                        \
   const int bps_ = bps;                                     \
-  const long long s = blockIdx.x / bps_;                    \
-  const int blk = blockIdx.x - (int)(s * bps_);             \
+  const int lbid = xcd_block(blockIdx.x, gridDim.x);        \
+  const long long s = lbid / bps_;                          \
+  const int blk = lbid - (int)(s * bps_);                   \
   const int cell0 = blk * kCellsPerBlock + threadIdx.x;
 
 __global__ void __launch_bounds__(kBlock)
@@ -282,7 +287,7 @@ k_pcg_init(int n, const double* __restrict__ b, double* __restrict__ x, double* 
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lbid] = t;
 }
 
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
@@ -314,7 +319,7 @@ k_spmv_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lbid] = t;
 }
 
 void launch_spmv_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
@@ -345,7 +350,7 @@ k_axpy_dot(int n, double* __restrict__ x, double* __restrict__ r, const double* 
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lbid] = t;
 }
 
 void launch_axpy_dot(hipStream_t st, int n, int batch, double* x, double* r, const double* p,
@@ -371,7 +376,7 @@ k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lbid] = t;
 }
 
 void launch_dot(hipStream_t st, int n, int batch, const double* a, const double* b,
@@ -424,7 +429,7 @@ k_true_residual(int m, const double* __restrict__ T, const double* __restrict__ 
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lbid] = t;
 }
 
 void launch_true_residual(hipStream_t st, int m, int batch, const double* T, const double* tb,
