@@ -88,9 +88,9 @@ enum {
  * Random streams (Philox4x32-10, key = seed, counter = (block, sample number,
  * level, tag)): tag 0 geometry uniforms (uniform q = word q%4 of block q/4),
  * tag 1 layer constants (normals z0..z3 of block 0 by Box-Muller), tag 2
- * circulant-embedding noise (noise point q = k2*n_ce + k1 takes (z0, z1) of
- * block q/2 for even q and (z2, z3) for odd q; real part -> layer 0, imaginary
- * part -> layer 1).
+ * circulant-embedding noise (noise point (k2, k1) takes (z0, z1) of block
+ * (k2/2)*n_ce + k1 for even k2 and (z2, z3) of that block for odd k2; real
+ * part -> layer 0, imaginary part -> layer 1).
  */
 typedef struct mlmc_model {
   int32_t dim;            /* 2                                                  */

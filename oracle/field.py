@@ -17,8 +17,10 @@
        independent samples of the zero-mean field on the torus;
     6. keep the grid points [0, m)^d.
   Layers 2p and 2p+1 take Re and Im of the embedding sample of pair p
-  (noise stream tag 2 + p).  Noise point q (row-major, x1 fastest) takes
-  (z0, z1) of block q // 2 when q is even and (z2, z3) when q is odd.
+  (noise stream tag 2 + p).  Noise point (k2, k1) takes (z0, z1) of block
+  (k2 // 2) n_ce + k1 when k2 is even and (z2, z3) of that block when k2 is
+  odd (3-D: block ((k3 n_ce + k2) // 2) n_ce + k1 with the same parity rule
+  on k3 n_ce + k2).
   All layers of a correlated model share sigma^2, lambda and the norm r.
 * The composite sample is k(x_ij) = exp(mu_l + g_l(x_ij)) with l the layer
   of the cell centre (Section 2: the partition is independent of k).
@@ -114,13 +116,14 @@ def min_embedding(m, sigma2, lam, norm_r, dim=2, limit=12):
 
 def ce_noise(model, level, sample, pair, n_ce, dim):
     """Complex white noise xi on the n_ce^d frequencies (layout [..., k2, k1])."""
-    npts = n_ce ** dim
-    nblk = (npts + 1) // 2
+    rows = n_ce ** (dim - 1)              # index of the line along x1: k2 (2-D), k3 n + k2 (3-D)
+    row = np.arange(rows)[:, None]
+    k1 = np.arange(n_ce)[None, :]
+    b = (row // 2) * n_ce + k1
+    nblk = ((rows + 1) // 2) * n_ce
     blk = philox.blocks(model.seed, sample, level, philox.TAG_CE_BASE + pair, np.arange(nblk))
     z = philox.normals_of_block(blk)
-    q = np.arange(npts)
-    b = q // 2
-    even = (q % 2) == 0
+    even = (row % 2) == 0
     re = np.where(even, z[b, 0], z[b, 2])
     im = np.where(even, z[b, 1], z[b, 3])
     return (re + 1j * im).reshape((n_ce,) * dim)

@@ -5,6 +5,7 @@
 // arguments, sizes buffers and enqueues launches on the context's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -452,7 +453,8 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   TRY(ws(ctx, "s_z", batch * n, &z));
   TRY(ws(ctx, "s_p", batch * n, &pv));
   TRY(ws(ctx, "s_q", batch * n, &q));
-  TRY(ws(ctx, "s_partial", (size_t)batch * bps, &partial));
+  const int parts_max = std::max(bps, mg_tiles_per_sample(m % 2 == 0 ? m : 2));
+  TRY(ws(ctx, "s_partial", (size_t)batch * parts_max, &partial));
   zl[0] = z;
   rl[0] = r;
   for (int l = 1; l <= L; ++l) {
@@ -539,9 +541,13 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       });
     }
   };
+  // z = M r, and the partials of r^T z: rz_parts per sample in `partial`
+  int rz_parts = bps;
+  if (fused) rz_parts = l0 == 0 ? 1 : mg_tiles_per_sample(ms[0]);
   auto vcycle = [&]() {
     if (!fused) {
       vcycle_unfused(0);
+      launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
       return;
     }
     for (int l = 0; l < l0; ++l) {
@@ -551,13 +557,14 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       });
     }
     timed(ctx, "k_mg_coarse_cycle", coarse_bytes, [&] {
-      launch_mg_coarse_cycle(st, batch, ncl, cdesc, rl[l0], zl[l0], Ainv, omega, S.active);
+      launch_mg_coarse_cycle(st, batch, ncl, cdesc, rl[l0], zl[l0], Ainv, omega, S.active,
+                             l0 == 0 ? partial : nullptr);
     });
     for (int l = l0 - 1; l >= 0; --l) {
       const double cells = (double)batch * ms[l] * ms[l];
       timed(ctx, "k_mg_up", cells * kBytesUp, [&] {
         launch_mg_up(st, ms[l], batch, Tl[l], tbl[l], rl[l], zpre[l], zl[l], zl[l + 1], omega,
-                     S.active);
+                     S.active, l == 0 ? partial : nullptr);
       });
     }
   };
@@ -565,8 +572,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps);
   launch_sc_init(st, batch, partial, bps, S, status, iters, relres);
   vcycle();
-  launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
-  launch_sc_rho(st, batch, partial, bps, S, status, 1);
+  launch_sc_rho(st, batch, partial, rz_parts, S, status, 1);
   launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
   CHECK_LAUNCH();
 
@@ -588,8 +594,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       if (*hcount == 0) break;
     }
     vcycle();
-    launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
-    launch_sc_rho(st, batch, partial, bps, S, status, 0);
+    launch_sc_rho(st, batch, partial, rz_parts, S, status, 0);
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
   }
   launch_true_residual(st, m, batch, T, tb, b, p, partial, bps);

@@ -54,11 +54,13 @@ __device__ __forceinline__ double to_uniform(uint32_t x) {
   return ((double)x + 0.5) * (1.0 / 4294967296.0);
 }
 
-// Box-Muller: two standard normals from two uniforms.
+// Box-Muller: two standard normals from two uniforms.  cos and sin of 2 pi u1
+// come from sincospi(2 u1), whose argument is exact (no rounding of 2 pi u1
+// and no range reduction by pi).
 __device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
   const double r = sqrt(-2.0 * log(u0));
   double s, c;
-  sincos(6.283185307179586 * u1, &s, &c);
+  sincospi(2.0 * u1, &s, &c);
   z0 = r * c;
   z1 = r * s;
 }

@@ -10,8 +10,9 @@
 //     -> eigenvalues Lambda (real); check min >= -1e-12 max; store
 //     sqrt(max(Lambda, 0) / n^2), transposed, for pass A;
 //   pass A, one workgroup per (sample, noise column k1): Philox normals
-//     xi(k2, k1) for all k2, scaled by sqrt(Lambda / n^2), FFT along k2 in
-//     LDS, keep rows j2 < m -> uT[sample][j2][k1];
+//     xi(k2, k1) for all k2 (rows 2p and 2p+1 take the two normal pairs of
+//     block p n + k1), scaled by sqrt(Lambda / n^2), FFT along k2 in LDS,
+//     keep rows j2 < m -> uT[sample][j2][k1];
 //   pass B, one workgroup per (sample, row j2 < m): FFT of uT[sample][j2][:]
 //     along k1 in LDS, keep j1 < m; Re -> layer 0, Im -> layer 1; the layer of
 //     each centre decides k = exp(mu_l + g_l); the plain coarse companion is
@@ -212,15 +213,22 @@ k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, int m, const double* 
   const int s = blk / n;
   const uint32_t sample = (uint32_t)(first + (uint64_t)s);
   const double* sq = sqT + (long long)k1 * n;
-  for (int k2 = threadIdx.x; k2 < n; k2 += kBlock) {
-    const uint32_t q = (uint32_t)k2 * (uint32_t)n + (uint32_t)k1;
-    const U4 b = stream_block(seed, q >> 1, sample, level, kTagNoise);
+  // rows 2p and 2p+1 of this column share Philox block p n + k1
+  for (int pr = threadIdx.x; 2 * pr < n; pr += kBlock) {
+    const uint32_t blkid = (uint32_t)pr * (uint32_t)n + (uint32_t)k1;
+    const U4 b = stream_block(seed, blkid, sample, level, kTagNoise);
+    const int k2 = 2 * pr;
     double zr, zi;
-    if ((q & 1u) == 0u) box_muller(to_uniform(b.x), to_uniform(b.y), zr, zi);
-    else box_muller(to_uniform(b.z), to_uniform(b.w), zr, zi);
+    box_muller(to_uniform(b.x), to_uniform(b.y), zr, zi);
     const double a = sq[k2];
     sre[k2] = a * zr;
     sim[k2] = a * zi;
+    if (k2 + 1 < n) {
+      box_muller(to_uniform(b.z), to_uniform(b.w), zr, zi);
+      const double a1 = sq[k2 + 1];
+      sre[k2 + 1] = a1 * zr;
+      sim[k2 + 1] = a1 * zi;
+    }
   }
   __syncthreads();
   fft_line(sre, sim, tw, pl);

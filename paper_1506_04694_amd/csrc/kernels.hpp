@@ -81,13 +81,17 @@ struct CoarseDesc {
 
 void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const double* tb,
                     const double* r, double* z, double* rc, const int32_t* active);
+// With rz_partial != NULL the kernel also writes r^T z per tile:
+// rz_partial[s * mg_tiles_per_sample(m) + tile].
+int mg_tiles_per_sample(int m);
 void launch_mg_up(hipStream_t st, int m, int batch, const double* T, const double* tb,
                   const double* r, const double* zpre, double* z, const double* zc, double omega,
-                  const int32_t* active);
+                  const int32_t* active, double* rz_partial);
 size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev);
+// With rz_partial != NULL also writes r0^T z0 per sample (rz_partial[s]).
 void launch_mg_coarse_cycle(hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
                             const double* r0, double* z0, const double* Ainv, double omega,
-                            const int32_t* active);
+                            const int32_t* active, double* rz_partial);
 
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
                      double* partial, int bps);

@@ -28,6 +28,8 @@
 // Levels of 32 x 32 cells or fewer are handled by k_mg_coarse_cycle: one
 // workgroup per sample runs the remaining V-cycle entirely in LDS and applies
 // the coarsest inverse (a dense matrix-vector product).
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -154,7 +156,7 @@ __global__ void __launch_bounds__(kBlock)
 k_mg_up(int m, int tx, int ty, int tiles_per_sample, const double* __restrict__ T,
         const double* __restrict__ tb, const double* __restrict__ r,
         const double* __restrict__ zpre, double* __restrict__ z, const double* __restrict__ zc,
-        double omega, const int32_t* __restrict__ active) {
+        double omega, const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
   extern __shared__ double lds[];
   const long long s = blockIdx.x / tiles_per_sample;
   if (!active[s]) return;
@@ -197,9 +199,17 @@ k_mg_up(int m, int tx, int ty, int tiles_per_sample, const double* __restrict__ 
     if (((i + j) & 1) == 0) L.z[f] = (L.r[f] + nsum_at(L, W, f)) / diag_at(L, W, f);
   }
   __syncthreads();
+  double acc = 0.0;
   for (int c = threadIdx.x; c < tcells; c += kBlock) {
     const int cj = c / tx, ci = c - cj * tx;
-    zs[(g.Y0 + cj) * m + g.X0 + ci] = L.z[(cj + 3) * W + ci + 3];
+    const int f = (cj + 3) * W + ci + 3;
+    zs[(g.Y0 + cj) * m + g.X0 + ci] = L.z[f];
+    acc += L.r[f] * L.z[f];
+  }
+  if (rz_partial) {
+    __shared__ double red[kBlock / kWave];
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) rz_partial[blockIdx.x] = t;
   }
 }
 
@@ -232,14 +242,18 @@ __device__ __forceinline__ FrameLoad frame_load(const double* __restrict__ Ts,
 
 // ------------------------------------------------------------------ fixed-tile variants
 // Same algorithm as k_mg_down / k_mg_up for tiles of compile-time size TX x TY
-// (used when TX divides m and TY divides m).  The frame width is a constant,
-// each thread owns the frame cells f = tid + 256 k in every phase, so its
-// right-hand side and diagonal stay in registers; LDS holds the faces and z.
-// Tiles of one sample are mapped to one XCD (shared L2 for the halos).
+// (used when TX and TY divide m), organised for occupancy: each of the 512
+// threads owns the frame cells f = tid + 512 k in every phase and keeps their
+// four faces, right-hand side and z in registers; LDS holds only z, which is
+// what neighbours read.  All loads use clamped, always-valid addresses and are
+// resolved by selects, so a thread's loads are issued back to back.  Tiles of
+// one sample run on one XCD, so the halo re-reads hit that XCD's L2.
+constexpr int kMgThreads = 512;
+
 template <int TX, int TY>
 struct Tile {
   static constexpr int W = TX + 5, H = TY + 5, F = W * H;
-  static constexpr int K = (F + kBlock - 1) / kBlock;
+  static constexpr int K = (F + kMgThreads - 1) / kMgThreads;
 };
 
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
@@ -248,14 +262,41 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   return x * per + (x < rem ? x : rem) + q;
 }
 
+struct CellFaces {
+  double te, tw, tn, ts;
+  int c;      // clamped linear index of the cell in its sample
+  bool in;    // inside the domain
+};
+
+// Faces of cell (i, j): east/north from T, west/south from the neighbour's
+// east/north face or from the boundary arrays; everything 0 outside.
+__device__ __forceinline__ CellFaces cell_faces(const double* __restrict__ Ts,
+                                                const double* __restrict__ tbs, int m, int i,
+                                                int j) {
+  CellFaces v;
+  const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
+  const int iw = max(ic - 1, 0), js = max(jc - 1, 0);
+  const int n = m * m;
+  v.c = jc * m + ic;
+  v.in = i >= 0 && i < m && j >= 0 && j < m;
+  const double te = Ts[v.c], tn = Ts[n + v.c];
+  const double tw = Ts[jc * m + iw], ts = Ts[n + js * m + ic];
+  const double twb = tbs[jc], tsb = tbs[m + ic];
+  v.te = v.in ? te : 0.0;
+  v.tn = v.in ? tn : 0.0;
+  v.tw = v.in ? (i > 0 ? tw : twb) : 0.0;
+  v.ts = v.in ? (j > 0 ? ts : tsb) : 0.0;
+  return v;
+}
+
 template <int TX, int TY>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMgThreads)
 k_mg_down_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
             const double* __restrict__ r, double* __restrict__ z, double* __restrict__ rc,
             const int32_t* __restrict__ active) {
   using G = Tile<TX, TY>;
-  constexpr int W = G::W, F = G::F, K = G::K;
-  __shared__ double ste[F], stn[F], sz[F];
+  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
+  __shared__ double sz[F];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -266,98 +307,81 @@ k_mg_down_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
   const double* Ts = T + s * 2 * n;
   const double* tbs = tb + s * 2 * m;
   const double* rs = r + s * n;
-  double rv[K], dv[K];
+  CellFaces cf[K];
+  double rv[K], zv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
-    rv[k] = 0.0;
-    if (f < F) {
-      const int fj = f / W, fi = f - fj * W;
-      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-      const FrameLoad v = frame_load(Ts, tbs, m, i, j);
-      const double rr = rs[v.c];
-      ste[f] = v.te;
-      stn[f] = v.tn;
-      rv[k] = v.in ? rr : 0.0;
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    cf[k] = cell_faces(Ts, tbs, m, X0 - 3 + fi, Y0 - 3 + fj);
+    const double rr = rs[cf[k].c];
+    rv[k] = cf[k].in ? rr : 0.0;
+  }
+  // red cells of R2: z = r / D; all other cells start at 0
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+    zv[k] = (cf[k].in && fi >= 1 && fj >= 1 && ((fi + fj) & 1) == 0) ? rv[k] / d : 0.0;
+    if (f < F) sz[f] = zv[k];
+  }
+  __syncthreads();
+  // black cells of R1
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
+      const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+               cf[k].ts * sz[f - W]) / d;
+      sz[f] = zv[k];
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
-    dv[k] = 1.0;
-    if (f < F) {
-      const int fj = f / W, fi = f - fj * W;
-      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-      double v = 0.0;
-      if (fi >= 1 && fj >= 1) {
-        dv[k] = ste[f] + ste[f - 1] + stn[f] + stn[f - W];
-        if (i >= 0 && i < m && j >= 0 && j < m && ((i + j) & 1) == 0) v = rv[k] / dv[k];
-      }
-      sz[f] = v;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
-    if (f < F) {
-      const int fj = f / W, fi = f - fj * W;
-      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-      if (fi >= 2 && fi < W - 1 && fj >= 2 && fj < G::H - 1 && i >= 0 && i < m && j >= 0 &&
-          j < m && ((i + j) & 1) == 1)
-        sz[f] = (rv[k] + ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
-                 stn[f - W] * sz[f - W]) / dv[k];
-    }
-  }
-  __syncthreads();
+  // store the tile; residual of its red cells (black residuals vanish)
   double* zs = z + s * n;
-#pragma unroll
-  for (int c0 = 0; c0 < TX * TY; c0 += kBlock) {
-    const int c = c0 + threadIdx.x;
-    const int cj = c / TX, ci = c - cj * TX;
-    zs[(Y0 + cj) * m + X0 + ci] = sz[(cj + 3) * W + ci + 3];
-  }
-  const int mc = m / 2;
-  double* rcs = rc + s * (long long)mc * mc;
-  constexpr int HX = TX / 2, HY = TY / 2;
-  // Residual of the tile's red cells (black residuals vanish), computed over
-  // each thread's own frame cells, parked in the face array once every thread
-  // is done reading faces, then summed per 2x2 block.
   double res[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
     res[k] = 0.0;
-    if (f < F) {
-      const int fj = f / W, fi = f - fj * W;
-      if (fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY && ((fi + fj) & 1) == 0)
-        res[k] = ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
-                 stn[f - W] * sz[f - W];
+    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
+      zs[cf[k].c] = zv[k];
+      if (((fi + fj) & 1) == 0)
+        res[k] = cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+                 cf[k].ts * sz[f - W];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
-    if (f < F) ste[f] = res[k];
+    const int f = threadIdx.x + k * kMgThreads;
+    if (f < F) sz[f] = res[k];
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < HX * HY; c += kBlock) {
+  const int mc = m / 2;
+  double* rcs = rc + s * (long long)mc * mc;
+  constexpr int HX = TX / 2, HY = TY / 2;
+  for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
     const int cj = c / HX, ci = c - cj * HX;
     const int fa = (3 + 2 * cj) * W + 3 + 2 * ci;
-    rcs[(Y0 / 2 + cj) * mc + X0 / 2 + ci] = ste[fa] + ste[fa + W + 1];
+    rcs[(Y0 / 2 + cj) * mc + X0 / 2 + ci] = sz[fa] + sz[fa + W + 1];
   }
 }
 
 template <int TX, int TY>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMgThreads)
 k_mg_up_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
           const double* __restrict__ r, const double* __restrict__ zpre, double* __restrict__ z,
-          const double* __restrict__ zc, double omega, const int32_t* __restrict__ active) {
+          const double* __restrict__ zc, double omega, const int32_t* __restrict__ active,
+          double* __restrict__ rz_partial) {
   using G = Tile<TX, TY>;
-  constexpr int W = G::W, F = G::F, K = G::K;
-  __shared__ double ste[F], stn[F], sz[F];
+  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
+  __shared__ double sz[F];
+  __shared__ double red[kMgThreads / kWave];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -371,61 +395,72 @@ k_mg_up_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
   const double* rs = r + s * n;
   const double* zps = zpre + s * n;
   const double* zcs = zc + s * (long long)mc * mc;
-  double rv[K], dv[K];
+  CellFaces cf[K];
+  double rv[K], zv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
-    rv[k] = 0.0;
-    if (f < F) {
-      const int fj = f / W, fi = f - fj * W;
-      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-      const FrameLoad v = frame_load(Ts, tbs, m, i, j);
-      const double rr = rs[v.c];
-      const double zp = zps[v.c];
-      const double zcv = zcs[(v.jc >> 1) * mc + (v.ic >> 1)];
-      ste[f] = v.te;
-      stn[f] = v.tn;
-      rv[k] = v.in ? rr : 0.0;
-      sz[f] = v.in ? zp + omega * zcv : 0.0;
-    }
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+    cf[k] = cell_faces(Ts, tbs, m, i, j);
+    const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
+    const double rr = rs[cf[k].c], zp = zps[cf[k].c], zcv = zcs[(jc >> 1) * mc + (ic >> 1)];
+    rv[k] = cf[k].in ? rr : 0.0;
+    zv[k] = cf[k].in ? zp + omega * zcv : 0.0;
+    if (f < F) sz[f] = zv[k];
   }
   __syncthreads();
   // black sweep on R1
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
-    dv[k] = 1.0;
-    if (f < F) {
-      const int fj = f / W, fi = f - fj * W;
-      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-      if (fi >= 1 && fj >= 1) dv[k] = ste[f] + ste[f - 1] + stn[f] + stn[f - W];
-      if (fi >= 2 && fi < W - 1 && fj >= 2 && fj < G::H - 1 && i >= 0 && i < m && j >= 0 &&
-          j < m && ((i + j) & 1) == 1)
-        sz[f] = (rv[k] + ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
-                 stn[f - W] * sz[f - W]) / dv[k];
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
+      const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+               cf[k].ts * sz[f - W]) / d;
+      sz[f] = zv[k];
     }
   }
   __syncthreads();
-  // red sweep on the tile
+  // red sweep on the tile, store, r^T z
+  double* zs = z + s * n;
+  double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kBlock;
-    if (f < F) {
-      const int fj = f / W, fi = f - fj * W;
-      const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-      if (fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY && ((i + j) & 1) == 0)
-        sz[f] = (rv[k] + ste[f] * sz[f + 1] + ste[f - 1] * sz[f - 1] + stn[f] * sz[f + W] +
-                 stn[f - W] * sz[f - W]) / dv[k];
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
+      if (((fi + fj) & 1) == 0) {
+        const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+        zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+                 cf[k].ts * sz[f - W]) / d;
+      }
+      zs[cf[k].c] = zv[k];
+      acc += rv[k] * zv[k];
     }
   }
-  __syncthreads();
-  double* zs = z + s * n;
+  if (rz_partial) {
+    // fixed-order block sum over the 8 waves
+    acc = wave_sum(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
 #pragma unroll
-  for (int c0 = 0; c0 < TX * TY; c0 += kBlock) {
-    const int c = c0 + threadIdx.x;
-    const int cj = c / TX, ci = c - cj * TX;
-    zs[(Y0 + cj) * m + X0 + ci] = sz[(cj + 3) * W + ci + 3];
+      for (int w = 0; w < kMgThreads / kWave; ++w) t += red[w];
+      rz_partial[s * tps + tile] = t;
+    }
   }
+}
+
+static int g_tile_y = -1;
+static int tile_y() {
+  if (g_tile_y < 0) {
+    const char* e = getenv("MLMC_TILE_Y");
+    g_tile_y = (e && atoi(e) == 16) ? 16 : 32;
+  }
+  return g_tile_y;
 }
 
 // Largest even divisor of m that is <= cap.
@@ -439,10 +474,13 @@ static size_t frame_bytes(int tx, int ty) { return (size_t)4 * (tx + 5) * (ty + 
 
 void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const double* tb,
                     const double* r, double* z, double* rc, const int32_t* active) {
-  if (m % kTileX == 0 && m % kTileY == 0) {
-    const int nb = batch * (m / kTileX) * (m / kTileY);
-    hipLaunchKernelGGL((k_mg_down_t<kTileX, kTileY>), dim3(nb), dim3(kBlock), 0, st, m, T, tb, r,
-                       z, rc, active);
+  if (m % 64 == 0 && m % tile_y() == 0) {
+    if (tile_y() == 32)
+      hipLaunchKernelGGL((k_mg_down_t<64, 32>), dim3(batch * (m / 64) * (m / 32)),
+                         dim3(kMgThreads), 0, st, m, T, tb, r, z, rc, active);
+    else
+      hipLaunchKernelGGL((k_mg_down_t<64, 16>), dim3(batch * (m / 64) * (m / 16)),
+                         dim3(kMgThreads), 0, st, m, T, tb, r, z, rc, active);
     return;
   }
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
@@ -451,19 +489,30 @@ void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const dou
                      ty, tps, T, tb, r, z, rc, active);
 }
 
+int mg_tiles_per_sample(int m) {
+  if (m % 64 == 0 && m % tile_y() == 0) return (m / 64) * (m / tile_y());
+  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
+  return (m / tx) * (m / ty);
+}
+
 void launch_mg_up(hipStream_t st, int m, int batch, const double* T, const double* tb,
                   const double* r, const double* zpre, double* z, const double* zc, double omega,
-                  const int32_t* active) {
-  if (m % kTileX == 0 && m % kTileY == 0) {
-    const int nb = batch * (m / kTileX) * (m / kTileY);
-    hipLaunchKernelGGL((k_mg_up_t<kTileX, kTileY>), dim3(nb), dim3(kBlock), 0, st, m, T, tb, r,
-                       zpre, z, zc, omega, active);
+                  const int32_t* active, double* rz_partial) {
+  if (m % 64 == 0 && m % tile_y() == 0) {
+    if (tile_y() == 32)
+      hipLaunchKernelGGL((k_mg_up_t<64, 32>), dim3(batch * (m / 64) * (m / 32)),
+                         dim3(kMgThreads), 0, st, m, T, tb, r, zpre, z, zc, omega, active,
+                         rz_partial);
+    else
+      hipLaunchKernelGGL((k_mg_up_t<64, 16>), dim3(batch * (m / 64) * (m / 16)),
+                         dim3(kMgThreads), 0, st, m, T, tb, r, zpre, z, zc, omega, active,
+                         rz_partial);
     return;
   }
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
   const int tps = (m / tx) * (m / ty);
   hipLaunchKernelGGL(k_mg_up, dim3(batch * tps), dim3(kBlock), frame_bytes(tx, ty), st, m, tx, ty,
-                     tps, T, tb, r, zpre, z, zc, omega, active);
+                     tps, T, tb, r, zpre, z, zc, omega, active, rz_partial);
 }
 
 // ------------------------------------------------------------------ coarse cycle in LDS
@@ -498,7 +547,7 @@ __device__ void cc_sweep(double* te, double* tn, double* r, double* z, int m, in
 __global__ void __launch_bounds__(kBlock)
 k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
                   double* __restrict__ z0, const double* __restrict__ Ainv, double omega,
-                  const int32_t* __restrict__ active) {
+                  const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
   extern __shared__ double lds[];
   const int s = blockIdx.x;
   if (!active[s]) return;
@@ -591,9 +640,19 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
   // store level l0's correction
   {
     const int m = lv[0].m, P = lv[0].P, PP = P * P;
-    const double* zz = lds + lv[0].off + 3 * PP;
-    for (int c = threadIdx.x; c < m * m; c += kBlock)
-      z0[(long long)s * m * m + c] = zz[pidx(P, c % m, c / m)];
+    const double* rr = lds + lv[0].off + 2 * PP;
+    const double* zz = rr + PP;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < m * m; c += kBlock) {
+      const int f = pidx(P, c % m, c / m);
+      z0[(long long)s * m * m + c] = zz[f];
+      acc += rr[f] * zz[f];
+    }
+    if (rz_partial) {
+      __shared__ double red[kBlock / kWave];
+      const double t = block_sum(acc, red);
+      if (threadIdx.x == 0) rz_partial[s] = t;
+    }
   }
 }
 
@@ -606,10 +665,10 @@ size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev) {
 
 void launch_mg_coarse_cycle(hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
                             const double* r0, double* z0, const double* Ainv, double omega,
-                            const int32_t* active) {
+                            const int32_t* active, double* rz_partial) {
   hipLaunchKernelGGL(k_mg_coarse_cycle, dim3(batch), dim3(kBlock),
                      coarse_cycle_lds_bytes(desc, nlev), st, nlev, desc, r0, z0, Ainv, omega,
-                     active);
+                     active, rz_partial);
 }
 
 }  // namespace mlmc

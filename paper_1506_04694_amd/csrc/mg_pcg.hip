@@ -252,19 +252,9 @@ void launch_dense_apply(hipStream_t st, int m, int batch, const double* Ainv, co
 
 // ------------------------------------------------------------------ PCG vector kernels
 // Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c.
-// Logical block ids are remapped so that each XCD (with its own L2) runs a
-// contiguous range: the rows a block reads from its neighbours' cells are then
-// in the same L2.  Partials are indexed by the logical id, so the reduction
-// order does not depend on the remap.
-__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
-  const int x = bid & 7, q = bid >> 3;
-  const int per = nblocks >> 3, rem = nblocks & 7;
-  return x * per + (x < rem ? x : rem) + q;
-}
-
 #define PCG_PROLOGUE                                        \
   const int bps_ = bps;                                     \
-  const int lbid = xcd_block(blockIdx.x, gridDim.x);        \
+  const int lbid = blockIdx.x;                              \
   const long long s = lbid / bps_;                          \
   const int blk = lbid - (int)(s * bps_);                   \
   const int cell0 = blk * kCellsPerBlock + threadIdx.x;
