@@ -26,7 +26,7 @@ import workloads as W  # noqa: E402
 
 METRIC = "MLMC samples solved/s per level at 1e-10 QoI rel-err; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-DOMINANT = "rbgs_l0"
+DOMINANT = "k_mg_up"
 
 
 def parse():
@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--kernel", default=DOMINANT, help="kernel label timed for the roofline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-sample", action="store_true",
+                    help="skip timing the unbatched one-sample-per-call GPU path")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     return ap.parse_args()
 
@@ -108,6 +110,22 @@ def main():
             sums.append(s)
         return sums
 
+    def per_sample_baseline(budget_s=1.5):
+        """The same FP64 path with one sample per call (no batching), a few samples
+        per level: the plain per-sample GPU solve the batched form is compared to."""
+        out = []
+        for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+            lib.mlmc_level_run(ctx, wl.model, level, m, 10 ** 6, 1, wl.cgv, opts)  # warm
+            done, t0 = 0, time.perf_counter()
+            while time.perf_counter() - t0 < budget_s / len(wl.m_levels) and done < n:
+                lib.mlmc_level_run(ctx, wl.model, level, m, 10 ** 6 + 1 + done, 1, wl.cgv, opts)
+                done += 1
+            dt = (time.perf_counter() - t0) / done
+            out.append({"level": level, "m": m, "samples_timed": done, "ms_per_sample": 1e3 * dt,
+                        "samples_per_s": 1.0 / dt})
+        t_step = sum(n * o["ms_per_sample"] * 1e-3 for n, o in zip(wl.n_samples, out))
+        return {"value": sum(wl.n_samples) / t_step, "unit": "samples/s", "per_level": out}
+
     for w in range(args.warmup):
         step(w, False)
     torch.cuda.synchronize()
@@ -121,6 +139,7 @@ def main():
     prof = lib.mlmc_profile_read(ctx)
     lib.mlmc_profile_enable(ctx, None)
     est = lib.mlmc_estimate(sums)
+    single = per_sample_baseline() if not args.no_per_sample else None
     lib.mlmc_ctx_destroy(ctx)
 
     ms_per_step = 1e3 * elapsed / args.steps
@@ -149,7 +168,8 @@ def main():
                       "n_ce": [wl.model.n_ce[m] for m in wl.m_levels],
                       "model": "2 layers, 8-node interface, exp. covariance r=2, sigma2=1, "
                                "lambda=0.3, means 0/2"},
-           "per_level": per_level, "estimate": est, "roofline": roof}
+           "per_level": per_level, "estimate": est, "roofline": roof,
+           "per_sample_fp64_gpu": single}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)

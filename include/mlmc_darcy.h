@@ -109,6 +109,14 @@ typedef struct mlmc_model {
   uint64_t seed;
 } mlmc_model;
 
+/* Storage precision of the multigrid preconditioner (the outer CG, its
+ * residuals, dot products and the coarsest solve are always FP64). */
+enum {
+  MLMC_PREC_FP64 = 0,  /* hierarchy in FP64, FP64 arithmetic                        */
+  MLMC_PREC_FP32 = 1,  /* hierarchy in FP32, FP32 arithmetic, flexible outer CG      */
+  MLMC_PREC_BF16 = 2   /* hierarchy in bfloat16, FP32 arithmetic, flexible outer CG  */
+};
+
 /* Multigrid-preconditioned CG options (Section 3.5 uses ||r_m||/||r_0|| < 1e-10). */
 typedef struct mlmc_solver_opts {
   double tol;           /* relative residual tolerance in the 2-norm; x0 = 0        */
@@ -121,6 +129,8 @@ typedef struct mlmc_solver_opts {
   int32_t check_every;  /* iterations between host checks of the active count      */
   int32_t variant;      /* 0: fused LDS-tiled V-cycle kernels (needs nu1 = nu2 = 1,
                            else falls back to 1); 1: one launch per sweep / step     */
+  int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1   */
+  int32_t reserved;
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */

@@ -25,6 +25,7 @@ MLMC_OK, MLMC_EINVAL, MLMC_ENOMEM, MLMC_EDEVICE, MLMC_EBUSY, MLMC_ENOCONV, MLMC_
 STATUS_NAMES = {0: "MLMC_OK", 1: "MLMC_EINVAL", 2: "MLMC_ENOMEM", 3: "MLMC_EDEVICE",
                 4: "MLMC_EBUSY", 5: "MLMC_ENOCONV", 6: "MLMC_EEMBED"}
 MLMC_SAMPLE_OK, MLMC_SAMPLE_NOCONV, MLMC_SAMPLE_BREAKDOWN = 0, 1, 2
+MLMC_PREC_FP64, MLMC_PREC_FP32, MLMC_PREC_BF16 = 0, 1, 2
 
 EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_last_error",
             "mlmc_solver_opts_default", "mlmc_ce_min_embedding", "mlmc_sample_field",
@@ -46,7 +47,8 @@ class mlmc_solver_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("omega", ctypes.c_double),
                 ("maxit", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
                 ("coarse_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("variant", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class mlmc_level_sums(ctypes.Structure):

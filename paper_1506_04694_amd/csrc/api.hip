@@ -247,6 +247,8 @@ mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
     return fail(ctx, MLMC_EINVAL, "nu1 == nu2 >= 1 is required for a symmetric preconditioner");
   if (o->coarse_max < 1) return fail(ctx, MLMC_EINVAL, "coarse_max must be >= 1");
   if (!(o->omega > 0.0)) return fail(ctx, MLMC_EINVAL, "omega must be positive");
+  if (o->precision < MLMC_PREC_FP64 || o->precision > MLMC_PREC_BF16)
+    return fail(ctx, MLMC_EINVAL, "unknown precision");
   return MLMC_OK;
 }
 
@@ -259,8 +261,6 @@ constexpr double kBytesSpmv = 32.0;       // T (16) + p (8) + q write (8)
 constexpr double kBytesAxpy = 48.0;       // x, r, p, q read + x, r write
 constexpr double kBytesResRes = 34.0;     // T 16 + z 8 + r 8 + rc write 2
 constexpr double kBytesProlong = 18.0;    // z read + write 16 + zc 2
-constexpr double kBytesDown = 34.0;       // T 16 + r 8 + z write 8 + coarse r write 2
-constexpr double kBytesUp = 42.0;         // T 16 + r 8 + z_pre 8 + z_c 2 + z write 8
 
 }  // namespace
 
@@ -443,31 +443,39 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
                                       " > 8: m must be c * 2^k with c <= 8");
   const long long n = (long long)m * m;
   const int bps = blocks_per_sample(n);
+  const int prec = opts->precision;
+  const bool fused = opts->variant == 0 && opts->nu1 == 1;
+  if (prec != MLMC_PREC_FP64 && !fused)
+    return fail(ctx, MLMC_EINVAL, "reduced-precision multigrid needs variant 0 and nu1 = nu2 = 1");
+  const bool flexible = prec != MLMC_PREC_FP64;
+  const size_t eb = prec_bytes(prec);
 
+  // FP64 hierarchy (Galerkin coarsening, coarsest inverse) ...
   std::vector<const double*> Tl(L + 1), tbl(L + 1);
   std::vector<double*> zl(L + 1), rl(L + 1);
   Tl[0] = T;
   tbl[0] = tb;
-  double *r, *z, *pv, *q, *partial;
+  double *r, *z, *pv, *q, *partial, *partial2 = nullptr;
   TRY(ws(ctx, "s_r", batch * n, &r));
   TRY(ws(ctx, "s_z", batch * n, &z));
   TRY(ws(ctx, "s_p", batch * n, &pv));
   TRY(ws(ctx, "s_q", batch * n, &q));
   const int parts_max = std::max(bps, mg_tiles_per_sample(m % 2 == 0 ? m : 2));
   TRY(ws(ctx, "s_partial", (size_t)batch * parts_max, &partial));
+  if (flexible) TRY(ws(ctx, "s_partial2", (size_t)batch * bps, &partial2));
   zl[0] = z;
   rl[0] = r;
   for (int l = 1; l <= L; ++l) {
     const long long nl = (long long)ms[l] * ms[l];
-    double *Tc, *tbc, *zc, *rc;
+    double *Tc, *tbc;
     TRY(ws(ctx, lv("s_T", l), batch * 2 * nl, &Tc));
     TRY(ws(ctx, lv("s_tb", l), (size_t)batch * 2 * ms[l], &tbc));
-    TRY(ws(ctx, lv("s_zl", l), batch * nl, &zc));
-    TRY(ws(ctx, lv("s_rl", l), batch * nl, &rc));
+    if (!fused || prec == MLMC_PREC_FP64) {
+      TRY(ws(ctx, lv("s_zl", l), batch * nl, &zl[l]));
+      TRY(ws(ctx, lv("s_rl", l), batch * nl, &rl[l]));
+    }
     Tl[l] = Tc;
     tbl[l] = tbc;
-    zl[l] = zc;
-    rl[l] = rc;
     launch_coarsen(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tc, tbc);
   }
   const long long nc = (long long)ms[L] * ms[L];
@@ -475,6 +483,37 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   TRY(ws(ctx, "s_chol", batch * nc * nc, &work));
   TRY(ws(ctx, "s_ainv", batch * nc * nc, &Ainv));
   launch_dense_factor(st, ms[L], batch, Tl[L], tbl[L], work, Ainv);
+
+  // ... and, for reduced precision, its copy in the storage type.  Vectors of
+  // the fused cycle below the finest level (z_l, r_l, z_pre) use that type.
+  std::vector<const void*> Ts(L + 1), tbs(L + 1);
+  std::vector<void*> zs(L + 1), rs(L + 1), zpre(L + 1, nullptr);
+  zs[0] = z;
+  rs[0] = r;
+  for (int l = 0; l <= L; ++l) {
+    const long long nl = (long long)ms[l] * ms[l];
+    if (prec == MLMC_PREC_FP64) {
+      Ts[l] = Tl[l];
+      tbs[l] = tbl[l];
+    } else {
+      void *Tc, *tbc;
+      TRY(ws_get(ctx, lv("s_Tlo", l), batch * 2 * nl * eb + 256, &Tc));
+      TRY(ws_get(ctx, lv("s_tblo", l), (size_t)batch * 2 * ms[l] * eb + 256, &tbc));
+      launch_convert(st, prec, batch * 2 * nl, Tl[l], Tc);
+      launch_convert(st, prec, (long long)batch * 2 * ms[l], tbl[l], tbc);
+      Ts[l] = Tc;
+      tbs[l] = tbc;
+    }
+    if (l >= 1) {
+      if (prec == MLMC_PREC_FP64) {
+        zs[l] = zl[l];
+        rs[l] = rl[l];
+      } else {
+        TRY(ws_get(ctx, lv("s_zlo", l), batch * nl * eb + 256, &zs[l]));
+        TRY(ws_get(ctx, lv("s_rlo", l), batch * nl * eb + 256, &rs[l]));
+      }
+    }
+  }
 
   SolverState S;
   TRY(ws(ctx, "s_r0", batch, &S.r0sq));
@@ -488,27 +527,29 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   const int nu = opts->nu1;
   const double omega = opts->omega;
   const double cells0 = (double)batch * n;
-  const bool fused = opts->variant == 0 && nu == 1;
 
   // Fused V(1,1): tiled down/up kernels above level l0, one workgroup per
   // sample for levels l0..L (sizes <= kCoarseCycleMax).
   int l0 = L;
-  std::vector<double*> zpre(L + 1, nullptr);
   CoarseDesc cdesc{};
   if (fused) {
     l0 = 0;
     while (l0 < L && (ms[l0] > kCoarseCycleMax || L - l0 + 1 > kMaxCoarseLevels)) ++l0;
-    for (int l = 0; l < l0; ++l) TRY(ws(ctx, lv("s_zpre", l), batch * (long long)ms[l] * ms[l], &zpre[l]));
-    for (int q = 0; q + l0 <= L; ++q) {
-      cdesc.m[q] = ms[l0 + q];
-      cdesc.T[q] = Tl[l0 + q];
-      cdesc.tb[q] = tbl[l0 + q];
+    for (int l = 0; l < l0; ++l)
+      TRY(ws_get(ctx, lv("s_zpre", l), batch * (size_t)ms[l] * ms[l] * eb + 256, &zpre[l]));
+    for (int q2 = 0; q2 + l0 <= L; ++q2) {
+      cdesc.m[q2] = ms[l0 + q2];
+      cdesc.T[q2] = Ts[l0 + q2];
+      cdesc.tb[q2] = tbs[l0 + q2];
     }
   }
   const int ncl = L - l0 + 1;
+  // algorithmic bytes of the launches (for mlmc_profile_*)
+  const double ebd = (double)eb;
   double coarse_bytes = 0.0;
-  for (int l = l0; l <= L; ++l) coarse_bytes += 16.0 * ms[l] * ms[l];
-  coarse_bytes = batch * (coarse_bytes + 16.0 * ms[l0] * ms[l0] + 8.0 * nc * nc);
+  for (int l = l0; l <= L; ++l) coarse_bytes += 2.0 * ebd * ms[l] * ms[l];
+  coarse_bytes = batch * (coarse_bytes + (l0 == 0 ? 16.0 : 2.0 * ebd) * ms[l0] * ms[l0] +
+                          8.0 * nc * nc);
 
   std::function<void(int)> vcycle_unfused = [&](int l) {
     if (l == L) {
@@ -552,19 +593,24 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     }
     for (int l = 0; l < l0; ++l) {
       const double cells = (double)batch * ms[l] * ms[l];
-      timed(ctx, "k_mg_down", cells * kBytesDown, [&] {
-        launch_mg_down(st, ms[l], batch, Tl[l], tbl[l], rl[l], zpre[l], rl[l + 1], S.active);
+      // T 2 words, r (FP64 on the finest level), z_pre, coarse r (1/4 word)
+      const double by = cells * (ebd * 3.25 + (l == 0 ? 8.0 : ebd));
+      timed(ctx, "k_mg_down", by, [&] {
+        launch_mg_down(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], rs[l + 1],
+                       S.active);
       });
     }
     timed(ctx, "k_mg_coarse_cycle", coarse_bytes, [&] {
-      launch_mg_coarse_cycle(st, batch, ncl, cdesc, rl[l0], zl[l0], Ainv, omega, S.active,
-                             l0 == 0 ? partial : nullptr);
+      launch_mg_coarse_cycle(st, prec, l0 == 0, batch, ncl, cdesc, rs[l0], zs[l0], Ainv, omega,
+                             S.active, l0 == 0 ? partial : nullptr);
     });
     for (int l = l0 - 1; l >= 0; --l) {
       const double cells = (double)batch * ms[l] * ms[l];
-      timed(ctx, "k_mg_up", cells * kBytesUp, [&] {
-        launch_mg_up(st, ms[l], batch, Tl[l], tbl[l], rl[l], zpre[l], zl[l], zl[l + 1], omega,
-                     S.active, l == 0 ? partial : nullptr);
+      // T 2 words, r and z (FP64 on the finest level), z_pre, coarse z (1/4 word)
+      const double by = cells * (ebd * 3.25 + (l == 0 ? 16.0 : 2.0 * ebd));
+      timed(ctx, "k_mg_up", by, [&] {
+        launch_mg_up(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], zs[l],
+                     zs[l + 1], omega, S.active, l == 0 ? partial : nullptr);
       });
     }
   };
@@ -572,7 +618,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps);
   launch_sc_init(st, batch, partial, bps, S, status, iters, relres);
   vcycle();
-  launch_sc_rho(st, batch, partial, rz_parts, S, status, 1);
+  launch_sc_rho(st, batch, partial, rz_parts, S, status, 1, nullptr, 0);
   launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
   CHECK_LAUNCH();
 
@@ -583,8 +629,9 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       launch_spmv_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
     });
     launch_sc_alpha(st, batch, partial, bps, S, status);
-    timed(ctx, "k_axpy_dot", cells0 * kBytesAxpy, [&] {
-      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active);
+    timed(ctx, "k_axpy_dot", cells0 * (kBytesAxpy + (flexible ? 8.0 : 0.0)), [&] {
+      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,
+                      flexible ? z : nullptr, partial2);
     });
     launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
     CHECK_LAUNCH();
@@ -594,7 +641,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       if (*hcount == 0) break;
     }
     vcycle();
-    launch_sc_rho(st, batch, partial, rz_parts, S, status, 0);
+    launch_sc_rho(st, batch, partial, rz_parts, S, status, 0, partial2, bps);
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
   }
   launch_true_residual(st, m, batch, T, tb, b, p, partial, bps);

@@ -14,6 +14,11 @@ constexpr int kCellsPerThread = 4;   // cells per thread in per-sample vector ke
 constexpr int kCellsPerBlock = kBlock * kCellsPerThread;
 constexpr int kWave = 64;
 
+// bfloat16 storage (the upper half of an FP32 value); arithmetic is done in FP32.
+struct bf16_t {
+  uint16_t bits;
+};
+
 // Per-sample random parameters: [0..7] interface data, [8..11] log-k layer
 // constants (piecewise constant layers), [12..15] unused.
 constexpr int kParamStride = 16;

@@ -75,32 +75,36 @@ constexpr int kMaxCoarseLevels = 8;
 
 struct CoarseDesc {
   int m[kMaxCoarseLevels];
-  const double* T[kMaxCoarseLevels];
-  const double* tb[kMaxCoarseLevels];
+  const void* T[kMaxCoarseLevels];    // storage type of the hierarchy
+  const void* tb[kMaxCoarseLevels];
 };
 
-void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                    const double* r, double* z, double* rc, const int32_t* active);
-// With rz_partial != NULL the kernel also writes r^T z per tile:
-// rz_partial[s * mg_tiles_per_sample(m) + tile].
+// prec: MLMC_PREC_* storage of the hierarchy (T, tb, z_pre, z and r below the
+// finest level).  top: the level is the finest one, whose r and z are FP64.
+// With rz_partial != NULL (top only) the up kernel writes r^T z per tile:
+// rz_partial[s * mg_tiles_per_sample(m) + tile]; the coarse cycle per sample.
 int mg_tiles_per_sample(int m);
-void launch_mg_up(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                  const double* r, const double* zpre, double* z, const double* zc, double omega,
-                  const int32_t* active, double* rz_partial);
+size_t prec_bytes(int prec);
+void launch_mg_down(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+                    const void* tb, const void* r, void* z, void* rc, const int32_t* active);
+void launch_mg_up(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+                  const void* tb, const void* r, const void* zpre, void* z, const void* zc,
+                  double omega, const int32_t* active, double* rz_partial);
 size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev);
-// With rz_partial != NULL also writes r0^T z0 per sample (rz_partial[s]).
-void launch_mg_coarse_cycle(hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
-                            const double* r0, double* z0, const double* Ainv, double omega,
-                            const int32_t* active, double* rz_partial);
+void launch_mg_coarse_cycle(hipStream_t st, int prec, bool top, int batch, int nlev,
+                            const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
+                            double omega, const int32_t* active, double* rz_partial);
+void launch_convert(hipStream_t st, int prec, long long count, const double* x, void* y);
 
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
                      double* partial, int bps);
 void launch_spmv_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                      const double* p, double* q, double* partial, int bps,
                      const int32_t* active);
+// partial = sum r_new^2; with zold != NULL also partial2 = sum r_new . zold
 void launch_axpy_dot(hipStream_t st, int n, int batch, double* x, double* r, const double* p,
                      const double* q, const double* alpha, double* partial, int bps,
-                     const int32_t* active);
+                     const int32_t* active, const double* zold, double* partial2);
 void launch_dot(hipStream_t st, int n, int batch, const double* a, const double* b,
                 double* partial, int bps, const int32_t* active);
 void launch_pupdate(hipStream_t st, int n, int batch, double* p, const double* z,
@@ -110,8 +114,11 @@ void launch_true_residual(hipStream_t st, int m, int batch, const double* T, con
 
 void launch_sc_init(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
                     int32_t* status, int32_t* iters, double* relres);
-void launch_sc_rho(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
-                   int32_t* status, int first);
+// beta = rho_new / rho (standard) or (rho_new - r_new.z_old) / rho (flexible,
+// partial2 != NULL: Polak-Ribiere form, for a preconditioner that is not
+// exactly symmetric, e.g. one applied in reduced precision)
+void launch_sc_rho(hipStream_t st, int batch, const double* partial, int nparts, SolverState s,
+                   int32_t* status, int first, const double* partial2, int nparts2);
 void launch_sc_alpha(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
                      int32_t* status);
 void launch_sc_conv(hipStream_t st, int batch, const double* partial, int bps, SolverState s,

@@ -19,22 +19,286 @@
 //   result from one buffer and writes the final z to another, because its halo
 //   cells belong to tiles that other workgroups update in the same launch.
 //
-// Tiles are tx x ty cells (even, dividing m); the LDS frame starts three cells
-// below/left of the tile and spans (tx + 5) x (ty + 5) cells.  Outside the
-// domain z = 0 and faces are 0, except that the frame holds the west boundary
-// face in column i = -1 and the south boundary face in row j = -1, so every
-// cell's diagonal is Te(i) + Te(i-1) + Tn(j) + Tn(j-1) without branches.
+// Precision: every kernel is a template on the storage type S of the
+// multigrid hierarchy (operators T, intermediate z, restricted residuals):
+// double (FP64 arithmetic), float or bf16 (FP32 arithmetic).  On the finest
+// level (TOP) the residual r read and the correction z written are FP64, as is
+// the r^T z partial sum; the coarsest-grid solve runs in FP64 in any case.
 //
 // Levels of 32 x 32 cells or fewer are handled by k_mg_coarse_cycle: one
 // workgroup per sample runs the remaining V-cycle entirely in LDS and applies
 // the coarsest inverse (a dense matrix-vector product).
-#include <cstdlib>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace mlmc {
 
+// ------------------------------------------------------------------ storage types
+template <class S>
+struct Prec;
+template <>
+struct Prec<double> {
+  using C = double;
+  __device__ static __forceinline__ double ld(const double* p, long long i) { return p[i]; }
+  __device__ static __forceinline__ void st(double* p, long long i, double v) { p[i] = v; }
+};
+template <>
+struct Prec<float> {
+  using C = float;
+  __device__ static __forceinline__ float ld(const float* p, long long i) { return p[i]; }
+  __device__ static __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
+};
+template <>
+struct Prec<bf16_t> {
+  using C = float;
+  __device__ static __forceinline__ float ld(const bf16_t* p, long long i) {
+    return __uint_as_float((uint32_t)p[i].bits << 16);
+  }
+  // round to nearest, ties to even
+  __device__ static __forceinline__ void st(bf16_t* p, long long i, float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    p[i].bits = (uint16_t)(u >> 16);
+  }
+};
+
+// Type of the finest-level residual / correction: FP64; coarser levels: S.
+template <class S, bool TOP>
+using VecT = typename std::conditional<TOP, double, S>::type;
+
+template <class V>
+__device__ __forceinline__ typename Prec<V>::C ldv(const V* p, long long i) {
+  return Prec<V>::ld(p, i);
+}
+
+// ------------------------------------------------------------------ fixed-tile kernels
+// Tiles of compile-time size TX x TY (used when TX and TY divide m).  Each of
+// the 512 threads owns the frame cells f = tid + 512 k in every phase and
+// keeps their four faces, right-hand side and z in registers; LDS holds only
+// z, which is what neighbours read.  All loads use clamped, always-valid
+// addresses and are resolved by selects, so a thread's loads are issued back
+// to back.  Tiles of one sample run on one XCD, so the halo re-reads hit that
+// XCD's L2.  The frame starts three cells below/left of the tile and spans
+// (TX + 5) x (TY + 5) cells.
+constexpr int kMgThreads = 512;
+
+template <int TX, int TY>
+struct Tile {
+  static constexpr int W = TX + 5, H = TY + 5, F = W * H;
+  static constexpr int K = (F + kMgThreads - 1) / kMgThreads;
+};
+
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int x = bid & 7, q = bid >> 3;
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+template <class C>
+struct CellFaces {
+  C te, tw, tn, ts;
+  int c;    // clamped linear index of the cell in its sample
+  bool in;  // inside the domain
+};
+
+// Faces of cell (i, j): east/north from T, west/south from the neighbour's
+// east/north face or from the boundary arrays; everything 0 outside.
+template <class S>
+__device__ __forceinline__ CellFaces<typename Prec<S>::C> cell_faces(const S* __restrict__ Ts,
+                                                                     const S* __restrict__ tbs,
+                                                                     int m, int i, int j) {
+  using C = typename Prec<S>::C;
+  CellFaces<C> v;
+  const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
+  const int iw = max(ic - 1, 0), js = max(jc - 1, 0);
+  const int n = m * m;
+  v.c = jc * m + ic;
+  v.in = i >= 0 && i < m && j >= 0 && j < m;
+  const C te = ldv(Ts, v.c), tn = ldv(Ts, n + v.c);
+  const C tw = ldv(Ts, jc * m + iw), ts = ldv(Ts, n + js * m + ic);
+  const C twb = ldv(tbs, jc), tsb = ldv(tbs, m + ic);
+  v.te = v.in ? te : C(0);
+  v.tn = v.in ? tn : C(0);
+  v.tw = v.in ? (i > 0 ? tw : twb) : C(0);
+  v.ts = v.in ? (j > 0 ? ts : tsb) : C(0);
+  return v;
+}
+
+template <int TX, int TY, class S, bool TOP>
+__global__ void __launch_bounds__(kMgThreads)
+k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
+            const VecT<S, TOP>* __restrict__ r, S* __restrict__ z, S* __restrict__ rc,
+            const int32_t* __restrict__ active) {
+  using C = typename Prec<S>::C;
+  using G = Tile<TX, TY>;
+  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
+  __shared__ C sz[F];
+  const int ntx = m / TX, tps = ntx * (m / TY);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
+  const long long s = bid / tps;
+  if (!active[s]) return;
+  const int tile = bid - (int)(s * tps);
+  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
+  const long long n = (long long)m * m;
+  const S* Ts = T + s * 2 * n;
+  const S* tbs = tb + s * 2 * m;
+  const VecT<S, TOP>* rs = r + s * n;
+  CellFaces<C> cf[K];
+  C rv[K], zv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    cf[k] = cell_faces(Ts, tbs, m, X0 - 3 + fi, Y0 - 3 + fj);
+    const C rr = (C)ldv(rs, cf[k].c);
+    rv[k] = cf[k].in ? rr : C(0);
+  }
+  // red cells of R2: z = r / D; all other cells start at 0
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+    zv[k] = (cf[k].in && fi >= 1 && fj >= 1 && ((fi + fj) & 1) == 0) ? rv[k] / d : C(0);
+    if (f < F) sz[f] = zv[k];
+  }
+  __syncthreads();
+  // black cells of R1
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
+      const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+               cf[k].ts * sz[f - W]) / d;
+      sz[f] = zv[k];
+    }
+  }
+  __syncthreads();
+  // store the tile; residual of its red cells (black residuals vanish)
+  S* zs = z + s * n;
+  C res[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    res[k] = C(0);
+    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
+      Prec<S>::st(zs, cf[k].c, zv[k]);
+      if (((fi + fj) & 1) == 0)
+        res[k] = cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+                 cf[k].ts * sz[f - W];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    if (f < F) sz[f] = res[k];
+  }
+  __syncthreads();
+  const int mc = m / 2;
+  S* rcs = rc + s * (long long)mc * mc;
+  constexpr int HX = TX / 2, HY = TY / 2;
+  for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
+    const int cj = c / HX, ci = c - cj * HX;
+    const int fa = (3 + 2 * cj) * W + 3 + 2 * ci;
+    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sz[fa] + sz[fa + W + 1]);
+  }
+}
+
+template <int TX, int TY, class S, bool TOP>
+__global__ void __launch_bounds__(kMgThreads)
+k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
+          const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre,
+          VecT<S, TOP>* __restrict__ z, const S* __restrict__ zc, double omega,
+          const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
+  using C = typename Prec<S>::C;
+  using G = Tile<TX, TY>;
+  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
+  __shared__ C sz[F];
+  __shared__ double red[kMgThreads / kWave];
+  const int ntx = m / TX, tps = ntx * (m / TY);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
+  const long long s = bid / tps;
+  if (!active[s]) return;
+  const int tile = bid - (int)(s * tps);
+  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
+  const long long n = (long long)m * m;
+  const int mc = m / 2;
+  const S* Ts = T + s * 2 * n;
+  const S* tbs = tb + s * 2 * m;
+  const VecT<S, TOP>* rs = r + s * n;
+  const S* zps = zpre + s * n;
+  const S* zcs = zc + s * (long long)mc * mc;
+  const C om = (C)omega;
+  CellFaces<C> cf[K];
+  C rv[K], zv[K];
+  double rd[K];  // FP64 residual for the r^T z sum (finest level only)
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
+    cf[k] = cell_faces(Ts, tbs, m, i, j);
+    const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
+    const double rr = (double)ldv(rs, cf[k].c);
+    const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
+    rd[k] = cf[k].in ? rr : 0.0;
+    rv[k] = (C)rd[k];
+    zv[k] = cf[k].in ? zp + om * zcv : C(0);
+    if (f < F) sz[f] = zv[k];
+  }
+  __syncthreads();
+  // black sweep on R1
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
+      const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+               cf[k].ts * sz[f - W]) / d;
+      sz[f] = zv[k];
+    }
+  }
+  __syncthreads();
+  // red sweep on the tile, store, r^T z
+  VecT<S, TOP>* zs = z + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
+      if (((fi + fj) & 1) == 0) {
+        const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+        zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+                 cf[k].ts * sz[f - W]) / d;
+      }
+      Prec<VecT<S, TOP>>::st(zs, cf[k].c, zv[k]);
+      if (TOP) acc += rd[k] * (double)zv[k];
+    }
+  }
+  if (TOP && rz_partial) {
+    acc = wave_sum(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kMgThreads / kWave; ++w) t += red[w];
+      rz_partial[s * tps + tile] = t;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ runtime-tile kernels
+// Same algorithm for sizes the fixed tiles do not divide (tx, ty: even
+// divisors of m), 256 threads, all four frame arrays in LDS.
 struct FrameGeom {
   int m, tx, ty, W, H;  // level size, tile size, frame width/height
   int X0, Y0;           // tile origin (global cell indices)
@@ -60,71 +324,78 @@ __device__ __forceinline__ FrameGeom frame_of(int m, int tx, int ty, int tile) {
 
 // Face of cell (i, j) along x1 in the extended sense: i = -1 is the west
 // boundary face of row j; faces outside the domain are 0.
-__device__ __forceinline__ double load_te(const double* Ts, const double* tbs, int m, int i,
-                                          int j) {
-  if (j < 0 || j >= m) return 0.0;
-  if (i == -1) return tbs[j];
-  if (i < 0 || i >= m) return 0.0;
-  return Ts[j * m + i];
+template <class S>
+__device__ __forceinline__ typename Prec<S>::C load_te(const S* Ts, const S* tbs, int m, int i,
+                                                       int j) {
+  using C = typename Prec<S>::C;
+  if (j < 0 || j >= m) return C(0);
+  if (i == -1) return ldv(tbs, j);
+  if (i < 0 || i >= m) return C(0);
+  return ldv(Ts, j * m + i);
 }
 
-__device__ __forceinline__ double load_tn(const double* Ts, const double* tbs, int m, int i,
-                                          int j) {
-  if (i < 0 || i >= m) return 0.0;
-  if (j == -1) return tbs[m + i];
-  if (j < 0 || j >= m) return 0.0;
-  return Ts[m * m + j * m + i];
+template <class S>
+__device__ __forceinline__ typename Prec<S>::C load_tn(const S* Ts, const S* tbs, int m, int i,
+                                                       int j) {
+  using C = typename Prec<S>::C;
+  if (i < 0 || i >= m) return C(0);
+  if (j == -1) return ldv(tbs, m + i);
+  if (j < 0 || j >= m) return C(0);
+  return ldv(Ts, m * m + j * m + i);
 }
 
+template <class C>
 struct Lds {
-  double* te;
-  double* tn;
-  double* r;
-  double* z;
+  C* te;
+  C* tn;
+  C* r;
+  C* z;
 };
 
-__device__ __forceinline__ double diag_at(const Lds& s, int W, int f) {
+template <class C>
+__device__ __forceinline__ C diag_at(const Lds<C>& s, int W, int f) {
   return s.te[f] + s.te[f - 1] + s.tn[f] + s.tn[f - W];
 }
 
-__device__ __forceinline__ double nsum_at(const Lds& s, int W, int f) {
+template <class C>
+__device__ __forceinline__ C nsum_at(const Lds<C>& s, int W, int f) {
   return s.te[f] * s.z[f + 1] + s.te[f - 1] * s.z[f - 1] + s.tn[f] * s.z[f + W] +
          s.tn[f - W] * s.z[f - W];
 }
 
-// ------------------------------------------------------------------ down
+template <class S, bool TOP>
 __global__ void __launch_bounds__(kBlock)
-k_mg_down(int m, int tx, int ty, int tiles_per_sample, const double* __restrict__ T,
-          const double* __restrict__ tb, const double* __restrict__ r, double* __restrict__ z,
-          double* __restrict__ rc, const int32_t* __restrict__ active) {
-  extern __shared__ double lds[];
+k_mg_down(int m, int tx, int ty, int tiles_per_sample, const S* __restrict__ T,
+          const S* __restrict__ tb, const VecT<S, TOP>* __restrict__ r, S* __restrict__ z,
+          S* __restrict__ rc, const int32_t* __restrict__ active) {
+  using C = typename Prec<S>::C;
+  extern __shared__ double lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
   const long long s = blockIdx.x / tiles_per_sample;
   if (!active[s]) return;
   const FrameGeom g = frame_of(m, tx, ty, blockIdx.x - (int)(s * tiles_per_sample));
   const int W = g.W, H = g.H, F = W * H;
-  Lds L{lds, lds + F, lds + 2 * F, lds + 3 * F};
+  Lds<C> L{lds, lds + F, lds + 2 * F, lds + 3 * F};
   const long long n = (long long)m * m;
-  const double* Ts = T + s * 2 * n;
-  const double* tbs = tb + s * 2 * m;
-  const double* rs = r + s * n;
+  const S* Ts = T + s * 2 * n;
+  const S* tbs = tb + s * 2 * m;
+  const VecT<S, TOP>* rs = r + s * n;
   for (int f = threadIdx.x; f < F; f += kBlock) {
     const int fj = f / W, fi = f - fj * W;
     const int i = g.gi(fi), j = g.gj(fj);
     L.te[f] = load_te(Ts, tbs, m, i, j);
     L.tn[f] = load_tn(Ts, tbs, m, i, j);
-    L.r[f] = g.inside(i, j) ? rs[j * m + i] : 0.0;
+    L.r[f] = g.inside(i, j) ? (C)ldv(rs, j * m + i) : C(0);
   }
   __syncthreads();
-  // red cells of R2 (frame [1, W) x [1, H)): z = r / D; everything else 0
   for (int f = threadIdx.x; f < F; f += kBlock) {
     const int fj = f / W, fi = f - fj * W;
     const int i = g.gi(fi), j = g.gj(fj);
-    double v = 0.0;
+    C v = C(0);
     if (fi >= 1 && fj >= 1 && g.inside(i, j) && ((i + j) & 1) == 0) v = L.r[f] / diag_at(L, W, f);
     L.z[f] = v;
   }
   __syncthreads();
-  // black cells of R1 (frame [2, W-1) x [2, H-1))
   for (int f = threadIdx.x; f < F; f += kBlock) {
     const int fj = f / W, fi = f - fj * W;
     if (fi < 2 || fi >= W - 1 || fj < 2 || fj >= H - 1) continue;
@@ -133,55 +404,56 @@ k_mg_down(int m, int tx, int ty, int tiles_per_sample, const double* __restrict_
     L.z[f] = (L.r[f] + nsum_at(L, W, f)) / diag_at(L, W, f);
   }
   __syncthreads();
-  double* zs = z + s * n;
+  S* zs = z + s * n;
   const int tcells = tx * ty;
   for (int c = threadIdx.x; c < tcells; c += kBlock) {
     const int cj = c / tx, ci = c - cj * tx;
-    zs[(g.Y0 + cj) * m + g.X0 + ci] = L.z[(cj + 3) * W + ci + 3];
+    Prec<S>::st(zs, (g.Y0 + cj) * m + g.X0 + ci, L.z[(cj + 3) * W + ci + 3]);
   }
-  // restriction: sum of N(z_black) over the two red cells of each 2x2 block
   const int mc = m / 2, hx = tx / 2, hy = ty / 2;
-  double* rcs = rc + s * (long long)mc * mc;
+  S* rcs = rc + s * (long long)mc * mc;
   for (int c = threadIdx.x; c < hx * hy; c += kBlock) {
     const int cj = c / hx, ci = c - cj * hx;
-    const int fi0 = 3 + 2 * ci, fj0 = 3 + 2 * cj;     // frame index of the block's (0,0) cell
-    // global (X0 + 2ci, Y0 + 2cj) has even i + j (X0, Y0 even): red cells are (0,0) and (1,1)
+    const int fi0 = 3 + 2 * ci, fj0 = 3 + 2 * cj;
+    // (X0 + 2ci, Y0 + 2cj) has even i + j: the block's red cells are (0,0) and (1,1)
     const int fa = fj0 * W + fi0, fb = (fj0 + 1) * W + fi0 + 1;
-    rcs[(g.Y0 / 2 + cj) * mc + g.X0 / 2 + ci] = nsum_at(L, W, fa) + nsum_at(L, W, fb);
+    Prec<S>::st(rcs, (g.Y0 / 2 + cj) * mc + g.X0 / 2 + ci, nsum_at(L, W, fa) + nsum_at(L, W, fb));
   }
 }
 
-// ------------------------------------------------------------------ up
+template <class S, bool TOP>
 __global__ void __launch_bounds__(kBlock)
-k_mg_up(int m, int tx, int ty, int tiles_per_sample, const double* __restrict__ T,
-        const double* __restrict__ tb, const double* __restrict__ r,
-        const double* __restrict__ zpre, double* __restrict__ z, const double* __restrict__ zc,
-        double omega, const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
-  extern __shared__ double lds[];
+k_mg_up(int m, int tx, int ty, int tiles_per_sample, const S* __restrict__ T,
+        const S* __restrict__ tb, const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre,
+        VecT<S, TOP>* __restrict__ z, const S* __restrict__ zc, double omega,
+        const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
+  using C = typename Prec<S>::C;
+  extern __shared__ double lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
   const long long s = blockIdx.x / tiles_per_sample;
   if (!active[s]) return;
   const FrameGeom g = frame_of(m, tx, ty, blockIdx.x - (int)(s * tiles_per_sample));
   const int W = g.W, H = g.H, F = W * H;
-  Lds L{lds, lds + F, lds + 2 * F, lds + 3 * F};
+  Lds<C> L{lds, lds + F, lds + 2 * F, lds + 3 * F};
   const long long n = (long long)m * m;
   const int mc = m / 2;
-  const double* Ts = T + s * 2 * n;
-  const double* tbs = tb + s * 2 * m;
-  const double* rs = r + s * n;
-  const double* zps = zpre + s * n;  // down-sweep result; read-only here (other tiles' halos)
-  double* zs = z + s * n;
-  const double* zcs = zc + s * (long long)mc * mc;
+  const S* Ts = T + s * 2 * n;
+  const S* tbs = tb + s * 2 * m;
+  const VecT<S, TOP>* rs = r + s * n;
+  const S* zps = zpre + s * n;
+  VecT<S, TOP>* zs = z + s * n;
+  const S* zcs = zc + s * (long long)mc * mc;
+  const C om = (C)omega;
   for (int f = threadIdx.x; f < F; f += kBlock) {
     const int fj = f / W, fi = f - fj * W;
     const int i = g.gi(fi), j = g.gj(fj);
     L.te[f] = load_te(Ts, tbs, m, i, j);
     L.tn[f] = load_tn(Ts, tbs, m, i, j);
     const bool in = g.inside(i, j);
-    L.r[f] = in ? rs[j * m + i] : 0.0;
-    L.z[f] = in ? zps[j * m + i] + omega * zcs[(j >> 1) * mc + (i >> 1)] : 0.0;
+    L.r[f] = in ? (C)ldv(rs, j * m + i) : C(0);
+    L.z[f] = in ? ldv(zps, j * m + i) + om * ldv(zcs, (j >> 1) * mc + (i >> 1)) : C(0);
   }
   __syncthreads();
-  // black sweep on R1
   for (int f = threadIdx.x; f < F; f += kBlock) {
     const int fj = f / W, fi = f - fj * W;
     if (fi < 2 || fi >= W - 1 || fj < 2 || fj >= H - 1) continue;
@@ -190,7 +462,6 @@ k_mg_up(int m, int tx, int ty, int tiles_per_sample, const double* __restrict__ 
     L.z[f] = (L.r[f] + nsum_at(L, W, f)) / diag_at(L, W, f);
   }
   __syncthreads();
-  // red sweep on the tile, then store the tile
   const int tcells = tx * ty;
   for (int c = threadIdx.x; c < tcells; c += kBlock) {
     const int cj = c / tx, ci = c - cj * tx;
@@ -203,324 +474,23 @@ k_mg_up(int m, int tx, int ty, int tiles_per_sample, const double* __restrict__ 
   for (int c = threadIdx.x; c < tcells; c += kBlock) {
     const int cj = c / tx, ci = c - cj * tx;
     const int f = (cj + 3) * W + ci + 3;
-    zs[(g.Y0 + cj) * m + g.X0 + ci] = L.z[f];
-    acc += L.r[f] * L.z[f];
+    const long long e = (g.Y0 + cj) * m + g.X0 + ci;
+    Prec<VecT<S, TOP>>::st(zs, e, L.z[f]);
+    if (TOP) acc += (double)ldv(rs, e) * (double)L.z[f];
   }
-  if (rz_partial) {
+  if (TOP && rz_partial) {
     __shared__ double red[kBlock / kWave];
     const double t = block_sum(acc, red);
     if (threadIdx.x == 0) rz_partial[blockIdx.x] = t;
   }
 }
 
-// Branch-free load of one frame cell: every address is clamped into the
-// sample's arrays, so all loads of a thread are issued back to back and the
-// out-of-domain cases are resolved by selects afterwards.
-struct FrameLoad {
-  double te, tn;
-  int c, ic, jc;
-  bool in;
-};
-
-__device__ __forceinline__ FrameLoad frame_load(const double* __restrict__ Ts,
-                                                const double* __restrict__ tbs, int m, int i,
-                                                int j) {
-  FrameLoad v;
-  v.ic = min(max(i, 0), m - 1);
-  v.jc = min(max(j, 0), m - 1);
-  v.c = v.jc * m + v.ic;
-  const bool iin = i >= 0 && i < m, jin = j >= 0 && j < m;
-  v.in = iin && jin;
-  const double te = Ts[v.c];
-  const double tn = Ts[m * m + v.c];
-  const double tw = tbs[v.jc];
-  const double ts = tbs[m + v.ic];
-  v.te = v.in ? te : ((i == -1 && jin) ? tw : 0.0);
-  v.tn = v.in ? tn : ((j == -1 && iin) ? ts : 0.0);
-  return v;
-}
-
-// ------------------------------------------------------------------ fixed-tile variants
-// Same algorithm as k_mg_down / k_mg_up for tiles of compile-time size TX x TY
-// (used when TX and TY divide m), organised for occupancy: each of the 512
-// threads owns the frame cells f = tid + 512 k in every phase and keeps their
-// four faces, right-hand side and z in registers; LDS holds only z, which is
-// what neighbours read.  All loads use clamped, always-valid addresses and are
-// resolved by selects, so a thread's loads are issued back to back.  Tiles of
-// one sample run on one XCD, so the halo re-reads hit that XCD's L2.
-constexpr int kMgThreads = 512;
-
-template <int TX, int TY>
-struct Tile {
-  static constexpr int W = TX + 5, H = TY + 5, F = W * H;
-  static constexpr int K = (F + kMgThreads - 1) / kMgThreads;
-};
-
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
-  const int x = bid & 7, q = bid >> 3;
-  const int per = nblocks >> 3, rem = nblocks & 7;
-  return x * per + (x < rem ? x : rem) + q;
-}
-
-struct CellFaces {
-  double te, tw, tn, ts;
-  int c;      // clamped linear index of the cell in its sample
-  bool in;    // inside the domain
-};
-
-// Faces of cell (i, j): east/north from T, west/south from the neighbour's
-// east/north face or from the boundary arrays; everything 0 outside.
-__device__ __forceinline__ CellFaces cell_faces(const double* __restrict__ Ts,
-                                                const double* __restrict__ tbs, int m, int i,
-                                                int j) {
-  CellFaces v;
-  const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
-  const int iw = max(ic - 1, 0), js = max(jc - 1, 0);
-  const int n = m * m;
-  v.c = jc * m + ic;
-  v.in = i >= 0 && i < m && j >= 0 && j < m;
-  const double te = Ts[v.c], tn = Ts[n + v.c];
-  const double tw = Ts[jc * m + iw], ts = Ts[n + js * m + ic];
-  const double twb = tbs[jc], tsb = tbs[m + ic];
-  v.te = v.in ? te : 0.0;
-  v.tn = v.in ? tn : 0.0;
-  v.tw = v.in ? (i > 0 ? tw : twb) : 0.0;
-  v.ts = v.in ? (j > 0 ? ts : tsb) : 0.0;
-  return v;
-}
-
-template <int TX, int TY>
-__global__ void __launch_bounds__(kMgThreads)
-k_mg_down_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
-            const double* __restrict__ r, double* __restrict__ z, double* __restrict__ rc,
-            const int32_t* __restrict__ active) {
-  using G = Tile<TX, TY>;
-  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
-  __shared__ double sz[F];
-  const int ntx = m / TX, tps = ntx * (m / TY);
-  const int bid = xcd_tile(blockIdx.x, gridDim.x);
-  const long long s = bid / tps;
-  if (!active[s]) return;
-  const int tile = bid - (int)(s * tps);
-  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
-  const long long n = (long long)m * m;
-  const double* Ts = T + s * 2 * n;
-  const double* tbs = tb + s * 2 * m;
-  const double* rs = r + s * n;
-  CellFaces cf[K];
-  double rv[K], zv[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    cf[k] = cell_faces(Ts, tbs, m, X0 - 3 + fi, Y0 - 3 + fj);
-    const double rr = rs[cf[k].c];
-    rv[k] = cf[k].in ? rr : 0.0;
-  }
-  // red cells of R2: z = r / D; all other cells start at 0
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-    zv[k] = (cf[k].in && fi >= 1 && fj >= 1 && ((fi + fj) & 1) == 0) ? rv[k] / d : 0.0;
-    if (f < F) sz[f] = zv[k];
-  }
-  __syncthreads();
-  // black cells of R1
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
-      const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-               cf[k].ts * sz[f - W]) / d;
-      sz[f] = zv[k];
-    }
-  }
-  __syncthreads();
-  // store the tile; residual of its red cells (black residuals vanish)
-  double* zs = z + s * n;
-  double res[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    res[k] = 0.0;
-    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
-      zs[cf[k].c] = zv[k];
-      if (((fi + fj) & 1) == 0)
-        res[k] = cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-                 cf[k].ts * sz[f - W];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if (f < F) sz[f] = res[k];
-  }
-  __syncthreads();
-  const int mc = m / 2;
-  double* rcs = rc + s * (long long)mc * mc;
-  constexpr int HX = TX / 2, HY = TY / 2;
-  for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
-    const int cj = c / HX, ci = c - cj * HX;
-    const int fa = (3 + 2 * cj) * W + 3 + 2 * ci;
-    rcs[(Y0 / 2 + cj) * mc + X0 / 2 + ci] = sz[fa] + sz[fa + W + 1];
-  }
-}
-
-template <int TX, int TY>
-__global__ void __launch_bounds__(kMgThreads)
-k_mg_up_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
-          const double* __restrict__ r, const double* __restrict__ zpre, double* __restrict__ z,
-          const double* __restrict__ zc, double omega, const int32_t* __restrict__ active,
-          double* __restrict__ rz_partial) {
-  using G = Tile<TX, TY>;
-  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
-  __shared__ double sz[F];
-  __shared__ double red[kMgThreads / kWave];
-  const int ntx = m / TX, tps = ntx * (m / TY);
-  const int bid = xcd_tile(blockIdx.x, gridDim.x);
-  const long long s = bid / tps;
-  if (!active[s]) return;
-  const int tile = bid - (int)(s * tps);
-  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
-  const long long n = (long long)m * m;
-  const int mc = m / 2;
-  const double* Ts = T + s * 2 * n;
-  const double* tbs = tb + s * 2 * m;
-  const double* rs = r + s * n;
-  const double* zps = zpre + s * n;
-  const double* zcs = zc + s * (long long)mc * mc;
-  CellFaces cf[K];
-  double rv[K], zv[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-    cf[k] = cell_faces(Ts, tbs, m, i, j);
-    const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
-    const double rr = rs[cf[k].c], zp = zps[cf[k].c], zcv = zcs[(jc >> 1) * mc + (ic >> 1)];
-    rv[k] = cf[k].in ? rr : 0.0;
-    zv[k] = cf[k].in ? zp + omega * zcv : 0.0;
-    if (f < F) sz[f] = zv[k];
-  }
-  __syncthreads();
-  // black sweep on R1
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
-      const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-               cf[k].ts * sz[f - W]) / d;
-      sz[f] = zv[k];
-    }
-  }
-  __syncthreads();
-  // red sweep on the tile, store, r^T z
-  double* zs = z + s * n;
-  double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
-      if (((fi + fj) & 1) == 0) {
-        const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-        zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-                 cf[k].ts * sz[f - W]) / d;
-      }
-      zs[cf[k].c] = zv[k];
-      acc += rv[k] * zv[k];
-    }
-  }
-  if (rz_partial) {
-    // fixed-order block sum over the 8 waves
-    acc = wave_sum(acc);
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-#pragma unroll
-      for (int w = 0; w < kMgThreads / kWave; ++w) t += red[w];
-      rz_partial[s * tps + tile] = t;
-    }
-  }
-}
-
-static int g_tile_y = -1;
-static int tile_y() {
-  if (g_tile_y < 0) {
-    const char* e = getenv("MLMC_TILE_Y");
-    g_tile_y = (e && atoi(e) == 16) ? 16 : 32;
-  }
-  return g_tile_y;
-}
-
-// Largest even divisor of m that is <= cap.
-static int tile_dim(int m, int cap) {
-  for (int t = cap < m ? cap : m; t >= 2; --t)
-    if (m % t == 0 && (t % 2) == 0) return t;
-  return 2;
-}
-
-static size_t frame_bytes(int tx, int ty) { return (size_t)4 * (tx + 5) * (ty + 5) * sizeof(double); }
-
-void launch_mg_down(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                    const double* r, double* z, double* rc, const int32_t* active) {
-  if (m % 64 == 0 && m % tile_y() == 0) {
-    if (tile_y() == 32)
-      hipLaunchKernelGGL((k_mg_down_t<64, 32>), dim3(batch * (m / 64) * (m / 32)),
-                         dim3(kMgThreads), 0, st, m, T, tb, r, z, rc, active);
-    else
-      hipLaunchKernelGGL((k_mg_down_t<64, 16>), dim3(batch * (m / 64) * (m / 16)),
-                         dim3(kMgThreads), 0, st, m, T, tb, r, z, rc, active);
-    return;
-  }
-  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
-  const int tps = (m / tx) * (m / ty);
-  hipLaunchKernelGGL(k_mg_down, dim3(batch * tps), dim3(kBlock), frame_bytes(tx, ty), st, m, tx,
-                     ty, tps, T, tb, r, z, rc, active);
-}
-
-int mg_tiles_per_sample(int m) {
-  if (m % 64 == 0 && m % tile_y() == 0) return (m / 64) * (m / tile_y());
-  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
-  return (m / tx) * (m / ty);
-}
-
-void launch_mg_up(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                  const double* r, const double* zpre, double* z, const double* zc, double omega,
-                  const int32_t* active, double* rz_partial) {
-  if (m % 64 == 0 && m % tile_y() == 0) {
-    if (tile_y() == 32)
-      hipLaunchKernelGGL((k_mg_up_t<64, 32>), dim3(batch * (m / 64) * (m / 32)),
-                         dim3(kMgThreads), 0, st, m, T, tb, r, zpre, z, zc, omega, active,
-                         rz_partial);
-    else
-      hipLaunchKernelGGL((k_mg_up_t<64, 16>), dim3(batch * (m / 64) * (m / 16)),
-                         dim3(kMgThreads), 0, st, m, T, tb, r, zpre, z, zc, omega, active,
-                         rz_partial);
-    return;
-  }
-  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
-  const int tps = (m / tx) * (m / ty);
-  hipLaunchKernelGGL(k_mg_up, dim3(batch * tps), dim3(kBlock), frame_bytes(tx, ty), st, m, tx, ty,
-                     tps, T, tb, r, zpre, z, zc, omega, active, rz_partial);
-}
-
 // ------------------------------------------------------------------ coarse cycle in LDS
 // One workgroup per sample runs the V(1,1)-cycle on levels l0..L (m_l0 <= 32)
-// with every level's operator and vectors in LDS.  Level arrays use a padded
-// (m + 2)^2 layout with a one-cell ring: ring cells hold z = 0 and the
-// boundary faces (west face in column -1, south face in row -1), so the
-// stencil needs no branches.
+// in FP64 with every level's operator and vectors in LDS, whatever the
+// storage type of the hierarchy.  Level arrays use a padded (m + 2)^2 layout
+// with a one-cell ring: ring cells hold z = 0 and the boundary faces (west
+// face in column -1, south face in row -1), so the stencil needs no branches.
 struct CoarseLevel {
   int m, P, off;  // size, padded pitch (m + 2), offset of the level's arrays in LDS
 };
@@ -544,9 +514,10 @@ __device__ void cc_sweep(double* te, double* tn, double* r, double* z, int m, in
   __syncthreads();
 }
 
+template <class S, bool TOP>
 __global__ void __launch_bounds__(kBlock)
-k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
-                  double* __restrict__ z0, const double* __restrict__ Ainv, double omega,
+k_mg_coarse_cycle(int nlev, CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0,
+                  VecT<S, TOP>* __restrict__ z0, const double* __restrict__ Ainv, double omega,
                   const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
   extern __shared__ double lds[];
   const int s = blockIdx.x;
@@ -559,8 +530,7 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
     lv[l].off = off;
     off += 4 * lv[l].P * lv[l].P;
   }
-  double* vec = lds + off;  // coarsest right-hand side / solution scratch (n_c doubles)
-  // load operators (levels are stored in global memory with the library layout)
+  double* vec = lds + off;  // coarsest right-hand side (n_c doubles)
   for (int l = 0; l < nlev; ++l) {
     const int m = lv[l].m, P = lv[l].P, PP = P * P;
     double* te = lds + lv[l].off;
@@ -568,18 +538,19 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
     double* rr = tn + PP;
     double* zz = rr + PP;
     const long long n = (long long)m * m;
-    const double* Ts = desc.T[l] + (long long)s * 2 * n;
-    const double* tbs = desc.tb[l] + (long long)s * 2 * m;
+    const S* Ts = static_cast<const S*>(desc.T[l]) + (long long)s * 2 * n;
+    const S* tbs = static_cast<const S*>(desc.tb[l]) + (long long)s * 2 * m;
     for (int f = threadIdx.x; f < PP; f += kBlock) {
       const int j = f / P - 1, i = f % P - 1;
-      te[f] = load_te(Ts, tbs, m, i, j);
-      tn[f] = load_tn(Ts, tbs, m, i, j);
-      rr[f] = (l == 0 && i >= 0 && i < m && j >= 0 && j < m) ? r0[(long long)s * n + j * m + i] : 0.0;
+      te[f] = (double)load_te(Ts, tbs, m, i, j);
+      tn[f] = (double)load_tn(Ts, tbs, m, i, j);
+      rr[f] = (l == 0 && i >= 0 && i < m && j >= 0 && j < m)
+                  ? (double)ldv(r0, (long long)s * n + j * m + i)
+                  : 0.0;
       zz[f] = 0.0;
     }
   }
   __syncthreads();
-  // descend
   for (int l = 0; l < nlev - 1; ++l) {
     const int m = lv[l].m, P = lv[l].P, PP = P * P;
     double* te = lds + lv[l].off;
@@ -604,7 +575,6 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
     }
     __syncthreads();
   }
-  // coarsest: z = Ainv r
   {
     const int l = nlev - 1;
     const int m = lv[l].m, P = lv[l].P, PP = P * P, nc = m * m;
@@ -620,7 +590,6 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
     }
     __syncthreads();
   }
-  // ascend
   for (int l = nlev - 2; l >= 0; --l) {
     const int m = lv[l].m, P = lv[l].P, PP = P * P;
     double* te = lds + lv[l].off;
@@ -637,7 +606,6 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
     cc_sweep(te, tn, rr, zz, m, P, 1, false);
     cc_sweep(te, tn, rr, zz, m, P, 0, false);
   }
-  // store level l0's correction
   {
     const int m = lv[0].m, P = lv[0].P, PP = P * P;
     const double* rr = lds + lv[0].off + 2 * PP;
@@ -645,15 +613,132 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const double* __restrict__ r0,
     double acc = 0.0;
     for (int c = threadIdx.x; c < m * m; c += kBlock) {
       const int f = pidx(P, c % m, c / m);
-      z0[(long long)s * m * m + c] = zz[f];
+      Prec<VecT<S, TOP>>::st(z0, (long long)s * m * m + c, zz[f]);
       acc += rr[f] * zz[f];
     }
-    if (rz_partial) {
+    if (TOP && rz_partial) {
       __shared__ double red[kBlock / kWave];
       const double t = block_sum(acc, red);
       if (threadIdx.x == 0) rz_partial[s] = t;
     }
   }
+}
+
+// ------------------------------------------------------------------ conversions
+template <class S>
+__global__ void k_convert(long long count, const double* __restrict__ x, S* __restrict__ y) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < count) Prec<S>::st(y, g, (typename Prec<S>::C)x[g]);
+}
+
+// ------------------------------------------------------------------ launchers
+// Largest even divisor of m that is <= cap.
+static int tile_dim(int m, int cap) {
+  for (int t = cap < m ? cap : m; t >= 2; --t)
+    if (m % t == 0 && (t % 2) == 0) return t;
+  return 2;
+}
+
+template <class C>
+static size_t frame_bytes(int tx, int ty) {
+  return (size_t)4 * (tx + 5) * (ty + 5) * sizeof(C);
+}
+
+static bool fixed_tile(int m) { return m % kTileX == 0 && m % kTileY == 0; }
+
+int mg_tiles_per_sample(int m) {
+  if (fixed_tile(m)) return (m / kTileX) * (m / kTileY);
+  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
+  return (m / tx) * (m / ty);
+}
+
+template <class S, bool TOP>
+static void down_impl(hipStream_t st, int m, int batch, const void* T, const void* tb,
+                      const void* r, void* z, void* rc, const int32_t* active) {
+  using R = VecT<S, TOP>;
+  if (fixed_tile(m)) {
+    const int nb = batch * (m / kTileX) * (m / kTileY);
+    hipLaunchKernelGGL((k_mg_down_t<kTileX, kTileY, S, TOP>), dim3(nb), dim3(kMgThreads), 0, st,
+                       m, (const S*)T, (const S*)tb, (const R*)r, (S*)z, (S*)rc, active);
+    return;
+  }
+  using C = typename Prec<S>::C;
+  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
+  const int tps = (m / tx) * (m / ty);
+  hipLaunchKernelGGL((k_mg_down<S, TOP>), dim3(batch * tps), dim3(kBlock), frame_bytes<C>(tx, ty),
+                     st, m, tx, ty, tps, (const S*)T, (const S*)tb, (const R*)r, (S*)z, (S*)rc,
+                     active);
+}
+
+template <class S, bool TOP>
+static void up_impl(hipStream_t st, int m, int batch, const void* T, const void* tb,
+                    const void* r, const void* zpre, void* z, const void* zc, double omega,
+                    const int32_t* active, double* rz_partial) {
+  using R = VecT<S, TOP>;
+  if (fixed_tile(m)) {
+    const int nb = batch * (m / kTileX) * (m / kTileY);
+    hipLaunchKernelGGL((k_mg_up_t<kTileX, kTileY, S, TOP>), dim3(nb), dim3(kMgThreads), 0, st, m,
+                       (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (R*)z,
+                       (const S*)zc, omega, active, rz_partial);
+    return;
+  }
+  using C = typename Prec<S>::C;
+  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
+  const int tps = (m / tx) * (m / ty);
+  hipLaunchKernelGGL((k_mg_up<S, TOP>), dim3(batch * tps), dim3(kBlock), frame_bytes<C>(tx, ty), st,
+                     m, tx, ty, tps, (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (R*)z,
+                     (const S*)zc, omega, active, rz_partial);
+}
+
+template <class S>
+static void down_any(bool top, hipStream_t st, int m, int batch, const void* T, const void* tb,
+                     const void* r, void* z, void* rc, const int32_t* active) {
+  if (top) down_impl<S, true>(st, m, batch, T, tb, r, z, rc, active);
+  else down_impl<S, false>(st, m, batch, T, tb, r, z, rc, active);
+}
+
+template <class S>
+static void up_any(bool top, hipStream_t st, int m, int batch, const void* T, const void* tb,
+                   const void* r, const void* zpre, void* z, const void* zc, double omega,
+                   const int32_t* active, double* rz_partial) {
+  if (top) up_impl<S, true>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+  else up_impl<S, false>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+}
+
+template <class S>
+static void coarse_any(bool top, hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
+                       const void* r0, void* z0, const double* Ainv, double omega,
+                       const int32_t* active, double* rz_partial) {
+  const size_t lds = coarse_cycle_lds_bytes(desc, nlev);
+  if (top)
+    hipLaunchKernelGGL((k_mg_coarse_cycle<S, true>), dim3(batch), dim3(kBlock), lds, st, nlev, desc,
+                       (const double*)r0, (double*)z0, Ainv, omega, active, rz_partial);
+  else
+    hipLaunchKernelGGL((k_mg_coarse_cycle<S, false>), dim3(batch), dim3(kBlock), lds, st, nlev,
+                       desc, (const S*)r0, (S*)z0, Ainv, omega, active, rz_partial);
+}
+
+template <class S>
+static void convert_any(hipStream_t st, long long count, const double* x, void* y) {
+  hipLaunchKernelGGL((k_convert<S>), dim3(blocks_for(count)), dim3(kBlock), 0, st, count, x,
+                     (S*)y);
+}
+
+void launch_mg_down(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+                    const void* tb, const void* r, void* z, void* rc, const int32_t* active) {
+  if (prec == MLMC_PREC_FP64) down_any<double>(top, st, m, batch, T, tb, r, z, rc, active);
+  else if (prec == MLMC_PREC_FP32) down_any<float>(top, st, m, batch, T, tb, r, z, rc, active);
+  else down_any<bf16_t>(top, st, m, batch, T, tb, r, z, rc, active);
+}
+
+void launch_mg_up(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+                  const void* tb, const void* r, const void* zpre, void* z, const void* zc,
+                  double omega, const int32_t* active, double* rz_partial) {
+  if (prec == MLMC_PREC_FP64)
+    up_any<double>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+  else if (prec == MLMC_PREC_FP32)
+    up_any<float>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+  else up_any<bf16_t>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
 }
 
 size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev) {
@@ -663,12 +748,24 @@ size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev) {
   return words * sizeof(double);
 }
 
-void launch_mg_coarse_cycle(hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
-                            const double* r0, double* z0, const double* Ainv, double omega,
-                            const int32_t* active, double* rz_partial) {
-  hipLaunchKernelGGL(k_mg_coarse_cycle, dim3(batch), dim3(kBlock),
-                     coarse_cycle_lds_bytes(desc, nlev), st, nlev, desc, r0, z0, Ainv, omega,
-                     active, rz_partial);
+void launch_mg_coarse_cycle(hipStream_t st, int prec, bool top, int batch, int nlev,
+                            const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
+                            double omega, const int32_t* active, double* rz_partial) {
+  if (prec == MLMC_PREC_FP64)
+    coarse_any<double>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
+  else if (prec == MLMC_PREC_FP32)
+    coarse_any<float>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
+  else coarse_any<bf16_t>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
+}
+
+void launch_convert(hipStream_t st, int prec, long long count, const double* x, void* y) {
+  if (prec == MLMC_PREC_FP64) convert_any<double>(st, count, x, y);
+  else if (prec == MLMC_PREC_FP32) convert_any<float>(st, count, x, y);
+  else convert_any<bf16_t>(st, count, x, y);
+}
+
+size_t prec_bytes(int prec) {
+  return prec == MLMC_PREC_FP64 ? 8 : (prec == MLMC_PREC_FP32 ? 4 : 2);
 }
 
 }  // namespace mlmc

@@ -322,12 +322,13 @@ void launch_spmv_dot(hipStream_t st, int m, int batch, const double* T, const do
 __global__ void __launch_bounds__(kBlock)
 k_axpy_dot(int n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
            const double* __restrict__ q, const double* __restrict__ alpha,
-           double* __restrict__ partial, int bps, const int32_t* __restrict__ active) {
+           double* __restrict__ partial, int bps, const int32_t* __restrict__ active,
+           const double* __restrict__ zold, double* __restrict__ partial2) {
   __shared__ double sh[kBlock / kWave];
   PCG_PROLOGUE
   if (!active[s]) return;
   const double a = alpha[s];
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
 #pragma unroll
   for (int c = 0; c < kCellsPerThread; ++c) {
     const int cell = cell0 + c * kBlock;
@@ -337,17 +338,23 @@ k_axpy_dot(int n, double* __restrict__ x, double* __restrict__ r, const double* 
       const double rv = r[e] - a * q[e];
       r[e] = rv;
       acc += rv * rv;
+      if (zold) acc2 += rv * zold[e];
     }
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[lbid] = t;
+  if (zold) {
+    __syncthreads();
+    const double t2 = block_sum(acc2, sh);
+    if (threadIdx.x == 0) partial2[lbid] = t2;
+  }
 }
 
 void launch_axpy_dot(hipStream_t st, int n, int batch, double* x, double* r, const double* p,
                      const double* q, const double* alpha, double* partial, int bps,
-                     const int32_t* active) {
+                     const int32_t* active, const double* zold, double* partial2) {
   hipLaunchKernelGGL(k_axpy_dot, dim3(batch * bps), dim3(kBlock), 0, st, n, x, r, p, q, alpha,
-                     partial, bps, active);
+                     partial, bps, active, zold, partial2);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -460,24 +467,30 @@ void launch_sc_init(hipStream_t st, int batch, const double* partial, int bps, S
                      s, status, iters, relres);
 }
 
-__global__ void k_sc_rho(int batch, const double* __restrict__ partial, int bps, SolverState S,
-                         int32_t* __restrict__ status, int first) {
+__global__ void k_sc_rho(int batch, const double* __restrict__ partial, int nparts,
+                         SolverState S, int32_t* __restrict__ status, int first,
+                         const double* __restrict__ partial2, int nparts2) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= batch || !S.active[s]) return;
-  const double v = sum_partials(partial, bps, s);
+  const double v = sum_partials(partial, nparts, s);
   if (!(v > 0.0) || !isfinite(v)) {
     S.active[s] = 0;
     status[s] = MLMC_SAMPLE_BREAKDOWN;
     return;
   }
-  S.beta[s] = first ? 0.0 : v / S.rho[s];
+  if (first) {
+    S.beta[s] = 0.0;
+  } else {
+    const double rzold = partial2 ? sum_partials(partial2, nparts2, s) : 0.0;
+    S.beta[s] = (v - rzold) / S.rho[s];
+  }
   S.rho[s] = v;
 }
 
-void launch_sc_rho(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
-                   int32_t* status, int first) {
-  hipLaunchKernelGGL(k_sc_rho, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial, bps,
-                     s, status, first);
+void launch_sc_rho(hipStream_t st, int batch, const double* partial, int nparts, SolverState s,
+                   int32_t* status, int first, const double* partial2, int nparts2) {
+  hipLaunchKernelGGL(k_sc_rho, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial,
+                     nparts, s, status, first, partial2, nparts2);
 }
 
 __global__ void k_sc_alpha(int batch, const double* __restrict__ partial, int bps, SolverState S,

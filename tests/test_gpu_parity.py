@@ -349,3 +349,43 @@ def test_iterations_flat_in_grid_size(lib, ctx):
         sums = lib.mlmc_level_run(ctx, W.CE2, level, m, 0, 8, False, lib.mlmc_solver_opts_default())
         its.append(sums.iters_fine / 8)
     assert max(its) <= 25 and max(its) - min(its) <= 5, its
+
+
+# ------------------------------------------------------------------ reduced-precision multigrid
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("m", [40, 64, 96, 256])
+def test_mixed_precision_multigrid_qoi(lib, ctx, m, prec):
+    """FP32 / bfloat16 multigrid inside the FP64 flexible CG: the outer residual is
+    FP64, so the QoI reaches the same 1e-10 parity; iterations stay bounded."""
+    print("mixed precision %d m=%d" % (prec, m), flush=True)
+    rng = np.random.default_rng(500 + m)
+    batch = 3
+    kh = np.exp(1.5 * rng.standard_normal((batch, m, m)))
+    ref = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default())
+    out = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=prec))
+    assert np.all(out["status"] == 0), out["status"]
+    assert np.all(out["relres"] < 1e-12)
+    slack = 3 if prec == 1 else 12
+    assert np.all(out["iters"] <= ref["iters"] + slack), (out["iters"], ref["iters"])
+    for s in range(batch):
+        A, bb = ofv.assemble(kh[s])
+        q = oqoi.outflow(kh[s], osolve.direct_solve(A, bb))
+        assert abs(out["q_out"][s] - q) <= QTOL * q
+
+
+def test_mixed_precision_level_run_golden(lib, ctx):
+    rec = json.load(open(os.path.join(GOLDEN, "ce2_16_32_plain.json")))
+    for prec in (1, 2):
+        opts = lib.mlmc_solver_opts_default(precision=prec)
+        for lv in rec["levels"]:
+            n = len(lv["samples"])
+            sums, qf, qc, y = level_run(lib, ctx, W.CE2, lv["level"], lv["m"], 0, n, False, opts)
+            assert sums.n_failed == 0
+            for s, row in enumerate(lv["samples"]):
+                assert abs(qf[s] - row["Q_f"]) <= QTOL * abs(row["Q_f"])
+
+
+def test_mixed_precision_requires_fused(lib, ctx):
+    kh = np.ones((1, 16, 16))
+    with pytest.raises(lib.MlmcError):
+        solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=1, variant=1))
