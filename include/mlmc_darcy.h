@@ -187,6 +187,12 @@ mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m,
 mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
                               uint64_t first_sample, int batch, double* k, double* k_coarse);
 
+/* As mlmc_sample_field, for arbitrary sample numbers: batch slot s holds
+ * sample number sample_ids[s] (device uint32 [batch]). */
+mlmc_status mlmc_sample_field_ids(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
+                                  const uint32_t* sample_ids, int batch, double* k,
+                                  double* k_coarse);
+
 /* Coarse Grid Variates sub-samples (Section 4.1, eq. (4.1)): the 2^d coarse
  * samples k^(a)(I, J) = k(2I + a1, 2J + a2), a = a1 + 2 a2.
  *   k_fine device [batch][m][m] (m even); k_sub device [batch][4][m/2][m/2]. */
@@ -243,6 +249,16 @@ mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, in
                            const mlmc_solver_opts* opts, mlmc_level_sums* sums,
                            double* q_f, double* q_c, double* y);
 
+/* As mlmc_level_run for arbitrary sample numbers (device uint32 sample_ids[n]),
+ * with optional per-sample outputs: failed (device int32 [n], 1 when the fine or
+ * a coarse solve did not reach tol) and iters (device int32 [n], CG iterations
+ * of the fine solve).  A sample's results do not depend on the other samples
+ * of the call. */
+mlmc_status mlmc_level_run_ids(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
+                               const uint32_t* sample_ids, int n, int cgv,
+                               const mlmc_solver_opts* opts, mlmc_level_sums* sums, double* q_f,
+                               double* q_c, double* y, int32_t* failed, int32_t* iters);
+
 /* Estimator eq. (3.6) and the statistical part of eq. (3.7) from per-level
  * sums (host arithmetic only).  levels: host [n_levels]; out: host. */
 mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_estimate_t* out);
@@ -254,6 +270,73 @@ mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_esti
 mlmc_status mlmc_profile_enable(mlmc_ctx* ctx, const char* kernel_name);
 mlmc_status mlmc_profile_read(mlmc_ctx* ctx, int64_t* launches, double* total_ms,
                               double* algorithmic_bytes);
+
+/* ------------------------------------------------------------------------
+ * Request server with continuous batching (serving form of the estimator).
+ * A request is one estimator term (eq. (3.6), or eq. (4.2) with CGV): sample
+ * number `sample` of `level` on the m_fine grid.  Worker threads each own a
+ * context with its own HIP stream and device-resident workspaces; each takes
+ * the oldest waiting request plus later ones for the same (level, m_fine), up
+ * to max_batch, while the estimated device memory of the running batches stays
+ * within hbm_budget_bytes (a single request runs whenever nothing else does).
+ * Requests arriving while others run are admitted as workers and memory free
+ * up; batches of different workers overlap on the device.  Results are
+ * independent of batching.  Times are seconds on the server's clock
+ * (mlmc_serve_now).  All calls are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct mlmc_server mlmc_server;
+
+typedef struct mlmc_serve_opts {
+  int32_t device;
+  int32_t n_workers;          /* concurrent batches, 1..16 (default 3)            */
+  int32_t max_batch;          /* requests per batch (default 256)                 */
+  int32_t cgv;                /* 0: plain coarse companion, 1: CGV                */
+  uint64_t hbm_budget_bytes;  /* admission limit for running batches (default 64 GiB) */
+  int32_t n_grids;            /* entries in grid_m / grid_n_ce (correlated fields) */
+  int32_t grid_m[8];          /* fine grid sizes served ...                       */
+  int32_t grid_n_ce[8];       /* ... and their circulant-embedding sizes          */
+  int32_t reserved;
+  mlmc_solver_opts solver;
+} mlmc_serve_opts;
+
+typedef struct mlmc_request {
+  int32_t level;
+  int32_t m_fine;
+  uint32_t sample;
+  int32_t reserved;
+} mlmc_request;
+
+typedef struct mlmc_result {
+  uint64_t id;
+  int32_t level, m_fine;
+  uint32_t sample;
+  int32_t failed;      /* 1: a solve missed tol or the batch failed            */
+  int32_t iters;       /* CG iterations of the fine solve                      */
+  int32_t batch_size;  /* requests in the batch that served it                 */
+  int32_t status;      /* MLMC_OK, or the error of the batch                   */
+  int32_t reserved;
+  double q_f, q_c, y;  /* Q on the fine grid, coarse (companion mean), Y       */
+  double t_submit, t_start, t_done;
+} mlmc_result;
+
+/* Defaults: device 0, 3 workers, batches up to 256, plain MLMC, 64 GiB budget,
+ * mlmc_solver_opts_default. */
+mlmc_status mlmc_serve_opts_default(mlmc_serve_opts* opts);
+/* Starts the workers (model: host; copied). */
+mlmc_status mlmc_serve_start(const mlmc_model* model, const mlmc_serve_opts* opts,
+                             mlmc_server** out);
+/* Queues a request (host); id (host, may be NULL) receives its identifier. */
+mlmc_status mlmc_serve_submit(mlmc_server* srv, const mlmc_request* req, uint64_t* id);
+/* Moves up to max finished results into out (host); *n_out = number moved;
+ * *pending (may be NULL) = requests queued or finished and not yet polled. */
+mlmc_status mlmc_serve_poll(mlmc_server* srv, mlmc_result* out, int max, int* n_out,
+                            int64_t* pending);
+/* Current time on the server's clock in seconds. */
+double mlmc_serve_now(const mlmc_server* srv);
+mlmc_status mlmc_serve_stats(mlmc_server* srv, int64_t* batches, int64_t* queued, int* running,
+                             uint64_t* in_flight_bytes);
+/* Finishes running batches, drops queued requests, frees everything. */
+mlmc_status mlmc_serve_stop(mlmc_server* srv);
 
 #ifdef __cplusplus
 }

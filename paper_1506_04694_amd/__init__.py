@@ -30,7 +30,10 @@ MLMC_PREC_FP64, MLMC_PREC_FP32, MLMC_PREC_BF16 = 0, 1, 2
 EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_last_error",
             "mlmc_solver_opts_default", "mlmc_ce_min_embedding", "mlmc_sample_field",
             "mlmc_cgv_extract", "mlmc_assemble", "mlmc_solve", "mlmc_qoi_outflow",
-            "mlmc_level_run", "mlmc_estimate", "mlmc_profile_enable", "mlmc_profile_read"]
+            "mlmc_level_run", "mlmc_estimate", "mlmc_profile_enable", "mlmc_profile_read",
+            "mlmc_sample_field_ids", "mlmc_level_run_ids", "mlmc_serve_opts_default",
+            "mlmc_serve_start", "mlmc_serve_submit", "mlmc_serve_poll", "mlmc_serve_now",
+            "mlmc_serve_stats", "mlmc_serve_stop"]
 
 
 class mlmc_model(ctypes.Structure):
@@ -56,6 +59,32 @@ class mlmc_level_sums(ctypes.Structure):
                 ("sum_y", ctypes.c_double), ("sum_y2", ctypes.c_double),
                 ("sum_qf", ctypes.c_double), ("sum_qc", ctypes.c_double),
                 ("iters_fine", ctypes.c_int64), ("iters_coarse", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class mlmc_serve_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_workers", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("cgv", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("n_grids", ctypes.c_int32),
+                ("grid_m", ctypes.c_int32 * 8), ("grid_n_ce", ctypes.c_int32 * 8),
+                ("reserved", ctypes.c_int32), ("solver", mlmc_solver_opts)]
+
+
+class mlmc_request(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("m_fine", ctypes.c_int32),
+                ("sample", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class mlmc_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("level", ctypes.c_int32), ("m_fine", ctypes.c_int32),
+                ("sample", ctypes.c_uint32), ("failed", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("q_f", ctypes.c_double), ("q_c", ctypes.c_double), ("y", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -89,6 +118,20 @@ _SIGS = {
                             _P, _P, _P]),
     "mlmc_estimate": (_S, [ctypes.POINTER(mlmc_level_sums), _I, ctypes.POINTER(mlmc_estimate_t)]),
     "mlmc_profile_enable": (_S, [_P, ctypes.c_char_p]),
+    "mlmc_sample_field_ids": (_S, [_P, ctypes.POINTER(mlmc_model), _I, _I, _P, _I, _P, _P]),
+    "mlmc_level_run_ids": (_S, [_P, ctypes.POINTER(mlmc_model), _I, _I, _P, _I, _I,
+                                ctypes.POINTER(mlmc_solver_opts), ctypes.POINTER(mlmc_level_sums),
+                                _P, _P, _P, _P, _P]),
+    "mlmc_serve_opts_default": (_S, [ctypes.POINTER(mlmc_serve_opts)]),
+    "mlmc_serve_start": (_S, [ctypes.POINTER(mlmc_model), ctypes.POINTER(mlmc_serve_opts),
+                              ctypes.POINTER(_P)]),
+    "mlmc_serve_submit": (_S, [_P, ctypes.POINTER(mlmc_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "mlmc_serve_poll": (_S, [_P, ctypes.POINTER(mlmc_result), _I, ctypes.POINTER(_I),
+                             ctypes.POINTER(ctypes.c_int64)]),
+    "mlmc_serve_now": (ctypes.c_double, [_P]),
+    "mlmc_serve_stats": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_uint64)]),
+    "mlmc_serve_stop": (_S, [_P]),
     "mlmc_profile_read": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double)]),
 }
@@ -272,3 +315,94 @@ def mlmc_profile_read(ctx):
     by = ctypes.c_double()
     _check(ctx, _lib.mlmc_profile_read(ctx, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
     return {"launches": n.value, "total_ms": ms.value, "algorithmic_bytes": by.value}
+
+
+def _u32(t, numel, name):
+    import torch
+    if t is not None and t.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("%s must be int32/uint32" % name)
+    return _ptr(t, None, numel, name)
+
+
+def mlmc_sample_field_ids(ctx, model, m, level, sample_ids, batch, k, k_coarse=None):
+    mm = model if isinstance(model, mlmc_model) else model_for_grid(model, m)
+    _check(ctx, _lib.mlmc_sample_field_ids(ctx, ctypes.byref(mm), int(m), int(level),
+                                           _u32(sample_ids, batch, "sample_ids"), int(batch),
+                                           _f64(k, batch * m * m, "k"),
+                                           _f64(k_coarse, batch * (m // 2) ** 2, "k_coarse")))
+
+
+def mlmc_level_run_ids(ctx, model, level, m_fine, sample_ids, n, cgv, opts, sums=None,
+                       q_f=None, q_c=None, y=None, failed=None, iters=None, allow_noconv=False):
+    mm = model if isinstance(model, mlmc_model) else model_for_grid(model, m_fine)
+    if sums is None:
+        sums = mlmc_level_sums()
+    code = _lib.mlmc_level_run_ids(ctx, ctypes.byref(mm), int(level), int(m_fine),
+                                   _u32(sample_ids, n, "sample_ids"), int(n), int(bool(cgv)),
+                                   ctypes.byref(opts), ctypes.byref(sums), _f64(q_f, n, "q_f"),
+                                   _f64(q_c, n, "q_c"), _f64(y, n, "y"),
+                                   _i32(failed, n, "failed"), _i32(iters, n, "iters"))
+    if not (allow_noconv and code == MLMC_ENOCONV):
+        _check(ctx, code)
+    return sums
+
+
+def mlmc_serve_opts_default(**overrides):
+    o = mlmc_serve_opts()
+    _check(None, _lib.mlmc_serve_opts_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def serve_opts_for(model, grids, **overrides):
+    """Server options serving the fine grids `grids` of `model` (embedding sizes from model.n_ce)."""
+    o = mlmc_serve_opts_default(**overrides)
+    o.n_grids = len(grids)
+    for q, m in enumerate(grids):
+        o.grid_m[q] = int(m)
+        o.grid_n_ce[q] = int(model.n_ce.get(m, 0)) if getattr(model, "n_ce", None) else 0
+    return o
+
+
+def mlmc_serve_start(model, opts):
+    mm = model if isinstance(model, mlmc_model) else make_model(model)
+    h = ctypes.c_void_p()
+    code = _lib.mlmc_serve_start(ctypes.byref(mm), ctypes.byref(opts), ctypes.byref(h))
+    if code != MLMC_OK:
+        raise MlmcError(code, "mlmc_serve_start failed")
+    return h
+
+
+def mlmc_serve_submit(srv, level, m_fine, sample):
+    req = mlmc_request(int(level), int(m_fine), int(sample), 0)
+    rid = ctypes.c_uint64()
+    code = _lib.mlmc_serve_submit(srv, ctypes.byref(req), ctypes.byref(rid))
+    if code != MLMC_OK:
+        raise MlmcError(code, "mlmc_serve_submit rejected the request")
+    return rid.value
+
+
+def mlmc_serve_poll(srv, max_results=4096):
+    buf = (mlmc_result * max_results)()
+    n = ctypes.c_int()
+    pend = ctypes.c_int64()
+    _check(None, _lib.mlmc_serve_poll(srv, buf, int(max_results), ctypes.byref(n),
+                                      ctypes.byref(pend)))
+    return [buf[q].as_dict() for q in range(n.value)], pend.value
+
+
+def mlmc_serve_now(srv):
+    return _lib.mlmc_serve_now(srv)
+
+
+def mlmc_serve_stats(srv):
+    b, qd, ru, fl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_uint64()
+    _check(None, _lib.mlmc_serve_stats(srv, ctypes.byref(b), ctypes.byref(qd), ctypes.byref(ru),
+                                       ctypes.byref(fl)))
+    return {"batches": b.value, "queued": qd.value, "running": ru.value,
+            "in_flight_bytes": fl.value}
+
+
+def mlmc_serve_stop(srv):
+    _check(None, _lib.mlmc_serve_stop(srv))

@@ -345,20 +345,21 @@ mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m,
   return fail(ctx, MLMC_EEMBED, "no valid circulant embedding with n_ce <= 4096");
 }
 
-mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
-                              uint64_t first_sample, int batch, double* k, double* k_coarse) {
+static mlmc_status sample_field_impl(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
+                                     uint64_t first_sample, const uint32_t* ids, int batch,
+                                     double* k, double* k_coarse) {
   if (!ctx) return MLMC_EINVAL;
   TRY(check_model(ctx, model));
   if (m < 1 || batch < 0 || level < 0 || !k) return fail(ctx, MLMC_EINVAL, "bad m/batch/level/k");
   if (k_coarse && (m % 2)) return fail(ctx, MLMC_EINVAL, "k_coarse needs an even m");
-  if (first_sample + (uint64_t)batch > (1ull << 32))
+  if (!ids && first_sample + (uint64_t)batch > (1ull << 32))
     return fail(ctx, MLMC_EINVAL, "sample numbers must fit in 32 bits");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
   hipStream_t st = ctx->stream;
   double* params = nullptr;
   TRY(ws(ctx, "params", (size_t)batch * kParamStride, &params));
-  launch_sample_params(st, *model, level, first_sample, batch, params);
+  launch_sample_params(st, *model, level, first_sample, ids, batch, params);
   if (model->field_kind == MLMC_FIELD_PIECEWISE_CONSTANT) {
     launch_field_pc(st, *model, m, batch, params, k);
     if (k_coarse) launch_field_pc(st, *model, m / 2, batch, params, k_coarse);
@@ -372,13 +373,25 @@ mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int
   const double cells = (double)batch * m * m;
   const double ratio = (double)e->n / m;
   timed(ctx, "k_ce_pass_a", cells * (16.0 * ratio + 8.0 * ratio * ratio), [&] {
-    launch_ce_pass_a(st, *model, level, first_sample, batch, m, e->sqT, e->tw, e->plan, uT);
+    launch_ce_pass_a(st, *model, level, first_sample, ids, batch, m, e->sqT, e->tw, e->plan, uT);
   });
   timed(ctx, "k_ce_pass_b", cells * (16.0 * ratio + 8.0 + (k_coarse ? 2.0 : 0.0)), [&] {
     launch_ce_pass_b(st, *model, batch, m, uT, e->tw, e->plan, params, k, k_coarse);
   });
   CHECK_LAUNCH();
   return MLMC_OK;
+}
+
+mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
+                              uint64_t first_sample, int batch, double* k, double* k_coarse) {
+  return sample_field_impl(ctx, model, m, level, first_sample, nullptr, batch, k, k_coarse);
+}
+
+mlmc_status mlmc_sample_field_ids(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
+                                  const uint32_t* sample_ids, int batch, double* k,
+                                  double* k_coarse) {
+  if (!sample_ids && batch > 0) return fail(ctx, MLMC_EINVAL, "sample_ids is NULL");
+  return sample_field_impl(ctx, model, m, level, 0, sample_ids, batch, k, k_coarse);
 }
 
 mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch, const double* k_fine,
@@ -650,9 +663,11 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   return MLMC_OK;
 }
 
-mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
-                           uint64_t first_sample, int n, int cgv, const mlmc_solver_opts* opts,
-                           mlmc_level_sums* sums, double* q_f, double* q_c, double* y) {
+static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
+                                  uint64_t first_sample, const uint32_t* ids, int n, int cgv,
+                                  const mlmc_solver_opts* opts, mlmc_level_sums* sums, double* q_f,
+                                  double* q_c, double* y, int32_t* failed_out,
+                                  int32_t* iters_out) {
   if (!ctx) return MLMC_EINVAL;
   TRY(check_model(ctx, model));
   TRY(check_opts(ctx, opts));
@@ -683,7 +698,8 @@ mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, in
 
   double* kc = nullptr;
   if (ncomp > 0) TRY(ws(ctx, "lr_kc", (size_t)n * ncomp * ncl, &kc));
-  TRY(mlmc_sample_field(ctx, model, m, level, first_sample, n, k, (ncomp == 1) ? kc : nullptr));
+  TRY(sample_field_impl(ctx, model, m, level, first_sample, ids, n, k,
+                        (ncomp == 1) ? kc : nullptr));
   if (ncomp == 4) TRY(mlmc_cgv_extract(ctx, 2, m, n, k, kc));
 
   TRY(mlmc_assemble(ctx, 2, m, n, k, T, tb, b));
@@ -716,6 +732,10 @@ mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, in
     else HIP_TRY(hipMemsetAsync(q_c, 0, sizeof(double) * n, st));
   }
   if (y) HIP_TRY(hipMemcpyAsync(y, yv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  if (failed_out)
+    HIP_TRY(hipMemcpyAsync(failed_out, failed, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  if (iters_out)
+    HIP_TRY(hipMemcpyAsync(iters_out, itf, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
   CHECK_LAUNCH();
   double* h = static_cast<double*>(ctx->host_pinned);
   HIP_TRY(hipMemcpyAsync(h, out, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
@@ -730,6 +750,22 @@ mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, in
   sums->iters_coarse += (int64_t)llround(h[6]);
   if (h[4] > 0.5) return fail(ctx, MLMC_ENOCONV, "some solves did not reach the tolerance");
   return MLMC_OK;
+}
+
+mlmc_status mlmc_level_run(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
+                           uint64_t first_sample, int n, int cgv, const mlmc_solver_opts* opts,
+                           mlmc_level_sums* sums, double* q_f, double* q_c, double* y) {
+  return level_run_impl(ctx, model, level, m_fine, first_sample, nullptr, n, cgv, opts, sums, q_f,
+                        q_c, y, nullptr, nullptr);
+}
+
+mlmc_status mlmc_level_run_ids(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
+                               const uint32_t* sample_ids, int n, int cgv,
+                               const mlmc_solver_opts* opts, mlmc_level_sums* sums, double* q_f,
+                               double* q_c, double* y, int32_t* failed, int32_t* iters) {
+  if (!sample_ids && n > 0) return fail(ctx, MLMC_EINVAL, "sample_ids is NULL");
+  return level_run_impl(ctx, model, level, m_fine, 0, sample_ids, n, cgv, opts, sums, q_f, q_c, y,
+                        failed, iters);
 }
 
 mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_estimate_t* out) {

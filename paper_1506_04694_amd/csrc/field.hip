@@ -36,12 +36,13 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 }
 
 // ------------------------------------------------------------ per-sample parameters
-__global__ void k_sample_params(mlmc_model mdl, uint32_t level, uint64_t first, int batch,
+__global__ void k_sample_params(mlmc_model mdl, uint32_t level, uint64_t first,
+                                const uint32_t* __restrict__ ids, int batch,
                                 double* __restrict__ params) {
 #pragma clang fp contract(off)
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= batch) return;
-  const uint32_t sample = (uint32_t)(first + (uint64_t)s);
+  const uint32_t sample = ids ? ids[s] : (uint32_t)(first + (uint64_t)s);
   double prm[kParamStride];
 #pragma unroll
   for (int q = 0; q < kParamStride; ++q) prm[q] = 0.0;
@@ -73,9 +74,9 @@ __global__ void k_sample_params(mlmc_model mdl, uint32_t level, uint64_t first, 
 }
 
 void launch_sample_params(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
-                          int batch, double* params) {
+                          const uint32_t* ids, int batch, double* params) {
   hipLaunchKernelGGL(k_sample_params, dim3(blocks_for(batch)), dim3(kBlock), 0, st, mdl,
-                     (uint32_t)level, first, batch, params);
+                     (uint32_t)level, first, ids, batch, params);
 }
 
 // ------------------------------------------------------------ Example 1 field
@@ -202,7 +203,8 @@ void launch_ce_sqrt_transpose(hipStream_t st, const double2* lam, int n, double*
 
 // ------------------------------------------------------------ pass A
 __global__ void __launch_bounds__(kBlock)
-k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, int m, const double* __restrict__ sqT,
+k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __restrict__ ids,
+            int m, const double* __restrict__ sqT,
             const double2* __restrict__ tw, FftPlan pl, double2* __restrict__ uT) {
   extern __shared__ double lds[];
   const int n = pl.n;
@@ -211,7 +213,7 @@ k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, int m, const double* 
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int k1 = blk % n;
   const int s = blk / n;
-  const uint32_t sample = (uint32_t)(first + (uint64_t)s);
+  const uint32_t sample = ids ? ids[s] : (uint32_t)(first + (uint64_t)s);
   const double* sq = sqT + (long long)k1 * n;
   // rows 2p and 2p+1 of this column share Philox block p n + k1
   for (int pr = threadIdx.x; 2 * pr < n; pr += kBlock) {
@@ -238,11 +240,11 @@ k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, int m, const double* 
 }
 
 void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
-                      int batch, int m, const double* sqT, const double2* tw, const FftPlan& pl,
-                      double2* uT) {
+                      const uint32_t* ids, int batch, int m, const double* sqT,
+                      const double2* tw, const FftPlan& pl, double2* uT) {
   const int nblocks = batch * pl.n;
   hipLaunchKernelGGL(k_ce_pass_a, dim3(nblocks), dim3(kBlock), 2 * pl.n * sizeof(double), st,
-                     mdl.seed, (uint32_t)level, first, m, sqT, tw, pl, uT);
+                     mdl.seed, (uint32_t)level, first, ids, m, sqT, tw, pl, uT);
 }
 
 // ------------------------------------------------------------ pass B

@@ -10,8 +10,9 @@
 namespace mlmc {
 
 // ------------------------------------------------------------- field.hip
+// Sample number of batch slot s: ids[s] when ids != NULL, else first + s.
 void launch_sample_params(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
-                          int batch, double* params);
+                          const uint32_t* ids, int batch, double* params);
 void launch_field_pc(hipStream_t st, const mlmc_model& mdl, int m, int batch,
                      const double* params, double* k);
 void launch_ce_twiddles(hipStream_t st, int n, double2* tw);
@@ -23,8 +24,8 @@ void launch_ce_minmax(hipStream_t st, const double2* lam, long long count, doubl
                       int nblocks);
 void launch_ce_sqrt_transpose(hipStream_t st, const double2* lam, int n, double* sqT);
 void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
-                      int batch, int m, const double* sqT, const double2* tw, const FftPlan& pl,
-                      double2* uT);
+                      const uint32_t* ids, int batch, int m, const double* sqT,
+                      const double2* tw, const FftPlan& pl, double2* uT);
 void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, int batch, int m,
                       const double2* uT, const double2* tw, const FftPlan& pl,
                       const double* params, double* k, double* k_coarse);

@@ -1,0 +1,316 @@
+// Continuous-batching request server for MLMC samples (host side).
+//
+// A request is one term of the estimator eq. (3.6) (or eq. (4.2) with Coarse
+// Grid Variates): sample number `sample` of level `level` on the m_fine grid,
+// i.e. the fine solve and its coarse companion(s) and Y = Q_f - Q_c.
+//
+// Requests are queued as they arrive.  Each worker thread owns a context (its
+// own HIP stream at default priority and its own device workspaces, which stay
+// allocated between batches: fields, operators and multigrid hierarchies are
+// device-resident) and repeatedly takes the oldest waiting request together
+// with up to max_batch - 1 later requests for the same (level, grid), as long
+// as the estimated device memory of all running batches stays within the
+// budget; a lone request always runs when nothing else is running.  Batches of
+// different workers run concurrently on the device, so requests that arrive
+// while others are being solved start as soon as a worker and memory are free.
+// A sample's results do not depend on its batch (per-sample random streams and
+// per-sample fixed-order reductions), so a request gives the same numbers
+// alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/mlmc_darcy.h"
+
+namespace {
+
+struct Pending {
+  uint64_t id;
+  mlmc_request req;
+  double t_submit;
+};
+
+struct Worker {
+  mlmc_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  std::thread thread;
+  // device staging for one batch
+  uint32_t* d_ids = nullptr;
+  double* d_out = nullptr;     // q_f, q_c, y: 3 * max_batch
+  int32_t* d_flags = nullptr;  // failed, iters: 2 * max_batch
+  uint32_t* h_ids = nullptr;   // pinned
+  double* h_out = nullptr;
+  int32_t* h_flags = nullptr;
+};
+
+}  // namespace
+
+struct mlmc_server {
+  mlmc_serve_opts opts;
+  mlmc_model model;
+  std::vector<Worker> workers;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Pending> queue;
+  std::vector<mlmc_result> done;
+  uint64_t next_id = 1;
+  uint64_t in_flight_bytes = 0;
+  int running = 0;
+  bool stop = false;
+  std::string err;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  std::atomic<int64_t> batches{0};
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+int n_ce_for(const mlmc_server* s, int m) {
+  for (int q = 0; q < s->opts.n_grids; ++q)
+    if (s->opts.grid_m[q] == m) return s->opts.grid_n_ce[q];
+  return 0;
+}
+
+// Device bytes of one request's share of a batch: k, T (2), b, p, r, z, p, q,
+// z_pre and the multigrid hierarchy (about 1/3 of a level per array), plus the
+// companions on the coarse grid (1 plain, 4 with CGV), all FP64.
+uint64_t request_bytes(const mlmc_server* s, const mlmc_request& r) {
+  const double cells = (double)r.m_fine * r.m_fine;
+  const double ncomp = r.level == 0 ? 0.0 : (s->opts.cgv ? 4.0 : 1.0);
+  const double per_cell = 8.0 * (10.0 + 4.0 * 4.0 / 3.0);
+  double ce = 0.0;
+  const int nce = n_ce_for(s, r.m_fine);
+  if (s->model.field_kind == MLMC_FIELD_CORRELATED) ce = 16.0 * (double)nce * r.m_fine;
+  return (uint64_t)(cells * per_cell * (1.0 + ncomp / 4.0) + ce);
+}
+
+void worker_loop(mlmc_server* s, int wi) {
+  Worker& w = s->workers[wi];
+  (void)hipSetDevice(s->opts.device);
+  const int maxb = s->opts.max_batch;
+  std::vector<Pending> batch;
+  batch.reserve(maxb);
+  for (;;) {
+    uint64_t bytes = 0;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      for (;;) {
+        if (s->stop) return;
+        if (!s->queue.empty()) {
+          const mlmc_request key = s->queue.front().req;
+          const uint64_t one = request_bytes(s, key);
+          const uint64_t budget = s->opts.hbm_budget_bytes;
+          const bool fits_one = s->in_flight_bytes + one <= budget || s->running == 0;
+          if (fits_one) {
+            batch.clear();
+            bytes = 0;
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < maxb;) {
+              if (it->req.level == key.level && it->req.m_fine == key.m_fine &&
+                  (batch.empty() || s->in_flight_bytes + bytes + one <= budget)) {
+                batch.push_back(*it);
+                bytes += one;
+                it = s->queue.erase(it);
+              } else {
+                ++it;
+              }
+            }
+            s->in_flight_bytes += bytes;
+            ++s->running;
+            break;
+          }
+        }
+        s->cv.wait(lk);
+      }
+    }
+    const double t_start = s->now();
+    const int n = (int)batch.size();
+    for (int q = 0; q < n; ++q) w.h_ids[q] = batch[q].req.sample;
+    mlmc_model mdl = s->model;
+    mdl.n_ce = n_ce_for(s, batch[0].req.m_fine);
+    mlmc_level_sums sums;
+    std::memset(&sums, 0, sizeof sums);
+    mlmc_status st = MLMC_OK;
+    if (hipMemcpyAsync(w.d_ids, w.h_ids, sizeof(uint32_t) * n, hipMemcpyHostToDevice, w.stream) !=
+        hipSuccess)
+      st = MLMC_EDEVICE;
+    if (st == MLMC_OK)
+      st = mlmc_level_run_ids(w.ctx, &mdl, batch[0].req.level, batch[0].req.m_fine, w.d_ids, n,
+                              s->opts.cgv, &s->opts.solver, &sums, w.d_out, w.d_out + maxb,
+                              w.d_out + 2 * maxb, w.d_flags, w.d_flags + maxb);
+    if (st == MLMC_OK || st == MLMC_ENOCONV) {
+      (void)hipMemcpyAsync(w.h_out, w.d_out, sizeof(double) * 3 * maxb, hipMemcpyDeviceToHost,
+                           w.stream);
+      (void)hipMemcpyAsync(w.h_flags, w.d_flags, sizeof(int32_t) * 2 * maxb,
+                           hipMemcpyDeviceToHost, w.stream);
+      (void)hipStreamSynchronize(w.stream);
+    }
+    const double t_done = s->now();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (int q = 0; q < n; ++q) {
+        mlmc_result r;
+        std::memset(&r, 0, sizeof r);
+        r.id = batch[q].id;
+        r.level = batch[q].req.level;
+        r.m_fine = batch[q].req.m_fine;
+        r.sample = batch[q].req.sample;
+        r.batch_size = n;
+        r.t_submit = batch[q].t_submit;
+        r.t_start = t_start;
+        r.t_done = t_done;
+        if (st == MLMC_OK || st == MLMC_ENOCONV) {
+          r.q_f = w.h_out[q];
+          r.q_c = w.h_out[maxb + q];
+          r.y = w.h_out[2 * maxb + q];
+          r.failed = w.h_flags[q];
+          r.iters = w.h_flags[maxb + q];
+          r.status = MLMC_OK;
+        } else {
+          r.failed = 1;
+          r.status = st;
+        }
+        s->done.push_back(r);
+      }
+      if (st != MLMC_OK && st != MLMC_ENOCONV) s->err = mlmc_last_error(w.ctx);
+      s->in_flight_bytes -= bytes;
+      --s->running;
+      s->batches++;
+    }
+    s->cv.notify_all();
+  }
+}
+
+void release(mlmc_server* s) {
+  for (auto& w : s->workers) {
+    if (w.ctx) mlmc_ctx_destroy(w.ctx);
+    if (w.stream) (void)hipStreamDestroy(w.stream);
+    if (w.d_ids) (void)hipFree(w.d_ids);
+    if (w.d_out) (void)hipFree(w.d_out);
+    if (w.d_flags) (void)hipFree(w.d_flags);
+    if (w.h_ids) (void)hipHostFree(w.h_ids);
+    if (w.h_out) (void)hipHostFree(w.h_out);
+    if (w.h_flags) (void)hipHostFree(w.h_flags);
+  }
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlmc_status mlmc_serve_opts_default(mlmc_serve_opts* o) {
+  if (!o) return MLMC_EINVAL;
+  std::memset(o, 0, sizeof *o);
+  o->device = 0;
+  o->n_workers = 3;
+  o->max_batch = 256;
+  o->cgv = 0;
+  o->hbm_budget_bytes = 64ull << 30;
+  return mlmc_solver_opts_default(&o->solver);
+}
+
+mlmc_status mlmc_serve_start(const mlmc_model* model, const mlmc_serve_opts* opts,
+                             mlmc_server** out) {
+  if (!model || !opts || !out) return MLMC_EINVAL;
+  *out = nullptr;
+  if (opts->n_workers < 1 || opts->n_workers > 16 || opts->max_batch < 1 ||
+      opts->n_grids < 0 || opts->n_grids > 8)
+    return MLMC_EINVAL;
+  mlmc_server* s = new mlmc_server();
+  s->opts = *opts;
+  s->model = *model;
+  s->workers.resize(opts->n_workers);
+  if (hipSetDevice(opts->device) != hipSuccess) {
+    delete s;
+    return MLMC_EDEVICE;
+  }
+  const int maxb = opts->max_batch;
+  for (auto& w : s->workers) {
+    bool ok = hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) == hipSuccess &&
+              mlmc_ctx_create(opts->device, w.stream, &w.ctx) == MLMC_OK &&
+              hipMalloc(&w.d_ids, sizeof(uint32_t) * maxb) == hipSuccess &&
+              hipMalloc(&w.d_out, sizeof(double) * 3 * maxb) == hipSuccess &&
+              hipMalloc(&w.d_flags, sizeof(int32_t) * 2 * maxb) == hipSuccess &&
+              hipHostMalloc(&w.h_ids, sizeof(uint32_t) * maxb, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&w.h_out, sizeof(double) * 3 * maxb, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&w.h_flags, sizeof(int32_t) * 2 * maxb, hipHostMallocDefault) ==
+                  hipSuccess;
+    if (!ok) {
+      release(s);
+      return MLMC_ENOMEM;
+    }
+  }
+  for (int wi = 0; wi < opts->n_workers; ++wi)
+    s->workers[wi].thread = std::thread(worker_loop, s, wi);
+  *out = s;
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_serve_submit(mlmc_server* s, const mlmc_request* req, uint64_t* id) {
+  if (!s || !req) return MLMC_EINVAL;
+  if (req->level < 0 || req->m_fine < 1 || (req->level > 0 && req->m_fine % 2))
+    return MLMC_EINVAL;
+  if (s->model.field_kind == MLMC_FIELD_CORRELATED && n_ce_for(s, req->m_fine) == 0)
+    return MLMC_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return MLMC_EINVAL;
+    Pending p{s->next_id++, *req, s->now()};
+    if (id) *id = p.id;
+    s->queue.push_back(p);
+  }
+  s->cv.notify_all();
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_serve_poll(mlmc_server* s, mlmc_result* out, int max, int* n_out,
+                            int64_t* pending) {
+  if (!s || !n_out || (max > 0 && !out)) return MLMC_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  const int n = std::min<int>(max, (int)s->done.size());
+  for (int q = 0; q < n; ++q) out[q] = s->done[q];
+  s->done.erase(s->done.begin(), s->done.begin() + n);
+  *n_out = n;
+  if (pending) *pending = (int64_t)s->queue.size() + (int64_t)s->done.size();
+  return MLMC_OK;
+}
+
+double mlmc_serve_now(const mlmc_server* s) { return s ? s->now() : 0.0; }
+
+mlmc_status mlmc_serve_stats(mlmc_server* s, int64_t* batches, int64_t* queued, int* running,
+                             uint64_t* in_flight_bytes) {
+  if (!s) return MLMC_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (batches) *batches = s->batches.load();
+  if (queued) *queued = (int64_t)s->queue.size();
+  if (running) *running = s->running;
+  if (in_flight_bytes) *in_flight_bytes = s->in_flight_bytes;
+  return MLMC_OK;
+}
+
+mlmc_status mlmc_serve_stop(mlmc_server* s) {
+  if (!s) return MLMC_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (auto& w : s->workers)
+    if (w.thread.joinable()) w.thread.join();
+  release(s);
+  return MLMC_OK;
+}
+
+}  // extern "C"

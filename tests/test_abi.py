@@ -24,7 +24,7 @@ def lib():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+char\*|mlmc_status)\s+(mlmc_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\*|mlmc_status|double)\s+(mlmc_\w+)\s*\(", text, re.M)))
 
 
 def test_every_declared_symbol_is_exported(lib):
