@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--no-per-sample", action="store_true",
                     help="skip timing the unbatched one-sample-per-call GPU path")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--serve-rates", default="0.5,0.8",
+                    help="offered request rates as fractions of the batched throughput ('' = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="seconds of Poisson arrivals per offered rate")
     return ap.parse_args()
 
 
@@ -76,6 +80,57 @@ def cpu_baseline(wl, budget_s):
                          "/".join("%d^2" % m for m in wl.m_levels),
                          "/".join(str(n) for n in wl.n_samples), spent),
             "per_level_s_per_sample": [p["s_per_sample"] for p in per_level]}
+
+
+def serving_latency(lib, wl, rate, seconds, seed=1):
+    """Poisson arrivals of single-sample requests with the workload's level mix
+    (probability of level l proportional to N_l), served by the continuous-
+    batching server; latency = completion - submission on the server clock."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    probs = np.array(wl.n_samples, dtype=float)
+    probs /= probs.sum()
+    n_req = max(50, int(rate * seconds))
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    levels = rng.choice(len(wl.m_levels), size=n_req, p=probs)
+    opts = lib.serve_opts_for(wl.model, wl.m_levels, n_workers=3, max_batch=512, cgv=int(wl.cgv))
+    srv = lib.mlmc_serve_start(wl.model, opts)
+    results = {}
+    counters = [10 ** 7] * len(wl.m_levels)
+    try:
+        t = lib.mlmc_serve_now(srv) + 0.05
+        for g, lvl in zip(gaps, levels):
+            t += g
+            while lib.mlmc_serve_now(srv) < t:
+                pass
+            lib.mlmc_serve_submit(srv, int(lvl), wl.m_levels[lvl], counters[lvl])
+            counters[lvl] += 1
+            if len(results) % 64 == 0:
+                for r in lib.mlmc_serve_poll(srv)[0]:
+                    results[r["id"]] = r
+        t_end = time.time() + 60
+        while len(results) < n_req and time.time() < t_end:
+            for r in lib.mlmc_serve_poll(srv)[0]:
+                results[r["id"]] = r
+            time.sleep(0.001)
+        stats = lib.mlmc_serve_stats(srv)
+    finally:
+        lib.mlmc_serve_stop(srv)
+    rs = list(results.values())
+    lat = np.array([r["t_done"] - r["t_submit"] for r in rs])
+    span = max(r["t_done"] for r in rs) - min(r["t_submit"] for r in rs)
+    per_level = []
+    for lvl, m in enumerate(wl.m_levels):
+        ll = np.array([r["t_done"] - r["t_submit"] for r in rs if r["level"] == lvl])
+        if ll.size:
+            per_level.append({"level": lvl, "m": m, "requests": int(ll.size),
+                              "p50_ms": 1e3 * float(np.percentile(ll, 50)),
+                              "p99_ms": 1e3 * float(np.percentile(ll, 99))})
+    return {"offered_per_s": rate, "completed": len(rs), "submitted": n_req,
+            "achieved_per_s": len(rs) / span, "failed": int(sum(r["failed"] for r in rs)),
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "mean_batch": float(np.mean([r["batch_size"] for r in rs])), "batches": stats["batches"],
+            "per_level": per_level}
 
 
 def main():
@@ -144,6 +199,12 @@ def main():
 
     ms_per_step = 1e3 * elapsed / args.steps
     total = sum(wl.n_samples)
+    serving = None
+    if args.serve_rates:
+        sat = total / (elapsed / args.steps)
+        serving = {"saturation_estimate_per_s": sat, "workers": 3, "precision": "f64",
+                   "runs": [serving_latency(lib, wl, float(f) * sat, args.serve_seconds)
+                            for f in args.serve_rates.split(",") if f]}
     per_level = []
     for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
         t = sorted(level_times[level])[len(level_times[level]) // 2]
@@ -169,7 +230,7 @@ def main():
                       "model": "2 layers, 8-node interface, exp. covariance r=2, sigma2=1, "
                                "lambda=0.3, means 0/2"},
            "per_level": per_level, "estimate": est, "roofline": roof,
-           "per_sample_fp64_gpu": single}
+           "per_sample_fp64_gpu": single, "serving": serving}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)

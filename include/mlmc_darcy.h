@@ -259,6 +259,20 @@ mlmc_status mlmc_level_run_ids(mlmc_ctx* ctx, const mlmc_model* model, int level
                                const mlmc_solver_opts* opts, mlmc_level_sums* sums, double* q_f,
                                double* q_c, double* y, int32_t* failed, int32_t* iters);
 
+/* Every level of the estimator in one call: level l has n[l] samples starting
+ * at first_sample[l] on the m_fine[l] grid (embedding size n_ce[l] for
+ * correlated fields; n_ce may be NULL for piecewise constant models) and
+ * solver options opts[l].  Samples that share a grid -- the fine samples of
+ * one level and the coarse companions of the next finer level -- are solved in
+ * one batch with the options of the level whose fine grid it is, so the
+ * estimator takes one multigrid-PCG solve per distinct grid size.  Results
+ * are those of mlmc_level_run for each level (same samples, same numbers).
+ * All inputs host; sums[n_levels] (host) accumulate.  Synchronises. */
+mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels,
+                            const int* m_fine, const int* n_ce, const uint64_t* first_sample,
+                            const int* n, int cgv, const mlmc_solver_opts* opts,
+                            mlmc_level_sums* sums);
+
 /* Estimator eq. (3.6) and the statistical part of eq. (3.7) from per-level
  * sums (host arithmetic only).  levels: host [n_levels]; out: host. */
 mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_estimate_t* out);

@@ -33,7 +33,7 @@ EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_
             "mlmc_level_run", "mlmc_estimate", "mlmc_profile_enable", "mlmc_profile_read",
             "mlmc_sample_field_ids", "mlmc_level_run_ids", "mlmc_serve_opts_default",
             "mlmc_serve_start", "mlmc_serve_submit", "mlmc_serve_poll", "mlmc_serve_now",
-            "mlmc_serve_stats", "mlmc_serve_stop"]
+            "mlmc_serve_stats", "mlmc_serve_stop", "mlmc_run_levels"]
 
 
 class mlmc_model(ctypes.Structure):
@@ -132,6 +132,10 @@ _SIGS = {
     "mlmc_serve_stats": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_uint64)]),
     "mlmc_serve_stop": (_S, [_P]),
+    "mlmc_run_levels": (_S, [_P, ctypes.POINTER(mlmc_model), _I, ctypes.POINTER(_I),
+                             ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_uint64),
+                             ctypes.POINTER(_I), _I, ctypes.POINTER(mlmc_solver_opts),
+                             ctypes.POINTER(mlmc_level_sums)]),
     "mlmc_profile_read": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double)]),
 }
@@ -406,3 +410,23 @@ def mlmc_serve_stats(srv):
 
 def mlmc_serve_stop(srv):
     _check(None, _lib.mlmc_serve_stop(srv))
+
+
+def mlmc_run_levels(ctx, model, m_fine, first_sample, n, cgv, opts, sums=None, allow_noconv=False):
+    """All levels in one call; opts is one mlmc_solver_opts or a list (one per level).
+    Returns the list of mlmc_level_sums."""
+    L = len(m_fine)
+    if isinstance(opts, mlmc_solver_opts):
+        opts = [opts] * L
+    mm = make_model(model)
+    nce = [int(model.n_ce.get(m, 0)) if getattr(model, "n_ce", None) else 0 for m in m_fine]
+    if sums is None:
+        sums = [mlmc_level_sums() for _ in range(L)]
+    arr_s = (mlmc_level_sums * L)(*sums)
+    code = _lib.mlmc_run_levels(ctx, ctypes.byref(mm), L, (ctypes.c_int * L)(*m_fine),
+                                (ctypes.c_int * L)(*nce), (ctypes.c_uint64 * L)(*first_sample),
+                                (ctypes.c_int * L)(*n), int(bool(cgv)),
+                                (mlmc_solver_opts * L)(*opts), arr_s)
+    if not (allow_noconv and code == MLMC_ENOCONV):
+        _check(ctx, code)
+    return [arr_s[q] for q in range(L)]

@@ -768,6 +768,161 @@ mlmc_status mlmc_level_run_ids(mlmc_ctx* ctx, const mlmc_model* model, int level
                         failed, iters);
 }
 
+mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels,
+                            const int* m_fine, const int* n_ce, const uint64_t* first_sample,
+                            const int* n, int cgv, const mlmc_solver_opts* opts,
+                            mlmc_level_sums* sums) {
+  if (!ctx) return MLMC_EINVAL;
+  TRY(check_model(ctx, model));
+  if (n_levels < 1 || n_levels > 16 || !m_fine || !first_sample || !n || !opts || !sums)
+    return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_run_levels");
+  for (int l = 0; l < n_levels; ++l) {
+    TRY(check_opts(ctx, &opts[l]));
+    if (m_fine[l] < 1 || n[l] < 0 || (l > 0 && m_fine[l] % 2))
+      return fail(ctx, MLMC_EINVAL, "bad level size or sample count");
+  }
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  const int ncomp = cgv ? 4 : 1;
+
+  // Grid groups: fine samples of level l (grid m_l) and companions of level
+  // l' >= 1 (grid m_l' / 2); group order = first appearance, fine before
+  // companion, so level l's fine samples precede level l+1's companions.
+  struct Part {
+    int level, role;  // role 0 fine, 1 companions
+    long long off;    // first sample of the part within its group
+    long long count;
+  };
+  struct Group {
+    int m;
+    int opts_level;
+    long long count = 0;
+    std::vector<Part> parts;
+  };
+  std::vector<Group> groups;
+  auto group_of = [&](int m, int lvl) -> Group& {
+    for (auto& g : groups)
+      if (g.m == m) return g;
+    groups.push_back(Group{});
+    groups.back().m = m;
+    groups.back().opts_level = lvl;
+    return groups.back();
+  };
+  for (int l = 0; l < n_levels; ++l) {
+    Group& g = group_of(m_fine[l], l);
+    g.parts.push_back(Part{l, 0, g.count, n[l]});
+    g.count += n[l];
+    if (l > 0) {
+      Group& gc = group_of(m_fine[l] / 2, l);
+      gc.parts.push_back(Part{l, 1, gc.count, (long long)n[l] * ncomp});
+      gc.count += (long long)n[l] * ncomp;
+    }
+  }
+  // per group: k, T, tb, b, p, q, status, iters, relres
+  struct GroupBuf {
+    double *k, *T, *tb, *b, *p, *q, *rr;
+    int32_t *stt, *it;
+  };
+  std::vector<GroupBuf> gb(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const long long B = std::max<long long>(groups[gi].count, 1);
+    const long long cells = (long long)groups[gi].m * groups[gi].m;
+    const std::string tag = "rl" + std::to_string(gi) + "_";
+    TRY(ws(ctx, tag + "k", B * cells, &gb[gi].k));
+    TRY(ws(ctx, tag + "T", B * 2 * cells, &gb[gi].T));
+    TRY(ws(ctx, tag + "tb", (size_t)B * 2 * groups[gi].m, &gb[gi].tb));
+    TRY(ws(ctx, tag + "b", B * cells, &gb[gi].b));
+    TRY(ws(ctx, tag + "p", B * cells, &gb[gi].p));
+    TRY(ws(ctx, tag + "q", B, &gb[gi].q));
+    TRY(ws(ctx, tag + "rr", B, &gb[gi].rr));
+    TRY(ws(ctx, tag + "st", B, &gb[gi].stt));
+    TRY(ws(ctx, tag + "it", B, &gb[gi].it));
+  }
+  auto find = [&](int m, int level, int role, size_t* gi_out) -> const Part* {
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+      if (groups[gi].m == m)
+        for (auto& pt : groups[gi].parts)
+          if (pt.level == level && pt.role == role) {
+            *gi_out = gi;
+            return &pt;
+          }
+    return nullptr;
+  };
+  // sample every level straight into its group slots (plain companions too)
+  for (int l = 0; l < n_levels; ++l) {
+    if (n[l] == 0) continue;
+    size_t gf = 0, gcp = 0;
+    const Part* pf = find(m_fine[l], l, 0, &gf);
+    const Part* pc = l > 0 ? find(m_fine[l] / 2, l, 1, &gcp) : nullptr;
+    const long long cf = (long long)m_fine[l] * m_fine[l];
+    double* kf = gb[gf].k + pf->off * cf;
+    double* kc = nullptr;
+    if (pc) kc = gb[gcp].k + pc->off * (long long)(m_fine[l] / 2) * (m_fine[l] / 2);
+    mlmc_model mdl = *model;
+    mdl.n_ce = n_ce ? n_ce[l] : model->n_ce;
+    TRY(sample_field_impl(ctx, &mdl, m_fine[l], l, first_sample[l], nullptr, n[l], kf,
+                          (pc && !cgv) ? kc : nullptr));
+    if (pc && cgv) TRY(mlmc_cgv_extract(ctx, 2, m_fine[l], n[l], kf, kc));
+  }
+  // one assemble + solve + QoI per grid
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
+    if (g.count == 0) continue;
+    TRY(mlmc_assemble(ctx, 2, g.m, (int)g.count, gb[gi].k, gb[gi].T, gb[gi].tb, gb[gi].b));
+    TRY(mlmc_solve(ctx, 2, g.m, (int)g.count, gb[gi].T, gb[gi].tb, gb[gi].b, gb[gi].p,
+                   &opts[g.opts_level], gb[gi].stt, gb[gi].it, gb[gi].rr));
+    TRY(mlmc_qoi_outflow(ctx, 2, g.m, (int)g.count, gb[gi].k, gb[gi].p, gb[gi].q, nullptr));
+  }
+  // per level: Y, failures, sums
+  double *yv, *qcv, *out;
+  int32_t* failed;
+  long long nmax = 1;
+  for (int l = 0; l < n_levels; ++l) nmax = std::max<long long>(nmax, n[l]);
+  TRY(ws(ctx, "rlv_y", nmax, &yv));
+  TRY(ws(ctx, "rlv_qc", nmax, &qcv));
+  TRY(ws(ctx, "rlv_failed", nmax, &failed));
+  TRY(ws(ctx, "rlv_out", 8 * n_levels, &out));
+  for (int l = 0; l < n_levels; ++l) {
+    if (n[l] == 0) continue;
+    size_t gf = 0, gcp = 0;
+    const Part* pf = find(m_fine[l], l, 0, &gf);
+    const Part* pc = l > 0 ? find(m_fine[l] / 2, l, 1, &gcp) : nullptr;
+    const double* qf = gb[gf].q + pf->off;
+    const int32_t* stf = gb[gf].stt + pf->off;
+    const int32_t* itf = gb[gf].it + pf->off;
+    const double* qc = nullptr;
+    const int32_t *stc = nullptr, *itc = nullptr;
+    if (pc) {
+      launch_cgv_average(st, n[l], ncomp, gb[gcp].q + pc->off, qcv);
+      qc = qcv;
+      stc = gb[gcp].stt + pc->off;
+      itc = gb[gcp].it + pc->off;
+    }
+    launch_y_and_fail(st, n[l], qf, qc, stf, stc, pc ? ncomp : 0, yv, failed);
+    launch_level_reduce(st, n[l], yv, qf, qc, failed, itf, itc, pc ? ncomp : 0, out + 8 * l);
+  }
+  CHECK_LAUNCH();
+  std::vector<double> h(8 * n_levels);
+  HIP_TRY(hipMemcpyAsync(h.data(), out, sizeof(double) * 8 * n_levels, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  bool any_failed = false;
+  for (int l = 0; l < n_levels; ++l) {
+    if (n[l] == 0) continue;
+    const double* hl = h.data() + 8 * l;
+    sums[l].n += n[l];
+    sums[l].sum_y += hl[0];
+    sums[l].sum_y2 += hl[1];
+    sums[l].sum_qf += hl[2];
+    sums[l].sum_qc += hl[3];
+    sums[l].n_failed += (int64_t)llround(hl[4]);
+    sums[l].iters_fine += (int64_t)llround(hl[5]);
+    sums[l].iters_coarse += (int64_t)llround(hl[6]);
+    any_failed |= hl[4] > 0.5;
+  }
+  if (any_failed) return fail(ctx, MLMC_ENOCONV, "some solves did not reach the tolerance");
+  return MLMC_OK;
+}
+
 mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_estimate_t* out) {
   if (!levels || !out || n_levels < 1) return MLMC_EINVAL;
   double est = 0.0, var = 0.0;

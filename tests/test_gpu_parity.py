@@ -389,3 +389,20 @@ def test_mixed_precision_requires_fused(lib, ctx):
     kh = np.ones((1, 16, 16))
     with pytest.raises(lib.MlmcError):
         solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=1, variant=1))
+
+
+# ------------------------------------------------------------------ all levels in one call
+@pytest.mark.parametrize("cgv", [False, True])
+def test_run_levels_matches_level_runs(lib, ctx, cgv):
+    """Merging level l's fine samples with level l+1's companions into one solve per
+    grid does not change any sample's numbers, so the level sums are identical."""
+    model, ms, ns = W.CE2, [32, 64, 128], [48, 24, 8]
+    per = []
+    for level, (m, n) in enumerate(zip(ms, ns)):
+        per.append(lib.mlmc_level_run(ctx, model, level, m, 7, n, cgv,
+                                      lib.mlmc_solver_opts_default()))
+    allv = lib.mlmc_run_levels(ctx, model, ms, [7, 7, 7], ns, cgv, lib.mlmc_solver_opts_default())
+    for a, b in zip(per, allv):
+        assert a.n == b.n and a.n_failed == b.n_failed == 0
+        assert (a.sum_y, a.sum_y2, a.sum_qf, a.sum_qc) == (b.sum_y, b.sum_y2, b.sum_qf, b.sum_qc)
+        assert a.iters_fine == b.iters_fine and a.iters_coarse == b.iters_coarse
