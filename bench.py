@@ -43,6 +43,8 @@ def parse():
                     help="offered request rates as fractions of the batched throughput ('' = skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals per offered rate")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -133,8 +135,50 @@ def serving_latency(lib, wl, rate, seconds, seed=1):
             "per_level": per_level}
 
 
+KERNEL_SOURCES = {"k_mg_up": "mg_fused.hip", "k_mg_down": "mg_fused.hip",
+                  "k_mg_coarse_cycle": "mg_fused.hip", "k_spmv_dot": "mg_pcg.hip",
+                  "k_axpy_dot": "mg_pcg.hip", "k_ce_pass_a": "field.hip", "k_ce_pass_b": "field.hip"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/traffic_<kernel>.json), or None when there is none or the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+    src = KERNEL_SOURCES.get(kernel)
+    if not os.path.exists(path) or src is None:
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, "paper_1506_04694_amd", "csrc", src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration():
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB), three times."""
+    import torch
+    n = 2 ** 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n,
+                      "ms": 1e3 * dt, "GB_s_read_plus_write": 16 * n / dt / 1e9}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the sample-parallel path on a single "
               "MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -200,7 +244,7 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     total = sum(wl.n_samples)
     serving = None
-    if args.serve_rates:
+    if args.serve_rates and args.serve_rates != "none":
         sat = total / (elapsed / args.steps)
         serving = {"saturation_estimate_per_s": sat, "workers": 3, "precision": "f64",
                    "runs": [serving_latency(lib, wl, float(f) * sat, args.serve_seconds)
@@ -218,7 +262,8 @@ def main():
         achieved = prof["algorithmic_bytes"] / (prof["total_ms"] * 1e-3) / 1e9
         roof = {"kernel": args.kernel, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "launches": prof["launches"], "avg_launch_ms": avg_ms,
+                "traffic": measured_traffic(args.kernel), "launches": prof["launches"],
+                "avg_launch_ms": avg_ms,
                 "algorithmic_bytes_per_launch": prof["algorithmic_bytes"] / prof["launches"]}
     out = {"metric": METRIC, "value": total / (elapsed / args.steps), "unit": "samples/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
