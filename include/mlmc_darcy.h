@@ -130,7 +130,8 @@ typedef struct mlmc_solver_opts {
   int32_t variant;      /* 0: fused LDS-tiled V-cycle kernels (needs nu1 = nu2 = 1,
                            else falls back to 1); 1: one launch per sweep / step     */
   int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1   */
-  int32_t reserved;
+  int32_t cycle_max;    /* variant 0: levels of at most this size (2..32, 0 = 32) run
+                           in one workgroup per sample                              */
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */

@@ -23,6 +23,7 @@ DEFAULT_SPACE = {
     "omega": [1.8, 2.0, 2.2],
     "coarse_max": [2, 4, 8],
     "check_every": [4, 8],
+    "cycle_max": [16, 32],
 }
 
 

@@ -249,6 +249,8 @@ mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
   if (!(o->omega > 0.0)) return fail(ctx, MLMC_EINVAL, "omega must be positive");
   if (o->precision < MLMC_PREC_FP64 || o->precision > MLMC_PREC_BF16)
     return fail(ctx, MLMC_EINVAL, "unknown precision");
+  if (o->cycle_max < 0 || o->cycle_max == 1 || o->cycle_max > kCoarseCycleMax)
+    return fail(ctx, MLMC_EINVAL, "cycle_max must be 0 or in [2, 32]");
   return MLMC_OK;
 }
 
@@ -547,7 +549,8 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   CoarseDesc cdesc{};
   if (fused) {
     l0 = 0;
-    while (l0 < L && (ms[l0] > kCoarseCycleMax || L - l0 + 1 > kMaxCoarseLevels)) ++l0;
+    const int cmax = opts->cycle_max > 0 ? opts->cycle_max : kCoarseCycleMax;
+    while (l0 < L && (ms[l0] > cmax || L - l0 + 1 > kMaxCoarseLevels)) ++l0;
     for (int l = 0; l < l0; ++l)
       TRY(ws_get(ctx, lv("s_zpre", l), batch * (size_t)ms[l] * ms[l] * eb + 256, &zpre[l]));
     for (int q2 = 0; q2 + l0 <= L; ++q2) {
@@ -628,20 +631,36 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     }
   };
 
+  // CG direction: fused p-update + operator (ping-pong p buffers) when the
+  // finest grid takes fixed tiles, else separate p-update and operator kernels
+  const bool dir_fused = fused && cg_direction_fused(m);
+  double* pbuf[2] = {pv, nullptr};
+  if (dir_fused) TRY(ws(ctx, "s_p2", batch * n, &pbuf[1]));
+  const int dir_parts = dir_fused ? mg_tiles_per_sample(m) : bps;
+
   launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps);
   launch_sc_init(st, batch, partial, bps, S, status, iters, relres);
   vcycle();
   launch_sc_rho(st, batch, partial, rz_parts, S, status, 1, nullptr, 0);
-  launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
+  if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
   CHECK_LAUNCH();
 
   int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
   const int check = opts->check_every > 0 ? opts->check_every : 1;
   for (int it = 1;; ++it) {
-    timed(ctx, "k_spmv_dot", cells0 * kBytesSpmv, [&] {
-      launch_spmv_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
-    });
-    launch_sc_alpha(st, batch, partial, bps, S, status);
+    if (dir_fused) {
+      // iteration it writes p into pbuf[it % 2] from pbuf[(it - 1) % 2]
+      pv = pbuf[it & 1];
+      timed(ctx, "k_cg_direction_t", cells0 * 48.0, [&] {
+        launch_cg_direction(st, m, batch, T, tb, z, pbuf[(it - 1) & 1], pv, q, S.beta, it == 1,
+                            partial, S.active);
+      });
+    } else {
+      timed(ctx, "k_spmv_dot", cells0 * kBytesSpmv, [&] {
+        launch_spmv_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
+      });
+    }
+    launch_sc_alpha(st, batch, partial, dir_parts, S, status);
     timed(ctx, "k_axpy_dot", cells0 * (kBytesAxpy + (flexible ? 8.0 : 0.0)), [&] {
       launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,
                       flexible ? z : nullptr, partial2);
@@ -655,7 +674,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     }
     vcycle();
     launch_sc_rho(st, batch, partial, rz_parts, S, status, 0, partial2, bps);
-    launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
+    if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
   }
   launch_true_residual(st, m, batch, T, tb, b, p, partial, bps);
   launch_sc_final(st, batch, partial, bps, S, relres);

@@ -96,6 +96,12 @@ void launch_mg_coarse_cycle(hipStream_t st, int prec, bool top, int batch, int n
                             const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
                             double omega, const int32_t* active, double* rz_partial);
 void launch_convert(hipStream_t st, int prec, long long count, const double* x, void* y);
+// p_new = z + beta p_old (z when first), q = A p_new, partial[s * tiles + tile] = p_new . q;
+// available when cg_direction_fused(m) (fixed tiles; mg_tiles_per_sample(m) partials)
+bool cg_direction_fused(int m);
+void launch_cg_direction(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                         const double* z, const double* pold, double* pnew, double* q,
+                         const double* beta, int first, double* partial, const int32_t* active);
 
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
                      double* partial, int bps);

@@ -296,6 +296,75 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   }
 }
 
+// ------------------------------------------------------------------ CG direction + operator
+// One conjugate-gradient step's p = z + beta p_old (p = z on the first step)
+// and q = A p with the partial sums of p^T q per tile, over tiles of TX x TY
+// cells with a one-cell halo: halo values of p are recomputed from z and p_old
+// (the same formula the neighbouring tile uses), so p_new goes to a buffer
+// other than p_old.  All FP64, operator of the finest level.
+template <int TX, int TY>
+__global__ void __launch_bounds__(kMgThreads)
+k_cg_direction_t(int m, const double* __restrict__ T, const double* __restrict__ tb,
+                 const double* __restrict__ z, const double* __restrict__ pold,
+                 double* __restrict__ pnew, double* __restrict__ q,
+                 const double* __restrict__ beta, int first, double* __restrict__ partial,
+                 const int32_t* __restrict__ active) {
+  constexpr int W = TX + 2, H = TY + 2, F = W * H;
+  constexpr int K = (F + kMgThreads - 1) / kMgThreads;
+  __shared__ double sp[F];
+  __shared__ double red[kMgThreads / kWave];
+  const int ntx = m / TX, tps = ntx * (m / TY);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
+  const long long s = bid / tps;
+  if (!active[s]) return;
+  const int tile = bid - (int)(s * tps);
+  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
+  const long long n = (long long)m * m;
+  const double* Ts = T + s * 2 * n;
+  const double* tbs = tb + s * 2 * m;
+  const double* zs = z + s * n;
+  const double* ps = pold + s * n;
+  const double bt = first ? 0.0 : beta[s];
+  CellFaces<double> cf[K];
+  double pv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    const int i = X0 - 1 + fi, j = Y0 - 1 + fj;
+    cf[k] = cell_faces(Ts, tbs, m, i, j);
+    const double zv = zs[cf[k].c], po = ps[cf[k].c];
+    pv[k] = cf[k].in ? (first ? zv : zv + bt * po) : 0.0;
+    if (f < F) sp[f] = pv[k];
+  }
+  __syncthreads();
+  double* pn = pnew + s * n;
+  double* qs = q + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    if (f < F && fi >= 1 && fi <= TX && fj >= 1 && fj <= TY) {
+      const double d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+      const double qv = d * pv[k] - (cf[k].te * sp[f + 1] + cf[k].tw * sp[f - 1] +
+                                     cf[k].tn * sp[f + W] + cf[k].ts * sp[f - W]);
+      pn[cf[k].c] = pv[k];
+      qs[cf[k].c] = qv;
+      acc += pv[k] * qv;
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kMgThreads / kWave; ++w) t += red[w];
+    partial[s * tps + tile] = t;
+  }
+}
+
 // ------------------------------------------------------------------ runtime-tile kernels
 // Same algorithm for sizes the fixed tiles do not divide (tx, ty: even
 // divisors of m), 256 threads, all four frame arrays in LDS.
@@ -762,6 +831,16 @@ void launch_convert(hipStream_t st, int prec, long long count, const double* x, 
   if (prec == MLMC_PREC_FP64) convert_any<double>(st, count, x, y);
   else if (prec == MLMC_PREC_FP32) convert_any<float>(st, count, x, y);
   else convert_any<bf16_t>(st, count, x, y);
+}
+
+bool cg_direction_fused(int m) { return fixed_tile(m); }
+
+void launch_cg_direction(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                         const double* z, const double* pold, double* pnew, double* q,
+                         const double* beta, int first, double* partial, const int32_t* active) {
+  const int nb = batch * (m / kTileX) * (m / kTileY);
+  hipLaunchKernelGGL((k_cg_direction_t<kTileX, kTileY>), dim3(nb), dim3(kMgThreads), 0, st, m, T,
+                     tb, z, pold, pnew, q, beta, first, partial, active);
 }
 
 size_t prec_bytes(int prec) {

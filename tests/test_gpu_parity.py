@@ -406,3 +406,18 @@ def test_run_levels_matches_level_runs(lib, ctx, cgv):
         assert a.n == b.n and a.n_failed == b.n_failed == 0
         assert (a.sum_y, a.sum_y2, a.sum_qf, a.sum_qc) == (b.sum_y, b.sum_y2, b.sum_qf, b.sum_qc)
         assert a.iters_fine == b.iters_fine and a.iters_coarse == b.iters_coarse
+
+
+@pytest.mark.parametrize("cycle_max", [8, 16])
+def test_coarse_cycle_threshold_same_preconditioner(lib, ctx, cycle_max):
+    """Moving levels between the tiled kernels and the one-workgroup coarse cycle
+    changes only rounding: iterations +-1, QoIs at the oracle."""
+    rng = np.random.default_rng(700 + cycle_max)
+    kh = np.exp(1.5 * rng.standard_normal((3, 128, 128)))
+    a = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default())
+    b = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(cycle_max=cycle_max))
+    assert np.all(b["status"] == 0) and np.all(np.abs(a["iters"] - b["iters"]) <= 1)
+    for s in range(3):
+        A, bb = ofv.assemble(kh[s])
+        q = oqoi.outflow(kh[s], osolve.direct_solve(A, bb))
+        assert abs(b["q_out"][s] - q) <= QTOL * q
