@@ -120,7 +120,7 @@ enum {
 /* Multigrid-preconditioned CG options (Section 3.5 uses ||r_m||/||r_0|| < 1e-10). */
 typedef struct mlmc_solver_opts {
   double tol;           /* relative residual tolerance in the 2-norm; x0 = 0        */
-  double omega;         /* scaling of the coarse-grid correction (default 2)        */
+  double omega;         /* scaling of the coarse-grid correction (default 1.9)      */
   int32_t maxit;        /* iteration cap (default 200)                              */
   int32_t nu1, nu2;     /* red-black Gauss-Seidel sweeps before / after (default 1) */
   int32_t coarse_max;   /* coarsen while the grid is even and larger than this
@@ -132,6 +132,10 @@ typedef struct mlmc_solver_opts {
   int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1   */
   int32_t cycle_max;    /* variant 0: levels of at most this size (2..32, 0 = 32) run
                            in one workgroup per sample                              */
+  int32_t gamma;        /* coarse-grid visits on levels finer than gamma_min_m:
+                           1 V-cycle, 2 W-cycle (default 2)                         */
+  int32_t gamma_min_m;  /* levels of size m <= gamma_min_m take one visit (V);
+                           0: gamma on every level (default 32)                     */
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */
@@ -164,8 +168,9 @@ mlmc_status mlmc_ctx_set_stream(mlmc_ctx* ctx, void* hip_stream);
 /* Message of the last failed call on ctx (never NULL; "" when none). */
 const char* mlmc_last_error(const mlmc_ctx* ctx);
 
-/* Fill `opts` with the defaults: tol 1e-13, omega 2, maxit 200, nu1 = nu2 = 1,
- * coarse_max 4, check_every 4. */
+/* Fill `opts` with the defaults: tol 1e-13, omega 1.9, maxit 200, nu1 = nu2 = 1,
+ * coarse_max 4, check_every 4, variant 0, FP64, cycle_max 32, gamma 2,
+ * gamma_min_m 32. */
 mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* opts);
 
 /* Circulant embedding (Section 3.4, exact sampling of eq. (2.3) on a grid):

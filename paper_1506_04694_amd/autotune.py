@@ -20,7 +20,8 @@ import paper_1506_04694_amd as lib
 
 DEFAULT_SPACE = {
     "precision": [lib.MLMC_PREC_FP64, lib.MLMC_PREC_FP32, lib.MLMC_PREC_BF16],
-    "omega": [1.8, 2.0, 2.2],
+    "omega": [1.8, 1.9, 2.0],
+    "gamma": [1, 2],
     "coarse_max": [2, 4, 8],
     "check_every": [4, 8],
     "cycle_max": [16, 32],

@@ -50,6 +50,7 @@ struct mlmc_ctx {
   std::map<std::tuple<int, int, double, double, int>, CeEntry> ce;
   void* host_pinned = nullptr;  // small pinned staging buffer
   std::string prof_name;
+  double prof_scale = 1.0;  // share of the batch a launch works on (restart passes)
   std::vector<ProfEvent> prof;
   std::vector<hipEvent_t> event_pool;
 };
@@ -127,7 +128,7 @@ hipEvent_t pool_event(mlmc_ctx* ctx) {
 template <class F>
 void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch) {
   if (!ctx->prof_name.empty() && ctx->prof_name == name) {
-    ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes};
+    ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes * ctx->prof_scale};
     (void)hipEventRecord(pe.a, ctx->stream);
     launch();
     (void)hipEventRecord(pe.b, ctx->stream);
@@ -251,6 +252,8 @@ mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
     return fail(ctx, MLMC_EINVAL, "unknown precision");
   if (o->cycle_max < 0 || o->cycle_max == 1 || o->cycle_max > kCoarseCycleMax)
     return fail(ctx, MLMC_EINVAL, "cycle_max must be 0 or in [2, 32]");
+  if (o->gamma < 1 || o->gamma > 2) return fail(ctx, MLMC_EINVAL, "gamma must be 1 or 2");
+  if (o->gamma_min_m < 0) return fail(ctx, MLMC_EINVAL, "gamma_min_m must be >= 0");
   return MLMC_OK;
 }
 
@@ -319,12 +322,14 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* o) {
   if (!o) return MLMC_EINVAL;
   std::memset(o, 0, sizeof *o);
   o->tol = 1e-13;
-  o->omega = 2.0;
+  o->omega = 1.9;
   o->maxit = 200;
   o->nu1 = 1;
   o->nu2 = 1;
   o->coarse_max = 4;
   o->check_every = 4;
+  o->gamma = 2;
+  o->gamma_min_m = 32;
   return MLMC_OK;
 }
 
@@ -543,16 +548,23 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   const double omega = opts->omega;
   const double cells0 = (double)batch * n;
 
-  // Fused V(1,1): tiled down/up kernels above level l0, one workgroup per
+  // Fused cycle: tiled down/mid/up kernels above level l0, one workgroup per
   // sample for levels l0..L (sizes <= kCoarseCycleMax).
   int l0 = L;
   CoarseDesc cdesc{};
+  std::vector<void*> zmid(L + 1, nullptr);  // W-cycle: z after the second visit's pre-smoothing
+  // coarse-grid visits of level l (W on the fine levels only, by default)
+  int cur_gamma = opts->gamma;
+  auto visits = [&](int l) { return ms[l] > opts->gamma_min_m ? cur_gamma : 1; };
   if (fused) {
     l0 = 0;
     const int cmax = opts->cycle_max > 0 ? opts->cycle_max : kCoarseCycleMax;
     while (l0 < L && (ms[l0] > cmax || L - l0 + 1 > kMaxCoarseLevels)) ++l0;
-    for (int l = 0; l < l0; ++l)
+    for (int l = 0; l < l0; ++l) {
       TRY(ws_get(ctx, lv("s_zpre", l), batch * (size_t)ms[l] * ms[l] * eb + 256, &zpre[l]));
+      if (visits(l) == 2)
+        TRY(ws_get(ctx, lv("s_zmid", l), batch * (size_t)ms[l] * ms[l] * eb + 256, &zmid[l]));
+    }
     for (int q2 = 0; q2 + l0 <= L; ++q2) {
       cdesc.m[q2] = ms[l0 + q2];
       cdesc.T[q2] = Ts[l0 + q2];
@@ -583,52 +595,82 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
         launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
       });
     }
-    timed(ctx, "k_resid_restrict", cells * kBytesResRes, [&] {
-      launch_resid_restrict(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], rl[l + 1], S.active);
-    });
-    vcycle_unfused(l + 1);
-    timed(ctx, "k_prolong", cells * kBytesProlong,
-          [&] { launch_prolong(st, ml, batch, zl[l + 1], zl[l], omega, S.active); });
-    for (int it = 0; it < nu; ++it) {
-      timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
-        launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+    for (int visit = 0; visit < visits(l); ++visit) {
+      if (visit > 0) {
+        for (int it = 0; it < nu; ++it) {
+          timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
+            launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
+          });
+          timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
+            launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+          });
+        }
+      }
+      timed(ctx, "k_resid_restrict", cells * kBytesResRes, [&] {
+        launch_resid_restrict(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], rl[l + 1], S.active);
       });
-      timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
-        launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
-      });
+      vcycle_unfused(l + 1);
+      timed(ctx, "k_prolong", cells * kBytesProlong,
+            [&] { launch_prolong(st, ml, batch, zl[l + 1], zl[l], omega, S.active); });
+      for (int it = 0; it < nu; ++it) {
+        timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
+          launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+        });
+        timed(ctx, "k_rbgs", cells * kBytesRbgs, [&] {
+          launch_rbgs(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
+        });
+      }
     }
   };
   // z = M r, and the partials of r^T z: rz_parts per sample in `partial`
   int rz_parts = bps;
   if (fused) rz_parts = l0 == 0 ? 1 : mg_tiles_per_sample(ms[0]);
+  // Fused gamma-cycle: on a tiled level l, the down kernel pre-smooths and
+  // restricts; after the first coarse visit the mid kernel adds the correction,
+  // post- and pre-smooths and restricts again; the up kernel adds the last
+  // correction and post-smooths.  Levels l0..L run in the in-LDS kernel.
+  std::function<void(int)> fcycle = [&](int l) {
+    if (l == l0) {
+      unsigned wmask = 0;
+      for (int q2 = 0; l0 + q2 < L; ++q2)
+        if (visits(l0 + q2) == 2) wmask |= 1u << q2;
+      timed(ctx, "k_mg_coarse_cycle", coarse_bytes, [&] {
+        launch_mg_coarse_cycle(st, prec, l0 == 0, batch, ncl, cdesc, rs[l0], zs[l0], Ainv, omega,
+                               wmask, S.active, l0 == 0 ? partial : nullptr);
+      });
+      return;
+    }
+    const double cells = (double)batch * ms[l] * ms[l];
+    const double rb = l == 0 ? 8.0 : ebd;  // r (FP64 on the finest level)
+    // T 2 words, r, z_pre write, coarse r write (1/4 word)
+    timed(ctx, "k_mg_down", cells * (ebd * 3.25 + rb), [&] {
+      launch_mg_down(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], rs[l + 1],
+                     S.active);
+    });
+    fcycle(l + 1);
+    const void* zin = zpre[l];
+    if (visits(l) == 2) {
+      // T 2 words, r, z_pre, coarse z (1/4), z write, coarse r write (1/4)
+      timed(ctx, "k_mg_mid", cells * (ebd * 4.5 + rb), [&] {
+        launch_mg_mid(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], zmid[l],
+                      zs[l + 1], omega, rs[l + 1], S.active);
+      });
+      fcycle(l + 1);
+      zin = zmid[l];
+    }
+    // T 2 words, r and z (FP64 on the finest level), z_in, coarse z (1/4 word)
+    timed(ctx, "k_mg_up", cells * (ebd * 3.25 + (l == 0 ? 16.0 : 2.0 * ebd)), [&] {
+      launch_mg_up(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zin, zs[l], zs[l + 1],
+                   omega, S.active, l == 0 ? partial : nullptr);
+    });
+  };
   auto vcycle = [&]() {
     if (!fused) {
       vcycle_unfused(0);
       launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
       return;
     }
-    for (int l = 0; l < l0; ++l) {
-      const double cells = (double)batch * ms[l] * ms[l];
-      // T 2 words, r (FP64 on the finest level), z_pre, coarse r (1/4 word)
-      const double by = cells * (ebd * 3.25 + (l == 0 ? 8.0 : ebd));
-      timed(ctx, "k_mg_down", by, [&] {
-        launch_mg_down(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], rs[l + 1],
-                       S.active);
-      });
-    }
-    timed(ctx, "k_mg_coarse_cycle", coarse_bytes, [&] {
-      launch_mg_coarse_cycle(st, prec, l0 == 0, batch, ncl, cdesc, rs[l0], zs[l0], Ainv, omega,
-                             S.active, l0 == 0 ? partial : nullptr);
-    });
-    for (int l = l0 - 1; l >= 0; --l) {
-      const double cells = (double)batch * ms[l] * ms[l];
-      // T 2 words, r and z (FP64 on the finest level), z_pre, coarse z (1/4 word)
-      const double by = cells * (ebd * 3.25 + (l == 0 ? 16.0 : 2.0 * ebd));
-      timed(ctx, "k_mg_up", by, [&] {
-        launch_mg_up(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], zs[l],
-                     zs[l + 1], omega, S.active, l == 0 ? partial : nullptr);
-      });
-    }
+    fcycle(0);
   };
 
   // CG direction: fused p-update + operator (ping-pong p buffers) when the
@@ -638,43 +680,69 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   if (dir_fused) TRY(ws(ctx, "s_p2", batch * n, &pbuf[1]));
   const int dir_parts = dir_fused ? mg_tiles_per_sample(m) : bps;
 
-  launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps);
-  launch_sc_init(st, batch, partial, bps, S, status, iters, relres);
-  vcycle();
-  launch_sc_rho(st, batch, partial, rz_parts, S, status, 1, nullptr, 0);
-  if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
-  CHECK_LAUNCH();
-
   int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
   const int check = opts->check_every > 0 ? opts->check_every : 1;
-  for (int it = 1;; ++it) {
-    if (dir_fused) {
-      // iteration it writes p into pbuf[it % 2] from pbuf[(it - 1) % 2]
-      pv = pbuf[it & 1];
-      timed(ctx, "k_cg_direction_t", cells0 * 48.0, [&] {
-        launch_cg_direction(st, m, batch, T, tb, z, pbuf[(it - 1) & 1], pv, q, S.beta, it == 1,
-                            partial, S.active);
-      });
-    } else {
-      timed(ctx, "k_spmv_dot", cells0 * kBytesSpmv, [&] {
-        launch_spmv_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
-      });
-    }
-    launch_sc_alpha(st, batch, partial, dir_parts, S, status);
-    timed(ctx, "k_axpy_dot", cells0 * (kBytesAxpy + (flexible ? 8.0 : 0.0)), [&] {
-      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,
-                      flexible ? z : nullptr, partial2);
-    });
-    launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
-    CHECK_LAUNCH();
-    if (it % check == 0 || it >= opts->maxit) {
-      HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      if (*hcount == 0) break;
-    }
+  // One PCG pass over the active samples (all of them, or with `restart` the
+  // ones marked by launch_sc_restart), x0 = 0.
+  auto pcg_pass = [&](bool restart) -> mlmc_status {
+    launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
+    launch_sc_init(st, batch, partial, bps, S, status, iters, relres, restart ? 1 : 0);
     vcycle();
-    launch_sc_rho(st, batch, partial, rz_parts, S, status, 0, partial2, bps);
-    if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
+    launch_sc_rho(st, batch, partial, rz_parts, S, status, 1, nullptr, 0);
+    if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
+    CHECK_LAUNCH();
+    for (int it = 1;; ++it) {
+      if (dir_fused) {
+        // iteration it writes p into pbuf[it % 2] from pbuf[(it - 1) % 2]
+        pv = pbuf[it & 1];
+        timed(ctx, "k_cg_direction_t", cells0 * 48.0, [&] {
+          launch_cg_direction(st, m, batch, T, tb, z, pbuf[(it - 1) & 1], pv, q, S.beta, it == 1,
+                              partial, S.active);
+        });
+      } else {
+        timed(ctx, "k_spmv_dot", cells0 * kBytesSpmv, [&] {
+          launch_spmv_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
+        });
+      }
+      launch_sc_alpha(st, batch, partial, dir_parts, S, status);
+      timed(ctx, "k_axpy_dot", cells0 * (kBytesAxpy + (flexible ? 8.0 : 0.0)), [&] {
+        launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,
+                        flexible ? z : nullptr, partial2);
+      });
+      launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
+      CHECK_LAUNCH();
+      if (it % check == 0 || it >= opts->maxit) {
+        HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (*hcount == 0) break;
+      }
+      vcycle();
+      launch_sc_rho(st, batch, partial, rz_parts, S, status, 0, partial2, bps);
+      if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
+    }
+    return MLMC_OK;
+  };
+  TRY(pcg_pass(false));
+  // The W-cycle preconditioner is symmetric but, with over-corrected coarse
+  // steps, not positive definite for every operator (two coarse visits act as
+  // 2B - BAB, indefinite once B A has an eigenvalue above 2); a sample whose
+  // W-preconditioned iteration breaks down (r^T z <= 0) is solved again from
+  // x0 = 0 with the V-cycle, positive definite for any omega > 0.  Its
+  // iteration count includes both passes.
+  if (cur_gamma == 2) {
+    int32_t* carried;
+    TRY(ws(ctx, "s_carried", batch, &carried));
+    launch_sc_restart(st, batch, S, status, iters, carried);
+    HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*hcount > 0) {
+      cur_gamma = 1;
+      ctx->prof_scale = (double)*hcount / batch;
+      const mlmc_status rc = pcg_pass(true);
+      ctx->prof_scale = 1.0;
+      TRY(rc);
+      launch_iters_add(st, batch, iters, carried);
+    }
   }
   launch_true_residual(st, m, batch, T, tb, b, p, partial, bps);
   launch_sc_final(st, batch, partial, bps, S, relres);

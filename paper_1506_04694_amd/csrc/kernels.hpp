@@ -91,10 +91,17 @@ void launch_mg_down(hipStream_t st, int prec, bool top, int m, int batch, const 
 void launch_mg_up(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
                   const void* tb, const void* r, const void* zpre, void* z, const void* zc,
                   double omega, const int32_t* active, double* rz_partial);
+// Second coarse correction of a W-cycle level: z = zpre + omega P zc,
+// black-red-black sweeps, z and the restricted residual rc.
+void launch_mg_mid(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+                   const void* tb, const void* r, const void* zpre, void* z, const void* zc,
+                   double omega, void* rc, const int32_t* active);
 size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev);
+// Bit l of wmask: level l of the LDS-held levels takes two coarse visits (W).
 void launch_mg_coarse_cycle(hipStream_t st, int prec, bool top, int batch, int nlev,
                             const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
-                            double omega, const int32_t* active, double* rz_partial);
+                            double omega, unsigned wmask, const int32_t* active,
+                            double* rz_partial);
 void launch_convert(hipStream_t st, int prec, long long count, const double* x, void* y);
 // p_new = z + beta p_old (z when first), q = A p_new, partial[s * tiles + tile] = p_new . q;
 // available when cg_direction_fused(m) (fixed tiles; mg_tiles_per_sample(m) partials)
@@ -103,8 +110,9 @@ void launch_cg_direction(hipStream_t st, int m, int batch, const double* T, cons
                          const double* z, const double* pold, double* pnew, double* q,
                          const double* beta, int first, double* partial, const int32_t* active);
 
+// only != NULL: initialise just the samples with only[s] != 0
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
-                     double* partial, int bps);
+                     double* partial, int bps, const int32_t* only);
 void launch_spmv_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                      const double* p, double* q, double* partial, int bps,
                      const int32_t* active);
@@ -119,8 +127,12 @@ void launch_pupdate(hipStream_t st, int n, int batch, double* p, const double* z
 void launch_true_residual(hipStream_t st, int m, int batch, const double* T, const double* tb,
                           const double* b, const double* x, double* partial, int bps);
 
+// restart != 0: only the samples with S.active set (after launch_sc_restart)
 void launch_sc_init(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
-                    int32_t* status, int32_t* iters, double* relres);
+                    int32_t* status, int32_t* iters, double* relres, int restart);
+void launch_sc_restart(hipStream_t st, int batch, SolverState s, int32_t* status, int32_t* iters,
+                       int32_t* carried);
+void launch_iters_add(hipStream_t st, int batch, int32_t* iters, const int32_t* carried);
 // beta = rho_new / rho (standard) or (rho_new - r_new.z_old) / rho (flexible,
 // partial2 != NULL: Polak-Ribiere form, for a preconditioner that is not
 // exactly symmetric, e.g. one applied in reduced precision)

@@ -210,6 +210,104 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   }
 }
 
+// mid: the second coarse correction of a W-cycle level.  From z1 (the down
+// result) and the first correction e1: z = z1 + omega P e1, then black, red
+// and black sweeps (the post-smoothing of the first correction, black then
+// red, followed by the pre-smoothing of the second, red then black, whose red
+// sweep repeats the one just done and is dropped), then the restricted
+// residual as in down.  Halo: the residual on the tile needs the last black
+// sweep one cell out, that sweep the red sweep two cells out, that one the
+// first black sweep three cells out, which needs z four cells out.
+template <int TX, int TY, class S, bool TOP>
+__global__ void __launch_bounds__(kMgThreads)
+k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
+           const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre, S* __restrict__ z,
+           const S* __restrict__ zc, double omega, S* __restrict__ rc,
+           const int32_t* __restrict__ active) {
+  using C = typename Prec<S>::C;
+  constexpr int W = TX + 8, H = TY + 8, F = W * H;
+  constexpr int K = (F + kMgThreads - 1) / kMgThreads;
+  __shared__ C sz[F];
+  const int ntx = m / TX, tps = ntx * (m / TY);
+  const int bid = xcd_tile(blockIdx.x, gridDim.x);
+  const long long s = bid / tps;
+  if (!active[s]) return;
+  const int tile = bid - (int)(s * tps);
+  const int X0 = (tile % ntx) * TX, Y0 = (tile / ntx) * TY;
+  const long long n = (long long)m * m;
+  const int mc = m / 2;
+  const S* Ts = T + s * 2 * n;
+  const S* tbs = tb + s * 2 * m;
+  const S* zps = zpre + s * n;
+  const S* zcs = zc + s * (long long)mc * mc;
+  const C om = (C)omega;
+  CellFaces<C> cf[K];
+  C rv[K], zv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    const int i = X0 - 4 + fi, j = Y0 - 4 + fj;
+    cf[k] = cell_faces(Ts, tbs, m, i, j);
+    const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
+    const C rr = (C)ldv(r + s * n, cf[k].c);
+    const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
+    rv[k] = cf[k].in ? rr : C(0);
+    zv[k] = cf[k].in ? zp + om * zcv : C(0);
+    if (f < F) sz[f] = zv[k];
+  }
+  __syncthreads();
+  // black on R3, red on R2, black on R1
+#pragma unroll
+  for (int pass = 0; pass < 3; ++pass) {
+    const int d = 3 - pass, col = (pass == 1) ? 0 : 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int f = threadIdx.x + k * kMgThreads;
+      const int fj = f / W, fi = f - fj * W;
+      if (f < F && cf[k].in && fi >= 4 - d && fi < W - 4 + d && fj >= 4 - d && fj < H - 4 + d &&
+          ((fi + fj) & 1) == col) {
+        const C dd = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+        zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
+                 cf[k].ts * sz[f - W]) / dd;
+        sz[f] = zv[k];
+      }
+    }
+    __syncthreads();
+  }
+  // store the tile; residual of its red cells (black residuals vanish after the black sweep)
+  S* zs = z + s * n;
+  C res[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    res[k] = C(0);
+    if (f < F && fi >= 4 && fi < 4 + TX && fj >= 4 && fj < 4 + TY) {
+      Prec<S>::st(zs, cf[k].c, zv[k]);
+      if (((fi + fj) & 1) == 0) {
+        const C dd = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
+        res[k] = rv[k] - dd * zv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] +
+                 cf[k].tn * sz[f + W] + cf[k].ts * sz[f - W];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    if (f < F) sz[f] = res[k];
+  }
+  __syncthreads();
+  S* rcs = rc + s * (long long)mc * mc;
+  constexpr int HX = TX / 2, HY = TY / 2;
+  for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
+    const int cj = c / HX, ci = c - cj * HX;
+    const int fa = (4 + 2 * cj) * W + 4 + 2 * ci;
+    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sz[fa] + sz[fa + W + 1]);
+  }
+}
+
 template <int TX, int TY, class S, bool TOP>
 __global__ void __launch_bounds__(kMgThreads)
 k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
@@ -554,8 +652,72 @@ k_mg_up(int m, int tx, int ty, int tiles_per_sample, const S* __restrict__ T,
   }
 }
 
+// Runtime-tile form of the mid kernel: the frame reaches four cells around the
+// tile; the restriction computes each coarse cell's two red residuals directly.
+template <class S, bool TOP>
+__global__ void __launch_bounds__(kBlock)
+k_mg_mid(int m, int tx, int ty, int tiles_per_sample, const S* __restrict__ T,
+         const S* __restrict__ tb, const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre,
+         S* __restrict__ z, const S* __restrict__ zc, double omega, S* __restrict__ rc,
+         const int32_t* __restrict__ active) {
+  using C = typename Prec<S>::C;
+  extern __shared__ double lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
+  const long long s = blockIdx.x / tiles_per_sample;
+  if (!active[s]) return;
+  const int tile = blockIdx.x - (int)(s * tiles_per_sample);
+  const int ntx = m / tx;
+  const int X0 = (tile % ntx) * tx, Y0 = (tile / ntx) * ty;
+  const int W = tx + 8, H = ty + 8, F = W * H;
+  Lds<C> L{lds, lds + F, lds + 2 * F, lds + 3 * F};
+  const long long n = (long long)m * m;
+  const int mc = m / 2;
+  const S* Ts = T + s * 2 * n;
+  const S* tbs = tb + s * 2 * m;
+  const VecT<S, TOP>* rs = r + s * n;
+  const S* zps = zpre + s * n;
+  const S* zcs = zc + s * (long long)mc * mc;
+  const C om = (C)omega;
+  for (int f = threadIdx.x; f < F; f += kBlock) {
+    const int fj = f / W, fi = f - fj * W;
+    const int i = X0 - 4 + fi, j = Y0 - 4 + fj;
+    L.te[f] = load_te(Ts, tbs, m, i, j);
+    L.tn[f] = load_tn(Ts, tbs, m, i, j);
+    const bool in = i >= 0 && i < m && j >= 0 && j < m;
+    L.r[f] = in ? (C)ldv(rs, j * m + i) : C(0);
+    L.z[f] = in ? ldv(zps, j * m + i) + om * ldv(zcs, (j >> 1) * mc + (i >> 1)) : C(0);
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 3; ++pass) {
+    const int d = 3 - pass, col = (pass == 1) ? 0 : 1;
+    for (int f = threadIdx.x; f < F; f += kBlock) {
+      const int fj = f / W, fi = f - fj * W;
+      if (fi < 4 - d || fi >= W - 4 + d || fj < 4 - d || fj >= H - 4 + d) continue;
+      const int i = X0 - 4 + fi, j = Y0 - 4 + fj;
+      if (i < 0 || i >= m || j < 0 || j >= m || ((i + j) & 1) != col) continue;
+      L.z[f] = (L.r[f] + nsum_at(L, W, f)) / diag_at(L, W, f);
+    }
+    __syncthreads();
+  }
+  S* zs = z + s * n;
+  for (int c = threadIdx.x; c < tx * ty; c += kBlock) {
+    const int cj = c / tx, ci = c - cj * tx;
+    Prec<S>::st(zs, (Y0 + cj) * m + X0 + ci, L.z[(cj + 4) * W + ci + 4]);
+  }
+  const int hx = tx / 2, hy = ty / 2;
+  S* rcs = rc + s * (long long)mc * mc;
+  for (int c = threadIdx.x; c < hx * hy; c += kBlock) {
+    const int cj = c / hx, ci = c - cj * hx;
+    // (X0 + 2ci, Y0 + 2cj) has even i + j: the block's red cells are (0,0) and (1,1)
+    const int fa = (4 + 2 * cj) * W + 4 + 2 * ci, fb = fa + W + 1;
+    const C ra = L.r[fa] - diag_at(L, W, fa) * L.z[fa] + nsum_at(L, W, fa);
+    const C rb = L.r[fb] - diag_at(L, W, fb) * L.z[fb] + nsum_at(L, W, fb);
+    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, ra + rb);
+  }
+}
+
 // ------------------------------------------------------------------ coarse cycle in LDS
-// One workgroup per sample runs the V(1,1)-cycle on levels l0..L (m_l0 <= 32)
+// One workgroup per sample runs the V- or W-cycle on levels l0..L (m_l0 <= 32)
 // in FP64 with every level's operator and vectors in LDS, whatever the
 // storage type of the hierarchy.  Level arrays use a padded (m + 2)^2 layout
 // with a one-cell ring: ring cells hold z = 0 and the boundary faces (west
@@ -587,7 +749,8 @@ template <class S, bool TOP>
 __global__ void __launch_bounds__(kBlock)
 k_mg_coarse_cycle(int nlev, CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0,
                   VecT<S, TOP>* __restrict__ z0, const double* __restrict__ Ainv, double omega,
-                  const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
+                  unsigned wmask, const int32_t* __restrict__ active,
+                  double* __restrict__ rz_partial) {
   extern __shared__ double lds[];
   const int s = blockIdx.x;
   if (!active[s]) return;
@@ -620,14 +783,59 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0
     }
   }
   __syncthreads();
-  for (int l = 0; l < nlev - 1; ++l) {
+  // V/W-cycle without recursion (bit l of wmask: level l takes two coarse
+  // visits).  Entering a level downwards (r set, z = 0): red and black sweeps
+  // from zero, restrict the residual, go down.  Coming back up: add the
+  // prolonged correction, black and red sweeps; then leave upwards, or, on a
+  // W level after its first visit, pre-smooth again (its red sweep would repeat
+  // the one just done, so only the black sweep) and go down again.
+  unsigned once = 0;  // bit l: level l has had its first coarse visit
+  int l = 0;
+  bool descending = true;
+  for (;;) {
     const int m = lv[l].m, P = lv[l].P, PP = P * P;
     double* te = lds + lv[l].off;
     double* tn = te + PP;
     double* rr = tn + PP;
     double* zz = rr + PP;
-    cc_sweep(te, tn, rr, zz, m, P, 0, true);
-    cc_sweep(te, tn, rr, zz, m, P, 1, false);
+    if (l == nlev - 1) {
+      const int nc = m * m;
+      for (int q = threadIdx.x; q < nc; q += kBlock) vec[q] = rr[pidx(P, q % m, q / m)];
+      __syncthreads();
+      const double* A = Ainv + (long long)s * nc * nc;
+      for (int q = threadIdx.x; q < nc; q += kBlock) {
+        double acc = 0.0;
+        for (int p = 0; p < nc; ++p) acc += A[q * nc + p] * vec[p];
+        zz[pidx(P, q % m, q / m)] = acc;
+      }
+      __syncthreads();
+      if (l == 0) break;
+      --l;
+      descending = false;
+      continue;
+    }
+    if (descending) {
+      cc_sweep(te, tn, rr, zz, m, P, 0, true);
+      cc_sweep(te, tn, rr, zz, m, P, 1, false);
+    } else {
+      const int Pc = lv[l + 1].P, PPc = Pc * Pc;
+      const double* zc = lds + lv[l + 1].off + 3 * PPc;
+      for (int c = threadIdx.x; c < m * m; c += kBlock) {
+        const int j = c / m, i = c - j * m;
+        zz[pidx(P, i, j)] += omega * zc[pidx(Pc, i / 2, j / 2)];
+      }
+      __syncthreads();
+      cc_sweep(te, tn, rr, zz, m, P, 1, false);
+      cc_sweep(te, tn, rr, zz, m, P, 0, false);
+      if (!(wmask >> l & 1u) || (once >> l & 1u)) {
+        once &= ~(1u << l);
+        if (l == 0) break;
+        --l;
+        continue;
+      }
+      once |= 1u << l;
+      cc_sweep(te, tn, rr, zz, m, P, 1, false);
+    }
     const int mc = lv[l + 1].m, Pc = lv[l + 1].P, PPc = Pc * Pc;
     double* rc = lds + lv[l + 1].off + 2 * PPc;
     for (int c = threadIdx.x; c < mc * mc; c += kBlock) {
@@ -643,37 +851,8 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0
       rc[pidx(Pc, I, J)] = acc;
     }
     __syncthreads();
-  }
-  {
-    const int l = nlev - 1;
-    const int m = lv[l].m, P = lv[l].P, PP = P * P, nc = m * m;
-    double* rr = lds + lv[l].off + 2 * PP;
-    double* zz = rr + PP;
-    for (int q = threadIdx.x; q < nc; q += kBlock) vec[q] = rr[pidx(P, q % m, q / m)];
-    __syncthreads();
-    const double* A = Ainv + (long long)s * nc * nc;
-    for (int q = threadIdx.x; q < nc; q += kBlock) {
-      double acc = 0.0;
-      for (int p = 0; p < nc; ++p) acc += A[q * nc + p] * vec[p];
-      zz[pidx(P, q % m, q / m)] = acc;
-    }
-    __syncthreads();
-  }
-  for (int l = nlev - 2; l >= 0; --l) {
-    const int m = lv[l].m, P = lv[l].P, PP = P * P;
-    double* te = lds + lv[l].off;
-    double* tn = te + PP;
-    double* rr = tn + PP;
-    double* zz = rr + PP;
-    const int Pc = lv[l + 1].P, PPc = Pc * Pc;
-    const double* zc = lds + lv[l + 1].off + 3 * PPc;
-    for (int c = threadIdx.x; c < m * m; c += kBlock) {
-      const int j = c / m, i = c - j * m;
-      zz[pidx(P, i, j)] += omega * zc[pidx(Pc, i / 2, j / 2)];
-    }
-    __syncthreads();
-    cc_sweep(te, tn, rr, zz, m, P, 1, false);
-    cc_sweep(te, tn, rr, zz, m, P, 0, false);
+    ++l;
+    descending = true;
   }
   {
     const int m = lv[0].m, P = lv[0].P, PP = P * P;
@@ -759,6 +938,43 @@ static void up_impl(hipStream_t st, int m, int batch, const void* T, const void*
                      (const S*)zc, omega, active, rz_partial);
 }
 
+template <class S, bool TOP>
+static void mid_impl(hipStream_t st, int m, int batch, const void* T, const void* tb, const void* r,
+                     const void* zpre, void* z, const void* zc, double omega, void* rc,
+                     const int32_t* active) {
+  using R = VecT<S, TOP>;
+  if (fixed_tile(m)) {
+    const int nb = batch * (m / kTileX) * (m / kTileY);
+    hipLaunchKernelGGL((k_mg_mid_t<kTileX, kTileY, S, TOP>), dim3(nb), dim3(kMgThreads), 0, st, m,
+                       (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (S*)z,
+                       (const S*)zc, omega, (S*)rc, active);
+    return;
+  }
+  using C = typename Prec<S>::C;
+  const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
+  const int tps = (m / tx) * (m / ty);
+  const size_t lds = (size_t)4 * (tx + 8) * (ty + 8) * sizeof(C);
+  hipLaunchKernelGGL((k_mg_mid<S, TOP>), dim3(batch * tps), dim3(kBlock), lds, st, m, tx, ty, tps,
+                     (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (S*)z, (const S*)zc,
+                     omega, (S*)rc, active);
+}
+
+template <class S>
+static void mid_any(bool top, hipStream_t st, int m, int batch, const void* T, const void* tb,
+                    const void* r, const void* zpre, void* z, const void* zc, double omega,
+                    void* rc, const int32_t* active) {
+  if (top) mid_impl<S, true>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+  else mid_impl<S, false>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+}
+
+void launch_mg_mid(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+                   const void* tb, const void* r, const void* zpre, void* z, const void* zc,
+                   double omega, void* rc, const int32_t* active) {
+  if (prec == MLMC_PREC_FP64) mid_any<double>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+  else if (prec == MLMC_PREC_FP32) mid_any<float>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+  else mid_any<bf16_t>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+}
+
 template <class S>
 static void down_any(bool top, hipStream_t st, int m, int batch, const void* T, const void* tb,
                      const void* r, void* z, void* rc, const int32_t* active) {
@@ -776,15 +992,15 @@ static void up_any(bool top, hipStream_t st, int m, int batch, const void* T, co
 
 template <class S>
 static void coarse_any(bool top, hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
-                       const void* r0, void* z0, const double* Ainv, double omega,
+                       const void* r0, void* z0, const double* Ainv, double omega, unsigned wmask,
                        const int32_t* active, double* rz_partial) {
   const size_t lds = coarse_cycle_lds_bytes(desc, nlev);
   if (top)
     hipLaunchKernelGGL((k_mg_coarse_cycle<S, true>), dim3(batch), dim3(kBlock), lds, st, nlev, desc,
-                       (const double*)r0, (double*)z0, Ainv, omega, active, rz_partial);
+                       (const double*)r0, (double*)z0, Ainv, omega, wmask, active, rz_partial);
   else
     hipLaunchKernelGGL((k_mg_coarse_cycle<S, false>), dim3(batch), dim3(kBlock), lds, st, nlev,
-                       desc, (const S*)r0, (S*)z0, Ainv, omega, active, rz_partial);
+                       desc, (const S*)r0, (S*)z0, Ainv, omega, wmask, active, rz_partial);
 }
 
 template <class S>
@@ -819,12 +1035,14 @@ size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev) {
 
 void launch_mg_coarse_cycle(hipStream_t st, int prec, bool top, int batch, int nlev,
                             const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
-                            double omega, const int32_t* active, double* rz_partial) {
+                            double omega, unsigned wmask, const int32_t* active,
+                            double* rz_partial) {
   if (prec == MLMC_PREC_FP64)
-    coarse_any<double>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
+    coarse_any<double>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, wmask, active, rz_partial);
   else if (prec == MLMC_PREC_FP32)
-    coarse_any<float>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
-  else coarse_any<bf16_t>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
+    coarse_any<float>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, wmask, active, rz_partial);
+  else
+    coarse_any<bf16_t>(top, st, batch, nlev, desc, r0, z0, Ainv, omega, wmask, active, rz_partial);
 }
 
 void launch_convert(hipStream_t st, int prec, long long count, const double* x, void* y) {

@@ -261,9 +261,10 @@ void launch_dense_apply(hipStream_t st, int m, int batch, const double* Ainv, co
 
 __global__ void __launch_bounds__(kBlock)
 k_pcg_init(int n, const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
-           double* __restrict__ partial, int bps) {
+           double* __restrict__ partial, int bps, const int32_t* __restrict__ only) {
   __shared__ double sh[kBlock / kWave];
   PCG_PROLOGUE
+  if (only && !only[s]) return;
   double acc = 0.0;
 #pragma unroll
   for (int c = 0; c < kCellsPerThread; ++c) {
@@ -281,8 +282,9 @@ k_pcg_init(int n, const double* __restrict__ b, double* __restrict__ x, double* 
 }
 
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
-                     double* partial, int bps) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(batch * bps), dim3(kBlock), 0, st, n, b, x, r, partial, bps);
+                     double* partial, int bps, const int32_t* only) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(batch * bps), dim3(kBlock), 0, st, n, b, x, r, partial, bps,
+                     only);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -445,9 +447,9 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
 
 __global__ void k_sc_init(int batch, const double* __restrict__ partial, int bps, SolverState S,
                           int32_t* __restrict__ status, int32_t* __restrict__ iters,
-                          double* __restrict__ relres) {
+                          double* __restrict__ relres, int restart) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= batch) return;
+  if (s >= batch || (restart && !S.active[s])) return;
   const double v = sum_partials(partial, bps, s);
   S.r0sq[s] = v;
   iters[s] = 0;
@@ -462,9 +464,43 @@ __global__ void k_sc_init(int batch, const double* __restrict__ partial, int bps
 }
 
 void launch_sc_init(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
-                    int32_t* status, int32_t* iters, double* relres) {
+                    int32_t* status, int32_t* iters, double* relres, int restart) {
   hipLaunchKernelGGL(k_sc_init, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial, bps,
-                     s, status, iters, relres);
+                     s, status, iters, relres, restart);
+}
+
+// Marks the samples whose iteration broke down for a second pass (active = 1),
+// moves their iteration counts to `carried` and writes how many there are to
+// *S.count.  One workgroup.
+__global__ void k_sc_restart(int batch, SolverState S, int32_t* __restrict__ status,
+                             int32_t* __restrict__ iters, int32_t* __restrict__ carried) {
+  __shared__ double red[kBlock / kWave];
+  double cnt = 0.0;
+  for (int s = threadIdx.x; s < batch; s += kBlock) {
+    const int v = status[s];
+    const bool again = v == MLMC_SAMPLE_BREAKDOWN;
+    S.active[s] = again ? 1 : 0;
+    carried[s] = again ? iters[s] : 0;
+    cnt += again ? 1.0 : 0.0;
+  }
+  const double t = block_sum(cnt, red);
+  if (threadIdx.x == 0) *S.count = (int32_t)t;
+}
+
+void launch_sc_restart(hipStream_t st, int batch, SolverState s, int32_t* status, int32_t* iters,
+                       int32_t* carried) {
+  hipLaunchKernelGGL(k_sc_restart, dim3(1), dim3(kBlock), 0, st, batch, s, status, iters, carried);
+}
+
+__global__ void k_iters_add(int batch, int32_t* __restrict__ iters,
+                            const int32_t* __restrict__ carried) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < batch) iters[s] += carried[s];
+}
+
+void launch_iters_add(hipStream_t st, int batch, int32_t* iters, const int32_t* carried) {
+  hipLaunchKernelGGL(k_iters_add, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, iters,
+                     carried);
 }
 
 __global__ void k_sc_rho(int batch, const double* __restrict__ partial, int nparts,

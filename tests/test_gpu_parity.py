@@ -227,6 +227,10 @@ def test_solve_failure_paths(lib, ctx):
         solve_batch(lib, ctx, kh[[0]], lib.mlmc_solver_opts_default(nu1=2, nu2=1))
     assert e.value.code == lib.MLMC_EINVAL
     with pytest.raises(lib.MlmcError):
+        solve_batch(lib, ctx, kh[[0]], lib.mlmc_solver_opts_default(gamma=3))
+    with pytest.raises(lib.MlmcError):
+        solve_batch(lib, ctx, kh[[0]], lib.mlmc_solver_opts_default(gamma_min_m=-1))
+    with pytest.raises(lib.MlmcError):
         solve_batch(lib, ctx, np.ones((1, 88, 88)))     # 88 = 11 * 8: coarsest 11 > 8
 
 
@@ -321,17 +325,19 @@ def test_layered_ce_full_level_sampled(lib, ctx, level):
 
 
 # ------------------------------------------------------------------ fused vs per-sweep V-cycle
+@pytest.mark.parametrize("gamma,gmin", [(1, 32), (2, 32), (2, 0)])
 @pytest.mark.parametrize("m", [8, 24, 40, 64, 96, 128, 256])
-def test_fused_vcycle_matches_unfused(lib, ctx, m):
-    """The fused tiled V-cycle and the one-launch-per-sweep V-cycle are the same
+def test_fused_cycle_matches_unfused(lib, ctx, m, gamma, gmin):
+    """The fused tiled V-/W-cycle and the one-launch-per-sweep cycle are the same
     preconditioner: equal iteration counts (+-1 from rounding) and QoIs, both at
-    the oracle's value."""
-    print("fused vs unfused m=%d" % m, flush=True)
+    the oracle's value.  gmin = 0 puts W on the levels held in LDS too."""
+    print("fused vs unfused m=%d gamma=%d gamma_min_m=%d" % (m, gamma, gmin), flush=True)
     rng = np.random.default_rng(300 + m)
     batch = 3
     kh = np.exp(1.5 * rng.standard_normal((batch, m, m)))
-    a = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=0))
-    b = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=1))
+    kw = dict(gamma=gamma, gamma_min_m=gmin)
+    a = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=0, **kw))
+    b = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=1, **kw))
     assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
     assert np.all(np.abs(a["iters"] - b["iters"]) <= 1), (a["iters"], b["iters"])
     for s in range(batch):
@@ -341,14 +347,39 @@ def test_fused_vcycle_matches_unfused(lib, ctx, m):
         assert abs(b["q_out"][s] - q) <= QTOL * q
 
 
-def test_iterations_flat_in_grid_size(lib, ctx):
+@pytest.mark.parametrize("gamma,bound,spread", [(1, 25, 5), (2, 12, 3)])
+def test_iterations_flat_in_grid_size(lib, ctx, gamma, bound, spread):
     """Multigrid-preconditioned CG needs a bounded number of iterations on the
-    layered correlated model from 64^2 to 512^2 (optimal solver, Section 3.5)."""
+    layered correlated model from 64^2 to 512^2 (optimal solver, Section 3.5);
+    the W-cycle needs fewer than the V-cycle."""
     its = []
     for level, m in enumerate([64, 128, 256, 512]):
-        sums = lib.mlmc_level_run(ctx, W.CE2, level, m, 0, 8, False, lib.mlmc_solver_opts_default())
+        sums = lib.mlmc_level_run(ctx, W.CE2, level, m, 0, 8, False,
+                                  lib.mlmc_solver_opts_default(gamma=gamma))
         its.append(sums.iters_fine / 8)
-    assert max(its) <= 25 and max(its) - min(its) <= 5, its
+    print("gamma %d mean iterations %s" % (gamma, its), flush=True)
+    assert max(its) <= bound and max(its) - min(its) <= spread, its
+
+
+def test_w_cycle_breakdown_restarts_with_v(lib, ctx):
+    """Samples of the layered workload on which the W-cycle preconditioner with
+    omega = 2 is indefinite (its PCG breaks down in the first iterations) are solved again
+    with the V-cycle: every status is OK, the restarted samples report both
+    passes' iterations, and their QoIs match the V-cycle solve and the oracle."""
+    model, m = FULL.model, 128
+    ids = [31, 601, 672, 0, 1]
+    kk = f64(len(ids), m, m)
+    sid = torch.tensor(ids, dtype=torch.int32, device=DEV)
+    lib.mlmc_sample_field_ids(ctx, model, m, 1, sid, len(ids), kk)
+    kh = kk.cpu().numpy()
+    w = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(omega=2.0))
+    v = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(omega=2.0, gamma=1))
+    print("W iterations", w["iters"], "V iterations", v["iters"], flush=True)
+    assert np.all(w["status"] == 0) and np.all(w["relres"] < 1e-12)
+    assert np.max(w["iters"][:3]) >= 15 and np.all(w["iters"][3:] <= 12)
+    np.testing.assert_allclose(w["q_out"], v["q_out"], rtol=QTOL)
+    q = omlmc.solve_qoi(kh[0])[0]
+    assert abs(w["q_out"][0] - q) <= QTOL * q
 
 
 # ------------------------------------------------------------------ reduced-precision multigrid
