@@ -7,6 +7,8 @@ samples) sample k by circulant embedding, assemble the finite volume system,
 solve it by multigrid-preconditioned CG to relative residual 1e-13, take the
 outflow QoI, do the same for the plain coarse companion (levels >= 1), and
 reduce Y = Q_f - Q_c into the level sums.  Every step draws fresh samples.
+The levels run one after another (each on its own context and stream);
+--concurrent-levels runs them at once from four host threads.
 
 Prints one JSON line: value = Y-samples per second over all levels (the
 per-level rates are in "per_level"), a roofline entry for the dominant
@@ -17,6 +19,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +46,8 @@ def parse():
                     help="offered request rates as fractions of the batched throughput ('' = skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals per offered rate")
+    ap.add_argument("--concurrent-levels", action="store_true",
+                    help="run the levels of a step at once (own streams and host threads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -196,17 +201,44 @@ def main():
     nlev = len(wl.m_levels)
     level_times = [[] for _ in range(nlev)]
     iters = [[] for _ in range(nlev)]
+    # Each level runs on its own context and stream.  With --concurrent-levels
+    # the levels (independent of each other) also run from their own host
+    # threads, so one level's latency-bound coarse-grid launches overlap
+    # another's bandwidth-bound fine-grid launches; kernel durations then
+    # include that overlap, so the roofline entry is only meaningful without it.
+    lstreams = [torch.cuda.Stream(dev) for _ in range(nlev)]
+    lctx = [lib.mlmc_ctx_create(dev, st) for st in lstreams]
 
     def step(idx, record):
-        sums = []
-        for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
-            t0 = time.perf_counter()
-            s = lib.mlmc_level_run(ctx, wl.model, level, m, idx * n, n, wl.cgv, opts)
-            dt = time.perf_counter() - t0
+        sums = [None] * nlev
+        errors = []
+
+        def run(level):
+            m, n = wl.m_levels[level], wl.n_samples[level]
+            try:
+                t0 = time.perf_counter()
+                s = lib.mlmc_level_run(lctx[level], wl.model, level, m, idx * n, n, wl.cgv, opts)
+                lstreams[level].synchronize()
+                dt = time.perf_counter() - t0
+            except Exception as e:  # noqa: BLE001 - re-raised below on the main thread
+                errors.append(e)
+                return
             if record:
                 level_times[level].append(dt)
                 iters[level].append((s.iters_fine / n, s.iters_coarse / max(n, 1)))
-            sums.append(s)
+            sums[level] = s
+
+        if not args.concurrent_levels:
+            for level in range(nlev):
+                run(level)
+        else:
+            threads = [threading.Thread(target=run, args=(level,)) for level in range(nlev)]
+            for th in threads:
+                th.start()
+            for th in threads:
+                th.join()
+        if errors:
+            raise errors[0]
         return sums
 
     def per_sample_baseline(budget_s=1.5):
@@ -228,17 +260,24 @@ def main():
     for w in range(args.warmup):
         step(w, False)
     torch.cuda.synchronize()
-    lib.mlmc_profile_enable(ctx, args.kernel)
+    for c in lctx:
+        lib.mlmc_profile_enable(c, args.kernel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         sums = step(args.warmup + k, True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = lib.mlmc_profile_read(ctx)
-    lib.mlmc_profile_enable(ctx, None)
+    prof = {"launches": 0, "total_ms": 0.0, "algorithmic_bytes": 0.0}
+    for c in lctx:
+        pr = lib.mlmc_profile_read(c)
+        for key in prof:
+            prof[key] += pr[key]
+        lib.mlmc_profile_enable(c, None)
     est = lib.mlmc_estimate(sums)
     single = per_sample_baseline() if not args.no_per_sample else None
+    for c in lctx:
+        lib.mlmc_ctx_destroy(c)
     lib.mlmc_ctx_destroy(ctx)
 
     ms_per_step = 1e3 * elapsed / args.steps
@@ -274,6 +313,7 @@ def main():
                       "n_ce": [wl.model.n_ce[m] for m in wl.m_levels],
                       "model": "2 layers, 8-node interface, exp. covariance r=2, sigma2=1, "
                                "lambda=0.3, means 0/2"},
+           "levels_concurrent": bool(args.concurrent_levels),
            "per_level": per_level, "estimate": est, "roofline": roof,
            "per_sample_fp64_gpu": single, "serving": serving}
     if not args.no_cpu_baseline:

@@ -132,10 +132,11 @@ typedef struct mlmc_solver_opts {
   int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1   */
   int32_t cycle_max;    /* variant 0: levels of at most this size (2..32, 0 = 32) run
                            in one workgroup per sample                              */
-  int32_t gamma;        /* coarse-grid visits on levels finer than gamma_min_m:
-                           1 V-cycle, 2 W-cycle (default 2)                         */
-  int32_t gamma_min_m;  /* levels of size m <= gamma_min_m take one visit (V);
-                           0: gamma on every level (default 32)                     */
+  int32_t gamma;        /* coarse-grid visits on the gamma_levels finest levels:
+                           1 V-cycle, 2 W-cycle (default 2); a second visit
+                           re-smooths the level before restricting again        */
+  int32_t gamma_levels; /* number of finest levels taking gamma visits, the
+                           coarser ones take one (default 2; 0 = every level)  */
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */
@@ -170,7 +171,7 @@ const char* mlmc_last_error(const mlmc_ctx* ctx);
 
 /* Fill `opts` with the defaults: tol 1e-13, omega 1.9, maxit 200, nu1 = nu2 = 1,
  * coarse_max 4, check_every 4, variant 0, FP64, cycle_max 32, gamma 2,
- * gamma_min_m 32. */
+ * gamma_levels 2. */
 mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* opts);
 
 /* Circulant embedding (Section 3.4, exact sampling of eq. (2.3) on a grid):

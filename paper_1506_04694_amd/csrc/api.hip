@@ -253,7 +253,7 @@ mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
   if (o->cycle_max < 0 || o->cycle_max == 1 || o->cycle_max > kCoarseCycleMax)
     return fail(ctx, MLMC_EINVAL, "cycle_max must be 0 or in [2, 32]");
   if (o->gamma < 1 || o->gamma > 2) return fail(ctx, MLMC_EINVAL, "gamma must be 1 or 2");
-  if (o->gamma_min_m < 0) return fail(ctx, MLMC_EINVAL, "gamma_min_m must be >= 0");
+  if (o->gamma_levels < 0) return fail(ctx, MLMC_EINVAL, "gamma_levels must be >= 0");
   return MLMC_OK;
 }
 
@@ -329,7 +329,7 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* o) {
   o->coarse_max = 4;
   o->check_every = 4;
   o->gamma = 2;
-  o->gamma_min_m = 32;
+  o->gamma_levels = 2;
   return MLMC_OK;
 }
 
@@ -553,9 +553,11 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   int l0 = L;
   CoarseDesc cdesc{};
   std::vector<void*> zmid(L + 1, nullptr);  // W-cycle: z after the second visit's pre-smoothing
-  // coarse-grid visits of level l (W on the fine levels only, by default)
+  // coarse-grid visits of level l (W on the finest levels only, by default)
   int cur_gamma = opts->gamma;
-  auto visits = [&](int l) { return ms[l] > opts->gamma_min_m ? cur_gamma : 1; };
+  auto visits = [&](int l) {
+    return (opts->gamma_levels == 0 || l < opts->gamma_levels) ? cur_gamma : 1;
+  };
   if (fused) {
     l0 = 0;
     const int cmax = opts->cycle_max > 0 ? opts->cycle_max : kCoarseCycleMax;

@@ -1,5 +1,5 @@
-// LDS-resident mixed-radix (2, 3, 4, 5) complex FP64 FFT for one line of
-// length n <= kFftMax, computed by one 256-thread workgroup.
+// LDS-resident mixed-radix (2, 3, 4, 5) complex FP64 FFT for lines of length
+// n <= kFftMax, one or several lines per 256-thread workgroup.
 //
 // Stockham autosort formulation (natural-order input and output): at a stage
 // of radix R with span Ns (product of the radices already applied), butterfly
@@ -11,6 +11,8 @@
 // X_k = sum_j x_j exp(-2 pi i jk / n).  Twiddles come from a table
 // tw[q] = exp(-2 pi i q / n), q < n, in device memory.
 #pragma once
+
+#include <algorithm>
 
 #include "common.hpp"
 
@@ -76,7 +78,7 @@ __device__ __forceinline__ void dft_small(double* xr, double* xi) {
 }
 
 template <int R>
-__device__ __forceinline__ void fft_stage(double* __restrict__ sre, double* __restrict__ sim,
+__device__ __forceinline__ void fft_stage_one(double* __restrict__ sre, double* __restrict__ sim,
                                           const double2* __restrict__ tw, int n, int ns) {
   constexpr int kMaxC = (kFftMax / R + kBlock - 1) / kBlock;
   const int nb = n / R;
@@ -119,19 +121,112 @@ __device__ __forceinline__ void fft_stage(double* __restrict__ sre, double* __re
   __syncthreads();
 }
 
-// In-place forward FFT of the line held in LDS (sre, sim).  All threads of
-// the workgroup must call it; the caller synchronises before the first stage.
+// In-place forward FFT of one line held in LDS (sre, sim) by kBlock threads,
+// butterfly slots sized per radix for the longest line; for lines whose widest
+// stage needs more than one pass of the workgroup this form keeps fewer values
+// live than fft_lines.  All threads call it; the caller synchronises before.
 __device__ __forceinline__ void fft_line(double* sre, double* sim, const double2* tw,
                                          const FftPlan& pl) {
   int ns = 1;
   for (int st = 0; st < pl.nstages; ++st) {
     const int R = pl.radix[st];
-    if (R == 4) fft_stage<4>(sre, sim, tw, pl.n, ns);
-    else if (R == 2) fft_stage<2>(sre, sim, tw, pl.n, ns);
-    else if (R == 3) fft_stage<3>(sre, sim, tw, pl.n, ns);
-    else fft_stage<5>(sre, sim, tw, pl.n, ns);
+    if (R == 4) fft_stage_one<4>(sre, sim, tw, pl.n, ns);
+    else if (R == 2) fft_stage_one<2>(sre, sim, tw, pl.n, ns);
+    else if (R == 3) fft_stage_one<3>(sre, sim, tw, pl.n, ns);
+    else fft_stage_one<5>(sre, sim, tw, pl.n, ns);
     ns *= R;
   }
+}
+
+// q = floor(a / d) for 0 <= a < 2^22, 1 <= d <= 2^13, through one FP32
+// multiply: (a + 1/2) / d stays at least 1/(2d) away from an integer, more than
+// the two roundings (relative 2^-24 each) can move it.
+__device__ __forceinline__ int div_small(int a, float inv_d) {
+  return (int)(((float)a + 0.5f) * inv_d);
+}
+
+// One Stockham stage of radix R over L lines (line q at sre + q n) by a
+// workgroup of T threads; C is the largest number of butterflies (L n / R over
+// T threads) a thread takes.
+template <int R, int C, int T>
+__device__ __forceinline__ void fft_stage(double* __restrict__ sre, double* __restrict__ sim,
+                                          const double2* __restrict__ tw, int n, int ns, int L) {
+  const int nb = n / R;
+  const int step = n / (ns * R);
+  const int total = L * nb;
+  const float inv_nb = 1.0f / (float)nb, inv_ns = 1.0f / (float)ns;
+  double vr[C][R], vi[C][R];
+  int base[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int b = threadIdx.x + c * T;
+    if (b < total) {
+      const int q = div_small(b, inv_nb);
+      const int j = b - q * nb;
+      const int jq = div_small(j, inv_ns);
+      const int kk = j - jq * ns;
+      const double* xr = sre + q * n;
+      const double* xi = sim + q * n;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vr[c][r] = xr[j + r * nb];
+        vi[c][r] = xi[j + r * nb];
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const double2 w = tw[r * kk * step];
+        const double a = vr[c][r], bb = vi[c][r];
+        vr[c][r] = a * w.x - bb * w.y;
+        vi[c][r] = a * w.y + bb * w.x;
+      }
+      base[c] = q * n + jq * ns * R + kk;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int b = threadIdx.x + c * T;
+    if (b < total) {
+      dft_small<R>(vr[c], vi[c]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sre[base[c] + r * ns] = vr[c][r];
+        sim[base[c] + r * ns] = vi[c][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// In-place forward FFT of L lines held in LDS (line q at sre + q n, sim + q n)
+// by a workgroup of T threads.  All threads call it; the caller synchronises
+// before.
+template <int C, int T>
+__device__ __forceinline__ void fft_lines(double* sre, double* sim, const double2* tw,
+                                          const FftPlan& pl, int L) {
+  int ns = 1;
+  for (int st = 0; st < pl.nstages; ++st) {
+    const int R = pl.radix[st];
+    if (R == 4) fft_stage<4, C, T>(sre, sim, tw, pl.n, ns, L);
+    else if (R == 2) fft_stage<2, C, T>(sre, sim, tw, pl.n, ns, L);
+    else if (R == 3) fft_stage<3, C, T>(sre, sim, tw, pl.n, ns, L);
+    else fft_stage<5, C, T>(sre, sim, tw, pl.n, ns, L);
+    ns *= R;
+  }
+}
+
+// Launch shape for lines of the plan's length on 256-thread workgroups: when
+// the widest stage has at most 128 butterflies, L >= 2 lines per workgroup (as
+// many as keep it within 256, at most 8) with one butterfly per thread and
+// stage (fft_lines<1, 256>); otherwise one line per workgroup (fft_line).
+// Measured on MI355X for the embedding lengths 135 and 375: 2.9x and 1.4x
+// faster than one line per workgroup; for 960 and 1875 the single-line form
+// is faster than multi-slot fft_lines (fewer live registers).
+inline int fft_lines_per_group(const FftPlan& pl) {
+  int widest = 1;
+  for (int st = 0; st < pl.nstages; ++st) widest = std::max(widest, pl.n / pl.radix[st]);
+  const int L = 256 / widest;
+  return L < 2 ? 1 : (L > 8 ? 8 : L);
 }
 
 }  // namespace mlmc

@@ -133,9 +133,11 @@ void launch_ce_first_row(hipStream_t st, int n, int m, double sigma2, double lam
                      sigma2, lambda, norm_r, c);
 }
 
-// In-place FFT of nlines lines of a complex array (setup only).
-__global__ void k_fft_lines(double2* __restrict__ data, long long line_stride,
-                            long long elem_stride, const double2* __restrict__ tw, FftPlan pl) {
+// In-place FFT of nlines lines of a complex array (setup only), one line per
+// workgroup.
+__global__ void __launch_bounds__(kBlock)
+k_fft_lines(double2* __restrict__ data, long long line_stride, long long elem_stride,
+            const double2* __restrict__ tw, FftPlan pl) {
   extern __shared__ double lds[];
   double* sre = lds;
   double* sim = lds + pl.n;
@@ -202,95 +204,152 @@ void launch_ce_sqrt_transpose(hipStream_t st, const double2* lam, int n, double*
 }
 
 // ------------------------------------------------------------ pass A
-__global__ void __launch_bounds__(kBlock)
+// Workgroup = L consecutive columns k1 of one sample (C = 0: one column and
+// the single-line FFT): noise of the columns
+// scaled by sqrt(Lambda), FFT along k2, the first m outputs of each column to
+// uT[s][j2][k1] (the L columns give L adjacent entries of every row j2).
+template <int C, int T>
+__global__ void __launch_bounds__(T)
 k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __restrict__ ids,
-            int m, const double* __restrict__ sqT,
-            const double2* __restrict__ tw, FftPlan pl, double2* __restrict__ uT) {
+            int m, const double* __restrict__ sqT, const double2* __restrict__ tw, FftPlan pl,
+            int L, int groups, double2* __restrict__ uT) {
   extern __shared__ double lds[];
   const int n = pl.n;
   double* sre = lds;
-  double* sim = lds + n;
+  double* sim = lds + L * n;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int k1 = blk % n;
-  const int s = blk / n;
+  const int s = blk / groups;
+  const int k1_0 = (blk - s * groups) * L;
+  const int lines = min(L, n - k1_0);
   const uint32_t sample = ids ? ids[s] : (uint32_t)(first + (uint64_t)s);
-  const double* sq = sqT + (long long)k1 * n;
-  // rows 2p and 2p+1 of this column share Philox block p n + k1
-  for (int pr = threadIdx.x; 2 * pr < n; pr += kBlock) {
-    const uint32_t blkid = (uint32_t)pr * (uint32_t)n + (uint32_t)k1;
-    const U4 b = stream_block(seed, blkid, sample, level, kTagNoise);
+  // rows 2p and 2p+1 of column k1 share Philox block p n + k1
+  const int npairs = (n + 1) / 2;
+  const float inv_pairs = 1.0f / (float)npairs;
+  for (int t = threadIdx.x; t < L * npairs; t += T) {
+    const int q = div_small(t, inv_pairs);
+    const int pr = t - q * npairs;
     const int k2 = 2 * pr;
+    double* xr = sre + q * n;
+    double* xi = sim + q * n;
+    if (q >= lines) {
+      xr[k2] = 0.0;
+      xi[k2] = 0.0;
+      if (k2 + 1 < n) {
+        xr[k2 + 1] = 0.0;
+        xi[k2 + 1] = 0.0;
+      }
+      continue;
+    }
+    const int k1 = k1_0 + q;
+    const double* sq = sqT + (long long)k1 * n;
+    const U4 bk = stream_block(seed, (uint32_t)pr * (uint32_t)n + (uint32_t)k1, sample, level,
+                               kTagNoise);
     double zr, zi;
-    box_muller(to_uniform(b.x), to_uniform(b.y), zr, zi);
+    box_muller(to_uniform(bk.x), to_uniform(bk.y), zr, zi);
     const double a = sq[k2];
-    sre[k2] = a * zr;
-    sim[k2] = a * zi;
+    xr[k2] = a * zr;
+    xi[k2] = a * zi;
     if (k2 + 1 < n) {
-      box_muller(to_uniform(b.z), to_uniform(b.w), zr, zi);
+      box_muller(to_uniform(bk.z), to_uniform(bk.w), zr, zi);
       const double a1 = sq[k2 + 1];
-      sre[k2 + 1] = a1 * zr;
-      sim[k2 + 1] = a1 * zi;
+      xr[k2 + 1] = a1 * zr;
+      xi[k2 + 1] = a1 * zi;
     }
   }
   __syncthreads();
-  fft_line(sre, sim, tw, pl);
-  double2* out = uT + (long long)s * m * n + k1;
-  for (int j2 = threadIdx.x; j2 < m; j2 += kBlock)
-    out[(long long)j2 * n] = make_double2(sre[j2], sim[j2]);
+  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
+  else fft_lines<C, T>(sre, sim, tw, pl, L);
+  double2* out = uT + (long long)s * m * n + k1_0;
+  const float inv_lines = 1.0f / (float)lines;
+  for (int t = threadIdx.x; t < lines * m; t += T) {
+    const int j2 = div_small(t, inv_lines);
+    const int q = t - j2 * lines;
+    out[(long long)j2 * n + q] = make_double2(sre[q * n + j2], sim[q * n + j2]);
+  }
+}
+
+template <int C, int T>
+static void pass_a_c(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
+                     const uint32_t* ids, int batch, int m, const double* sqT, const double2* tw,
+                     const FftPlan& pl, int L, double2* uT) {
+  const int groups = (pl.n + L - 1) / L;
+  hipLaunchKernelGGL((k_ce_pass_a<C, T>), dim3(batch * groups), dim3(T),
+                     2 * (size_t)L * pl.n * sizeof(double), st, mdl.seed, (uint32_t)level, first,
+                     ids, m, sqT, tw, pl, L, groups, uT);
 }
 
 void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
                       const uint32_t* ids, int batch, int m, const double* sqT,
                       const double2* tw, const FftPlan& pl, double2* uT) {
-  const int nblocks = batch * pl.n;
-  hipLaunchKernelGGL(k_ce_pass_a, dim3(nblocks), dim3(kBlock), 2 * pl.n * sizeof(double), st,
-                     mdl.seed, (uint32_t)level, first, ids, m, sqT, tw, pl, uT);
+  const int L = fft_lines_per_group(pl);
+  if (L > 1) pass_a_c<1, kBlock>(st, mdl, level, first, ids, batch, m, sqT, tw, pl, L, uT);
+  else pass_a_c<0, kBlock>(st, mdl, level, first, ids, batch, m, sqT, tw, pl, 1, uT);
 }
 
 // ------------------------------------------------------------ pass B
-__global__ void __launch_bounds__(kBlock)
+// Workgroup = L consecutive rows j2 of one sample (C = 0: one row and the
+// single-line FFT): FFT along k1 of uT[s][j2][.],
+// the first m outputs give the two Gaussian layers (real / imaginary part), then
+// k = exp(mean + g) of each cell's layer, and the plain coarse companion's
+// cells from the even rows and columns.
+template <int C, int T>
+__global__ void __launch_bounds__(T)
 k_ce_pass_b(int kind, int n_nodes, int n_layers, double mu0, double mu1, int m,
-            const double2* __restrict__ uT,
-            const double2* __restrict__ tw, FftPlan pl, const double* __restrict__ params,
-            double* __restrict__ k, double* __restrict__ kc) {
+            const double2* __restrict__ uT, const double2* __restrict__ tw, FftPlan pl, int L,
+            int groups, const double* __restrict__ params, double* __restrict__ k,
+            double* __restrict__ kc) {
   extern __shared__ double lds[];
   const int n = pl.n;
   double* sre = lds;
-  double* sim = lds + n;
-  const int j2 = blockIdx.x % m;
-  const int s = blockIdx.x / m;
-  const double2* in = uT + ((long long)s * m + j2) * n;
-  for (int q = threadIdx.x; q < n; q += kBlock) {
-    const double2 v = in[q];
+  double* sim = lds + L * n;
+  const int s = blockIdx.x / groups;
+  const int j2_0 = (blockIdx.x - s * groups) * L;
+  const int lines = min(L, m - j2_0);
+  const double2* in = uT + ((long long)s * m + j2_0) * n;
+  for (int q = threadIdx.x; q < L * n; q += T) {
+    const double2 v = q < lines * n ? in[q] : make_double2(0.0, 0.0);
     sre[q] = v.x;
     sim[q] = v.y;
   }
   __syncthreads();
-  fft_line(sre, sim, tw, pl);
+  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
+  else fft_lines<C, T>(sre, sim, tw, pl, L);
   const double* prm = params + (long long)s * kParamStride;
-  const double y = centre(j2, m);
-  double* krow = k + ((long long)s * m + j2) * m;
   const int mc = m / 2;
-  const bool crow = (kc != nullptr) && ((j2 & 1) == 0);
-  double* kcrow = crow ? kc + ((long long)s * mc + j2 / 2) * mc : nullptr;
-  const double yc = crow ? centre(j2 / 2, mc) : 0.0;
-  for (int j1 = threadIdx.x; j1 < m; j1 += kBlock) {
-    const double g0 = sre[j1], g1 = sim[j1];
+  const float inv_m = 1.0f / (float)m;
+  for (int t = threadIdx.x; t < lines * m; t += T) {
+    const int q = div_small(t, inv_m);
+    const int j1 = t - q * m;
+    const int j2 = j2_0 + q;
+    const double g0 = sre[q * n + j1], g1 = sim[q * n + j1];
+    const double y = centre(j2, m);
     const int l = n_layers > 1 ? layer_of(kind, n_nodes, prm, centre(j1, m), y) : 0;
-    krow[j1] = exp(l == 0 ? mu0 + g0 : mu1 + g1);
-    if (crow && (j1 & 1) == 0) {
+    k[((long long)s * m + j2) * m + j1] = exp(l == 0 ? mu0 + g0 : mu1 + g1);
+    if (kc != nullptr && ((j2 & 1) == 0) && ((j1 & 1) == 0)) {
+      const double yc = centre(j2 / 2, mc);
       const int lc = n_layers > 1 ? layer_of(kind, n_nodes, prm, centre(j1 / 2, mc), yc) : 0;
-      kcrow[j1 / 2] = exp(lc == 0 ? mu0 + g0 : mu1 + g1);
+      kc[((long long)s * mc + j2 / 2) * mc + j1 / 2] = exp(lc == 0 ? mu0 + g0 : mu1 + g1);
     }
   }
+}
+
+template <int C, int T>
+static void pass_b_c(hipStream_t st, const mlmc_model& mdl, int batch, int m, const double2* uT,
+                     const double2* tw, const FftPlan& pl, int L, const double* params, double* k,
+                     double* k_coarse) {
+  const int groups = (m + L - 1) / L;
+  hipLaunchKernelGGL((k_ce_pass_b<C, T>), dim3(batch * groups), dim3(T),
+                     2 * (size_t)L * pl.n * sizeof(double), st, mdl.interface_kind, mdl.n_nodes,
+                     mdl.n_layers, mdl.mu[0], mdl.mu[1], m, uT, tw, pl, L, groups, params, k,
+                     k_coarse);
 }
 
 void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, int batch, int m,
                       const double2* uT, const double2* tw, const FftPlan& pl,
                       const double* params, double* k, double* k_coarse) {
-  hipLaunchKernelGGL(k_ce_pass_b, dim3(batch * m), dim3(kBlock), 2 * pl.n * sizeof(double), st,
-                     mdl.interface_kind, mdl.n_nodes, mdl.n_layers, mdl.mu[0], mdl.mu[1], m, uT,
-                     tw, pl, params, k, k_coarse);
+  const int L = fft_lines_per_group(pl);
+  if (L > 1) pass_b_c<1, kBlock>(st, mdl, batch, m, uT, tw, pl, L, params, k, k_coarse);
+  else pass_b_c<0, kBlock>(st, mdl, batch, m, uT, tw, pl, 1, params, k, k_coarse);
 }
 
 // ------------------------------------------------------------ CGV sub-lattices

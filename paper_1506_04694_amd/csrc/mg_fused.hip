@@ -76,17 +76,18 @@ __device__ __forceinline__ typename Prec<V>::C ldv(const V* p, long long i) {
 // ------------------------------------------------------------------ fixed-tile kernels
 // Tiles of compile-time size TX x TY (used when TX and TY divide m).  Each of
 // the 512 threads owns the frame cells f = tid + 512 k in every phase and
-// keeps their four faces, right-hand side and z in registers; LDS holds only
-// z, which is what neighbours read.  All loads use clamped, always-valid
-// addresses and are resolved by selects, so a thread's loads are issued back
-// to back.  Tiles of one sample run on one XCD, so the halo re-reads hit that
-// XCD's L2.  The frame starts three cells below/left of the tile and spans
-// (TX + 5) x (TY + 5) cells.
+// keeps their four faces, reciprocal diagonal, right-hand side and z in
+// registers; LDS holds z, which is what neighbours read, and the residuals the
+// restriction sums.  All loads use clamped, always-valid addresses and are
+// resolved by selects, so a thread's loads are issued back to back.  Tiles of
+// one sample run on one XCD, so the halo re-reads hit that XCD's L2.  The
+// down/up frame reaches two cells around the tile ((TX + 4) x (TY + 4)), the
+// mid frame four.
 constexpr int kMgThreads = 512;
 
-template <int TX, int TY>
+template <int TX, int TY, int HALO>
 struct Tile {
-  static constexpr int W = TX + 5, H = TY + 5, F = W * H;
+  static constexpr int W = TX + 2 * HALO, H = TY + 2 * HALO, F = W * H;
   static constexpr int K = (F + kMgThreads - 1) / kMgThreads;
 };
 
@@ -103,38 +104,66 @@ struct CellFaces {
   bool in;  // inside the domain
 };
 
-// Faces of cell (i, j): east/north from T, west/south from the neighbour's
-// east/north face or from the boundary arrays; everything 0 outside.
+// Faces of frame cells in two steps.  own_faces loads a cell's east and north
+// faces from T (0 outside the domain); the caller writes them to two frame
+// arrays in LDS, synchronises, and adjacent_faces takes the west and south
+// faces from the neighbours' copies there, or from the boundary arrays on the
+// domain's west / south edge.  Two global loads per frame cell instead of four
+// (plus the boundary arrays only where a lane is on that edge).
 template <class S>
-__device__ __forceinline__ CellFaces<typename Prec<S>::C> cell_faces(const S* __restrict__ Ts,
-                                                                     const S* __restrict__ tbs,
-                                                                     int m, int i, int j) {
+__device__ __forceinline__ CellFaces<typename Prec<S>::C> own_faces(const S* __restrict__ Ts, int m,
+                                                                    int i, int j) {
   using C = typename Prec<S>::C;
   CellFaces<C> v;
   const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
-  const int iw = max(ic - 1, 0), js = max(jc - 1, 0);
-  const int n = m * m;
   v.c = jc * m + ic;
   v.in = i >= 0 && i < m && j >= 0 && j < m;
-  const C te = ldv(Ts, v.c), tn = ldv(Ts, n + v.c);
-  const C tw = ldv(Ts, jc * m + iw), ts = ldv(Ts, n + js * m + ic);
-  const C twb = ldv(tbs, jc), tsb = ldv(tbs, m + ic);
+  const C te = ldv(Ts, v.c), tn = ldv(Ts, m * m + v.c);
   v.te = v.in ? te : C(0);
   v.tn = v.in ? tn : C(0);
-  v.tw = v.in ? (i > 0 ? tw : twb) : C(0);
-  v.ts = v.in ? (j > 0 ? ts : tsb) : C(0);
+  v.tw = C(0);
+  v.ts = C(0);
   return v;
 }
 
+// valid: f is a cell of the frame (fi, fj its column and row, W the pitch).
+// Cells on the frame's own west column / south row (not on the domain edge)
+// load the neighbour's face from T.
+template <class S, class C>
+__device__ __forceinline__ void adjacent_faces(CellFaces<C>& v, const C* se, const C* sn,
+                                               const S* __restrict__ Ts,
+                                               const S* __restrict__ tbs, int m, int i, int j,
+                                               int f, int fi, int fj, int W, bool valid) {
+  if (!valid || !v.in) return;
+  if (i == 0) v.tw = ldv(tbs, j);
+  else if (fi > 0) v.tw = se[f - 1];
+  else v.tw = ldv(Ts, v.c - 1);
+  if (j == 0) v.ts = ldv(tbs, m + i);
+  else if (fj > 0) v.ts = sn[f - W];
+  else v.ts = ldv(Ts, m * m + v.c - m);
+}
+
+template <class C>
+__device__ __forceinline__ C inv_diag(const CellFaces<C>& f) {
+  return f.in ? C(1) / (f.te + f.tw + f.tn + f.ts) : C(0);
+}
+
+template <class C>
+__device__ __forceinline__ C nsum_lds(const CellFaces<C>& f, const C* sz, int fr, int W) {
+  return f.te * sz[fr + 1] + f.tw * sz[fr - 1] + f.tn * sz[fr + W] + f.ts * sz[fr - W];
+}
+
+// down: pre-smoothing from z = 0 (red, then black) and the restricted residual.
 template <int TX, int TY, class S, bool TOP>
 __global__ void __launch_bounds__(kMgThreads)
 k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
             const VecT<S, TOP>* __restrict__ r, S* __restrict__ z, S* __restrict__ rc,
             const int32_t* __restrict__ active) {
   using C = typename Prec<S>::C;
-  using G = Tile<TX, TY>;
+  using G = Tile<TX, TY, 2>;
   constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
   __shared__ C sz[F];
+  __shared__ C sres[F];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -146,22 +175,34 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const S* tbs = tb + s * 2 * m;
   const VecT<S, TOP>* rs = r + s * n;
   CellFaces<C> cf[K];
-  C rv[K], zv[K];
+  C rv[K], zv[K], di[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    cf[k] = cell_faces(Ts, tbs, m, X0 - 3 + fi, Y0 - 3 + fj);
+    cf[k] = own_faces(Ts, m, X0 - 2 + fi, Y0 - 2 + fj);
     const C rr = (C)ldv(rs, cf[k].c);
     rv[k] = cf[k].in ? rr : C(0);
+    if (f < F) {
+      sz[f] = cf[k].te;
+      sres[f] = cf[k].tn;
+    }
   }
-  // red cells of R2: z = r / D; all other cells start at 0
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-    zv[k] = (cf[k].in && fi >= 1 && fj >= 1 && ((fi + fj) & 1) == 0) ? rv[k] / d : C(0);
+    adjacent_faces(cf[k], sz, sres, Ts, tbs, m, X0 - 2 + fi, Y0 - 2 + fj, f, fi, fj, W, f < F);
+    di[k] = inv_diag(cf[k]);
+  }
+  __syncthreads();
+  // red cells of the frame: z = r / D; black cells start at 0
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    zv[k] = ((fi + fj) & 1) == 0 ? rv[k] * di[k] : C(0);
     if (f < F) sz[f] = zv[k];
   }
   __syncthreads();
@@ -170,34 +211,22 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
-      const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-               cf[k].ts * sz[f - W]) / d;
+    if (f < F && cf[k].in && fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1 && ((fi + fj) & 1)) {
+      zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
       sz[f] = zv[k];
     }
   }
   __syncthreads();
   // store the tile; residual of its red cells (black residuals vanish)
   S* zs = z + s * n;
-  C res[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    res[k] = C(0);
-    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
+    if (f < F && fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) {
       Prec<S>::st(zs, cf[k].c, zv[k]);
-      if (((fi + fj) & 1) == 0)
-        res[k] = cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-                 cf[k].ts * sz[f - W];
+      if (((fi + fj) & 1) == 0) sres[f] = nsum_lds(cf[k], sz, f, W);
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if (f < F) sz[f] = res[k];
   }
   __syncthreads();
   const int mc = m / 2;
@@ -205,8 +234,9 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   constexpr int HX = TX / 2, HY = TY / 2;
   for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
     const int cj = c / HX, ci = c - cj * HX;
-    const int fa = (3 + 2 * cj) * W + 3 + 2 * ci;
-    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sz[fa] + sz[fa + W + 1]);
+    // (X0 + 2ci, Y0 + 2cj) has even i + j: the block's red cells are (0,0) and (1,1)
+    const int fa = (2 + 2 * cj) * W + 2 + 2 * ci;
+    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sres[fa] + sres[fa + W + 1]);
   }
 }
 
@@ -225,9 +255,10 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
            const S* __restrict__ zc, double omega, S* __restrict__ rc,
            const int32_t* __restrict__ active) {
   using C = typename Prec<S>::C;
-  constexpr int W = TX + 8, H = TY + 8, F = W * H;
-  constexpr int K = (F + kMgThreads - 1) / kMgThreads;
+  using G = Tile<TX, TY, 4>;
+  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
   __shared__ C sz[F];
+  __shared__ C sres[F];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -242,18 +273,35 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const S* zcs = zc + s * (long long)mc * mc;
   const C om = (C)omega;
   CellFaces<C> cf[K];
-  C rv[K], zv[K];
+  C rv[K], zv[K], di[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
     const int i = X0 - 4 + fi, j = Y0 - 4 + fj;
-    cf[k] = cell_faces(Ts, tbs, m, i, j);
+    cf[k] = own_faces(Ts, m, i, j);
     const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
     const C rr = (C)ldv(r + s * n, cf[k].c);
     const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
     rv[k] = cf[k].in ? rr : C(0);
     zv[k] = cf[k].in ? zp + om * zcv : C(0);
+    if (f < F) {
+      sz[f] = cf[k].te;
+      sres[f] = cf[k].tn;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    adjacent_faces(cf[k], sz, sres, Ts, tbs, m, X0 - 4 + fi, Y0 - 4 + fj, f, fi, fj, W, f < F);
+    di[k] = inv_diag(cf[k]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
     if (f < F) sz[f] = zv[k];
   }
   __syncthreads();
@@ -267,9 +315,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
       const int fj = f / W, fi = f - fj * W;
       if (f < F && cf[k].in && fi >= 4 - d && fi < W - 4 + d && fj >= 4 - d && fj < H - 4 + d &&
           ((fi + fj) & 1) == col) {
-        const C dd = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-        zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-                 cf[k].ts * sz[f - W]) / dd;
+        zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
         sz[f] = zv[k];
       }
     }
@@ -277,26 +323,17 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   }
   // store the tile; residual of its red cells (black residuals vanish after the black sweep)
   S* zs = z + s * n;
-  C res[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    res[k] = C(0);
     if (f < F && fi >= 4 && fi < 4 + TX && fj >= 4 && fj < 4 + TY) {
       Prec<S>::st(zs, cf[k].c, zv[k]);
       if (((fi + fj) & 1) == 0) {
         const C dd = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-        res[k] = rv[k] - dd * zv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] +
-                 cf[k].tn * sz[f + W] + cf[k].ts * sz[f - W];
+        sres[f] = rv[k] - dd * zv[k] + nsum_lds(cf[k], sz, f, W);
       }
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if (f < F) sz[f] = res[k];
   }
   __syncthreads();
   S* rcs = rc + s * (long long)mc * mc;
@@ -304,10 +341,12 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
     const int cj = c / HX, ci = c - cj * HX;
     const int fa = (4 + 2 * cj) * W + 4 + 2 * ci;
-    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sz[fa] + sz[fa + W + 1]);
+    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sres[fa] + sres[fa + W + 1]);
   }
 }
 
+// up: z = z_in + omega P e, post-smoothing (black, then red) and, on the finest
+// level, the per-tile partial of r^T z.
 template <int TX, int TY, class S, bool TOP>
 __global__ void __launch_bounds__(kMgThreads)
 k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
@@ -315,9 +354,10 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
           VecT<S, TOP>* __restrict__ z, const S* __restrict__ zc, double omega,
           const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
   using C = typename Prec<S>::C;
-  using G = Tile<TX, TY>;
+  using G = Tile<TX, TY, 2>;
   constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
   __shared__ C sz[F];
+  __shared__ C sn[F];
   __shared__ double red[kMgThreads / kWave];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -334,20 +374,37 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const S* zcs = zc + s * (long long)mc * mc;
   const C om = (C)omega;
   CellFaces<C> cf[K];
-  C rv[K], zv[K];
+  C rv[K], zv[K], di[K];
   double rd[K];  // FP64 residual for the r^T z sum (finest level only)
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    const int i = X0 - 3 + fi, j = Y0 - 3 + fj;
-    cf[k] = cell_faces(Ts, tbs, m, i, j);
+    const int i = X0 - 2 + fi, j = Y0 - 2 + fj;
+    cf[k] = own_faces(Ts, m, i, j);
     const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
     const double rr = (double)ldv(rs, cf[k].c);
     const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
     rd[k] = cf[k].in ? rr : 0.0;
     rv[k] = (C)rd[k];
     zv[k] = cf[k].in ? zp + om * zcv : C(0);
+    if (f < F) {
+      sz[f] = cf[k].te;
+      sn[f] = cf[k].tn;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    adjacent_faces(cf[k], sz, sn, Ts, tbs, m, X0 - 2 + fi, Y0 - 2 + fj, f, fi, fj, W, f < F);
+    di[k] = inv_diag(cf[k]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
     if (f < F) sz[f] = zv[k];
   }
   __syncthreads();
@@ -356,10 +413,8 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    if (f < F && cf[k].in && fi >= 2 && fi < W - 1 && fj >= 2 && fj < H - 1 && ((fi + fj) & 1)) {
-      const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-      zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-               cf[k].ts * sz[f - W]) / d;
+    if (f < F && cf[k].in && fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1 && ((fi + fj) & 1)) {
+      zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
       sz[f] = zv[k];
     }
   }
@@ -371,12 +426,8 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    if (f < F && fi >= 3 && fi < 3 + TX && fj >= 3 && fj < 3 + TY) {
-      if (((fi + fj) & 1) == 0) {
-        const C d = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-        zv[k] = (rv[k] + cf[k].te * sz[f + 1] + cf[k].tw * sz[f - 1] + cf[k].tn * sz[f + W] +
-                 cf[k].ts * sz[f - W]) / d;
-      }
+    if (f < F && fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) {
+      if (((fi + fj) & 1) == 0) zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
       Prec<VecT<S, TOP>>::st(zs, cf[k].c, zv[k]);
       if (TOP) acc += rd[k] * (double)zv[k];
     }
@@ -410,6 +461,7 @@ k_cg_direction_t(int m, const double* __restrict__ T, const double* __restrict__
   constexpr int W = TX + 2, H = TY + 2, F = W * H;
   constexpr int K = (F + kMgThreads - 1) / kMgThreads;
   __shared__ double sp[F];
+  __shared__ double sn[F];
   __shared__ double red[kMgThreads / kWave];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -430,9 +482,25 @@ k_cg_direction_t(int m, const double* __restrict__ T, const double* __restrict__
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
     const int i = X0 - 1 + fi, j = Y0 - 1 + fj;
-    cf[k] = cell_faces(Ts, tbs, m, i, j);
+    cf[k] = own_faces(Ts, m, i, j);
     const double zv = zs[cf[k].c], po = ps[cf[k].c];
     pv[k] = cf[k].in ? (first ? zv : zv + bt * po) : 0.0;
+    if (f < F) {
+      sp[f] = cf[k].te;
+      sn[f] = cf[k].tn;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
+    const int fj = f / W, fi = f - fj * W;
+    adjacent_faces(cf[k], sp, sn, Ts, tbs, m, X0 - 1 + fi, Y0 - 1 + fj, f, fi, fj, W, f < F);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = threadIdx.x + k * kMgThreads;
     if (f < F) sp[f] = pv[k];
   }
   __syncthreads();
@@ -872,6 +940,254 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0
   }
 }
 
+// V-cycle form of the coarse cycle (optionally W at its finest level) with
+// the operator in registers.  One
+// workgroup of 512 threads per sample; thread t owns cells t and t + 512 of
+// level l0 (m <= 32) and cell t of every coarser smoothing level, with their
+// faces, reciprocal diagonal, right-hand side and z in registers.  LDS holds
+// only z of every level (padded (m + 2)^2 layout, zero ring), the residual
+// the restriction gathers, and the coarsest right-hand side.  NL = number of
+// smoothing levels (the coarsest, solved with its dense inverse, is level NL).
+constexpr int kCcThreads = 512;
+constexpr int kCcMaxSmooth = 5;
+
+struct CcCell {
+  double te, tw, tn, ts, di, r, z;
+  int cell, f;  // linear index in the level, index in the padded z array
+  bool in;      // the slot holds a cell of the level
+  bool red;
+};
+
+template <class S>
+__device__ __forceinline__ void cc_load(CcCell& c, const S* __restrict__ Ts,
+                                        const S* __restrict__ tbs, int m, int cell) {
+  const int n = m * m;
+  c.in = cell < n;
+  const int q = c.in ? cell : 0;
+  const int j = q / m, i = q - j * m;
+  c.cell = q;
+  c.f = pidx(m + 2, i, j);
+  c.red = ((i + j) & 1) == 0;
+  const double te = (double)ldv(Ts, q), tn = (double)ldv(Ts, n + q);
+  const double tw = (double)(i > 0 ? ldv(Ts, q - 1) : ldv(tbs, j));
+  const double ts = (double)(j > 0 ? ldv(Ts, n + q - m) : ldv(tbs, m + i));
+  c.te = te;
+  c.tn = tn;
+  c.tw = tw;
+  c.ts = ts;
+  c.di = c.in ? 1.0 / (te + tw + tn + ts) : 0.0;
+  c.r = 0.0;
+  c.z = 0.0;
+}
+
+__device__ __forceinline__ double cc_nsum(const CcCell& c, const double* z, int P) {
+  return c.te * z[c.f + 1] + c.tw * z[c.f - 1] + c.tn * z[c.f + P] + c.ts * z[c.f - P];
+}
+
+// One colour of a Gauss-Seidel sweep over a thread's slots (zero: z = 0 before).
+template <int K>
+__device__ __forceinline__ void cc_smooth(CcCell* c, double* z, int P, bool red, bool zero) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (c[k].in && c[k].red == red) {
+      c[k].z = zero ? c[k].r * c[k].di : (c[k].r + cc_nsum(c[k], z, P)) * c[k].di;
+      z[c[k].f] = c[k].z;
+    }
+  }
+  __syncthreads();
+}
+
+// Restriction of the red-cell residuals held in sres (level of size m) to the
+// coarse level: coarse cell t gathers fine cells (2I, 2J) and (2I + 1, 2J + 1).
+__device__ __forceinline__ double cc_gather(const double* sres, int m, int mc, int t) {
+  if (t >= mc * mc) return 0.0;
+  const int J = t / mc, I = t - J * mc;
+  return sres[(2 * J) * m + 2 * I] + sres[(2 * J + 1) * m + 2 * I + 1];
+}
+
+__device__ __forceinline__ void cc_residual(const CcCell& c, const double* z, int P, double* sres) {
+  if (c.in && c.red)
+    sres[c.cell] = c.r - (c.te + c.tw + c.tn + c.ts) * c.z + cc_nsum(c, z, P);
+}
+
+__device__ __forceinline__ void cc_prolong(CcCell& c, double* z, const double* zc, int m, int Pc,
+                                           double omega) {
+  if (c.in) {
+    const int j = c.cell / m, i = c.cell - j * m;
+    c.z += omega * zc[pidx(Pc, i >> 1, j >> 1)];
+    z[c.f] = c.z;
+  }
+}
+
+// W0: level l0 takes two coarse visits (W), the levels below one (V).
+template <class S, bool TOP, int NL, bool W0>
+__global__ void __launch_bounds__(kCcThreads)
+k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>* __restrict__ z0,
+              const double* __restrict__ Ainv, double omega, const int32_t* __restrict__ active,
+              double* __restrict__ rz_partial) {
+  extern __shared__ double lds[];
+  const int s = blockIdx.x;
+  if (!active[s]) return;
+  const int t = threadIdx.x;
+  int zoff[NL + 1];
+  int off = 0;
+#pragma unroll
+  for (int l = 0; l <= NL; ++l) {
+    zoff[l] = off;
+    off += (desc.m[l] + 2) * (desc.m[l] + 2);
+  }
+  double* sres = lds + off;                        // m0^2 residuals of the level being restricted
+  double* vec = sres + desc.m[0] * desc.m[0];      // coarsest right-hand side
+  for (int q = t; q < off; q += kCcThreads) lds[q] = 0.0;
+  // level l0: two slots; coarser smoothing levels: one
+  CcCell c0[2];
+  CcCell cl[NL > 1 ? NL - 1 : 1];
+  const int m0 = desc.m[0];
+  const long long n0 = (long long)m0 * m0;
+  {
+    const S* Ts = static_cast<const S*>(desc.T[0]) + (long long)s * 2 * n0;
+    const S* tbs = static_cast<const S*>(desc.tb[0]) + (long long)s * 2 * m0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      cc_load(c0[k], Ts, tbs, m0, t + k * kCcThreads);
+      const double rr = (double)ldv(r0, (long long)s * n0 + c0[k].cell);
+      c0[k].r = c0[k].in ? rr : 0.0;
+    }
+  }
+#pragma unroll
+  for (int l = 1; l < NL; ++l) {
+    const int m = desc.m[l];
+    const long long n = (long long)m * m;
+    cc_load(cl[l - 1], static_cast<const S*>(desc.T[l]) + (long long)s * 2 * n,
+            static_cast<const S*>(desc.tb[l]) + (long long)s * 2 * m, m, t);
+  }
+  __syncthreads();
+  const int mL = desc.m[NL], nL = mL * mL;
+  if (NL == 0) {
+    // the coarsest level is level l0: dense inverse only
+    for (int q = t; q < nL; q += kCcThreads) vec[q] = (double)ldv(r0, (long long)s * nL + q);
+    __syncthreads();
+    double acc = 0.0;
+    if (t < nL) {
+      const double* A = Ainv + (long long)s * nL * nL;
+      for (int p = 0; p < nL; ++p) acc += A[t * nL + p] * vec[p];
+      Prec<VecT<S, TOP>>::st(z0, (long long)s * nL + t, acc);
+      acc *= vec[t];
+    }
+    if (TOP && rz_partial) {
+      __shared__ double red[kCcThreads / kWave];
+      acc = wave_sum(acc);
+      if ((t & (kWave - 1)) == 0) red[t / kWave] = acc;
+      __syncthreads();
+      if (t == 0) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kCcThreads / kWave; ++w) sum += red[w];
+        rz_partial[s] = sum;
+      }
+    }
+    return;
+  }
+  // right-hand side of level 1 (or of the coarsest) from the red residuals in sres
+  auto hand_down = [&](int l) {
+    const double rc = cc_gather(sres, desc.m[l], desc.m[l + 1], t);
+    if (l + 1 < NL) {
+#pragma unroll
+      for (int q = 1; q < NL; ++q)
+        if (q == l + 1) cl[q - 1].r = rc;
+    } else if (t < nL) {
+      vec[t] = rc;
+    }
+    __syncthreads();
+  };
+  // ---- level l0 pre-smoothing: red from zero, black, residual
+  {
+    double* z = lds + zoff[0];
+    const int P = m0 + 2;
+    cc_smooth<2>(c0, z, P, true, true);
+    cc_smooth<2>(c0, z, P, false, false);
+    cc_residual(c0[0], z, P, sres);
+    cc_residual(c0[1], z, P, sres);
+    __syncthreads();
+    hand_down(0);
+  }
+  for (int visit = 0; visit < (W0 ? 2 : 1); ++visit) {
+    if (visit > 0) {
+      // second visit: pre-smoothing from the current z (its red sweep would
+      // repeat the last one, so only black), residual
+      double* z = lds + zoff[0];
+      const int P = m0 + 2;
+      cc_smooth<2>(c0, z, P, false, false);
+      cc_residual(c0[0], z, P, sres);
+      cc_residual(c0[1], z, P, sres);
+      __syncthreads();
+      hand_down(0);
+    }
+    // ---- V-cycle on levels 1 .. NL - 1 from z = 0
+#pragma unroll
+    for (int l = 1; l < NL; ++l) {
+      const int P = desc.m[l] + 2;
+      double* z = lds + zoff[l];
+      CcCell& c = cl[l - 1];
+      cc_smooth<1>(&c, z, P, true, true);
+      cc_smooth<1>(&c, z, P, false, false);
+      cc_residual(c, z, P, sres);
+      __syncthreads();
+      hand_down(l);
+    }
+    // ---- coarsest level: dense inverse
+    {
+      double* z = lds + zoff[NL];
+      if (t < nL) {
+        const double* A = Ainv + (long long)s * nL * nL;
+        double acc = 0.0;
+        for (int p = 0; p < nL; ++p) acc += A[t * nL + p] * vec[p];
+        z[pidx(mL + 2, t % mL, t / mL)] = acc;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int l = NL - 1; l >= 1; --l) {
+      const int m = desc.m[l], P = m + 2, Pc = desc.m[l + 1] + 2;
+      double* z = lds + zoff[l];
+      CcCell& c = cl[l - 1];
+      cc_prolong(c, z, lds + zoff[l + 1], m, Pc, omega);
+      __syncthreads();
+      cc_smooth<1>(&c, z, P, false, false);
+      cc_smooth<1>(&c, z, P, true, false);
+    }
+    // ---- level l0: correction and post-smoothing (black, red)
+    {
+      double* z = lds + zoff[0];
+      const int P = m0 + 2, Pc = desc.m[1] + 2;
+      cc_prolong(c0[0], z, lds + zoff[1], m0, Pc, omega);
+      cc_prolong(c0[1], z, lds + zoff[1], m0, Pc, omega);
+      __syncthreads();
+      cc_smooth<2>(c0, z, P, false, false);
+      cc_smooth<2>(c0, z, P, true, false);
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (c0[k].in) {
+      Prec<VecT<S, TOP>>::st(z0, (long long)s * n0 + c0[k].cell, c0[k].z);
+      acc += c0[k].r * c0[k].z;
+    }
+  if (TOP && rz_partial) {
+    __shared__ double red[kCcThreads / kWave];
+    acc = wave_sum(acc);
+    if ((t & (kWave - 1)) == 0) red[t / kWave] = acc;
+    __syncthreads();
+    if (t == 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < kCcThreads / kWave; ++w) sum += red[w];
+      rz_partial[s] = sum;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ conversions
 template <class S>
 __global__ void k_convert(long long count, const double* __restrict__ x, S* __restrict__ y) {
@@ -990,10 +1306,55 @@ static void up_any(bool top, hipStream_t st, int m, int batch, const void* T, co
   else up_impl<S, false>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
 }
 
+template <class S, bool TOP, int NL, bool W0>
+static void coarse_v_impl(hipStream_t st, int batch, const CoarseDesc& desc, const void* r0,
+                          void* z0, const double* Ainv, double omega, const int32_t* active,
+                          double* rz_partial) {
+  using R = VecT<S, TOP>;
+  size_t words = 0;
+  for (int l = 0; l <= NL; ++l) words += (size_t)(desc.m[l] + 2) * (desc.m[l] + 2);
+  words += (size_t)desc.m[0] * desc.m[0] + (size_t)desc.m[NL] * desc.m[NL];
+  hipLaunchKernelGGL((k_mg_coarse_v<S, TOP, NL, W0>), dim3(batch), dim3(kCcThreads),
+                     words * sizeof(double), st, desc, (const R*)r0, (R*)z0, Ainv, omega, active,
+                     rz_partial);
+}
+
+template <class S, bool TOP, bool W0>
+static void coarse_v_nl(hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
+                        const void* r0, void* z0, const double* Ainv, double omega,
+                        const int32_t* active, double* rz_partial) {
+#define CCV(NL) coarse_v_impl<S, TOP, NL, W0>(st, batch, desc, r0, z0, Ainv, omega, active, rz_partial)
+  switch (nlev - 1) {
+    case 0: CCV(0); break;
+    case 1: CCV(1); break;
+    case 2: CCV(2); break;
+    case 3: CCV(3); break;
+    case 4: CCV(4); break;
+    default: CCV(5); break;
+  }
+#undef CCV
+}
+
+template <class S, bool TOP>
+static void coarse_v_any(hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
+                         const void* r0, void* z0, const double* Ainv, double omega, bool w0,
+                         const int32_t* active, double* rz_partial) {
+  if (w0) coarse_v_nl<S, TOP, true>(st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
+  else coarse_v_nl<S, TOP, false>(st, batch, nlev, desc, r0, z0, Ainv, omega, active, rz_partial);
+}
+
 template <class S>
 static void coarse_any(bool top, hipStream_t st, int batch, int nlev, const CoarseDesc& desc,
                        const void* r0, void* z0, const double* Ainv, double omega, unsigned wmask,
                        const int32_t* active, double* rz_partial) {
+  if ((wmask & ~1u) == 0 && nlev - 1 <= kCcMaxSmooth && desc.m[0] <= 32) {
+    const bool w0 = (wmask & 1u) && nlev > 1;
+    if (top)
+      coarse_v_any<S, true>(st, batch, nlev, desc, r0, z0, Ainv, omega, w0, active, rz_partial);
+    else
+      coarse_v_any<S, false>(st, batch, nlev, desc, r0, z0, Ainv, omega, w0, active, rz_partial);
+    return;
+  }
   const size_t lds = coarse_cycle_lds_bytes(desc, nlev);
   if (top)
     hipLaunchKernelGGL((k_mg_coarse_cycle<S, true>), dim3(batch), dim3(kBlock), lds, st, nlev, desc,
