@@ -29,7 +29,7 @@ import workloads as W  # noqa: E402
 
 METRIC = "MLMC samples solved/s per level at 1e-10 QoI rel-err; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-DOMINANT = "k_mg_up"
+DOMINANT = "k_mg_mid"
 
 
 def parse():
@@ -140,8 +140,9 @@ def serving_latency(lib, wl, rate, seconds, seed=1):
             "per_level": per_level}
 
 
-KERNEL_SOURCES = {"k_mg_up": "mg_fused.hip", "k_mg_down": "mg_fused.hip",
-                  "k_mg_coarse_cycle": "mg_fused.hip", "k_spmv_dot": "mg_pcg.hip",
+KERNEL_SOURCES = {"k_mg_mid": "mg_fused.hip", "k_mg_up": "mg_fused.hip",
+                  "k_mg_down": "mg_fused.hip", "k_mg_coarse_cycle": "mg_fused.hip",
+                  "k_cg_direction_t": "mg_fused.hip", "k_spmv_dot": "mg_pcg.hip",
                   "k_axpy_dot": "mg_pcg.hip", "k_ce_pass_a": "field.hip", "k_ce_pass_b": "field.hip"}
 
 

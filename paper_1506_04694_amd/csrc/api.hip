@@ -37,7 +37,9 @@ struct Buffer {
 
 struct ProfEvent {
   hipEvent_t a, b;
-  double bytes;
+  double bytes;  // algorithmic bytes of the launch over the whole batch
+  int iter;      // PCG iteration it belongs to (samples still active then do the
+                 // work); 0: bytes already final
 };
 
 }  // namespace
@@ -51,6 +53,7 @@ struct mlmc_ctx {
   void* host_pinned = nullptr;  // small pinned staging buffer
   std::string prof_name;
   double prof_scale = 1.0;  // share of the batch a launch works on (restart passes)
+  int prof_iter = 0;        // PCG iteration of the launches being enqueued (0: n/a)
   std::vector<ProfEvent> prof;
   std::vector<hipEvent_t> event_pool;
 };
@@ -128,7 +131,7 @@ hipEvent_t pool_event(mlmc_ctx* ctx) {
 template <class F>
 void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch) {
   if (!ctx->prof_name.empty() && ctx->prof_name == name) {
-    ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes * ctx->prof_scale};
+    ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes * ctx->prof_scale, ctx->prof_iter};
     (void)hipEventRecord(pe.a, ctx->stream);
     launch();
     (void)hipEventRecord(pe.b, ctx->stream);
@@ -689,11 +692,13 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   auto pcg_pass = [&](bool restart) -> mlmc_status {
     launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
     launch_sc_init(st, batch, partial, bps, S, status, iters, relres, restart ? 1 : 0);
+    ctx->prof_iter = restart ? 0 : 1;
     vcycle();
     launch_sc_rho(st, batch, partial, rz_parts, S, status, 1, nullptr, 0);
     if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
     CHECK_LAUNCH();
     for (int it = 1;; ++it) {
+      ctx->prof_iter = restart ? 0 : it;
       if (dir_fused) {
         // iteration it writes p into pbuf[it % 2] from pbuf[(it - 1) % 2]
         pv = pbuf[it & 1];
@@ -718,13 +723,31 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
         HIP_TRY(hipStreamSynchronize(st));
         if (*hcount == 0) break;
       }
+      ctx->prof_iter = restart ? 0 : it + 1;
       vcycle();
       launch_sc_rho(st, batch, partial, rz_parts, S, status, 0, partial2, bps);
       if (!dir_fused) launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
     }
     return MLMC_OK;
   };
+  const size_t prof_begin = ctx->prof.size();
   TRY(pcg_pass(false));
+  ctx->prof_iter = 0;
+  // profiled launches: the work of iteration it is done for the samples with
+  // iters >= it (converged or failed samples skip their tiles)
+  if (ctx->prof.size() > prof_begin) {
+    std::vector<int32_t> hi(batch);
+    HIP_TRY(hipMemcpyAsync(hi.data(), iters, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::sort(hi.begin(), hi.end());
+    for (size_t e = prof_begin; e < ctx->prof.size(); ++e) {
+      ProfEvent& pe = ctx->prof[e];
+      if (pe.iter <= 0) continue;
+      const long long active = hi.end() - std::lower_bound(hi.begin(), hi.end(), pe.iter);
+      pe.bytes *= (double)active / batch;
+      pe.iter = 0;
+    }
+  }
   // The W-cycle preconditioner is symmetric but, with over-corrected coarse
   // steps, not positive definite for every operator (two coarse visits act as
   // 2B - BAB, indefinite once B A has an eigenvalue above 2); a sample whose

@@ -84,6 +84,7 @@ __device__ __forceinline__ typename Prec<V>::C ldv(const V* p, long long i) {
 // down/up frame reaches two cells around the tile ((TX + 4) x (TY + 4)), the
 // mid frame four.
 constexpr int kMgThreads = 512;
+constexpr int kMidThreads = 512;  // the mid kernel's frame is larger
 
 template <int TX, int TY, int HALO>
 struct Tile {
@@ -249,14 +250,14 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
 // sweep one cell out, that sweep the red sweep two cells out, that one the
 // first black sweep three cells out, which needs z four cells out.
 template <int TX, int TY, class S, bool TOP>
-__global__ void __launch_bounds__(kMgThreads)
+__global__ void __launch_bounds__(kMidThreads)
 k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
            const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre, S* __restrict__ z,
            const S* __restrict__ zc, double omega, S* __restrict__ rc,
            const int32_t* __restrict__ active) {
   using C = typename Prec<S>::C;
   using G = Tile<TX, TY, 4>;
-  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
+  constexpr int W = G::W, H = G::H, F = G::F, K = (F + kMidThreads - 1) / kMidThreads;
   __shared__ C sz[F];
   __shared__ C sres[F];
   const int ntx = m / TX, tps = ntx * (m / TY);
@@ -276,7 +277,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   C rv[K], zv[K], di[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
+    const int f = threadIdx.x + k * kMidThreads;
     const int fj = f / W, fi = f - fj * W;
     const int i = X0 - 4 + fi, j = Y0 - 4 + fj;
     cf[k] = own_faces(Ts, m, i, j);
@@ -293,7 +294,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
+    const int f = threadIdx.x + k * kMidThreads;
     const int fj = f / W, fi = f - fj * W;
     adjacent_faces(cf[k], sz, sres, Ts, tbs, m, X0 - 4 + fi, Y0 - 4 + fj, f, fi, fj, W, f < F);
     di[k] = inv_diag(cf[k]);
@@ -301,7 +302,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
+    const int f = threadIdx.x + k * kMidThreads;
     if (f < F) sz[f] = zv[k];
   }
   __syncthreads();
@@ -311,7 +312,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
     const int d = 3 - pass, col = (pass == 1) ? 0 : 1;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int f = threadIdx.x + k * kMgThreads;
+      const int f = threadIdx.x + k * kMidThreads;
       const int fj = f / W, fi = f - fj * W;
       if (f < F && cf[k].in && fi >= 4 - d && fi < W - 4 + d && fj >= 4 - d && fj < H - 4 + d &&
           ((fi + fj) & 1) == col) {
@@ -325,7 +326,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   S* zs = z + s * n;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
+    const int f = threadIdx.x + k * kMidThreads;
     const int fj = f / W, fi = f - fj * W;
     if (f < F && fi >= 4 && fi < 4 + TX && fj >= 4 && fj < 4 + TY) {
       Prec<S>::st(zs, cf[k].c, zv[k]);
@@ -338,7 +339,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   __syncthreads();
   S* rcs = rc + s * (long long)mc * mc;
   constexpr int HX = TX / 2, HY = TY / 2;
-  for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
+  for (int c = threadIdx.x; c < HX * HY; c += kMidThreads) {
     const int cj = c / HX, ci = c - cj * HX;
     const int fa = (4 + 2 * cj) * W + 4 + 2 * ci;
     Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sres[fa] + sres[fa + W + 1]);
@@ -1261,7 +1262,7 @@ static void mid_impl(hipStream_t st, int m, int batch, const void* T, const void
   using R = VecT<S, TOP>;
   if (fixed_tile(m)) {
     const int nb = batch * (m / kTileX) * (m / kTileY);
-    hipLaunchKernelGGL((k_mg_mid_t<kTileX, kTileY, S, TOP>), dim3(nb), dim3(kMgThreads), 0, st, m,
+    hipLaunchKernelGGL((k_mg_mid_t<kTileX, kTileY, S, TOP>), dim3(nb), dim3(kMidThreads), 0, st, m,
                        (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (S*)z,
                        (const S*)zc, omega, (S*)rc, active);
     return;
