@@ -46,6 +46,8 @@ def parse():
                     help="offered request rates as fractions of the batched throughput ('' = skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals per offered rate")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the all-levels-in-one-call and FP32-multigrid forms")
     ap.add_argument("--concurrent-levels", action="store_true",
                     help="run the levels of a step at once (own streams and host threads)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -180,6 +182,57 @@ def copy_calibration():
                       "ms": 1e3 * dt, "GB_s_read_plus_write": 16 * n / dt / 1e9}), flush=True)
 
 
+def path_variants(lib, torch, wl, ctx, opts, args):
+    """Two other forms of the same step, timed over args.steps steps each after the
+    main measurement (not part of `value`):
+    * all levels in one call (mlmc_run_levels: one solve per distinct grid, level
+      l's fine samples merged with level l+1's companions), FP64;
+    * the per-level step with the multigrid hierarchy stored in FP32 inside the FP64
+      flexible CG, with the largest relative QoI difference to the FP64 solve of
+      the same samples."""
+    nlev = len(wl.m_levels)
+    base = 100  # step numbers (sample ranges) not used by the main measurement
+
+    def timed(f):
+        f(base)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            f(base + 1 + k)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    def merged(idx):
+        lib.mlmc_run_levels(ctx, wl.model, wl.m_levels, [idx * n for n in wl.n_samples],
+                            wl.n_samples, wl.cgv, opts)
+
+    o32 = lib.mlmc_solver_opts_default(precision=lib.MLMC_PREC_FP32)
+
+    def per_level(o, idx, q=None):
+        for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+            kw = {} if q is None else {"q_f": q[level][0], "q_c": q[level][1]}
+            lib.mlmc_level_run(ctx, wl.model, level, m, idx * n, n, wl.cgv, o, **kw)
+
+    t_merged = timed(merged)
+    t_fp32 = timed(lambda idx: per_level(o32, idx))
+    qs = []
+    for o in (opts, o32):
+        q = [(torch.empty(n, dtype=torch.float64, device="cuda"),
+              torch.empty(n, dtype=torch.float64, device="cuda")) for n in wl.n_samples]
+        per_level(o, base, q)
+        qs.append(q)
+    torch.cuda.synchronize()
+    dev = 0.0
+    for level in range(nlev):
+        for which in ((0,) if level == 0 else (0, 1)):   # Q_f, and Q_c on levels >= 1
+            a, b = qs[0][level][which], qs[1][level][which]
+            dev = max(dev, ((a - b).abs() / a.abs()).max().item())
+    total = sum(wl.n_samples)
+    return {"all_levels_one_call_fp64": {"value": total / t_merged, "ms_per_step": 1e3 * t_merged},
+            "multigrid_fp32_in_fp64_cg": {"value": total / t_fp32, "ms_per_step": 1e3 * t_fp32,
+                                          "max_qoi_rel_diff_vs_fp64": dev}}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -277,6 +330,7 @@ def main():
         lib.mlmc_profile_enable(c, None)
     est = lib.mlmc_estimate(sums)
     single = per_sample_baseline() if not args.no_per_sample else None
+    variants = None if args.no_variants else path_variants(lib, torch, wl, ctx, opts, args)
     for c in lctx:
         lib.mlmc_ctx_destroy(c)
     lib.mlmc_ctx_destroy(ctx)
@@ -316,7 +370,7 @@ def main():
                                "lambda=0.3, means 0/2"},
            "levels_concurrent": bool(args.concurrent_levels),
            "per_level": per_level, "estimate": est, "roofline": roof,
-           "per_sample_fp64_gpu": single, "serving": serving}
+           "per_sample_fp64_gpu": single, "variants": variants, "serving": serving}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)
