@@ -14,7 +14,11 @@ Conventions (readings where the paper or the workload is silent):
 * layer 0 is the bottom layer; a centre lying exactly on an interface
   belongs to the upper layer (a measure-zero event);
 * piecewise-linear nodes sit at x = q/(n-1), q = 0..n-1;
-* in 3D the interface is extruded along x3, as the paper does in 3D.
+* in 3D the 2-D interfaces are extruded along x3, as the paper does in 3D;
+* the tilted plane (3D workload) is x2 = a + (b - a) x1 + c (x3 - 1/2) with
+  a, b ~ U(y_lo, y_hi) and c ~ U(-0.1, 0.1) (uniforms 0, 1, 2): the paper's
+  straight line from (0, a) to (1, b), tilted along x3; x2 stays the
+  vertical axis and x1 the flow direction.
 """
 import numpy as np
 
@@ -23,6 +27,7 @@ from . import philox
 HORIZONTAL = 0
 PIECEWISE_LINEAR = 1
 PAPER_TWO_LINES = 2
+TILTED_PLANE = 3
 NO_INTERFACE = 4
 
 
@@ -52,6 +57,11 @@ def interface_params(model, level, sample):
         u = geometry_uniforms(model, level, sample, 4)
         lo = np.array([0.8, 0.6, 0.2, 0.4])
         return {"y": lo + 0.1 * u}
+    if kind == TILTED_PLANE:
+        u = geometry_uniforms(model, level, sample, 3)
+        a = model.y_lo + (model.y_hi - model.y_lo) * u[0]
+        b = model.y_lo + (model.y_hi - model.y_lo) * u[1]
+        return {"a": a, "b": b, "c": -0.1 + 0.2 * u[2]}
     if kind == NO_INTERFACE:
         return {}
     raise ValueError("unknown interface kind %r" % kind)
@@ -83,6 +93,13 @@ def layer_ids(model, level, sample, m):
         upper = y1 + x1 * (y2 - y1)
         lower = y3 + x1 * (y4 - y3)
         lid = np.where(x2 < lower, 0, np.where(x2 < upper, 1, 2))
+    elif kind == TILTED_PLANE:
+        a, b, c = prm["a"], prm["b"], prm["c"]
+        if d == 3:
+            x3 = x[:, None, None]
+            plane = a + (b - a) * x[None, None, :] + c * (x3 - 0.5)
+            return np.where(x[None, :, None] < plane, 0, 1).astype(np.int64)
+        lid = np.where(x2 < a + (b - a) * x1, 0, 1)
     elif kind == NO_INTERFACE:
         lid = np.zeros((m, m), dtype=np.int64)
     lid = np.broadcast_to(lid, (m, m)).astype(np.int64)

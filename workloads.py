@@ -17,6 +17,7 @@ from typing import List, Tuple
 HORIZONTAL = 0        # one horizontal interface at height y0 ~ U(y_lo, y_hi)
 PIECEWISE_LINEAR = 1  # n_nodes equispaced nodes (x_q = q/(n-1)), heights ~ U(y_lo, y_hi)
 PAPER_TWO_LINES = 2   # Section 3.4: lines (0,y1)-(1,y2) and (0,y3)-(1,y4), three layers
+TILTED_PLANE = 3      # 3-D: x2 = a + (b - a) x1 + c (x3 - 1/2), a, b ~ U(y_lo, y_hi), c ~ U(-0.1, 0.1)
 NO_INTERFACE = 4      # a single layer (stationary field, Section 4.2)
 
 # field_kind
@@ -83,3 +84,13 @@ STATIONARY_1NORM = Model(interface_kind=NO_INTERFACE, n_layers=1, field_kind=COR
                          norm_r=1, mu=(0.0, 0.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0),
                          lam=(0.3, 0.3, 0.3, 0.3), seed=0,
                          n_ce={4: 8, 8: 16, 16: 32, 32: 64, 64: 128, 128: 256, 256: 512})
+
+# 3-D served model: tilted planar interface, two layers with independent
+# stationary Gaussian fields, exponential covariance with the 1-norm (separable,
+# so the embedding of length 2m is non-negative), sigma^2 = 1, lambda = 0.2,
+# means 0 (bottom) and 2 (top).
+TILTED3 = Model(dim=3, interface_kind=TILTED_PLANE, n_layers=2, field_kind=CORRELATED_CE,
+                norm_r=1, mu=(0.0, 2.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0),
+                lam=(0.2, 0.2, 0.2, 0.2), seed=0,
+                n_ce={4: 8, 8: 16, 16: 32, 32: 64, 64: 128, 128: 256})
+SERVED_3D = Workload("3d-ce-tilted-32-128", TILTED3, [32, 64, 128], [64, 16, 4])
