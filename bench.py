@@ -91,6 +91,27 @@ def cpu_baseline(wl, budget_s):
             "per_level_s_per_sample": [p["s_per_sample"] for p in per_level]}
 
 
+def step_rate_3d(lib, torch, wl, reps=2):
+    """Y-samples/s of one pass over every level of a 3-D workload (level runs
+    one after another, FP64, after one warm-up pass)."""
+    ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
+    opts = lib.mlmc_solver_opts_default()
+    first = 0
+    try:
+        for rep in range(reps + 1):
+            if rep == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+                lib.mlmc_level_run(ctx, wl.model, level, m, first, n, wl.cgv, opts)
+            first += max(wl.n_samples)
+        torch.cuda.synchronize()
+        per_pass = (time.perf_counter() - t0) / reps
+    finally:
+        lib.mlmc_ctx_destroy(ctx)
+    return sum(wl.n_samples) / per_pass, per_pass
+
+
 def serving_latency(lib, wl, rate, seconds, seed=1):
     """Poisson arrivals of single-sample requests with the workload's level mix
     (probability of level l proportional to N_l), served by the continuous-
@@ -343,6 +364,13 @@ def main():
         serving = {"saturation_estimate_per_s": sat, "workers": 3, "precision": "f64",
                    "runs": [serving_latency(lib, wl, float(f) * sat, args.serve_seconds)
                             for f in args.serve_rates.split(",") if f]}
+        wl3 = W.SERVED_3D
+        sat3, pass3 = step_rate_3d(lib, torch, wl3)
+        serving["3d"] = {"workload": wl3.name, "levels_m": wl3.m_levels,
+                         "samples_per_pass": wl3.n_samples, "pass_ms": 1e3 * pass3,
+                         "saturation_estimate_per_s": sat3,
+                         "runs": [serving_latency(lib, wl3, float(f) * sat3, args.serve_seconds)
+                                  for f in args.serve_rates.split(",") if f]}
     per_level = []
     for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
         t = sorted(level_times[level])[len(level_times[level]) // 2]

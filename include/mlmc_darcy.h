@@ -70,6 +70,9 @@ enum {
   MLMC_IFACE_PAPER_TWO_LINES = 2,  /* Section 3.4: lines (0,y1)-(1,y2), (0,y3)-(1,y4),
                                       y1~U(.8,.9) y2~U(.6,.7) y3~U(.2,.3) y4~U(.4,.5);
                                       3 layers                                        */
+  MLMC_IFACE_TILTED_PLANE = 3,     /* x2 = a + (b-a) x1 + c (x3 - 1/2), a, b ~ U(y_lo,
+                                      y_hi), c ~ U(-0.1, 0.1); 2 layers; in 2-D the
+                                      line from (0,a) to (1,b)                        */
   MLMC_IFACE_NONE = 4              /* one layer (stationary field)                    */
 };
 
@@ -90,10 +93,12 @@ enum {
  * tag 1 layer constants (normals z0..z3 of block 0 by Box-Muller), tag 2
  * circulant-embedding noise (noise point (k2, k1) takes (z0, z1) of block
  * (k2/2)*n_ce + k1 for even k2 and (z2, z3) of that block for odd k2; real
- * part -> layer 0, imaginary part -> layer 1).
+ * part -> layer 0, imaginary part -> layer 1).  In 3-D the noise lines along
+ * x1 are numbered row = k3 n_ce + k2 and take the same rule with row in place
+ * of k2.
  */
 typedef struct mlmc_model {
-  int32_t dim;            /* 2                                                  */
+  int32_t dim;            /* 2 or 3                                             */
   int32_t interface_kind; /* MLMC_IFACE_*                                       */
   int32_t n_nodes;        /* nodes of a piecewise-linear interface (2..8)       */
   int32_t n_layers;       /* layers actually used (1..3)                        */
@@ -180,17 +185,19 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* opts);
  * n_ce_out: host. */
 mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m, int* n_ce_out);
 
-/* Sample k at the cell centres of an m x m grid for samples first_sample ..
+/* Sample k at the cell centres of an m^d grid for samples first_sample ..
  * first_sample + batch - 1 of `level` (Section 2, Examples 1-2, Section 3.4).
- *   k        device, [batch][m][m], written.
- *   k_coarse device, [batch][m/2][m/2] or NULL.  When given (m even), also
+ *   k        device, [batch][m][m] (d = 2) or [batch][m][m][m] (d = 3,
+ *            k[s][l][j][i] at x = ((i+1/2)h, (j+1/2)h, (l+1/2)h)), written.
+ *   k_coarse device, [batch][m/2]^d or NULL.  When given (m even), also
  *            writes the plain MLMC coarse sample of the same omega (eq. (3.6)):
  *            layers re-evaluated at the coarse centres; piecewise constant
  *            layers keep their value; correlated layers take the Gaussian
- *            value of fine cell (2I, 2J).
- * Correlated fields need model->n_ce valid for m (else MLMC_EEMBED); the
- * embedding eigenvalues are computed once per (m, n_ce, sigma2, lambda, r)
- * and cached in the context. */
+ *            value of fine cell (2I, 2J) (3-D: (2I, 2J, 2L)).
+ * Correlated fields need model->n_ce valid for m (else MLMC_EEMBED; 3-D
+ * embeddings are limited to n_ce <= 512, else MLMC_EINVAL); the embedding
+ * eigenvalues are computed once per (d, m, n_ce, sigma2, lambda, r) and cached
+ * in the context. */
 mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
                               uint64_t first_sample, int batch, double* k, double* k_coarse);
 
@@ -201,14 +208,17 @@ mlmc_status mlmc_sample_field_ids(mlmc_ctx* ctx, const mlmc_model* model, int m,
                                   double* k_coarse);
 
 /* Coarse Grid Variates sub-samples (Section 4.1, eq. (4.1)): the 2^d coarse
- * samples k^(a)(I, J) = k(2I + a1, 2J + a2), a = a1 + 2 a2.
- *   k_fine device [batch][m][m] (m even); k_sub device [batch][4][m/2][m/2]. */
+ * samples k^(a)(I, J) = k(2I + a1, 2J + a2), a = a1 + 2 a2 (3-D:
+ * k^(a)(I, J, L) = k(2I + a1, 2J + a2, 2L + a3), a = a1 + 2 a2 + 4 a3).
+ *   k_fine device [batch][m]^d (m even); k_sub device [batch][2^d][m/2]^d. */
 mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch,
                              const double* k_fine, double* k_sub);
 
 /* Finite volume system eq. (3.3), harmonic-mean faces, Model Problem 2
- * (p = 1 on x1 = 0, p = 0 on x1 = 1, no flow on x2 = 0, 1; f = 0).
+ * (p = 1 on x1 = 0, p = 0 on x1 = 1, no flow on the other faces; f = 0).
+ * A face between cells P and Q has T = h^(d-2) 2 k_P k_Q / (k_P + k_Q);
  * Dirichlet faces use the half-cell distance: T = 2 k_P h^(d-2).
+ * d = 2:
  *   k   device [batch][m][m]            (input, positive)
  *   T   device [batch][2][m][m]: T[s][0][j][i] = transmissibility of the face
  *       x1 = (i+1)h of cell (i,j) (for i = m-1: the outflow boundary face);
@@ -216,6 +226,13 @@ mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch,
  *   tb  device [batch][2][m]: tb[s][0][j] = face x1 = 0 of cell (0,j) (inflow
  *       boundary); tb[s][1][i] = face x2 = 0 of cell (i,0) (0, no flow).
  *   b   device [batch][m][m]: right-hand side (tb[s][0][j] in column i = 0).
+ * d = 3 (cell (i, j, l), c = (l m + j) m + i):
+ *   k, b device [batch][m][m][m];
+ *   T   device [batch][3][m^3]: T[s][0][c] face x1 = (i+1)h (i = m-1: outflow
+ *       boundary), T[s][1][c] face x2 = (j+1)h, T[s][2][c] face x3 = (l+1)h
+ *       (0 on x2 = 1 and x3 = 1);
+ *   tb  device [batch][3][m^2]: tb[s][0][l m + j] face x1 = 0 (inflow),
+ *       tb[s][1][l m + i] face x2 = 0, tb[s][2][j m + i] face x3 = 0 (0).
  * Row P of the system: sum over faces T_f (p_P - p_nb) = b_P, where boundary
  * faces have p_nb = 0 after moving the Dirichlet data to b. */
 mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
@@ -223,9 +240,12 @@ mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double
 
 /* Solve A p = b for each sample of the batch (operator as produced by
  * mlmc_assemble) with conjugate gradients preconditioned by one symmetric
- * geometric multigrid V-cycle (Section 3.5; aggregation coarsening with
- * Galerkin coarse operators, red-black Gauss-Seidel smoothing).
- *   p       device [batch][m][m], written (initial guess 0).
+ * geometric multigrid cycle (Section 3.5; aggregation coarsening with
+ * Galerkin coarse operators, red-black Gauss-Seidel smoothing; W on the
+ * opts->gamma_levels finest levels when opts->gamma = 2).
+ *   p       device [batch][m]^d, written (initial guess 0).
+ * d = 2 needs m = c 2^k with c <= 8; d = 3 needs c <= 4 and FP64 precision
+ * (else MLMC_EINVAL).
  *   status  device int32 [batch], iters device int32 [batch],
  *   relres  device double [batch] = ||b - A p|| / ||b|| recomputed at exit.
  * A sample that fails is reported in status[]; it never stops the batch.
@@ -236,10 +256,10 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
                        double* relres);
 
 /* Outflow M^(2) through x1 = 1 (Section 3.4) of the discrete solution:
- * q_out[s] = sum_j 2 k(m-1, j) h^(d-2) p(m-1, j); q_in[s] (optional, may be
- * NULL) = sum_j 2 k(0, j) h^(d-2) (1 - p(0, j)) (equal to q_out for the exact
- * solution: local conservation).  k, p device [batch][m][m]; q_out, q_in
- * device [batch]. */
+ * q_out[s] = sum over the cells with i = m-1 of 2 k h^(d-2) p; q_in[s]
+ * (optional, may be NULL) = sum over the cells with i = 0 of 2 k h^(d-2)
+ * (1 - p) (equal to q_out for the exact solution: local conservation).
+ * k, p device [batch][m]^d; q_out, q_in device [batch]. */
 mlmc_status mlmc_qoi_outflow(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
                              const double* p, double* q_out, double* q_in);
 

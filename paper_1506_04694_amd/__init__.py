@@ -254,37 +254,42 @@ def mlmc_ce_min_embedding(ctx, model, m):
 
 def mlmc_sample_field(ctx, model, m, level, first_sample, batch, k, k_coarse=None):
     mm = model if isinstance(model, mlmc_model) else model_for_grid(model, m)
+    d = int(mm.dim)
     _check(ctx, _lib.mlmc_sample_field(ctx, ctypes.byref(mm), int(m), int(level),
                                        int(first_sample), int(batch),
-                                       _f64(k, batch * m * m, "k"),
-                                       _f64(k_coarse, batch * (m // 2) ** 2, "k_coarse")))
+                                       _f64(k, batch * m ** d, "k"),
+                                       _f64(k_coarse, batch * (m // 2) ** d, "k_coarse")))
 
 
 def mlmc_cgv_extract(ctx, dim, m, batch, k_fine, k_sub):
-    _check(ctx, _lib.mlmc_cgv_extract(ctx, int(dim), int(m), int(batch),
-                                      _f64(k_fine, batch * m * m, "k_fine"),
-                                      _f64(k_sub, batch * 4 * (m // 2) ** 2, "k_sub")))
+    d = int(dim)
+    _check(ctx, _lib.mlmc_cgv_extract(ctx, d, int(m), int(batch),
+                                      _f64(k_fine, batch * m ** d, "k_fine"),
+                                      _f64(k_sub, batch * 2 ** d * (m // 2) ** d, "k_sub")))
 
 
 def mlmc_assemble(ctx, dim, m, batch, k, T, tb, b):
-    n = batch * m * m
-    _check(ctx, _lib.mlmc_assemble(ctx, int(dim), int(m), int(batch), _f64(k, n, "k"),
-                                   _f64(T, 2 * n, "T"), _f64(tb, 2 * batch * m, "tb"),
+    d = int(dim)
+    n = batch * m ** d
+    _check(ctx, _lib.mlmc_assemble(ctx, d, int(m), int(batch), _f64(k, n, "k"),
+                                   _f64(T, d * n, "T"), _f64(tb, d * batch * m ** (d - 1), "tb"),
                                    _f64(b, n, "b")))
 
 
 def mlmc_solve(ctx, dim, m, batch, T, tb, b, p, opts, status, iters, relres):
-    n = batch * m * m
-    _check(ctx, _lib.mlmc_solve(ctx, int(dim), int(m), int(batch), _f64(T, 2 * n, "T"),
-                                _f64(tb, 2 * batch * m, "tb"), _f64(b, n, "b"),
+    d = int(dim)
+    n = batch * m ** d
+    _check(ctx, _lib.mlmc_solve(ctx, d, int(m), int(batch), _f64(T, d * n, "T"),
+                                _f64(tb, d * batch * m ** (d - 1), "tb"), _f64(b, n, "b"),
                                 _f64(p, n, "p"), ctypes.byref(opts),
                                 _i32(status, batch, "status"), _i32(iters, batch, "iters"),
                                 _f64(relres, batch, "relres")))
 
 
 def mlmc_qoi_outflow(ctx, dim, m, batch, k, p, q_out, q_in=None):
-    n = batch * m * m
-    _check(ctx, _lib.mlmc_qoi_outflow(ctx, int(dim), int(m), int(batch), _f64(k, n, "k"),
+    d = int(dim)
+    n = batch * m ** d
+    _check(ctx, _lib.mlmc_qoi_outflow(ctx, d, int(m), int(batch), _f64(k, n, "k"),
                                       _f64(p, n, "p"), _f64(q_out, batch, "q_out"),
                                       _f64(q_in, batch, "q_in")))
 
@@ -333,8 +338,8 @@ def mlmc_sample_field_ids(ctx, model, m, level, sample_ids, batch, k, k_coarse=N
     mm = model if isinstance(model, mlmc_model) else model_for_grid(model, m)
     _check(ctx, _lib.mlmc_sample_field_ids(ctx, ctypes.byref(mm), int(m), int(level),
                                            _u32(sample_ids, batch, "sample_ids"), int(batch),
-                                           _f64(k, batch * m * m, "k"),
-                                           _f64(k_coarse, batch * (m // 2) ** 2, "k_coarse")))
+                                           _f64(k, batch * m ** int(mm.dim), "k"),
+                                           _f64(k_coarse, batch * (m // 2) ** int(mm.dim), "k_coarse")))
 
 
 def mlmc_level_run_ids(ctx, model, level, m_fine, sample_ids, n, cgv, opts, sums=None,

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmlmc_darcy.so")
-SOURCES = ["field.hip", "fv.hip", "mg_pcg.hip", "mg_fused.hip", "api.hip", "serve.hip"]
+SOURCES = ["field.hip", "fv.hip", "mg_pcg.hip", "mg_fused.hip", "d3.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("MLMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
@@ -40,7 +40,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
         results = list(ex.map(_compile, SOURCES))
     objs = [o for o, _ in results]
     if verbose:

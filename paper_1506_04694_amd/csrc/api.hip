@@ -27,7 +27,7 @@ struct CeEntry {
   int n = 0;
   FftPlan plan{};
   double2* tw = nullptr;
-  double* sqT = nullptr;
+  double* sqT = nullptr;  // 2-D: sqrt(Lambda / n^2) transposed; 3-D: sqrt(Lambda / n^3)
 };
 
 struct Buffer {
@@ -49,7 +49,7 @@ struct mlmc_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   std::map<std::string, Buffer> ws;
-  std::map<std::tuple<int, int, double, double, int>, CeEntry> ce;
+  std::map<std::tuple<int, int, int, double, double, int>, CeEntry> ce;  // (dim, m, n, ...)
   void* host_pinned = nullptr;  // small pinned staging buffer
   std::string prof_name;
   double prof_scale = 1.0;  // share of the batch a launch works on (restart passes)
@@ -162,10 +162,10 @@ FftPlan make_plan(int n) {
 
 mlmc_status check_model(mlmc_ctx* ctx, const mlmc_model* mdl) {
   if (!mdl) return fail(ctx, MLMC_EINVAL, "model is NULL");
-  if (mdl->dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (mdl->dim != 2 && mdl->dim != 3) return fail(ctx, MLMC_EINVAL, "dim must be 2 or 3");
   const int k = mdl->interface_kind;
   if (k != MLMC_IFACE_HORIZONTAL && k != MLMC_IFACE_PIECEWISE_LINEAR &&
-      k != MLMC_IFACE_PAPER_TWO_LINES && k != MLMC_IFACE_NONE)
+      k != MLMC_IFACE_PAPER_TWO_LINES && k != MLMC_IFACE_TILTED_PLANE && k != MLMC_IFACE_NONE)
     return fail(ctx, MLMC_EINVAL, "unknown interface_kind");
   if (k == MLMC_IFACE_PIECEWISE_LINEAR && (mdl->n_nodes < 2 || mdl->n_nodes > 8))
     return fail(ctx, MLMC_EINVAL, "n_nodes must be in [2, 8]");
@@ -192,9 +192,9 @@ mlmc_status check_model(mlmc_ctx* ctx, const mlmc_model* mdl) {
 
 // Embedding eigenvalues for (m, n, sigma2, lambda, r); computed once, cached.
 // With `check_only`, a failing embedding is reported but not cached.
-mlmc_status ce_get(mlmc_ctx* ctx, int m, int n, double sigma2, double lambda, int r,
+mlmc_status ce_get(mlmc_ctx* ctx, int dim, int m, int n, double sigma2, double lambda, int r,
                    CeEntry** out) {
-  auto key = std::make_tuple(m, n, sigma2, lambda, r);
+  auto key = std::make_tuple(dim, m, n, sigma2, lambda, r);
   auto it = ctx->ce.find(key);
   if (it != ctx->ce.end()) {
     *out = &it->second;
@@ -202,22 +202,34 @@ mlmc_status ce_get(mlmc_ctx* ctx, int m, int n, double sigma2, double lambda, in
   }
   if (n < 2 * m || n > kFftMax || !five_smooth(n))
     return fail(ctx, MLMC_EINVAL, "n_ce must satisfy 2m <= n_ce <= 4096 with factors 2, 3, 5");
+  if (dim == 3 && n > kFftMax3)
+    return fail(ctx, MLMC_EINVAL, "3-D n_ce must be <= " + std::to_string(kFftMax3));
   CeEntry e;
   e.n = n;
   e.plan = make_plan(n);
+  const long long npts = dim == 3 ? (long long)n * n * n : (long long)n * n;
   HIP_TRY(hipMalloc(&e.tw, sizeof(double2) * n));
-  HIP_TRY(hipMalloc(&e.sqT, sizeof(double) * (size_t)n * n));
+  HIP_TRY(hipMalloc(&e.sqT, sizeof(double) * (size_t)npts));
   double2* c = nullptr;
-  TRY(ws(ctx, "ce_setup", (size_t)n * n, &c));
+  TRY(ws(ctx, "ce_setup", (size_t)npts, &c));
   hipStream_t st = ctx->stream;
   launch_ce_twiddles(st, n, e.tw);
-  launch_ce_first_row(st, n, m, sigma2, lambda, r, c);
-  launch_fft_lines(st, c, n, n, n, 1, e.tw, e.plan);   // along x1 (rows)
-  launch_fft_lines(st, c, n, n, 1, n, e.tw, e.plan);   // along x2 (columns)
+  if (dim == 3) {
+    // Lambda = FFT3(c): along x1 (lines of n), x2 (per x3 slab) and x3
+    launch_ce_first_row3(st, n, m, sigma2, lambda, r, c);
+    launch_fft_lines(st, c, n, n * n, n, 1, e.tw, e.plan);
+    for (int k3 = 0; k3 < n; ++k3)
+      launch_fft_lines(st, c + (long long)k3 * n * n, n, n, 1, n, e.tw, e.plan);
+    launch_fft_lines(st, c, n, n * n, 1, (long long)n * n, e.tw, e.plan);
+  } else {
+    launch_ce_first_row(st, n, m, sigma2, lambda, r, c);
+    launch_fft_lines(st, c, n, n, n, 1, e.tw, e.plan);   // along x1 (rows)
+    launch_fft_lines(st, c, n, n, 1, n, e.tw, e.plan);   // along x2 (columns)
+  }
   const int nb = 256;
   double* part = nullptr;
   TRY(ws(ctx, "ce_minmax", 2 * nb, &part));
-  launch_ce_minmax(st, c, (long long)n * n, part, nb);
+  launch_ce_minmax(st, c, npts, part, nb);
   CHECK_LAUNCH();
   std::vector<double> h(2 * nb);
   HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
@@ -236,7 +248,8 @@ mlmc_status ce_get(mlmc_ctx* ctx, int m, int n, double sigma2, double lambda, in
              hi > 0 ? lo / hi : 0.0);
     return fail(ctx, MLMC_EEMBED, buf);
   }
-  launch_ce_sqrt_transpose(st, c, n, e.sqT);
+  if (dim == 3) launch_ce_sqrt3(st, c, n, e.sqT);
+  else launch_ce_sqrt_transpose(st, c, n, e.sqT);
   CHECK_LAUNCH();
   auto res = ctx->ce.emplace(key, e);
   *out = &res.first->second;
@@ -341,10 +354,12 @@ mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m,
   TRY(check_model(ctx, model));
   if (m < 1) return fail(ctx, MLMC_EINVAL, "m must be positive");
   (void)hipSetDevice(ctx->device);
-  for (int n = 2 * m; n <= kFftMax; ++n) {
+  const int n_max = model->dim == 3 ? kFftMax3 : kFftMax;
+  for (int n = 2 * m; n <= n_max; ++n) {
     if (!five_smooth(n)) continue;
     CeEntry* e = nullptr;
-    mlmc_status s = ce_get(ctx, m, n, model->sigma2[0], model->lambda[0], model->norm_r, &e);
+    mlmc_status s =
+        ce_get(ctx, model->dim, m, n, model->sigma2[0], model->lambda[0], model->norm_r, &e);
     if (s == MLMC_OK) {
       *n_ce_out = n;
       ctx->err.clear();
@@ -352,7 +367,8 @@ mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m,
     }
     if (s != MLMC_EEMBED) return s;
   }
-  return fail(ctx, MLMC_EEMBED, "no valid circulant embedding with n_ce <= 4096");
+  return fail(ctx, MLMC_EEMBED,
+              "no valid circulant embedding with n_ce <= " + std::to_string(n_max));
 }
 
 static mlmc_status sample_field_impl(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,
@@ -371,13 +387,29 @@ static mlmc_status sample_field_impl(mlmc_ctx* ctx, const mlmc_model* model, int
   TRY(ws(ctx, "params", (size_t)batch * kParamStride, &params));
   launch_sample_params(st, *model, level, first_sample, ids, batch, params);
   if (model->field_kind == MLMC_FIELD_PIECEWISE_CONSTANT) {
-    launch_field_pc(st, *model, m, batch, params, k);
-    if (k_coarse) launch_field_pc(st, *model, m / 2, batch, params, k_coarse);
+    if (model->dim == 3) {
+      launch_field_pc3(st, *model, m, batch, params, k);
+      if (k_coarse) launch_field_pc3(st, *model, m / 2, batch, params, k_coarse);
+    } else {
+      launch_field_pc(st, *model, m, batch, params, k);
+      if (k_coarse) launch_field_pc(st, *model, m / 2, batch, params, k_coarse);
+    }
     CHECK_LAUNCH();
     return MLMC_OK;
   }
   CeEntry* e = nullptr;
-  TRY(ce_get(ctx, m, model->n_ce, model->sigma2[0], model->lambda[0], model->norm_r, &e));
+  TRY(ce_get(ctx, model->dim, m, model->n_ce, model->sigma2[0], model->lambda[0], model->norm_r,
+             &e));
+  if (model->dim == 3) {
+    const int nn = e->n;
+    double2 *u1 = nullptr, *u2 = nullptr;
+    TRY(ws(ctx, "ce3_u1", (size_t)batch * nn * nn * m, &u1));
+    TRY(ws(ctx, "ce3_u2", (size_t)batch * nn * m * m, &u2));
+    launch_ce3(st, *model, level, first_sample, ids, batch, m, e->sqT, e->tw, e->plan, params, u1,
+               u2, k, k_coarse);
+    CHECK_LAUNCH();
+    return MLMC_OK;
+  }
   double2* uT = nullptr;
   TRY(ws(ctx, "ce_uT", (size_t)batch * m * e->n, &uT));
   const double cells = (double)batch * m * m;
@@ -407,12 +439,13 @@ mlmc_status mlmc_sample_field_ids(mlmc_ctx* ctx, const mlmc_model* model, int m,
 mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch, const double* k_fine,
                              double* k_sub) {
   if (!ctx) return MLMC_EINVAL;
-  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (dim != 2 && dim != 3) return fail(ctx, MLMC_EINVAL, "dim must be 2 or 3");
   if (m < 2 || (m % 2) || batch < 0 || !k_fine || !k_sub)
     return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_cgv_extract");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
-  launch_cgv_extract(ctx->stream, m, batch, k_fine, k_sub);
+  if (dim == 3) launch_cgv_extract3(ctx->stream, m, batch, k_fine, k_sub);
+  else launch_cgv_extract(ctx->stream, m, batch, k_fine, k_sub);
   CHECK_LAUNCH();
   return MLMC_OK;
 }
@@ -420,11 +453,16 @@ mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch, const dou
 mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double* k, double* T,
                           double* tb, double* b) {
   if (!ctx) return MLMC_EINVAL;
-  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (dim != 2 && dim != 3) return fail(ctx, MLMC_EINVAL, "dim must be 2 or 3");
   if (m < 1 || batch < 0 || !k || !T || !tb || !b)
     return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_assemble");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
+  if (dim == 3) {
+    launch_assemble3(ctx->stream, m, batch, k, T, tb, b);
+    CHECK_LAUNCH();
+    return MLMC_OK;
+  }
   timed(ctx, "k_assemble", (double)batch * m * m * 40.0,
         [&] { launch_assemble(ctx->stream, m, batch, k, T, tb, b); });
   CHECK_LAUNCH();
@@ -434,12 +472,146 @@ mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double
 mlmc_status mlmc_qoi_outflow(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
                              const double* p, double* q_out, double* q_in) {
   if (!ctx) return MLMC_EINVAL;
-  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (dim != 2 && dim != 3) return fail(ctx, MLMC_EINVAL, "dim must be 2 or 3");
   if (m < 1 || batch < 0 || !k || !p || !q_out)
     return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_qoi_outflow");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
-  launch_qoi(ctx->stream, m, batch, k, p, q_out, q_in);
+  if (dim == 3) launch_qoi3(ctx->stream, m, batch, k, p, q_out, q_in);
+  else launch_qoi(ctx->stream, m, batch, k, p, q_out, q_in);
+  CHECK_LAUNCH();
+  return MLMC_OK;
+}
+
+// 3-D solve: PCG with the one-launch-per-sweep multigrid cycle (V, or W on the
+// opts->gamma_levels finest levels), FP64; same per-sample scalars, convergence
+// checks and W breakdown restart as in 2-D.
+static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T, const double* tb,
+                               const double* b, double* p, const mlmc_solver_opts* opts,
+                               int32_t* status, int32_t* iters, double* relres) {
+  hipStream_t st = ctx->stream;
+  if (opts->precision != MLMC_PREC_FP64)
+    return fail(ctx, MLMC_EINVAL, "the 3-D solver runs in FP64 only");
+  std::vector<int> ms{m};
+  while (ms.back() % 2 == 0 && ms.back() > opts->coarse_max) ms.push_back(ms.back() / 2);
+  const int L = (int)ms.size() - 1;
+  if (ms[L] > 4)
+    return fail(ctx, MLMC_EINVAL, "coarsest 3-D grid " + std::to_string(ms[L]) +
+                                      " > 4: m must be c * 2^k with c <= 4");
+  const long long n = (long long)m * m * m;
+  const int bps = blocks_per_sample(n);
+  double *r, *z, *pv, *q, *partial;
+  TRY(ws(ctx, "s3_r", batch * n, &r));
+  TRY(ws(ctx, "s3_z", batch * n, &z));
+  TRY(ws(ctx, "s3_p", batch * n, &pv));
+  TRY(ws(ctx, "s3_q", batch * n, &q));
+  TRY(ws(ctx, "s3_partial", (size_t)batch * bps, &partial));
+  std::vector<const double*> Tl(L + 1), tbl(L + 1);
+  std::vector<double*> zl(L + 1), rl(L + 1);
+  Tl[0] = T;
+  tbl[0] = tb;
+  zl[0] = z;
+  rl[0] = r;
+  for (int l = 1; l <= L; ++l) {
+    const long long nl = (long long)ms[l] * ms[l] * ms[l];
+    double *Tc, *tbc;
+    TRY(ws(ctx, lv("s3_T", l), batch * 3 * nl, &Tc));
+    TRY(ws(ctx, lv("s3_tb", l), (size_t)batch * 3 * ms[l] * ms[l], &tbc));
+    TRY(ws(ctx, lv("s3_zl", l), batch * nl, &zl[l]));
+    TRY(ws(ctx, lv("s3_rl", l), batch * nl, &rl[l]));
+    launch_coarsen3(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tc, tbc);
+    Tl[l] = Tc;
+    tbl[l] = tbc;
+  }
+  const int nc = ms[L] * ms[L] * ms[L];
+  double* Ainv = nullptr;
+  TRY(ws(ctx, "s3_ainv", (size_t)batch * nc * nc, &Ainv));
+  launch_dense_factor3(st, ms[L], batch, Tl[L], tbl[L], Ainv);
+  SolverState S;
+  TRY(ws(ctx, "s3_r0", batch, &S.r0sq));
+  TRY(ws(ctx, "s3_rho", batch, &S.rho));
+  TRY(ws(ctx, "s3_alpha", batch, &S.alpha));
+  TRY(ws(ctx, "s3_beta", batch, &S.beta));
+  TRY(ws(ctx, "s3_active", batch, &S.active));
+  TRY(ws(ctx, "s3_count", 1, &S.count));
+  CHECK_LAUNCH();
+  const int nu = opts->nu1;
+  const double omega = opts->omega;
+  int cur_gamma = opts->gamma;
+  auto visits = [&](int l) {
+    return (opts->gamma_levels == 0 || l < opts->gamma_levels) ? cur_gamma : 1;
+  };
+  std::function<void(int)> cycle = [&](int l) {
+    if (l == L) {
+      launch_dense_apply_n(st, nc, batch, Ainv, rl[L], zl[L], S.active);
+      return;
+    }
+    const int ml = ms[l];
+    for (int it = 0; it < nu; ++it) {
+      launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, it == 0);
+      launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+    }
+    for (int visit = 0; visit < visits(l); ++visit) {
+      if (visit > 0)
+        for (int it = 0; it < nu; ++it) {
+          launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
+          launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+        }
+      launch_resid_restrict3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], rl[l + 1], S.active);
+      cycle(l + 1);
+      launch_prolong3(st, ml, batch, zl[l + 1], zl[l], omega, S.active);
+      for (int it = 0; it < nu; ++it) {
+        launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+        launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
+      }
+    }
+  };
+  auto precond = [&]() {
+    cycle(0);
+    launch_dot(st, (int)n, batch, r, z, partial, bps, S.active);
+  };
+  int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
+  const int check = opts->check_every > 0 ? opts->check_every : 1;
+  auto pcg_pass = [&](bool restart) -> mlmc_status {
+    launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
+    launch_sc_init(st, batch, partial, bps, S, status, iters, relres, restart ? 1 : 0);
+    precond();
+    launch_sc_rho(st, batch, partial, bps, S, status, 1, nullptr, 0);
+    launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
+    CHECK_LAUNCH();
+    for (int it = 1;; ++it) {
+      launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
+      launch_sc_alpha(st, batch, partial, bps, S, status);
+      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active, nullptr,
+                      nullptr);
+      launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
+      CHECK_LAUNCH();
+      if (it % check == 0 || it >= opts->maxit) {
+        HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (*hcount == 0) break;
+      }
+      precond();
+      launch_sc_rho(st, batch, partial, bps, S, status, 0, nullptr, 0);
+      launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
+    }
+    return MLMC_OK;
+  };
+  TRY(pcg_pass(false));
+  if (cur_gamma == 2) {  // V-cycle restart where the W preconditioner broke down
+    int32_t* carried;
+    TRY(ws(ctx, "s3_carried", batch, &carried));
+    launch_sc_restart(st, batch, S, status, iters, carried);
+    HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*hcount > 0) {
+      cur_gamma = 1;
+      TRY(pcg_pass(true));
+      launch_iters_add(st, batch, iters, carried);
+    }
+  }
+  launch_true_residual3(st, m, batch, T, tb, b, p, partial, bps);
+  launch_sc_final(st, batch, partial, bps, S, relres);
   CHECK_LAUNCH();
   return MLMC_OK;
 }
@@ -449,12 +621,13 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
                        const mlmc_solver_opts* opts, int32_t* status, int32_t* iters,
                        double* relres) {
   if (!ctx) return MLMC_EINVAL;
-  if (dim != 2) return fail(ctx, MLMC_EINVAL, "only dim = 2 is implemented");
+  if (dim != 2 && dim != 3) return fail(ctx, MLMC_EINVAL, "dim must be 2 or 3");
   TRY(check_opts(ctx, opts));
   if (m < 1 || batch < 0 || !T || !tb || !b || !p || !status || !iters || !relres)
     return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_solve");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
+  if (dim == 3) return solve3_impl(ctx, m, batch, T, tb, b, p, opts, status, iters, relres);
   hipStream_t st = ctx->stream;
 
   // grid hierarchy: halve while even and above coarse_max
@@ -789,15 +962,18 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
   if (n == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
   hipStream_t st = ctx->stream;
-  const int m = m_fine, mc = m / 2;
-  const long long nf = (long long)m * m, ncl = (long long)mc * mc;
-  const int ncomp = level == 0 ? 0 : (cgv ? 4 : 1);
+  const int m = m_fine, mc = m / 2, d = model->dim;
+  const long long nf = d == 3 ? (long long)m * m * m : (long long)m * m;
+  const long long ncl = d == 3 ? (long long)mc * mc * mc : (long long)mc * mc;
+  const long long fface = d == 3 ? (long long)m * m : m;     // boundary faces per side
+  const long long cface = d == 3 ? (long long)mc * mc : mc;
+  const int ncomp = level == 0 ? 0 : (cgv ? (1 << d) : 1);
 
   double *k, *T, *tb, *b, *p, *qf, *yv, *relres, *out;
   int32_t *stf, *itf, *failed;
   TRY(ws(ctx, "lr_k", n * nf, &k));
-  TRY(ws(ctx, "lr_T", n * 2 * nf, &T));
-  TRY(ws(ctx, "lr_tb", (size_t)n * 2 * m, &tb));
+  TRY(ws(ctx, "lr_T", n * d * nf, &T));
+  TRY(ws(ctx, "lr_tb", (size_t)n * d * fface, &tb));
   TRY(ws(ctx, "lr_b", n * nf, &b));
   TRY(ws(ctx, "lr_p", n * nf, &p));
   TRY(ws(ctx, "lr_qf", n, &qf));
@@ -812,28 +988,28 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
   if (ncomp > 0) TRY(ws(ctx, "lr_kc", (size_t)n * ncomp * ncl, &kc));
   TRY(sample_field_impl(ctx, model, m, level, first_sample, ids, n, k,
                         (ncomp == 1) ? kc : nullptr));
-  if (ncomp == 4) TRY(mlmc_cgv_extract(ctx, 2, m, n, k, kc));
+  if (ncomp > 1) TRY(mlmc_cgv_extract(ctx, d, m, n, k, kc));
 
-  TRY(mlmc_assemble(ctx, 2, m, n, k, T, tb, b));
-  TRY(mlmc_solve(ctx, 2, m, n, T, tb, b, p, opts, stf, itf, relres));
-  TRY(mlmc_qoi_outflow(ctx, 2, m, n, k, p, qf, nullptr));
+  TRY(mlmc_assemble(ctx, d, m, n, k, T, tb, b));
+  TRY(mlmc_solve(ctx, d, m, n, T, tb, b, p, opts, stf, itf, relres));
+  TRY(mlmc_qoi_outflow(ctx, d, m, n, k, p, qf, nullptr));
 
   double* qcv = nullptr;
   int32_t *stc = nullptr, *itc = nullptr;
   if (ncomp > 0) {
     const int nb = n * ncomp;
     double *Tc, *tbc, *bc, *pc, *qcomp;
-    TRY(ws(ctx, "lr_Tc", (size_t)nb * 2 * ncl, &Tc));
-    TRY(ws(ctx, "lr_tbc", (size_t)nb * 2 * mc, &tbc));
+    TRY(ws(ctx, "lr_Tc", (size_t)nb * d * ncl, &Tc));
+    TRY(ws(ctx, "lr_tbc", (size_t)nb * d * cface, &tbc));
     TRY(ws(ctx, "lr_bc", (size_t)nb * ncl, &bc));
     TRY(ws(ctx, "lr_pc", (size_t)nb * ncl, &pc));
     TRY(ws(ctx, "lr_qcomp", nb, &qcomp));
     TRY(ws(ctx, "lr_qc", n, &qcv));
     TRY(ws(ctx, "lr_stc", nb, &stc));
     TRY(ws(ctx, "lr_itc", nb, &itc));
-    TRY(mlmc_assemble(ctx, 2, mc, nb, kc, Tc, tbc, bc));
-    TRY(mlmc_solve(ctx, 2, mc, nb, Tc, tbc, bc, pc, opts, stc, itc, relres));
-    TRY(mlmc_qoi_outflow(ctx, 2, mc, nb, kc, pc, qcomp, nullptr));
+    TRY(mlmc_assemble(ctx, d, mc, nb, kc, Tc, tbc, bc));
+    TRY(mlmc_solve(ctx, d, mc, nb, Tc, tbc, bc, pc, opts, stc, itc, relres));
+    TRY(mlmc_qoi_outflow(ctx, d, mc, nb, kc, pc, qcomp, nullptr));
     launch_cgv_average(st, n, ncomp, qcomp, qcv);
   }
   launch_y_and_fail(st, n, qf, qcv, stf, stc, ncomp, yv, failed);
@@ -894,6 +1070,15 @@ mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels
       return fail(ctx, MLMC_EINVAL, "bad level size or sample count");
   }
   (void)hipSetDevice(ctx->device);
+  if (model->dim == 3) {  // 3-D: one level run after another
+    for (int l = 0; l < n_levels; ++l) {
+      mlmc_model ml = *model;
+      if (n_ce) ml.n_ce = n_ce[l];
+      TRY(level_run_impl(ctx, &ml, l, m_fine[l], first_sample[l], nullptr, n[l], cgv, &opts[l],
+                         &sums[l], nullptr, nullptr, nullptr, nullptr, nullptr));
+    }
+    return MLMC_OK;
+  }
   hipStream_t st = ctx->stream;
   const int ncomp = cgv ? 4 : 1;
 

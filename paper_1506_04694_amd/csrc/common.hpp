@@ -90,8 +90,20 @@ __device__ __forceinline__ int layer_of(int kind, int n_nodes, const double* prm
     const double upper = prm[0] + x * (prm[1] - prm[0]);
     const double lower = prm[2] + x * (prm[3] - prm[2]);
     return y < lower ? 0 : (y < upper ? 1 : 2);
+  } else if (kind == MLMC_IFACE_TILTED_PLANE) {
+    return y < prm[0] + (prm[1] - prm[0]) * x ? 0 : 1;  // the plane's trace at x3 = 1/2
   }
   return 0;
+}
+
+// 3-D: the tilted plane x2 = a + (b - a) x1 + c (x3 - 1/2); the 2-D interfaces
+// are extruded along x3.
+__device__ __forceinline__ int layer_of3(int kind, int n_nodes, const double* prm, double x,
+                                         double y, double z) {
+#pragma clang fp contract(off)
+  if (kind == MLMC_IFACE_TILTED_PLANE)
+    return y < prm[0] + (prm[1] - prm[0]) * x + prm[2] * (z - 0.5) ? 0 : 1;
+  return layer_of(kind, n_nodes, prm, x, y);
 }
 
 __device__ __forceinline__ double centre(int i, int m) {

@@ -1,0 +1,635 @@
+// The 3-D path: sample, assemble, multigrid-preconditioned CG and QoI on
+// m x m x m grids (Sections 2, 3.1, 3.4 and 3.5 with d = 3).
+//
+// Layout per sample s (n = m^3 cells, c = (l m + j) m + i, x1 fastest):
+//   k[s][l][j][i];
+//   T[s][0][c] face x1 = (i+1)h (i = m-1: the Dirichlet face at x1 = 1),
+//   T[s][1][c] face x2 = (j+1)h, T[s][2][c] face x3 = (l+1)h (0 on the top);
+//   tb[s][0][l m + j] face x1 = 0 of cell (0, j, l) (Dirichlet, p = 1),
+//   tb[s][1][l m + i] face x2 = 0, tb[s][2][j m + i] face x3 = 0 (no flow: 0);
+//   (A x)_c = (sum of the six face T) x_c - sum over interior faces T x_nb.
+// A face between cells P and Q has T = h^(d-2) 2 k_P k_Q / (k_P + k_Q) = h
+// times the harmonic mean; a Dirichlet face T = 2 k_P h (half-cell distance).
+//
+// The multigrid is the same as in 2-D with 2 x 2 x 2 aggregation (the
+// Galerkin coarse face is the sum of the four fine faces it covers), one
+// launch per colour sweep, restriction and prolongation, and the dense
+// inverse on the coarsest grid (<= 4^3 unknowns).
+#include <cfloat>
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace mlmc {
+
+struct Faces3 {
+  double te, tw, tn, ts, tu, td;
+};
+
+__device__ __forceinline__ Faces3 load_faces3(const double* __restrict__ Ts,
+                                              const double* __restrict__ tbs, int m, int i, int j,
+                                              int l) {
+  const long long n = (long long)m * m * m;
+  const int mm = m * m;
+  const long long c = ((long long)l * m + j) * m + i;
+  Faces3 f;
+  f.te = Ts[c];
+  f.tw = i > 0 ? Ts[c - 1] : tbs[l * m + j];
+  f.tn = Ts[n + c];
+  f.ts = j > 0 ? Ts[n + c - m] : tbs[mm + l * m + i];
+  f.tu = Ts[2 * n + c];
+  f.td = l > 0 ? Ts[2 * n + c - mm] : tbs[2 * mm + j * m + i];
+  return f;
+}
+
+__device__ __forceinline__ double nsum3(const double* __restrict__ x, int m, int i, int j, int l,
+                                        const Faces3& f) {
+  const long long c = ((long long)l * m + j) * m + i;
+  const long long mm = (long long)m * m;
+  double o = 0.0;
+  if (i < m - 1) o += f.te * x[c + 1];
+  if (i > 0) o += f.tw * x[c - 1];
+  if (j < m - 1) o += f.tn * x[c + m];
+  if (j > 0) o += f.ts * x[c - m];
+  if (l < m - 1) o += f.tu * x[c + mm];
+  if (l > 0) o += f.td * x[c - mm];
+  return o;
+}
+
+__device__ __forceinline__ double diag3(const Faces3& f) {
+  return f.te + f.tw + f.tn + f.ts + f.tu + f.td;
+}
+
+__device__ __forceinline__ void cell_of(long long rem, int m, int& i, int& j, int& l) {
+  l = (int)(rem / ((long long)m * m));
+  const int r2 = (int)(rem - (long long)l * m * m);
+  j = r2 / m;
+  i = r2 - j * m;
+}
+
+// ------------------------------------------------------------------ assembly
+__global__ void k_assemble3(int m, long long total, const double* __restrict__ k,
+                            double* __restrict__ T, double* __restrict__ tb,
+                            double* __restrict__ b) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long n = (long long)m * m * m;
+  const int mm = m * m;
+  const long long s = g / n;
+  const long long c = g - s * n;
+  int i, j, l;
+  cell_of(c, m, i, j, l);
+  const double h = 1.0 / (double)m;
+  const double* ks = k + s * n;
+  const double kc = ks[c];
+  double* Ts = T + s * 3 * n;
+  Ts[c] = i < m - 1 ? h * (2.0 * kc * ks[c + 1] / (kc + ks[c + 1])) : 2.0 * kc * h;
+  Ts[n + c] = j < m - 1 ? h * (2.0 * kc * ks[c + m] / (kc + ks[c + m])) : 0.0;
+  Ts[2 * n + c] = l < m - 1 ? h * (2.0 * kc * ks[c + mm] / (kc + ks[c + mm])) : 0.0;
+  double* tbs = tb + s * 3 * mm;
+  const double tw = 2.0 * kc * h;
+  if (i == 0) tbs[l * m + j] = tw;
+  if (j == 0) tbs[mm + l * m + i] = 0.0;
+  if (l == 0) tbs[2 * mm + j * m + i] = 0.0;
+  b[g] = i == 0 ? tw : 0.0;
+}
+
+void launch_assemble3(hipStream_t st, int m, int batch, const double* k, double* T, double* tb,
+                      double* b) {
+  const long long total = (long long)batch * m * m * m;
+  hipLaunchKernelGGL(k_assemble3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, k, T,
+                     tb, b);
+}
+
+// ------------------------------------------------------------------ QoI
+// Q_out = sum over the x1 = 1 faces of 2 k h p, Q_in = sum over x1 = 0 of
+// 2 k h (1 - p); one wave per sample, fixed-order sums.
+__global__ void k_qoi3(int m, int batch, const double* __restrict__ k, const double* __restrict__ p,
+                       double* __restrict__ qout, double* __restrict__ qin) {
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (wave >= batch) return;
+  const long long n = (long long)m * m * m;
+  const long long base = wave * n;
+  const double h = 1.0 / (double)m;
+  double so = 0.0, si = 0.0;
+  for (int q = lane; q < m * m; q += kWave) {
+    const long long row = base + (long long)q * m;  // q = l m + j
+    so += 2.0 * k[row + m - 1] * h * p[row + m - 1];
+    si += 2.0 * k[row] * h * (1.0 - p[row]);
+  }
+  so = wave_sum(so);
+  si = wave_sum(si);
+  if (lane == 0) {
+    qout[wave] = so;
+    if (qin) qin[wave] = si;
+  }
+}
+
+void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double* p, double* qout,
+                 double* qin) {
+  const long long threads = (long long)batch * kWave;
+  hipLaunchKernelGGL(k_qoi3, dim3(blocks_for(threads)), dim3(kBlock), 0, st, m, batch, k, p, qout,
+                     qin);
+}
+
+// ------------------------------------------------------------------ hierarchy
+__global__ void k_coarsen3(int m, long long total, const double* __restrict__ T,
+                           const double* __restrict__ tb, double* __restrict__ Tc,
+                           double* __restrict__ tbc) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int mc = m / 2;
+  const long long nc = (long long)mc * mc * mc, n = (long long)m * m * m;
+  const long long s = g / nc;
+  const long long rem = g - s * nc;
+  int I, J, L;
+  cell_of(rem, mc, I, J, L);
+  const double* Ts = T + s * 3 * n;
+  double* Tcs = Tc + s * 3 * nc;
+  const int i = 2 * I, j = 2 * J, l = 2 * L;
+  auto at = [&](int a, int bb, int cc) { return ((long long)cc * m + bb) * m + a; };
+  Tcs[rem] = Ts[at(i + 1, j, l)] + Ts[at(i + 1, j + 1, l)] + Ts[at(i + 1, j, l + 1)] +
+             Ts[at(i + 1, j + 1, l + 1)];
+  Tcs[nc + rem] = Ts[n + at(i, j + 1, l)] + Ts[n + at(i + 1, j + 1, l)] +
+                  Ts[n + at(i, j + 1, l + 1)] + Ts[n + at(i + 1, j + 1, l + 1)];
+  Tcs[2 * nc + rem] = Ts[2 * n + at(i, j, l + 1)] + Ts[2 * n + at(i + 1, j, l + 1)] +
+                      Ts[2 * n + at(i, j + 1, l + 1)] + Ts[2 * n + at(i + 1, j + 1, l + 1)];
+  const int mm = m * m, mmc = mc * mc;
+  const double* tbs = tb + s * 3 * mm;
+  double* tbcs = tbc + s * 3 * mmc;
+  if (I == 0)
+    tbcs[L * mc + J] = tbs[l * m + j] + tbs[l * m + j + 1] + tbs[(l + 1) * m + j] +
+                       tbs[(l + 1) * m + j + 1];
+  if (J == 0)
+    tbcs[mmc + L * mc + I] = tbs[mm + l * m + i] + tbs[mm + l * m + i + 1] +
+                             tbs[mm + (l + 1) * m + i] + tbs[mm + (l + 1) * m + i + 1];
+  if (L == 0)
+    tbcs[2 * mmc + J * mc + I] = tbs[2 * mm + j * m + i] + tbs[2 * mm + j * m + i + 1] +
+                                 tbs[2 * mm + (j + 1) * m + i] + tbs[2 * mm + (j + 1) * m + i + 1];
+}
+
+void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                     double* Tc, double* tbc) {
+  const long long total = (long long)batch * (m / 2) * (m / 2) * (m / 2);
+  hipLaunchKernelGGL(k_coarsen3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T, tb,
+                     Tc, tbc);
+}
+
+// ------------------------------------------------------------------ smoother
+// One thread per cell of the colour ((i + j + l) % 2 == color); m even.
+__global__ void k_rbgs3(int m, long long total, const double* __restrict__ T,
+                        const double* __restrict__ tb, double* __restrict__ z,
+                        const double* __restrict__ r, const int32_t* __restrict__ active,
+                        int color, int zero_init) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int half = m / 2;
+  const long long per = (long long)m * m * half;
+  const long long s = g / per;
+  if (!active[s]) return;
+  const long long rem = g - s * per;
+  const int row = (int)(rem / half);  // row = l m + j
+  const int l = row / m, j = row - l * m;
+  const int i = 2 * (int)(rem - (long long)row * half) + ((j + l + color) & 1);
+  const long long n = (long long)m * m * m;
+  const Faces3 f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
+  double* zs = z + s * n;
+  const long long c = ((long long)l * m + j) * m + i;
+  const double rv = r[s * n + c];
+  zs[c] = zero_init ? rv / diag3(f) : (rv + nsum3(zs, m, i, j, l, f)) / diag3(f);
+}
+
+void launch_rbgs3(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
+                  const double* r, const int32_t* active, int color, int zero_init) {
+  const long long total = (long long)batch * m * m * (m / 2);
+  hipLaunchKernelGGL(k_rbgs3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T, tb, z,
+                     r, active, color, zero_init);
+}
+
+// rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z)
+__global__ void k_resid_restrict3(int m, long long total, const double* __restrict__ T,
+                                  const double* __restrict__ tb, const double* __restrict__ z,
+                                  const double* __restrict__ r, double* __restrict__ rc,
+                                  const int32_t* __restrict__ active) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int mc = m / 2;
+  const long long nc = (long long)mc * mc * mc, n = (long long)m * m * m;
+  const long long s = g / nc;
+  if (!active[s]) return;
+  int I, J, L;
+  cell_of(g - s * nc, mc, I, J, L);
+  const double* Ts = T + s * 3 * n;
+  const double* tbs = tb + s * 3 * m * m;
+  const double* zs = z + s * n;
+  const double* rs = r + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = 2 * I + a, j = 2 * J + bb, l = 2 * L + cc;
+        const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
+        const long long c = ((long long)l * m + j) * m + i;
+        acc += rs[c] - (diag3(f) * zs[c] - nsum3(zs, m, i, j, l, f));
+      }
+  rc[g] = acc;
+}
+
+void launch_resid_restrict3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                            const double* z, const double* r, double* rc,
+                            const int32_t* active) {
+  const long long total = (long long)batch * (m / 2) * (m / 2) * (m / 2);
+  hipLaunchKernelGGL(k_resid_restrict3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T,
+                     tb, z, r, rc, active);
+}
+
+__global__ void k_prolong3(int m, long long total, const double* __restrict__ zc,
+                           double* __restrict__ z, double omega,
+                           const int32_t* __restrict__ active) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long n = (long long)m * m * m;
+  const long long s = g / n;
+  if (!active[s]) return;
+  int i, j, l;
+  cell_of(g - s * n, m, i, j, l);
+  const int mc = m / 2;
+  z[g] += omega * zc[s * (long long)mc * mc * mc + ((long long)(l / 2) * mc + j / 2) * mc + i / 2];
+}
+
+void launch_prolong3(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
+                     const int32_t* active) {
+  const long long total = (long long)batch * m * m * m;
+  hipLaunchKernelGGL(k_prolong3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, zc, z,
+                     omega, active);
+}
+
+// ------------------------------------------------------------------ coarsest grid
+// Explicit inverse of each sample's coarsest matrix (n = m^3 <= 64) by
+// Gauss-Jordan elimination without pivoting (SPD), as in 2-D.
+__global__ void __launch_bounds__(64)
+k_dense_factor3(int m, int batch, const double* __restrict__ T, const double* __restrict__ tb,
+                double* __restrict__ Ainv) {
+  __shared__ double A[64 * 64];
+  __shared__ double col[64];
+  const int s = blockIdx.x;
+  if (s >= batch) return;
+  const int n = m * m * m, mm = m * m;
+  const double* Ts = T + (long long)s * 3 * n;
+  const double* tbs = tb + (long long)s * 3 * mm;
+  for (int q = threadIdx.x; q < n * n; q += 64) A[q] = 0.0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += 64) {
+    int i, j, l;
+    cell_of(c, m, i, j, l);
+    const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
+    A[c * n + c] = diag3(f);
+    if (i < m - 1) A[c * n + c + 1] = A[(c + 1) * n + c] = -f.te;
+    if (j < m - 1) A[c * n + c + m] = A[(c + m) * n + c] = -f.tn;
+    if (l < m - 1) A[c * n + c + mm] = A[(c + mm) * n + c] = -f.tu;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    for (int i = threadIdx.x; i < n; i += 64) col[i] = A[i * n + k];
+    __syncthreads();
+    const double piv = col[k];
+    for (int j = threadIdx.x; j < n; j += 64) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) / piv;
+    __syncthreads();
+    for (int q = threadIdx.x; q < n * n; q += 64) {
+      const int i = q / n, j = q - i * n;
+      if (i != k) A[q] = (j == k ? 0.0 : A[q]) - col[i] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  double* X = Ainv + (long long)s * n * n;
+  for (int q = threadIdx.x; q < n * n; q += 64) X[q] = A[q];
+}
+
+void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                          double* Ainv) {
+  hipLaunchKernelGGL(k_dense_factor3, dim3(batch), dim3(64), 0, st, m, batch, T, tb, Ainv);
+}
+
+// ------------------------------------------------------------------ PCG stencil kernels
+// Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c.
+__global__ void __launch_bounds__(kBlock)
+k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
+            const double* __restrict__ p, double* __restrict__ q, double* __restrict__ partial,
+            int bps, const int32_t* __restrict__ active) {
+  __shared__ double sh[kBlock / kWave];
+  const long long s = blockIdx.x / bps;
+  const int blk = blockIdx.x - (int)(s * bps);
+  if (!active[s]) return;
+  const long long n = (long long)m * m * m;
+  const double* Ts = T + s * 3 * n;
+  const double* tbs = tb + s * 3 * m * m;
+  const double* ps = p + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const long long cell = (long long)blk * kCellsPerBlock + threadIdx.x + c * kBlock;
+    if (cell < n) {
+      int i, j, l;
+      cell_of(cell, m, i, j, l);
+      const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
+      const double v = diag3(f) * ps[cell] - nsum3(ps, m, i, j, l, f);
+      q[s * n + cell] = v;
+      acc += ps[cell] * v;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                      const double* p, double* q, double* partial, int bps,
+                      const int32_t* active) {
+  hipLaunchKernelGGL(k_spmv3_dot, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q, partial,
+                     bps, active);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_true_residual3(int m, const double* __restrict__ T, const double* __restrict__ tb,
+                 const double* __restrict__ b, const double* __restrict__ x,
+                 double* __restrict__ partial, int bps) {
+  __shared__ double sh[kBlock / kWave];
+  const long long s = blockIdx.x / bps;
+  const int blk = blockIdx.x - (int)(s * bps);
+  const long long n = (long long)m * m * m;
+  const double* Ts = T + s * 3 * n;
+  const double* tbs = tb + s * 3 * m * m;
+  const double* xs = x + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const long long cell = (long long)blk * kCellsPerBlock + threadIdx.x + c * kBlock;
+    if (cell < n) {
+      int i, j, l;
+      cell_of(cell, m, i, j, l);
+      const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
+      const double rv = b[s * n + cell] - (diag3(f) * xs[cell] - nsum3(xs, m, i, j, l, f));
+      acc += rv * rv;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_true_residual3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                           const double* b, const double* x, double* partial, int bps) {
+  hipLaunchKernelGGL(k_true_residual3, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, b, x,
+                     partial, bps);
+}
+
+// ------------------------------------------------------------------ fields
+// Example 1 (piecewise constant layers) on the m^3 centres.
+__global__ void k_field_pc3(int kind, int n_nodes, int m, long long total,
+                            const double* __restrict__ params, double* __restrict__ k) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long n = (long long)m * m * m;
+  const long long s = g / n;
+  int i, j, l;
+  cell_of(g - s * n, m, i, j, l);
+  const double* prm = params + s * kParamStride;
+  const int ly = layer_of3(kind, n_nodes, prm, centre(i, m), centre(j, m), centre(l, m));
+  k[g] = exp(prm[8 + ly]);
+}
+
+void launch_field_pc3(hipStream_t st, const mlmc_model& mdl, int m, int batch,
+                      const double* params, double* k) {
+  const long long total = (long long)batch * m * m * m;
+  hipLaunchKernelGGL(k_field_pc3, dim3(blocks_for(total)), dim3(kBlock), 0, st,
+                     mdl.interface_kind, mdl.n_nodes, m, total, params, k);
+}
+
+// ---- circulant embedding in 3-D: c, Lambda = FFT3(c), sqrt(Lambda / n^3)
+// c[a3][a2][a1] = sigma2 exp(-||(d1, d2, d3)||_r / lambda), d = min(a, n - a) h  (eq. (2.3))
+__global__ void k_ce_first_row3(int n, int m, double sigma2, double lambda, int norm_r,
+                                double2* __restrict__ c) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nn = (long long)n * n;
+  if (g >= nn * n) return;
+  const int a3 = (int)(g / nn);
+  const int r2 = (int)(g - (long long)a3 * nn);
+  const int a2 = r2 / n, a1 = r2 - a2 * n;
+  const double h = 1.0 / (double)m;
+  const double d1 = (double)min(a1, n - a1) * h;
+  const double d2 = (double)min(a2, n - a2) * h;
+  const double d3 = (double)min(a3, n - a3) * h;
+  const double dist = norm_r == 1 ? d1 + d2 + d3 : sqrt(d1 * d1 + d2 * d2 + d3 * d3);
+  c[g] = make_double2(sigma2 * exp(-dist / lambda), 0.0);
+}
+
+void launch_ce_first_row3(hipStream_t st, int n, int m, double sigma2, double lambda, int norm_r,
+                          double2* c) {
+  const long long total = (long long)n * n * n;
+  hipLaunchKernelGGL(k_ce_first_row3, dim3(blocks_for(total)), dim3(kBlock), 0, st, n, m, sigma2,
+                     lambda, norm_r, c);
+}
+
+__global__ void k_ce_sqrt3(const double2* __restrict__ lam, long long count, double n3,
+                           double* __restrict__ sq) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= count) return;
+  sq[g] = sqrt(fmax(lam[g].x, 0.0) / n3);
+}
+
+void launch_ce_sqrt3(hipStream_t st, const double2* lam, int n, double* sq) {
+  const long long total = (long long)n * n * n;
+  const double n3 = (double)n * (double)n * (double)n;
+  hipLaunchKernelGGL(k_ce_sqrt3, dim3(blocks_for(total)), dim3(kBlock), 0, st, lam, total, n3,
+                     sq);
+}
+
+// Pass A: L consecutive noise rows r = k3 n + k2 (lines along x1) of one
+// sample: xi(k1) = (z0, z1) of Philox block (r/2) n + k1 for even r, (z2, z3)
+// for odd r; scaled by sqrt(Lambda / n^3); FFT along x1; the first m outputs
+// to u1[s][r][j1].
+template <int C>
+__global__ void __launch_bounds__(kBlock)
+k_ce3_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __restrict__ ids,
+             int m, const double* __restrict__ sq, const double2* __restrict__ tw, FftPlan pl,
+             int L, int groups, double2* __restrict__ u1) {
+  extern __shared__ double lds[];
+  const int n = pl.n;
+  double* sre = lds;
+  double* sim = lds + L * n;
+  const int s = blockIdx.x / groups;
+  const int r0 = (blockIdx.x - s * groups) * L;
+  const int rows = n * n;
+  const int lines = min(L, rows - r0);
+  const uint32_t sample = ids ? ids[s] : (uint32_t)(first + (uint64_t)s);
+  const float inv_n = 1.0f / (float)n;
+  for (int t = threadIdx.x; t < L * n; t += kBlock) {
+    const int q = div_small(t, inv_n);
+    const int k1 = t - q * n;
+    if (q >= lines) {
+      sre[t] = 0.0;
+      sim[t] = 0.0;
+      continue;
+    }
+    const int r = r0 + q;
+    const U4 bk = stream_block(seed, (uint32_t)(r / 2) * (uint32_t)n + (uint32_t)k1, sample, level,
+                               kTagNoise);
+    double zr, zi;
+    if ((r & 1) == 0) box_muller(to_uniform(bk.x), to_uniform(bk.y), zr, zi);
+    else box_muller(to_uniform(bk.z), to_uniform(bk.w), zr, zi);
+    const double a = sq[(long long)r * n + k1];
+    sre[t] = a * zr;
+    sim[t] = a * zi;
+  }
+  __syncthreads();
+  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
+  else fft_lines<C, kBlock>(sre, sim, tw, pl, L);
+  double2* out = u1 + ((long long)s * rows + r0) * m;
+  const float inv_m = 1.0f / (float)m;
+  for (int t = threadIdx.x; t < lines * m; t += kBlock) {
+    const int q = div_small(t, inv_m);
+    const int j1 = t - q * m;
+    out[t] = make_double2(sre[q * n + j1], sim[q * n + j1]);
+  }
+}
+
+// Pass B: lines along x2 for fixed (k3, j1), L consecutive j1 of one sample:
+// u1[s][k3 n + k2][j1] -> FFT over k2 -> u2[s][k3][j2][j1], j2 < m.
+template <int C>
+__global__ void __launch_bounds__(kBlock)
+k_ce3_pass_b(int m, const double2* __restrict__ u1, const double2* __restrict__ tw, FftPlan pl,
+             int L, int groups, double2* __restrict__ u2) {
+  extern __shared__ double lds[];
+  const int n = pl.n;
+  double* sre = lds;
+  double* sim = lds + L * n;
+  const int per_k3 = (m + L - 1) / L;
+  const long long s = blockIdx.x / groups;
+  const int rem = blockIdx.x - (int)(s * groups);
+  const int k3 = rem / per_k3;
+  const int j1_0 = (rem - k3 * per_k3) * L;
+  const int lines = min(L, m - j1_0);
+  const double2* in = u1 + ((long long)s * n * n + (long long)k3 * n) * m + j1_0;
+  for (int t = threadIdx.x; t < L * n; t += kBlock) {
+    const int k2 = t / L, q = t - k2 * L;  // L adjacent j1 of row k2 are contiguous
+    const double2 v = q < lines ? in[(long long)k2 * m + q] : make_double2(0.0, 0.0);
+    sre[q * n + k2] = v.x;
+    sim[q * n + k2] = v.y;
+  }
+  __syncthreads();
+  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
+  else fft_lines<C, kBlock>(sre, sim, tw, pl, L);
+  double2* out = u2 + ((long long)s * n + k3) * m * m + j1_0;
+  for (int t = threadIdx.x; t < lines * m; t += kBlock) {
+    const int j2 = t / lines, q = t - j2 * lines;
+    out[(long long)j2 * m + q] = make_double2(sre[q * n + j2], sim[q * n + j2]);
+  }
+}
+
+// Pass C: lines along x3 for fixed (j2, j1), L consecutive j1 of one sample:
+// u2[s][k3][j2][j1] -> FFT over k3 -> g at j3 < m (Re: layer 0, Im: layer 1),
+// k = exp(mu_l + g_l) with l the layer of the centre, and the plain coarse
+// companion (layers re-evaluated at the coarse centres, Gaussian values of the
+// fine cell (2I, 2J, 2L)).
+template <int C>
+__global__ void __launch_bounds__(kBlock)
+k_ce3_pass_c(int kind, int n_nodes, int n_layers, double mu0, double mu1, int m,
+             const double2* __restrict__ u2, const double2* __restrict__ tw, FftPlan pl, int L,
+             int groups, const double* __restrict__ params, double* __restrict__ k,
+             double* __restrict__ kc) {
+  extern __shared__ double lds[];
+  const int n = pl.n;
+  double* sre = lds;
+  double* sim = lds + L * n;
+  const int per_j2 = (m + L - 1) / L;
+  const long long s = blockIdx.x / groups;
+  const int rem = blockIdx.x - (int)(s * groups);
+  const int j2 = rem / per_j2;
+  const int j1_0 = (rem - j2 * per_j2) * L;
+  const int lines = min(L, m - j1_0);
+  const long long mm = (long long)m * m;
+  const double2* in = u2 + (long long)s * n * mm + (long long)j2 * m + j1_0;
+  for (int t = threadIdx.x; t < L * n; t += kBlock) {
+    const int k3 = t / L, q = t - k3 * L;
+    const double2 v = q < lines ? in[(long long)k3 * mm + q] : make_double2(0.0, 0.0);
+    sre[q * n + k3] = v.x;
+    sim[q * n + k3] = v.y;
+  }
+  __syncthreads();
+  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
+  else fft_lines<C, kBlock>(sre, sim, tw, pl, L);
+  const double* prm = params + s * kParamStride;
+  const int mc = m / 2;
+  for (int t = threadIdx.x; t < lines * m; t += kBlock) {
+    const int j3 = t / lines, q = t - j3 * lines;
+    const int j1 = j1_0 + q;
+    const double g0 = sre[q * n + j3], g1 = sim[q * n + j3];
+    const int ly = n_layers > 1 ? layer_of3(kind, n_nodes, prm, centre(j1, m), centre(j2, m),
+                                            centre(j3, m))
+                                : 0;
+    k[s * mm * m + ((long long)j3 * m + j2) * m + j1] = exp(ly == 0 ? mu0 + g0 : mu1 + g1);
+    if (kc != nullptr && ((j1 | j2 | j3) & 1) == 0) {
+      const int lc = n_layers > 1 ? layer_of3(kind, n_nodes, prm, centre(j1 / 2, mc),
+                                              centre(j2 / 2, mc), centre(j3 / 2, mc))
+                                  : 0;
+      kc[s * (long long)mc * mc * mc + ((long long)(j3 / 2) * mc + j2 / 2) * mc + j1 / 2] =
+          exp(lc == 0 ? mu0 + g0 : mu1 + g1);
+    }
+  }
+}
+
+void launch_ce3(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
+                const uint32_t* ids, int batch, int m, const double* sq, const double2* tw,
+                const FftPlan& pl, const double* params, double2* u1, double2* u2, double* k,
+                double* k_coarse) {
+  const int n = pl.n;
+  const int L = fft_lines_per_group(pl);
+  const size_t lds = 2 * (size_t)L * n * sizeof(double);
+  const int ga = (n * n + L - 1) / L;
+  const int gb = n * ((m + L - 1) / L);
+  const int gc = m * ((m + L - 1) / L);
+  if (L > 1) {
+    hipLaunchKernelGGL(k_ce3_pass_a<1>, dim3(batch * ga), dim3(kBlock), lds, st, mdl.seed,
+                       (uint32_t)level, first, ids, m, sq, tw, pl, L, ga, u1);
+    hipLaunchKernelGGL(k_ce3_pass_b<1>, dim3(batch * gb), dim3(kBlock), lds, st, m, u1, tw, pl, L,
+                       gb, u2);
+    hipLaunchKernelGGL(k_ce3_pass_c<1>, dim3(batch * gc), dim3(kBlock), lds, st,
+                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, mdl.mu[0], mdl.mu[1], m, u2,
+                       tw, pl, L, gc, params, k, k_coarse);
+  } else {
+    hipLaunchKernelGGL(k_ce3_pass_a<0>, dim3(batch * ga), dim3(kBlock), lds, st, mdl.seed,
+                       (uint32_t)level, first, ids, m, sq, tw, pl, 1, ga, u1);
+    hipLaunchKernelGGL(k_ce3_pass_b<0>, dim3(batch * gb), dim3(kBlock), lds, st, m, u1, tw, pl, 1,
+                       gb, u2);
+    hipLaunchKernelGGL(k_ce3_pass_c<0>, dim3(batch * gc), dim3(kBlock), lds, st,
+                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, mdl.mu[0], mdl.mu[1], m, u2,
+                       tw, pl, 1, gc, params, k, k_coarse);
+  }
+}
+
+// ---- plain coarse companion of a piecewise constant sample, CGV sub-lattices
+__global__ void k_cgv_extract3(int m, long long total, const double* __restrict__ kf,
+                               double* __restrict__ ksub) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int mc = m / 2;
+  const long long nc = (long long)mc * mc * mc;
+  const long long sa = g / nc;  // sample * 8 + a
+  int I, J, L;
+  cell_of(g - sa * nc, mc, I, J, L);
+  const long long s = sa >> 3;
+  const int a = (int)(sa & 7);
+  const int i = 2 * I + (a & 1), j = 2 * J + ((a >> 1) & 1), l = 2 * L + (a >> 2);
+  ksub[g] = kf[s * (long long)m * m * m + ((long long)l * m + j) * m + i];
+}
+
+void launch_cgv_extract3(hipStream_t st, int m, int batch, const double* kf, double* ksub) {
+  const long long total = (long long)batch * 8 * (m / 2) * (m / 2) * (m / 2);
+  hipLaunchKernelGGL(k_cgv_extract3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, kf,
+                     ksub);
+}
+
+}  // namespace mlmc

@@ -61,6 +61,11 @@ __global__ void k_sample_params(mlmc_model mdl, uint32_t level, uint64_t first,
     const uint32_t w[4] = {b.x, b.y, b.z, b.w};
     const double lo[4] = {0.8, 0.6, 0.2, 0.4};
     for (int t = 0; t < 4; ++t) prm[t] = lo[t] + 0.1 * to_uniform(w[t]);
+  } else if (mdl.interface_kind == MLMC_IFACE_TILTED_PLANE) {
+    const U4 b = stream_block(mdl.seed, 0, sample, level, kTagGeometry);
+    prm[0] = mdl.y_lo + (mdl.y_hi - mdl.y_lo) * to_uniform(b.x);
+    prm[1] = mdl.y_lo + (mdl.y_hi - mdl.y_lo) * to_uniform(b.y);
+    prm[2] = -0.1 + 0.2 * to_uniform(b.z);
   }
   {
     const U4 b = stream_block(mdl.seed, 0, sample, level, kTagLayerConst);

@@ -147,4 +147,38 @@ void launch_sc_final(hipStream_t st, int batch, const double* partial, int bps, 
 
 inline int blocks_per_sample(long long n) { return (int)((n + kCellsPerBlock - 1) / kCellsPerBlock); }
 
+// ---- 3-D path (d3.hip): layout T[s][3][m^3], tb[s][3][m^2] (west, south,
+// bottom faces), k, b, x [s][m^3] with x1 fastest.
+void launch_assemble3(hipStream_t st, int m, int batch, const double* k, double* T, double* tb,
+                      double* b);
+void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double* p, double* qout,
+                 double* qin);
+void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                     double* Tc, double* tbc);
+void launch_rbgs3(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
+                  const double* r, const int32_t* active, int color, int zero_init);
+void launch_resid_restrict3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                            const double* z, const double* r, double* rc, const int32_t* active);
+void launch_prolong3(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
+                     const int32_t* active);
+void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                          double* Ainv);
+void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                      const double* p, double* q, double* partial, int bps, const int32_t* active);
+void launch_true_residual3(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                           const double* b, const double* x, double* partial, int bps);
+void launch_field_pc3(hipStream_t st, const mlmc_model& mdl, int m, int batch,
+                      const double* params, double* k);
+void launch_ce_first_row3(hipStream_t st, int n, int m, double sigma2, double lambda, int norm_r,
+                          double2* c);
+void launch_ce_sqrt3(hipStream_t st, const double2* lam, int n, double* sq);
+void launch_ce3(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
+                const uint32_t* ids, int batch, int m, const double* sq, const double2* tw,
+                const FftPlan& pl, const double* params, double2* u1, double2* u2, double* k,
+                double* k_coarse);
+void launch_cgv_extract3(hipStream_t st, int m, int batch, const double* kf, double* ksub);
+// z = A^-1 r for n unknowns per sample (coarsest grid of either dimension).
+void launch_dense_apply_n(hipStream_t st, int n, int batch, const double* Ainv, const double* r,
+                          double* z, const int32_t* active);
+
 }  // namespace mlmc

@@ -243,6 +243,13 @@ __global__ void k_dense_apply(int n, long long total, const double* __restrict__
   z[g] = acc;
 }
 
+void launch_dense_apply_n(hipStream_t st, int n, int batch, const double* Ainv, const double* r,
+                          double* z, const int32_t* active) {
+  const long long total = (long long)batch * n;
+  hipLaunchKernelGGL(k_dense_apply, dim3(blocks_for(total)), dim3(kBlock), 0, st, n, total, Ainv,
+                     r, z, active);
+}
+
 void launch_dense_apply(hipStream_t st, int m, int batch, const double* Ainv, const double* r,
                         double* z, const int32_t* active) {
   const long long total = (long long)batch * m * m;

@@ -83,17 +83,21 @@ int n_ce_for(const mlmc_server* s, int m) {
   return 0;
 }
 
-// Device bytes of one request's share of a batch: k, T (2), b, p, r, z, p, q,
+// Device bytes of one request's share of a batch: k, T (d), b, p, r, z, p, q,
 // z_pre and the multigrid hierarchy (about 1/3 of a level per array), plus the
-// companions on the coarse grid (1 plain, 4 with CGV), all FP64.
+// companions on the coarse grid (1 plain, 2^d with CGV), all FP64, and the
+// circulant-embedding scratch (2-D: n m; 3-D: n^2 m + n m^2 complex values).
 uint64_t request_bytes(const mlmc_server* s, const mlmc_request& r) {
-  const double cells = (double)r.m_fine * r.m_fine;
-  const double ncomp = r.level == 0 ? 0.0 : (s->opts.cgv ? 4.0 : 1.0);
-  const double per_cell = 8.0 * (10.0 + 4.0 * 4.0 / 3.0);
+  const int d = s->model.dim;
+  const double m = (double)r.m_fine;
+  const double cells = d == 3 ? m * m * m : m * m;
+  const double ncomp = r.level == 0 ? 0.0 : (s->opts.cgv ? (double)(1 << d) : 1.0);
+  const double per_cell = 8.0 * (10.0 + (d + 2) * 4.0 / 3.0);
   double ce = 0.0;
-  const int nce = n_ce_for(s, r.m_fine);
-  if (s->model.field_kind == MLMC_FIELD_CORRELATED) ce = 16.0 * (double)nce * r.m_fine;
-  return (uint64_t)(cells * per_cell * (1.0 + ncomp / 4.0) + ce);
+  const double nce = (double)n_ce_for(s, r.m_fine);
+  if (s->model.field_kind == MLMC_FIELD_CORRELATED)
+    ce = d == 3 ? 16.0 * (nce * nce * m + nce * m * m) : 16.0 * nce * m;
+  return (uint64_t)(cells * per_cell * (1.0 + ncomp / (double)(1 << d)) + ce);
 }
 
 void worker_loop(mlmc_server* s, int wi) {
