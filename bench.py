@@ -29,7 +29,11 @@ import workloads as W  # noqa: E402
 
 METRIC = "MLMC samples solved/s per level at 1e-10 QoI rel-err; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-DOMINANT = "k_mg_mid"
+# The dominant kernel of the step: the W second visit on the finest grid of
+# every solve, k_mg_mid_t<64, 32, double, true> (its own instantiation, the
+# top line of the rocprofv3 summary).  "@0" selects that level's launches.
+DOMINANT = "k_mg_mid@0"
+DOMINANT_SYMBOL = "mlmc::k_mg_mid_t<64, 32, double, true>"
 
 
 def parse():
@@ -91,50 +95,61 @@ def cpu_baseline(wl, budget_s):
             "per_level_s_per_sample": [p["s_per_sample"] for p in per_level]}
 
 
-def step_rate_3d(lib, torch, wl, reps=2):
-    """Y-samples/s of one pass over every level of a 3-D workload (level runs
-    one after another, FP64, after one warm-up pass)."""
+def serve_setup(lib, kinds, models, solvers):
+    """Server options for request kinds [(model index, level, m, count)]."""
+    grids = [[] for _ in models]
+    for mi, _, m, _ in kinds:
+        if m not in grids[mi]:
+            grids[mi].append(m)
+    return lib.serve_opts_for_models(list(zip(models, grids)), n_workers=3, max_batch=512)
+
+
+def pass_rate(lib, torch, kinds, models, solvers, reps=2):
+    """Requests/s of one batched pass over every kind (count samples each, level
+    runs one after another with the kind's model and solver options), after one
+    warm-up pass: the saturation estimate the offered loads are scaled to."""
     ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
-    opts = lib.mlmc_solver_opts_default()
     first = 0
     try:
         for rep in range(reps + 1):
             if rep == 1:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-            for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
-                lib.mlmc_level_run(ctx, wl.model, level, m, first, n, wl.cgv, opts)
-            first += max(wl.n_samples)
+            for mi, level, m, n in kinds:
+                lib.mlmc_level_run(ctx, models[mi], level, m, first, n, False, solvers[mi])
+            first += max(k[3] for k in kinds)
         torch.cuda.synchronize()
         per_pass = (time.perf_counter() - t0) / reps
     finally:
         lib.mlmc_ctx_destroy(ctx)
-    return sum(wl.n_samples) / per_pass, per_pass
+    return sum(k[3] for k in kinds) / per_pass, per_pass
 
 
-def serving_latency(lib, wl, rate, seconds, seed=1):
-    """Poisson arrivals of single-sample requests with the workload's level mix
-    (probability of level l proportional to N_l), served by the continuous-
-    batching server; latency = completion - submission on the server clock."""
+def serving_latency(lib, kinds, models, solvers, rate, seconds, seed=1):
+    """Poisson arrivals at `rate` of single-sample requests of the given kinds
+    (probability proportional to each kind's count), served by one continuous-
+    batching server for all models; latency = completion - submission on the
+    server clock."""
     import numpy as np
     rng = np.random.default_rng(seed)
-    probs = np.array(wl.n_samples, dtype=float)
+    probs = np.array([k[3] for k in kinds], dtype=float)
     probs /= probs.sum()
     n_req = max(50, int(rate * seconds))
     gaps = rng.exponential(1.0 / rate, size=n_req)
-    levels = rng.choice(len(wl.m_levels), size=n_req, p=probs)
-    opts = lib.serve_opts_for(wl.model, wl.m_levels, n_workers=3, max_batch=512, cgv=int(wl.cgv))
-    srv = lib.mlmc_serve_start(wl.model, opts)
+    picks = rng.choice(len(kinds), size=n_req, p=probs)
+    srv = lib.mlmc_serve_start_models(models, serve_setup(lib, kinds, models, solvers),
+                                      solvers=solvers)
     results = {}
-    counters = [10 ** 7] * len(wl.m_levels)
+    counters = [10 ** 7] * len(kinds)
     try:
         t = lib.mlmc_serve_now(srv) + 0.05
-        for g, lvl in zip(gaps, levels):
+        for g, kq in zip(gaps, picks):
             t += g
             while lib.mlmc_serve_now(srv) < t:
                 pass
-            lib.mlmc_serve_submit(srv, int(lvl), wl.m_levels[lvl], counters[lvl])
-            counters[lvl] += 1
+            mi, level, m, _ = kinds[kq]
+            lib.mlmc_serve_submit(srv, level, m, counters[kq], model=mi)
+            counters[kq] += 1
             if len(results) % 64 == 0:
                 for r in lib.mlmc_serve_poll(srv)[0]:
                     results[r["id"]] = r
@@ -149,21 +164,23 @@ def serving_latency(lib, wl, rate, seconds, seed=1):
     rs = list(results.values())
     lat = np.array([r["t_done"] - r["t_submit"] for r in rs])
     span = max(r["t_done"] for r in rs) - min(r["t_submit"] for r in rs)
-    per_level = []
-    for lvl, m in enumerate(wl.m_levels):
-        ll = np.array([r["t_done"] - r["t_submit"] for r in rs if r["level"] == lvl])
+    per_kind = []
+    for mi, level, m, _ in kinds:
+        ll = np.array([r["t_done"] - r["t_submit"] for r in rs
+                       if r["model"] == mi and r["level"] == level and r["m_fine"] == m])
         if ll.size:
-            per_level.append({"level": lvl, "m": m, "requests": int(ll.size),
-                              "p50_ms": 1e3 * float(np.percentile(ll, 50)),
-                              "p99_ms": 1e3 * float(np.percentile(ll, 99))})
+            per_kind.append({"model": mi, "dim": int(models[mi].dim), "level": level, "m": m,
+                             "requests": int(ll.size),
+                             "p50_ms": 1e3 * float(np.percentile(ll, 50)),
+                             "p99_ms": 1e3 * float(np.percentile(ll, 99))})
     return {"offered_per_s": rate, "completed": len(rs), "submitted": n_req,
             "achieved_per_s": len(rs) / span, "failed": int(sum(r["failed"] for r in rs)),
             "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
             "mean_batch": float(np.mean([r["batch_size"] for r in rs])), "batches": stats["batches"],
-            "per_level": per_level}
+            "per_kind": per_kind}
 
 
-KERNEL_SOURCES = {"k_mg_mid": "mg_fused.hip", "k_mg_up": "mg_fused.hip",
+KERNEL_SOURCES = {"k_mg_mid@0": "mg_fused.hip", "k_mg_mid": "mg_fused.hip", "k_mg_up": "mg_fused.hip",
                   "k_mg_down": "mg_fused.hip", "k_mg_coarse_cycle": "mg_fused.hip",
                   "k_cg_direction_t": "mg_fused.hip", "k_spmv_dot": "mg_pcg.hip",
                   "k_axpy_dot": "mg_pcg.hip", "k_ce_pass_a": "field.hip", "k_ce_pass_b": "field.hip"}
@@ -171,10 +188,10 @@ KERNEL_SOURCES = {"k_mg_mid": "mg_fused.hip", "k_mg_up": "mg_fused.hip",
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (profiles/traffic_<kernel>.json), or None when there is none or the kernel's
+    (profiles/traffic_<kernel>.json, "@<level>" written "_level<level>"), or None when there is none or the kernel's
     source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel.replace("@", "_level"))
     src = KERNEL_SOURCES.get(kernel)
     if not os.path.exists(path) or src is None:
         return None
@@ -252,6 +269,80 @@ def path_variants(lib, torch, wl, ctx, opts, args):
     return {"all_levels_one_call_fp64": {"value": total / t_merged, "ms_per_step": 1e3 * t_merged},
             "multigrid_fp32_in_fp64_cg": {"value": total / t_fp32, "ms_per_step": 1e3 * t_fp32,
                                           "max_qoi_rel_diff_vs_fp64": dev}}
+
+
+def other_configs(lib, torch, steps):
+    """The other batched workloads, each timed over `steps` passes after one warm-up
+    pass (not part of `value`):
+    * Coarse Grid Variates on the piecewise constant model, levels 64^2..512^2
+      (4096/1024/256/64 samples, 2^d = 4 sub-lattice companions per fine sample),
+      all levels in one call (mlmc_run_levels) and level by level; FP64;
+    * the high-contrast field on 1024^2 (256 samples) with the multigrid in FP64,
+      FP32 and bfloat16 inside the FP64 CG, with the largest relative QoI
+      difference of each reduced precision to the FP64 solve of the same samples."""
+    ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
+    opts = lib.mlmc_solver_opts_default()
+
+    def timed(f):
+        f(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            f(1 + k)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    out = {}
+    try:
+        wl = W.CGV_PC
+        total = sum(wl.n_samples)
+
+        def merged(idx):
+            lib.mlmc_run_levels(ctx, wl.model, wl.m_levels, [idx * n for n in wl.n_samples],
+                                wl.n_samples, True, opts)
+
+        def per_level(idx):
+            for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+                lib.mlmc_level_run(ctx, wl.model, level, m, idx * n, n, True, opts)
+
+        t_merged, t_level = timed(merged), timed(per_level)
+        out["cgv"] = {"workload": wl.name, "levels_m": wl.m_levels, "samples": wl.n_samples,
+                      "companions_per_sample": 4, "dtype": "f64",
+                      "all_levels_one_call": {"value": total / t_merged,
+                                              "ms_per_step": 1e3 * t_merged},
+                      "level_by_level": {"value": total / t_level, "ms_per_step": 1e3 * t_level}}
+
+        wl = W.HIGH_CONTRAST
+        m, n = wl.m_levels[0], wl.n_samples[0]
+        runs, qs = {}, {}
+        for name, prec in (("f64", lib.MLMC_PREC_FP64), ("f32", lib.MLMC_PREC_FP32),
+                           ("bf16", lib.MLMC_PREC_BF16)):
+            o = lib.mlmc_solver_opts_default(precision=prec, tol=wl.tol)
+            if prec == lib.MLMC_PREC_BF16:
+                o.omega = wl.omega_bf16
+            sums = []
+
+            def run(idx):
+                sums.append(lib.mlmc_level_run(ctx, wl.model, 0, m, idx * n, n, False, o,
+                                               allow_noconv=True))
+
+            t = timed(run)
+            q = torch.empty(n, dtype=torch.float64, device="cuda")
+            lib.mlmc_level_run(ctx, wl.model, 0, m, 0, n, False, o, q_f=q, allow_noconv=True)
+            qs[name] = q
+            runs[name] = {"value": n / t, "ms_per_step": 1e3 * t,
+                          "mean_iters": sums[-1].iters_fine / n,
+                          "failed_solves": int(sum(x.n_failed for x in sums))}
+        torch.cuda.synchronize()
+        for name in ("f32", "bf16"):
+            runs[name]["max_qoi_rel_diff_vs_fp64"] = \
+                ((qs[name] - qs["f64"]).abs() / qs["f64"].abs()).max().item()
+        out["high_contrast"] = {"workload": wl.name, "m": m, "samples": n, "tol_relres": wl.tol,
+                                "omega_bf16": wl.omega_bf16,
+                                "multigrid_precision": runs}
+    finally:
+        lib.mlmc_ctx_destroy(ctx)
+    return out
 
 
 def main():
@@ -349,9 +440,24 @@ def main():
         for key in prof:
             prof[key] += pr[key]
         lib.mlmc_profile_enable(c, None)
+    # the same kernel function over every level (all instantiations), one more step
+    prof_all = None
+    base_kernel = args.kernel.split("@")[0]
+    if base_kernel != args.kernel:
+        for c in lctx:
+            lib.mlmc_profile_enable(c, base_kernel)
+        step(args.warmup + args.steps, False)
+        torch.cuda.synchronize()
+        prof_all = {"launches": 0, "total_ms": 0.0, "algorithmic_bytes": 0.0}
+        for c in lctx:
+            pr = lib.mlmc_profile_read(c)
+            for key in prof_all:
+                prof_all[key] += pr[key]
+            lib.mlmc_profile_enable(c, None)
     est = lib.mlmc_estimate(sums)
     single = per_sample_baseline() if not args.no_per_sample else None
     variants = None if args.no_variants else path_variants(lib, torch, wl, ctx, opts, args)
+    configs = None if args.no_variants else other_configs(lib, torch, args.steps)
     for c in lctx:
         lib.mlmc_ctx_destroy(c)
     lib.mlmc_ctx_destroy(ctx)
@@ -360,17 +466,27 @@ def main():
     total = sum(wl.n_samples)
     serving = None
     if args.serve_rates and args.serve_rates != "none":
+        rates = [float(f) for f in args.serve_rates.split(",") if f]
+        # the bench workload's levels, FP64, one model
+        kinds = [(0, level, m, n) for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples))]
         sat = total / (elapsed / args.steps)
-        serving = {"saturation_estimate_per_s": sat, "workers": 3, "precision": "f64",
-                   "runs": [serving_latency(lib, wl, float(f) * sat, args.serve_seconds)
-                            for f in args.serve_rates.split(",") if f]}
-        wl3 = W.SERVED_3D
-        sat3, pass3 = step_rate_3d(lib, torch, wl3)
-        serving["3d"] = {"workload": wl3.name, "levels_m": wl3.m_levels,
-                         "samples_per_pass": wl3.n_samples, "pass_ms": 1e3 * pass3,
-                         "saturation_estimate_per_s": sat3,
-                         "runs": [serving_latency(lib, wl3, float(f) * sat3, args.serve_seconds)
-                                  for f in args.serve_rates.split(",") if f]}
+        serving = {"workload": wl.name, "saturation_estimate_per_s": sat, "workers": 3,
+                   "precision": "f64",
+                   "runs": [serving_latency(lib, kinds, [wl.model], [opts], f * sat,
+                                            args.serve_seconds) for f in rates]}
+        # the mixed 2-D / 3-D stream: three models in one server
+        models = W.SERVED_MIX_MODELS
+        solvers = [lib.mlmc_solver_opts_default(
+            precision=lib.MLMC_PREC_FP32 if p == "f32" else lib.MLMC_PREC_FP64, tol=tl)
+            for p, tl in zip(W.SERVED_MIX_PRECISION, W.SERVED_MIX_TOL)]
+        sat_mix, pass_mix = pass_rate(lib, torch, W.SERVED_MIX_KINDS, models, solvers)
+        serving["mixed_2d_3d"] = {
+            "kinds": [{"model": mi, "dim": int(models[mi].dim), "level": lv, "m": m, "count": c}
+                      for mi, lv, m, c in W.SERVED_MIX_KINDS],
+            "precision": W.SERVED_MIX_PRECISION, "tol_relres": W.SERVED_MIX_TOL,
+            "batched_pass_ms": 1e3 * pass_mix, "saturation_estimate_per_s": sat_mix,
+            "runs": [serving_latency(lib, W.SERVED_MIX_KINDS, models, solvers, f * sat_mix,
+                                     args.serve_seconds) for f in rates]}
     per_level = []
     for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
         t = sorted(level_times[level])[len(level_times[level]) // 2]
@@ -382,11 +498,21 @@ def main():
     if prof["launches"] > 0 and prof["total_ms"] > 0:
         avg_ms = prof["total_ms"] / prof["launches"]
         achieved = prof["algorithmic_bytes"] / (prof["total_ms"] * 1e-3) / 1e9
-        roof = {"kernel": args.kernel, "bound": "hbm", "achieved": round(achieved, 1),
+        roof = {"kernel": args.kernel,
+                "symbol": DOMINANT_SYMBOL if args.kernel == DOMINANT else None,
+                "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.kernel), "launches": prof["launches"],
                 "avg_launch_ms": avg_ms,
                 "algorithmic_bytes_per_launch": prof["algorithmic_bytes"] / prof["launches"]}
+        if prof_all and prof_all["launches"] > 0:
+            ach = prof_all["algorithmic_bytes"] / (prof_all["total_ms"] * 1e-3) / 1e9
+            roof["all_levels"] = {
+                "kernel": base_kernel, "achieved": round(ach, 1),
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(base_kernel),
+                "launches": prof_all["launches"],
+                "avg_launch_ms": prof_all["total_ms"] / prof_all["launches"],
+                "algorithmic_bytes_per_launch": prof_all["algorithmic_bytes"] / prof_all["launches"]}
     out = {"metric": METRIC, "value": total / (elapsed / args.steps), "unit": "samples/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -398,7 +524,8 @@ def main():
                                "lambda=0.3, means 0/2"},
            "levels_concurrent": bool(args.concurrent_levels),
            "per_level": per_level, "estimate": est, "roofline": roof,
-           "per_sample_fp64_gpu": single, "variants": variants, "serving": serving}
+           "per_sample_fp64_gpu": single, "variants": variants, "other_configs": configs,
+           "serving": serving}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -307,7 +307,11 @@ mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_esti
 /* Kernel timing: when enabled, every launch of the named kernel is bracketed
  * by HIP events on the context's stream; mlmc_profile_read returns the launch
  * count, the summed event time and the algorithmic bytes the library counts
- * for those launches.  kernel_name NULL disables.  Host outputs. */
+ * for those launches.  kernel_name NULL disables.  Host outputs.
+ * The tiled multigrid kernels (k_mg_down, k_mg_mid, k_mg_up) also answer to
+ * "<name>@<level>", which times the launches on that level of each solve only
+ * (level 0 = the finest grid, the kernel instantiation that works on FP64
+ * residuals). */
 mlmc_status mlmc_profile_enable(mlmc_ctx* ctx, const char* kernel_name);
 mlmc_status mlmc_profile_read(mlmc_ctx* ctx, int64_t* launches, double* total_ms,
                               double* algorithmic_bytes);
@@ -336,6 +340,7 @@ typedef struct mlmc_serve_opts {
   int32_t n_grids;            /* entries in grid_m / grid_n_ce (correlated fields) */
   int32_t grid_m[8];          /* fine grid sizes served ...                       */
   int32_t grid_n_ce[8];       /* ... and their circulant-embedding sizes          */
+  int32_t grid_model[8];      /* ... for this model index (0 with one model)      */
   int32_t reserved;
   mlmc_solver_opts solver;
 } mlmc_serve_opts;
@@ -344,7 +349,7 @@ typedef struct mlmc_request {
   int32_t level;
   int32_t m_fine;
   uint32_t sample;
-  int32_t reserved;
+  int32_t model;       /* index of the model (0 .. n_models - 1)               */
 } mlmc_request;
 
 typedef struct mlmc_result {
@@ -355,7 +360,7 @@ typedef struct mlmc_result {
   int32_t iters;       /* CG iterations of the fine solve                      */
   int32_t batch_size;  /* requests in the batch that served it                 */
   int32_t status;      /* MLMC_OK, or the error of the batch                   */
-  int32_t reserved;
+  int32_t model;       /* model index of the request                           */
   double q_f, q_c, y;  /* Q on the fine grid, coarse (companion mean), Y       */
   double t_submit, t_start, t_done;
 } mlmc_result;
@@ -363,10 +368,22 @@ typedef struct mlmc_result {
 /* Defaults: device 0, 3 workers, batches up to 256, plain MLMC, 64 GiB budget,
  * mlmc_solver_opts_default. */
 mlmc_status mlmc_serve_opts_default(mlmc_serve_opts* opts);
-/* Starts the workers (model: host; copied). */
+/* Starts the workers for one model (host; copied); opts->solver for every batch. */
 mlmc_status mlmc_serve_start(const mlmc_model* model, const mlmc_serve_opts* opts,
                              mlmc_server** out);
-/* Queues a request (host); id (host, may be NULL) receives its identifier. */
+/* Starts the workers for n_models (1..8) models at once, e.g. 2-D and 3-D fields
+ * in one request stream.  models: host [n_models] (copied); solvers: host
+ * [n_models] solver options per model (copied), or NULL for opts->solver;
+ * grid q of opts serves model opts->grid_model[q].  A batch holds requests of
+ * one (model, level, m_fine) and runs with that model's solver options.
+ * MLMC_EINVAL for a count out of range, a grid of an unknown model or a model
+ * whose dim is not 2 or 3. */
+mlmc_status mlmc_serve_start_models(const mlmc_model* models, const mlmc_solver_opts* solvers,
+                                    int n_models, const mlmc_serve_opts* opts,
+                                    mlmc_server** out);
+/* Queues a request (host); id (host, may be NULL) receives its identifier.
+ * MLMC_EINVAL for an unknown model, a bad level or grid, or a grid with no
+ * embedding size for a correlated model. */
 mlmc_status mlmc_serve_submit(mlmc_server* srv, const mlmc_request* req, uint64_t* id);
 /* Moves up to max finished results into out (host); *n_out = number moved;
  * *pending (may be NULL) = requests queued or finished and not yet polled. */

@@ -33,7 +33,7 @@ EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_
             "mlmc_level_run", "mlmc_estimate", "mlmc_profile_enable", "mlmc_profile_read",
             "mlmc_sample_field_ids", "mlmc_level_run_ids", "mlmc_serve_opts_default",
             "mlmc_serve_start", "mlmc_serve_submit", "mlmc_serve_poll", "mlmc_serve_now",
-            "mlmc_serve_stats", "mlmc_serve_stop", "mlmc_run_levels"]
+            "mlmc_serve_stats", "mlmc_serve_stop", "mlmc_run_levels", "mlmc_serve_start_models"]
 
 
 class mlmc_model(ctypes.Structure):
@@ -70,19 +70,20 @@ class mlmc_serve_opts(ctypes.Structure):
                 ("max_batch", ctypes.c_int32), ("cgv", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("n_grids", ctypes.c_int32),
                 ("grid_m", ctypes.c_int32 * 8), ("grid_n_ce", ctypes.c_int32 * 8),
-                ("reserved", ctypes.c_int32), ("solver", mlmc_solver_opts)]
+                ("grid_model", ctypes.c_int32 * 8), ("reserved", ctypes.c_int32),
+                ("solver", mlmc_solver_opts)]
 
 
 class mlmc_request(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("m_fine", ctypes.c_int32),
-                ("sample", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("sample", ctypes.c_uint32), ("model", ctypes.c_int32)]
 
 
 class mlmc_result(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("level", ctypes.c_int32), ("m_fine", ctypes.c_int32),
                 ("sample", ctypes.c_uint32), ("failed", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("batch_size", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("model", ctypes.c_int32),
                 ("q_f", ctypes.c_double), ("q_c", ctypes.c_double), ("y", ctypes.c_double),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double)]
@@ -126,6 +127,8 @@ _SIGS = {
     "mlmc_serve_opts_default": (_S, [ctypes.POINTER(mlmc_serve_opts)]),
     "mlmc_serve_start": (_S, [ctypes.POINTER(mlmc_model), ctypes.POINTER(mlmc_serve_opts),
                               ctypes.POINTER(_P)]),
+    "mlmc_serve_start_models": (_S, [ctypes.POINTER(mlmc_model), ctypes.POINTER(mlmc_solver_opts),
+                                     _I, ctypes.POINTER(mlmc_serve_opts), ctypes.POINTER(_P)]),
     "mlmc_serve_submit": (_S, [_P, ctypes.POINTER(mlmc_request), ctypes.POINTER(ctypes.c_uint64)]),
     "mlmc_serve_poll": (_S, [_P, ctypes.POINTER(mlmc_result), _I, ctypes.POINTER(_I),
                              ctypes.POINTER(ctypes.c_int64)]),
@@ -367,11 +370,23 @@ def mlmc_serve_opts_default(**overrides):
 
 def serve_opts_for(model, grids, **overrides):
     """Server options serving the fine grids `grids` of `model` (embedding sizes from model.n_ce)."""
+    return serve_opts_for_models([(model, grids)], **overrides)
+
+
+def serve_opts_for_models(model_grids, **overrides):
+    """Server options for several models: model_grids = [(model, grids), ...]; grid entries
+    of the q-th pair serve model index q (embedding sizes from model.n_ce)."""
     o = mlmc_serve_opts_default(**overrides)
-    o.n_grids = len(grids)
-    for q, m in enumerate(grids):
-        o.grid_m[q] = int(m)
-        o.grid_n_ce[q] = int(model.n_ce.get(m, 0)) if getattr(model, "n_ce", None) else 0
+    q = 0
+    for mi, (model, grids) in enumerate(model_grids):
+        for m in grids:
+            if q >= 8:
+                raise ValueError("at most 8 (model, grid) entries")
+            o.grid_m[q] = int(m)
+            o.grid_n_ce[q] = int(model.n_ce.get(m, 0)) if getattr(model, "n_ce", None) else 0
+            o.grid_model[q] = mi
+            q += 1
+    o.n_grids = q
     return o
 
 
@@ -384,8 +399,21 @@ def mlmc_serve_start(model, opts):
     return h
 
 
-def mlmc_serve_submit(srv, level, m_fine, sample):
-    req = mlmc_request(int(level), int(m_fine), int(sample), 0)
+def mlmc_serve_start_models(models, opts, solvers=None):
+    """models: list of workload models or mlmc_model; solvers: list of mlmc_solver_opts
+    (one per model) or None for opts.solver."""
+    L = len(models)
+    arr = (mlmc_model * L)(*[m if isinstance(m, mlmc_model) else make_model(m) for m in models])
+    sol = None if solvers is None else (mlmc_solver_opts * L)(*solvers)
+    h = ctypes.c_void_p()
+    code = _lib.mlmc_serve_start_models(arr, sol, L, ctypes.byref(opts), ctypes.byref(h))
+    if code != MLMC_OK:
+        raise MlmcError(code, "mlmc_serve_start_models failed")
+    return h
+
+
+def mlmc_serve_submit(srv, level, m_fine, sample, model=0):
+    req = mlmc_request(int(level), int(m_fine), int(sample), int(model))
     rid = ctypes.c_uint64()
     code = _lib.mlmc_serve_submit(srv, ctypes.byref(req), ctypes.byref(rid))
     if code != MLMC_OK:

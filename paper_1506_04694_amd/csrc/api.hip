@@ -127,10 +127,21 @@ hipEvent_t pool_event(mlmc_ctx* ctx) {
   return e;
 }
 
-// Brackets a launch with events when `name` is the profiled kernel.
+// Brackets a launch with events when `name` is the profiled kernel.  Launches
+// of a multigrid level pass `level`; the profiled name "<name>@<level>" then
+// selects that level's launches only (level 0: the finest grid of a solve,
+// a kernel instantiation of its own).
 template <class F>
-void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch) {
-  if (!ctx->prof_name.empty() && ctx->prof_name == name) {
+void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch, int level = -1) {
+  bool hit = false;
+  if (!ctx->prof_name.empty()) {
+    const std::string& p = ctx->prof_name;
+    const size_t at = p.find('@');
+    hit = at == std::string::npos ? p == name
+                                  : (p.compare(0, at, name) == 0 && std::strlen(name) == at &&
+                                     level >= 0 && std::to_string(level) == p.substr(at + 1));
+  }
+  if (hit) {
     ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes * ctx->prof_scale, ctx->prof_iter};
     (void)hipEventRecord(pe.a, ctx->stream);
     launch();
@@ -824,7 +835,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     timed(ctx, "k_mg_down", cells * (ebd * 3.25 + rb), [&] {
       launch_mg_down(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], rs[l + 1],
                      S.active);
-    });
+    }, l);
     fcycle(l + 1);
     const void* zin = zpre[l];
     if (visits(l) == 2) {
@@ -832,7 +843,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       timed(ctx, "k_mg_mid", cells * (ebd * 4.5 + rb), [&] {
         launch_mg_mid(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], zmid[l],
                       zs[l + 1], omega, rs[l + 1], S.active);
-      });
+      }, l);
       fcycle(l + 1);
       zin = zmid[l];
     }
@@ -840,7 +851,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     timed(ctx, "k_mg_up", cells * (ebd * 3.25 + (l == 0 ? 16.0 : 2.0 * ebd)), [&] {
       launch_mg_up(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zin, zs[l], zs[l + 1],
                    omega, S.active, l == 0 ? partial : nullptr);
-    });
+    }, l);
   };
   auto vcycle = [&]() {
     if (!fused) {

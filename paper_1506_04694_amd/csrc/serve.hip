@@ -4,11 +4,15 @@
 // Grid Variates): sample number `sample` of level `level` on the m_fine grid,
 // i.e. the fine solve and its coarse companion(s) and Y = Q_f - Q_c.
 //
+// A server may serve several models at once (for instance 2-D and 3-D fields
+// of different laws); a request names its model by index, and every batch
+// holds requests of one (model, level, grid) with that model's solver options.
+//
 // Requests are queued as they arrive.  Each worker thread owns a context (its
 // own HIP stream at default priority and its own device workspaces, which stay
 // allocated between batches: fields, operators and multigrid hierarchies are
 // device-resident) and repeatedly takes the oldest waiting request together
-// with up to max_batch - 1 later requests for the same (level, grid), as long
+// with up to max_batch - 1 later requests for the same (model, level, grid), as long
 // as the estimated device memory of all running batches stays within the
 // budget; a lone request always runs when nothing else is running.  Batches of
 // different workers run concurrently on the device, so requests that arrive
@@ -56,7 +60,8 @@ struct Worker {
 
 struct mlmc_server {
   mlmc_serve_opts opts;
-  mlmc_model model;
+  std::vector<mlmc_model> models;
+  std::vector<mlmc_solver_opts> solvers;  // one per model
   std::vector<Worker> workers;
   std::mutex mu;
   std::condition_variable cv;
@@ -77,9 +82,9 @@ struct mlmc_server {
 
 namespace {
 
-int n_ce_for(const mlmc_server* s, int m) {
+int n_ce_for(const mlmc_server* s, int model, int m) {
   for (int q = 0; q < s->opts.n_grids; ++q)
-    if (s->opts.grid_m[q] == m) return s->opts.grid_n_ce[q];
+    if (s->opts.grid_model[q] == model && s->opts.grid_m[q] == m) return s->opts.grid_n_ce[q];
   return 0;
 }
 
@@ -88,14 +93,15 @@ int n_ce_for(const mlmc_server* s, int m) {
 // companions on the coarse grid (1 plain, 2^d with CGV), all FP64, and the
 // circulant-embedding scratch (2-D: n m; 3-D: n^2 m + n m^2 complex values).
 uint64_t request_bytes(const mlmc_server* s, const mlmc_request& r) {
-  const int d = s->model.dim;
+  const mlmc_model& mdl = s->models[r.model];
+  const int d = mdl.dim;
   const double m = (double)r.m_fine;
   const double cells = d == 3 ? m * m * m : m * m;
   const double ncomp = r.level == 0 ? 0.0 : (s->opts.cgv ? (double)(1 << d) : 1.0);
   const double per_cell = 8.0 * (10.0 + (d + 2) * 4.0 / 3.0);
   double ce = 0.0;
-  const double nce = (double)n_ce_for(s, r.m_fine);
-  if (s->model.field_kind == MLMC_FIELD_CORRELATED)
+  const double nce = (double)n_ce_for(s, r.model, r.m_fine);
+  if (mdl.field_kind == MLMC_FIELD_CORRELATED)
     ce = d == 3 ? 16.0 * (nce * nce * m + nce * m * m) : 16.0 * nce * m;
   return (uint64_t)(cells * per_cell * (1.0 + ncomp / (double)(1 << d)) + ce);
 }
@@ -121,7 +127,8 @@ void worker_loop(mlmc_server* s, int wi) {
             batch.clear();
             bytes = 0;
             for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < maxb;) {
-              if (it->req.level == key.level && it->req.m_fine == key.m_fine &&
+              if (it->req.model == key.model && it->req.level == key.level &&
+                  it->req.m_fine == key.m_fine &&
                   (batch.empty() || s->in_flight_bytes + bytes + one <= budget)) {
                 batch.push_back(*it);
                 bytes += one;
@@ -141,8 +148,9 @@ void worker_loop(mlmc_server* s, int wi) {
     const double t_start = s->now();
     const int n = (int)batch.size();
     for (int q = 0; q < n; ++q) w.h_ids[q] = batch[q].req.sample;
-    mlmc_model mdl = s->model;
-    mdl.n_ce = n_ce_for(s, batch[0].req.m_fine);
+    const int mi = batch[0].req.model;
+    mlmc_model mdl = s->models[mi];
+    mdl.n_ce = n_ce_for(s, mi, batch[0].req.m_fine);
     mlmc_level_sums sums;
     std::memset(&sums, 0, sizeof sums);
     mlmc_status st = MLMC_OK;
@@ -151,7 +159,7 @@ void worker_loop(mlmc_server* s, int wi) {
       st = MLMC_EDEVICE;
     if (st == MLMC_OK)
       st = mlmc_level_run_ids(w.ctx, &mdl, batch[0].req.level, batch[0].req.m_fine, w.d_ids, n,
-                              s->opts.cgv, &s->opts.solver, &sums, w.d_out, w.d_out + maxb,
+                              s->opts.cgv, &s->solvers[mi], &sums, w.d_out, w.d_out + maxb,
                               w.d_out + 2 * maxb, w.d_flags, w.d_flags + maxb);
     if (st == MLMC_OK || st == MLMC_ENOCONV) {
       (void)hipMemcpyAsync(w.h_out, w.d_out, sizeof(double) * 3 * maxb, hipMemcpyDeviceToHost,
@@ -170,6 +178,7 @@ void worker_loop(mlmc_server* s, int wi) {
         r.level = batch[q].req.level;
         r.m_fine = batch[q].req.m_fine;
         r.sample = batch[q].req.sample;
+        r.model = mi;
         r.batch_size = n;
         r.t_submit = batch[q].t_submit;
         r.t_start = t_start;
@@ -225,16 +234,22 @@ mlmc_status mlmc_serve_opts_default(mlmc_serve_opts* o) {
   return mlmc_solver_opts_default(&o->solver);
 }
 
-mlmc_status mlmc_serve_start(const mlmc_model* model, const mlmc_serve_opts* opts,
-                             mlmc_server** out) {
-  if (!model || !opts || !out) return MLMC_EINVAL;
+mlmc_status mlmc_serve_start_models(const mlmc_model* models, const mlmc_solver_opts* solvers,
+                                    int n_models, const mlmc_serve_opts* opts, mlmc_server** out) {
+  if (!models || !opts || !out) return MLMC_EINVAL;
   *out = nullptr;
-  if (opts->n_workers < 1 || opts->n_workers > 16 || opts->max_batch < 1 ||
-      opts->n_grids < 0 || opts->n_grids > 8)
+  if (n_models < 1 || n_models > 8 || opts->n_workers < 1 || opts->n_workers > 16 ||
+      opts->max_batch < 1 || opts->n_grids < 0 || opts->n_grids > 8)
     return MLMC_EINVAL;
+  for (int q = 0; q < opts->n_grids; ++q)
+    if (opts->grid_model[q] < 0 || opts->grid_model[q] >= n_models) return MLMC_EINVAL;
+  for (int q = 0; q < n_models; ++q)
+    if (models[q].dim != 2 && models[q].dim != 3) return MLMC_EINVAL;
   mlmc_server* s = new mlmc_server();
   s->opts = *opts;
-  s->model = *model;
+  s->models.assign(models, models + n_models);
+  s->solvers.assign(n_models, opts->solver);
+  if (solvers) s->solvers.assign(solvers, solvers + n_models);
   s->workers.resize(opts->n_workers);
   if (hipSetDevice(opts->device) != hipSuccess) {
     delete s;
@@ -262,11 +277,18 @@ mlmc_status mlmc_serve_start(const mlmc_model* model, const mlmc_serve_opts* opt
   return MLMC_OK;
 }
 
+mlmc_status mlmc_serve_start(const mlmc_model* model, const mlmc_serve_opts* opts,
+                             mlmc_server** out) {
+  return mlmc_serve_start_models(model, nullptr, 1, opts, out);
+}
+
 mlmc_status mlmc_serve_submit(mlmc_server* s, const mlmc_request* req, uint64_t* id) {
   if (!s || !req) return MLMC_EINVAL;
+  if (req->model < 0 || req->model >= (int)s->models.size()) return MLMC_EINVAL;
   if (req->level < 0 || req->m_fine < 1 || (req->level > 0 && req->m_fine % 2))
     return MLMC_EINVAL;
-  if (s->model.field_kind == MLMC_FIELD_CORRELATED && n_ce_for(s, req->m_fine) == 0)
+  if (s->models[req->model].field_kind == MLMC_FIELD_CORRELATED &&
+      n_ce_for(s, req->model, req->m_fine) == 0)
     return MLMC_EINVAL;
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -50,6 +50,10 @@ int main(void) {
   P(mlmc_model, y_lo); P(mlmc_model, mu); P(mlmc_model, sigma2); P(mlmc_model, lambda);
   P(mlmc_model, seed); P(mlmc_solver_opts, maxit); P(mlmc_solver_opts, check_every); P(mlmc_solver_opts, gamma); P(mlmc_solver_opts, gamma_levels);
   P(mlmc_level_sums, sum_y); P(mlmc_level_sums, iters_coarse);
+  printf("mlmc_serve_opts %zu\nmlmc_request %zu\nmlmc_result %zu\n", sizeof(mlmc_serve_opts),
+         sizeof(mlmc_request), sizeof(mlmc_result));
+  P(mlmc_serve_opts, hbm_budget_bytes); P(mlmc_serve_opts, grid_model); P(mlmc_serve_opts, solver);
+  P(mlmc_request, model); P(mlmc_result, model); P(mlmc_result, q_f); P(mlmc_result, t_done);
   return 0;
 }
 """
@@ -75,6 +79,12 @@ def test_struct_layouts_match_header(lib, tmp_path):
     assert int(vals["mlmc_solver_opts.gamma"]) == lib.mlmc_solver_opts.gamma.offset
     assert int(vals["mlmc_solver_opts.gamma_levels"]) == lib.mlmc_solver_opts.gamma_levels.offset
     assert int(vals["mlmc_level_sums.iters_coarse"]) == lib.mlmc_level_sums.iters_coarse.offset
+    for st in ("mlmc_serve_opts", "mlmc_request", "mlmc_result"):
+        assert int(vals[st]) == ctypes.sizeof(getattr(lib, st)), st
+    for st, f in (("mlmc_serve_opts", "hbm_budget_bytes"), ("mlmc_serve_opts", "grid_model"),
+                  ("mlmc_serve_opts", "solver"), ("mlmc_request", "model"),
+                  ("mlmc_result", "model"), ("mlmc_result", "q_f"), ("mlmc_result", "t_done")):
+        assert int(vals["%s.%s" % (st, f)]) == getattr(getattr(lib, st), f).offset, (st, f)
 
 
 def test_solver_defaults(lib):

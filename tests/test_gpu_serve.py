@@ -6,6 +6,8 @@
 * A device-memory budget smaller than two requests serialises the batches
   (batch size 1, never two running) without failures.
 * Malformed requests are refused.
+* One server serves several models (2-D with an FP32 multigrid, 3-D in FP64):
+  each result equals the direct level run of its own model and options.
 """
 import time
 
@@ -127,3 +129,67 @@ def test_serve_rejects_bad_requests(lib):
             lib.mlmc_serve_submit(srv, 0, 48, 0)      # grid without an embedding size
     finally:
         lib.mlmc_serve_stop(srv)
+
+
+def test_serve_two_models_2d_fp32_and_3d(lib):
+    """One server for a 2-D model (multigrid in FP32 inside the FP64 CG) and the
+    3-D model (FP64): interleaved requests of both come back bitwise equal to
+    the direct level runs of their own model and options, and within 1e-10 of
+    the oracle."""
+    print("serve 2-D + 3-D", flush=True)
+    m3 = W.TILTED3
+    opts = lib.serve_opts_for_models([(MODEL, [32, 64]), (m3, [16, 32])], n_workers=3,
+                                     max_batch=8)
+    s2 = lib.mlmc_solver_opts_default(precision=lib.MLMC_PREC_FP32)
+    s3 = lib.mlmc_solver_opts_default()
+    srv = lib.mlmc_serve_start_models([MODEL, m3], opts, solvers=[s2, s3])
+    reqs = []
+    for i in range(6):
+        reqs += [(0, 32, 500 + i, 0), (1, 64, 600 + i, 0), (0, 16, 700 + i, 1)]
+        if i % 2 == 0:
+            reqs.append((1, 32, 800 + i, 1))
+    try:
+        with pytest.raises(lib.MlmcError):
+            lib.mlmc_serve_submit(srv, 0, 32, 0, model=2)      # no such model
+        with pytest.raises(lib.MlmcError):
+            lib.mlmc_serve_submit(srv, 0, 64, 0, model=1)      # 64 is not a 3-D grid here
+        ids = [lib.mlmc_serve_submit(srv, *r) for r in reqs]
+        got = drain(lib, srv, len(ids))
+    finally:
+        lib.mlmc_serve_stop(srv)
+    by_req = {r: got[i] for r, i in zip(reqs, ids)}
+    assert all(v["failed"] == 0 and v["status"] == 0 for v in by_req.values())
+    assert all(v["model"] == r[3] for r, v in by_req.items())
+    ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
+    try:
+        for model_i, model, sol in ((0, MODEL, s2), (1, m3, s3)):
+            for level in (0, 1):
+                rs = [r for r in reqs if r[3] == model_i and r[0] == level]
+                m = rs[0][1]
+                sid = torch.tensor([r[2] for r in rs], dtype=torch.int32, device="cuda:0")
+                qf = torch.empty(len(rs), dtype=torch.float64, device="cuda:0")
+                qc = torch.empty_like(qf)
+                lib.mlmc_level_run_ids(ctx, model, level, m, sid, len(rs), False, sol,
+                                       q_f=qf, q_c=qc)
+                torch.cuda.synchronize()
+                for q, r in enumerate(rs):
+                    assert qf[q].item() == by_req[r]["q_f"], r
+                    assert qc[q].item() == by_req[r]["q_c"], r
+    finally:
+        lib.mlmc_ctx_destroy(ctx)
+    for r in ((1, 64, 600, 0), (1, 32, 800, 1)):
+        level, m, sample, mi = r
+        model = (MODEL, m3)[mi]
+        k, kc = ofield.sample_k(model, level, sample, m, with_coarse=True)
+        qf_ref, qc_ref = omlmc.solve_qoi(k)[0], omlmc.solve_qoi(kc)[0]
+        assert abs(by_req[r]["q_f"] - qf_ref) <= 1e-10 * qf_ref, r
+        assert abs(by_req[r]["q_c"] - qc_ref) <= 1e-10 * qc_ref, r
+
+
+def test_serve_start_models_refusals(lib):
+    opts = lib.serve_opts_for_models([(MODEL, [32])])
+    opts.grid_model[0] = 1                                   # grid of a model not given
+    with pytest.raises(lib.MlmcError):
+        lib.mlmc_serve_start_models([MODEL], opts)
+    with pytest.raises(lib.MlmcError):
+        lib.mlmc_serve_start_models([], lib.serve_opts_for_models([(MODEL, [32])]))
