@@ -160,7 +160,7 @@ __device__ __forceinline__ C nsum_lds(const CellFaces<C>& f, const C* sz, int fr
 
 // down: pre-smoothing from z = 0 (red, then black) and the restricted residual.
 template <int TX, int TY, class S, bool TOP>
-__global__ void __launch_bounds__(kMgThreads)
+__global__ void __launch_bounds__(kMgThreads, 8)
 k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
             const VecT<S, TOP>* __restrict__ r, S* __restrict__ z, S* __restrict__ rc,
             const int32_t* __restrict__ active) {
@@ -179,8 +179,11 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const S* Ts = T + s * 2 * n;
   const S* tbs = tb + s * 2 * m;
   const VecT<S, TOP>* rs = r + s * n;
+  // z lives in LDS only; flags per slot: bit 0 a frame cell inside the domain,
+  // bit 1 inside the ring of the black sweep, bit 4 black, bit 5 on the tile.
   CellFaces<C> cf[K];
-  C rv[K], zv[K], di[K];
+  C rv[K], di[K];
+  unsigned fl[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
@@ -200,26 +203,25 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
     const int fj = f / W, fi = f - fj * W;
     adjacent_faces(cf[k], sz, sres, Ts, tbs, m, X0 - 2 + fi, Y0 - 2 + fj, f, fi, fj, W, f < F);
     di[k] = inv_diag(cf[k]);
+    unsigned b = (f < F && cf[k].in) ? 1u : 0u;
+    if (fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1) b |= 2u;
+    if ((fi + fj) & 1) b |= 16u;
+    if (fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) b |= 32u;
+    fl[k] = b;
   }
   __syncthreads();
   // red cells of the frame: z = r / D; black cells start at 0
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    zv[k] = ((fi + fj) & 1) == 0 ? rv[k] * di[k] : C(0);
-    if (f < F) sz[f] = zv[k];
+    if (f < F) sz[f] = (fl[k] & 16u) ? C(0) : rv[k] * di[k];
   }
   __syncthreads();
   // black cells of R1
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && cf[k].in && fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1 && ((fi + fj) & 1)) {
-      zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-      sz[f] = zv[k];
-    }
+    if ((fl[k] & 19u) == 19u) sz[f] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
   }
   __syncthreads();
   // store the tile; residual of its red cells (black residuals vanish)
@@ -227,10 +229,10 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) {
-      Prec<S>::st(zs, cf[k].c, zv[k]);
-      if (((fi + fj) & 1) == 0) sres[f] = nsum_lds(cf[k], sz, f, W);
+    if (fl[k] & 32u) {
+      const int fj = f / W, fi = f - fj * W;
+      Prec<S>::st(zs, (long long)(Y0 - 2 + fj) * m + (X0 - 2 + fi), sz[f]);
+      if (!(fl[k] & 16u)) sres[f] = nsum_lds(cf[k], sz, f, W);
     }
   }
   __syncthreads();
@@ -254,7 +256,7 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
 // sweep one cell out, that sweep the red sweep two cells out, that one the
 // first black sweep three cells out, which needs z four cells out.
 template <int TX, int TY, class S, bool TOP>
-__global__ void __launch_bounds__(kMidThreads)
+__global__ void __launch_bounds__(kMidThreads, 8)
 k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
            const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre, S* __restrict__ z,
            const S* __restrict__ zc, double omega, S* __restrict__ rc,
@@ -264,6 +266,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   constexpr int W = G::W, H = G::H, F = G::F, K = (F + kMidThreads - 1) / kMidThreads;
   __shared__ C sz[F];
   __shared__ C sres[F];
+  __shared__ C ste[F];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -277,8 +280,17 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const S* zps = zpre + s * n;
   const S* zcs = zc + s * (long long)mc * mc;
   const C om = (C)omega;
+  // z of the frame lives in LDS only (sz, written as soon as it is loaded; the
+  // east / north faces are exchanged through ste / sres); registers hold each
+  // cell's faces, reciprocal diagonal and right-hand side, which keeps the
+  // kernel within 64 VGPRs: two workgroups per CU, so one's loads overlap the
+  // other's sweeps.
+  // Per slot, one word of flags: bit 0 a frame cell inside the domain, bits 1-3
+  // inside the rings swept by the three passes (R3, R2, R1), bit 4 black, bit 5
+  // on the tile.
   CellFaces<C> cf[K];
-  C rv[K], zv[K], di[K];
+  C rv[K], di[K];
+  unsigned fl[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMidThreads;
@@ -289,9 +301,9 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
     const C rr = (C)ldv(r + s * n, cf[k].c);
     const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
     rv[k] = cf[k].in ? rr : C(0);
-    zv[k] = cf[k].in ? zp + om * zcv : C(0);
     if (f < F) {
-      sz[f] = cf[k].te;
+      sz[f] = cf[k].in ? zp + om * zcv : C(0);
+      ste[f] = cf[k].te;
       sres[f] = cf[k].tn;
     }
   }
@@ -300,29 +312,26 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMidThreads;
     const int fj = f / W, fi = f - fj * W;
-    adjacent_faces(cf[k], sz, sres, Ts, tbs, m, X0 - 4 + fi, Y0 - 4 + fj, f, fi, fj, W, f < F);
+    adjacent_faces(cf[k], ste, sres, Ts, tbs, m, X0 - 4 + fi, Y0 - 4 + fj, f, fi, fj, W, f < F);
     di[k] = inv_diag(cf[k]);
-  }
-  __syncthreads();
+    unsigned b = (f < F && cf[k].in) ? 1u : 0u;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMidThreads;
-    if (f < F) sz[f] = zv[k];
+    for (int d = 3; d >= 1; --d)
+      if (fi >= 4 - d && fi < W - 4 + d && fj >= 4 - d && fj < H - 4 + d) b |= 2u << (3 - d);
+    if ((fi + fj) & 1) b |= 16u;
+    if (fi >= 4 && fi < 4 + TX && fj >= 4 && fj < 4 + TY) b |= 32u;
+    fl[k] = b;
   }
   __syncthreads();
   // black on R3, red on R2, black on R1
 #pragma unroll
   for (int pass = 0; pass < 3; ++pass) {
-    const int d = 3 - pass, col = (pass == 1) ? 0 : 1;
+    const unsigned want = 1u | (2u << pass) | (pass == 1 ? 0u : 16u);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int f = threadIdx.x + k * kMidThreads;
-      const int fj = f / W, fi = f - fj * W;
-      if (f < F && cf[k].in && fi >= 4 - d && fi < W - 4 + d && fj >= 4 - d && fj < H - 4 + d &&
-          ((fi + fj) & 1) == col) {
-        zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-        sz[f] = zv[k];
-      }
+      if ((fl[k] & (17u | (2u << pass))) == want)
+        sz[f] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
     }
     __syncthreads();
   }
@@ -331,12 +340,13 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMidThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && fi >= 4 && fi < 4 + TX && fj >= 4 && fj < 4 + TY) {
-      Prec<S>::st(zs, cf[k].c, zv[k]);
-      if (((fi + fj) & 1) == 0) {
+    if (fl[k] & 32u) {
+      const int fj = f / W, fi = f - fj * W;
+      const C zf = sz[f];
+      Prec<S>::st(zs, (long long)(Y0 - 4 + fj) * m + (X0 - 4 + fi), zf);
+      if (!(fl[k] & 16u)) {
         const C dd = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-        sres[f] = rv[k] - dd * zv[k] + nsum_lds(cf[k], sz, f, W);
+        sres[f] = rv[k] - dd * zf + nsum_lds(cf[k], sz, f, W);
       }
     }
   }
@@ -353,7 +363,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
 // up: z = z_in + omega P e, post-smoothing (black, then red) and, on the finest
 // level, the per-tile partial of r^T z.
 template <int TX, int TY, class S, bool TOP>
-__global__ void __launch_bounds__(kMgThreads)
+__global__ void __launch_bounds__(kMgThreads, 8)
 k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
           const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre,
           VecT<S, TOP>* __restrict__ z, const S* __restrict__ zc, double omega,
@@ -363,6 +373,7 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
   __shared__ C sz[F];
   __shared__ C sn[F];
+  __shared__ C se[F];
   __shared__ double red[kMgThreads / kWave];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -378,9 +389,14 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const S* zps = zpre + s * n;
   const S* zcs = zc + s * (long long)mc * mc;
   const C om = (C)omega;
+  // z lives in LDS only (written as soon as it is loaded; east / north faces
+  // are exchanged through se / sn); flags per slot: bit 0 a frame cell inside
+  // the domain, bit 1 inside the ring of the black sweep, bit 4 black, bit 5 on
+  // the tile.
   CellFaces<C> cf[K];
-  C rv[K], zv[K], di[K];
+  C rv[K], di[K];
   double rd[K];  // FP64 residual for the r^T z sum (finest level only)
+  unsigned fl[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
@@ -392,9 +408,9 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
     const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
     rd[k] = cf[k].in ? rr : 0.0;
     rv[k] = (C)rd[k];
-    zv[k] = cf[k].in ? zp + om * zcv : C(0);
     if (f < F) {
-      sz[f] = cf[k].te;
+      sz[f] = cf[k].in ? zp + om * zcv : C(0);
+      se[f] = cf[k].te;
       sn[f] = cf[k].tn;
     }
   }
@@ -403,25 +419,20 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
     const int fj = f / W, fi = f - fj * W;
-    adjacent_faces(cf[k], sz, sn, Ts, tbs, m, X0 - 2 + fi, Y0 - 2 + fj, f, fi, fj, W, f < F);
+    adjacent_faces(cf[k], se, sn, Ts, tbs, m, X0 - 2 + fi, Y0 - 2 + fj, f, fi, fj, W, f < F);
     di[k] = inv_diag(cf[k]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if (f < F) sz[f] = zv[k];
+    unsigned b = (f < F && cf[k].in) ? 1u : 0u;
+    if (fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1) b |= 2u;
+    if ((fi + fj) & 1) b |= 16u;
+    if (fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) b |= 32u;
+    fl[k] = b;
   }
   __syncthreads();
   // black sweep on R1
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && cf[k].in && fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1 && ((fi + fj) & 1)) {
-      zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-      sz[f] = zv[k];
-    }
+    if ((fl[k] & 19u) == 19u) sz[f] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
   }
   __syncthreads();
   // red sweep on the tile, store, r^T z
@@ -430,11 +441,11 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    if (f < F && fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) {
-      if (((fi + fj) & 1) == 0) zv[k] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-      Prec<VecT<S, TOP>>::st(zs, cf[k].c, zv[k]);
-      if (TOP) acc += rd[k] * (double)zv[k];
+    if (fl[k] & 32u) {
+      const int fj = f / W, fi = f - fj * W;
+      const C zf = (fl[k] & 16u) ? sz[f] : (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
+      Prec<VecT<S, TOP>>::st(zs, (long long)(Y0 - 2 + fj) * m + (X0 - 2 + fi), zf);
+      if (TOP) acc += rd[k] * (double)zf;
     }
   }
   if (TOP && rz_partial) {

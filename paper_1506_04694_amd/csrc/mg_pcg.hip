@@ -445,19 +445,53 @@ void launch_true_residual(hipStream_t st, int m, int batch, const double* T, con
 }
 
 // ------------------------------------------------------------------ per-sample scalars
-__device__ __forceinline__ double sum_partials(const double* __restrict__ partial, int bps,
-                                               int s) {
+// A sample's scalars come from its partial sums.  With few partials per sample
+// (small grids, large batches) one thread per sample adds them in order; with
+// many (kWideSum or more: large grids, few samples) one wave per sample does:
+// lane l adds partials l, l + 64, ... in order and a fixed shuffle tree adds the
+// lanes (result in lane 0).  The form depends only on the partial count, so a
+// sample's scalars depend only on its own partials.  Both forms run kBlock
+// threads per workgroup.
+constexpr int kWideSum = 16;
+
+template <bool WIDE>
+__device__ __forceinline__ double sum_partials_t(const double* __restrict__ partial, int bps,
+                                                 int s, int lane) {
   double acc = 0.0;
+  if (WIDE) {
+    for (int q = lane; q < bps; q += kWave) acc += partial[(long long)s * bps + q];
+    return wave_sum(acc);
+  }
   for (int q = 0; q < bps; ++q) acc += partial[(long long)s * bps + q];
   return acc;
 }
 
+#define SC_PROLOGUE                                                                         \
+  const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;                  \
+  const int s = (int)(WIDE ? gtid / kWave : gtid);                                         \
+  const int lane = WIDE ? (int)(threadIdx.x & (kWave - 1)) : 0;
+
+static inline dim3 sc_grid(int batch, bool wide) {
+  const long long threads = (long long)batch * (wide ? kWave : 1);
+  return dim3((unsigned)((threads + kBlock - 1) / kBlock));
+}
+
+#define SC_LAUNCH(kern, batch, bps, ...)                                                   \
+  do {                                                                                     \
+    if ((bps) >= kWideSum)                                                                 \
+      hipLaunchKernelGGL(kern<true>, sc_grid(batch, true), dim3(kBlock), 0, __VA_ARGS__);  \
+    else                                                                                   \
+      hipLaunchKernelGGL(kern<false>, sc_grid(batch, false), dim3(kBlock), 0, __VA_ARGS__); \
+  } while (0)
+
+template <bool WIDE>
 __global__ void k_sc_init(int batch, const double* __restrict__ partial, int bps, SolverState S,
                           int32_t* __restrict__ status, int32_t* __restrict__ iters,
                           double* __restrict__ relres, int restart) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  SC_PROLOGUE
   if (s >= batch || (restart && !S.active[s])) return;
-  const double v = sum_partials(partial, bps, s);
+  const double v = sum_partials_t<WIDE>(partial, bps, s, lane);
+  if (lane != 0) return;
   S.r0sq[s] = v;
   iters[s] = 0;
   relres[s] = 0.0;
@@ -472,8 +506,7 @@ __global__ void k_sc_init(int batch, const double* __restrict__ partial, int bps
 
 void launch_sc_init(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
                     int32_t* status, int32_t* iters, double* relres, int restart) {
-  hipLaunchKernelGGL(k_sc_init, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial, bps,
-                     s, status, iters, relres, restart);
+  SC_LAUNCH(k_sc_init, batch, bps, st, batch, partial, bps, s, status, iters, relres, restart);
 }
 
 // Marks the samples whose iteration broke down for a second pass (active = 1),
@@ -510,38 +543,39 @@ void launch_iters_add(hipStream_t st, int batch, int32_t* iters, const int32_t* 
                      carried);
 }
 
+template <bool WIDE>
 __global__ void k_sc_rho(int batch, const double* __restrict__ partial, int nparts,
                          SolverState S, int32_t* __restrict__ status, int first,
                          const double* __restrict__ partial2, int nparts2) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  SC_PROLOGUE
   if (s >= batch || !S.active[s]) return;
-  const double v = sum_partials(partial, nparts, s);
+  const double v = sum_partials_t<WIDE>(partial, nparts, s, lane);
+  const double rzold =
+      (!first && partial2) ? sum_partials_t<WIDE>(partial2, nparts2, s, lane) : 0.0;
+  if (lane != 0) return;
   if (!(v > 0.0) || !isfinite(v)) {
     S.active[s] = 0;
     status[s] = MLMC_SAMPLE_BREAKDOWN;
     return;
   }
-  if (first) {
-    S.beta[s] = 0.0;
-  } else {
-    const double rzold = partial2 ? sum_partials(partial2, nparts2, s) : 0.0;
-    S.beta[s] = (v - rzold) / S.rho[s];
-  }
+  S.beta[s] = first ? 0.0 : (v - rzold) / S.rho[s];
   S.rho[s] = v;
 }
 
 void launch_sc_rho(hipStream_t st, int batch, const double* partial, int nparts, SolverState s,
                    int32_t* status, int first, const double* partial2, int nparts2) {
-  hipLaunchKernelGGL(k_sc_rho, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial,
-                     nparts, s, status, first, partial2, nparts2);
+  SC_LAUNCH(k_sc_rho, batch, std::max(nparts, partial2 ? nparts2 : 0), st, batch, partial, nparts,
+            s, status, first, partial2, nparts2);
 }
 
+template <bool WIDE>
 __global__ void k_sc_alpha(int batch, const double* __restrict__ partial, int bps, SolverState S,
                            int32_t* __restrict__ status) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) *S.count = 0;
+  SC_PROLOGUE
+  if (blockIdx.x == 0 && threadIdx.x == 0) *S.count = 0;
   if (s >= batch || !S.active[s]) return;
-  const double v = sum_partials(partial, bps, s);
+  const double v = sum_partials_t<WIDE>(partial, bps, s, lane);
+  if (lane != 0) return;
   if (!(v > 0.0) || !isfinite(v)) {
     S.active[s] = 0;
     status[s] = MLMC_SAMPLE_BREAKDOWN;
@@ -552,16 +586,17 @@ __global__ void k_sc_alpha(int batch, const double* __restrict__ partial, int bp
 
 void launch_sc_alpha(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
                      int32_t* status) {
-  hipLaunchKernelGGL(k_sc_alpha, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial,
-                     bps, s, status);
+  SC_LAUNCH(k_sc_alpha, batch, bps, st, batch, partial, bps, s, status);
 }
 
+template <bool WIDE>
 __global__ void k_sc_conv(int batch, const double* __restrict__ partial, int bps, SolverState S,
                           int32_t* __restrict__ status, int32_t* __restrict__ iters,
                           double* __restrict__ relres, double tol, int maxit) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  SC_PROLOGUE
   if (s >= batch || !S.active[s]) return;
-  const double v = sum_partials(partial, bps, s);
+  const double v = sum_partials_t<WIDE>(partial, bps, s, lane);
+  if (lane != 0) return;
   const int it = iters[s] + 1;
   iters[s] = it;
   const double rr = sqrt(v / S.r0sq[s]);
@@ -582,23 +617,23 @@ __global__ void k_sc_conv(int batch, const double* __restrict__ partial, int bps
 
 void launch_sc_conv(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
                     int32_t* status, int32_t* iters, double* relres, double tol, int maxit) {
-  hipLaunchKernelGGL(k_sc_conv, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial, bps,
-                     s, status, iters, relres, tol, maxit);
+  SC_LAUNCH(k_sc_conv, batch, bps, st, batch, partial, bps, s, status, iters, relres, tol, maxit);
 }
 
+template <bool WIDE>
 __global__ void k_sc_final(int batch, const double* __restrict__ partial, int bps, SolverState S,
                            double* __restrict__ relres) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  SC_PROLOGUE
   if (s >= batch) return;
-  const double v = sum_partials(partial, bps, s);
+  const double v = sum_partials_t<WIDE>(partial, bps, s, lane);
+  if (lane != 0) return;
   const double r0 = S.r0sq[s];
   relres[s] = r0 > 0.0 ? sqrt(v / r0) : 0.0;
 }
 
 void launch_sc_final(hipStream_t st, int batch, const double* partial, int bps, SolverState s,
                      double* relres) {
-  hipLaunchKernelGGL(k_sc_final, dim3(blocks_for(batch)), dim3(kBlock), 0, st, batch, partial,
-                     bps, s, relres);
+  SC_LAUNCH(k_sc_final, batch, bps, st, batch, partial, bps, s, relres);
 }
 
 }  // namespace mlmc
