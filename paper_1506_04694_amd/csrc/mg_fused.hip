@@ -966,6 +966,7 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0
 // smoothing levels (the coarsest, solved with its dense inverse, is level NL).
 constexpr int kCcThreads = 512;
 constexpr int kCcMaxSmooth = 5;
+constexpr int kCcLdsInv = 16;
 
 struct CcCell {
   double te, tw, tn, ts, di, r, z;
@@ -1035,6 +1036,69 @@ __device__ __forceinline__ void cc_prolong(CcCell& c, double* z, const double* z
   }
 }
 
+// The levels below l0 keep their cells' faces, reciprocal diagonal and
+// right-hand side in LDS (six arrays of m_l^2 words per level); thread t owns
+// cell t of such a level.  Same arithmetic, in the same order, as a CcCell.
+struct CcLds {
+  double *te, *tw, *tn, *ts, *di, *r;
+};
+
+__device__ __forceinline__ CcLds ccl_at(double* base, int n) {
+  return CcLds{base, base + n, base + 2 * n, base + 3 * n, base + 4 * n, base + 5 * n};
+}
+
+template <class S>
+__device__ __forceinline__ void ccl_load(const CcLds& a, const S* __restrict__ Ts,
+                                         const S* __restrict__ tbs, int m, int t) {
+  const int n = m * m;
+  if (t >= n) return;
+  const int j = t / m, i = t - j * m;
+  const double te = (double)ldv(Ts, t), tn = (double)ldv(Ts, n + t);
+  const double tw = (double)(i > 0 ? ldv(Ts, t - 1) : ldv(tbs, j));
+  const double ts = (double)(j > 0 ? ldv(Ts, n + t - m) : ldv(tbs, m + i));
+  a.te[t] = te;
+  a.tw[t] = tw;
+  a.tn[t] = tn;
+  a.ts[t] = ts;
+  a.di[t] = 1.0 / (te + tw + tn + ts);
+  a.r[t] = 0.0;
+}
+
+__device__ __forceinline__ double ccl_nsum(const CcLds& a, const double* z, int t, int f, int P) {
+  return a.te[t] * z[f + 1] + a.tw[t] * z[f - 1] + a.tn[t] * z[f + P] + a.ts[t] * z[f - P];
+}
+
+__device__ __forceinline__ void ccl_smooth(const CcLds& a, double* z, int m, int t, bool red,
+                                           bool zero) {
+  if (t < m * m) {
+    const int j = t / m, i = t - j * m;
+    if ((((i + j) & 1) == 0) == red) {
+      const int P = m + 2, f = pidx(P, i, j);
+      z[f] = zero ? a.r[t] * a.di[t] : (a.r[t] + ccl_nsum(a, z, t, f, P)) * a.di[t];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void ccl_residual(const CcLds& a, const double* z, int m, int t,
+                                             double* sres) {
+  if (t < m * m) {
+    const int j = t / m, i = t - j * m;
+    if (((i + j) & 1) == 0) {
+      const int P = m + 2, f = pidx(P, i, j);
+      sres[t] = a.r[t] - (a.te[t] + a.tw[t] + a.tn[t] + a.ts[t]) * z[f] + ccl_nsum(a, z, t, f, P);
+    }
+  }
+}
+
+__device__ __forceinline__ void ccl_prolong(double* z, const double* zc, int m, int Pc, int t,
+                                            double omega) {
+  if (t < m * m) {
+    const int j = t / m, i = t - j * m;
+    z[pidx(m + 2, i, j)] += omega * zc[pidx(Pc, i >> 1, j >> 1)];
+  }
+}
+
 // W0: level l0 takes two coarse visits (W), the levels below one (V).
 template <class S, bool TOP, int NL, bool W0>
 __global__ void __launch_bounds__(kCcThreads)
@@ -1054,10 +1118,28 @@ k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>
   }
   double* sres = lds + off;                        // m0^2 residuals of the level being restricted
   double* vec = sres + desc.m[0] * desc.m[0];      // coarsest right-hand side
+  CcLds cl[NL > 1 ? NL - 1 : 1];                   // levels 1 .. NL - 1, after vec
+  const int nLc = desc.m[NL] * desc.m[NL];
+  // the coarsest inverse is staged in LDS when it is small (<= kCcLdsInv
+  // unknowns): its global loads then overlap the set-up instead of lying on
+  // the cycle's critical path at every visit
+  const double* Ag = Ainv + (long long)s * nLc * nLc;
+  const double* A = Ag;
+  {
+    double* p = vec + nLc;
+#pragma unroll
+    for (int l = 1; l < NL; ++l) {
+      cl[l - 1] = ccl_at(p, desc.m[l] * desc.m[l]);
+      p += 6 * desc.m[l] * desc.m[l];
+    }
+    if (nLc <= kCcLdsInv) {
+      for (int q = t; q < nLc * nLc; q += kCcThreads) p[q] = Ag[q];
+      A = p;
+    }
+  }
   for (int q = t; q < off; q += kCcThreads) lds[q] = 0.0;
-  // level l0: two slots; coarser smoothing levels: one
+  // level l0: two slots per thread, in registers
   CcCell c0[2];
-  CcCell cl[NL > 1 ? NL - 1 : 1];
   const int m0 = desc.m[0];
   const long long n0 = (long long)m0 * m0;
   {
@@ -1074,8 +1156,8 @@ k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>
   for (int l = 1; l < NL; ++l) {
     const int m = desc.m[l];
     const long long n = (long long)m * m;
-    cc_load(cl[l - 1], static_cast<const S*>(desc.T[l]) + (long long)s * 2 * n,
-            static_cast<const S*>(desc.tb[l]) + (long long)s * 2 * m, m, t);
+    ccl_load(cl[l - 1], static_cast<const S*>(desc.T[l]) + (long long)s * 2 * n,
+             static_cast<const S*>(desc.tb[l]) + (long long)s * 2 * m, m, t);
   }
   __syncthreads();
   const int mL = desc.m[NL], nL = mL * mL;
@@ -1085,7 +1167,6 @@ k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>
     __syncthreads();
     double acc = 0.0;
     if (t < nL) {
-      const double* A = Ainv + (long long)s * nL * nL;
       for (int p = 0; p < nL; ++p) acc += A[t * nL + p] * vec[p];
       Prec<VecT<S, TOP>>::st(z0, (long long)s * nL + t, acc);
       acc *= vec[t];
@@ -1110,7 +1191,7 @@ k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>
     if (l + 1 < NL) {
 #pragma unroll
       for (int q = 1; q < NL; ++q)
-        if (q == l + 1) cl[q - 1].r = rc;
+        if (q == l + 1 && t < desc.m[q] * desc.m[q]) cl[q - 1].r[t] = rc;
     } else if (t < nL) {
       vec[t] = rc;
     }
@@ -1142,12 +1223,12 @@ k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>
     // ---- V-cycle on levels 1 .. NL - 1 from z = 0
 #pragma unroll
     for (int l = 1; l < NL; ++l) {
-      const int P = desc.m[l] + 2;
+      const int m = desc.m[l];
       double* z = lds + zoff[l];
-      CcCell& c = cl[l - 1];
-      cc_smooth<1>(&c, z, P, true, true);
-      cc_smooth<1>(&c, z, P, false, false);
-      cc_residual(c, z, P, sres);
+      const CcLds& c = cl[l - 1];
+      ccl_smooth(c, z, m, t, true, true);
+      ccl_smooth(c, z, m, t, false, false);
+      ccl_residual(c, z, m, t, sres);
       __syncthreads();
       hand_down(l);
     }
@@ -1155,7 +1236,6 @@ k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>
     {
       double* z = lds + zoff[NL];
       if (t < nL) {
-        const double* A = Ainv + (long long)s * nL * nL;
         double acc = 0.0;
         for (int p = 0; p < nL; ++p) acc += A[t * nL + p] * vec[p];
         z[pidx(mL + 2, t % mL, t / mL)] = acc;
@@ -1164,13 +1244,13 @@ k_mg_coarse_v(CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0, VecT<S, TOP>
     }
 #pragma unroll
     for (int l = NL - 1; l >= 1; --l) {
-      const int m = desc.m[l], P = m + 2, Pc = desc.m[l + 1] + 2;
+      const int m = desc.m[l], Pc = desc.m[l + 1] + 2;
       double* z = lds + zoff[l];
-      CcCell& c = cl[l - 1];
-      cc_prolong(c, z, lds + zoff[l + 1], m, Pc, omega);
+      const CcLds& c = cl[l - 1];
+      ccl_prolong(z, lds + zoff[l + 1], m, Pc, t, omega);
       __syncthreads();
-      cc_smooth<1>(&c, z, P, false, false);
-      cc_smooth<1>(&c, z, P, true, false);
+      ccl_smooth(c, z, m, t, false, false);
+      ccl_smooth(c, z, m, t, true, false);
     }
     // ---- level l0: correction and post-smoothing (black, red)
     {
@@ -1330,6 +1410,9 @@ static void coarse_v_impl(hipStream_t st, int batch, const CoarseDesc& desc, con
   size_t words = 0;
   for (int l = 0; l <= NL; ++l) words += (size_t)(desc.m[l] + 2) * (desc.m[l] + 2);
   words += (size_t)desc.m[0] * desc.m[0] + (size_t)desc.m[NL] * desc.m[NL];
+  for (int l = 1; l < NL; ++l) words += 6 * (size_t)desc.m[l] * desc.m[l];
+  const size_t nLc = (size_t)desc.m[NL] * desc.m[NL];
+  if (nLc <= (size_t)kCcLdsInv) words += nLc * nLc;
   hipLaunchKernelGGL((k_mg_coarse_v<S, TOP, NL, W0>), dim3(batch), dim3(kCcThreads),
                      words * sizeof(double), st, desc, (const R*)r0, (R*)z0, Ainv, omega, active,
                      rz_partial);
