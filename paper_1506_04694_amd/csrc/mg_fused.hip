@@ -73,6 +73,17 @@ __device__ __forceinline__ typename Prec<V>::C ldv(const V* p, long long i) {
   return Prec<V>::ld(p, i);
 }
 
+// Load element i (< 2^32 / sizeof(V)) of a per-sample array whose base is
+// uniform across the workgroup: the byte offset is an unsigned 32-bit value,
+// so the load takes the base from scalar registers and one VGPR of offset
+// instead of a 64-bit VGPR address.
+template <class V>
+__device__ __forceinline__ typename Prec<V>::C ldo(const V* p, unsigned i) {
+  const V* q = reinterpret_cast<const V*>(reinterpret_cast<const char*>(p) +
+                                          (size_t)(i * (unsigned)sizeof(V)));
+  return Prec<V>::ld(q, 0);
+}
+
 // ------------------------------------------------------------------ fixed-tile kernels
 // Tiles of compile-time size TX x TY (used when TX and TY divide m).  Each of
 // the 512 threads owns the frame cells f = tid + 512 k in every phase and
@@ -123,7 +134,7 @@ __device__ __forceinline__ CellFaces<typename Prec<S>::C> own_faces(const S* __r
   const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
   v.c = jc * m + ic;
   v.in = i >= 0 && i < m && j >= 0 && j < m;
-  const C te = ldv(Ts, v.c), tn = ldv(Ts, m * m + v.c);
+  const C te = ldo(Ts, (unsigned)v.c), tn = ldo(Ts, (unsigned)(m * m + v.c));
   v.te = v.in ? te : C(0);
   v.tn = v.in ? tn : C(0);
   v.tw = C(0);
@@ -285,12 +296,13 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   // cell's faces, reciprocal diagonal and right-hand side, which keeps the
   // kernel within 64 VGPRs: two workgroups per CU, so one's loads overlap the
   // other's sweeps.
-  // Per slot, one word of flags: bit 0 a frame cell inside the domain, bits 1-3
-  // inside the rings swept by the three passes (R3, R2, R1), bit 4 black, bit 5
-  // on the tile.
+  // Per slot, one byte of flags (byte k of fl for slot k): bit 0 a frame cell
+  // inside the domain, bits 1-3 inside the rings swept by the three passes (R3,
+  // R2, R1), bit 4 black, bit 5 on the tile.
   CellFaces<C> cf[K];
   C rv[K], di[K];
-  unsigned fl[K];
+  static_assert(K <= 4, "one flag byte per slot");
+  unsigned fl = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int f = threadIdx.x + k * kMidThreads;
@@ -298,8 +310,8 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
     const int i = X0 - 4 + fi, j = Y0 - 4 + fj;
     cf[k] = own_faces(Ts, m, i, j);
     const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
-    const C rr = (C)ldv(r + s * n, cf[k].c);
-    const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
+    const C rr = (C)ldo(r + s * n, (unsigned)cf[k].c);
+    const C zp = ldo(zps, (unsigned)cf[k].c), zcv = ldo(zcs, (unsigned)((jc >> 1) * mc + (ic >> 1)));
     rv[k] = cf[k].in ? rr : C(0);
     if (f < F) {
       sz[f] = cf[k].in ? zp + om * zcv : C(0);
@@ -320,7 +332,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
       if (fi >= 4 - d && fi < W - 4 + d && fj >= 4 - d && fj < H - 4 + d) b |= 2u << (3 - d);
     if ((fi + fj) & 1) b |= 16u;
     if (fi >= 4 && fi < 4 + TX && fj >= 4 && fj < 4 + TY) b |= 32u;
-    fl[k] = b;
+    fl |= b << (8 * k);
   }
   __syncthreads();
   // black on R3, red on R2, black on R1
@@ -330,7 +342,7 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int f = threadIdx.x + k * kMidThreads;
-      if ((fl[k] & (17u | (2u << pass))) == want)
+      if (((fl >> (8 * k)) & (17u | (2u << pass))) == want)
         sz[f] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
     }
     __syncthreads();
@@ -339,12 +351,15 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   S* zs = z + s * n;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMidThreads;
-    if (fl[k] & 32u) {
+    int f = threadIdx.x + k * kMidThreads;
+    // recomputed here rather than kept from the start (an empty asm makes the
+    // index opaque), which keeps the kernel within 64 VGPRs without a spill
+    asm volatile("" : "+v"(f));
+    if ((fl >> (8 * k)) & 32u) {
       const int fj = f / W, fi = f - fj * W;
       const C zf = sz[f];
       Prec<S>::st(zs, (long long)(Y0 - 4 + fj) * m + (X0 - 4 + fi), zf);
-      if (!(fl[k] & 16u)) {
+      if (!((fl >> (8 * k)) & 16u)) {
         const C dd = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
         sres[f] = rv[k] - dd * zf + nsum_lds(cf[k], sz, f, W);
       }
