@@ -221,10 +221,12 @@ def copy_calibration():
 
 
 def path_variants(lib, torch, wl, ctx, opts, args):
-    """Two other forms of the same step, timed over args.steps steps each after the
+    """Other forms of the same step, timed over args.steps steps each after the
     main measurement (not part of `value`):
     * all levels in one call (mlmc_run_levels: one solve per distinct grid, level
-      l's fine samples merged with level l+1's companions), FP64;
+      l's fine samples merged with level l+1's companions), FP64, with eager
+      launches and with the PCG iterations replayed from captured HIP graphs;
+    * the per-level step with graph-replayed iterations;
     * the per-level step with the multigrid hierarchy stored in FP32 inside the FP64
       flexible CG, with the largest relative QoI difference to the FP64 solve of
       the same samples."""
@@ -251,7 +253,15 @@ def path_variants(lib, torch, wl, ctx, opts, args):
             kw = {} if q is None else {"q_f": q[level][0], "q_c": q[level][1]}
             lib.mlmc_level_run(ctx, wl.model, level, m, idx * n, n, wl.cgv, o, **kw)
 
+    og = lib.mlmc_solver_opts_default(graph=1)
+
+    def merged_graph(idx):
+        lib.mlmc_run_levels(ctx, wl.model, wl.m_levels, [idx * n for n in wl.n_samples],
+                            wl.n_samples, wl.cgv, og)
+
     t_merged = timed(merged)
+    t_merged_graph = timed(merged_graph)
+    t_graph = timed(lambda idx: per_level(og, idx))
     t_fp32 = timed(lambda idx: per_level(o32, idx))
     qs = []
     for o in (opts, o32):
@@ -267,6 +277,9 @@ def path_variants(lib, torch, wl, ctx, opts, args):
             dev = max(dev, ((a - b).abs() / a.abs()).max().item())
     total = sum(wl.n_samples)
     return {"all_levels_one_call_fp64": {"value": total / t_merged, "ms_per_step": 1e3 * t_merged},
+            "all_levels_one_call_fp64_graph": {"value": total / t_merged_graph,
+                                               "ms_per_step": 1e3 * t_merged_graph},
+            "per_level_fp64_graph": {"value": total / t_graph, "ms_per_step": 1e3 * t_graph},
             "multigrid_fp32_in_fp64_cg": {"value": total / t_fp32, "ms_per_step": 1e3 * t_fp32,
                                           "max_qoi_rel_diff_vs_fp64": dev}}
 

@@ -132,8 +132,10 @@ typedef struct mlmc_solver_opts {
                            (default 4); the coarsest grid (<= 8 x 8) is solved by
                            dense Cholesky                                           */
   int32_t check_every;  /* iterations between host checks of the active count      */
-  int32_t variant;      /* 0: fused LDS-tiled V-cycle kernels (needs nu1 = nu2 = 1,
-                           else falls back to 1); 1: one launch per sweep / step     */
+  int32_t variant;      /* 0: fused LDS-tiled cycle kernels, and for 64 x 64 FP64
+                           the whole solve of a sample in one workgroup (needs
+                           nu1 = nu2 = 1, else falls back to 1); 1: one launch
+                           per sweep / step; 2: the tiled kernels on every grid */
   int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1   */
   int32_t cycle_max;    /* variant 0: levels of at most this size (2..32, 0 = 32) run
                            in one workgroup per sample                              */
@@ -142,6 +144,12 @@ typedef struct mlmc_solver_opts {
                            re-smooths the level before restricting again        */
   int32_t gamma_levels; /* number of finest levels taking gamma visits, the
                            coarser ones take one (default 2; 0 = every level)  */
+  int32_t graph;        /* 1: after the first host check, run the 2-D fused
+                           iteration as replays of a captured HIP graph of
+                           check_every iterations (even check_every; cached per
+                           context and configuration; bitwise the same results;
+                           not while a kernel is being profiled); default 0 */
+  int32_t reserved;
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */

@@ -52,7 +52,8 @@ class mlmc_solver_opts(ctypes.Structure):
                 ("coarse_max", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("cycle_max", ctypes.c_int32), ("gamma", ctypes.c_int32),
-                ("gamma_levels", ctypes.c_int32)]
+                ("gamma_levels", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class mlmc_level_sums(ctypes.Structure):

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmlmc_darcy.so")
-SOURCES = ["field.hip", "fv.hip", "mg_pcg.hip", "mg_fused.hip", "d3.hip", "api.hip", "serve.hip"]
+SOURCES = ["field.hip", "fv.hip", "mg_pcg.hip", "mg_fused.hip", "onchip.hip", "d3.hip", "api.hip",
+           "serve.hip"]
 ARCH = os.environ.get("MLMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -35,6 +35,16 @@ struct Buffer {
   size_t bytes = 0;
 };
 
+// An instantiated graph of `check_every` PCG iterations of one solve
+// configuration; `key` holds every value its launches depend on (sizes,
+// options, buffer addresses and the workspace generation).
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+constexpr size_t kGraphCache = 8;
+
 struct ProfEvent {
   hipEvent_t a, b;
   double bytes;  // algorithmic bytes of the launch over the whole batch
@@ -56,6 +66,9 @@ struct mlmc_ctx {
   int prof_iter = 0;        // PCG iteration of the launches being enqueued (0: n/a)
   std::vector<ProfEvent> prof;
   std::vector<hipEvent_t> event_pool;
+  uint64_t ws_gen = 0;             // bumped whenever a workspace is (re)allocated
+  hipStream_t capture_stream = nullptr;  // private stream graphs are captured on
+  std::vector<GraphEntry> graphs;  // PCG iteration graphs, oldest first
 };
 
 namespace {
@@ -103,6 +116,7 @@ mlmc_status ws_get(mlmc_ctx* ctx, const std::string& name, size_t bytes, void** 
     }
     b.ptr = p;
     b.bytes = bytes;
+    ++ctx->ws_gen;
   }
   *out = b.ptr;
   return MLMC_OK;
@@ -281,6 +295,8 @@ mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
     return fail(ctx, MLMC_EINVAL, "cycle_max must be 0 or in [2, 32]");
   if (o->gamma < 1 || o->gamma > 2) return fail(ctx, MLMC_EINVAL, "gamma must be 1 or 2");
   if (o->gamma_levels < 0) return fail(ctx, MLMC_EINVAL, "gamma_levels must be >= 0");
+  if (o->graph != 0 && o->graph != 1) return fail(ctx, MLMC_EINVAL, "graph must be 0 or 1");
+  if (o->variant < 0 || o->variant > 2) return fail(ctx, MLMC_EINVAL, "variant must be 0, 1 or 2");
   return MLMC_OK;
 }
 
@@ -332,6 +348,11 @@ mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx) {
     (void)hipEventDestroy(pe.b);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto& g : ctx->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   delete ctx;
   return MLMC_OK;
@@ -357,6 +378,8 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* o) {
   o->check_every = 4;
   o->gamma = 2;
   o->gamma_levels = 2;
+  o->graph = 0;
+  o->reserved = 0;
   return MLMC_OK;
 }
 
@@ -651,9 +674,38 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   const long long n = (long long)m * m;
   const int bps = blocks_per_sample(n);
   const int prec = opts->precision;
-  const bool fused = opts->variant == 0 && opts->nu1 == 1;
+  const bool fused = (opts->variant == 0 || opts->variant == 2) && opts->nu1 == 1;
   if (prec != MLMC_PREC_FP64 && !fused)
     return fail(ctx, MLMC_EINVAL, "reduced-precision multigrid needs variant 0 and nu1 = nu2 = 1");
+
+  // 64 x 64 in FP64: the whole solve of a sample in one workgroup (same
+  // hierarchy and cycle; the vectors never leave the CU)
+  if (opts->variant == 0 && opts->nu1 == 1 && prec == MLMC_PREC_FP64 && m == 64 && L == 4) {
+    OcHierarchy h{};
+    h.T[0] = T;
+    h.tb[0] = tb;
+    for (int l = 1; l <= L; ++l) {
+      const long long nl = (long long)ms[l] * ms[l];
+      double *Tc, *tbc;
+      TRY(ws(ctx, lv("s_T", l), batch * 2 * nl, &Tc));
+      TRY(ws(ctx, lv("s_tb", l), (size_t)batch * 2 * ms[l], &tbc));
+      launch_coarsen(st, ms[l - 1], batch, h.T[l - 1], h.tb[l - 1], Tc, tbc);
+      h.T[l] = Tc;
+      h.tb[l] = tbc;
+    }
+    double *work = nullptr, *Ainv = nullptr;
+    TRY(ws(ctx, "s_chol", (size_t)batch * 256, &work));
+    TRY(ws(ctx, "s_ainv", (size_t)batch * 256, &Ainv));
+    launch_dense_factor(st, 4, batch, h.T[L], h.tb[L], work, Ainv);
+    // compulsory bytes per sample: T and tb of every level, b, x, the inverse
+    const double bytes = (double)batch * (8.0 * (2.0 * 5456 + 2.0 * 124) + 16.0 * n + 8.0 * 256);
+    timed(ctx, "k_pcg_onchip64", bytes, [&] {
+      launch_pcg_onchip64(st, batch, h, b, p, Ainv, opts->tol, opts->maxit, opts->omega,
+                          opts->gamma, opts->gamma_levels, status, iters, relres);
+    });
+    CHECK_LAUNCH();
+    return MLMC_OK;
+  }
   const bool flexible = prec != MLMC_PREC_FP64;
   const size_t eb = prec_bytes(prec);
 
@@ -871,6 +923,87 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
 
   int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
   const int check = opts->check_every > 0 ? opts->check_every : 1;
+  // Graph form (opts->graph): after the first host check the iterations run
+  // as replays of one captured graph of `check` iterations, a host check after
+  // each replay.  The captured launches are those of the eager loop, in the
+  // same order and with the same arguments (the ping-pong p buffers repeat
+  // with the chunk when `check` is even), so the results are bitwise equal.
+  // Not with profiling (its events are per launch) nor on restart passes.
+  const bool use_graph = opts->graph != 0 && dir_fused && ctx->prof_name.empty() && check % 2 == 0;
+  auto chunk_body = [&](int k0) {
+    for (int it = k0 + 1; it <= k0 + check; ++it) {
+      vcycle();
+      launch_sc_rho(st, batch, partial, rz_parts, S, status, 0, partial2, bps);
+      pv = pbuf[it & 1];
+      launch_cg_direction(st, m, batch, T, tb, z, pbuf[(it - 1) & 1], pv, q, S.beta, false,
+                          partial, S.active);
+      launch_sc_alpha(st, batch, partial, dir_parts, S, status);
+      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,
+                      flexible ? z : nullptr, partial2);
+      launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
+    }
+  };
+  auto graph_chunks = [&](int k) -> mlmc_status {
+    auto bits = [](double v) {
+      uint64_t u;
+      std::memcpy(&u, &v, sizeof u);
+      return u;
+    };
+    const std::vector<uint64_t> key = {
+        ctx->ws_gen, (uint64_t)m, (uint64_t)batch, (uint64_t)prec, bits(omega), bits(opts->tol),
+        (uint64_t)opts->maxit, (uint64_t)cur_gamma, (uint64_t)opts->gamma_levels,
+        (uint64_t)check, (uint64_t)opts->cycle_max, (uint64_t)opts->coarse_max,
+        (uint64_t)(uintptr_t)T, (uint64_t)(uintptr_t)tb, (uint64_t)(uintptr_t)b,
+        (uint64_t)(uintptr_t)p, (uint64_t)(uintptr_t)status, (uint64_t)(uintptr_t)iters,
+        (uint64_t)(uintptr_t)relres};
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : ctx->graphs)
+      if (g.key == key) exec = g.exec;
+    if (!exec) {
+      GraphEntry g;
+      g.key = key;
+      // capture on the context's own capture stream (the caller's stream may be
+      // the null stream, which cannot capture); the launches record, not run
+      if (!ctx->capture_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+      const hipStream_t run_st = st;
+      st = ctx->capture_stream;
+      const hipError_t be = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (be != hipSuccess) {
+        st = run_st;
+        return fail(ctx, MLMC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(be));
+      }
+      chunk_body(k);
+      const hipError_t le = hipGetLastError();
+      const hipError_t ce = hipStreamEndCapture(st, &g.graph);
+      st = run_st;
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        return fail(ctx, MLMC_EDEVICE, std::string("graph capture: ") +
+                                           hipGetErrorString(le != hipSuccess ? le : ce));
+      }
+      if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g.graph);
+        return fail(ctx, MLMC_EDEVICE, "graph instantiation failed");
+      }
+      if (ctx->graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        (void)hipGraphDestroy(ctx->graphs.front().graph);
+        ctx->graphs.erase(ctx->graphs.begin());
+      }
+      ctx->graphs.push_back(g);
+      exec = g.exec;
+    }
+    // every sample stops by maxit (marked not converged), so the count reaches 0
+    for (; k < opts->maxit + check; k += check) {
+      HIP_TRY(hipGraphLaunch(exec, st));
+      HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (*hcount == 0) break;
+    }
+    pv = pbuf[(k + check) & 1];
+    return MLMC_OK;
+  };
   // One PCG pass over the active samples (all of them, or with `restart` the
   // ones marked by launch_sc_restart), x0 = 0.
   auto pcg_pass = [&](bool restart) -> mlmc_status {
@@ -906,6 +1039,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
         HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (*hcount == 0) break;
+        if (use_graph && !restart && it % check == 0) return graph_chunks(it);
       }
       ctx->prof_iter = restart ? 0 : it + 1;
       vcycle();

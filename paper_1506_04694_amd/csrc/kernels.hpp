@@ -178,6 +178,17 @@ void launch_ce3(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first
                 double* k_coarse);
 void launch_cgv_extract3(hipStream_t st, int m, int batch, const double* kf, double* ksub);
 // z = A^-1 r for n unknowns per sample (coarsest grid of either dimension).
+// Operators of the levels 64, 32, 16, 8 and 4 of a 64 x 64 solve (device).
+struct OcHierarchy {
+  const double* T[5];
+  const double* tb[5];
+};
+// One workgroup per sample: the whole PCG solve of a 64 x 64 system on chip.
+void launch_pcg_onchip64(hipStream_t st, int batch, const OcHierarchy& h, const double* b,
+                         double* x, const double* Ainv, double tol, int maxit, double omega,
+                         int gamma, int gamma_levels, int32_t* status, int32_t* iters,
+                         double* relres);
+
 void launch_dense_apply_n(hipStream_t st, int n, int batch, const double* Ainv, const double* r,
                           double* z, const int32_t* active);
 

@@ -48,7 +48,7 @@ int main(void) {
          sizeof(mlmc_model), sizeof(mlmc_solver_opts), sizeof(mlmc_level_sums),
          sizeof(mlmc_estimate_t));
   P(mlmc_model, y_lo); P(mlmc_model, mu); P(mlmc_model, sigma2); P(mlmc_model, lambda);
-  P(mlmc_model, seed); P(mlmc_solver_opts, maxit); P(mlmc_solver_opts, check_every); P(mlmc_solver_opts, gamma); P(mlmc_solver_opts, gamma_levels);
+  P(mlmc_model, seed); P(mlmc_solver_opts, maxit); P(mlmc_solver_opts, check_every); P(mlmc_solver_opts, gamma); P(mlmc_solver_opts, gamma_levels); P(mlmc_solver_opts, graph);
   P(mlmc_level_sums, sum_y); P(mlmc_level_sums, iters_coarse);
   printf("mlmc_serve_opts %zu\nmlmc_request %zu\nmlmc_result %zu\n", sizeof(mlmc_serve_opts),
          sizeof(mlmc_request), sizeof(mlmc_result));
@@ -78,6 +78,7 @@ def test_struct_layouts_match_header(lib, tmp_path):
     assert int(vals["mlmc_solver_opts.check_every"]) == lib.mlmc_solver_opts.check_every.offset
     assert int(vals["mlmc_solver_opts.gamma"]) == lib.mlmc_solver_opts.gamma.offset
     assert int(vals["mlmc_solver_opts.gamma_levels"]) == lib.mlmc_solver_opts.gamma_levels.offset
+    assert int(vals["mlmc_solver_opts.graph"]) == lib.mlmc_solver_opts.graph.offset
     assert int(vals["mlmc_level_sums.iters_coarse"]) == lib.mlmc_level_sums.iters_coarse.offset
     for st in ("mlmc_serve_opts", "mlmc_request", "mlmc_result"):
         assert int(vals[st]) == ctypes.sizeof(getattr(lib, st)), st
@@ -91,6 +92,7 @@ def test_solver_defaults(lib):
     o = lib.mlmc_solver_opts_default()
     assert o.tol == 1e-13 and o.omega == 1.9 and o.nu1 == o.nu2 == 1 and o.maxit == 200
     assert o.gamma == 2 and o.gamma_levels == 2 and o.variant == 0 and o.precision == lib.MLMC_PREC_FP64
+    assert o.graph == 0
 
 
 def test_estimate_matches_oracle(lib):

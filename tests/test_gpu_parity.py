@@ -479,3 +479,90 @@ def test_coarse_cycle_threshold_same_preconditioner(lib, ctx, cycle_max):
         A, bb = ofv.assemble(kh[s])
         q = oqoi.outflow(kh[s], osolve.direct_solve(A, bb))
         assert abs(b["q_out"][s] - q) <= QTOL * q
+
+
+# ------------------------------------------------------------------ graph-captured iterations
+def test_graph_iterations_bitwise_equal_eager(lib, ctx):
+    """PCG iterations replayed from a captured HIP graph give the eager results bit
+    for bit.  Level runs alternate between the graph and the eager form and between
+    grids, so cached graphs are replayed again after other eager work, and every
+    replay is compared with the eager run of the same samples."""
+    wl = FULL
+    plan = [(1, 128, 64), (3, 512, 4), (1, 128, 64), (2, 256, 16), (3, 512, 4), (1, 128, 64)]
+    for rep, (level, m, n) in enumerate(plan):
+        print("graph vs eager: level %d m %d rep %d" % (level, m, rep), flush=True)
+        first = 7 + 11 * rep
+        se, qfe, qce, _ = level_run(lib, ctx, wl.model, level, m, first, n, False)
+        sg, qfg, qcg, _ = level_run(lib, ctx, wl.model, level, m, first, n, False,
+                                    lib.mlmc_solver_opts_default(graph=1))
+        assert sg.n_failed == 0
+        assert np.array_equal(qfe, qfg) and np.array_equal(qce, qcg), rep
+        assert (se.iters_fine, se.iters_coarse) == (sg.iters_fine, sg.iters_coarse)
+        level_run(lib, ctx, wl.model, 0, 64, 3 + rep, 32, False)       # eager work in between
+
+
+@pytest.mark.parametrize("check,prec,omega", [(2, 0, 1.9), (6, 0, 1.9), (4, 1, 1.9), (4, 0, 2.0)])
+def test_graph_solve_options(lib, ctx, check, prec, omega):
+    """Graph form against the eager form for other check intervals, the FP32 hierarchy
+    (flexible CG) and omega = 2, where some samples' W iterations break down and are
+    restarted with the V-cycle: status, iterations, relres and the pressure bitwise."""
+    model, m = FULL.model, 128
+    ids = [31, 601, 672, 0, 1, 2]
+    kk = f64(len(ids), m, m)
+    sid = torch.tensor(ids, dtype=torch.int32, device=DEV)
+    lib.mlmc_sample_field_ids(ctx, model, m, 1, sid, len(ids), kk)
+    kh = kk.cpu().numpy()
+    kw = dict(check_every=check, precision=prec, omega=omega)
+    eager = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(**kw))
+    for rep in range(3):
+        graph = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(graph=1, **kw))
+        for key in ("status", "iters", "relres", "p"):
+            assert np.array_equal(eager[key], graph[key]), (rep, key)
+    assert np.all(eager["status"] == 0)
+
+
+def test_graph_option_refused(lib, ctx):
+    kh = np.ones((1, 16, 16))
+    with pytest.raises(lib.MlmcError):
+        solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(graph=2))
+
+
+# ------------------------------------------------------------------ on-chip 64 x 64 solver
+@pytest.mark.parametrize("gamma,glev,omega", [(2, 2, 1.9), (1, 2, 1.9), (2, 1, 1.9), (2, 0, 1.9),
+                                              (2, 2, 2.0)])
+def test_onchip_64_matches_tiled(lib, ctx, gamma, glev, omega):
+    """The one-workgroup solve of 64 x 64 samples (variant 0) against the tiled
+    kernels (variant 2) with the same hierarchy and cycle: same status, the same
+    iteration counts up to one, pressures to 1e-12 and QoIs to 1e-12 relative, and
+    QoIs within 1e-10 of the oracle.  omega = 2 exercises the V-cycle restart."""
+    model, m = FULL.model, 64
+    ids = [31, 601, 672, 0, 1, 2, 3, 4]
+    kk = f64(len(ids), m, m)
+    sid = torch.tensor(ids, dtype=torch.int32, device=DEV)
+    lib.mlmc_sample_field_ids(ctx, model, m, 0, sid, len(ids), kk)
+    kh = kk.cpu().numpy()
+    kw = dict(gamma=gamma, gamma_levels=glev, omega=omega)
+    oc = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=0, **kw))
+    ti = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=2, **kw))
+    print("on-chip iterations", oc["iters"], "tiled", ti["iters"], flush=True)
+    assert np.array_equal(oc["status"], ti["status"]) and np.all(oc["status"] == 0)
+    assert np.max(np.abs(oc["iters"] - ti["iters"])) <= 1
+    assert np.all(oc["relres"] < 1e-12)
+    np.testing.assert_allclose(oc["q_out"], ti["q_out"], rtol=1e-12)
+    assert np.max(np.abs(oc["p"] - ti["p"])) <= 1e-12
+    for s in (0, 3):
+        q = omlmc.solve_qoi(kh[s])[0]
+        assert abs(oc["q_out"][s] - q) <= QTOL * q
+
+
+def test_onchip_64_level_run_full_size(lib, ctx):
+    """The 64^2 level of the layered workload (4096 samples) through the on-chip
+    solver: no failures, batch-invariant results and oracle parity on samples."""
+    m, n = 64, 4096
+    sums, qf, _, _ = level_run(lib, ctx, FULL.model, 0, m, 0, n, False)
+    assert sums.n_failed == 0
+    sums2, qf2, _, _ = level_run(lib, ctx, FULL.model, 0, m, 100, 7, False)
+    assert np.array_equal(qf[100:107], qf2)
+    for s in (0, 2047, 4095):
+        q = omlmc.solve_qoi(ofield.sample_k(FULL.model, 0, s, m))[0]
+        assert abs(qf[s] - q) <= QTOL * q
