@@ -870,7 +870,31 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   // restricts; after the first coarse visit the mid kernel adds the correction,
   // post- and pre-smooths and restricts again; the up kernel adds the last
   // correction and post-smooths.  Levels l0..L run in the in-LDS kernel.
+  // A 64^2 level below the finest (with 32, 16, 8, 4 under it) runs its whole
+  // sub-cycle in one workgroup per sample (FP64, variant 0).
+  int l64 = -1;
+  OcHierarchy h64{};
+  if (fused && opts->variant == 0 && prec == MLMC_PREC_FP64 && L >= 5 && ms[L - 4] == 64 &&
+      ms[L] == 4) {
+    l64 = L - 4;
+    for (int q2 = 0; q2 <= 4; ++q2) {
+      h64.T[q2] = Tl[l64 + q2];
+      h64.tb[q2] = tbl[l64 + q2];
+    }
+  }
   std::function<void(int)> fcycle = [&](int l) {
+    if (l == l64) {
+      unsigned wmask = 0;
+      for (int q2 = 0; q2 < 4; ++q2)
+        if (visits(l + q2) == 2) wmask |= 1u << q2;
+      // T, tb and r read once, z written once per sample (FP64)
+      const double bytes = (double)batch * (8.0 * (2.0 * 5456 + 2.0 * 124) + 16.0 * 4096 + 2048.0);
+      timed(ctx, "k_cycle_onchip64", bytes, [&] {
+        launch_cycle_onchip64(st, batch, h64, static_cast<const double*>(rs[l]),
+                              static_cast<double*>(zs[l]), Ainv, omega, wmask, S.active);
+      });
+      return;
+    }
     if (l == l0) {
       unsigned wmask = 0;
       for (int q2 = 0; l0 + q2 < L; ++q2)

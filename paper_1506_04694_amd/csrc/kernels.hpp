@@ -183,6 +183,11 @@ struct OcHierarchy {
   const double* T[5];
   const double* tb[5];
 };
+// One workgroup per sample: z = M r for a 64 x 64 level and the four below it
+// (wmask bit k: level k of the five takes two coarse visits).
+void launch_cycle_onchip64(hipStream_t st, int batch, const OcHierarchy& h, const double* r,
+                           double* z, const double* Ainv, double omega, unsigned wmask,
+                           const int32_t* active);
 // One workgroup per sample: the whole PCG solve of a 64 x 64 system on chip.
 void launch_pcg_onchip64(hipStream_t st, int batch, const OcHierarchy& h, const double* b,
                          double* x, const double* Ainv, double tol, int maxit, double omega,

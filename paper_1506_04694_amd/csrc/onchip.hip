@@ -343,25 +343,16 @@ __device__ __forceinline__ double oc_dot(double v, double* lds, int t) {
   return s;
 }
 
-}  // namespace
-
-// One workgroup per sample.  Tl / tbl: operators of the levels 64, 32, 16, 8,
-// 4 (Galerkin); Ainv: inverse of each sample's 4^2 operator; b, x: [batch][64^2].
-template <unsigned WMASK>
-__global__ void __launch_bounds__(kOcT)
-k_pcg_onchip64(OcHierarchy h, const double* __restrict__ b, double* __restrict__ x,
-               const double* __restrict__ Ainv, double tol, int maxit, double omega,
-               int32_t* __restrict__ status, int32_t* __restrict__ iters,
-               double* __restrict__ relres) {
-  __shared__ double lds[kOcWords];
-  const int t = threadIdx.x;
-  const int s = blockIdx.x;
-  constexpr int m = 64, n = m * m, w = 32;
+// Set-up of one sample's hierarchy in LDS and registers: the 64^2 faces into
+// their planes (boundary faces into the frames), the reciprocal diagonals and
+// the right-hand side rhs (64^2, [j][i]) into registers, 32^2 cells into
+// registers, 16^2 and 8^2 cells into LDS, the 4^2 inverse into LDS.
+__device__ __forceinline__ void oc_setup(OcRegs& g, double* lds, const OcHierarchy& h,
+                                         const double* __restrict__ rhs,
+                                         const double* __restrict__ Ainv, int s, int t) {
+  constexpr int m = 64, n = m * m;
   for (int q = t; q < kOcSres; q += kOcT) lds[q] = 0.0;  // zero frames of every plane
   __syncthreads();
-  OcRegs g;
-  const double* bs = b + (long long)s * n;
-  double xr[2][2], pr_[2][2];
   {
     const double* Ts = h.T[0] + (long long)s * 2 * n;
     const double* tbs = h.tb[0] + (long long)s * 2 * m;
@@ -371,8 +362,8 @@ k_pcg_onchip64(OcHierarchy h, const double* __restrict__ b, double* __restrict__
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const int pr = t + sl * kOcT;
-    int j, cp;
-    oc_pair<0>(pr, j, cp);
+      int j, cp;
+      oc_pair<0>(pr, j, cp);
 #pragma unroll
       for (int col = 0; col < 2; ++col) {
         const int i = 2 * cp + (col == 0 ? (j & 1) : 1 - (j & 1));
@@ -385,9 +376,7 @@ k_pcg_onchip64(OcHierarchy h, const double* __restrict__ b, double* __restrict__
         if (i == 0) te[(1 - col) * pl + f - 1] = c.tw;
         if (j == 0) tn[(1 - col) * pl + f - P] = c.ts;
         g.di0[sl][col] = c.di;
-        g.r0[sl][col] = oc_ld(bs, j * m + i);
-        xr[sl][col] = 0.0;
-        pr_[sl][col] = 0.0;
+        g.r0[sl][col] = oc_ld(rhs, j * m + i);
       }
     }
   }
@@ -418,6 +407,26 @@ k_pcg_onchip64(OcHierarchy h, const double* __restrict__ b, double* __restrict__
   }
   if (t < 256) lds[kOcAinv + t] = oc_ld(Ainv + (long long)s * 256, t);
   __syncthreads();
+}
+
+}  // namespace
+
+// One workgroup per sample.  h: operators of the levels 64, 32, 16, 8, 4
+// (Galerkin); Ainv: inverse of each sample's 4^2 operator; b, x: [batch][64^2].
+template <unsigned WMASK>
+__global__ void __launch_bounds__(kOcT)
+k_pcg_onchip64(OcHierarchy h, const double* __restrict__ b, double* __restrict__ x,
+               const double* __restrict__ Ainv, double tol, int maxit, double omega,
+               int32_t* __restrict__ status, int32_t* __restrict__ iters,
+               double* __restrict__ relres) {
+  __shared__ double lds[kOcWords];
+  const int t = threadIdx.x;
+  const int s = blockIdx.x;
+  constexpr int m = 64, n = m * m, w = 32;
+  OcRegs g;
+  const double* bs = b + (long long)s * n;
+  oc_setup(g, lds, h, bs, Ainv, s, t);
+  double xr[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, pr_[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 
   // r0 = b (x0 = 0)
   double acc = 0.0;
@@ -554,6 +563,52 @@ k_pcg_onchip64(OcHierarchy h, const double* __restrict__ b, double* __restrict__
     iters[s] = it;
     relres[s] = r0sq > 0.0 ? sqrt(v / r0sq) : 0.0;
   }
+}
+
+// The W/V cycle of a 64^2 level that is not the finest of its solve, in one
+// workgroup per sample: z = M_64 r for the levels 64, 32, 16, 8 and the 4^2
+// inverse, the same cycle as the tiled down / mid / up kernels and the
+// coarse-grid kernel, in one launch per visit instead of five.  r, z:
+// [batch][64^2]; inactive samples are skipped.
+template <unsigned WMASK>
+__global__ void __launch_bounds__(kOcT)
+k_cycle_onchip64(OcHierarchy h, const double* __restrict__ r, double* __restrict__ z,
+                 const double* __restrict__ Ainv, double omega,
+                 const int32_t* __restrict__ active) {
+  __shared__ double lds[kOcWords];
+  const int t = threadIdx.x;
+  const int s = blockIdx.x;
+  if (!active[s]) return;
+  constexpr int m = 64, n = m * m;
+  OcRegs g;
+  oc_setup(g, lds, h, r + (long long)s * n, Ainv, s, t);
+  oc_cycle<0, WMASK>(g, lds, t, omega);
+  constexpr int P = oc_P(0);
+  double* zs = z + (long long)s * n;
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl) {
+    const int pr = t + sl * kOcT;
+    int j, cp;
+    oc_pair<0>(pr, j, cp);
+    zs[j * m + 2 * cp + (j & 1)] = lds[oc_zi(P, j, cp)];
+    zs[j * m + 2 * cp + 1 - (j & 1)] = lds[oc_plane(0) + oc_zi(P, j, cp)];
+  }
+}
+
+void launch_cycle_onchip64(hipStream_t st, int batch, const OcHierarchy& h, const double* r,
+                           double* z, const double* Ainv, double omega, unsigned wmask,
+                           const int32_t* active) {
+#define OC_LAUNCH(M)                                                                          \
+  hipLaunchKernelGGL(k_cycle_onchip64<M>, dim3(batch), dim3(kOcT), 0, st, h, r, z, Ainv, omega, \
+                     active)
+  switch (wmask & 15u) {
+    case 0u: OC_LAUNCH(0u); break;
+    case 1u: OC_LAUNCH(1u); break;
+    case 3u: OC_LAUNCH(3u); break;
+    case 7u: OC_LAUNCH(7u); break;
+    default: OC_LAUNCH(15u); break;
+  }
+#undef OC_LAUNCH
 }
 
 void launch_pcg_onchip64(hipStream_t st, int batch, const OcHierarchy& h, const double* b,

@@ -566,3 +566,19 @@ def test_onchip_64_level_run_full_size(lib, ctx):
     for s in (0, 2047, 4095):
         q = omlmc.solve_qoi(ofield.sample_k(FULL.model, 0, s, m))[0]
         assert abs(qf[s] - q) <= QTOL * q
+
+
+@pytest.mark.parametrize("m,glev", [(128, 2), (128, 0), (256, 2), (512, 3)])
+def test_onchip_subcycle_matches_tiled(lib, ctx, m, glev):
+    """Larger solves run the cycle of their 64^2 level (and below) in one workgroup
+    per sample (variant 0); against the all-tiled cycle (variant 2): the same
+    status, iterations up to one and QoIs to 1e-12."""
+    rng = np.random.default_rng(700 + m)
+    kh = np.exp(1.5 * rng.standard_normal((3, m, m)))
+    kw = dict(gamma_levels=glev)
+    oc = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=0, **kw))
+    ti = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(variant=2, **kw))
+    print("m %d sub-cycle iterations %s tiled %s" % (m, oc["iters"], ti["iters"]), flush=True)
+    assert np.all(oc["status"] == 0) and np.all(ti["status"] == 0)
+    assert np.max(np.abs(oc["iters"] - ti["iters"])) <= 1
+    np.testing.assert_allclose(oc["q_out"], ti["q_out"], rtol=1e-12)
