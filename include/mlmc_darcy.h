@@ -136,7 +136,9 @@ typedef struct mlmc_solver_opts {
                            the whole solve of a sample in one workgroup (needs
                            nu1 = nu2 = 1, else falls back to 1); 1: one launch
                            per sweep / step; 2: the tiled kernels on every grid */
-  int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1   */
+  int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1;
+                           64 x 64 solves (variant 0) run on chip in FP64 at
+                           every setting                                      */
   int32_t cycle_max;    /* variant 0: levels of at most this size (2..32, 0 = 32) run
                            in one workgroup per sample                              */
   int32_t gamma;        /* coarse-grid visits on the gamma_levels finest levels:

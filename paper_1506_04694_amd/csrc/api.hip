@@ -678,9 +678,11 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   if (prec != MLMC_PREC_FP64 && !fused)
     return fail(ctx, MLMC_EINVAL, "reduced-precision multigrid needs variant 0 and nu1 = nu2 = 1");
 
-  // 64 x 64 in FP64: the whole solve of a sample in one workgroup (same
-  // hierarchy and cycle; the vectors never leave the CU)
-  if (opts->variant == 0 && opts->nu1 == 1 && prec == MLMC_PREC_FP64 && m == 64 && L == 4) {
+  // 64 x 64: the whole solve of a sample in one workgroup (same hierarchy and
+  // cycle; the vectors never leave the CU).  It computes in FP64 at every
+  // precision setting: a reduced-precision hierarchy would save no memory
+  // traffic here, whose only HBM traffic is T, b in and p out.
+  if (opts->variant == 0 && opts->nu1 == 1 && m == 64 && L == 4) {
     OcHierarchy h{};
     h.T[0] = T;
     h.tb[0] = tb;
