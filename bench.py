@@ -284,6 +284,36 @@ def path_variants(lib, torch, wl, ctx, opts, args):
                                           "max_qoi_rel_diff_vs_fp64": dev}}
 
 
+def cgv_variance(lib, torch, ctx, opts):
+    """Section 4.2's experiment: the sample variance of Y_l = Q_l - Q_{l-1} with one
+    coarse companion (the plain estimator; the coarse sample is the fine field's
+    sub-lattice of even indices) and with Coarse Grid Variates (the mean over the
+    2^d sub-lattices, eq. (4.1)), from the same fine samples, on the stationary
+    log-normal field with the 1-norm covariance, lambda 0.3, sigma^2 1, Model
+    Problem 2, fine grids h_l = 1/8 upwards in 2-D and 3-D."""
+    out = {"model": "stationary log-normal, exp. covariance r=1, sigma2=1, lambda=0.3 "
+                    "(no layers)", "qoi": "outflow at x1 = 1 (Model Problem 2)"}
+    for key, model, levels in (("2d", W.STATIONARY_1NORM, W.CGV_VARIANCE_2D),
+                               ("3d", W.STATIONARY_1NORM_3D, W.CGV_VARIANCE_3D)):
+        rows = []
+        for level, (m, n) in enumerate(levels, start=1):
+            row = {"h": 1.0 / m, "m_fine": m, "samples": n}
+            for name, cgv in (("plain", False), ("cgv", True)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = lib.mlmc_level_run(ctx, model, level, m, 0, n, cgv, opts)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                mean = s.sum_y / s.n
+                var = (s.sum_y2 - s.n * mean * mean) / (s.n - 1)
+                row[name] = {"var_y": var, "mean_y": mean, "ms": 1e3 * t,
+                             "samples_per_s": n / t, "failed_solves": int(s.n_failed)}
+            row["variance_ratio"] = row["plain"]["var_y"] / row["cgv"]["var_y"]
+            rows.append(row)
+        out[key] = rows
+    return out
+
+
 def other_configs(lib, torch, steps):
     """The other batched workloads, each timed over `steps` passes after one warm-up
     pass (not part of `value`):
@@ -292,7 +322,8 @@ def other_configs(lib, torch, steps):
       all levels in one call (mlmc_run_levels) and level by level; FP64;
     * the high-contrast field on 1024^2 (256 samples) with the multigrid in FP64,
       FP32 and bfloat16 inside the FP64 CG, with the largest relative QoI
-      difference of each reduced precision to the FP64 solve of the same samples."""
+      difference of each reduced precision to the FP64 solve of the same samples;
+    * Section 4.2's variance experiment (cgv_variance)."""
     ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
     opts = lib.mlmc_solver_opts_default()
 
@@ -353,6 +384,7 @@ def other_configs(lib, torch, steps):
         out["high_contrast"] = {"workload": wl.name, "m": m, "samples": n, "tol_relres": wl.tol,
                                 "omega_bf16": wl.omega_bf16,
                                 "multigrid_precision": runs}
+        out["cgv_variance"] = cgv_variance(lib, torch, ctx, opts)
     finally:
         lib.mlmc_ctx_destroy(ctx)
     return out

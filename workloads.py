@@ -93,6 +93,14 @@ STATIONARY_1NORM = Model(interface_kind=NO_INTERFACE, n_layers=1, field_kind=COR
                          lam=(0.3, 0.3, 0.3, 0.3), seed=0,
                          n_ce={4: 8, 8: 16, 16: 32, 32: 64, 64: 128, 128: 256, 256: 512})
 
+STATIONARY_1NORM_3D = STATIONARY_1NORM.with_(dim=3)
+
+# The variance experiment of Section 4.2: V[Y_l] of the plain and the CGV
+# estimator on the stationary 1-norm field, fine grids h_l = 1/8 .. 1/256 in
+# 2-D and 1/8 .. 1/64 in 3-D; (fine grid m_l, samples).
+CGV_VARIANCE_2D = [(8, 8192), (16, 8192), (32, 8192), (64, 8192), (128, 4096), (256, 1024)]
+CGV_VARIANCE_3D = [(8, 4096), (16, 2048), (32, 1024), (64, 256)]
+
 # 3-D served model: tilted planar interface, two layers with independent
 # stationary Gaussian fields, exponential covariance with the 1-norm (separable,
 # so the embedding of length 2m is non-negative), sigma^2 = 1, lambda = 0.2,
