@@ -19,10 +19,20 @@ from . import field, fv, qoi, solve
 
 
 def solve_qoi(k, bc=fv.MP2):
-    """Exact discrete outflow and inflow for one permeability sample."""
+    """Exact discrete QoI for one permeability sample: Model Problem 2, the
+    outflow and the inflow; Model Problem 1, M^(1) (box mean of the pressure)
+    and None."""
     A, b = fv.assemble(k, bc)
     p = solve.direct_solve(A, b)
+    if bc == fv.MP1:
+        return qoi.box_average(p.reshape(k.shape)), None
     return qoi.outflow(k, p), qoi.inflow(k, p)
+
+
+def problem_of(model):
+    """Boundary value problem of a model record: problem 1 = Model Problem 1,
+    anything else (default 0) = Model Problem 2."""
+    return fv.MP1 if getattr(model, "problem", 0) == 1 else fv.MP2
 
 
 def level_sample(model, level, sample, m_fine, cgv=False, lam_eig=None):
@@ -31,19 +41,20 @@ def level_sample(model, level, sample, m_fine, cgv=False, lam_eig=None):
     Returns dict with Q_f (fine QoI), Q_c (coarse QoI; 0 on level 0), Y = Q_f - Q_c,
     and the individual companion QoIs.
     """
+    bc = problem_of(model)
     if level == 0:
         k = field.sample_k(model, level, sample, m_fine, lam_eig=lam_eig)
-        qf, _ = solve_qoi(k)
+        qf, _ = solve_qoi(k, bc)
         return {"Q_f": qf, "Q_c": 0.0, "Y": qf, "companions": []}
     if cgv:
         k = field.sample_k(model, level, sample, m_fine, lam_eig=lam_eig)
-        qf, _ = solve_qoi(k)
-        comps = [solve_qoi(kc)[0] for kc in field.cgv_sublattices(k)]
+        qf, _ = solve_qoi(k, bc)
+        comps = [solve_qoi(kc, bc)[0] for kc in field.cgv_sublattices(k)]
         qc = sum(comps) / len(comps)
     else:
         k, kc = field.sample_k(model, level, sample, m_fine, lam_eig=lam_eig, with_coarse=True)
-        qf, _ = solve_qoi(k)
-        comps = [solve_qoi(kc)[0]]
+        qf, _ = solve_qoi(k, bc)
+        comps = [solve_qoi(kc, bc)[0]]
         qc = comps[0]
     return {"Q_f": qf, "Q_c": qc, "Y": qf - qc, "companions": comps}
 

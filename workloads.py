@@ -39,6 +39,9 @@ class Model:
     sigma2: Tuple[float, ...] = (1.0, 1.0, 1.0, 1.0)
     lam: Tuple[float, ...] = (0.3, 0.3, 0.3, 0.3)
     seed: int = 0
+    # boundary value problem: 0 = Model Problem 2 (outflow), 1 = Model Problem 1
+    # (f = 1, p = 0 on the boundary, mean pressure over D* around the centre)
+    problem: int = 0
     # circulant-embedding length per direction, one per MLMC grid size m
     n_ce: dict = field(default_factory=dict)
 
@@ -94,6 +97,16 @@ STATIONARY_1NORM = Model(interface_kind=NO_INTERFACE, n_layers=1, field_kind=COR
                          n_ce={4: 8, 8: 16, 16: 32, 32: 64, 64: 128, 128: 256, 256: 512})
 
 STATIONARY_1NORM_3D = STATIONARY_1NORM.with_(dim=3)
+
+# Model Problem 1 (f = 1, p = 0 on the boundary, QoI = mean pressure over the
+# centred box D* of side 1/8): on the layered bench model, and on the paper's
+# own three layers between two random lines with independent N(0, 1) log-k
+# constants (Section 3.4, Fig. 2).
+MP1_CE2 = CE2.with_(problem=1)
+MP1_LAYERED = Workload("2d-ce-8node-mp1-64-512", MP1_CE2, [64, 128, 256, 512],
+                       [4096, 1024, 256, 64])
+MP1_PAPER3 = Model(interface_kind=PAPER_TWO_LINES, n_layers=3, field_kind=PIECEWISE_CONSTANT,
+                   mu=(0.0, 0.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0), seed=0, problem=1)
 
 # The variance experiment of Section 4.2: V[Y_l] of the plain and the CGV
 # estimator on the stationary 1-norm field, fine grids h_l = 1/8 .. 1/256 in
