@@ -323,7 +323,8 @@ def other_configs(lib, torch, steps):
     * the high-contrast field on 1024^2 (256 samples) with the multigrid in FP64,
       FP32 and bfloat16 inside the FP64 CG, with the largest relative QoI
       difference of each reduced precision to the FP64 solve of the same samples;
-    * Section 4.2's variance experiment (cgv_variance)."""
+    * Section 4.2's variance experiment (cgv_variance);
+    * Model Problem 1 on the bench workload's levels, level by level."""
     ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
     opts = lib.mlmc_solver_opts_default()
 
@@ -385,6 +386,31 @@ def other_configs(lib, torch, steps):
                                 "omega_bf16": wl.omega_bf16,
                                 "multigrid_precision": runs}
         out["cgv_variance"] = cgv_variance(lib, torch, ctx, opts)
+
+        # Model Problem 1 on the bench model's levels (f = 1, p = 0 on the boundary,
+        # mean pressure over the centred box of side 1/8)
+        wl = W.MP1_LAYERED
+        total = sum(wl.n_samples)
+        lv_ms = {}
+        iters = {}
+
+        def mp1_levels(idx):
+            for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = lib.mlmc_level_run(ctx, wl.model, level, m, idx * n, n, False, opts)
+                torch.cuda.synchronize()
+                lv_ms.setdefault(level, []).append(1e3 * (time.perf_counter() - t0))
+                iters[level] = s.iters_fine / n
+
+        t = timed(mp1_levels)
+        out["model_problem_1"] = {
+            "workload": wl.name, "levels_m": wl.m_levels, "samples": wl.n_samples,
+            "qoi": "mean pressure over [7/16, 9/16]^2", "dtype": "f64",
+            "value": total / t, "ms_per_step": 1e3 * t,
+            "per_level": [{"level": l, "m": m, "ms": sorted(lv_ms[l])[len(lv_ms[l]) // 2],
+                           "mean_iters_fine": iters[l]}
+                          for l, m in enumerate(wl.m_levels)]}
     finally:
         lib.mlmc_ctx_destroy(ctx)
     return out

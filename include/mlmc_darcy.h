@@ -76,6 +76,17 @@ enum {
   MLMC_IFACE_NONE = 4              /* one layer (stationary field)                    */
 };
 
+/* Boundary value problem and quantity of interest (Section 3.4). */
+enum {
+  MLMC_PROBLEM_OUTFLOW = 0,      /* Model Problem 2: p = 1 on x1 = 0, p = 0 on x1 = 1,
+                                    no flow elsewhere, f = 0; QoI = outflow M^(2)
+                                    through x1 = 1                                   */
+  MLMC_PROBLEM_MEAN_PRESSURE = 1 /* Model Problem 1: f = 1, p = 0 on the whole
+                                    boundary; QoI = M^(1), the mean pressure over
+                                    D* = [1/2 - 1/16, 1/2 + 1/16]^d (the paper fixes
+                                    neither the point nor D*)                       */
+};
+
 /* Per-layer law (Section 2). */
 enum {
   MLMC_FIELD_PIECEWISE_CONSTANT = 0, /* Example 1: k_l = exp(mu_l + sqrt(sigma2_l) z_l) */
@@ -106,7 +117,8 @@ typedef struct mlmc_model {
   int32_t norm_r;         /* 1 or 2: the l_r norm of eq. (2.3)                  */
   int32_t n_ce;           /* circulant-embedding points per direction for the grid
                              being sampled (>= 2m, factors 2, 3, 5 only, <= 4096) */
-  int32_t reserved;
+  int32_t problem;        /* MLMC_PROBLEM_*: boundary value problem and QoI of the
+                             level runs and the server                         */
   double y_lo, y_hi;      /* range of interface heights                         */
   double mu[4];           /* layer means of log k                               */
   double sigma2[4];       /* layer variances of log k                           */
@@ -248,6 +260,13 @@ mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch,
 mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
                           double* T, double* tb, double* b);
 
+/* As mlmc_assemble for either model problem (MLMC_PROBLEM_*).  Model Problem 1
+ * (Section 3.4: f = 1, p = 0 on every boundary face): every boundary face is a
+ * Dirichlet face with T = 2 k_P h^(d-2) (tb[s][1] and the x2 = 1 (and x3 = 1)
+ * faces are no longer 0) and b = f h^d = h^d in every cell.  Same layouts. */
+mlmc_status mlmc_assemble_problem(mlmc_ctx* ctx, int problem, int dim, int m, int batch,
+                                  const double* k, double* T, double* tb, double* b);
+
 /* Solve A p = b for each sample of the batch (operator as produced by
  * mlmc_assemble) with conjugate gradients preconditioned by one symmetric
  * geometric multigrid cycle (Section 3.5; aggregation coarsening with
@@ -272,6 +291,13 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
  * k, p device [batch][m]^d; q_out, q_in device [batch]. */
 mlmc_status mlmc_qoi_outflow(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
                              const double* p, double* q_out, double* q_in);
+
+/* Model Problem 1's QoI M^(1) (Section 3.4) of the discrete, cell-wise constant
+ * pressure: the mean over the box [lo, hi]^d (0 <= lo < hi <= 1),
+ *   q[s] = sum over cells P of p_P |P cap [lo, hi]^d| / (hi - lo)^d.
+ * p device [batch][m]^d; q device [batch]. */
+mlmc_status mlmc_qoi_box_mean(mlmc_ctx* ctx, int dim, int m, int batch, const double* p,
+                              double lo, double hi, double* q);
 
 /* One level of the estimator for samples first_sample .. first_sample + n - 1:
  * sample (fine grid m_fine), assemble, solve, QoI; for level >= 1 also the

@@ -16,12 +16,17 @@
     5. y = FFT(sqrt(Lambda / n_ce^d) * xi): Re y and Im y are two
        independent samples of the zero-mean field on the torus;
     6. keep the grid points [0, m)^d.
-  Layers 2p and 2p+1 take Re and Im of the embedding sample of pair p
-  (noise stream tag 2 + p).  Noise point (k2, k1) takes (z0, z1) of block
+  Layers share embedding samples ("pairs") only when their (sigma^2, lambda)
+  agree: layer l, in order, takes the Im part of the first earlier pair with
+  its own (sigma^2, lambda) whose Im part is still free, and otherwise opens a
+  new pair and takes its Re part.  Pair p draws its noise from stream tag
+  2 + p and uses the eigenvalues of its own covariance (Section 3.4's three
+  layers: bottom and top with lambda 0.3 share pair 0 as Re and Im, the middle
+  layer with lambda 0.1 has pair 1).  Equal parameters give layers 2p, 2p+1
+  the Re and Im parts of pair p.  Noise point (k2, k1) takes (z0, z1) of block
   (k2 // 2) n_ce + k1 when k2 is even and (z2, z3) of that block when k2 is
   odd (3-D: block ((k3 n_ce + k2) // 2) n_ce + k1 with the same parity rule
-  on k3 n_ce + k2).
-  All layers of a correlated model share sigma^2, lambda and the norm r.
+  on k3 n_ce + k2).  All layers share the norm r and the embedding size.
 * The composite sample is k(x_ij) = exp(mu_l + g_l(x_ij)) with l the layer
   of the cell centre (Section 2: the partition is independent of k).
 * Plain MLMC coarse sample (eq. (3.6): coarse and fine from the same omega):
@@ -144,24 +149,42 @@ def ce_pair_sample(model, level, sample, pair, m, n_ce, lam_eig):
     return ce_transform(xi, lam_eig, m)
 
 
+def ce_pairs(model):
+    """Embedding samples of a correlated model, in order: [sigma2, lambda,
+    [layer taking Re, layer taking Im or None]] (rule in the module doc)."""
+    pairs = []
+    for l in range(model.n_layers):
+        key = (float(model.sigma2[l]), float(model.lam[l]))
+        for p in pairs:
+            if (p[0], p[1]) == key and p[2][1] is None:
+                p[2][1] = l
+                break
+        else:
+            pairs.append([key[0], key[1], [l, None]])
+    return pairs
+
+
 def gaussian_layers(model, level, sample, m, n_ce=None, lam_eig=None):
-    """Zero-mean Gaussian field of every layer at the m^d cell centres."""
+    """Zero-mean Gaussian field of every layer at the m^d cell centres.
+    lam_eig: eigenvalues for pairs with the covariance of layer 0 (optional)."""
     if n_ce is None:
         n_ce = model.n_ce[m]
-    if lam_eig is None:
-        lam_eig = ce_eigenvalues(n_ce, m, model.sigma2[0], model.lam[0], model.norm_r, model.dim)
-    g = []
-    for pair in range((model.n_layers + 1) // 2):
-        re, im = ce_pair_sample(model, level, sample, pair, m, n_ce, lam_eig)
-        g.append(re)
-        g.append(im)
-    return g[:model.n_layers]
+    g = [None] * model.n_layers
+    for p, (sigma2, lam, (l_re, l_im)) in enumerate(ce_pairs(model)):
+        if lam_eig is not None and (sigma2, lam) == (model.sigma2[0], model.lam[0]):
+            eig = lam_eig
+        else:
+            eig = ce_eigenvalues(n_ce, m, sigma2, lam, model.norm_r, model.dim)
+        re, im = ce_pair_sample(model, level, sample, p, m, n_ce, eig)
+        g[l_re] = re
+        if l_im is not None:
+            g[l_im] = im
+    return g
 
 
 def check_ce_model(model):
-    for l in range(1, model.n_layers):
-        if model.sigma2[l] != model.sigma2[0] or model.lam[l] != model.lam[0]:
-            raise ValueError("correlated layers must share sigma^2 and lambda")
+    if not 1 <= model.n_layers <= 4:
+        raise ValueError("1 to 4 layers")
 
 
 # ------------------------------------------------------------ composite k

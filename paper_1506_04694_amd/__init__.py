@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "MLMC_OK", 1: "MLMC_EINVAL", 2: "MLMC_ENOMEM", 3: "MLMC_EDEVI
                 4: "MLMC_EBUSY", 5: "MLMC_ENOCONV", 6: "MLMC_EEMBED"}
 MLMC_SAMPLE_OK, MLMC_SAMPLE_NOCONV, MLMC_SAMPLE_BREAKDOWN = 0, 1, 2
 MLMC_PREC_FP64, MLMC_PREC_FP32, MLMC_PREC_BF16 = 0, 1, 2
+MLMC_PROBLEM_OUTFLOW, MLMC_PROBLEM_MEAN_PRESSURE = 0, 1
 
 EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_last_error",
             "mlmc_solver_opts_default", "mlmc_ce_min_embedding", "mlmc_sample_field",
@@ -33,14 +34,15 @@ EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_
             "mlmc_level_run", "mlmc_estimate", "mlmc_profile_enable", "mlmc_profile_read",
             "mlmc_sample_field_ids", "mlmc_level_run_ids", "mlmc_serve_opts_default",
             "mlmc_serve_start", "mlmc_serve_submit", "mlmc_serve_poll", "mlmc_serve_now",
-            "mlmc_serve_stats", "mlmc_serve_stop", "mlmc_run_levels", "mlmc_serve_start_models"]
+            "mlmc_serve_stats", "mlmc_serve_stop", "mlmc_run_levels", "mlmc_serve_start_models",
+            "mlmc_assemble_problem", "mlmc_qoi_box_mean"]
 
 
 class mlmc_model(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("interface_kind", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int32), ("n_layers", ctypes.c_int32),
                 ("field_kind", ctypes.c_int32), ("norm_r", ctypes.c_int32),
-                ("n_ce", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_ce", ctypes.c_int32), ("problem", ctypes.c_int32),
                 ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
                 ("mu", ctypes.c_double * 4), ("sigma2", ctypes.c_double * 4),
                 ("lambda_", ctypes.c_double * 4), ("seed", ctypes.c_uint64)]
@@ -143,6 +145,8 @@ _SIGS = {
                              ctypes.POINTER(mlmc_level_sums)]),
     "mlmc_profile_read": (_S, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double)]),
+    "mlmc_assemble_problem": (_S, [_P, _I, _I, _I, _I, _P, _P, _P, _P]),
+    "mlmc_qoi_box_mean": (_S, [_P, _I, _I, _I, _P, ctypes.c_double, ctypes.c_double, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -205,6 +209,7 @@ def make_model(model, n_ce=0):
         mm.sigma2[l] = float(model.sigma2[l])
         mm.lambda_[l] = float(model.lam[l])
     mm.seed = int(model.seed)
+    mm.problem = int(getattr(model, "problem", 0))
     return mm
 
 
@@ -278,6 +283,21 @@ def mlmc_assemble(ctx, dim, m, batch, k, T, tb, b):
     _check(ctx, _lib.mlmc_assemble(ctx, d, int(m), int(batch), _f64(k, n, "k"),
                                    _f64(T, d * n, "T"), _f64(tb, d * batch * m ** (d - 1), "tb"),
                                    _f64(b, n, "b")))
+
+
+def mlmc_assemble_problem(ctx, problem, dim, m, batch, k, T, tb, b):
+    d = int(dim)
+    n = batch * m ** d
+    _check(ctx, _lib.mlmc_assemble_problem(ctx, int(problem), d, int(m), int(batch),
+                                           _f64(k, n, "k"), _f64(T, d * n, "T"),
+                                           _f64(tb, d * batch * m ** (d - 1), "tb"),
+                                           _f64(b, n, "b")))
+
+
+def mlmc_qoi_box_mean(ctx, dim, m, batch, p, lo, hi, q):
+    d = int(dim)
+    _check(ctx, _lib.mlmc_qoi_box_mean(ctx, d, int(m), int(batch), _f64(p, batch * m ** d, "p"),
+                                       float(lo), float(hi), _f64(q, batch, "q")))
 
 
 def mlmc_solve(ctx, dim, m, batch, T, tb, b, p, opts, status, iters, relres):

@@ -212,6 +212,8 @@ mlmc_status check_model(mlmc_ctx* ctx, const mlmc_model* mdl) {
     return fail(ctx, MLMC_EINVAL, "unknown field_kind");
   }
   if (!(mdl->y_lo <= mdl->y_hi)) return fail(ctx, MLMC_EINVAL, "y_lo > y_hi");
+  if (mdl->problem != MLMC_PROBLEM_OUTFLOW && mdl->problem != MLMC_PROBLEM_MEAN_PRESSURE)
+    return fail(ctx, MLMC_EINVAL, "unknown problem");
   return MLMC_OK;
 }
 
@@ -484,23 +486,54 @@ mlmc_status mlmc_cgv_extract(mlmc_ctx* ctx, int dim, int m, int batch, const dou
   return MLMC_OK;
 }
 
-mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double* k, double* T,
-                          double* tb, double* b) {
+mlmc_status mlmc_assemble_problem(mlmc_ctx* ctx, int problem, int dim, int m, int batch,
+                                  const double* k, double* T, double* tb, double* b) {
   if (!ctx) return MLMC_EINVAL;
   if (dim != 2 && dim != 3) return fail(ctx, MLMC_EINVAL, "dim must be 2 or 3");
+  if (problem != MLMC_PROBLEM_OUTFLOW && problem != MLMC_PROBLEM_MEAN_PRESSURE)
+    return fail(ctx, MLMC_EINVAL, "unknown problem");
   if (m < 1 || batch < 0 || !k || !T || !tb || !b)
     return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_assemble");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
   if (dim == 3) {
-    launch_assemble3(ctx->stream, m, batch, k, T, tb, b);
+    launch_assemble3(ctx->stream, problem, m, batch, k, T, tb, b);
     CHECK_LAUNCH();
     return MLMC_OK;
   }
   timed(ctx, "k_assemble", (double)batch * m * m * 40.0,
-        [&] { launch_assemble(ctx->stream, m, batch, k, T, tb, b); });
+        [&] { launch_assemble(ctx->stream, problem, m, batch, k, T, tb, b); });
   CHECK_LAUNCH();
   return MLMC_OK;
+}
+
+mlmc_status mlmc_assemble(mlmc_ctx* ctx, int dim, int m, int batch, const double* k, double* T,
+                          double* tb, double* b) {
+  return mlmc_assemble_problem(ctx, MLMC_PROBLEM_OUTFLOW, dim, m, batch, k, T, tb, b);
+}
+
+mlmc_status mlmc_qoi_box_mean(mlmc_ctx* ctx, int dim, int m, int batch, const double* p,
+                              double lo, double hi, double* q) {
+  if (!ctx) return MLMC_EINVAL;
+  if (dim != 2 && dim != 3) return fail(ctx, MLMC_EINVAL, "dim must be 2 or 3");
+  if (m < 1 || batch < 0 || !p || !q || !(lo >= 0.0) || !(hi <= 1.0) || !(lo < hi))
+    return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_qoi_box_mean");
+  if (batch == 0) return MLMC_OK;
+  (void)hipSetDevice(ctx->device);
+  launch_qoi_box(ctx->stream, dim, m, batch, lo, hi, p, q);
+  CHECK_LAUNCH();
+  return MLMC_OK;
+}
+
+// D* of Model Problem 1 in the level runs: the centred box of side 1/8.
+constexpr double kMp1Lo = 0.5 - 1.0 / 16.0, kMp1Hi = 0.5 + 1.0 / 16.0;
+
+// The QoI of the model's problem for a solved batch.
+static mlmc_status model_qoi(mlmc_ctx* ctx, const mlmc_model* model, int dim, int m, int batch,
+                             const double* k, const double* p, double* q) {
+  if (model->problem == MLMC_PROBLEM_MEAN_PRESSURE)
+    return mlmc_qoi_box_mean(ctx, dim, m, batch, p, kMp1Lo, kMp1Hi, q);
+  return mlmc_qoi_outflow(ctx, dim, m, batch, k, p, q, nullptr);
 }
 
 mlmc_status mlmc_qoi_outflow(mlmc_ctx* ctx, int dim, int m, int batch, const double* k,
@@ -1161,9 +1194,9 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
                         (ncomp == 1) ? kc : nullptr));
   if (ncomp > 1) TRY(mlmc_cgv_extract(ctx, d, m, n, k, kc));
 
-  TRY(mlmc_assemble(ctx, d, m, n, k, T, tb, b));
+  TRY(mlmc_assemble_problem(ctx, model->problem, d, m, n, k, T, tb, b));
   TRY(mlmc_solve(ctx, d, m, n, T, tb, b, p, opts, stf, itf, relres));
-  TRY(mlmc_qoi_outflow(ctx, d, m, n, k, p, qf, nullptr));
+  TRY(model_qoi(ctx, model, d, m, n, k, p, qf));
 
   double* qcv = nullptr;
   int32_t *stc = nullptr, *itc = nullptr;
@@ -1178,9 +1211,9 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
     TRY(ws(ctx, "lr_qc", n, &qcv));
     TRY(ws(ctx, "lr_stc", nb, &stc));
     TRY(ws(ctx, "lr_itc", nb, &itc));
-    TRY(mlmc_assemble(ctx, d, mc, nb, kc, Tc, tbc, bc));
+    TRY(mlmc_assemble_problem(ctx, model->problem, d, mc, nb, kc, Tc, tbc, bc));
     TRY(mlmc_solve(ctx, d, mc, nb, Tc, tbc, bc, pc, opts, stc, itc, relres));
-    TRY(mlmc_qoi_outflow(ctx, d, mc, nb, kc, pc, qcomp, nullptr));
+    TRY(model_qoi(ctx, model, d, mc, nb, kc, pc, qcomp));
     launch_cgv_average(st, n, ncomp, qcomp, qcv);
   }
   launch_y_and_fail(st, n, qf, qcv, stf, stc, ncomp, yv, failed);
@@ -1336,10 +1369,11 @@ mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group& g = groups[gi];
     if (g.count == 0) continue;
-    TRY(mlmc_assemble(ctx, 2, g.m, (int)g.count, gb[gi].k, gb[gi].T, gb[gi].tb, gb[gi].b));
+    TRY(mlmc_assemble_problem(ctx, model->problem, 2, g.m, (int)g.count, gb[gi].k, gb[gi].T,
+                              gb[gi].tb, gb[gi].b));
     TRY(mlmc_solve(ctx, 2, g.m, (int)g.count, gb[gi].T, gb[gi].tb, gb[gi].b, gb[gi].p,
                    &opts[g.opts_level], gb[gi].stt, gb[gi].it, gb[gi].rr));
-    TRY(mlmc_qoi_outflow(ctx, 2, g.m, (int)g.count, gb[gi].k, gb[gi].p, gb[gi].q, nullptr));
+    TRY(model_qoi(ctx, model, 2, g.m, (int)g.count, gb[gi].k, gb[gi].p, gb[gi].q));
   }
   // per level: Y, failures, sums
   double *yv, *qcv, *out;

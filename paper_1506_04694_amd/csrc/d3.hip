@@ -69,7 +69,10 @@ __device__ __forceinline__ void cell_of(long long rem, int m, int& i, int& j, in
 }
 
 // ------------------------------------------------------------------ assembly
-__global__ void k_assemble3(int m, long long total, const double* __restrict__ k,
+// Model Problem 2 as in 2-D, with T scaled by the face area / centre distance
+// h^2 / h = h; Model Problem 1: every boundary face Dirichlet (T = 2 k h),
+// b = f h^3 = h^3.
+__global__ void k_assemble3(int problem, int m, long long total, const double* __restrict__ k,
                             double* __restrict__ T, double* __restrict__ tb,
                             double* __restrict__ b) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,22 +87,24 @@ __global__ void k_assemble3(int m, long long total, const double* __restrict__ k
   const double* ks = k + s * n;
   const double kc = ks[c];
   double* Ts = T + s * 3 * n;
-  Ts[c] = i < m - 1 ? h * (2.0 * kc * ks[c + 1] / (kc + ks[c + 1])) : 2.0 * kc * h;
-  Ts[n + c] = j < m - 1 ? h * (2.0 * kc * ks[c + m] / (kc + ks[c + m])) : 0.0;
-  Ts[2 * n + c] = l < m - 1 ? h * (2.0 * kc * ks[c + mm] / (kc + ks[c + mm])) : 0.0;
-  double* tbs = tb + s * 3 * mm;
+  const bool mp1 = problem == MLMC_PROBLEM_MEAN_PRESSURE;
   const double tw = 2.0 * kc * h;
+  const double side = mp1 ? tw : 0.0;  // faces x2 = 0, 1 and x3 = 0, 1
+  Ts[c] = i < m - 1 ? h * (2.0 * kc * ks[c + 1] / (kc + ks[c + 1])) : tw;
+  Ts[n + c] = j < m - 1 ? h * (2.0 * kc * ks[c + m] / (kc + ks[c + m])) : side;
+  Ts[2 * n + c] = l < m - 1 ? h * (2.0 * kc * ks[c + mm] / (kc + ks[c + mm])) : side;
+  double* tbs = tb + s * 3 * mm;
   if (i == 0) tbs[l * m + j] = tw;
-  if (j == 0) tbs[mm + l * m + i] = 0.0;
-  if (l == 0) tbs[2 * mm + j * m + i] = 0.0;
-  b[g] = i == 0 ? tw : 0.0;
+  if (j == 0) tbs[mm + l * m + i] = side;
+  if (l == 0) tbs[2 * mm + j * m + i] = side;
+  b[g] = mp1 ? h * h * h : (i == 0 ? tw : 0.0);
 }
 
-void launch_assemble3(hipStream_t st, int m, int batch, const double* k, double* T, double* tb,
-                      double* b) {
+void launch_assemble3(hipStream_t st, int problem, int m, int batch, const double* k, double* T,
+                      double* tb, double* b) {
   const long long total = (long long)batch * m * m * m;
-  hipLaunchKernelGGL(k_assemble3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, k, T,
-                     tb, b);
+  hipLaunchKernelGGL(k_assemble3, dim3(blocks_for(total)), dim3(kBlock), 0, st, problem, m, total,
+                     k, T, tb, b);
 }
 
 // ------------------------------------------------------------------ QoI

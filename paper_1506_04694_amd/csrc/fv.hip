@@ -6,8 +6,13 @@
 // x1 = 0 and x1 = 1 (half-cell distance), T = 0 on the no-flow faces; the
 // inflow data p = 1 enters the right-hand side b = T on column i = 0.
 //
+// Model Problem 1 (Section 3.4): f = 1 and p = 0 on the whole boundary, so
+// every boundary face is a Dirichlet face (T = 2 k_P) and b = f h^2 = h^2.
+//
 // QoI (Section 3.4, M^(2)): outflow through x1 = 1 as the sum of the
 // boundary-face fluxes 2 k p over the last column; inflow likewise at x1 = 0.
+// M^(1): the mean of the cell-wise constant pressure over a box [lo, hi]^d,
+// each cell weighted by its overlap with the box.
 //
 // Estimator sums (eq. (3.6), (3.7), (4.2)): one workgroup reduces a level's
 // Y, Q_f, Q_c in a fixed order (per-thread strided sums, then a fixed tree),
@@ -17,7 +22,7 @@
 
 namespace mlmc {
 
-__global__ void k_assemble(int m, long long total, const double* __restrict__ k,
+__global__ void k_assemble(int problem, int m, long long total, const double* __restrict__ k,
                            double* __restrict__ T, double* __restrict__ tb,
                            double* __restrict__ b) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -34,26 +39,28 @@ __global__ void k_assemble(int m, long long total, const double* __restrict__ k,
   } else {
     te = 2.0 * kp;
   }
+  const bool mp1 = problem == MLMC_PROBLEM_MEAN_PRESSURE;
   if (j < m - 1) {
     const double kq = k[g + m];
     tn = 2.0 * kp * kq / (kp + kq);
   } else {
-    tn = 0.0;
+    tn = mp1 ? 2.0 * kp : 0.0;
   }
   double* Ts = T + s * 2 * n;
   Ts[rem] = te;
   Ts[n + rem] = tn;
-  b[g] = (i == 0) ? 2.0 * kp : 0.0;
+  const double h = 1.0 / (double)m;
+  b[g] = mp1 ? h * h : ((i == 0) ? 2.0 * kp : 0.0);
   double* tbs = tb + s * 2 * m;
   if (i == 0) tbs[j] = 2.0 * kp;
-  if (j == 0) tbs[m + i] = 0.0;
+  if (j == 0) tbs[m + i] = mp1 ? 2.0 * kp : 0.0;
 }
 
-void launch_assemble(hipStream_t st, int m, int batch, const double* k, double* T, double* tb,
-                     double* b) {
+void launch_assemble(hipStream_t st, int problem, int m, int batch, const double* k, double* T,
+                     double* tb, double* b) {
   const long long total = (long long)batch * m * m;
-  hipLaunchKernelGGL(k_assemble, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, k, T,
-                     tb, b);
+  hipLaunchKernelGGL(k_assemble, dim3(blocks_for(total)), dim3(kBlock), 0, st, problem, m, total,
+                     k, T, tb, b);
 }
 
 // One wave per sample.
@@ -83,6 +90,50 @@ void launch_qoi(hipStream_t st, int m, int batch, const double* k, const double*
   const long long threads = (long long)batch * kWave;
   hipLaunchKernelGGL(k_qoi, dim3(blocks_for(threads)), dim3(kBlock), 0, st, m, batch, k, p, qout,
                      qin);
+}
+
+// Overlap of cell i's interval [i/m, (i+1)/m] with [lo, hi].
+__device__ __forceinline__ double cell_overlap(int i, int m, double lo, double hi) {
+  const double a = (double)i / (double)m, b = (double)(i + 1) / (double)m;
+  return fmax(fmin(b, hi) - fmax(a, lo), 0.0);
+}
+
+// M^(1) over [lo, hi]^d, one wave per sample: the lanes take the cells of the
+// box's index range in turn (the cells with nonzero overlap lie in [i0, i1) on
+// every axis), then a fixed shuffle tree.
+__global__ void k_qoi_box(int dim, int m, int batch, int i0, int i1, double lo, double hi,
+                          const double* __restrict__ p, double* __restrict__ q) {
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (wave >= batch) return;
+  const int w = i1 - i0;
+  const long long per = dim == 3 ? (long long)m * m * m : (long long)m * m;
+  const double* ps = p + wave * per;
+  const int cells = dim == 3 ? w * w * w : w * w;
+  double acc = 0.0;
+  for (int t = lane; t < cells; t += kWave) {
+    const int a = t % w, r = t / w;
+    const int i = i0 + a, j = i0 + r % w, l = dim == 3 ? i0 + r / w : 0;
+    double wt = cell_overlap(i, m, lo, hi) * cell_overlap(j, m, lo, hi);
+    if (dim == 3) wt *= cell_overlap(l, m, lo, hi);
+    acc += wt * ps[((long long)l * m + j) * m + i];
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const double side = hi - lo;
+    q[wave] = acc / (dim == 3 ? side * side * side : side * side);
+  }
+}
+
+void launch_qoi_box(hipStream_t st, int dim, int m, int batch, double lo, double hi,
+                    const double* p, double* q) {
+  // index range of the cells that meet the box (clamped to the grid)
+  int i0 = (int)floor(lo * m) - 1, i1 = (int)ceil(hi * m) + 1;
+  i0 = i0 < 0 ? 0 : i0;
+  i1 = i1 > m ? m : i1;
+  const long long threads = (long long)batch * kWave;
+  hipLaunchKernelGGL(k_qoi_box, dim3(blocks_for(threads)), dim3(kBlock), 0, st, dim, m, batch, i0,
+                     i1, lo, hi, p, q);
 }
 
 // Q^cgv = 2^-d sum_j Q(k^(j))  (eq. (4.1)); companions of sample s at s*ncomp + j.

@@ -32,8 +32,10 @@ void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, int batch, int m,
 void launch_cgv_extract(hipStream_t st, int m, int batch, const double* kf, double* ksub);
 
 // ------------------------------------------------------------- fv.hip
-void launch_assemble(hipStream_t st, int m, int batch, const double* k, double* T, double* tb,
-                     double* b);
+void launch_assemble(hipStream_t st, int problem, int m, int batch, const double* k, double* T,
+                     double* tb, double* b);
+void launch_qoi_box(hipStream_t st, int dim, int m, int batch, double lo, double hi,
+                    const double* p, double* q);
 void launch_qoi(hipStream_t st, int m, int batch, const double* k, const double* p, double* qout,
                 double* qin);
 void launch_cgv_average(hipStream_t st, int batch, int ncomp, const double* qcomp, double* qc);
@@ -149,8 +151,8 @@ inline int blocks_per_sample(long long n) { return (int)((n + kCellsPerBlock - 1
 
 // ---- 3-D path (d3.hip): layout T[s][3][m^3], tb[s][3][m^2] (west, south,
 // bottom faces), k, b, x [s][m^3] with x1 fastest.
-void launch_assemble3(hipStream_t st, int m, int batch, const double* k, double* T, double* tb,
-                      double* b);
+void launch_assemble3(hipStream_t st, int problem, int m, int batch, const double* k, double* T,
+                      double* tb, double* b);
 void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double* p, double* qout,
                  double* qin);
 void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const double* tb,

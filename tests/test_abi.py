@@ -48,7 +48,7 @@ int main(void) {
          sizeof(mlmc_model), sizeof(mlmc_solver_opts), sizeof(mlmc_level_sums),
          sizeof(mlmc_estimate_t));
   P(mlmc_model, y_lo); P(mlmc_model, mu); P(mlmc_model, sigma2); P(mlmc_model, lambda);
-  P(mlmc_model, seed); P(mlmc_solver_opts, maxit); P(mlmc_solver_opts, check_every); P(mlmc_solver_opts, gamma); P(mlmc_solver_opts, gamma_levels); P(mlmc_solver_opts, graph);
+  P(mlmc_model, seed); P(mlmc_model, problem); P(mlmc_solver_opts, maxit); P(mlmc_solver_opts, check_every); P(mlmc_solver_opts, gamma); P(mlmc_solver_opts, gamma_levels); P(mlmc_solver_opts, graph);
   P(mlmc_level_sums, sum_y); P(mlmc_level_sums, iters_coarse);
   printf("mlmc_serve_opts %zu\nmlmc_request %zu\nmlmc_result %zu\n", sizeof(mlmc_serve_opts),
          sizeof(mlmc_request), sizeof(mlmc_result));
@@ -75,6 +75,7 @@ def test_struct_layouts_match_header(lib, tmp_path):
     assert int(vals["mlmc_model.lambda"]) == lib.mlmc_model.lambda_.offset
     assert int(vals["mlmc_model.seed"]) == lib.mlmc_model.seed.offset
     assert int(vals["mlmc_model.y_lo"]) == lib.mlmc_model.y_lo.offset
+    assert int(vals["mlmc_model.problem"]) == lib.mlmc_model.problem.offset
     assert int(vals["mlmc_solver_opts.check_every"]) == lib.mlmc_solver_opts.check_every.offset
     assert int(vals["mlmc_solver_opts.gamma"]) == lib.mlmc_solver_opts.gamma.offset
     assert int(vals["mlmc_solver_opts.gamma_levels"]) == lib.mlmc_solver_opts.gamma_levels.offset

@@ -105,6 +105,16 @@ STATIONARY_1NORM_3D = STATIONARY_1NORM.with_(dim=3)
 MP1_CE2 = CE2.with_(problem=1)
 MP1_LAYERED = Workload("2d-ce-8node-mp1-64-512", MP1_CE2, [64, 128, 256, 512],
                        [4096, 1024, 256, 64])
+# Section 3.4's piecewise correlated model: three layers between two random
+# lines; bottom and top mean 0, lambda 0.3; middle mean 4, lambda 0.1; all
+# sigma^2 = 1, 2-norm covariance, independent layers; the embedding sizes of the
+# lambda = 0.3 layers (valid for lambda = 0.1 too).
+PAPER3_CE = Model(interface_kind=PAPER_TWO_LINES, n_layers=3, field_kind=CORRELATED_CE,
+                  norm_r=2, mu=(0.0, 4.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0),
+                  lam=(0.3, 0.1, 0.3, 0.3), seed=0,
+                  n_ce={8: 16, 16: 32, 32: 72, 64: 135, 128: 375, 256: 960, 512: 1875})
+PAPER3_LAYERED = Workload("2d-ce-paper3-64-512", PAPER3_CE, [64, 128, 256, 512],
+                          [4096, 1024, 256, 64])
 MP1_PAPER3 = Model(interface_kind=PAPER_TWO_LINES, n_layers=3, field_kind=PIECEWISE_CONSTANT,
                    mu=(0.0, 0.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0), seed=0, problem=1)
 
