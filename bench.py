@@ -324,7 +324,9 @@ def other_configs(lib, torch, steps):
       FP32 and bfloat16 inside the FP64 CG, with the largest relative QoI
       difference of each reduced precision to the FP64 solve of the same samples;
     * Section 4.2's variance experiment (cgv_variance);
-    * Model Problem 1 on the bench workload's levels, level by level."""
+    * Model Problem 1 on the bench workload's levels, level by level;
+    * Section 3.4's three-layer correlated model (per-layer correlation lengths),
+      both model problems, all levels in one call."""
     ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
     opts = lib.mlmc_solver_opts_default()
 
@@ -404,13 +406,32 @@ def other_configs(lib, torch, steps):
                 iters[level] = s.iters_fine / n
 
         t = timed(mp1_levels)
-        out["model_problem_1"] = {
+        mp1 = {
             "workload": wl.name, "levels_m": wl.m_levels, "samples": wl.n_samples,
             "qoi": "mean pressure over [7/16, 9/16]^2", "dtype": "f64",
             "value": total / t, "ms_per_step": 1e3 * t,
             "per_level": [{"level": l, "m": m, "ms": sorted(lv_ms[l])[len(lv_ms[l]) // 2],
                            "mean_iters_fine": iters[l]}
                           for l, m in enumerate(wl.m_levels)]}
+        out["model_problem_1"] = mp1
+
+        # Section 3.4's three layers (lambda 0.3 / 0.1 / 0.3, means 0 / 4 / 0; two
+        # embedding samples per field) on the bench levels, both model problems
+        wl = W.PAPER3_LAYERED
+        total = sum(wl.n_samples)
+        runs = {}
+        for name, problem in (("model_problem_2", 0), ("model_problem_1", 1)):
+            mdl = wl.model.with_(problem=problem)
+
+            def levels(idx):
+                lib.mlmc_run_levels(ctx, mdl, wl.m_levels, [idx * n for n in wl.n_samples],
+                                    wl.n_samples, False, opts)
+
+            t = timed(levels)
+            runs[name] = {"value": total / t, "ms_per_step": 1e3 * t}
+        out["paper_three_layers"] = {"workload": wl.name, "levels_m": wl.m_levels,
+                                     "samples": wl.n_samples, "dtype": "f64",
+                                     "all_levels_one_call": runs}
     finally:
         lib.mlmc_ctx_destroy(ctx)
     return out

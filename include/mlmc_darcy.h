@@ -91,9 +91,10 @@ enum {
 enum {
   MLMC_FIELD_PIECEWISE_CONSTANT = 0, /* Example 1: k_l = exp(mu_l + sqrt(sigma2_l) z_l) */
   MLMC_FIELD_CORRELATED = 1          /* Example 2: k = exp(mu_l + g_l(x)), g_l Gaussian
-                                        with covariance eq. (2.3), sampled by circulant
-                                        embedding; all layers share sigma2, lambda, r;
-                                        at most 2 layers                               */
+                                        with covariance eq. (2.3) of the layer's own
+                                        sigma2, lambda (all layers share r and n_ce),
+                                        sampled by circulant embedding; independent
+                                        across layers                                  */
 };
 
 /*
@@ -102,11 +103,14 @@ enum {
  * Random streams (Philox4x32-10, key = seed, counter = (block, sample number,
  * level, tag)): tag 0 geometry uniforms (uniform q = word q%4 of block q/4),
  * tag 1 layer constants (normals z0..z3 of block 0 by Box-Muller), tag 2
- * circulant-embedding noise (noise point (k2, k1) takes (z0, z1) of block
- * (k2/2)*n_ce + k1 for even k2 and (z2, z3) of that block for odd k2; real
- * part -> layer 0, imaginary part -> layer 1).  In 3-D the noise lines along
- * x1 are numbered row = k3 n_ce + k2 and take the same rule with row in place
- * of k2.
+ * circulant-embedding noise of embedding sample p at tag 2 + p (noise point
+ * (k2, k1) takes (z0, z1) of block (k2/2)*n_ce + k1 for even k2 and (z2, z3)
+ * of that block for odd k2).  Layers share an embedding sample only when their
+ * (sigma2, lambda) agree: layer l, in order, takes the imaginary part of the
+ * first earlier sample with its covariance whose imaginary part is free, else
+ * the real part of a new sample (two layers of one covariance: real part ->
+ * layer 0, imaginary part -> layer 1).  In 3-D the noise lines along x1 are
+ * numbered row = k3 n_ce + k2 and take the same rule with row in place of k2.
  */
 typedef struct mlmc_model {
   int32_t dim;            /* 2 or 3                                             */
@@ -203,7 +207,8 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* opts);
 
 /* Circulant embedding (Section 3.4, exact sampling of eq. (2.3) on a grid):
  * smallest n_ce >= 2m with prime factors in {2,3,5} whose embedding
- * eigenvalues satisfy min >= -1e-12 max.  Synchronises the stream.
+ * eigenvalues satisfy min >= -1e-12 max for every layer's covariance.
+ * Synchronises the stream.
  * n_ce_out: host. */
 mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m, int* n_ce_out);
 

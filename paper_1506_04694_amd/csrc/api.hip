@@ -201,12 +201,8 @@ mlmc_status check_model(mlmc_ctx* ctx, const mlmc_model* mdl) {
     if (!(mdl->sigma2[l] >= 0.0) || !std::isfinite(mdl->mu[l]))
       return fail(ctx, MLMC_EINVAL, "layer parameters must be finite with sigma2 >= 0");
   if (mdl->field_kind == MLMC_FIELD_CORRELATED) {
-    if (mdl->n_layers > 2)
-      return fail(ctx, MLMC_EINVAL, "correlated fields support at most 2 layers");
-    for (int l = 1; l < mdl->n_layers; ++l)
-      if (mdl->sigma2[l] != mdl->sigma2[0] || mdl->lambda[l] != mdl->lambda[0])
-        return fail(ctx, MLMC_EINVAL, "correlated layers must share sigma2 and lambda");
-    if (!(mdl->lambda[0] > 0.0)) return fail(ctx, MLMC_EINVAL, "lambda must be positive");
+    for (int l = 0; l < mdl->n_layers; ++l)
+      if (!(mdl->lambda[l] > 0.0)) return fail(ctx, MLMC_EINVAL, "lambda must be positive");
     if (mdl->norm_r != 1 && mdl->norm_r != 2) return fail(ctx, MLMC_EINVAL, "norm_r must be 1 or 2");
   } else if (mdl->field_kind != MLMC_FIELD_PIECEWISE_CONSTANT) {
     return fail(ctx, MLMC_EINVAL, "unknown field_kind");
@@ -385,17 +381,46 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* o) {
   return MLMC_OK;
 }
 
+// Embedding samples of a correlated model: layer l, in order, takes the
+// imaginary part of the first earlier sample with its own (sigma2, lambda)
+// whose imaginary part is free, else starts a new sample (real part); sample p
+// draws its noise from stream tag 2 + p.  Returns the number of samples.
+static int ce_pairs(const mlmc_model* mdl, CePair* pr) {
+  int np = 0;
+  for (int l = 0; l < mdl->n_layers; ++l) {
+    int q = 0;
+    for (; q < np; ++q)
+      if (pr[q].l_im < 0 && mdl->sigma2[pr[q].l_re] == mdl->sigma2[l] &&
+          mdl->lambda[pr[q].l_re] == mdl->lambda[l])
+        break;
+    if (q < np) {
+      pr[q].l_im = l;
+      pr[q].mu_im = mdl->mu[l];
+    } else {
+      pr[np] = CePair{kTagNoise + (uint32_t)np, l, -1, mdl->mu[l], 0.0};
+      ++np;
+    }
+  }
+  return np;
+}
+
 mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m, int* n_ce_out) {
   if (!ctx || !n_ce_out) return MLMC_EINVAL;
   TRY(check_model(ctx, model));
   if (m < 1) return fail(ctx, MLMC_EINVAL, "m must be positive");
   (void)hipSetDevice(ctx->device);
   const int n_max = model->dim == 3 ? kFftMax3 : kFftMax;
+  CePair pr[4];
+  const int np = ce_pairs(model, pr);
   for (int n = 2 * m; n <= n_max; ++n) {
     if (!five_smooth(n)) continue;
-    CeEntry* e = nullptr;
-    mlmc_status s =
-        ce_get(ctx, model->dim, m, n, model->sigma2[0], model->lambda[0], model->norm_r, &e);
+    // the smallest size that embeds every pair's covariance
+    mlmc_status s = MLMC_OK;
+    for (int q = 0; q < np && s == MLMC_OK; ++q) {
+      CeEntry* e = nullptr;
+      const int l = pr[q].l_re;
+      s = ce_get(ctx, model->dim, m, n, model->sigma2[l], model->lambda[l], model->norm_r, &e);
+    }
     if (s == MLMC_OK) {
       *n_ce_out = n;
       ctx->err.clear();
@@ -433,29 +458,39 @@ static mlmc_status sample_field_impl(mlmc_ctx* ctx, const mlmc_model* model, int
     CHECK_LAUNCH();
     return MLMC_OK;
   }
-  CeEntry* e = nullptr;
-  TRY(ce_get(ctx, model->dim, m, model->n_ce, model->sigma2[0], model->lambda[0], model->norm_r,
-             &e));
-  if (model->dim == 3) {
-    const int nn = e->n;
-    double2 *u1 = nullptr, *u2 = nullptr;
-    TRY(ws(ctx, "ce3_u1", (size_t)batch * nn * nn * m, &u1));
-    TRY(ws(ctx, "ce3_u2", (size_t)batch * nn * m * m, &u2));
-    launch_ce3(st, *model, level, first_sample, ids, batch, m, e->sqT, e->tw, e->plan, params, u1,
-               u2, k, k_coarse);
-    CHECK_LAUNCH();
-    return MLMC_OK;
+  CePair pr[4];
+  const int np = ce_pairs(model, pr);
+  for (int q = 0; q < np; ++q) {
+    CeEntry* e = nullptr;
+    const int l = pr[q].l_re;
+    TRY(ce_get(ctx, model->dim, m, model->n_ce, model->sigma2[l], model->lambda[l], model->norm_r,
+               &e));
+    if (model->dim == 3) {
+      const int nn = e->n;
+      double2 *u1 = nullptr, *u2 = nullptr;
+      TRY(ws(ctx, "ce3_u1", (size_t)batch * nn * nn * m, &u1));
+      TRY(ws(ctx, "ce3_u2", (size_t)batch * nn * m * m, &u2));
+      launch_ce3(st, *model, pr[q], level, first_sample, ids, batch, m, e->sqT, e->tw, e->plan,
+                 params, u1, u2, k, k_coarse);
+      continue;
+    }
+    double2* uT = nullptr;
+    TRY(ws(ctx, "ce_uT", (size_t)batch * m * e->n, &uT));
+    const double cells = (double)batch * m * m;
+    const double ratio = (double)e->n / m;
+    // bytes of pass B: its reads of uT and its writes of k, which the pairs
+    // split between them (every cell is written once over all pairs)
+    const double kshare = 1.0 / np;
+    timed(ctx, "k_ce_pass_a", cells * (16.0 * ratio + 8.0 * ratio * ratio), [&] {
+      launch_ce_pass_a(st, *model, pr[q], level, first_sample, ids, batch, m, e->sqT, e->tw,
+                       e->plan, uT);
+    });
+    timed(ctx, "k_ce_pass_b", cells * (16.0 * ratio + kshare * (8.0 + (k_coarse ? 2.0 : 0.0))),
+          [&] {
+            launch_ce_pass_b(st, *model, pr[q], batch, m, uT, e->tw, e->plan, params, k,
+                             k_coarse);
+          });
   }
-  double2* uT = nullptr;
-  TRY(ws(ctx, "ce_uT", (size_t)batch * m * e->n, &uT));
-  const double cells = (double)batch * m * m;
-  const double ratio = (double)e->n / m;
-  timed(ctx, "k_ce_pass_a", cells * (16.0 * ratio + 8.0 * ratio * ratio), [&] {
-    launch_ce_pass_a(st, *model, level, first_sample, ids, batch, m, e->sqT, e->tw, e->plan, uT);
-  });
-  timed(ctx, "k_ce_pass_b", cells * (16.0 * ratio + 8.0 + (k_coarse ? 2.0 : 0.0)), [&] {
-    launch_ce_pass_b(st, *model, batch, m, uT, e->tw, e->plan, params, k, k_coarse);
-  });
   CHECK_LAUNCH();
   return MLMC_OK;
 }

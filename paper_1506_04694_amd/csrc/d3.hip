@@ -458,7 +458,8 @@ void launch_ce_sqrt3(hipStream_t st, const double2* lam, int n, double* sq) {
 // to u1[s][r][j1].
 template <int C>
 __global__ void __launch_bounds__(kBlock)
-k_ce3_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __restrict__ ids,
+k_ce3_pass_a(uint64_t seed, uint32_t tag, uint32_t level, uint64_t first,
+             const uint32_t* __restrict__ ids,
              int m, const double* __restrict__ sq, const double2* __restrict__ tw, FftPlan pl,
              int L, int groups, double2* __restrict__ u1) {
   extern __shared__ double lds[];
@@ -481,7 +482,7 @@ k_ce3_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __re
     }
     const int r = r0 + q;
     const U4 bk = stream_block(seed, (uint32_t)(r / 2) * (uint32_t)n + (uint32_t)k1, sample, level,
-                               kTagNoise);
+                               tag);
     double zr, zi;
     if ((r & 1) == 0) box_muller(to_uniform(bk.x), to_uniform(bk.y), zr, zi);
     else box_muller(to_uniform(bk.z), to_uniform(bk.w), zr, zi);
@@ -541,7 +542,7 @@ k_ce3_pass_b(int m, const double2* __restrict__ u1, const double2* __restrict__ 
 // fine cell (2I, 2J, 2L)).
 template <int C>
 __global__ void __launch_bounds__(kBlock)
-k_ce3_pass_c(int kind, int n_nodes, int n_layers, double mu0, double mu1, int m,
+k_ce3_pass_c(int kind, int n_nodes, int n_layers, CePair pr, int m,
              const double2* __restrict__ u2, const double2* __restrict__ tw, FftPlan pl, int L,
              int groups, const double* __restrict__ params, double* __restrict__ k,
              double* __restrict__ kc) {
@@ -575,18 +576,21 @@ k_ce3_pass_c(int kind, int n_nodes, int n_layers, double mu0, double mu1, int m,
     const int ly = n_layers > 1 ? layer_of3(kind, n_nodes, prm, centre(j1, m), centre(j2, m),
                                             centre(j3, m))
                                 : 0;
-    k[s * mm * m + ((long long)j3 * m + j2) * m + j1] = exp(ly == 0 ? mu0 + g0 : mu1 + g1);
+    if (ly == pr.l_re || ly == pr.l_im)
+      k[s * mm * m + ((long long)j3 * m + j2) * m + j1] =
+          exp(ly == pr.l_re ? pr.mu_re + g0 : pr.mu_im + g1);
     if (kc != nullptr && ((j1 | j2 | j3) & 1) == 0) {
       const int lc = n_layers > 1 ? layer_of3(kind, n_nodes, prm, centre(j1 / 2, mc),
                                               centre(j2 / 2, mc), centre(j3 / 2, mc))
                                   : 0;
-      kc[s * (long long)mc * mc * mc + ((long long)(j3 / 2) * mc + j2 / 2) * mc + j1 / 2] =
-          exp(lc == 0 ? mu0 + g0 : mu1 + g1);
+      if (lc == pr.l_re || lc == pr.l_im)
+        kc[s * (long long)mc * mc * mc + ((long long)(j3 / 2) * mc + j2 / 2) * mc + j1 / 2] =
+            exp(lc == pr.l_re ? pr.mu_re + g0 : pr.mu_im + g1);
     }
   }
 }
 
-void launch_ce3(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
+void launch_ce3(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int level, uint64_t first,
                 const uint32_t* ids, int batch, int m, const double* sq, const double2* tw,
                 const FftPlan& pl, const double* params, double2* u1, double2* u2, double* k,
                 double* k_coarse) {
@@ -598,19 +602,19 @@ void launch_ce3(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first
   const int gc = m * ((m + L - 1) / L);
   if (L > 1) {
     hipLaunchKernelGGL(k_ce3_pass_a<1>, dim3(batch * ga), dim3(kBlock), lds, st, mdl.seed,
-                       (uint32_t)level, first, ids, m, sq, tw, pl, L, ga, u1);
+                       pr.tag, (uint32_t)level, first, ids, m, sq, tw, pl, L, ga, u1);
     hipLaunchKernelGGL(k_ce3_pass_b<1>, dim3(batch * gb), dim3(kBlock), lds, st, m, u1, tw, pl, L,
                        gb, u2);
     hipLaunchKernelGGL(k_ce3_pass_c<1>, dim3(batch * gc), dim3(kBlock), lds, st,
-                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, mdl.mu[0], mdl.mu[1], m, u2,
+                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, pr, m, u2,
                        tw, pl, L, gc, params, k, k_coarse);
   } else {
     hipLaunchKernelGGL(k_ce3_pass_a<0>, dim3(batch * ga), dim3(kBlock), lds, st, mdl.seed,
-                       (uint32_t)level, first, ids, m, sq, tw, pl, 1, ga, u1);
+                       pr.tag, (uint32_t)level, first, ids, m, sq, tw, pl, 1, ga, u1);
     hipLaunchKernelGGL(k_ce3_pass_b<0>, dim3(batch * gb), dim3(kBlock), lds, st, m, u1, tw, pl, 1,
                        gb, u2);
     hipLaunchKernelGGL(k_ce3_pass_c<0>, dim3(batch * gc), dim3(kBlock), lds, st,
-                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, mdl.mu[0], mdl.mu[1], m, u2,
+                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, pr, m, u2,
                        tw, pl, 1, gc, params, k, k_coarse);
   }
 }

@@ -14,9 +14,13 @@
 //     block p n + k1), scaled by sqrt(Lambda / n^2), FFT along k2 in LDS,
 //     keep rows j2 < m -> uT[sample][j2][k1];
 //   pass B, one workgroup per (sample, row j2 < m): FFT of uT[sample][j2][:]
-//     along k1 in LDS, keep j1 < m; Re -> layer 0, Im -> layer 1; the layer of
-//     each centre decides k = exp(mu_l + g_l); the plain coarse companion is
-//     written from the even (j1, j2) cells in the same pass.
+//     along k1 in LDS, keep j1 < m; Re -> the pair's first layer, Im -> its
+//     second; the layer of each centre decides k = exp(mu_l + g_l) on the
+//     cells of the pair's layers; the plain coarse companion is written from
+//     the even (j1, j2) cells in the same pass.
+// Layers with different covariances use separate embedding samples (pairs,
+// each with its own eigenvalues and noise stream tag 2 + pair); passes A and B
+// run once per pair and each pass B writes the cells of its own layers.
 // Pass A's stores are strided by n; its block order is remapped so that the
 // columns k1 that share cache lines run on the same XCD (and its L2).
 #include <float.h>
@@ -215,9 +219,10 @@ void launch_ce_sqrt_transpose(hipStream_t st, const double2* lam, int n, double*
 // uT[s][j2][k1] (the L columns give L adjacent entries of every row j2).
 template <int C, int T>
 __global__ void __launch_bounds__(T)
-k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __restrict__ ids,
-            int m, const double* __restrict__ sqT, const double2* __restrict__ tw, FftPlan pl,
-            int L, int groups, double2* __restrict__ uT) {
+k_ce_pass_a(uint64_t seed, uint32_t tag, uint32_t level, uint64_t first,
+            const uint32_t* __restrict__ ids, int m, const double* __restrict__ sqT,
+            const double2* __restrict__ tw, FftPlan pl, int L, int groups,
+            double2* __restrict__ uT) {
   extern __shared__ double lds[];
   const int n = pl.n;
   double* sre = lds;
@@ -247,8 +252,7 @@ k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __res
     }
     const int k1 = k1_0 + q;
     const double* sq = sqT + (long long)k1 * n;
-    const U4 bk = stream_block(seed, (uint32_t)pr * (uint32_t)n + (uint32_t)k1, sample, level,
-                               kTagNoise);
+    const U4 bk = stream_block(seed, (uint32_t)pr * (uint32_t)n + (uint32_t)k1, sample, level, tag);
     double zr, zi;
     box_muller(to_uniform(bk.x), to_uniform(bk.y), zr, zi);
     const double a = sq[k2];
@@ -274,21 +278,22 @@ k_ce_pass_a(uint64_t seed, uint32_t level, uint64_t first, const uint32_t* __res
 }
 
 template <int C, int T>
-static void pass_a_c(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
-                     const uint32_t* ids, int batch, int m, const double* sqT, const double2* tw,
-                     const FftPlan& pl, int L, double2* uT) {
+static void pass_a_c(hipStream_t st, const mlmc_model& mdl, uint32_t tag, int level,
+                     uint64_t first, const uint32_t* ids, int batch, int m, const double* sqT,
+                     const double2* tw, const FftPlan& pl, int L, double2* uT) {
   const int groups = (pl.n + L - 1) / L;
   hipLaunchKernelGGL((k_ce_pass_a<C, T>), dim3(batch * groups), dim3(T),
-                     2 * (size_t)L * pl.n * sizeof(double), st, mdl.seed, (uint32_t)level, first,
-                     ids, m, sqT, tw, pl, L, groups, uT);
+                     2 * (size_t)L * pl.n * sizeof(double), st, mdl.seed, tag, (uint32_t)level,
+                     first, ids, m, sqT, tw, pl, L, groups, uT);
 }
 
-void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
-                      const uint32_t* ids, int batch, int m, const double* sqT,
+void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int level,
+                      uint64_t first, const uint32_t* ids, int batch, int m, const double* sqT,
                       const double2* tw, const FftPlan& pl, double2* uT) {
   const int L = fft_lines_per_group(pl);
-  if (L > 1) pass_a_c<1, kBlock>(st, mdl, level, first, ids, batch, m, sqT, tw, pl, L, uT);
-  else pass_a_c<0, kBlock>(st, mdl, level, first, ids, batch, m, sqT, tw, pl, 1, uT);
+  if (L > 1)
+    pass_a_c<1, kBlock>(st, mdl, pr.tag, level, first, ids, batch, m, sqT, tw, pl, L, uT);
+  else pass_a_c<0, kBlock>(st, mdl, pr.tag, level, first, ids, batch, m, sqT, tw, pl, 1, uT);
 }
 
 // ------------------------------------------------------------ pass B
@@ -299,7 +304,7 @@ void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, int level, uint64_t
 // cells from the even rows and columns.
 template <int C, int T>
 __global__ void __launch_bounds__(T)
-k_ce_pass_b(int kind, int n_nodes, int n_layers, double mu0, double mu1, int m,
+k_ce_pass_b(int kind, int n_nodes, int n_layers, CePair pr, int m,
             const double2* __restrict__ uT, const double2* __restrict__ tw, FftPlan pl, int L,
             int groups, const double* __restrict__ params, double* __restrict__ k,
             double* __restrict__ kc) {
@@ -329,32 +334,34 @@ k_ce_pass_b(int kind, int n_nodes, int n_layers, double mu0, double mu1, int m,
     const double g0 = sre[q * n + j1], g1 = sim[q * n + j1];
     const double y = centre(j2, m);
     const int l = n_layers > 1 ? layer_of(kind, n_nodes, prm, centre(j1, m), y) : 0;
-    k[((long long)s * m + j2) * m + j1] = exp(l == 0 ? mu0 + g0 : mu1 + g1);
+    if (l == pr.l_re || l == pr.l_im)
+      k[((long long)s * m + j2) * m + j1] = exp(l == pr.l_re ? pr.mu_re + g0 : pr.mu_im + g1);
     if (kc != nullptr && ((j2 & 1) == 0) && ((j1 & 1) == 0)) {
       const double yc = centre(j2 / 2, mc);
       const int lc = n_layers > 1 ? layer_of(kind, n_nodes, prm, centre(j1 / 2, mc), yc) : 0;
-      kc[((long long)s * mc + j2 / 2) * mc + j1 / 2] = exp(lc == 0 ? mu0 + g0 : mu1 + g1);
+      if (lc == pr.l_re || lc == pr.l_im)
+        kc[((long long)s * mc + j2 / 2) * mc + j1 / 2] =
+            exp(lc == pr.l_re ? pr.mu_re + g0 : pr.mu_im + g1);
     }
   }
 }
 
 template <int C, int T>
-static void pass_b_c(hipStream_t st, const mlmc_model& mdl, int batch, int m, const double2* uT,
-                     const double2* tw, const FftPlan& pl, int L, const double* params, double* k,
-                     double* k_coarse) {
+static void pass_b_c(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int batch, int m,
+                     const double2* uT, const double2* tw, const FftPlan& pl, int L,
+                     const double* params, double* k, double* k_coarse) {
   const int groups = (m + L - 1) / L;
   hipLaunchKernelGGL((k_ce_pass_b<C, T>), dim3(batch * groups), dim3(T),
                      2 * (size_t)L * pl.n * sizeof(double), st, mdl.interface_kind, mdl.n_nodes,
-                     mdl.n_layers, mdl.mu[0], mdl.mu[1], m, uT, tw, pl, L, groups, params, k,
-                     k_coarse);
+                     mdl.n_layers, pr, m, uT, tw, pl, L, groups, params, k, k_coarse);
 }
 
-void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, int batch, int m,
+void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int batch, int m,
                       const double2* uT, const double2* tw, const FftPlan& pl,
                       const double* params, double* k, double* k_coarse) {
   const int L = fft_lines_per_group(pl);
-  if (L > 1) pass_b_c<1, kBlock>(st, mdl, batch, m, uT, tw, pl, L, params, k, k_coarse);
-  else pass_b_c<0, kBlock>(st, mdl, batch, m, uT, tw, pl, 1, params, k, k_coarse);
+  if (L > 1) pass_b_c<1, kBlock>(st, mdl, pr, batch, m, uT, tw, pl, L, params, k, k_coarse);
+  else pass_b_c<0, kBlock>(st, mdl, pr, batch, m, uT, tw, pl, 1, params, k, k_coarse);
 }
 
 // ------------------------------------------------------------ CGV sub-lattices

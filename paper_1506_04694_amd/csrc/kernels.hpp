@@ -23,10 +23,19 @@ void launch_fft_lines(hipStream_t st, double2* data, int n, int nlines, long lon
 void launch_ce_minmax(hipStream_t st, const double2* lam, long long count, double* partial,
                       int nblocks);
 void launch_ce_sqrt_transpose(hipStream_t st, const double2* lam, int n, double* sqT);
-void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
-                      const uint32_t* ids, int batch, int m, const double* sqT,
+// One circulant-embedding sample ("pair") of a correlated model: the noise
+// stream tag it draws from, the layer taking its real part and the layer taking
+// its imaginary part (l_im < 0: none), with their means.  Layers share a sample
+// only when their covariance parameters agree.
+struct CePair {
+  uint32_t tag;
+  int l_re, l_im;
+  double mu_re, mu_im;
+};
+void launch_ce_pass_a(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int level,
+                      uint64_t first, const uint32_t* ids, int batch, int m, const double* sqT,
                       const double2* tw, const FftPlan& pl, double2* uT);
-void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, int batch, int m,
+void launch_ce_pass_b(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int batch, int m,
                       const double2* uT, const double2* tw, const FftPlan& pl,
                       const double* params, double* k, double* k_coarse);
 void launch_cgv_extract(hipStream_t st, int m, int batch, const double* kf, double* ksub);
@@ -174,7 +183,7 @@ void launch_field_pc3(hipStream_t st, const mlmc_model& mdl, int m, int batch,
 void launch_ce_first_row3(hipStream_t st, int n, int m, double sigma2, double lambda, int norm_r,
                           double2* c);
 void launch_ce_sqrt3(hipStream_t st, const double2* lam, int n, double* sq);
-void launch_ce3(hipStream_t st, const mlmc_model& mdl, int level, uint64_t first,
+void launch_ce3(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int level, uint64_t first,
                 const uint32_t* ids, int batch, int m, const double* sq, const double2* tw,
                 const FftPlan& pl, const double* params, double2* u1, double2* u2, double* k,
                 double* k_coarse);
