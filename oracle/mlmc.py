@@ -80,3 +80,38 @@ def estimate(sums):
         per_level.append({"mean_y": mean, "var_y": var})
     return {"estimate": q, "variance_of_estimate": var_sum,
             "std_error": float(np.sqrt(var_sum)), "levels": per_level}
+
+
+# ------------------------------------------------------- choosing L and N_l
+# Section 3.2 splits the mean square error eq. (3.7) evenly: the variance
+# sum_l V_l / N_l and the squared bias (E[Q_L - Q])^2 each get eps^2 / 2, and
+# N_l is chosen so that the variance part is reached at the least total cost
+# sum_l N_l C_l.  With a Lagrange multiplier for the constraint
+# sum_l V_l / N_l = eps^2 / 2 the minimiser over real N_l is
+#     N_l = 2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k),
+# rounded up here.  The rates of the complexity theorem (M1)-(M3),
+# |E[Y_l]| ~ h_l^alpha, V[Y_l] ~ h_l^beta, C_l ~ h_l^-gamma, are the least
+# squares slopes of log2 of the measured values against log2(1/h_l) over the
+# levels l >= 1 (level 0 has no difference).  With h_l = h_{l-1} / 2 the
+# remaining bias of the finest level L is estimated as |E[Y_L]| / (2^alpha - 1)
+# (the geometric tail of the differences beyond L).
+
+def optimal_samples(var, cost, eps):
+    """Rounded-up minimiser of sum N_l C_l subject to sum V_l / N_l = eps^2 / 2."""
+    var = np.asarray(var, dtype=np.float64)
+    cost = np.asarray(cost, dtype=np.float64)
+    total = np.sum(np.sqrt(var * cost))
+    return np.ceil(2.0 / eps ** 2 * np.sqrt(var / cost) * total).astype(np.int64)
+
+
+def fit_rate(h, values):
+    """Least squares slope p of log2|value| = c + p log2(h) (values ~ h^p)."""
+    x = np.log2(np.asarray(h, dtype=np.float64))
+    y = np.log2(np.abs(np.asarray(values, dtype=np.float64)))
+    A = np.stack([x, np.ones_like(x)], axis=1)
+    return float(np.linalg.lstsq(A, y, rcond=None)[0][0])
+
+
+def bias_estimate(mean_y_finest, alpha):
+    """Bias of the finest level from its mean difference and the rate alpha."""
+    return abs(mean_y_finest) / (2.0 ** alpha - 1.0)
