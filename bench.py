@@ -17,6 +17,7 @@ sample of the same workload.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import threading
@@ -326,7 +327,8 @@ def other_configs(lib, torch, steps):
     * Section 4.2's variance experiment (cgv_variance);
     * Model Problem 1 on the bench workload's levels, level by level;
     * Section 3.4's three-layer correlated model (per-layer correlation lengths),
-      both model problems, all levels in one call."""
+      both model problems, all levels in one call;
+    * adaptive MLMC to a root mean square error (Section 3.2), plain and CGV."""
     ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
     opts = lib.mlmc_solver_opts_default()
 
@@ -432,6 +434,22 @@ def other_configs(lib, torch, steps):
         out["paper_three_layers"] = {"workload": wl.name, "levels_m": wl.m_levels,
                                      "samples": wl.n_samples, "dtype": "f64",
                                      "all_levels_one_call": runs}
+
+        # adaptive MLMC (Section 3.2) on the layered bench model, plain and CGV
+        ada = {}
+        for name, cgv in (("plain", 0), ("cgv", 1)):
+            ao = lib.mlmc_adaptive_opts_default(eps=W.ADAPTIVE_EPS, n_initial=64, cgv=cgv)
+            r = lib.mlmc_adaptive(ctx, W.CE2, W.ADAPTIVE_LEVELS, ao, opts)
+            L1 = r.n_levels
+            ada[name] = {"converged": bool(r.converged), "levels": L1,
+                         "m": W.ADAPTIVE_LEVELS[:L1], "estimate": r.estimate,
+                         "rmse_bound": math.sqrt(r.variance + r.bias ** 2),
+                         "seconds": r.seconds, "n": [r.n[l] for l in range(L1)],
+                         "var_y": [r.var_y[l] for l in range(L1)],
+                         "cost_ms_per_sample": [1e3 * r.cost[l] for l in range(L1)],
+                         "alpha": r.alpha, "beta": r.beta, "gamma": r.gamma}
+        out["adaptive"] = {"model": "layered CE (bench model)", "eps": W.ADAPTIVE_EPS,
+                           "runs": ada}
     finally:
         lib.mlmc_ctx_destroy(ctx)
     return out

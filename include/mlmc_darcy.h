@@ -345,6 +345,72 @@ mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels
  * sums (host arithmetic only).  levels: host [n_levels]; out: host. */
 mlmc_status mlmc_estimate(const mlmc_level_sums* levels, int n_levels, mlmc_estimate_t* out);
 
+/* ---------------------------------------------------------------- choosing L and N_l
+ * Section 3.2 splits the mean square error eq. (3.7) evenly between the
+ * variance sum_l V_l / N_l and the squared bias (E[Q_L - Q])^2, eps^2 / 2 each,
+ * and takes the N_l that reach the variance part at the least cost
+ * sum_l N_l C_l (C_l: cost of one sample of Y_l). */
+
+/* N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k)), the minimiser of
+ * the cost under the variance constraint, rounded up.  var, cost (> 0),
+ * n_out: host [n_levels].  Host arithmetic only. */
+mlmc_status mlmc_optimal_samples(const double* var, const double* cost, int n_levels, double eps,
+                                 int64_t* n_out);
+
+/* Rates of the complexity theorem's (M1)-(M3) as least squares slopes of
+ * log2 |E[Y_l]|, log2 V[Y_l] and log2 C_l against log2 h_l (h_l = 1/m_l) over
+ * the levels l >= 1: |E[Y_l]| ~ h^alpha, V[Y_l] ~ h^beta, C_l ~ h^-gamma.
+ * sums, cost, m: host [n_levels] (n_levels >= 3, n >= 2 per level).  Host only. */
+mlmc_status mlmc_rates(const mlmc_level_sums* sums, const double* cost, const int* m,
+                       int n_levels, double* alpha, double* beta, double* gamma);
+
+#define MLMC_MAX_LEVELS 16
+
+typedef struct mlmc_adaptive_opts {
+  double eps;           /* target root mean square error (> 0)                          */
+  double alpha;         /* rate of |E[Y_l]| for the bias estimate; 0: fitted over the
+                           levels l >= 1 (at least 0.5)                                  */
+  int32_t n_initial;    /* samples of a newly added level (>= 2, default 64)            */
+  int32_t min_levels;   /* levels to start with (2..max_levels, default 3)              */
+  int32_t cgv;          /* 1: Coarse Grid Variates estimator (eq. (4.2))                */
+  int32_t reserved;
+  int64_t max_samples;  /* cap on the samples of one level (default 2^24)              */
+} mlmc_adaptive_opts;
+
+typedef struct mlmc_adaptive_result {
+  int32_t n_levels;           /* levels used (L + 1)                                   */
+  int32_t converged;          /* 1: variance <= eps^2/2 and bias <= eps/sqrt(2)         */
+  double estimate;            /* eq. (3.6)                                             */
+  double variance;            /* sum_l V_l / N_l                                       */
+  double bias;                /* |E[Y_L]| / (2^alpha - 1)                              */
+  double alpha, beta, gamma;  /* alpha used; beta, gamma fitted (NaN below 3 levels)   */
+  double seconds;             /* wall time of the level runs                           */
+  int64_t n[MLMC_MAX_LEVELS];       /* samples per level                              */
+  double mean_y[MLMC_MAX_LEVELS];   /* sample mean of Y_l                             */
+  double var_y[MLMC_MAX_LEVELS];    /* unbiased sample variance of Y_l                */
+  double cost[MLMC_MAX_LEVELS];     /* seconds per sample of level l                  */
+  mlmc_level_sums sums[MLMC_MAX_LEVELS];
+} mlmc_adaptive_result;
+
+/* Defaults: eps 1e-2, alpha 0 (fitted), n_initial 64, min_levels 3, cgv 0,
+ * max_samples 2^24. */
+mlmc_status mlmc_adaptive_opts_default(mlmc_adaptive_opts* opts);
+
+/* MLMC to a root mean square error eps (Section 3.2): start with min_levels
+ * levels of n_initial samples; repeatedly run each level's missing samples
+ * (mlmc_level_run, new sample numbers after those already taken; at most 4x
+ * the level's samples per round), take its cost per sample from its largest
+ * call (the per-call overhead does not grow with the samples), and set N_l by
+ * mlmc_optimal_samples from the sample variances; once no level lacks samples, estimate the bias of the finest
+ * level and add the next level (n_initial samples) while it exceeds
+ * eps / sqrt(2) and levels remain.  Level l uses the grid m_levels[l]
+ * (m_levels[l] = 2 m_levels[l-1]) and, for correlated fields, n_ce[l] (NULL:
+ * model->n_ce).  model, m_levels, n_ce, opts, solver, out: host.
+ * max_levels <= MLMC_MAX_LEVELS.  Synchronises. */
+mlmc_status mlmc_adaptive(mlmc_ctx* ctx, const mlmc_model* model, int max_levels,
+                          const int* m_levels, const int* n_ce, const mlmc_adaptive_opts* opts,
+                          const mlmc_solver_opts* solver, mlmc_adaptive_result* out);
+
 /* Kernel timing: when enabled, every launch of the named kernel is bracketed
  * by HIP events on the context's stream; mlmc_profile_read returns the launch
  * count, the summed event time and the algorithmic bytes the library counts

@@ -35,7 +35,9 @@ EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_
             "mlmc_sample_field_ids", "mlmc_level_run_ids", "mlmc_serve_opts_default",
             "mlmc_serve_start", "mlmc_serve_submit", "mlmc_serve_poll", "mlmc_serve_now",
             "mlmc_serve_stats", "mlmc_serve_stop", "mlmc_run_levels", "mlmc_serve_start_models",
-            "mlmc_assemble_problem", "mlmc_qoi_box_mean"]
+            "mlmc_assemble_problem", "mlmc_qoi_box_mean", "mlmc_optimal_samples", "mlmc_rates",
+            "mlmc_adaptive_opts_default", "mlmc_adaptive"]
+MLMC_MAX_LEVELS = 16
 
 
 class mlmc_model(ctypes.Structure):
@@ -100,6 +102,25 @@ class mlmc_estimate_t(ctypes.Structure):
                 ("std_error", ctypes.c_double)]
 
 
+class mlmc_adaptive_opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("n_initial", ctypes.c_int32), ("min_levels", ctypes.c_int32),
+                ("cgv", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_samples", ctypes.c_int64)]
+
+
+class mlmc_adaptive_result(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("estimate", ctypes.c_double), ("variance", ctypes.c_double),
+                ("bias", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("n", ctypes.c_int64 * MLMC_MAX_LEVELS),
+                ("mean_y", ctypes.c_double * MLMC_MAX_LEVELS),
+                ("var_y", ctypes.c_double * MLMC_MAX_LEVELS),
+                ("cost", ctypes.c_double * MLMC_MAX_LEVELS),
+                ("sums", mlmc_level_sums * MLMC_MAX_LEVELS)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _U64 = ctypes.c_uint64
@@ -147,6 +168,15 @@ _SIGS = {
                                ctypes.POINTER(ctypes.c_double)]),
     "mlmc_assemble_problem": (_S, [_P, _I, _I, _I, _I, _P, _P, _P, _P]),
     "mlmc_qoi_box_mean": (_S, [_P, _I, _I, _I, _P, ctypes.c_double, ctypes.c_double, _P]),
+    "mlmc_optimal_samples": (_S, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  _I, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]),
+    "mlmc_rates": (_S, [ctypes.POINTER(mlmc_level_sums), ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(_I), _I, ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "mlmc_adaptive_opts_default": (_S, [ctypes.POINTER(mlmc_adaptive_opts)]),
+    "mlmc_adaptive": (_S, [_P, ctypes.POINTER(mlmc_model), _I, ctypes.POINTER(_I),
+                           ctypes.POINTER(_I), ctypes.POINTER(mlmc_adaptive_opts),
+                           ctypes.POINTER(mlmc_solver_opts), ctypes.POINTER(mlmc_adaptive_result)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -485,3 +515,46 @@ def mlmc_run_levels(ctx, model, m_fine, first_sample, n, cgv, opts, sums=None, a
     if not (allow_noconv and code == MLMC_ENOCONV):
         _check(ctx, code)
     return [arr_s[q] for q in range(L)]
+
+
+# ------------------------------------------------------------------ choosing L and N_l
+def mlmc_optimal_samples(var, cost, eps):
+    """Host arithmetic: N_l for the variance part eps^2/2 at the least cost."""
+    L = len(var)
+    out = (ctypes.c_int64 * L)()
+    code = _lib.mlmc_optimal_samples((ctypes.c_double * L)(*map(float, var)),
+                                     (ctypes.c_double * L)(*map(float, cost)), L, float(eps), out)
+    _check(None, code)
+    return [int(v) for v in out]
+
+
+def mlmc_rates(sums, cost, m):
+    """Host arithmetic: (alpha, beta, gamma) fitted over the levels l >= 1."""
+    L = len(sums)
+    a, b, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    code = _lib.mlmc_rates((mlmc_level_sums * L)(*sums), (ctypes.c_double * L)(*map(float, cost)),
+                           (ctypes.c_int * L)(*m), L, ctypes.byref(a), ctypes.byref(b),
+                           ctypes.byref(g))
+    _check(None, code)
+    return a.value, b.value, g.value
+
+
+def mlmc_adaptive_opts_default(**kw):
+    o = mlmc_adaptive_opts()
+    _check(None, _lib.mlmc_adaptive_opts_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mlmc_adaptive(ctx, model, m_levels, opts, solver):
+    """MLMC to the root mean square error opts.eps; returns mlmc_adaptive_result."""
+    L = len(m_levels)
+    mm = make_model(model)
+    nce = None
+    if getattr(model, "n_ce", None):
+        nce = (ctypes.c_int * L)(*[int(model.n_ce.get(m, 0)) for m in m_levels])
+    out = mlmc_adaptive_result()
+    _check(ctx, _lib.mlmc_adaptive(ctx, ctypes.byref(mm), L, (ctypes.c_int * L)(*m_levels), nce,
+                                   ctypes.byref(opts), ctypes.byref(solver), ctypes.byref(out)))
+    return out

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmlmc_darcy.so")
 SOURCES = ["field.hip", "fv.hip", "mg_pcg.hip", "mg_fused.hip", "onchip.hip", "d3.hip", "api.hip",
-           "serve.hip"]
+           "serve.hip", "adaptive.cpp"]
 ARCH = os.environ.get("MLMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
@@ -31,7 +31,7 @@ def hipcc():
 
 
 def _compile(src):
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

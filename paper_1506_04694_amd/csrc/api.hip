@@ -311,6 +311,13 @@ constexpr double kBytesProlong = 18.0;    // z read + write 16 + zc 2
 }  // namespace
 
 // =================================================================== public ABI
+namespace mlmc {
+// Error message for the host-side drivers of other source files.
+mlmc_status set_error(mlmc_ctx* ctx, mlmc_status code, const char* msg) {
+  return fail(ctx, code, msg);
+}
+}  // namespace mlmc
+
 extern "C" {
 
 mlmc_status mlmc_ctx_create(int device, void* hip_stream, mlmc_ctx** out) {

@@ -27,6 +27,9 @@ void launch_ce_sqrt_transpose(hipStream_t st, const double2* lam, int n, double*
 // stream tag it draws from, the layer taking its real part and the layer taking
 // its imaginary part (l_im < 0: none), with their means.  Layers share a sample
 // only when their covariance parameters agree.
+// Sets the context's last-error message (host drivers outside api.hip).
+mlmc_status set_error(mlmc_ctx* ctx, mlmc_status code, const char* msg);
+
 struct CePair {
   uint32_t tag;
   int l_re, l_im;

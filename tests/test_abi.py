@@ -54,6 +54,10 @@ int main(void) {
          sizeof(mlmc_request), sizeof(mlmc_result));
   P(mlmc_serve_opts, hbm_budget_bytes); P(mlmc_serve_opts, grid_model); P(mlmc_serve_opts, solver);
   P(mlmc_request, model); P(mlmc_result, model); P(mlmc_result, q_f); P(mlmc_result, t_done);
+  printf("mlmc_adaptive_opts %zu\nmlmc_adaptive_result %zu\n", sizeof(mlmc_adaptive_opts),
+         sizeof(mlmc_adaptive_result));
+  P(mlmc_adaptive_opts, max_samples); P(mlmc_adaptive_result, n); P(mlmc_adaptive_result, cost);
+  P(mlmc_adaptive_result, sums);
   return 0;
 }
 """
@@ -81,11 +85,14 @@ def test_struct_layouts_match_header(lib, tmp_path):
     assert int(vals["mlmc_solver_opts.gamma_levels"]) == lib.mlmc_solver_opts.gamma_levels.offset
     assert int(vals["mlmc_solver_opts.graph"]) == lib.mlmc_solver_opts.graph.offset
     assert int(vals["mlmc_level_sums.iters_coarse"]) == lib.mlmc_level_sums.iters_coarse.offset
-    for st in ("mlmc_serve_opts", "mlmc_request", "mlmc_result"):
+    for st in ("mlmc_serve_opts", "mlmc_request", "mlmc_result", "mlmc_adaptive_opts",
+               "mlmc_adaptive_result"):
         assert int(vals[st]) == ctypes.sizeof(getattr(lib, st)), st
     for st, f in (("mlmc_serve_opts", "hbm_budget_bytes"), ("mlmc_serve_opts", "grid_model"),
                   ("mlmc_serve_opts", "solver"), ("mlmc_request", "model"),
-                  ("mlmc_result", "model"), ("mlmc_result", "q_f"), ("mlmc_result", "t_done")):
+                  ("mlmc_result", "model"), ("mlmc_result", "q_f"), ("mlmc_result", "t_done"),
+                  ("mlmc_adaptive_opts", "max_samples"), ("mlmc_adaptive_result", "n"),
+                  ("mlmc_adaptive_result", "cost"), ("mlmc_adaptive_result", "sums")):
         assert int(vals["%s.%s" % (st, f)]) == getattr(getattr(lib, st), f).offset, (st, f)
 
 

@@ -115,6 +115,10 @@ PAPER3_CE = Model(interface_kind=PAPER_TWO_LINES, n_layers=3, field_kind=CORRELA
                   n_ce={8: 16, 16: 32, 32: 72, 64: 135, 128: 375, 256: 960, 512: 1875})
 PAPER3_LAYERED = Workload("2d-ce-paper3-64-512", PAPER3_CE, [64, 128, 256, 512],
                           [4096, 1024, 256, 64])
+# Adaptive MLMC (Section 3.2) on the layered model: root mean square error and
+# the available hierarchy.
+ADAPTIVE_EPS = 1.5e-2
+ADAPTIVE_LEVELS = [16, 32, 64, 128, 256, 512]
 MP1_PAPER3 = Model(interface_kind=PAPER_TWO_LINES, n_layers=3, field_kind=PIECEWISE_CONSTANT,
                    mu=(0.0, 0.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0), seed=0, problem=1)
 
