@@ -193,3 +193,43 @@ def test_serve_start_models_refusals(lib):
         lib.mlmc_serve_start_models([MODEL], opts)
     with pytest.raises(lib.MlmcError):
         lib.mlmc_serve_start_models([], lib.serve_opts_for_models([(MODEL, [32])]))
+
+
+def test_serve_model_problems_and_three_layers(lib):
+    """One server for the layered model under Model Problem 2 and under Model
+    Problem 1, and for the paper's three-layer model (two embedding samples per
+    field): each result is bitwise the direct level run of its own model and
+    within 1e-10 of the oracle's QoI of its problem."""
+    print("serve MP2 + MP1 + three layers", flush=True)
+    models = [MODEL, W.MP1_CE2, W.PAPER3_CE]
+    opts = lib.serve_opts_for_models([(mdl, [32, 64]) for mdl in models], n_workers=3,
+                                     max_batch=8)
+    srv = lib.mlmc_serve_start_models(models, opts)
+    reqs = []
+    for i in range(5):
+        for mi in range(3):
+            reqs.append((i % 2, 32 if i % 2 == 0 else 64, 900 + 10 * mi + i, mi))
+    try:
+        ids = [lib.mlmc_serve_submit(srv, *r) for r in reqs]
+        got = drain(lib, srv, len(ids))
+    finally:
+        lib.mlmc_serve_stop(srv)
+    by_req = {r: got[i] for r, i in zip(reqs, ids)}
+    assert all(v["failed"] == 0 and v["status"] == 0 for v in by_req.values())
+    ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
+    try:
+        for r, v in by_req.items():
+            level, m, sample, mi = r
+            qf = torch.empty(1, dtype=torch.float64, device="cuda:0")
+            qc = torch.empty_like(qf)
+            lib.mlmc_level_run(ctx, models[mi], level, m, sample, 1, False,
+                               lib.mlmc_solver_opts_default(), q_f=qf, q_c=qc)
+            torch.cuda.synchronize()
+            assert qf.item() == v["q_f"] and qc.item() == v["q_c"], r
+    finally:
+        lib.mlmc_ctx_destroy(ctx)
+    for r in ((1, 64, 911, 1), (0, 32, 920, 2)):
+        level, m, sample, mi = r
+        ref = omlmc.level_sample(models[mi], level, sample, m)
+        assert abs(by_req[r]["q_f"] - ref["Q_f"]) <= 1e-10 * ref["Q_f"], r
+        assert abs(by_req[r]["q_c"] - ref["Q_c"]) <= 1e-10 * abs(ref["Q_c"]) + 1e-300, r
