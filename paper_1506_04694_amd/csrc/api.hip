@@ -173,15 +173,20 @@ bool five_smooth(int n) {
   return n == 1;
 }
 
+// Stage order: the odd radices first.  A Stockham stage with span ns writes
+// runs of ns consecutive elements at stride R ns, so a radix-4 stage at ns = 1
+// stores with a stride of 8 dwords (8-way LDS bank conflicts on 64 banks),
+// while radix 5 or 3 there strides by 10 or 6 dwords (2-way), and the even
+// radices come once ns has grown.
 FftPlan make_plan(int n) {
   FftPlan pl{};
   pl.n = n;
   int r = n;
   auto push = [&](int R) { pl.radix[pl.nstages++] = R; r /= R; };
+  while (r % 5 == 0) push(5);
+  while (r % 3 == 0) push(3);
   while (r % 4 == 0) push(4);
   while (r % 2 == 0) push(2);
-  while (r % 3 == 0) push(3);
-  while (r % 5 == 0) push(5);
   return pl;
 }
 
