@@ -278,7 +278,8 @@ mlmc_status mlmc_assemble_problem(mlmc_ctx* ctx, int problem, int dim, int m, in
  * Galerkin coarse operators, red-black Gauss-Seidel smoothing; W on the
  * opts->gamma_levels finest levels when opts->gamma = 2).
  *   p       device [batch][m]^d, written (initial guess 0).
- * d = 2 needs m = c 2^k with c <= 8; d = 3 needs c <= 4 and FP64 precision
+ * d = 2 needs m = c 2^k with c <= 8; d = 3 needs c <= 4 and an FP64 or FP32
+ * hierarchy (bfloat16 is 2-D only)
  * (else MLMC_EINVAL).
  *   status  device int32 [batch], iters device int32 [batch],
  *   relres  device double [batch] = ||b - A p|| / ||b|| recomputed at exit.

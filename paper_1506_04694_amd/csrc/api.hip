@@ -604,8 +604,11 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
                                const double* b, double* p, const mlmc_solver_opts* opts,
                                int32_t* status, int32_t* iters, double* relres) {
   hipStream_t st = ctx->stream;
-  if (opts->precision != MLMC_PREC_FP64)
-    return fail(ctx, MLMC_EINVAL, "the 3-D solver runs in FP64 only");
+  if (opts->precision == MLMC_PREC_BF16)
+    return fail(ctx, MLMC_EINVAL, "the 3-D multigrid hierarchy is FP64 or FP32");
+  // FP32: the hierarchy (operators, z and r below the finest level) in float
+  // inside a flexible FP64 CG, as in 2-D; the coarsest inverse stays FP64.
+  const bool f32 = opts->precision == MLMC_PREC_FP32;
   std::vector<int> ms{m};
   while (ms.back() % 2 == 0 && ms.back() > opts->coarse_max) ms.push_back(ms.back() / 2);
   const int L = (int)ms.size() - 1;
@@ -641,6 +644,36 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   double* Ainv = nullptr;
   TRY(ws(ctx, "s3_ainv", (size_t)batch * nc * nc, &Ainv));
   launch_dense_factor3(st, ms[L], batch, Tl[L], tbl[L], Ainv);
+  // the operators and vectors the cycle works on, in the hierarchy's type
+  std::vector<const void*> Th(L + 1), tbh(L + 1);
+  std::vector<void*> zh(L + 1), rh(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    const long long nl = (long long)ms[l] * ms[l] * ms[l];
+    const long long fl = (long long)ms[l] * ms[l];
+    if (!f32) {
+      Th[l] = Tl[l];
+      tbh[l] = tbl[l];
+      zh[l] = zl[l];
+      rh[l] = rl[l];
+      continue;
+    }
+    void *Tf, *tbf;
+    TRY(ws_get(ctx, lv("s3_Tf", l), (size_t)batch * 3 * nl * sizeof(float) + 256, &Tf));
+    TRY(ws_get(ctx, lv("s3_tbf", l), (size_t)batch * 3 * fl * sizeof(float) + 256, &tbf));
+    launch_convert(st, MLMC_PREC_FP32, batch * 3 * nl, Tl[l], Tf);
+    launch_convert(st, MLMC_PREC_FP32, batch * 3 * fl, tbl[l], tbf);
+    Th[l] = Tf;
+    tbh[l] = tbf;
+    if (l == 0) {
+      zh[0] = z;
+      rh[0] = r;
+    } else {
+      TRY(ws_get(ctx, lv("s3_zf", l), (size_t)batch * nl * sizeof(float) + 256, &zh[l]));
+      TRY(ws_get(ctx, lv("s3_rf", l), (size_t)batch * nl * sizeof(float) + 256, &rh[l]));
+    }
+  }
+  double* partial2 = nullptr;
+  if (f32) TRY(ws(ctx, "s3_partial2", (size_t)batch * bps, &partial2));
   SolverState S;
   TRY(ws(ctx, "s3_r0", batch, &S.r0sq));
   TRY(ws(ctx, "s3_rho", batch, &S.rho));
@@ -657,26 +690,33 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   };
   std::function<void(int)> cycle = [&](int l) {
     if (l == L) {
-      launch_dense_apply_n(st, nc, batch, Ainv, rl[L], zl[L], S.active);
+      if (f32 && L > 0)
+        launch_dense_apply3f(st, nc, batch, Ainv, (const float*)rh[L], (float*)zh[L], S.active);
+      else launch_dense_apply_n(st, nc, batch, Ainv, rl[L], zl[L], S.active);
       return;
     }
     const int ml = ms[l];
+    const bool top = l == 0;
+    auto sweep = [&](int color, int zero) {
+      launch_rbgs3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], S.active, color, zero);
+    };
     for (int it = 0; it < nu; ++it) {
-      launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, it == 0);
-      launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+      sweep(0, it == 0);
+      sweep(1, 0);
     }
     for (int visit = 0; visit < visits(l); ++visit) {
       if (visit > 0)
         for (int it = 0; it < nu; ++it) {
-          launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
-          launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
+          sweep(0, 0);
+          sweep(1, 0);
         }
-      launch_resid_restrict3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], rl[l + 1], S.active);
+      launch_resid_restrict3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], rh[l + 1],
+                               S.active);
       cycle(l + 1);
-      launch_prolong3(st, ml, batch, zl[l + 1], zl[l], omega, S.active);
+      launch_prolong3_p(st, f32, top, ml, batch, zh[l + 1], zh[l], omega, S.active);
       for (int it = 0; it < nu; ++it) {
-        launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 1, 0);
-        launch_rbgs3(st, ml, batch, Tl[l], tbl[l], zl[l], rl[l], S.active, 0, 0);
+        sweep(1, 0);
+        sweep(0, 0);
       }
     }
   };
@@ -696,8 +736,9 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     for (int it = 1;; ++it) {
       launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
       launch_sc_alpha(st, batch, partial, bps, S, status);
-      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active, nullptr,
-                      nullptr);
+      // flexible form with a reduced-precision cycle: also r_new . z_old
+      launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,
+                      f32 ? z : nullptr, partial2);
       launch_sc_conv(st, batch, partial, bps, S, status, iters, relres, opts->tol, opts->maxit);
       CHECK_LAUNCH();
       if (it % check == 0 || it >= opts->maxit) {
@@ -706,7 +747,7 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
         if (*hcount == 0) break;
       }
       precond();
-      launch_sc_rho(st, batch, partial, bps, S, status, 0, nullptr, 0);
+      launch_sc_rho(st, batch, partial, bps, S, status, 0, partial2, f32 ? bps : 0);
       launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
     }
     return MLMC_OK;

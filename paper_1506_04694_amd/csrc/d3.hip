@@ -23,17 +23,22 @@
 
 namespace mlmc {
 
-struct Faces3 {
-  double te, tw, tn, ts, tu, td;
+// Faces of a cell in the storage type S of the operator (double, or float for
+// a reduced-precision multigrid hierarchy; the arithmetic is done in S).
+template <class S>
+struct Faces3T {
+  S te, tw, tn, ts, tu, td;
 };
+using Faces3 = Faces3T<double>;
 
-__device__ __forceinline__ Faces3 load_faces3(const double* __restrict__ Ts,
-                                              const double* __restrict__ tbs, int m, int i, int j,
-                                              int l) {
+template <class S>
+__device__ __forceinline__ Faces3T<S> load_faces3(const S* __restrict__ Ts,
+                                                  const S* __restrict__ tbs, int m, int i, int j,
+                                                  int l) {
   const long long n = (long long)m * m * m;
   const int mm = m * m;
   const long long c = ((long long)l * m + j) * m + i;
-  Faces3 f;
+  Faces3T<S> f;
   f.te = Ts[c];
   f.tw = i > 0 ? Ts[c - 1] : tbs[l * m + j];
   f.tn = Ts[n + c];
@@ -43,21 +48,25 @@ __device__ __forceinline__ Faces3 load_faces3(const double* __restrict__ Ts,
   return f;
 }
 
-__device__ __forceinline__ double nsum3(const double* __restrict__ x, int m, int i, int j, int l,
-                                        const Faces3& f) {
+// Neighbour sum over the interior faces, x of type X (the level's vector
+// type), accumulated in the operator's type S.
+template <class S, class X>
+__device__ __forceinline__ S nsum3(const X* __restrict__ x, int m, int i, int j, int l,
+                                   const Faces3T<S>& f) {
   const long long c = ((long long)l * m + j) * m + i;
   const long long mm = (long long)m * m;
-  double o = 0.0;
-  if (i < m - 1) o += f.te * x[c + 1];
-  if (i > 0) o += f.tw * x[c - 1];
-  if (j < m - 1) o += f.tn * x[c + m];
-  if (j > 0) o += f.ts * x[c - m];
-  if (l < m - 1) o += f.tu * x[c + mm];
-  if (l > 0) o += f.td * x[c - mm];
+  S o = S(0);
+  if (i < m - 1) o += f.te * (S)x[c + 1];
+  if (i > 0) o += f.tw * (S)x[c - 1];
+  if (j < m - 1) o += f.tn * (S)x[c + m];
+  if (j > 0) o += f.ts * (S)x[c - m];
+  if (l < m - 1) o += f.tu * (S)x[c + mm];
+  if (l > 0) o += f.td * (S)x[c - mm];
   return o;
 }
 
-__device__ __forceinline__ double diag3(const Faces3& f) {
+template <class S>
+__device__ __forceinline__ S diag3(const Faces3T<S>& f) {
   return f.te + f.tw + f.tn + f.ts + f.tu + f.td;
 }
 
@@ -184,9 +193,12 @@ void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const do
 
 // ------------------------------------------------------------------ smoother
 // One thread per cell of the colour ((i + j + l) % 2 == color); m even.
-__global__ void k_rbgs3(int m, long long total, const double* __restrict__ T,
-                        const double* __restrict__ tb, double* __restrict__ z,
-                        const double* __restrict__ r, const int32_t* __restrict__ active,
+// S: operator storage and arithmetic type; V: type of the level's z and r
+// (double on the finest level, whose z and r are the CG's).
+template <class S, class V>
+__global__ void k_rbgs3(int m, long long total, const S* __restrict__ T,
+                        const S* __restrict__ tb, V* __restrict__ z,
+                        const V* __restrict__ r, const int32_t* __restrict__ active,
                         int color, int zero_init) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -199,24 +211,39 @@ __global__ void k_rbgs3(int m, long long total, const double* __restrict__ T,
   const int l = row / m, j = row - l * m;
   const int i = 2 * (int)(rem - (long long)row * half) + ((j + l + color) & 1);
   const long long n = (long long)m * m * m;
-  const Faces3 f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
-  double* zs = z + s * n;
+  const Faces3T<S> f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
+  V* zs = z + s * n;
   const long long c = ((long long)l * m + j) * m + i;
-  const double rv = r[s * n + c];
-  zs[c] = zero_init ? rv / diag3(f) : (rv + nsum3(zs, m, i, j, l, f)) / diag3(f);
+  const S rv = (S)r[s * n + c];
+  zs[c] = (V)(zero_init ? rv / diag3(f) : (rv + nsum3(zs, m, i, j, l, f)) / diag3(f));
+}
+
+template <class S, class V>
+static void rbgs3_t(hipStream_t st, int m, int batch, const void* T, const void* tb, void* z,
+                    const void* r, const int32_t* active, int color, int zero_init) {
+  const long long total = (long long)batch * m * m * (m / 2);
+  hipLaunchKernelGGL((k_rbgs3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total,
+                     (const S*)T, (const S*)tb, (V*)z, (const V*)r, active, color, zero_init);
 }
 
 void launch_rbgs3(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
                   const double* r, const int32_t* active, int color, int zero_init) {
-  const long long total = (long long)batch * m * m * (m / 2);
-  hipLaunchKernelGGL(k_rbgs3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T, tb, z,
-                     r, active, color, zero_init);
+  rbgs3_t<double, double>(st, m, batch, T, tb, z, r, active, color, zero_init);
 }
 
-// rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z)
-__global__ void k_resid_restrict3(int m, long long total, const double* __restrict__ T,
-                                  const double* __restrict__ tb, const double* __restrict__ z,
-                                  const double* __restrict__ r, double* __restrict__ rc,
+void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
+                    const void* tb, void* z, const void* r, const int32_t* active, int color,
+                    int zero_init) {
+  if (!f32) rbgs3_t<double, double>(st, m, batch, T, tb, z, r, active, color, zero_init);
+  else if (top) rbgs3_t<float, double>(st, m, batch, T, tb, z, r, active, color, zero_init);
+  else rbgs3_t<float, float>(st, m, batch, T, tb, z, r, active, color, zero_init);
+}
+
+// rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z); rc in S.
+template <class S, class V>
+__global__ void k_resid_restrict3(int m, long long total, const S* __restrict__ T,
+                                  const S* __restrict__ tb, const V* __restrict__ z,
+                                  const V* __restrict__ r, S* __restrict__ rc,
                                   const int32_t* __restrict__ active) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -226,11 +253,11 @@ __global__ void k_resid_restrict3(int m, long long total, const double* __restri
   if (!active[s]) return;
   int I, J, L;
   cell_of(g - s * nc, mc, I, J, L);
-  const double* Ts = T + s * 3 * n;
-  const double* tbs = tb + s * 3 * m * m;
-  const double* zs = z + s * n;
-  const double* rs = r + s * n;
-  double acc = 0.0;
+  const S* Ts = T + s * 3 * n;
+  const S* tbs = tb + s * 3 * m * m;
+  const V* zs = z + s * n;
+  const V* rs = r + s * n;
+  S acc = S(0);
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
@@ -238,23 +265,40 @@ __global__ void k_resid_restrict3(int m, long long total, const double* __restri
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int i = 2 * I + a, j = 2 * J + bb, l = 2 * L + cc;
-        const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
+        const Faces3T<S> f = load_faces3(Ts, tbs, m, i, j, l);
         const long long c = ((long long)l * m + j) * m + i;
-        acc += rs[c] - (diag3(f) * zs[c] - nsum3(zs, m, i, j, l, f));
+        acc += (S)rs[c] - (diag3(f) * (S)zs[c] - nsum3(zs, m, i, j, l, f));
       }
   rc[g] = acc;
+}
+
+template <class S, class V>
+static void resid_restrict3_t(hipStream_t st, int m, int batch, const void* T, const void* tb,
+                              const void* z, const void* r, void* rc, const int32_t* active) {
+  const long long total = (long long)batch * (m / 2) * (m / 2) * (m / 2);
+  hipLaunchKernelGGL((k_resid_restrict3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m,
+                     total, (const S*)T, (const S*)tb, (const V*)z, (const V*)r, (S*)rc, active);
 }
 
 void launch_resid_restrict3(hipStream_t st, int m, int batch, const double* T, const double* tb,
                             const double* z, const double* r, double* rc,
                             const int32_t* active) {
-  const long long total = (long long)batch * (m / 2) * (m / 2) * (m / 2);
-  hipLaunchKernelGGL(k_resid_restrict3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, T,
-                     tb, z, r, rc, active);
+  resid_restrict3_t<double, double>(st, m, batch, T, tb, z, r, rc, active);
 }
 
-__global__ void k_prolong3(int m, long long total, const double* __restrict__ zc,
-                           double* __restrict__ z, double omega,
+void launch_resid_restrict3_p(hipStream_t st, bool f32, bool top, int m, int batch,
+                              const void* T, const void* tb, const void* z, const void* r,
+                              void* rc, const int32_t* active) {
+  if (!f32) resid_restrict3_t<double, double>(st, m, batch, T, tb, z, r, rc, active);
+  else if (top) resid_restrict3_t<float, double>(st, m, batch, T, tb, z, r, rc, active);
+  else resid_restrict3_t<float, float>(st, m, batch, T, tb, z, r, rc, active);
+}
+
+// z += omega * (coarse correction of the cell's 2 x 2 x 2 block); zc in S,
+// z in V (the addition is done in V).
+template <class S, class V>
+__global__ void k_prolong3(int m, long long total, const S* __restrict__ zc,
+                           V* __restrict__ z, double omega,
                            const int32_t* __restrict__ active) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -264,14 +308,52 @@ __global__ void k_prolong3(int m, long long total, const double* __restrict__ zc
   int i, j, l;
   cell_of(g - s * n, m, i, j, l);
   const int mc = m / 2;
-  z[g] += omega * zc[s * (long long)mc * mc * mc + ((long long)(l / 2) * mc + j / 2) * mc + i / 2];
+  z[g] += (V)omega *
+          (V)zc[s * (long long)mc * mc * mc + ((long long)(l / 2) * mc + j / 2) * mc + i / 2];
+}
+
+template <class S, class V>
+static void prolong3_t(hipStream_t st, int m, int batch, const void* zc, void* z, double omega,
+                       const int32_t* active) {
+  const long long total = (long long)batch * m * m * m;
+  hipLaunchKernelGGL((k_prolong3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total,
+                     (const S*)zc, (V*)z, omega, active);
 }
 
 void launch_prolong3(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
                      const int32_t* active) {
-  const long long total = (long long)batch * m * m * m;
-  hipLaunchKernelGGL(k_prolong3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, zc, z,
-                     omega, active);
+  prolong3_t<double, double>(st, m, batch, zc, z, omega, active);
+}
+
+void launch_prolong3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* zc,
+                       void* z, double omega, const int32_t* active) {
+  if (!f32) prolong3_t<double, double>(st, m, batch, zc, z, omega, active);
+  else if (top) prolong3_t<float, double>(st, m, batch, zc, z, omega, active);
+  else prolong3_t<float, float>(st, m, batch, zc, z, omega, active);
+}
+
+// z = A^-1 r on the coarsest grid for vectors of a reduced-precision
+// hierarchy: FP64 inverse and sums, r and z in float.
+__global__ void k_dense_apply3f(int n, long long total, const double* __restrict__ Ainv,
+                                const float* __restrict__ r, float* __restrict__ z,
+                                const int32_t* __restrict__ active) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long s = g / n;
+  if (!active[s]) return;
+  const int q = (int)(g - s * n);
+  const double* A = Ainv + s * n * n + (long long)q * n;
+  const float* rs = r + s * n;
+  double acc = 0.0;
+  for (int p = 0; p < n; ++p) acc += A[p] * (double)rs[p];
+  z[g] = (float)acc;
+}
+
+void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, const float* r,
+                          float* z, const int32_t* active) {
+  const long long total = (long long)batch * n;
+  hipLaunchKernelGGL(k_dense_apply3f, dim3(blocks_for(total)), dim3(kBlock), 0, st, n, total,
+                     Ainv, r, z, active);
 }
 
 // ------------------------------------------------------------------ coarsest grid

@@ -177,6 +177,19 @@ void launch_prolong3(hipStream_t st, int m, int batch, const double* zc, double*
                      const int32_t* active);
 void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, const double* tb,
                           double* Ainv);
+// Multigrid sweeps of a 3-D hierarchy in FP64 (f32 false) or with the operator,
+// z and r stored and computed in float (f32 true); on the finest level (top)
+// z and r are the CG's FP64 vectors in either case.
+void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
+                    const void* tb, void* z, const void* r, const int32_t* active, int color,
+                    int zero_init);
+void launch_resid_restrict3_p(hipStream_t st, bool f32, bool top, int m, int batch,
+                              const void* T, const void* tb, const void* z, const void* r,
+                              void* rc, const int32_t* active);
+void launch_prolong3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* zc,
+                       void* z, double omega, const int32_t* active);
+void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, const float* r,
+                          float* z, const int32_t* active);
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                       const double* p, double* q, double* partial, int bps, const int32_t* active);
 void launch_true_residual3(hipStream_t st, int m, int batch, const double* T, const double* tb,

@@ -168,10 +168,44 @@ def test_solve_3d_closed_forms(lib, ctx):
     assert abs(out["q_out"][0] - kj.mean()) <= 1e-11 * kj.mean()
 
 
+@pytest.mark.parametrize("m", [4, 8, 16, 32])
+def test_solve_3d_fp32_hierarchy(lib, ctx, m):
+    """The multigrid hierarchy in FP32 inside the flexible FP64 CG: every QoI at
+    the oracle's value (1e-10), iteration counts within a few of the FP64 ones."""
+    print("3-D FP32 hierarchy m=%d" % m, flush=True)
+    rng = np.random.default_rng(700 + m)
+    batch = 3
+    kh = np.exp(1.5 * rng.standard_normal((batch, m, m, m)))
+    o32 = solve3(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=lib.MLMC_PREC_FP32))
+    o64 = solve3(lib, ctx, kh)
+    assert np.all(o32["status"] == 0), o32["status"]
+    assert np.all(o32["iters"] <= o64["iters"] + 3), (o32["iters"], o64["iters"])
+    for s in range(batch):
+        A, b = ofv.assemble(kh[s])
+        q = oqoi.outflow(kh[s], osolve.direct_solve(A, b))
+        assert abs(o32["q_out"][s] - q) <= QTOL * q, (s, o32["q_out"][s], q)
+
+
+def test_level_run_3d_fp32_matches_oracle(lib, ctx):
+    m, n = 32, 3
+    print("3-D level run FP32 hierarchy m=%d" % m, flush=True)
+    qf, qc = f64(n), f64(n)
+    sums = lib.mlmc_level_run(ctx, MODEL, 1, m, 40, n, False,
+                              lib.mlmc_solver_opts_default(precision=lib.MLMC_PREC_FP32),
+                              q_f=qf, q_c=qc)
+    torch.cuda.synchronize()
+    assert sums.n_failed == 0
+    qf, qc = qf.cpu().numpy(), qc.cpu().numpy()
+    for s in range(n):
+        ref = omlmc.level_sample(MODEL, 1, 40 + s, m)
+        assert abs(qf[s] - ref["Q_f"]) <= QTOL * ref["Q_f"], (s, qf[s], ref["Q_f"])
+        assert abs(qc[s] - ref["Q_c"]) <= QTOL * ref["Q_c"], (s, qc[s], ref["Q_c"])
+
+
 def test_solve_3d_refusals(lib, ctx):
     kh = np.ones((1, 8, 8, 8))
     with pytest.raises(lib.MlmcError):
-        solve3(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=1))
+        solve3(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=lib.MLMC_PREC_BF16))
     with pytest.raises(lib.MlmcError):
         solve3(lib, ctx, np.ones((1, 10, 10, 10)))          # coarsest 5 > 4
 

@@ -142,11 +142,11 @@ SERVED_3D = Workload("3d-ce-tilted-32-128", TILTED3, [32, 64, 128], [64, 16, 4])
 # 64^2..512^2, the high-contrast 2-D model on 1024^2 and the 3-D model on
 # 32^3..128^3 in one server, each kind drawn with probability proportional to
 # its count; 2-D requests with the multigrid in FP32 inside the FP64 CG
-# (high contrast at its own tolerance), 3-D in FP64.
+# (high contrast at its own tolerance), 3-D with its FP32 hierarchy likewise.
 #   kinds: (model index, level, fine grid m, count)
 SERVED_MIX_MODELS = [CE2, CE_HC, TILTED3]
 SERVED_MIX_KINDS = [(0, 0, 64, 4096), (0, 1, 128, 1024), (0, 2, 256, 256), (0, 3, 512, 64),
                     (1, 0, 1024, 16),
                     (2, 0, 32, 64), (2, 1, 64, 16), (2, 2, 128, 4)]
-SERVED_MIX_PRECISION = ["f32", "f32", "f64"]
+SERVED_MIX_PRECISION = ["f32", "f32", "f32"]
 SERVED_MIX_TOL = [1e-13, 1e-15, 1e-13]
