@@ -123,8 +123,11 @@ mlmc_status mlmc_adaptive(mlmc_ctx* ctx, const mlmc_model* model, int max_levels
     // the missing samples of every level, each call a block of new sample numbers
     for (int l = 0; l <= L; ++l) {
       int64_t todo = dn[l];
+      // at most 2^26 fine cells per call (about 0.5 GB per FP64 field)
+      const double cells = std::pow((double)m_levels[l], (double)model->dim);
+      const int64_t cap = std::max<int64_t>(1, (int64_t)((double)(1 << 26) / cells));
       while (todo > 0) {
-        const int chunk = (int)std::min<int64_t>(todo, (int64_t)1 << 20);
+        const int chunk = (int)std::min<int64_t>(todo, std::min<int64_t>(cap, (int64_t)1 << 20));
         mlmc_model mdl = *model;
         if (n_ce) mdl.n_ce = n_ce[l];
         const auto t0 = std::chrono::steady_clock::now();
