@@ -167,7 +167,10 @@ typedef struct mlmc_solver_opts {
                            check_every iterations (even check_every; cached per
                            context and configuration; bitwise the same results;
                            not while a kernel is being profiled); default 0 */
-  int32_t reserved;
+  int32_t initial_guess; /* 1: p holds an initial guess on entry (2-D solves; the
+                            on-chip 64 x 64 path and the 3-D solver start from
+                            zero).  The stopping rule is ||r||/||b|| < tol either
+                            way (||b|| = ||r_0|| for the zero guess); default 0 */
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */

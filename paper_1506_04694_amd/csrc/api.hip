@@ -299,6 +299,8 @@ mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
   if (o->gamma < 1 || o->gamma > 2) return fail(ctx, MLMC_EINVAL, "gamma must be 1 or 2");
   if (o->gamma_levels < 0) return fail(ctx, MLMC_EINVAL, "gamma_levels must be >= 0");
   if (o->graph != 0 && o->graph != 1) return fail(ctx, MLMC_EINVAL, "graph must be 0 or 1");
+  if (o->initial_guess != 0 && o->initial_guess != 1)
+    return fail(ctx, MLMC_EINVAL, "initial_guess must be 0 or 1");
   if (o->variant < 0 || o->variant > 2) return fail(ctx, MLMC_EINVAL, "variant must be 0, 1 or 2");
   return MLMC_OK;
 }
@@ -389,7 +391,7 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* o) {
   o->gamma = 2;
   o->gamma_levels = 2;
   o->graph = 0;
-  o->reserved = 0;
+  o->initial_guess = 0;
   return MLMC_OK;
 }
 
@@ -1154,7 +1156,10 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   // One PCG pass over the active samples (all of them, or with `restart` the
   // ones marked by launch_sc_restart), x0 = 0.
   auto pcg_pass = [&](bool restart) -> mlmc_status {
-    launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
+    // a restart pass starts its samples from zero
+    if (!restart && opts->initial_guess)
+      launch_pcg_init_guess(st, m, batch, T, tb, b, p, r, partial, bps);
+    else launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
     launch_sc_init(st, batch, partial, bps, S, status, iters, relres, restart ? 1 : 0);
     ctx->prof_iter = restart ? 0 : 1;
     vcycle();
@@ -1282,15 +1287,17 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
                         (ncomp == 1) ? kc : nullptr));
   if (ncomp > 1) TRY(mlmc_cgv_extract(ctx, d, m, n, k, kc));
 
-  TRY(mlmc_assemble_problem(ctx, model->problem, d, m, n, k, T, tb, b));
-  TRY(mlmc_solve(ctx, d, m, n, T, tb, b, p, opts, stf, itf, relres));
-  TRY(model_qoi(ctx, model, d, m, n, k, p, qf));
-
+  // The companions are solved first: in 2-D the fine solve then starts from
+  // the solution of each sample's first companion, injected to the fine cells
+  // (about one CG iteration fewer; same stopping rule ||r||/||b|| < tol).
+  mlmc_solver_opts zero_guess = *opts;
+  zero_guess.initial_guess = 0;
   double* qcv = nullptr;
+  double* pc = nullptr;
   int32_t *stc = nullptr, *itc = nullptr;
   if (ncomp > 0) {
     const int nb = n * ncomp;
-    double *Tc, *tbc, *bc, *pc, *qcomp;
+    double *Tc, *tbc, *bc, *qcomp;
     TRY(ws(ctx, "lr_Tc", (size_t)nb * d * ncl, &Tc));
     TRY(ws(ctx, "lr_tbc", (size_t)nb * d * cface, &tbc));
     TRY(ws(ctx, "lr_bc", (size_t)nb * ncl, &bc));
@@ -1300,10 +1307,18 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
     TRY(ws(ctx, "lr_stc", nb, &stc));
     TRY(ws(ctx, "lr_itc", nb, &itc));
     TRY(mlmc_assemble_problem(ctx, model->problem, d, mc, nb, kc, Tc, tbc, bc));
-    TRY(mlmc_solve(ctx, d, mc, nb, Tc, tbc, bc, pc, opts, stc, itc, relres));
+    TRY(mlmc_solve(ctx, d, mc, nb, Tc, tbc, bc, pc, &zero_guess, stc, itc, relres));
     TRY(model_qoi(ctx, model, d, mc, nb, kc, pc, qcomp));
     launch_cgv_average(st, n, ncomp, qcomp, qcv);
   }
+  TRY(mlmc_assemble_problem(ctx, model->problem, d, m, n, k, T, tb, b));
+  mlmc_solver_opts fine = zero_guess;
+  if (d == 2 && ncomp > 0) {
+    launch_inject(st, m, n, ncomp, pc, p);
+    fine.initial_guess = 1;
+  }
+  TRY(mlmc_solve(ctx, d, m, n, T, tb, b, p, &fine, stf, itf, relres));
+  TRY(model_qoi(ctx, model, d, m, n, k, p, qf));
   launch_y_and_fail(st, n, qf, qcv, stf, stc, ncomp, yv, failed);
   launch_level_reduce(st, n, yv, qf, qcv, failed, itf, itc, ncomp, out);
   if (q_f) HIP_TRY(hipMemcpyAsync(q_f, qf, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
@@ -1453,14 +1468,37 @@ mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels
                           (pc && !cgv) ? kc : nullptr));
     if (pc && cgv) TRY(mlmc_cgv_extract(ctx, 2, m_fine[l], n[l], kf, kc));
   }
-  // one assemble + solve + QoI per grid
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
+  // one assemble + solve + QoI per grid, smallest grid first: as in
+  // mlmc_level_run, the fine samples of a level l >= 1 start from the
+  // solutions of their first companions (solved with grid m_l / 2, earlier),
+  // the other samples from zero, which gives the same iterates as a solve
+  // without a guess
+  std::vector<size_t> order(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) order[gi] = gi;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t b2) { return groups[a].m < groups[b2].m; });
+  for (size_t gi : order) {
     const Group& g = groups[gi];
     if (g.count == 0) continue;
     TRY(mlmc_assemble_problem(ctx, model->problem, 2, g.m, (int)g.count, gb[gi].k, gb[gi].T,
                               gb[gi].tb, gb[gi].b));
-    TRY(mlmc_solve(ctx, 2, g.m, (int)g.count, gb[gi].T, gb[gi].tb, gb[gi].b, gb[gi].p,
-                   &opts[g.opts_level], gb[gi].stt, gb[gi].it, gb[gi].rr));
+    mlmc_solver_opts o = opts[g.opts_level];
+    o.initial_guess = 0;
+    const long long cells = (long long)g.m * g.m;
+    for (const Part& pt : g.parts) {
+      size_t gcp = 0;
+      const Part* pc = (pt.role == 0 && pt.level > 0 && pt.count > 0 && g.m % 2 == 0)
+                           ? find(g.m / 2, pt.level, 1, &gcp)
+                           : nullptr;
+      if (!pc) continue;
+      if (!o.initial_guess)
+        HIP_TRY(hipMemsetAsync(gb[gi].p, 0, sizeof(double) * g.count * cells, st));
+      o.initial_guess = 1;
+      launch_inject(st, g.m, (int)pt.count, ncomp, gb[gcp].p + pc->off * (cells / 4),
+                    gb[gi].p + pt.off * cells);
+    }
+    TRY(mlmc_solve(ctx, 2, g.m, (int)g.count, gb[gi].T, gb[gi].tb, gb[gi].b, gb[gi].p, &o,
+                   gb[gi].stt, gb[gi].it, gb[gi].rr));
     TRY(model_qoi(ctx, model, 2, g.m, (int)g.count, gb[gi].k, gb[gi].p, gb[gi].q));
   }
   // per level: Y, failures, sums

@@ -127,6 +127,10 @@ void launch_cg_direction(hipStream_t st, int m, int batch, const double* T, cons
 // only != NULL: initialise just the samples with only[s] != 0
 void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* x, double* r,
                      double* partial, int bps, const int32_t* only);
+void launch_pcg_init_guess(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                           const double* b, const double* x, double* r, double* partial,
+                           int bps);
+void launch_inject(hipStream_t st, int m, int batch, int ncomp, const double* xc, double* x);
 void launch_spmv_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                      const double* p, double* q, double* partial, int bps,
                      const int32_t* active);

@@ -294,6 +294,64 @@ void launch_pcg_init(hipStream_t st, int n, int batch, const double* b, double* 
                      only);
 }
 
+// Start from the initial guess held in x: r = b - A x, and the same partial
+// sums of b^2 as k_pcg_init (the stopping rule is relative to ||b||, which for
+// x = 0 is ||r_0||; with x = 0 the result equals k_pcg_init's bit for bit).
+__global__ void __launch_bounds__(kBlock)
+k_pcg_init_guess(int m, const double* __restrict__ T, const double* __restrict__ tb,
+                 const double* __restrict__ b, const double* __restrict__ x,
+                 double* __restrict__ r, double* __restrict__ partial, int bps) {
+  __shared__ double sh[kBlock / kWave];
+  PCG_PROLOGUE
+  const int n = m * m;
+  const double* Ts = T + s * 2 * n;
+  const double* tbs = tb + s * 2 * m;
+  const double* xs = x + s * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const int cell = cell0 + c * kBlock;
+    if (cell < n) {
+      const int j = cell / m, i = cell - j * m;
+      const Faces f = load_faces(Ts, tbs, m, i, j);
+      const long long e = s * n + cell;
+      const double v = b[e];
+      r[e] = v - apply_at(xs, m, i, j, f);
+      acc += v * v;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[lbid] = t;
+}
+
+void launch_pcg_init_guess(hipStream_t st, int m, int batch, const double* T, const double* tb,
+                           const double* b, const double* x, double* r, double* partial,
+                           int bps) {
+  hipLaunchKernelGGL(k_pcg_init_guess, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, b, x, r,
+                     partial, bps);
+}
+
+// x0 of a fine grid from the solution of a coarse companion of the same
+// sample (companion 0 of the sample's ncomp, stored one after another): each
+// fine cell takes the value of the coarse cell that contains it.
+__global__ void k_inject(int m, long long total, int ncomp, const double* __restrict__ xc,
+                         double* __restrict__ x) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long n = (long long)m * m;
+  const long long s = g / n;
+  const int rem = (int)(g - s * n);
+  const int j = rem / m, i = rem - j * m;
+  const int mc = m / 2;
+  x[g] = xc[s * ncomp * (long long)mc * mc + (j / 2) * mc + i / 2];
+}
+
+void launch_inject(hipStream_t st, int m, int batch, int ncomp, const double* xc, double* x) {
+  const long long total = (long long)batch * m * m;
+  hipLaunchKernelGGL(k_inject, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, ncomp, xc,
+                     x);
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_spmv_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
            const double* __restrict__ p, double* __restrict__ q, double* __restrict__ partial,
