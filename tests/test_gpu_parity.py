@@ -234,6 +234,54 @@ def test_solve_failure_paths(lib, ctx):
         solve_batch(lib, ctx, np.ones((1, 88, 88)))     # 88 = 11 * 8: coarsest 11 > 8
 
 
+# ------------------------------------------------------------------ initial guess
+def solve_with_guess(lib, ctx, kh, x0, opts):
+    batch, m, _ = kh.shape
+    k = torch.from_numpy(np.ascontiguousarray(kh)).to(DEV)
+    T, tb, b = f64(batch, 2, m, m), f64(batch, 2, m), f64(batch, m, m)
+    p = torch.from_numpy(np.ascontiguousarray(x0)).to(DEV)
+    st, it, rr, qo = i32(batch), i32(batch), f64(batch), f64(batch)
+    lib.mlmc_assemble(ctx, 2, m, batch, k, T, tb, b)
+    lib.mlmc_solve(ctx, 2, m, batch, T, tb, b, p, opts, st, it, rr)
+    lib.mlmc_qoi_outflow(ctx, 2, m, batch, k, p, qo)
+    torch.cuda.synchronize()
+    return p.cpu().numpy(), st.cpu().numpy(), it.cpu().numpy(), qo.cpu().numpy()
+
+
+@pytest.mark.parametrize("m", [32, 64, 128])
+def test_initial_guess(lib, ctx, m):
+    """A zero guess with initial_guess = 1 gives the zero-start solve bit for bit;
+    a perturbed guess still reaches the oracle's QoI; the on-chip 64 x 64 path
+    starts from zero whatever p holds."""
+    print("initial guess m=%d" % m, flush=True)
+    rng = np.random.default_rng(40 + m)
+    batch = 3
+    kh = np.exp(1.5 * rng.standard_normal((batch, m, m)))
+    zero = np.zeros((batch, m, m))
+    pa, sa, ia, qa = solve_with_guess(lib, ctx, kh, zero, lib.mlmc_solver_opts_default())
+    pb, sb, ib, qb = solve_with_guess(lib, ctx, kh, zero,
+                                      lib.mlmc_solver_opts_default(initial_guess=1))
+    assert np.array_equal(pa, pb) and np.array_equal(ia, ib)
+    x1 = (np.arange(m) + 0.5) / m
+    guess = (1.0 - x1)[None, None, :] + 0.05 * rng.standard_normal((batch, m, m))
+    pc, sc, ic, qc = solve_with_guess(lib, ctx, kh, guess,
+                                      lib.mlmc_solver_opts_default(initial_guess=1))
+    assert np.all(sc == 0)
+    for s in range(batch):
+        A, bb = ofv.assemble(kh[s])
+        q = oqoi.outflow(kh[s], osolve.direct_solve(A, bb))
+        assert abs(qc[s] - q) <= QTOL * q, (s, qc[s], q)
+    if m == 64:
+        assert np.array_equal(pc, pa)          # on chip: the guess is not used
+
+
+def test_initial_guess_option_checked(lib, ctx):
+    kh = np.ones((1, 16, 16))
+    with pytest.raises(lib.MlmcError):
+        solve_with_guess(lib, ctx, kh, np.zeros((1, 16, 16)),
+                         lib.mlmc_solver_opts_default(initial_guess=2))
+
+
 # ------------------------------------------------------------------ level runs
 def level_run(lib, ctx, model, level, m, first, n, cgv, opts=None):
     qf, qc, y = f64(n), f64(n), f64(n)
