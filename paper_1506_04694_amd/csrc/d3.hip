@@ -359,7 +359,9 @@ void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, 
 // ------------------------------------------------------------------ coarsest grid
 // Explicit inverse of each sample's coarsest matrix (n = m^3 <= 64) by
 // Gauss-Jordan elimination without pivoting (SPD), as in 2-D.
-__global__ void __launch_bounds__(64)
+// 256 threads per sample: each elimination step updates n^2 <= 4096 entries.
+constexpr int kDenseThreads3 = 256;
+__global__ void __launch_bounds__(kDenseThreads3)
 k_dense_factor3(int m, int batch, const double* __restrict__ T, const double* __restrict__ tb,
                 double* __restrict__ Ainv) {
   __shared__ double A[64 * 64];
@@ -369,9 +371,9 @@ k_dense_factor3(int m, int batch, const double* __restrict__ T, const double* __
   const int n = m * m * m, mm = m * m;
   const double* Ts = T + (long long)s * 3 * n;
   const double* tbs = tb + (long long)s * 3 * mm;
-  for (int q = threadIdx.x; q < n * n; q += 64) A[q] = 0.0;
+  for (int q = threadIdx.x; q < n * n; q += kDenseThreads3) A[q] = 0.0;
   __syncthreads();
-  for (int c = threadIdx.x; c < n; c += 64) {
+  for (int c = threadIdx.x; c < n; c += kDenseThreads3) {
     int i, j, l;
     cell_of(c, m, i, j, l);
     const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
@@ -382,24 +384,26 @@ k_dense_factor3(int m, int batch, const double* __restrict__ T, const double* __
   }
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    for (int i = threadIdx.x; i < n; i += 64) col[i] = A[i * n + k];
+    for (int i = threadIdx.x; i < n; i += kDenseThreads3) col[i] = A[i * n + k];
     __syncthreads();
     const double piv = col[k];
-    for (int j = threadIdx.x; j < n; j += 64) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) / piv;
+    for (int j = threadIdx.x; j < n; j += kDenseThreads3)
+      A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) / piv;
     __syncthreads();
-    for (int q = threadIdx.x; q < n * n; q += 64) {
+    for (int q = threadIdx.x; q < n * n; q += kDenseThreads3) {
       const int i = q / n, j = q - i * n;
       if (i != k) A[q] = (j == k ? 0.0 : A[q]) - col[i] * A[k * n + j];
     }
     __syncthreads();
   }
   double* X = Ainv + (long long)s * n * n;
-  for (int q = threadIdx.x; q < n * n; q += 64) X[q] = A[q];
+  for (int q = threadIdx.x; q < n * n; q += kDenseThreads3) X[q] = A[q];
 }
 
 void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, const double* tb,
                           double* Ainv) {
-  hipLaunchKernelGGL(k_dense_factor3, dim3(batch), dim3(64), 0, st, m, batch, T, tb, Ainv);
+  hipLaunchKernelGGL(k_dense_factor3, dim3(batch), dim3(kDenseThreads3), 0, st, m, batch, T, tb,
+                     Ainv);
 }
 
 // ------------------------------------------------------------------ PCG stencil kernels
