@@ -690,7 +690,30 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   auto visits = [&](int l) {
     return (opts->gamma_levels == 0 || l < opts->gamma_levels) ? cur_gamma : 1;
   };
+  // levels from the first one of side <= 8 down run in one in-LDS kernel (nu = 1)
+  int l0 = -1;
+  CoarseDesc cdesc{};
+  if (nu == 1)
+    for (int l = 0; l < L; ++l)
+      if (ms[l] <= 8) {
+        l0 = l;
+        break;
+      }
+  if (l0 >= 0)
+    for (int q2 = 0; l0 + q2 <= L; ++q2) {
+      cdesc.m[q2] = ms[l0 + q2];
+      cdesc.T[q2] = Th[l0 + q2];
+      cdesc.tb[q2] = tbh[l0 + q2];
+    }
   std::function<void(int)> cycle = [&](int l) {
+    if (l == l0) {
+      unsigned wmask = 0;
+      for (int q2 = 0; l0 + q2 < L; ++q2)
+        if (visits(l0 + q2) == 2) wmask |= 1u << q2;
+      launch_coarse3_cycle(st, f32, l0 == 0, batch, L - l0 + 1, cdesc, rh[l0], zh[l0], Ainv, omega,
+                           wmask, S.active);
+      return;
+    }
     if (l == L) {
       if (f32 && L > 0)
         launch_dense_apply3f(st, nc, batch, Ainv, (const float*)rh[L], (float*)zh[L], S.active);
