@@ -154,6 +154,30 @@ def test_solve_3d_cycles_same_solution(lib, ctx, gamma, glev):
         assert abs(out["q_out"][s] - q) <= QTOL * q
 
 
+@pytest.mark.parametrize("m,coarse_max,glev,prec", [(6, 4, 2, 0), (8, 1, 0, 0), (8, 2, 0, 1),
+                                                    (12, 4, 0, 0), (16, 1, 2, 1), (24, 2, 0, 0),
+                                                    (32, 1, 0, 1)])
+def test_solve_3d_small_level_cycle(lib, ctx, m, coarse_max, glev, prec):
+    """The levels of side <= 8 run as one in-LDS cycle: hierarchies of two to
+    four such levels (coarsest 1, 2, 3 or 4), W on every level or on the two
+    finest, FP64 and FP32 hierarchies, the cycle starting at the finest level
+    (m <= 8) or below it.  QoIs at the oracle's value, iterations bounded."""
+    print("3-D small-level cycle m=%d coarse_max=%d gamma_levels=%d precision=%d"
+          % (m, coarse_max, glev, prec), flush=True)
+    rng = np.random.default_rng(1100 + m + coarse_max)
+    batch = 3
+    kh = np.exp(1.5 * rng.standard_normal((batch, m, m, m)))
+    opts = lib.mlmc_solver_opts_default(gamma=2, gamma_levels=glev, coarse_max=coarse_max,
+                                        precision=prec)
+    out = solve3(lib, ctx, kh, opts)
+    assert np.all(out["status"] == 0), out["status"]
+    assert np.all(out["iters"] <= 40), out["iters"]
+    for s in range(batch):
+        A, b = ofv.assemble(kh[s])
+        q = oqoi.outflow(kh[s], osolve.direct_solve(A, b))
+        assert abs(out["q_out"][s] - q) <= QTOL * q, (s, out["q_out"][s], q)
+
+
 def test_solve_3d_closed_forms(lib, ctx):
     m = 8
     kh = np.full((1, m, m, m), 3.7)
