@@ -474,6 +474,7 @@ def main():
     stream = torch.cuda.current_stream(dev)
     ctx = lib.mlmc_ctx_create(dev, stream)
     opts = lib.mlmc_solver_opts_default()
+    lopts = [lib.mlmc_solver_opts_default(**o) for o in W.LAYERED_CE_LEVEL_OPTS]
     nlev = len(wl.m_levels)
     level_times = [[] for _ in range(nlev)]
     iters = [[] for _ in range(nlev)]
@@ -493,7 +494,8 @@ def main():
             m, n = wl.m_levels[level], wl.n_samples[level]
             try:
                 t0 = time.perf_counter()
-                s = lib.mlmc_level_run(lctx[level], wl.model, level, m, idx * n, n, wl.cgv, opts)
+                s = lib.mlmc_level_run(lctx[level], wl.model, level, m, idx * n, n, wl.cgv,
+                                       lopts[level])
                 lstreams[level].synchronize()
                 dt = time.perf_counter() - t0
             except Exception as e:  # noqa: BLE001 - re-raised below on the main thread
@@ -522,10 +524,11 @@ def main():
         per level: the plain per-sample GPU solve the batched form is compared to."""
         out = []
         for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
-            lib.mlmc_level_run(ctx, wl.model, level, m, 10 ** 6, 1, wl.cgv, opts)  # warm
+            lib.mlmc_level_run(ctx, wl.model, level, m, 10 ** 6, 1, wl.cgv, lopts[level])  # warm
             done, t0 = 0, time.perf_counter()
             while time.perf_counter() - t0 < budget_s / len(wl.m_levels) and done < n:
-                lib.mlmc_level_run(ctx, wl.model, level, m, 10 ** 6 + 1 + done, 1, wl.cgv, opts)
+                lib.mlmc_level_run(ctx, wl.model, level, m, 10 ** 6 + 1 + done, 1, wl.cgv,
+                                   lopts[level])
                 done += 1
             dt = (time.perf_counter() - t0) / done
             out.append({"level": level, "m": m, "samples_timed": done, "ms_per_sample": 1e3 * dt,
@@ -630,6 +633,7 @@ def main():
            "config": {"workload": wl.name, "levels_m": wl.m_levels, "samples": wl.n_samples,
                       "estimator": "cgv" if wl.cgv else "plain", "tol_relres": opts.tol,
                       "n_ce": [wl.model.n_ce[m] for m in wl.m_levels],
+                      "solver_overrides_per_level": list(W.LAYERED_CE_LEVEL_OPTS),
                       "model": "2 layers, 8-node interface, exp. covariance r=2, sigma2=1, "
                                "lambda=0.3, means 0/2"},
            "levels_concurrent": bool(args.concurrent_levels),

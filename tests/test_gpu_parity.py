@@ -353,11 +353,13 @@ FULL = W.LAYERED_CE
 
 @pytest.mark.parametrize("level", [0, 1, 2, 3])
 def test_layered_ce_full_level_sampled(lib, ctx, level):
-    """Each level of the layered correlated workload at its full size (the launch the
-    bench times), with sampled samples checked against the oracle one by one."""
+    """Each level of the layered correlated workload at its full size with the
+    solver options the bench times it with, sampled samples checked against the
+    oracle one by one."""
     m, n = FULL.m_levels[level], FULL.n_samples[level]
     print("full level %d: %d x %d^2" % (level, n, m), flush=True)
-    sums, qf, qc, y = level_run(lib, ctx, FULL.model, level, m, 0, n, False)
+    opts = lib.mlmc_solver_opts_default(**W.LAYERED_CE_LEVEL_OPTS[level])
+    sums, qf, qc, y = level_run(lib, ctx, FULL.model, level, m, 0, n, False, opts)
     assert sums.n == n and sums.n_failed == 0
     assert np.all(np.isfinite(qf)) and np.all(qf > 0)
     lam = ofield.ce_eigenvalues(FULL.model.n_ce[m], m, 1.0, 0.3, 2)
