@@ -690,12 +690,13 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   auto visits = [&](int l) {
     return (opts->gamma_levels == 0 || l < opts->gamma_levels) ? cur_gamma : 1;
   };
-  // levels from the first one of side <= 8 down run in one in-LDS kernel (nu = 1)
+  // levels from the first one of side <= 8 (FP64) or 16 (FP32) down run in one
+  // in-LDS kernel (nu = 1)
   int l0 = -1;
   CoarseDesc cdesc{};
   if (nu == 1)
     for (int l = 0; l < L; ++l)
-      if (ms[l] <= 8) {
+      if (ms[l] <= coarse3_max_side(f32)) {
         l0 = l;
         break;
       }

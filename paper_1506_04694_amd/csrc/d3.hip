@@ -357,14 +357,28 @@ void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, 
 }
 
 // ------------------------------------------------------------------ coarse cycle in LDS
-// One 256-thread workgroup per sample runs the V- or W-cycle on the levels
-// l0..L of a 3-D hierarchy (m_l0 <= kLds3Max) with every level's operator and
-// vectors in LDS, in FP64 whatever the storage type, instead of one launch per
-// sweep on these small grids.  Level arrays use a padded (m + 2)^3 layout with
-// a one-cell ring: ring cells hold z = 0 and the boundary faces (west face at
-// i = -1, south face at j = -1, bottom face at l = -1), so the stencil needs no
-// branches.  Same steps and order as the per-sweep cycle.
-constexpr int kLds3Max = 8;
+// One workgroup per sample runs the V- or W-cycle on the levels l0..L of a
+// 3-D hierarchy with every level's operator and vectors in LDS, instead of one
+// launch per sweep on these small grids.  FP64 hierarchy: levels of side <= 8
+// in FP64 (about 53 KB), 256 threads.  FP32 hierarchy: levels of side <= 16
+// in FP32, the arithmetic of its per-sweep kernels (about 143 KB, one
+// workgroup per CU), 512 threads.  Level arrays use a padded (m + 2)^3 layout
+// with a one-cell ring: ring cells hold z = 0 and the boundary faces (west face
+// at i = -1, south face at j = -1, bottom face at l = -1), so the stencil needs
+// no branches.  Same steps and order as the per-sweep cycle.
+template <class E>
+struct Lds3Cfg;
+template <>
+struct Lds3Cfg<double> {
+  static constexpr int kMax = 8, kThreads = 256;
+  // 5 (m + 2)^3 words for m = 8, 4, 2, 1 and the coarsest right-hand side
+  static constexpr int kWords = 5 * (1000 + 216 + 64 + 27) + 64;
+};
+template <>
+struct Lds3Cfg<float> {
+  static constexpr int kMax = 16, kThreads = 512;
+  static constexpr int kWords = 5 * (5832 + 1000 + 216 + 64 + 27) + 64;
+};
 
 struct Lds3Level {
   int m, P, off;  // size, padded pitch (m + 2), offset of the level's arrays
@@ -374,41 +388,44 @@ __device__ __forceinline__ int pidx3(int P, int i, int j, int l) {
   return ((l + 1) * P + (j + 1)) * P + (i + 1);
 }
 
-// arrays of a level: te, tn, tu, r, z, each P^3 doubles
-__device__ void c3_sweep(double* a, int m, int P, int color, bool zero) {
+// arrays of a level: te, tn, tu, r, z, each P^3 words
+template <class E, int NT>
+__device__ void c3_sweep(E* a, int m, int P, int color, bool zero) {
   const int PPP = P * P * P, PP = P * P;
-  double* te = a;
-  double* tn = a + PPP;
-  double* tu = a + 2 * PPP;
-  double* rr = a + 3 * PPP;
-  double* zz = a + 4 * PPP;
+  E* te = a;
+  E* tn = a + PPP;
+  E* tu = a + 2 * PPP;
+  E* rr = a + 3 * PPP;
+  E* zz = a + 4 * PPP;
   const int half = m / 2 > 0 ? m / 2 : 1;
   const int cnt = m * m * half;
-  for (int c = threadIdx.x; c < cnt; c += 256) {
+  for (int c = threadIdx.x; c < cnt; c += NT) {
     const int row = c / half;  // row = l m + j
     const int l = row / m, j = row - l * m;
     const int i = 2 * (c - row * half) + ((j + l + color) & 1);
     if (i >= m) continue;
     const int f = pidx3(P, i, j, l);
-    const double d = te[f] + te[f - 1] + tn[f] + tn[f - P] + tu[f] + tu[f - PP];
+    const E d = te[f] + te[f - 1] + tn[f] + tn[f - P] + tu[f] + tu[f - PP];
     if (zero) {
       zz[f] = rr[f] / d;
     } else {
-      const double ns = te[f] * zz[f + 1] + te[f - 1] * zz[f - 1] + tn[f] * zz[f + P] +
-                        tn[f - P] * zz[f - P] + tu[f] * zz[f + PP] + tu[f - PP] * zz[f - PP];
+      const E ns = te[f] * zz[f + 1] + te[f - 1] * zz[f - 1] + tn[f] * zz[f + P] +
+                   tn[f - P] * zz[f - P] + tu[f] * zz[f + PP] + tu[f - PP] * zz[f - PP];
       zz[f] = (rr[f] + ns) / d;
     }
   }
   __syncthreads();
 }
 
-// S: storage type of the hierarchy; V: type of the first level's r and z.
-template <class S, class V>
-__global__ void __launch_bounds__(256)
+// S: storage type of the hierarchy; V: type of the first level's r and z;
+// E: LDS and arithmetic type.
+template <class S, class V, class E>
+__global__ void __launch_bounds__(Lds3Cfg<E>::kThreads)
 k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restrict__ z0,
                 const double* __restrict__ Ainv, double omega, unsigned wmask,
                 const int32_t* __restrict__ active) {
-  extern __shared__ double lds[];
+  constexpr int NT = Lds3Cfg<E>::kThreads;
+  __shared__ E lds[Lds3Cfg<E>::kWords];
   const int s = blockIdx.x;
   if (!active[s]) return;
   Lds3Level lv[kMaxCoarseLevels];
@@ -419,26 +436,26 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
     lv[q].off = off;
     off += 5 * lv[q].P * lv[q].P * lv[q].P;
   }
-  double* vec = lds + off;  // coarsest right-hand side
+  E* vec = lds + off;  // coarsest right-hand side
   for (int q = 0; q < nlev; ++q) {
     const int m = lv[q].m, P = lv[q].P, PPP = P * P * P, mm = m * m;
-    double* a = lds + lv[q].off;
+    E* a = lds + lv[q].off;
     const long long n = (long long)mm * m;
     const S* Ts = static_cast<const S*>(desc.T[q]) + (long long)s * 3 * n;
     const S* tbs = static_cast<const S*>(desc.tb[q]) + (long long)s * 3 * mm;
-    for (int f = threadIdx.x; f < PPP; f += 256) {
+    for (int f = threadIdx.x; f < PPP; f += NT) {
       const int i = f % P - 1, j = (f / P) % P - 1, l = f / (P * P) - 1;
       const bool ii = i >= 0 && i < m, jj = j >= 0 && j < m, ll = l >= 0 && l < m;
       const long long c = ((long long)l * m + j) * m + i;
-      double te = 0.0, tn = 0.0, tu = 0.0;
-      if (jj && ll) te = i == -1 ? (double)tbs[l * m + j] : (ii ? (double)Ts[c] : 0.0);
-      if (ii && ll) tn = j == -1 ? (double)tbs[mm + l * m + i] : (jj ? (double)Ts[n + c] : 0.0);
-      if (ii && jj) tu = l == -1 ? (double)tbs[2 * mm + j * m + i] : (ll ? (double)Ts[2 * n + c] : 0.0);
+      E te = E(0), tn = E(0), tu = E(0);
+      if (jj && ll) te = i == -1 ? (E)tbs[l * m + j] : (ii ? (E)Ts[c] : E(0));
+      if (ii && ll) tn = j == -1 ? (E)tbs[mm + l * m + i] : (jj ? (E)Ts[n + c] : E(0));
+      if (ii && jj) tu = l == -1 ? (E)tbs[2 * mm + j * m + i] : (ll ? (E)Ts[2 * n + c] : E(0));
       a[f] = te;
       a[PPP + f] = tn;
       a[2 * PPP + f] = tu;
-      a[3 * PPP + f] = (q == 0 && ii && jj && ll) ? (double)r0[(long long)s * n + c] : 0.0;
-      a[4 * PPP + f] = 0.0;
+      a[3 * PPP + f] = (q == 0 && ii && jj && ll) ? (E)r0[(long long)s * n + c] : E(0);
+      a[4 * PPP + f] = E(0);
     }
   }
   __syncthreads();
@@ -449,22 +466,22 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
   bool descending = true;
   for (;;) {
     const int m = lv[q].m, P = lv[q].P, PPP = P * P * P, PP = P * P;
-    double* a = lds + lv[q].off;
-    double* te = a;
-    double* tn = a + PPP;
-    double* tu = a + 2 * PPP;
-    double* rr = a + 3 * PPP;
-    double* zz = a + 4 * PPP;
+    E* a = lds + lv[q].off;
+    E* te = a;
+    E* tn = a + PPP;
+    E* tu = a + 2 * PPP;
+    E* rr = a + 3 * PPP;
+    E* zz = a + 4 * PPP;
     if (q == nlev - 1) {
       const int nc = m * m * m;
-      for (int c = threadIdx.x; c < nc; c += 256)
+      for (int c = threadIdx.x; c < nc; c += NT)
         vec[c] = rr[pidx3(P, c % m, (c / m) % m, c / (m * m))];
       __syncthreads();
       const double* A = Ainv + (long long)s * nc * nc;
-      for (int c = threadIdx.x; c < nc; c += 256) {
+      for (int c = threadIdx.x; c < nc; c += NT) {
         double acc = 0.0;
-        for (int p2 = 0; p2 < nc; ++p2) acc += A[(long long)c * nc + p2] * vec[p2];
-        zz[pidx3(P, c % m, (c / m) % m, c / (m * m))] = acc;
+        for (int p2 = 0; p2 < nc; ++p2) acc += A[(long long)c * nc + p2] * (double)vec[p2];
+        zz[pidx3(P, c % m, (c / m) % m, c / (m * m))] = (E)acc;
       }
       __syncthreads();
       if (q == 0) break;
@@ -473,18 +490,19 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
       continue;
     }
     if (descending) {
-      c3_sweep(a, m, P, 0, true);
-      c3_sweep(a, m, P, 1, false);
+      c3_sweep<E, NT>(a, m, P, 0, true);
+      c3_sweep<E, NT>(a, m, P, 1, false);
     } else {
       const int Pc = lv[q + 1].P, PPPc = Pc * Pc * Pc;
-      const double* zc = lds + lv[q + 1].off + 4 * PPPc;
-      for (int c = threadIdx.x; c < m * m * m; c += 256) {
+      const E* zc = lds + lv[q + 1].off + 4 * PPPc;
+      const E om = (E)omega;
+      for (int c = threadIdx.x; c < m * m * m; c += NT) {
         const int i = c % m, j = (c / m) % m, l = c / (m * m);
-        zz[pidx3(P, i, j, l)] += omega * zc[pidx3(Pc, i / 2, j / 2, l / 2)];
+        zz[pidx3(P, i, j, l)] += om * zc[pidx3(Pc, i / 2, j / 2, l / 2)];
       }
       __syncthreads();
-      c3_sweep(a, m, P, 1, false);
-      c3_sweep(a, m, P, 0, false);
+      c3_sweep<E, NT>(a, m, P, 1, false);
+      c3_sweep<E, NT>(a, m, P, 0, false);
       if (!(wmask >> q & 1u) || (once >> q & 1u)) {
         once &= ~(1u << q);
         if (q == 0) break;
@@ -492,19 +510,19 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
         continue;
       }
       once |= 1u << q;
-      c3_sweep(a, m, P, 1, false);
+      c3_sweep<E, NT>(a, m, P, 1, false);
     }
     // residual, restricted to the next level (sum over the 2 x 2 x 2 block)
     const int mc = lv[q + 1].m, Pc = lv[q + 1].P, PPPc = Pc * Pc * Pc;
-    double* rc = lds + lv[q + 1].off + 3 * PPPc;
-    for (int c = threadIdx.x; c < mc * mc * mc; c += 256) {
+    E* rc = lds + lv[q + 1].off + 3 * PPPc;
+    for (int c = threadIdx.x; c < mc * mc * mc; c += NT) {
       const int I = c % mc, J = (c / mc) % mc, L = c / (mc * mc);
-      double acc = 0.0;
+      E acc = E(0);
       for (int cc = 0; cc < 2; ++cc)
         for (int bb = 0; bb < 2; ++bb)
           for (int aa = 0; aa < 2; ++aa) {
             const int f = pidx3(P, 2 * I + aa, 2 * J + bb, 2 * L + cc);
-            const double d = te[f] + te[f - 1] + tn[f] + tn[f - P] + tu[f] + tu[f - PP];
+            const E d = te[f] + te[f - 1] + tn[f] + tn[f - P] + tu[f] + tu[f - PP];
             acc += rr[f] - (d * zz[f] - (te[f] * zz[f + 1] + te[f - 1] * zz[f - 1] +
                                          tn[f] * zz[f + P] + tn[f - P] * zz[f - P] +
                                          tu[f] * zz[f + PP] + tu[f - PP] * zz[f - PP]));
@@ -517,33 +535,30 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
   }
   {
     const int m = lv[0].m, P = lv[0].P, PPP = P * P * P;
-    const double* zz = lds + lv[0].off + 4 * PPP;
+    const E* zz = lds + lv[0].off + 4 * PPP;
     const long long n = (long long)m * m * m;
-    for (int c = threadIdx.x; c < n; c += 256)
+    for (int c = threadIdx.x; c < n; c += NT)
       z0[(long long)s * n + c] = (V)zz[pidx3(P, c % m, (c / m) % m, c / (m * m))];
   }
 }
 
-size_t coarse3_lds_bytes(int nlev, const int* m) {
-  size_t words = 0;
-  for (int q = 0; q < nlev; ++q) words += 5 * (size_t)(m[q] + 2) * (m[q] + 2) * (m[q] + 2);
-  const int mc = m[nlev - 1];
-  return (words + (size_t)mc * mc * mc) * sizeof(double);
-}
+int coarse3_max_side(bool f32) { return f32 ? Lds3Cfg<float>::kMax : Lds3Cfg<double>::kMax; }
 
 void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nlev,
                           const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
                           double omega, unsigned wmask, const int32_t* active) {
-  const size_t lds = coarse3_lds_bytes(nlev, desc.m);
   if (!f32)
-    hipLaunchKernelGGL((k_coarse3_cycle<double, double>), dim3(batch), dim3(256), lds, st, nlev,
-                       desc, (const double*)r0, (double*)z0, Ainv, omega, wmask, active);
+    hipLaunchKernelGGL((k_coarse3_cycle<double, double, double>), dim3(batch),
+                       dim3(Lds3Cfg<double>::kThreads), 0, st, nlev, desc, (const double*)r0,
+                       (double*)z0, Ainv, omega, wmask, active);
   else if (top)
-    hipLaunchKernelGGL((k_coarse3_cycle<float, double>), dim3(batch), dim3(256), lds, st, nlev,
-                       desc, (const double*)r0, (double*)z0, Ainv, omega, wmask, active);
+    hipLaunchKernelGGL((k_coarse3_cycle<float, double, float>), dim3(batch),
+                       dim3(Lds3Cfg<float>::kThreads), 0, st, nlev, desc, (const double*)r0,
+                       (double*)z0, Ainv, omega, wmask, active);
   else
-    hipLaunchKernelGGL((k_coarse3_cycle<float, float>), dim3(batch), dim3(256), lds, st, nlev,
-                       desc, (const float*)r0, (float*)z0, Ainv, omega, wmask, active);
+    hipLaunchKernelGGL((k_coarse3_cycle<float, float, float>), dim3(batch),
+                       dim3(Lds3Cfg<float>::kThreads), 0, st, nlev, desc, (const float*)r0,
+                       (float*)z0, Ainv, omega, wmask, active);
 }
 
 // ------------------------------------------------------------------ coarsest grid

@@ -195,8 +195,10 @@ void launch_prolong3_p(hipStream_t st, bool f32, bool top, int m, int batch, con
 void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, const float* r,
                           float* z, const int32_t* active);
 // The cycle on levels l0..L of a 3-D hierarchy (desc: their sizes and
-// operators, m_l0 <= 8) in LDS, one workgroup per sample; wmask bit q: level
-// l0 + q takes two coarse visits.  r0, z0: the vectors of level l0.
+// operators, m_l0 <= coarse3_max_side(f32), coarsest <= 4) in LDS, one
+// workgroup per sample; wmask bit q: level l0 + q takes two coarse visits.
+// r0, z0: the vectors of level l0.
+int coarse3_max_side(bool f32);
 void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nlev,
                           const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
                           double omega, unsigned wmask, const int32_t* active);

@@ -155,13 +155,14 @@ def test_solve_3d_cycles_same_solution(lib, ctx, gamma, glev):
 
 
 @pytest.mark.parametrize("m,coarse_max,glev,prec", [(6, 4, 2, 0), (8, 1, 0, 0), (8, 2, 0, 1),
-                                                    (12, 4, 0, 0), (16, 1, 2, 1), (24, 2, 0, 0),
-                                                    (32, 1, 0, 1)])
+                                                    (12, 4, 0, 0), (12, 2, 2, 1), (16, 1, 2, 1),
+                                                    (24, 2, 0, 0), (24, 4, 0, 1), (32, 1, 0, 1),
+                                                    (32, 4, 2, 1)])
 def test_solve_3d_small_level_cycle(lib, ctx, m, coarse_max, glev, prec):
-    """The levels of side <= 8 run as one in-LDS cycle: hierarchies of two to
-    four such levels (coarsest 1, 2, 3 or 4), W on every level or on the two
-    finest, FP64 and FP32 hierarchies, the cycle starting at the finest level
-    (m <= 8) or below it.  QoIs at the oracle's value, iterations bounded."""
+    """The levels of side <= 8 (FP64 hierarchy) or <= 16 (FP32) run as one
+    in-LDS cycle: hierarchies of two to five such levels (coarsest 1, 2, 3 or
+    4), W on every level or on the two finest, the cycle starting at the finest
+    level or below it.  QoIs at the oracle's value, iterations bounded."""
     print("3-D small-level cycle m=%d coarse_max=%d gamma_levels=%d precision=%d"
           % (m, coarse_max, glev, prec), flush=True)
     rng = np.random.default_rng(1100 + m + coarse_max)
