@@ -362,7 +362,8 @@ void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, 
 // launch per sweep on these small grids.  FP64 hierarchy: levels of side <= 8
 // in FP64 (about 53 KB), 256 threads.  FP32 hierarchy: levels of side <= 16
 // in FP32, the arithmetic of its per-sweep kernels (about 143 KB, one
-// workgroup per CU), 512 threads.  Level arrays use a padded (m + 2)^3 layout
+// workgroup per CU, so 1024 threads cost no occupancy: two cells per thread
+// and sweep at 16^3).  Level arrays use a padded (m + 2)^3 layout
 // with a one-cell ring: ring cells hold z = 0 and the boundary faces (west face
 // at i = -1, south face at j = -1, bottom face at l = -1), so the stencil needs
 // no branches.  Same steps and order as the per-sweep cycle.
@@ -376,7 +377,7 @@ struct Lds3Cfg<double> {
 };
 template <>
 struct Lds3Cfg<float> {
-  static constexpr int kMax = 16, kThreads = 512;
+  static constexpr int kMax = 16, kThreads = 1024;
   static constexpr int kWords = 5 * (5832 + 1000 + 216 + 64 + 27) + 64;
 };
 
