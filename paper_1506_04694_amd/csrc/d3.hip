@@ -478,11 +478,18 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
       for (int c = threadIdx.x; c < nc; c += NT)
         vec[c] = rr[pidx3(P, c % m, (c / m) % m, c / (m * m))];
       __syncthreads();
+      // row c of the inverse by the 16 lanes t = 16 c + k (entries k, k + 16, ...),
+      // summed over the lane group; groups never straddle the loop bound
       const double* A = Ainv + (long long)s * nc * nc;
-      for (int c = threadIdx.x; c < nc; c += NT) {
+      for (int t = threadIdx.x; t < 16 * nc; t += NT) {
+        const int c = t >> 4, k = t & 15;
         double acc = 0.0;
-        for (int p2 = 0; p2 < nc; ++p2) acc += A[(long long)c * nc + p2] * (double)vec[p2];
-        zz[pidx3(P, c % m, (c / m) % m, c / (m * m))] = (E)acc;
+        for (int p2 = k; p2 < nc; p2 += 16) acc += A[(long long)c * nc + p2] * (double)vec[p2];
+        acc += __shfl_xor(acc, 8, 16);
+        acc += __shfl_xor(acc, 4, 16);
+        acc += __shfl_xor(acc, 2, 16);
+        acc += __shfl_xor(acc, 1, 16);
+        if (k == 0) zz[pidx3(P, c % m, (c / m) % m, c / (m * m))] = (E)acc;
       }
       __syncthreads();
       if (q == 0) break;
@@ -516,19 +523,20 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
     // residual, restricted to the next level (sum over the 2 x 2 x 2 block)
     const int mc = lv[q + 1].m, Pc = lv[q + 1].P, PPPc = Pc * Pc * Pc;
     E* rc = lds + lv[q + 1].off + 3 * PPPc;
-    for (int c = threadIdx.x; c < mc * mc * mc; c += NT) {
+    // one fine cell per lane, t = 8 c + (aa + 2 bb + 4 cc), summed over the
+    // 8-lane group of coarse cell c (groups never straddle the loop bound)
+    for (int t = threadIdx.x; t < 8 * mc * mc * mc; t += NT) {
+      const int c = t >> 3, k = t & 7;
       const int I = c % mc, J = (c / mc) % mc, L = c / (mc * mc);
-      E acc = E(0);
-      for (int cc = 0; cc < 2; ++cc)
-        for (int bb = 0; bb < 2; ++bb)
-          for (int aa = 0; aa < 2; ++aa) {
-            const int f = pidx3(P, 2 * I + aa, 2 * J + bb, 2 * L + cc);
-            const E d = te[f] + te[f - 1] + tn[f] + tn[f - P] + tu[f] + tu[f - PP];
-            acc += rr[f] - (d * zz[f] - (te[f] * zz[f + 1] + te[f - 1] * zz[f - 1] +
-                                         tn[f] * zz[f + P] + tn[f - P] * zz[f - P] +
-                                         tu[f] * zz[f + PP] + tu[f - PP] * zz[f - PP]));
-          }
-      rc[pidx3(Pc, I, J, L)] = acc;
+      const int f = pidx3(P, 2 * I + (k & 1), 2 * J + ((k >> 1) & 1), 2 * L + (k >> 2));
+      const E d = te[f] + te[f - 1] + tn[f] + tn[f - P] + tu[f] + tu[f - PP];
+      E v = rr[f] - (d * zz[f] - (te[f] * zz[f + 1] + te[f - 1] * zz[f - 1] + tn[f] * zz[f + P] +
+                                  tn[f - P] * zz[f - P] + tu[f] * zz[f + PP] +
+                                  tu[f - PP] * zz[f - PP]));
+      v += __shfl_xor(v, 4, 8);
+      v += __shfl_xor(v, 2, 8);
+      v += __shfl_xor(v, 1, 8);
+      if (k == 0) rc[pidx3(Pc, I, J, L)] = v;
     }
     __syncthreads();
     ++q;
