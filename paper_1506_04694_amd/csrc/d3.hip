@@ -400,9 +400,11 @@ __device__ void c3_sweep(E* a, int m, int P, int color, bool zero) {
   E* zz = a + 4 * PPP;
   const int half = m / 2 > 0 ? m / 2 : 1;
   const int cnt = m * m * half;
+  // quotients through one FP32 multiply (exact for these small operands)
+  const float inv_half = 1.0f / (float)half, inv_m = 1.0f / (float)m;
   for (int c = threadIdx.x; c < cnt; c += NT) {
-    const int row = c / half;  // row = l m + j
-    const int l = row / m, j = row - l * m;
+    const int row = div_small(c, inv_half);  // row = l m + j
+    const int l = div_small(row, inv_m), j = row - l * m;
     const int i = 2 * (c - row * half) + ((j + l + color) & 1);
     if (i >= m) continue;
     const int f = pidx3(P, i, j, l);
@@ -444,8 +446,10 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
     const long long n = (long long)mm * m;
     const S* Ts = static_cast<const S*>(desc.T[q]) + (long long)s * 3 * n;
     const S* tbs = static_cast<const S*>(desc.tb[q]) + (long long)s * 3 * mm;
+    const float inv_P = 1.0f / (float)P;
     for (int f = threadIdx.x; f < PPP; f += NT) {
-      const int i = f % P - 1, j = (f / P) % P - 1, l = f / (P * P) - 1;
+      const int row = div_small(f, inv_P), lp = div_small(row, inv_P);  // row = (l+1) P + (j+1)
+      const int i = f - row * P - 1, j = row - lp * P - 1, l = lp - 1;
       const bool ii = i >= 0 && i < m, jj = j >= 0 && j < m, ll = l >= 0 && l < m;
       const long long c = ((long long)l * m + j) * m + i;
       E te = E(0), tn = E(0), tu = E(0);
@@ -504,8 +508,10 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
       const int Pc = lv[q + 1].P, PPPc = Pc * Pc * Pc;
       const E* zc = lds + lv[q + 1].off + 4 * PPPc;
       const E om = (E)omega;
+      const float inv_m = 1.0f / (float)m;
       for (int c = threadIdx.x; c < m * m * m; c += NT) {
-        const int i = c % m, j = (c / m) % m, l = c / (m * m);
+        const int row = div_small(c, inv_m), i = c - row * m;  // row = l m + j
+        const int l = div_small(row, inv_m), j = row - l * m;
         zz[pidx3(P, i, j, l)] += om * zc[pidx3(Pc, i / 2, j / 2, l / 2)];
       }
       __syncthreads();
@@ -525,9 +531,11 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
     E* rc = lds + lv[q + 1].off + 3 * PPPc;
     // one fine cell per lane, t = 8 c + (aa + 2 bb + 4 cc), summed over the
     // 8-lane group of coarse cell c (groups never straddle the loop bound)
+    const float inv_mc = 1.0f / (float)mc;
     for (int t = threadIdx.x; t < 8 * mc * mc * mc; t += NT) {
       const int c = t >> 3, k = t & 7;
-      const int I = c % mc, J = (c / mc) % mc, L = c / (mc * mc);
+      const int row = div_small(c, inv_mc), I = c - row * mc;  // row = L mc + J
+      const int L = div_small(row, inv_mc), J = row - L * mc;
       const int f = pidx3(P, 2 * I + (k & 1), 2 * J + ((k >> 1) & 1), 2 * L + (k >> 2));
       const E d = te[f] + te[f - 1] + tn[f] + tn[f - P] + tu[f] + tu[f - PP];
       E v = rr[f] - (d * zz[f] - (te[f] * zz[f + 1] + te[f - 1] * zz[f - 1] + tn[f] * zz[f + P] +
