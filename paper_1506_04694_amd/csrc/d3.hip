@@ -77,6 +77,70 @@ __device__ __forceinline__ void cell_of(long long rem, int m, int& i, int& j, in
   i = r2 - j * m;
 }
 
+// Quotient n / d for 0 <= n < 2^32 and a divisor 1 <= d < 2^31 fixed per launch,
+// through a multiply-high (Granlund and Montgomery, PLDI 1994, round-up
+// method): with l = ceil(log2 d) and mul = floor(2^32 (2^l - d) / d) + 1,
+// t = mulhi(n, mul) and q = (t + ((n - t) >> 1)) >> (l - 1) (l = 0: q = n).
+// The per-sweep kernels index their cells with it instead of 64-bit divisions.
+struct FastDiv {
+  uint32_t d, mul, s1, s2;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  d = d > 0 ? d : 1u;  // (empty grids)
+  FastDiv f{d, 1u, 0u, 0u};
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  f.mul = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d + 1) & 0xFFFFFFFFull);
+  f.s1 = l > 0 ? 1u : 0u;
+  f.s2 = l > 0 ? (uint32_t)(l - 1) : 0u;
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  const uint32_t t = __umulhi(n, f.mul);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// Cell (i, j, l) and sample s of flat index g = s n + (l a + j) b + i, where n is
+// the per-sample count, mm.d = a b and m.d = b (a = b = m for a whole grid),
+// through three FastDivs, or 64-bit divisions when the launch has 2^32 or more
+// threads (fast = false).
+struct CellDiv {
+  FastDiv per, mm, m;
+  int fast;
+};
+
+inline CellDiv make_celldiv(long long total, long long per, int m) {
+  CellDiv c;
+  c.fast = total < (1ll << 32) && per < (1ll << 31);
+  c.per = make_fastdiv(c.fast ? (uint32_t)per : 1u);
+  c.mm = make_fastdiv((uint32_t)m * (uint32_t)m);
+  c.m = make_fastdiv((uint32_t)m);
+  return c;
+}
+
+__device__ __forceinline__ long long split_cell(long long g, long long per, const CellDiv& cd,
+                                                int& i, int& j, int& l) {
+  if (cd.fast) {
+    const uint32_t gg = (uint32_t)g;
+    const uint32_t s = fdiv(gg, cd.per);
+    const uint32_t rem = gg - s * cd.per.d;
+    l = (int)fdiv(rem, cd.mm);
+    const uint32_t r2 = rem - (uint32_t)l * cd.mm.d;
+    j = (int)fdiv(r2, cd.m);
+    i = (int)(r2 - (uint32_t)j * cd.m.d);
+    return (long long)s;
+  }
+  const long long s = g / per;
+  const long long rem = g - s * per;
+  l = (int)(rem / (long long)cd.mm.d);
+  const long long r2 = rem - (long long)l * cd.mm.d;
+  j = (int)(r2 / (long long)cd.m.d);
+  i = (int)(r2 - (long long)j * cd.m.d);
+  return s;
+}
+
 // ------------------------------------------------------------------ assembly
 // Model Problem 2 as in 2-D, with T scaled by the face area / centre distance
 // h^2 / h = h; Model Problem 1: every boundary face Dirichlet (T = 2 k h),
@@ -199,17 +263,17 @@ template <class S, class V>
 __global__ void k_rbgs3(int m, long long total, const S* __restrict__ T,
                         const S* __restrict__ tb, V* __restrict__ z,
                         const V* __restrict__ r, const int32_t* __restrict__ active,
-                        int color, int zero_init) {
+                        int color, int zero_init, CellDiv cd) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int half = m / 2;
   const long long per = (long long)m * m * half;
-  const long long s = g / per;
+  // (sample, l, j, h) of g as a cell of an m x m x half grid: the red or black
+  // cell of column pair h in row (l, j)
+  int h, j, l;
+  const long long s = split_cell(g, per, cd, h, j, l);
   if (!active[s]) return;
-  const long long rem = g - s * per;
-  const int row = (int)(rem / half);  // row = l m + j
-  const int l = row / m, j = row - l * m;
-  const int i = 2 * (int)(rem - (long long)row * half) + ((j + l + color) & 1);
+  const int i = 2 * h + ((j + l + color) & 1);
   const long long n = (long long)m * m * m;
   const Faces3T<S> f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
   V* zs = z + s * n;
@@ -222,8 +286,12 @@ template <class S, class V>
 static void rbgs3_t(hipStream_t st, int m, int batch, const void* T, const void* tb, void* z,
                     const void* r, const int32_t* active, int color, int zero_init) {
   const long long total = (long long)batch * m * m * (m / 2);
+  // split_cell's rows are (l, j) pairs of m x m, the fastest index a column pair
+  CellDiv cd = make_celldiv(total, (long long)m * m * (m / 2), m);
+  cd.mm = make_fastdiv((uint32_t)m * (uint32_t)(m / 2));
+  cd.m = make_fastdiv((uint32_t)(m / 2));
   hipLaunchKernelGGL((k_rbgs3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total,
-                     (const S*)T, (const S*)tb, (V*)z, (const V*)r, active, color, zero_init);
+                     (const S*)T, (const S*)tb, (V*)z, (const V*)r, active, color, zero_init, cd);
 }
 
 void launch_rbgs3(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
@@ -244,15 +312,14 @@ template <class S, class V>
 __global__ void k_resid_restrict3(int m, long long total, const S* __restrict__ T,
                                   const S* __restrict__ tb, const V* __restrict__ z,
                                   const V* __restrict__ r, S* __restrict__ rc,
-                                  const int32_t* __restrict__ active) {
+                                  const int32_t* __restrict__ active, CellDiv cd) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int mc = m / 2;
   const long long nc = (long long)mc * mc * mc, n = (long long)m * m * m;
-  const long long s = g / nc;
-  if (!active[s]) return;
   int I, J, L;
-  cell_of(g - s * nc, mc, I, J, L);
+  const long long s = split_cell(g, nc, cd, I, J, L);
+  if (!active[s]) return;
   const S* Ts = T + s * 3 * n;
   const S* tbs = tb + s * 3 * m * m;
   const V* zs = z + s * n;
@@ -276,8 +343,10 @@ template <class S, class V>
 static void resid_restrict3_t(hipStream_t st, int m, int batch, const void* T, const void* tb,
                               const void* z, const void* r, void* rc, const int32_t* active) {
   const long long total = (long long)batch * (m / 2) * (m / 2) * (m / 2);
+  const CellDiv cd = make_celldiv(total, (long long)(m / 2) * (m / 2) * (m / 2), m / 2);
   hipLaunchKernelGGL((k_resid_restrict3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m,
-                     total, (const S*)T, (const S*)tb, (const V*)z, (const V*)r, (S*)rc, active);
+                     total, (const S*)T, (const S*)tb, (const V*)z, (const V*)r, (S*)rc, active,
+                     cd);
 }
 
 void launch_resid_restrict3(hipStream_t st, int m, int batch, const double* T, const double* tb,
@@ -299,14 +368,13 @@ void launch_resid_restrict3_p(hipStream_t st, bool f32, bool top, int m, int bat
 template <class S, class V>
 __global__ void k_prolong3(int m, long long total, const S* __restrict__ zc,
                            V* __restrict__ z, double omega,
-                           const int32_t* __restrict__ active) {
+                           const int32_t* __restrict__ active, CellDiv cd) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const long long n = (long long)m * m * m;
-  const long long s = g / n;
-  if (!active[s]) return;
   int i, j, l;
-  cell_of(g - s * n, m, i, j, l);
+  const long long s = split_cell(g, n, cd, i, j, l);
+  if (!active[s]) return;
   const int mc = m / 2;
   z[g] += (V)omega *
           (V)zc[s * (long long)mc * mc * mc + ((long long)(l / 2) * mc + j / 2) * mc + i / 2];
@@ -316,8 +384,9 @@ template <class S, class V>
 static void prolong3_t(hipStream_t st, int m, int batch, const void* zc, void* z, double omega,
                        const int32_t* active) {
   const long long total = (long long)batch * m * m * m;
+  const CellDiv cd = make_celldiv(total, (long long)m * m * m, m);
   hipLaunchKernelGGL((k_prolong3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total,
-                     (const S*)zc, (V*)z, omega, active);
+                     (const S*)zc, (V*)z, omega, active, cd);
 }
 
 void launch_prolong3(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
