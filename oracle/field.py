@@ -7,7 +7,7 @@
   exp(g_l(x)), g_l a stationary Gaussian field with mean mu_l and covariance
   sigma_l^2 exp(-||x - y||_r / lambda_l).  Section 3.4 samples such fields by
   circulant embedding (Wood and Chan 1994; Dietrich and Newsam 1997), which
-  is exact on a regular grid.  The steps, in order:
+  is exact on a regular grid.  The method, in order:
     1. first row of the covariance matrix of the embedding torus of
        n_ce^d points with spacing h = 1/m, distance per axis min(a, n_ce-a) h;
     2. its eigenvalues Lambda = FFT(first row) (forward DFT, exp(-2 pi i jk/N));
@@ -135,7 +135,10 @@ def ce_noise(model, level, sample, pair, n_ce, dim):
 
 
 def ce_transform(xi, lam_eig, m):
-    """Steps 5-6: y = FFT(sqrt(Lambda / n_ce^d) xi), restricted to [0, m)^d."""
+    """Circulant embedding sample (Section 3.4, covariance eq. (2.3)): the
+    scaled noise sqrt(Lambda / n_ce^d) xi transformed by the forward DFT,
+    y = FFT(sqrt(Lambda / n_ce^d) xi); Re y and Im y restricted to the grid
+    points [0, m)^d."""
     dim = xi.ndim
     n_ce = xi.shape[0]
     y = np.fft.fftn(np.sqrt(lam_eig / float(n_ce ** dim)) * xi)

@@ -18,12 +18,13 @@ import numpy as np
 from . import field, fv, qoi, solve
 
 
-def solve_qoi(k, bc=fv.MP2):
+def solve_qoi(k, bc=fv.MP2, solver="auto"):
     """Exact discrete QoI for one permeability sample: Model Problem 2, the
     outflow and the inflow; Model Problem 1, M^(1) (box mean of the pressure)
-    and None."""
+    and None.  solver: "direct", "cg" or "auto" (direct solve except for 3-D
+    grids above 32^3, which take the conjugate gradient solve to 1e-14)."""
     A, b = fv.assemble(k, bc)
-    p = solve.direct_solve(A, b)
+    p = solve.solve(A, b, k.ndim, k.shape[0], solver)
     if bc == fv.MP1:
         return qoi.box_average(p.reshape(k.shape)), None
     return qoi.outflow(k, p), qoi.inflow(k, p)
@@ -35,7 +36,7 @@ def problem_of(model):
     return fv.MP1 if getattr(model, "problem", 0) == 1 else fv.MP2
 
 
-def level_sample(model, level, sample, m_fine, cgv=False, lam_eig=None):
+def level_sample(model, level, sample, m_fine, cgv=False, lam_eig=None, solver="auto"):
     """One term of eq. (3.6) (or eq. (4.2) when cgv) for sample `sample` of level `level`.
 
     Returns dict with Q_f (fine QoI), Q_c (coarse QoI; 0 on level 0), Y = Q_f - Q_c,
@@ -44,17 +45,17 @@ def level_sample(model, level, sample, m_fine, cgv=False, lam_eig=None):
     bc = problem_of(model)
     if level == 0:
         k = field.sample_k(model, level, sample, m_fine, lam_eig=lam_eig)
-        qf, _ = solve_qoi(k, bc)
+        qf, _ = solve_qoi(k, bc, solver)
         return {"Q_f": qf, "Q_c": 0.0, "Y": qf, "companions": []}
     if cgv:
         k = field.sample_k(model, level, sample, m_fine, lam_eig=lam_eig)
-        qf, _ = solve_qoi(k, bc)
-        comps = [solve_qoi(kc, bc)[0] for kc in field.cgv_sublattices(k)]
+        qf, _ = solve_qoi(k, bc, solver)
+        comps = [solve_qoi(kc, bc, solver)[0] for kc in field.cgv_sublattices(k)]
         qc = sum(comps) / len(comps)
     else:
         k, kc = field.sample_k(model, level, sample, m_fine, lam_eig=lam_eig, with_coarse=True)
-        qf, _ = solve_qoi(k, bc)
-        comps = [solve_qoi(kc, bc)[0]]
+        qf, _ = solve_qoi(k, bc, solver)
+        comps = [solve_qoi(kc, bc, solver)[0]]
         qc = comps[0]
     return {"Q_f": qf, "Q_c": qc, "Y": qf - qc, "companions": comps}
 

@@ -2,46 +2,51 @@
 complexity theorem's (M1)-(M3)).
 
 * optimal_samples: the rounded-up N meets the variance constraint
-  sum V_l / N_l <= eps^2 / 2 (with equality before rounding), and its cost is
-  within rounding of the least cost found by a general-purpose constrained
-  minimiser (scipy SLSQP) started from a different point.
+  sum V_l / N_l <= eps^2 / 2, and it is the ceiling of the exact minimiser of
+  sum N_l C_l under sum V_l / N_l = eps^2 / 2.  That minimiser is fixed by the
+  first-order (KKT) conditions of the problem, checked without the closed form:
+  stationarity C_l = mu V_l / N_l^2 with one multiplier mu for every level
+  (N_l = sqrt(mu V_l / C_l)), mu found by a scalar root-finder on the
+  constraint; and every feasible move away from it costs more.
 * fit_rate recovers exact power laws and is the slope of the least squares
   line through (log2 h, log2 value).
 * bias_estimate: for differences E[Y_l] = c h_l^alpha the tail beyond L sums
   exactly to the estimate.
 """
 import numpy as np
-from scipy.optimize import minimize
+from scipy.optimize import brentq
 
 from oracle import mlmc
 
 
-def test_optimal_samples_meets_constraint_at_least_cost():
+def test_optimal_samples_is_the_ceiling_of_the_kkt_point():
     rng = np.random.default_rng(5)
-    for _ in range(5):
-        L1 = rng.integers(2, 6)
+    for _ in range(8):
+        L1 = int(rng.integers(2, 7))
         V = np.exp(rng.standard_normal(L1) * 2 - 4)
         C = np.exp(rng.standard_normal(L1) * 2)
-        eps = 0.01
-        N = mlmc.optimal_samples(V, C, eps)
-        assert np.sum(V / N) <= eps ** 2 / 2 * (1 + 1e-12)
-        # continuous minimiser by SLSQP on log N from a far start
+        eps = float(10.0 ** rng.uniform(-3, -1.5))
         target = eps ** 2 / 2
-
-        scale = np.sum(N * C)
-
-        def cost(u):
-            return np.sum(np.exp(u) * C) / scale
-
-        cons = {"type": "eq", "fun": lambda u: (np.sum(V / np.exp(u)) - target) / target}
-        # feasible start: every level takes an equal share of the variance budget
-        u0 = np.log(2.0 * L1 * V / eps ** 2)
-        res = minimize(cost, u0, constraints=[cons], method="SLSQP",
-                       options={"ftol": 1e-14, "maxiter": 500})
-        assert res.success
-        # N costs at most the rounding (one sample per level) above the minimum
-        assert 1.0 <= res.fun * (1 + 1e-6) + np.sum(C) / scale
-        np.testing.assert_allclose(np.exp(res.x), N.astype(float), rtol=5e-3, atol=1.0)
+        N = mlmc.optimal_samples(V, C, eps)
+        assert np.sum(V / N) <= target * (1 + 1e-12)
+        # stationarity of the Lagrangian sum N C + mu (sum V / N - target):
+        # C_l - mu V_l / N_l^2 = 0, i.e. N_l(mu) = sqrt(mu V_l / C_l); the
+        # constraint fixes mu (monotone in mu, so a bracketing root-finder)
+        def excess(log_mu):
+            return np.sum(V / np.sqrt(np.exp(log_mu) * V / C)) / target - 1.0
+        log_mu = brentq(excess, -200.0, 200.0, xtol=1e-14, rtol=1e-15)
+        Nstar = np.sqrt(np.exp(log_mu) * V / C)
+        assert np.all(N >= Nstar * (1 - 1e-9))
+        assert np.all(N < Nstar + 1.0 + 1e-9 * Nstar)
+        # every feasible direction away from N* raises the cost: move along
+        # random directions u, then rescale all levels back onto the constraint
+        base = np.sum(Nstar * C)
+        for _ in range(20):
+            u = rng.standard_normal(L1) * 0.05
+            Nm = Nstar * np.exp(u)
+            Nm *= np.sum(V / Nm) / target          # back onto sum V / N = target
+            assert abs(np.sum(V / Nm) / target - 1.0) < 1e-12
+            assert np.sum(Nm * C) >= base * (1 - 1e-12)
 
 
 def test_fit_rate_recovers_power_laws():

@@ -70,6 +70,30 @@ def test_piecewise_constant_values():
         assert len(np.unique(k)) == len(np.unique(lid))
 
 
+def test_piecewise_constant_law_moments_at_general_variance():
+    """Example 1 with unequal means and variances (sigma^2 = 3 and 0.5): over
+    many samples log k of each layer has mean mu_l and variance sigma_l^2 (the
+    sample mean within 5 standard errors, the sample variance within 5 of its
+    standard errors sigma^2 sqrt(2 / (N - 1))), and the two layers are
+    uncorrelated.  A law written with sigma^2 z instead of sigma z, or with the
+    layers' parameters swapped, fails."""
+    model = W.PC2.with_(mu=(-1.0, 2.0, 0.0, 0.0), sigma2=(3.0, 0.5, 1.0, 1.0), seed=11)
+    n = 6000
+    z = np.array([field.layer_constants(model, 0, s) for s in range(n)])
+    for l in range(2):
+        mu, s2 = model.mu[l], model.sigma2[l]
+        assert abs(z[:, l].mean() - mu) <= 5.0 * np.sqrt(s2 / n), (l, z[:, l].mean())
+        v = z[:, l].var(ddof=1)
+        assert abs(v - s2) <= 5.0 * s2 * np.sqrt(2.0 / (n - 1)), (l, v)
+    corr = np.corrcoef(z[:, 0], z[:, 1])[0, 1]
+    assert abs(corr) <= 5.0 / np.sqrt(n)
+    # the composite field takes exactly these values on its layers
+    for s in range(3):
+        k = field.sample_k(model, 0, s, 16)
+        lid = geometry.layer_ids(model, 0, s, 16)
+        assert np.allclose(np.log(k), z[s][lid], rtol=0, atol=1e-14)
+
+
 def _ce_linear_map(n_ce, m, sigma2, lam, r, dim=2):
     lam_eig = field.ce_eigenvalues(n_ce, m, sigma2, lam, r, dim)
     npts = n_ce ** dim
