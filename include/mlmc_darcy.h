@@ -151,7 +151,9 @@ typedef struct mlmc_solver_opts {
   int32_t variant;      /* 0: fused LDS-tiled cycle kernels, and for 64 x 64 FP64
                            the whole solve of a sample in one workgroup (needs
                            nu1 = nu2 = 1, else falls back to 1); 1: one launch
-                           per sweep / step; 2: the tiled kernels on every grid */
+                           per sweep / step (3-D: also on the small levels the
+                           in-LDS cycle takes otherwise); 2: the tiled kernels on
+                           every grid */
   int32_t precision;    /* MLMC_PREC_*; reduced precision needs variant 0, nu = 1;
                            64 x 64 solves (variant 0) run on chip in FP64 at
                            every setting                                      */

@@ -631,21 +631,19 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   tbl[0] = tb;
   zl[0] = z;
   rl[0] = r;
+  std::vector<double*> Tw(L + 1, nullptr), tbw(L + 1, nullptr);
   for (int l = 1; l <= L; ++l) {
     const long long nl = (long long)ms[l] * ms[l] * ms[l];
-    double *Tc, *tbc;
-    TRY(ws(ctx, lv("s3_T", l), batch * 3 * nl, &Tc));
-    TRY(ws(ctx, lv("s3_tb", l), (size_t)batch * 3 * ms[l] * ms[l], &tbc));
+    TRY(ws(ctx, lv("s3_T", l), batch * 3 * nl, &Tw[l]));
+    TRY(ws(ctx, lv("s3_tb", l), (size_t)batch * 3 * ms[l] * ms[l], &tbw[l]));
     TRY(ws(ctx, lv("s3_zl", l), batch * nl, &zl[l]));
     TRY(ws(ctx, lv("s3_rl", l), batch * nl, &rl[l]));
-    launch_coarsen3(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tc, tbc);
-    Tl[l] = Tc;
-    tbl[l] = tbc;
+    Tl[l] = Tw[l];
+    tbl[l] = tbw[l];
   }
   const int nc = ms[L] * ms[L] * ms[L];
   double* Ainv = nullptr;
   TRY(ws(ctx, "s3_ainv", (size_t)batch * nc * nc, &Ainv));
-  launch_dense_factor3(st, ms[L], batch, Tl[L], tbl[L], Ainv);
   // the operators and vectors the cycle works on, in the hierarchy's type
   std::vector<const void*> Th(L + 1), tbh(L + 1);
   std::vector<void*> zh(L + 1), rh(L + 1);
@@ -662,8 +660,6 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     void *Tf, *tbf;
     TRY(ws_get(ctx, lv("s3_Tf", l), (size_t)batch * 3 * nl * sizeof(float) + 256, &Tf));
     TRY(ws_get(ctx, lv("s3_tbf", l), (size_t)batch * 3 * fl * sizeof(float) + 256, &tbf));
-    launch_convert(st, MLMC_PREC_FP32, batch * 3 * nl, Tl[l], Tf);
-    launch_convert(st, MLMC_PREC_FP32, batch * 3 * fl, tbl[l], tbf);
     Th[l] = Tf;
     tbh[l] = tbf;
     if (l == 0) {
@@ -683,6 +679,19 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   TRY(ws(ctx, "s3_beta", batch, &S.beta));
   TRY(ws(ctx, "s3_active", batch, &S.active));
   TRY(ws(ctx, "s3_count", 1, &S.count));
+  int32_t* carried = nullptr;  // iterations of a W pass whose sample restarts with V
+  if (opts->gamma == 2) TRY(ws(ctx, "s3_carried", batch, &carried));
+  // every workspace is in hand: the hierarchy's set-up launches
+  for (int l = 1; l <= L; ++l)
+    launch_coarsen3(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tw[l], tbw[l]);
+  launch_dense_factor3(st, ms[L], batch, Tl[L], tbl[L], Ainv);
+  if (f32)
+    for (int l = 0; l <= L; ++l) {
+      const long long nl = (long long)ms[l] * ms[l] * ms[l];
+      const long long fl = (long long)ms[l] * ms[l];
+      launch_convert(st, MLMC_PREC_FP32, batch * 3 * nl, Tl[l], const_cast<void*>(Th[l]));
+      launch_convert(st, MLMC_PREC_FP32, batch * 3 * fl, tbl[l], const_cast<void*>(tbh[l]));
+    }
   CHECK_LAUNCH();
   const int nu = opts->nu1;
   const double omega = opts->omega;
@@ -691,10 +700,10 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     return (opts->gamma_levels == 0 || l < opts->gamma_levels) ? cur_gamma : 1;
   };
   // levels from the first one of side <= 8 (FP64) or 16 (FP32) down run in one
-  // in-LDS kernel (nu = 1)
+  // in-LDS kernel (nu = 1; variant 1 keeps the per-sweep launches on every level)
   int l0 = -1;
   CoarseDesc cdesc{};
-  if (nu == 1)
+  if (nu == 1 && opts->variant != 1)
     for (int l = 0; l < L; ++l)
       if (ms[l] <= coarse3_max_side(f32)) {
         l0 = l;
@@ -780,8 +789,6 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   };
   TRY(pcg_pass(false));
   if (cur_gamma == 2) {  // V-cycle restart where the W preconditioner broke down
-    int32_t* carried;
-    TRY(ws(ctx, "s3_carried", batch, &carried));
     launch_sc_restart(st, batch, S, status, iters, carried);
     HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -833,18 +840,21 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     OcHierarchy h{};
     h.T[0] = T;
     h.tb[0] = tb;
+    double* Tw[5] = {};
+    double* tbw[5] = {};
     for (int l = 1; l <= L; ++l) {
       const long long nl = (long long)ms[l] * ms[l];
-      double *Tc, *tbc;
-      TRY(ws(ctx, lv("s_T", l), batch * 2 * nl, &Tc));
-      TRY(ws(ctx, lv("s_tb", l), (size_t)batch * 2 * ms[l], &tbc));
-      launch_coarsen(st, ms[l - 1], batch, h.T[l - 1], h.tb[l - 1], Tc, tbc);
-      h.T[l] = Tc;
-      h.tb[l] = tbc;
+      TRY(ws(ctx, lv("s_T", l), batch * 2 * nl, &Tw[l]));
+      TRY(ws(ctx, lv("s_tb", l), (size_t)batch * 2 * ms[l], &tbw[l]));
+      h.T[l] = Tw[l];
+      h.tb[l] = tbw[l];
     }
     double *work = nullptr, *Ainv = nullptr;
     TRY(ws(ctx, "s_chol", (size_t)batch * 256, &work));
     TRY(ws(ctx, "s_ainv", (size_t)batch * 256, &Ainv));
+    // every workspace is in hand before the first launch
+    for (int l = 1; l <= L; ++l)
+      launch_coarsen(st, ms[l - 1], batch, h.T[l - 1], h.tb[l - 1], Tw[l], tbw[l]);
     launch_dense_factor(st, 4, batch, h.T[L], h.tb[L], work, Ainv);
     // compulsory bytes per sample: T and tb of every level, b, x, the inverse
     const double bytes = (double)batch * (8.0 * (2.0 * 5456 + 2.0 * 124) + 16.0 * n + 8.0 * 256);
@@ -873,24 +883,22 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   if (flexible) TRY(ws(ctx, "s_partial2", (size_t)batch * bps, &partial2));
   zl[0] = z;
   rl[0] = r;
+  std::vector<double*> Tw(L + 1, nullptr), tbw(L + 1, nullptr);
   for (int l = 1; l <= L; ++l) {
     const long long nl = (long long)ms[l] * ms[l];
-    double *Tc, *tbc;
-    TRY(ws(ctx, lv("s_T", l), batch * 2 * nl, &Tc));
-    TRY(ws(ctx, lv("s_tb", l), (size_t)batch * 2 * ms[l], &tbc));
+    TRY(ws(ctx, lv("s_T", l), batch * 2 * nl, &Tw[l]));
+    TRY(ws(ctx, lv("s_tb", l), (size_t)batch * 2 * ms[l], &tbw[l]));
     if (!fused || prec == MLMC_PREC_FP64) {
       TRY(ws(ctx, lv("s_zl", l), batch * nl, &zl[l]));
       TRY(ws(ctx, lv("s_rl", l), batch * nl, &rl[l]));
     }
-    Tl[l] = Tc;
-    tbl[l] = tbc;
-    launch_coarsen(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tc, tbc);
+    Tl[l] = Tw[l];
+    tbl[l] = tbw[l];
   }
   const long long nc = (long long)ms[L] * ms[L];
   double *work = nullptr, *Ainv = nullptr;
   TRY(ws(ctx, "s_chol", batch * nc * nc, &work));
   TRY(ws(ctx, "s_ainv", batch * nc * nc, &Ainv));
-  launch_dense_factor(st, ms[L], batch, Tl[L], tbl[L], work, Ainv);
 
   // ... and, for reduced precision, its copy in the storage type.  Vectors of
   // the fused cycle below the finest level (z_l, r_l, z_pre) use that type.
@@ -907,8 +915,6 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       void *Tc, *tbc;
       TRY(ws_get(ctx, lv("s_Tlo", l), batch * 2 * nl * eb + 256, &Tc));
       TRY(ws_get(ctx, lv("s_tblo", l), (size_t)batch * 2 * ms[l] * eb + 256, &tbc));
-      launch_convert(st, prec, batch * 2 * nl, Tl[l], Tc);
-      launch_convert(st, prec, (long long)batch * 2 * ms[l], tbl[l], tbc);
       Ts[l] = Tc;
       tbs[l] = tbc;
     }
@@ -930,7 +936,8 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   TRY(ws(ctx, "s_beta", batch, &S.beta));
   TRY(ws(ctx, "s_active", batch, &S.active));
   TRY(ws(ctx, "s_count", 1, &S.count));
-  CHECK_LAUNCH();
+  int32_t* carried = nullptr;  // iterations of a W pass whose sample restarts with V
+  if (opts->gamma == 2) TRY(ws(ctx, "s_carried", batch, &carried));
 
   const int nu = opts->nu1;
   const double omega = opts->omega;
@@ -955,6 +962,26 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       if (visits(l) == 2)
         TRY(ws_get(ctx, lv("s_zmid", l), batch * (size_t)ms[l] * ms[l] * eb + 256, &zmid[l]));
     }
+  }
+  // CG direction: fused p-update + operator (ping-pong p buffers) when the
+  // finest grid takes fixed tiles, else separate p-update and operator kernels
+  const bool dir_fused = fused && cg_direction_fused(m);
+  double* pbuf[2] = {pv, nullptr};
+  if (dir_fused) TRY(ws(ctx, "s_p2", batch * n, &pbuf[1]));
+  const int dir_parts = dir_fused ? mg_tiles_per_sample(m) : bps;
+
+  // every workspace is in hand: the hierarchy's set-up launches
+  for (int l = 1; l <= L; ++l)
+    launch_coarsen(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tw[l], tbw[l]);
+  launch_dense_factor(st, ms[L], batch, Tl[L], tbl[L], work, Ainv);
+  if (prec != MLMC_PREC_FP64)
+    for (int l = 0; l <= L; ++l) {
+      const long long nl = (long long)ms[l] * ms[l];
+      launch_convert(st, prec, batch * 2 * nl, Tl[l], const_cast<void*>(Ts[l]));
+      launch_convert(st, prec, (long long)batch * 2 * ms[l], tbl[l], const_cast<void*>(tbs[l]));
+    }
+  CHECK_LAUNCH();
+  if (fused) {
     for (int q2 = 0; q2 + l0 <= L; ++q2) {
       cdesc.m[q2] = ms[l0 + q2];
       cdesc.T[q2] = Ts[l0 + q2];
@@ -1086,13 +1113,6 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     }
     fcycle(0);
   };
-
-  // CG direction: fused p-update + operator (ping-pong p buffers) when the
-  // finest grid takes fixed tiles, else separate p-update and operator kernels
-  const bool dir_fused = fused && cg_direction_fused(m);
-  double* pbuf[2] = {pv, nullptr};
-  if (dir_fused) TRY(ws(ctx, "s_p2", batch * n, &pbuf[1]));
-  const int dir_parts = dir_fused ? mg_tiles_per_sample(m) : bps;
 
   int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
   const int check = opts->check_every > 0 ? opts->check_every : 1;
@@ -1249,8 +1269,6 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   // x0 = 0 with the V-cycle, positive definite for any omega > 0.  Its
   // iteration count includes both passes.
   if (cur_gamma == 2) {
-    int32_t* carried;
-    TRY(ws(ctx, "s_carried", batch, &carried));
     launch_sc_restart(st, batch, S, status, iters, carried);
     HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -4,6 +4,9 @@ C ABI.  Tolerances as in the 2-D parity tests: exact layer decisions, 1e-14
 relative for k of piecewise constant layers and for assembly, 1e-11 absolute
 in log k for embedded fields, 1e-10 relative for every QoI.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -62,10 +65,11 @@ def solve3(lib, ctx, kh, opts=None):
 
 
 # ------------------------------------------------------------------ fields
-@pytest.mark.parametrize("m,level", [(8, 0), (16, 1)])
-def test_field_3d_circulant_embedding(lib, ctx, m, level):
+@pytest.mark.parametrize("m,level,batch", [(8, 0, 3), (16, 1, 3), (32, 0, 2), (64, 1, 2),
+                                           (128, 2, 1)])
+def test_field_3d_circulant_embedding(lib, ctx, m, level, batch):
+    """The served grids' fields too (32^3..128^3, embeddings of 64^3..256^3)."""
     print("3-D field m=%d level=%d" % (m, level), flush=True)
-    batch = 3
     k, kc = f64(batch, m, m, m), f64(batch, m // 2, m // 2, m // 2)
     lib.mlmc_sample_field(ctx, MODEL, m, level, 5, batch, k, kc)
     torch.cuda.synchronize()
@@ -252,21 +256,82 @@ def test_level_run_3d_matches_oracle(lib, ctx, cgv):
         assert abs(qc[s] - ref["Q_c"]) <= QTOL * ref["Q_c"], (s, qc[s], ref["Q_c"])
 
 
-def test_level_run_3d_served_sizes(lib, ctx):
-    """The served 3-D grids (32^3, 64^3, 128^3): every solve converges, inflow
-    equals outflow (flux conservation of the discrete solution) and the 32^3
-    sample matches the oracle."""
+GOLDEN3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "tilted3_64_128_plain.json")
+
+
+def _served_opts(lib, prec):
+    return lib.mlmc_solver_opts_default(
+        precision=lib.MLMC_PREC_FP32 if prec == "f32" else lib.MLMC_PREC_FP64)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_level_run_3d_served_sizes(lib, ctx, prec):
+    """The served 3-D level runs (32^3/64, 64^3/16, 128^3/4 samples) with the
+    FP64 hierarchy and with the FP32 hierarchy the served mix uses: every solve
+    converges; the 32^3 sample matches the oracle's direct solve; samples 0 and
+    1 of the 64^3 and 128^3 levels match the oracle's conjugate gradient solve
+    to 1e-14 (stored by tests/golden/make_golden.py), fine and coarse QoI."""
+    with open(GOLDEN3) as f:
+        gold = {lv["level"]: lv for lv in json.load(f)["levels"]}
     for level, (m, n) in enumerate(zip(W.SERVED_3D.m_levels, W.SERVED_3D.n_samples)):
-        print("3-D served level %d m=%d n=%d" % (level, m, n), flush=True)
+        print("3-D served level %d m=%d n=%d %s" % (level, m, n, prec), flush=True)
         qf, qc = f64(n), f64(n)
-        sums = lib.mlmc_level_run(ctx, MODEL, level, m, 0, n, False,
-                                  lib.mlmc_solver_opts_default(), q_f=qf, q_c=qc)
+        sums = lib.mlmc_level_run(ctx, MODEL, level, m, 0, n, False, _served_opts(lib, prec),
+                                  q_f=qf, q_c=qc)
         torch.cuda.synchronize()
         assert sums.n_failed == 0
         assert sums.iters_fine / n <= 30, sums.iters_fine / n
+        qf, qc = qf.cpu().numpy(), qc.cpu().numpy()
         if m == 32:
             ref = omlmc.level_sample(MODEL, level, 0, m)
-            assert abs(qf[0].item() - ref["Q_f"]) <= QTOL * ref["Q_f"]
+            assert abs(qf[0] - ref["Q_f"]) <= QTOL * ref["Q_f"]
+            assert abs(qc[0] - ref["Q_c"]) <= QTOL * ref["Q_c"]
+        else:
+            lv = gold[level]
+            assert lv["m"] == m
+            for row in lv["samples"]:
+                s = row["sample"]
+                assert abs(qf[s] - row["Q_f"]) <= QTOL * row["Q_f"], (m, s, qf[s], row["Q_f"])
+                assert abs(qc[s] - row["Q_c"]) <= QTOL * row["Q_c"], (m, s, qc[s], row["Q_c"])
+
+
+def test_level_run_3d_served_sizes_fp32_equals_fp64(lib, ctx):
+    """Per sample, the FP32-hierarchy served level runs give the FP64
+    hierarchy's QoIs to 1e-10 on every sample of 64^3 and 128^3."""
+    for level, (m, n) in enumerate(zip(W.SERVED_3D.m_levels, W.SERVED_3D.n_samples)):
+        if m < 64:
+            continue
+        print("3-D served FP32 vs FP64 m=%d" % m, flush=True)
+        out = {}
+        for prec in ("f64", "f32"):
+            qf, qc = f64(n), f64(n)
+            sums = lib.mlmc_level_run(ctx, MODEL, level, m, 100, n, False,
+                                      _served_opts(lib, prec), q_f=qf, q_c=qc)
+            torch.cuda.synchronize()
+            assert sums.n_failed == 0
+            out[prec] = (qf.cpu().numpy(), qc.cpu().numpy())
+        np.testing.assert_allclose(out["f32"][0], out["f64"][0], rtol=QTOL, atol=0)
+        np.testing.assert_allclose(out["f32"][1], out["f64"][1], rtol=QTOL, atol=0)
+
+
+@pytest.mark.parametrize("m", [8, 16, 32])
+@pytest.mark.parametrize("gamma,gamma_levels", [(1, 2), (2, 2), (2, 0)])
+def test_in_lds_cycle_equals_per_sweep_cycle(lib, ctx, m, gamma, gamma_levels):
+    """The in-LDS coarse cycle takes the per-sweep cycle's steps in its order:
+    with the FP64 hierarchy both give the same per-sample iteration counts (a
+    wrongly ordered visit or restriction would change them) and the same QoIs
+    to rounding; variant 1 forces the per-sweep cycle on every level."""
+    print("3-D in-LDS vs per-sweep m=%d gamma=%d/%d" % (m, gamma, gamma_levels), flush=True)
+    rng = np.random.default_rng(1200 + m)
+    kh = np.exp(1.5 * rng.standard_normal((4, m, m, m)))
+    lds = solve3(lib, ctx, kh, lib.mlmc_solver_opts_default(gamma=gamma,
+                                                            gamma_levels=gamma_levels))
+    per = solve3(lib, ctx, kh, lib.mlmc_solver_opts_default(gamma=gamma, gamma_levels=gamma_levels,
+                                                            variant=1))
+    assert np.all(lds["status"] == 0) and np.all(per["status"] == 0)
+    np.testing.assert_array_equal(lds["iters"], per["iters"])
+    np.testing.assert_allclose(lds["q_out"], per["q_out"], rtol=1e-12, atol=0)
 
 
 def test_serve_3d(lib, ctx):
