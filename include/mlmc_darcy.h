@@ -295,6 +295,31 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
                        const mlmc_solver_opts* opts, int32_t* status, int32_t* iters,
                        double* relres);
 
+/* mlmc_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, layouts, results and errors as mlmc_solve (the same kernels run),
+ * but every workspace -- residual, search and correction vectors, the
+ * multigrid hierarchy, per-sample scalars and partial sums -- is carved from
+ * one static 64 MiB device array in the library instead of the context's
+ * allocated workspaces.  No hipMalloc, hipFree or allocating library call is
+ * made.  Limits and behaviour:
+ *   - the solve's workspaces must fit in the 64 MiB array (about 2500 samples
+ *     of 64 x 64, 57 of 128 x 128, 14 of 256 x 256 with the FP64 defaults;
+ *     3-D: 52 of 32^3); a larger batch is refused with MLMC_EINVAL and a
+ *     message naming the workspace that did not fit, before any work is
+ *     enqueued;
+ *   - opts->graph must be 0 (MLMC_EINVAL otherwise); kernel timing
+ *     (mlmc_profile_enable) does not record this call;
+ *   - each device holds one copy of the array for the life of the process and
+ *     every call on that device uses it: calls that overlap on one device (two
+ *     contexts or streams, or threads) race and corrupt each other's results.
+ *     Calls on one stream are ordered and safe.  The array keeps the previous
+ *     call's contents; nothing in the solve reads a workspace before writing it. */
+mlmc_status mlmc_solve_noalloc(mlmc_ctx* ctx, int dim, int m, int batch, const double* T,
+                               const double* tb, const double* b, double* p,
+                               const mlmc_solver_opts* opts, int32_t* status, int32_t* iters,
+                               double* relres);
+
 /* Outflow M^(2) through x1 = 1 (Section 3.4) of the discrete solution:
  * q_out[s] = sum over the cells with i = m-1 of 2 k h^(d-2) p; q_in[s]
  * (optional, may be NULL) = sum over the cells with i = 0 of 2 k h^(d-2)

@@ -36,7 +36,7 @@ EXPORTED = ["mlmc_ctx_create", "mlmc_ctx_destroy", "mlmc_ctx_set_stream", "mlmc_
             "mlmc_serve_start", "mlmc_serve_submit", "mlmc_serve_poll", "mlmc_serve_now",
             "mlmc_serve_stats", "mlmc_serve_stop", "mlmc_run_levels", "mlmc_serve_start_models",
             "mlmc_assemble_problem", "mlmc_qoi_box_mean", "mlmc_optimal_samples", "mlmc_rates",
-            "mlmc_adaptive_opts_default", "mlmc_adaptive"]
+            "mlmc_adaptive_opts_default", "mlmc_adaptive", "mlmc_solve_noalloc"]
 MLMC_MAX_LEVELS = 16
 
 
@@ -138,6 +138,8 @@ _SIGS = {
     "mlmc_assemble": (_S, [_P, _I, _I, _I, _P, _P, _P, _P]),
     "mlmc_solve": (_S, [_P, _I, _I, _I, _P, _P, _P, _P, ctypes.POINTER(mlmc_solver_opts),
                         _P, _P, _P]),
+    "mlmc_solve_noalloc": (_S, [_P, _I, _I, _I, _P, _P, _P, _P,
+                                ctypes.POINTER(mlmc_solver_opts), _P, _P, _P]),
     "mlmc_qoi_outflow": (_S, [_P, _I, _I, _I, _P, _P, _P, _P]),
     "mlmc_level_run": (_S, [_P, ctypes.POINTER(mlmc_model), _I, _I, _U64, _I, _I,
                             ctypes.POINTER(mlmc_solver_opts), ctypes.POINTER(mlmc_level_sums),
@@ -338,6 +340,18 @@ def mlmc_solve(ctx, dim, m, batch, T, tb, b, p, opts, status, iters, relres):
                                 _f64(p, n, "p"), ctypes.byref(opts),
                                 _i32(status, batch, "status"), _i32(iters, batch, "iters"),
                                 _f64(relres, batch, "relres")))
+
+
+def mlmc_solve_noalloc(ctx, dim, m, batch, T, tb, b, p, opts, status, iters, relres):
+    """mlmc_solve with every workspace in the library's static scratch array."""
+    d = int(dim)
+    n = batch * m ** d
+    _check(ctx, _lib.mlmc_solve_noalloc(ctx, d, int(m), int(batch), _f64(T, d * n, "T"),
+                                        _f64(tb, d * batch * m ** (d - 1), "tb"),
+                                        _f64(b, n, "b"), _f64(p, n, "p"), ctypes.byref(opts),
+                                        _i32(status, batch, "status"),
+                                        _i32(iters, batch, "iters"),
+                                        _f64(relres, batch, "relres")))
 
 
 def mlmc_qoi_outflow(ctx, dim, m, batch, k, p, q_out, q_in=None):

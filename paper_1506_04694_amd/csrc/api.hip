@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -69,6 +70,12 @@ struct mlmc_ctx {
   uint64_t ws_gen = 0;             // bumped whenever a workspace is (re)allocated
   hipStream_t capture_stream = nullptr;  // private stream graphs are captured on
   std::vector<GraphEntry> graphs;  // PCG iteration graphs, oldest first
+  // mlmc_solve_noalloc: while `arena` is set, workspaces are carved from the
+  // device's static scratch array (one region per name, 256-byte aligned)
+  // instead of being allocated
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  std::map<std::string, std::pair<size_t, size_t>> arena_names;  // name -> (offset, bytes)
 };
 
 namespace {
@@ -100,6 +107,27 @@ mlmc_status fail(mlmc_ctx* ctx, mlmc_status code, const std::string& msg) {
 
 // Grow-only named device workspace.
 mlmc_status ws_get(mlmc_ctx* ctx, const std::string& name, size_t bytes, void** out) {
+  if (ctx->arena) {
+    auto it = ctx->arena_names.find(name);
+    if (it != ctx->arena_names.end()) {
+      if (it->second.second < bytes)
+        return fail(ctx, MLMC_EINVAL, "workspace '" + name + "' requested twice with a larger size");
+      *out = ctx->arena + it->second.first;
+      return MLMC_OK;
+    }
+    const size_t off = (ctx->arena_used + 255) & ~(size_t)255;
+    if (off > ctx->arena_bytes || bytes > ctx->arena_bytes - off)
+      return fail(ctx, MLMC_EINVAL,
+                  "mlmc_solve_noalloc: the solve needs more than the " +
+                      std::to_string(ctx->arena_bytes >> 20) +
+                      " MiB scratch array (workspace '" + name + "' of " + std::to_string(bytes) +
+                      " bytes at offset " + std::to_string(off) +
+                      "); use a smaller batch or mlmc_solve");
+    ctx->arena_names[name] = {off, bytes};
+    ctx->arena_used = off + bytes;
+    *out = ctx->arena + off;
+    return MLMC_OK;
+  }
   Buffer& b = ctx->ws[name];
   if (b.bytes < bytes) {
     if (b.ptr) {
@@ -317,6 +345,34 @@ constexpr double kBytesProlong = 18.0;    // z read + write 16 + zc 2
 
 }  // namespace
 
+// ======================================================= scratch of mlmc_solve_noalloc
+// The device memory of the allocation-free solve: a file-scope array in the
+// code object, one copy per device, held until the process ends.  Host code
+// never passes `scratch` itself (its host-side name is not a device address):
+// mlmc_ctx_create looks up the array's address on its device once with
+// hipGetSymbolAddress and every later use goes through that pointer.
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxScratchDevices = 64;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+// Address of this device's scratch array (the device is current); looked up once.
+hipError_t scratch_setup(int device) {
+  if (device >= kMaxScratchDevices) return hipSuccess;  // noalloc unavailable there
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+  return e;
+}
+}  // namespace
+
 // =================================================================== public ABI
 namespace mlmc {
 // Error message for the host-side drivers of other source files.
@@ -334,6 +390,10 @@ mlmc_status mlmc_ctx_create(int device, void* hip_stream, mlmc_ctx** out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MLMC_EDEVICE;
   if (hipSetDevice(device) != hipSuccess) return MLMC_EDEVICE;
+  if (scratch_setup(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return MLMC_EDEVICE;
+  }
   ctx = new mlmc_ctx();
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
@@ -1285,6 +1345,30 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   launch_sc_final(st, batch, partial, bps, S, relres);
   CHECK_LAUNCH();
   return MLMC_OK;
+}
+
+mlmc_status mlmc_solve_noalloc(mlmc_ctx* ctx, int dim, int m, int batch, const double* T,
+                               const double* tb, const double* b, double* p,
+                               const mlmc_solver_opts* opts, int32_t* status, int32_t* iters,
+                               double* relres) {
+  if (!ctx) return MLMC_EINVAL;
+  if (opts && opts->graph)
+    return fail(ctx, MLMC_EINVAL, "mlmc_solve_noalloc: opts->graph = 1 needs a capture stream "
+                                  "and graph objects; use graph = 0");
+  void* base = ctx->device < kMaxScratchDevices ? g_scratch_ptr[ctx->device] : nullptr;
+  if (!base) return fail(ctx, MLMC_EDEVICE, "mlmc_solve_noalloc: no scratch array on this device");
+  ctx->arena = static_cast<char*>(base);
+  ctx->arena_bytes = kScratchBytes;
+  ctx->arena_used = 0;
+  ctx->arena_names.clear();
+  std::string prof;
+  prof.swap(ctx->prof_name);  // kernel timing would create events: off for this call
+  const mlmc_status rc = mlmc_solve(ctx, dim, m, batch, T, tb, b, p, opts, status, iters, relres);
+  prof.swap(ctx->prof_name);
+  ctx->arena = nullptr;
+  ctx->arena_bytes = ctx->arena_used = 0;
+  ctx->arena_names.clear();
+  return rc;
 }
 
 static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
