@@ -31,10 +31,10 @@ import workloads as W  # noqa: E402
 METRIC = "MLMC samples solved/s per level at 1e-10 QoI rel-err; HBM GB/s; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 # The dominant kernel of the step: the W second visit on the finest grid of
-# every solve, k_mg_mid_t<64, 32, double, true> (its own instantiation, the
+# every solve, k_mg_mid_p<64, 32, 768, double, true> (its own instantiation, the
 # top line of the rocprofv3 summary).  "@0" selects that level's launches.
 DOMINANT = "k_mg_mid@0"
-DOMINANT_SYMBOL = "mlmc::k_mg_mid_t<64, 32, double, true>"
+DOMINANT_SYMBOL = "mlmc::k_mg_mid_p<64, 32, 768, double, true>"
 
 
 def parse():

@@ -938,7 +938,8 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   TRY(ws(ctx, "s_z", batch * n, &z));
   TRY(ws(ctx, "s_p", batch * n, &pv));
   TRY(ws(ctx, "s_q", batch * n, &q));
-  const int parts_max = std::max(bps, mg_tiles_per_sample(m % 2 == 0 ? m : 2));
+  const int parts_max =
+      std::max({bps, mg_rz_parts(m % 2 == 0 ? m : 2, prec), m % 64 == 0 ? cg_dir_parts(m) : 1});
   TRY(ws(ctx, "s_partial", (size_t)batch * parts_max, &partial));
   if (flexible) TRY(ws(ctx, "s_partial2", (size_t)batch * bps, &partial2));
   zl[0] = z;
@@ -1028,7 +1029,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   const bool dir_fused = fused && cg_direction_fused(m);
   double* pbuf[2] = {pv, nullptr};
   if (dir_fused) TRY(ws(ctx, "s_p2", batch * n, &pbuf[1]));
-  const int dir_parts = dir_fused ? mg_tiles_per_sample(m) : bps;
+  const int dir_parts = dir_fused ? cg_dir_parts(m) : bps;
 
   // every workspace is in hand: the hierarchy's set-up launches
   for (int l = 1; l <= L; ++l)
@@ -1101,7 +1102,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   };
   // z = M r, and the partials of r^T z: rz_parts per sample in `partial`
   int rz_parts = bps;
-  if (fused) rz_parts = l0 == 0 ? 1 : mg_tiles_per_sample(ms[0]);
+  if (fused) rz_parts = l0 == 0 ? 1 : mg_rz_parts(ms[0], prec);
   // Fused gamma-cycle: on a tiled level l, the down kernel pre-smooths and
   // restricts; after the first coarse visit the mid kernel adds the correction,
   // post- and pre-smooths and restricts again; the up kernel adds the last

@@ -97,8 +97,8 @@ struct CoarseDesc {
 // prec: MLMC_PREC_* storage of the hierarchy (T, tb, z_pre, z and r below the
 // finest level).  top: the level is the finest one, whose r and z are FP64.
 // With rz_partial != NULL (top only) the up kernel writes r^T z per tile:
-// rz_partial[s * mg_tiles_per_sample(m) + tile]; the coarse cycle per sample.
-int mg_tiles_per_sample(int m);
+// rz_partial[s * mg_rz_parts(m, prec) + tile]; the coarse cycle per sample.
+int mg_rz_parts(int m, int prec);
 size_t prec_bytes(int prec);
 void launch_mg_down(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
                     const void* tb, const void* r, void* z, void* rc, const int32_t* active);
@@ -118,7 +118,8 @@ void launch_mg_coarse_cycle(hipStream_t st, int prec, bool top, int batch, int n
                             double* rz_partial);
 void launch_convert(hipStream_t st, int prec, long long count, const double* x, void* y);
 // p_new = z + beta p_old (z when first), q = A p_new, partial[s * tiles + tile] = p_new . q;
-// available when cg_direction_fused(m) (fixed tiles; mg_tiles_per_sample(m) partials)
+// available when cg_direction_fused(m) (fixed tiles; cg_dir_parts(m) partials)
+int cg_dir_parts(int m);
 bool cg_direction_fused(int m);
 void launch_cg_direction(hipStream_t st, int m, int batch, const double* T, const double* tb,
                          const double* z, const double* pold, double* pnew, double* q,

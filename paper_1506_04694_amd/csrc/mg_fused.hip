@@ -84,28 +84,14 @@ __device__ __forceinline__ typename Prec<V>::C ldo(const V* p, unsigned i) {
   return Prec<V>::ld(q, 0);
 }
 
-// ------------------------------------------------------------------ fixed-tile kernels
-// Tiles of compile-time size TX x TY (used when TX and TY divide m).  Each of
-// the 512 threads owns the frame cells f = tid + 512 k in every phase and
-// keeps their four faces, reciprocal diagonal, right-hand side and z in
-// registers; LDS holds z, which is what neighbours read, and the residuals the
-// restriction sums.  All loads use clamped, always-valid addresses and are
+// ------------------------------------------------------------------ fixed-tile helpers
+// Tiles of compile-time size TX x TY (used when TX and TY divide m).  Each
+// thread owns fixed frame cells in every phase and keeps their faces,
+// reciprocal diagonal and right-hand side in registers; LDS holds z, which is
+// what neighbours read.  All loads use clamped, always-valid addresses and are
 // resolved by selects, so a thread's loads are issued back to back.  Tiles of
-// one sample run on one XCD, so the halo re-reads hit that XCD's L2.  The
-// down/up frame reaches two cells around the tile ((TX + 4) x (TY + 4)), the
-// mid frame four.
+// one sample run on one XCD, so the halo re-reads hit that XCD's L2.
 constexpr int kMgThreads = 512;
-// The mid kernel's frame reaches four cells around the tile: a taller tile
-// (64 x 32, 1.41x halo overhead instead of 1.69x) on 1024 threads, measured
-// 6% (FP64) and 15% (FP32) faster than 64 x 16 on 512 threads.
-constexpr int kMidThreads = 1024;
-constexpr int kMidTileY = 32;
-
-template <int TX, int TY, int HALO>
-struct Tile {
-  static constexpr int W = TX + 2 * HALO, H = TY + 2 * HALO, F = W * H;
-  static constexpr int K = (F + kMgThreads - 1) / kMgThreads;
-};
 
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   const int x = bid & 7, q = bid >> 3;
@@ -169,17 +155,213 @@ __device__ __forceinline__ C nsum_lds(const CellFaces<C>& f, const C* sz, int fr
   return f.te * sz[fr + 1] + f.tw * sz[fr - 1] + f.tn * sz[fr + W] + f.ts * sz[fr - W];
 }
 
-// down: pre-smoothing from z = 0 (red, then black) and the restricted residual.
-template <int TX, int TY, class S, bool TOP>
-__global__ void __launch_bounds__(kMgThreads, 8)
-k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
+// ------------------------------------------------------------------ colour-split tile kernels
+// The down / mid / up steps of the fixed-tile kernels above, with the frame
+// split by colour: a thread owns "pairs" of horizontally adjacent frame cells
+// (columns 2q and 2q + 1 of a row; one red, one black), keeps both cells'
+// faces, reciprocal diagonals and right-hand sides in registers, and z lives
+// in two zero-padded LDS planes, one per colour, indexed by (row, q).  In a
+// half-sweep every lane then updates a cell of the swept colour (instead of
+// half the lanes idling), and its four neighbours -- all of the other colour
+// -- sit at contiguous plane addresses across the lanes:
+//   red cell of pair (fj, q):   west/east other-plane q - 1 + (fj & 1), q + (fj & 1),
+//                               north/south q in rows fj +- 1;
+//   black cell of pair (fj, q): west/east q - (fj & 1), q + 1 - (fj & 1), north/south q.
+// A pair's loads are 2-element vector loads (16 B in FP64); its west face is
+// the east face of the cell to its left (one scalar load), its south faces the
+// north faces of the row below.  The arithmetic and its order are those of the
+// kernels above, so the results are the same bit for bit (the r^T z partial of
+// up sums the cells in another order).
+template <class V>
+struct PairLd;
+template <>
+struct PairLd<double> {
+  __device__ static __forceinline__ void ld(const double* p, unsigned i, double& a, double& b) {
+    const double2 v = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(p) +
+                                                        (size_t)(i * 8u));
+    a = v.x;
+    b = v.y;
+  }
+  __device__ static __forceinline__ void st(double* p, long long i, double a, double b) {
+    *reinterpret_cast<double2*>(p + i) = make_double2(a, b);
+  }
+};
+template <>
+struct PairLd<float> {
+  __device__ static __forceinline__ void ld(const float* p, unsigned i, float& a, float& b) {
+    const float2 v = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(p) +
+                                                      (size_t)(i * 4u));
+    a = v.x;
+    b = v.y;
+  }
+  __device__ static __forceinline__ void st(float* p, long long i, float a, float b) {
+    *reinterpret_cast<float2*>(p + i) = make_float2(a, b);
+  }
+};
+template <>
+struct PairLd<bf16_t> {
+  __device__ static __forceinline__ void ld(const bf16_t* p, unsigned i, float& a, float& b) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p) +
+                                                          (size_t)(i * 2u));
+    a = __uint_as_float(w << 16);
+    b = __uint_as_float(w & 0xFFFF0000u);
+  }
+  __device__ static __forceinline__ void st(bf16_t* p, long long i, float a, float b) {
+    uint32_t ua = __float_as_uint(a), ub = __float_as_uint(b);
+    ua += 0x7FFFu + ((ua >> 16) & 1u);
+    ub += 0x7FFFu + ((ub >> 16) & 1u);
+    *reinterpret_cast<uint32_t*>(p + i) = (ua >> 16) | (ub & 0xFFFF0000u);
+  }
+};
+
+template <class C>
+struct PCell {
+  C te, tw, tn, ts, di, rv;
+};
+
+// Geometry of a colour-split frame: tile TX x TY, HALO cells around it.
+template <int TX, int TY, int HALO, int NT>
+struct PGeom {
+  static constexpr int W = TX + 2 * HALO, H = TY + 2 * HALO;
+  static constexpr int P = W / 2, NP = P * H;          // pairs per row, pairs
+  static constexpr int PP = P + 2, PL = PP * (H + 2);  // padded plane pitch, plane size
+  static constexpr int K = (NP + NT - 1) / NT;         // pair slots per thread
+  static_assert(K <= 4, "one flag byte per slot");
+  static_assert(HALO % 2 == 0 && TX % 2 == 0, "pairs start on even columns");
+  // plane index of pair (fj, q)
+  __device__ static __forceinline__ int at(int fj, int q) { return (fj + 1) * PP + q + 1; }
+};
+
+// Zero the padding ring of both planes (interior cells are written by their owners).
+template <class G, class C>
+__device__ __forceinline__ void zero_padding(C* zR, C* zB, int nt) {
+  for (int e = threadIdx.x; e < 2 * G::PP + 2 * G::H; e += nt) {
+    const int o = e < G::PP       ? e
+                  : e < 2 * G::PP ? (G::H + 1) * G::PP + e - G::PP
+                                  : (1 + (e - 2 * G::PP) / 2) * G::PP + ((e & 1) ? G::PP - 1 : 0);
+    zR[o] = C(0);
+    zB[o] = C(0);
+  }
+}
+
+// Operator rows and right-hand sides of the two cells of pair (fj, q) of the
+// frame whose cell (0, 0) is the global cell (X0 - HALO, Y0 - HALO): red and
+// black cell in that order, zero outside the domain (in = false).  Also the
+// clamped linear index c of the pair's first cell, for further pair loads.
+template <class S, class R, int HALO>
+__device__ __forceinline__ void pair_rows(const S* __restrict__ Ts, const S* __restrict__ tbs,
+                                          const R* __restrict__ rs, int m, int X0, int Y0, int fj,
+                                          int q, bool valid,
+                                          PCell<typename Prec<S>::C>& red,
+                                          PCell<typename Prec<S>::C>& black, bool& in,
+                                          unsigned& c, int& ic, int& jc, double (&rd)[2]) {
+  using C = typename Prec<S>::C;
+  const int i0 = X0 - HALO + 2 * q, j = Y0 - HALO + fj;
+  in = valid && i0 >= 0 && i0 < m && j >= 0 && j < m;  // m even: both cells or neither
+  ic = min(max(i0, 0), m - 2);
+  jc = min(max(j, 0), m - 1);
+  c = (unsigned)(jc * m + ic);
+  const unsigned mm = (unsigned)(m * m);
+  C te0, te1, tn0, tn1, tst0, tst1, tsb0, tsb1;
+  PairLd<S>::ld(Ts, c, te0, te1);
+  PairLd<S>::ld(Ts, mm + c, tn0, tn1);
+  PairLd<S>::ld(Ts, mm + (c >= (unsigned)m ? c - (unsigned)m : 0u), tst0, tst1);
+  PairLd<S>::ld(tbs, (unsigned)(m + ic), tsb0, tsb1);
+  const C twt = ldo(Ts, c > 0u ? c - 1u : 0u), twb = ldo(tbs, (unsigned)jc);
+  double r0, r1;
+  {
+    typename Prec<R>::C a, b;
+    PairLd<R>::ld(rs, c, a, b);
+    r0 = (double)a;
+    r1 = (double)b;
+  }
+  PCell<C> c0{te0, i0 == 0 ? twb : twt, tn0, j == 0 ? tsb0 : tst0, C(0), (C)r0};
+  PCell<C> c1{te1, te0, tn1, j == 0 ? tsb1 : tst1, C(0), (C)r1};
+  if (in) {
+    c0.di = C(1) / (c0.te + c0.tw + c0.tn + c0.ts);
+    c1.di = C(1) / (c1.te + c1.tw + c1.tn + c1.ts);
+  } else {
+    c0 = PCell<C>{C(0), C(0), C(0), C(0), C(0), C(0)};
+    c1 = c0;
+    r0 = r1 = 0.0;
+  }
+  const bool odd = fj & 1;  // red is the cell with even global i + j
+  red = odd ? c1 : c0;
+  black = odd ? c0 : c1;
+  rd[0] = odd ? r1 : r0;  // FP64 right-hand side, red then black
+  rd[1] = odd ? r0 : r1;
+}
+
+// Flag byte of a pair: bit 0 in the domain, bit e (e = 1..3) red cell at least
+// e cells inside the frame edge, bit 3 + e the same for the black cell, bit 7
+// pair on the tile.
+template <class G, int HALO>
+__device__ __forceinline__ unsigned pair_flags(int fj, int q, bool in) {
+  unsigned b = in ? 1u : 0u;
+  const int cR = 2 * q + (fj & 1), cB = 2 * q + 1 - (fj & 1);
+#pragma unroll
+  for (int e = 1; e < HALO; ++e) {
+    const bool row = fj >= e && fj < G::H - e;
+    if (row && cR >= e && cR < G::W - e) b |= 1u << e;
+    if (row && cB >= e && cB < G::W - e) b |= 1u << (3 + e);
+  }
+  if (fj >= HALO && fj < G::H - HALO && q >= HALO / 2 && q < G::P - HALO / 2) b |= 128u;
+  return b;
+}
+
+// N(z) of the red / black cell of pair (fj, q) from the other colour's plane.
+template <class G, class C>
+__device__ __forceinline__ C nsum_red(const PCell<C>& c, const C* zB, int o, int par) {
+  const int w = o - 1 + par;
+  return c.te * zB[w + 1] + c.tw * zB[w] + c.tn * zB[o + G::PP] + c.ts * zB[o - G::PP];
+}
+template <class G, class C>
+__device__ __forceinline__ C nsum_black(const PCell<C>& c, const C* zR, int o, int par) {
+  const int w = o - par;
+  return c.te * zR[w + 1] + c.tw * zR[w] + c.tn * zR[o + G::PP] + c.ts * zR[o - G::PP];
+}
+
+// One half-sweep over the pairs whose flags contain `want` (red or black cells).
+template <class G, int NT, bool RED, class C>
+__device__ __forceinline__ void pair_sweep(const PCell<C> (&cr)[G::K], const PCell<C> (&cb)[G::K],
+                                           unsigned fl, unsigned want, C* zR, C* zB) {
+#pragma unroll
+  for (int k = 0; k < G::K; ++k) {
+    if (((fl >> (8 * k)) & want) == want) {
+      int g = threadIdx.x + k * NT;
+      asm volatile("" : "+v"(g));  // keep the index math local to the sweep
+      const int fj = g / G::P, q = g - fj * G::P;
+      const int o = G::at(fj, q), par = fj & 1;
+      if (RED) zR[o] = (cr[k].rv + nsum_red<G>(cr[k], zB, o, par)) * cr[k].di;
+      else zB[o] = (cb[k].rv + nsum_black<G>(cb[k], zR, o, par)) * cb[k].di;
+    }
+  }
+}
+
+// Restriction: the coarse residual of each 2 x 2 block of the tile is the sum
+// of the residuals of its two red cells, stored in place of their red z.
+template <class G, int NT, int HALO, class S, class C>
+__device__ __forceinline__ void pair_restrict(const C* zR, S* __restrict__ rcs, int mc, int X0,
+                                              int Y0) {
+  constexpr int HX = (G::W - 2 * HALO) / 2, HY = (G::H - 2 * HALO) / 2;
+  for (int c = threadIdx.x; c < HX * HY; c += NT) {
+    const int cj = c / HX, ci = c - cj * HX;
+    // rows HALO + 2cj (red at column 2q) and HALO + 2cj + 1 (red at 2q + 1), q = HALO/2 + ci
+    const int o = G::at(HALO + 2 * cj, HALO / 2 + ci);
+    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, zR[o] + zR[o + G::PP]);
+  }
+}
+
+// down: red sweep from z = 0 (z_red = r / D), black sweep, store, restricted residual.
+template <int TX, int TY, int NT, class S, bool TOP>
+__global__ void __launch_bounds__(NT)
+k_mg_down_p(int m, const S* __restrict__ T, const S* __restrict__ tb,
             const VecT<S, TOP>* __restrict__ r, S* __restrict__ z, S* __restrict__ rc,
             const int32_t* __restrict__ active) {
   using C = typename Prec<S>::C;
-  using G = Tile<TX, TY, 2>;
-  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
-  __shared__ C sz[F];
-  __shared__ C sres[F];
+  using G = PGeom<TX, TY, 2, NT>;
+  __shared__ C zR[G::PL];
+  __shared__ C zB[G::PL];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -189,95 +371,59 @@ k_mg_down_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const long long n = (long long)m * m;
   const S* Ts = T + s * 2 * n;
   const S* tbs = tb + s * 2 * m;
-  const VecT<S, TOP>* rs = r + s * n;
-  // z lives in LDS only; flags per slot: bit 0 a frame cell inside the domain,
-  // bit 1 inside the ring of the black sweep, bit 4 black, bit 5 on the tile.
-  CellFaces<C> cf[K];
-  C rv[K], di[K];
-  unsigned fl[K];
+  zero_padding<G>(zR, zB, NT);
+  PCell<C> cr[G::K], cb[G::K];
+  unsigned fl = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    cf[k] = own_faces(Ts, m, X0 - 2 + fi, Y0 - 2 + fj);
-    const C rr = (C)ldv(rs, cf[k].c);
-    rv[k] = cf[k].in ? rr : C(0);
-    if (f < F) {
-      sz[f] = cf[k].te;
-      sres[f] = cf[k].tn;
+  for (int k = 0; k < G::K; ++k) {
+    const int g = threadIdx.x + k * NT;
+    const int fj = g / G::P, q = g - fj * G::P;
+    bool in;
+    unsigned c;
+    int ic, jc;
+    double rd[2];
+    pair_rows<S, VecT<S, TOP>, 2>(Ts, tbs, r + s * n, m, X0, Y0, fj, q, g < G::NP, cr[k], cb[k],
+                                  in, c, ic, jc, rd);
+    if (g < G::NP) {
+      const int o = G::at(fj, q);
+      zR[o] = in ? cr[k].rv * cr[k].di : C(0);
+      zB[o] = C(0);
     }
+    fl |= pair_flags<G, 2>(fj, q, in) << (8 * k);
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    adjacent_faces(cf[k], sz, sres, Ts, tbs, m, X0 - 2 + fi, Y0 - 2 + fj, f, fi, fj, W, f < F);
-    di[k] = inv_diag(cf[k]);
-    unsigned b = (f < F && cf[k].in) ? 1u : 0u;
-    if (fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1) b |= 2u;
-    if ((fi + fj) & 1) b |= 16u;
-    if (fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) b |= 32u;
-    fl[k] = b;
-  }
+  pair_sweep<G, NT, false>(cr, cb, fl, 1u | 16u, zR, zB);  // black on the frame less one ring
   __syncthreads();
-  // red cells of the frame: z = r / D; black cells start at 0
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if (f < F) sz[f] = (fl[k] & 16u) ? C(0) : rv[k] * di[k];
-  }
-  __syncthreads();
-  // black cells of R1
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if ((fl[k] & 19u) == 19u) sz[f] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-  }
-  __syncthreads();
-  // store the tile; residual of its red cells (black residuals vanish)
   S* zs = z + s * n;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if (fl[k] & 32u) {
-      const int fj = f / W, fi = f - fj * W;
-      Prec<S>::st(zs, (long long)(Y0 - 2 + fj) * m + (X0 - 2 + fi), sz[f]);
-      if (!(fl[k] & 16u)) sres[f] = nsum_lds(cf[k], sz, f, W);
+  for (int k = 0; k < G::K; ++k) {
+    if ((fl >> (8 * k)) & 128u) {
+      int g = threadIdx.x + k * NT;
+      asm volatile("" : "+v"(g));
+      const int fj = g / G::P, q = g - fj * G::P;
+      const int o = G::at(fj, q), par = fj & 1;
+      const C zr = zR[o], zb = zB[o];
+      PairLd<S>::st(zs, (long long)(Y0 - 2 + fj) * m + (X0 - 2 + 2 * q), par ? zb : zr,
+                    par ? zr : zb);
+      // red residual r - D z_red + N(z) = N(z_black) (z_red = r / D)
+      zR[o] = nsum_red<G>(cr[k], zB, o, par);
     }
   }
   __syncthreads();
-  const int mc = m / 2;
-  S* rcs = rc + s * (long long)mc * mc;
-  constexpr int HX = TX / 2, HY = TY / 2;
-  for (int c = threadIdx.x; c < HX * HY; c += kMgThreads) {
-    const int cj = c / HX, ci = c - cj * HX;
-    // (X0 + 2ci, Y0 + 2cj) has even i + j: the block's red cells are (0,0) and (1,1)
-    const int fa = (2 + 2 * cj) * W + 2 + 2 * ci;
-    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sres[fa] + sres[fa + W + 1]);
-  }
+  pair_restrict<G, NT, 2>(zR, rc + s * (long long)(m / 2) * (m / 2), m / 2, X0, Y0);
 }
 
-// mid: the second coarse correction of a W-cycle level.  From z1 (the down
-// result) and the first correction e1: z = z1 + omega P e1, then black, red
-// and black sweeps (the post-smoothing of the first correction, black then
-// red, followed by the pre-smoothing of the second, red then black, whose red
-// sweep repeats the one just done and is dropped), then the restricted
-// residual as in down.  Halo: the residual on the tile needs the last black
-// sweep one cell out, that sweep the red sweep two cells out, that one the
-// first black sweep three cells out, which needs z four cells out.
-template <int TX, int TY, class S, bool TOP>
-__global__ void __launch_bounds__(kMidThreads, 8)
-k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
+// mid: the second coarse correction of a W-cycle level (see k_mg_mid_t).
+template <int TX, int TY, int NT, class S, bool TOP>
+__global__ void __launch_bounds__(NT)
+k_mg_mid_p(int m, const S* __restrict__ T, const S* __restrict__ tb,
            const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre, S* __restrict__ z,
            const S* __restrict__ zc, double omega, S* __restrict__ rc,
            const int32_t* __restrict__ active) {
   using C = typename Prec<S>::C;
-  using G = Tile<TX, TY, 4>;
-  constexpr int W = G::W, H = G::H, F = G::F, K = (F + kMidThreads - 1) / kMidThreads;
-  __shared__ C sz[F];
-  __shared__ C sres[F];
-  __shared__ C ste[F];
+  using G = PGeom<TX, TY, 4, NT>;
+  __shared__ C zR[G::PL];
+  __shared__ C zB[G::PL];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -291,105 +437,70 @@ k_mg_mid_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const S* zps = zpre + s * n;
   const S* zcs = zc + s * (long long)mc * mc;
   const C om = (C)omega;
-  // z of the frame lives in LDS only (sz, written as soon as it is loaded; the
-  // east / north faces are exchanged through ste / sres); registers hold each
-  // cell's faces, reciprocal diagonal and right-hand side, which keeps the
-  // kernel within 64 VGPRs: two workgroups per CU, so one's loads overlap the
-  // other's sweeps.
-  // Per slot, one byte of flags (byte k of fl for slot k): bit 0 a frame cell
-  // inside the domain, bits 1-3 inside the rings swept by the three passes (R3,
-  // R2, R1), bit 4 black, bit 5 on the tile.
-  CellFaces<C> cf[K];
-  C rv[K], di[K];
-  static_assert(K <= 4, "one flag byte per slot");
+  zero_padding<G>(zR, zB, NT);
+  PCell<C> cr[G::K], cb[G::K];
   unsigned fl = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMidThreads;
-    const int fj = f / W, fi = f - fj * W;
-    const int i = X0 - 4 + fi, j = Y0 - 4 + fj;
-    cf[k] = own_faces(Ts, m, i, j);
-    const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
-    const C rr = (C)ldo(r + s * n, (unsigned)cf[k].c);
-    const C zp = ldo(zps, (unsigned)cf[k].c), zcv = ldo(zcs, (unsigned)((jc >> 1) * mc + (ic >> 1)));
-    rv[k] = cf[k].in ? rr : C(0);
-    if (f < F) {
-      sz[f] = cf[k].in ? zp + om * zcv : C(0);
-      ste[f] = cf[k].te;
-      sres[f] = cf[k].tn;
+  for (int k = 0; k < G::K; ++k) {
+    const int g = threadIdx.x + k * NT;
+    const int fj = g / G::P, q = g - fj * G::P;
+    bool in;
+    unsigned c;
+    int ic, jc;
+    double rd[2];
+    pair_rows<S, VecT<S, TOP>, 4>(Ts, tbs, r + s * n, m, X0, Y0, fj, q, g < G::NP, cr[k], cb[k],
+                                  in, c, ic, jc, rd);
+    C zp0, zp1;
+    PairLd<S>::ld(zps, c, zp0, zp1);
+    const C zcv = ldo(zcs, (unsigned)((jc >> 1) * mc + (ic >> 1)));
+    if (g < G::NP) {
+      const int o = G::at(fj, q);
+      const C z0 = in ? zp0 + om * zcv : C(0), z1 = in ? zp1 + om * zcv : C(0);
+      zR[o] = (fj & 1) ? z1 : z0;
+      zB[o] = (fj & 1) ? z0 : z1;
     }
+    fl |= pair_flags<G, 4>(fj, q, in) << (8 * k);
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMidThreads;
-    const int fj = f / W, fi = f - fj * W;
-    adjacent_faces(cf[k], ste, sres, Ts, tbs, m, X0 - 4 + fi, Y0 - 4 + fj, f, fi, fj, W, f < F);
-    di[k] = inv_diag(cf[k]);
-    unsigned b = (f < F && cf[k].in) ? 1u : 0u;
-#pragma unroll
-    for (int d = 3; d >= 1; --d)
-      if (fi >= 4 - d && fi < W - 4 + d && fj >= 4 - d && fj < H - 4 + d) b |= 2u << (3 - d);
-    if ((fi + fj) & 1) b |= 16u;
-    if (fi >= 4 && fi < 4 + TX && fj >= 4 && fj < 4 + TY) b |= 32u;
-    fl |= b << (8 * k);
-  }
+  pair_sweep<G, NT, false>(cr, cb, fl, 1u | (1u << 4), zR, zB);  // black, 1 cell in
   __syncthreads();
-  // black on R3, red on R2, black on R1
-#pragma unroll
-  for (int pass = 0; pass < 3; ++pass) {
-    const unsigned want = 1u | (2u << pass) | (pass == 1 ? 0u : 16u);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int f = threadIdx.x + k * kMidThreads;
-      if (((fl >> (8 * k)) & (17u | (2u << pass))) == want)
-        sz[f] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-    }
-    __syncthreads();
-  }
-  // store the tile; residual of its red cells (black residuals vanish after the black sweep)
+  pair_sweep<G, NT, true>(cr, cb, fl, 1u | (1u << 2), zR, zB);   // red, 2 cells in
+  __syncthreads();
+  pair_sweep<G, NT, false>(cr, cb, fl, 1u | (1u << 6), zR, zB);  // black, 3 cells in
+  __syncthreads();
   S* zs = z + s * n;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    int f = threadIdx.x + k * kMidThreads;
-    // recomputed here rather than kept from the start (an empty asm makes the
-    // index opaque), which keeps the kernel within 64 VGPRs without a spill
-    asm volatile("" : "+v"(f));
-    if ((fl >> (8 * k)) & 32u) {
-      const int fj = f / W, fi = f - fj * W;
-      const C zf = sz[f];
-      Prec<S>::st(zs, (long long)(Y0 - 4 + fj) * m + (X0 - 4 + fi), zf);
-      if (!((fl >> (8 * k)) & 16u)) {
-        const C dd = cf[k].te + cf[k].tw + cf[k].tn + cf[k].ts;
-        sres[f] = rv[k] - dd * zf + nsum_lds(cf[k], sz, f, W);
-      }
+  for (int k = 0; k < G::K; ++k) {
+    if ((fl >> (8 * k)) & 128u) {
+      int g = threadIdx.x + k * NT;
+      asm volatile("" : "+v"(g));
+      const int fj = g / G::P, q = g - fj * G::P;
+      const int o = G::at(fj, q), par = fj & 1;
+      const C zr = zR[o], zb = zB[o];
+      PairLd<S>::st(zs, (long long)(Y0 - 4 + fj) * m + (X0 - 4 + 2 * q), par ? zb : zr,
+                    par ? zr : zb);
+      const PCell<C>& c = cr[k];
+      const C dd = c.te + c.tw + c.tn + c.ts;
+      zR[o] = c.rv - dd * zr + nsum_red<G>(c, zB, o, par);  // black residuals vanish
     }
   }
   __syncthreads();
-  S* rcs = rc + s * (long long)mc * mc;
-  constexpr int HX = TX / 2, HY = TY / 2;
-  for (int c = threadIdx.x; c < HX * HY; c += kMidThreads) {
-    const int cj = c / HX, ci = c - cj * HX;
-    const int fa = (4 + 2 * cj) * W + 4 + 2 * ci;
-    Prec<S>::st(rcs, (Y0 / 2 + cj) * mc + X0 / 2 + ci, sres[fa] + sres[fa + W + 1]);
-  }
+  pair_restrict<G, NT, 4>(zR, rc + s * (long long)mc * mc, mc, X0, Y0);
 }
 
-// up: z = z_in + omega P e, post-smoothing (black, then red) and, on the finest
-// level, the per-tile partial of r^T z.
-template <int TX, int TY, class S, bool TOP>
-__global__ void __launch_bounds__(kMgThreads, 8)
-k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
+// up: z = z_in + omega P e, black sweep, red sweep on the tile, store and, on
+// the finest level, the per-tile partial of r^T z.
+template <int TX, int TY, int NT, class S, bool TOP>
+__global__ void __launch_bounds__(NT)
+k_mg_up_p(int m, const S* __restrict__ T, const S* __restrict__ tb,
           const VecT<S, TOP>* __restrict__ r, const S* __restrict__ zpre,
           VecT<S, TOP>* __restrict__ z, const S* __restrict__ zc, double omega,
           const int32_t* __restrict__ active, double* __restrict__ rz_partial) {
   using C = typename Prec<S>::C;
-  using G = Tile<TX, TY, 2>;
-  constexpr int W = G::W, H = G::H, F = G::F, K = G::K;
-  __shared__ C sz[F];
-  __shared__ C sn[F];
-  __shared__ C se[F];
-  __shared__ double red[kMgThreads / kWave];
+  using G = PGeom<TX, TY, 2, NT>;
+  __shared__ C zR[G::PL];
+  __shared__ C zB[G::PL];
+  __shared__ double red[(NT + kWave - 1) / kWave];
   const int ntx = m / TX, tps = ntx * (m / TY);
   const int bid = xcd_tile(blockIdx.x, gridDim.x);
   const long long s = bid / tps;
@@ -400,67 +511,54 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
   const int mc = m / 2;
   const S* Ts = T + s * 2 * n;
   const S* tbs = tb + s * 2 * m;
-  const VecT<S, TOP>* rs = r + s * n;
   const S* zps = zpre + s * n;
   const S* zcs = zc + s * (long long)mc * mc;
   const C om = (C)omega;
-  // z lives in LDS only (written as soon as it is loaded; east / north faces
-  // are exchanged through se / sn); flags per slot: bit 0 a frame cell inside
-  // the domain, bit 1 inside the ring of the black sweep, bit 4 black, bit 5 on
-  // the tile.
-  CellFaces<C> cf[K];
-  C rv[K], di[K];
-  double rd[K];  // FP64 residual for the r^T z sum (finest level only)
-  unsigned fl[K];
+  zero_padding<G>(zR, zB, NT);
+  PCell<C> cr[G::K], cb[G::K];
+  double rdr[G::K], rdb[G::K];  // FP64 right-hand sides for r^T z (finest level)
+  unsigned fl = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    const int i = X0 - 2 + fi, j = Y0 - 2 + fj;
-    cf[k] = own_faces(Ts, m, i, j);
-    const int ic = min(max(i, 0), m - 1), jc = min(max(j, 0), m - 1);
-    const double rr = (double)ldv(rs, cf[k].c);
-    const C zp = ldv(zps, cf[k].c), zcv = ldv(zcs, (jc >> 1) * mc + (ic >> 1));
-    rd[k] = cf[k].in ? rr : 0.0;
-    rv[k] = (C)rd[k];
-    if (f < F) {
-      sz[f] = cf[k].in ? zp + om * zcv : C(0);
-      se[f] = cf[k].te;
-      sn[f] = cf[k].tn;
+  for (int k = 0; k < G::K; ++k) {
+    const int g = threadIdx.x + k * NT;
+    const int fj = g / G::P, q = g - fj * G::P;
+    bool in;
+    unsigned c;
+    int ic, jc;
+    double rd[2];
+    pair_rows<S, VecT<S, TOP>, 2>(Ts, tbs, r + s * n, m, X0, Y0, fj, q, g < G::NP, cr[k], cb[k],
+                                  in, c, ic, jc, rd);
+    rdr[k] = rd[0];
+    rdb[k] = rd[1];
+    C zp0, zp1;
+    PairLd<S>::ld(zps, c, zp0, zp1);
+    const C zcv = ldo(zcs, (unsigned)((jc >> 1) * mc + (ic >> 1)));
+    if (g < G::NP) {
+      const int o = G::at(fj, q);
+      const C z0 = in ? zp0 + om * zcv : C(0), z1 = in ? zp1 + om * zcv : C(0);
+      zR[o] = (fj & 1) ? z1 : z0;
+      zB[o] = (fj & 1) ? z0 : z1;
     }
+    fl |= pair_flags<G, 2>(fj, q, in) << (8 * k);
   }
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    const int fj = f / W, fi = f - fj * W;
-    adjacent_faces(cf[k], se, sn, Ts, tbs, m, X0 - 2 + fi, Y0 - 2 + fj, f, fi, fj, W, f < F);
-    di[k] = inv_diag(cf[k]);
-    unsigned b = (f < F && cf[k].in) ? 1u : 0u;
-    if (fi >= 1 && fi < W - 1 && fj >= 1 && fj < H - 1) b |= 2u;
-    if ((fi + fj) & 1) b |= 16u;
-    if (fi >= 2 && fi < 2 + TX && fj >= 2 && fj < 2 + TY) b |= 32u;
-    fl[k] = b;
-  }
+  pair_sweep<G, NT, false>(cr, cb, fl, 1u | 16u, zR, zB);  // black on the frame less one ring
   __syncthreads();
-  // black sweep on R1
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if ((fl[k] & 19u) == 19u) sz[f] = (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-  }
-  __syncthreads();
-  // red sweep on the tile, store, r^T z
-  VecT<S, TOP>* zs = z + s * n;
+  using Z = VecT<S, TOP>;
+  Z* zs = z + s * n;
   double acc = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = threadIdx.x + k * kMgThreads;
-    if (fl[k] & 32u) {
-      const int fj = f / W, fi = f - fj * W;
-      const C zf = (fl[k] & 16u) ? sz[f] : (rv[k] + nsum_lds(cf[k], sz, f, W)) * di[k];
-      Prec<VecT<S, TOP>>::st(zs, (long long)(Y0 - 2 + fj) * m + (X0 - 2 + fi), zf);
-      if (TOP) acc += rd[k] * (double)zf;
+  for (int k = 0; k < G::K; ++k) {
+    if ((fl >> (8 * k)) & 128u) {
+      int g = threadIdx.x + k * NT;
+      asm volatile("" : "+v"(g));
+      const int fj = g / G::P, q = g - fj * G::P;
+      const int o = G::at(fj, q), par = fj & 1;
+      const C zb = zB[o];
+      const C zr = (cr[k].rv + nsum_red<G>(cr[k], zB, o, par)) * cr[k].di;  // red sweep
+      PairLd<Z>::st(zs, (long long)(Y0 - 2 + fj) * m + (X0 - 2 + 2 * q), par ? zb : zr,
+                    par ? zr : zb);
+      if (TOP) acc += rdr[k] * (double)zr + rdb[k] * (double)zb;
     }
   }
   if (TOP && rz_partial) {
@@ -470,7 +568,7 @@ k_mg_up_t(int m, const S* __restrict__ T, const S* __restrict__ tb,
     if (threadIdx.x == 0) {
       double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < kMgThreads / kWave; ++w) t += red[w];
+      for (int w = 0; w < (NT + kWave - 1) / kWave; ++w) t += red[w];
       rz_partial[s * tps + tile] = t;
     }
   }
@@ -1321,10 +1419,52 @@ static size_t frame_bytes(int tx, int ty) {
 
 static bool fixed_tile(int m) { return m % kTileX == 0 && m % kTileY == 0; }
 
-int mg_tiles_per_sample(int m) {
-  if (fixed_tile(m)) return (m / kTileX) * (m / kTileY);
+// Tile shapes of the colour-split kernels: the fastest of the shapes measured
+// per kernel and hierarchy precision on the 512 x 512 level with 64 samples
+// (FP64: down 64 x 32 on 1024 threads, mid 64 x 32 on 768, up 128 x 16 on 640
+// where 128 divides m, else 64 x 16 on 384; FP32 and bfloat16: down and up
+// 64 x 32 on 640 threads, mid 64 x 64 on 1024).  Every shape divides each m
+// that is a multiple of 64 (fixed_tile), except up's 128 x 16.
+static bool up_wide(int m) { return m % 128 == 0; }
+
+int mg_rz_parts(int m, int prec) {
+  if (fixed_tile(m)) {
+    if (prec == MLMC_PREC_FP64) return up_wide(m) ? (m / 128) * (m / 16) : (m / 64) * (m / 16);
+    return (m / 64) * (m / 32);
+  }
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
   return (m / tx) * (m / ty);
+}
+
+int cg_dir_parts(int m) { return (m / kTileX) * (m / kTileY); }
+
+template <int TX, int TY, int NT, class S, bool TOP>
+static void down_p(hipStream_t st, int m, int batch, const void* T, const void* tb, const void* r,
+                   void* z, void* rc, const int32_t* active) {
+  using R = VecT<S, TOP>;
+  hipLaunchKernelGGL((k_mg_down_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)),
+                     dim3(NT), 0, st, m, (const S*)T, (const S*)tb, (const R*)r, (S*)z, (S*)rc,
+                     active);
+}
+
+template <int TX, int TY, int NT, class S, bool TOP>
+static void up_p(hipStream_t st, int m, int batch, const void* T, const void* tb, const void* r,
+                 const void* zpre, void* z, const void* zc, double omega, const int32_t* active,
+                 double* rz_partial) {
+  using R = VecT<S, TOP>;
+  hipLaunchKernelGGL((k_mg_up_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)), dim3(NT),
+                     0, st, m, (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (R*)z,
+                     (const S*)zc, omega, active, rz_partial);
+}
+
+template <int TX, int TY, int NT, class S, bool TOP>
+static void mid_p(hipStream_t st, int m, int batch, const void* T, const void* tb, const void* r,
+                  const void* zpre, void* z, const void* zc, double omega, void* rc,
+                  const int32_t* active) {
+  using R = VecT<S, TOP>;
+  hipLaunchKernelGGL((k_mg_mid_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)),
+                     dim3(NT), 0, st, m, (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre,
+                     (S*)z, (const S*)zc, omega, (S*)rc, active);
 }
 
 template <class S, bool TOP>
@@ -1332,9 +1472,9 @@ static void down_impl(hipStream_t st, int m, int batch, const void* T, const voi
                       const void* r, void* z, void* rc, const int32_t* active) {
   using R = VecT<S, TOP>;
   if (fixed_tile(m)) {
-    const int nb = batch * (m / kTileX) * (m / kTileY);
-    hipLaunchKernelGGL((k_mg_down_t<kTileX, kTileY, S, TOP>), dim3(nb), dim3(kMgThreads), 0, st,
-                       m, (const S*)T, (const S*)tb, (const R*)r, (S*)z, (S*)rc, active);
+    if constexpr (std::is_same<S, double>::value)
+      down_p<64, 32, 1024, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
+    else down_p<64, 32, 640, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
     return;
   }
   using C = typename Prec<S>::C;
@@ -1351,10 +1491,11 @@ static void up_impl(hipStream_t st, int m, int batch, const void* T, const void*
                     const int32_t* active, double* rz_partial) {
   using R = VecT<S, TOP>;
   if (fixed_tile(m)) {
-    const int nb = batch * (m / kTileX) * (m / kTileY);
-    hipLaunchKernelGGL((k_mg_up_t<kTileX, kTileY, S, TOP>), dim3(nb), dim3(kMgThreads), 0, st, m,
-                       (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (R*)z,
-                       (const S*)zc, omega, active, rz_partial);
+    if constexpr (!std::is_same<S, double>::value)
+      up_p<64, 32, 640, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+    else if (up_wide(m))
+      up_p<128, 16, 640, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+    else up_p<64, 16, 384, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
     return;
   }
   using C = typename Prec<S>::C;
@@ -1371,10 +1512,9 @@ static void mid_impl(hipStream_t st, int m, int batch, const void* T, const void
                      const int32_t* active) {
   using R = VecT<S, TOP>;
   if (fixed_tile(m)) {
-    const int nb = batch * (m / kTileX) * (m / kMidTileY);
-    hipLaunchKernelGGL((k_mg_mid_t<kTileX, kMidTileY, S, TOP>), dim3(nb), dim3(kMidThreads), 0, st, m,
-                       (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (S*)z,
-                       (const S*)zc, omega, (S*)rc, active);
+    if constexpr (std::is_same<S, double>::value)
+      mid_p<64, 32, 768, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+    else mid_p<64, 64, 1024, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
     return;
   }
   using C = typename Prec<S>::C;
