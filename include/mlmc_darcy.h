@@ -458,10 +458,15 @@ mlmc_status mlmc_profile_read(mlmc_ctx* ctx, int64_t* launches, double* total_ms
  * Request server with continuous batching (serving form of the estimator).
  * A request is one estimator term (eq. (3.6), or eq. (4.2) with CGV): sample
  * number `sample` of `level` on the m_fine grid.  Worker threads each own a
- * context with its own HIP stream and device-resident workspaces; each takes
- * the oldest waiting request plus later ones for the same (level, m_fine), up
- * to max_batch, while the estimated device memory of the running batches stays
- * within hbm_budget_bytes (a single request runs whenever nothing else does).
+ * context with its own HIP stream and device-resident workspaces; a free
+ * worker takes a batch of one (model, level, m_fine) kind -- that kind's
+ * oldest waiting requests, up to max_batch, while the estimated device memory
+ * of the running batches stays within hbm_budget_bytes (a single request runs
+ * whenever nothing else does).  The kind is the one whose oldest request has
+ * waited longest in units of the kind's expected service time (estimated from
+ * its cells), among the kinds that fit the budget; while short requests wait,
+ * at most n_workers - 1 workers serve long kinds (above about 3 ms), unless a
+ * long request has waited 50 ms.
  * Requests arriving while others run are admitted as workers and memory free
  * up; batches of different workers overlap on the device.  Results are
  * independent of batching.  Times are seconds on the server's clock

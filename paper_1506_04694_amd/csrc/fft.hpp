@@ -78,18 +78,28 @@ __device__ __forceinline__ void dft_small(double* xr, double* xi) {
   }
 }
 
+// q = floor(a / d) for 0 <= a < 2^22, 1 <= d <= 2^13, through one FP32
+// multiply: (a + 1/2) / d stays at least 1/(2d) away from an integer, more than
+// the two roundings (relative 2^-24 each) can move it.
+__device__ __forceinline__ int div_small(int a, float inv_d) {
+  return (int)(((float)a + 0.5f) * inv_d);
+}
+
 template <int R>
 __device__ __forceinline__ void fft_stage_one(double* __restrict__ sre, double* __restrict__ sim,
                                           const double2* __restrict__ tw, int n, int ns) {
   constexpr int kMaxC = (kFftMax / R + kBlock - 1) / kBlock;
   const int nb = n / R;
   const int step = n / (ns * R);
+  // butterfly j splits as j = jq ns + kk (one FP32 multiply instead of an
+  // integer division per butterfly)
+  const float inv_ns = 1.0f / (float)ns;
   double vr[kMaxC][R], vi[kMaxC][R];
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c) {
     const int j = threadIdx.x + c * kBlock;
     if (j < nb) {
-      const int kk = j % ns;
+      const int kk = j - div_small(j, inv_ns) * ns;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         vr[c][r] = sre[j + r * nb];
@@ -109,9 +119,10 @@ __device__ __forceinline__ void fft_stage_one(double* __restrict__ sre, double* 
   for (int c = 0; c < kMaxC; ++c) {
     const int j = threadIdx.x + c * kBlock;
     if (j < nb) {
-      const int kk = j % ns;
+      const int jq = div_small(j, inv_ns);
+      const int kk = j - jq * ns;
       dft_small<R>(vr[c], vi[c]);
-      const int base = (j / ns) * ns * R + kk;
+      const int base = jq * ns * R + kk;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         sre[base + r * ns] = vr[c][r];
@@ -137,13 +148,6 @@ __device__ __forceinline__ void fft_line(double* sre, double* sim, const double2
     else fft_stage_one<5>(sre, sim, tw, pl.n, ns);
     ns *= R;
   }
-}
-
-// q = floor(a / d) for 0 <= a < 2^22, 1 <= d <= 2^13, through one FP32
-// multiply: (a + 1/2) / d stays at least 1/(2d) away from an integer, more than
-// the two roundings (relative 2^-24 each) can move it.
-__device__ __forceinline__ int div_small(int a, float inv_d) {
-  return (int)(((float)a + 0.5f) * inv_d);
 }
 
 // One Stockham stage of radix R over L lines (line q at sre + q n) by a

@@ -11,12 +11,18 @@
 // Requests are queued as they arrive.  Each worker thread owns a context (its
 // own HIP stream at default priority and its own device workspaces, which stay
 // allocated between batches: fields, operators and multigrid hierarchies are
-// device-resident) and repeatedly takes the oldest waiting request together
-// with up to max_batch - 1 later requests for the same (model, level, grid), as long
+// device-resident).  A free worker takes a batch of one (model, level, grid)
+// kind -- the oldest waiting requests of that kind, up to max_batch, as long
 // as the estimated device memory of all running batches stays within the
-// budget; a lone request always runs when nothing else is running.  Batches of
-// different workers run concurrently on the device, so requests that arrive
-// while others are being solved start as soon as a worker and memory are free.
+// budget (a lone request always runs when nothing else is running).  The kind
+// is chosen among those waiting by the age of their oldest request measured in
+// units of the kind's expected service time (so short requests do not queue
+// behind long ones, and a long request's priority grows until it is served),
+// skipping kinds that do not fit the budget; while short requests wait, at
+// most n_workers - 1 workers hold long batches, unless a long request has
+// waited kStarveS.  Batches of different workers run concurrently on the
+// device, so requests that arrive while others are being solved start as soon
+// as a worker and memory are free.
 // A sample's results do not depend on its batch (per-sample random streams and
 // per-sample fixed-order reductions), so a request gives the same numbers
 // alone and in any mix.
@@ -60,6 +66,7 @@ struct Worker {
 
 struct mlmc_server {
   mlmc_serve_opts opts;
+  int running_long = 0;  // batches of long kinds being served
   std::vector<mlmc_model> models;
   std::vector<mlmc_solver_opts> solvers;  // one per model
   std::vector<Worker> workers;
@@ -106,6 +113,73 @@ uint64_t request_bytes(const mlmc_server* s, const mlmc_request& r) {
   return (uint64_t)(cells * per_cell * (1.0 + ncomp / (double)(1 << d)) + ce);
 }
 
+// Expected service time of one request (seconds): a fixed per-batch part and a
+// part proportional to the cells solved (fine grid plus companions).
+double est_seconds(const mlmc_server* s, const mlmc_request& r) {
+  const int d = s->models[r.model].dim;
+  const double m = (double)r.m_fine;
+  const double cells = d == 3 ? m * m * m : m * m;
+  const double ncomp = r.level == 0 ? 0.0 : (s->opts.cgv ? (double)(1 << d) : 1.0);
+  return 1e-3 + cells * (1.0 + ncomp / (double)(1 << d)) * 1e-8;
+}
+constexpr double kLongS = 3e-3;    // kinds above this are "long"
+constexpr double kStarveS = 0.05;  // a long request waiting this long is served regardless
+
+bool same_kind(const mlmc_request& a, const mlmc_request& b) {
+  return a.model == b.model && a.level == b.level && a.m_fine == b.m_fine;
+}
+
+// Under the lock: the batch for a free worker (see the file comment); false
+// when no waiting kind is eligible now.
+bool pick_batch(mlmc_server* s, std::vector<Pending>& batch, uint64_t& bytes, bool& is_long) {
+  if (s->queue.empty()) return false;
+  struct Kind {
+    mlmc_request key;
+    double t_oldest, est;
+    uint64_t one;
+  };
+  std::vector<Kind> kinds;
+  for (const Pending& p : s->queue) {
+    bool seen = false;
+    for (const Kind& k : kinds) seen = seen || same_kind(k.key, p.req);
+    if (!seen) kinds.push_back({p.req, p.t_submit, est_seconds(s, p.req), request_bytes(s, p.req)});
+  }
+  const double now = s->now();
+  bool short_waiting = false;
+  for (const Kind& k : kinds) short_waiting = short_waiting || k.est <= kLongS;
+  const uint64_t budget = s->opts.hbm_budget_bytes;
+  int best = -1;
+  double best_prio = -1.0;
+  for (int q = 0; q < (int)kinds.size(); ++q) {
+    const Kind& k = kinds[q];
+    if (s->in_flight_bytes + k.one > budget && s->running > 0) continue;
+    const double age = now - k.t_oldest;
+    if (k.est > kLongS && short_waiting && s->running_long >= s->opts.n_workers - 1 &&
+        age < kStarveS)
+      continue;
+    const double prio = age / k.est;
+    if (prio > best_prio) {
+      best_prio = prio;
+      best = q;
+    }
+  }
+  if (best < 0) return false;
+  const Kind& k = kinds[best];
+  batch.clear();
+  bytes = 0;
+  for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < s->opts.max_batch;) {
+    if (same_kind(it->req, k.key) && (batch.empty() || s->in_flight_bytes + bytes + k.one <= budget)) {
+      batch.push_back(*it);
+      bytes += k.one;
+      it = s->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  is_long = k.est > kLongS;
+  return true;
+}
+
 void worker_loop(mlmc_server* s, int wi) {
   Worker& w = s->workers[wi];
   (void)hipSetDevice(s->opts.device);
@@ -114,35 +188,19 @@ void worker_loop(mlmc_server* s, int wi) {
   batch.reserve(maxb);
   for (;;) {
     uint64_t bytes = 0;
+    bool is_long = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       for (;;) {
         if (s->stop) return;
-        if (!s->queue.empty()) {
-          const mlmc_request key = s->queue.front().req;
-          const uint64_t one = request_bytes(s, key);
-          const uint64_t budget = s->opts.hbm_budget_bytes;
-          const bool fits_one = s->in_flight_bytes + one <= budget || s->running == 0;
-          if (fits_one) {
-            batch.clear();
-            bytes = 0;
-            for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < maxb;) {
-              if (it->req.model == key.model && it->req.level == key.level &&
-                  it->req.m_fine == key.m_fine &&
-                  (batch.empty() || s->in_flight_bytes + bytes + one <= budget)) {
-                batch.push_back(*it);
-                bytes += one;
-                it = s->queue.erase(it);
-              } else {
-                ++it;
-              }
-            }
-            s->in_flight_bytes += bytes;
-            ++s->running;
-            break;
-          }
+        if (pick_batch(s, batch, bytes, is_long)) {
+          s->in_flight_bytes += bytes;
+          ++s->running;
+          if (is_long) ++s->running_long;
+          break;
         }
-        s->cv.wait(lk);
+        // a kind held back only by the long-batch limit becomes eligible by age
+        s->cv.wait_for(lk, std::chrono::milliseconds(5));
       }
     }
     const double t_start = s->now();
@@ -199,6 +257,7 @@ void worker_loop(mlmc_server* s, int wi) {
       if (st != MLMC_OK && st != MLMC_ENOCONV) s->err = mlmc_last_error(w.ctx);
       s->in_flight_bytes -= bytes;
       --s->running;
+      if (is_long) --s->running_long;
       s->batches++;
     }
     s->cv.notify_all();

@@ -42,6 +42,9 @@ FILES = {
     # the served 3-D model on its two largest grids: samples 0 and 1 of level 1
     # (64^3, companions 32^3) and level 2 (128^3, companions 64^3)
     "tilted3_64_128_plain.json": (W.TILTED3, [32, 64, 128], 2, False, (1, 2)),
+    # the high-contrast field on 1024^2 (sigma^2 = 3, lambda = 0.1): samples 0-15,
+    # the subset the reduced-precision multigrid errors are stated on
+    "ce_hc_1024_fine.json": (W.CE_HC, [1024], 16, False, None),
 }
 
 

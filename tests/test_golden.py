@@ -8,12 +8,12 @@ import workloads as W
 from oracle import mlmc
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-MODELS = {"pc2": W.PC2, "ce2": W.CE2, "til": W.TILTED3}
+MODELS = {"pc2": W.PC2, "ce2": W.CE2, "til": W.TILTED3, "ce_": W.CE_HC}
 
 
 @pytest.mark.parametrize("name", ["pc2_16_32_plain.json", "pc2_16_32_cgv.json",
                                   "ce2_16_32_plain.json", "ce2_16_32_cgv.json",
-                                  "tilted3_64_128_plain.json"])
+                                  "tilted3_64_128_plain.json", "ce_hc_1024_fine.json"])
 def test_golden_reproduced_by_oracle(name):
     with open(os.path.join(GOLDEN, name)) as f:
         rec = json.load(f)
