@@ -149,13 +149,18 @@ def cpu_baseline(wl, budget_s):
             "aggregate": agg}
 
 
+SERVE_WORKERS = 4
+SERVE_MAX_BATCH = 64
+
+
 def serve_setup(lib, kinds, models, solvers):
     """Server options for request kinds [(model index, level, m, count)]."""
     grids = [[] for _ in models]
     for mi, _, m, _ in kinds:
         if m not in grids[mi]:
             grids[mi].append(m)
-    return lib.serve_opts_for_models(list(zip(models, grids)), n_workers=3, max_batch=512)
+    return lib.serve_opts_for_models(list(zip(models, grids)), n_workers=SERVE_WORKERS,
+                                     max_batch=SERVE_MAX_BATCH)
 
 
 def pass_rate(lib, torch, kinds, models, solvers, reps=2):
@@ -223,10 +228,18 @@ def serving_latency(lib, kinds, models, solvers, rate, seconds, seed=1):
         ll = np.array([r["t_done"] - r["t_submit"] for r in rs
                        if r["model"] == mi and r["level"] == level and r["m_fine"] == m])
         if ll.size:
+            sel = [r for r in rs if r["model"] == mi and r["level"] == level and r["m_fine"] == m]
+            wait = np.array([r["t_start"] - r["t_submit"] for r in sel])
+            serv = np.array([r["t_done"] - r["t_start"] for r in sel])
             per_kind.append({"model": mi, "dim": int(models[mi].dim), "level": level, "m": m,
                              "requests": int(ll.size),
                              "p50_ms": 1e3 * float(np.percentile(ll, 50)),
-                             "p99_ms": 1e3 * float(np.percentile(ll, 99))})
+                             "p99_ms": 1e3 * float(np.percentile(ll, 99)),
+                             "wait_p50_ms": 1e3 * float(np.percentile(wait, 50)),
+                             "wait_p99_ms": 1e3 * float(np.percentile(wait, 99)),
+                             "service_p50_ms": 1e3 * float(np.percentile(serv, 50)),
+                             "service_p99_ms": 1e3 * float(np.percentile(serv, 99)),
+                             "mean_batch": float(np.mean([r["batch_size"] for r in sel]))})
     return {"offered_per_s": rate, "completed": len(rs), "submitted": n_req,
             "achieved_per_s": len(rs) / span, "failed": int(sum(r["failed"] for r in rs)),
             "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
@@ -653,7 +666,8 @@ def main():
         # the bench workload's levels, FP64, one model
         kinds = [(0, level, m, n) for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples))]
         sat = total / (elapsed / args.steps)
-        serving = {"workload": wl.name, "saturation_estimate_per_s": sat, "workers": 3,
+        serving = {"workload": wl.name, "saturation_estimate_per_s": sat,
+                   "workers": SERVE_WORKERS, "max_batch": SERVE_MAX_BATCH,
                    "precision": "f64",
                    "runs": [serving_latency(lib, kinds, [wl.model], [opts], f * sat,
                                             args.serve_seconds) for f in rates]}

@@ -511,7 +511,11 @@ typedef struct mlmc_result {
 /* Defaults: device 0, 3 workers, batches up to 256, plain MLMC, 64 GiB budget,
  * mlmc_solver_opts_default. */
 mlmc_status mlmc_serve_opts_default(mlmc_serve_opts* opts);
-/* Starts the workers for one model (host; copied); opts->solver for every batch. */
+/* Starts the workers for one model (host; copied); opts->solver for every batch.
+ * Returns once every worker has warmed up: one level run of up to 16 samples
+ * (sample numbers 0xFFFFF000 and up) per served grid, so that each grid's
+ * embedding eigenvalues and the worker's workspaces exist before requests
+ * arrive.  Workspaces then grow geometrically with the batches served. */
 mlmc_status mlmc_serve_start(const mlmc_model* model, const mlmc_serve_opts* opts,
                              mlmc_server** out);
 /* Starts the workers for n_models (1..8) models at once, e.g. 2-D and 3-D fields

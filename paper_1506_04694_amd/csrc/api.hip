@@ -130,6 +130,11 @@ mlmc_status ws_get(mlmc_ctx* ctx, const std::string& name, size_t bytes, void** 
   }
   Buffer& b = ctx->ws[name];
   if (b.bytes < bytes) {
+    // grow by at least half the current size (rounded to 64 KiB / 1 MiB), so
+    // batches of slowly rising size reallocate rarely: a free waits for the device
+    if (b.bytes > 0) bytes = std::max(bytes, b.bytes + b.bytes / 2);
+    const size_t gran = bytes < ((size_t)16 << 20) ? ((size_t)64 << 10) : ((size_t)1 << 20);
+    bytes = (bytes + gran - 1) & ~(gran - 1);
     if (b.ptr) {
       HIP_TRY(hipStreamSynchronize(ctx->stream));  // earlier launches may still use it
       HIP_TRY(hipFree(b.ptr));

@@ -67,6 +67,7 @@ struct Worker {
 struct mlmc_server {
   mlmc_serve_opts opts;
   int running_long = 0;  // batches of long kinds being served
+  int warming = 0;       // workers still running their warm-up
   std::vector<mlmc_model> models;
   std::vector<mlmc_solver_opts> solvers;  // one per model
   std::vector<Worker> workers;
@@ -180,12 +181,47 @@ bool pick_batch(mlmc_server* s, std::vector<Pending>& batch, uint64_t& bytes, bo
   return true;
 }
 
+// Warm-up of one worker before it takes requests: for each served grid, one
+// level run of a few samples (numbers above any request's), so that the grid's
+// embedding eigenvalues and the worker's workspaces exist before the first
+// request of that kind arrives (computing them in the serving loop would stall
+// every batch on the device: freeing device memory waits for the device).
+void warm_up(mlmc_server* s, Worker& w) {
+  for (int q = 0; q < s->opts.n_grids; ++q) {
+    const int mi = s->opts.grid_model[q], m = s->opts.grid_m[q];
+    mlmc_request rq{m % 2 == 0 ? 1 : 0, m, 0u, mi};
+    const uint64_t one = request_bytes(s, rq);
+    const uint64_t share = s->opts.hbm_budget_bytes / (4ull * (uint64_t)s->opts.n_workers);
+    int wb = (int)std::max<uint64_t>(1, std::min<uint64_t>(share / std::max<uint64_t>(one, 1), 16));
+    wb = std::min(wb, s->opts.max_batch);
+    for (int t = 0; t < wb; ++t) w.h_ids[t] = 0xFFFFF000u + (uint32_t)t;
+    mlmc_model mdl = s->models[mi];
+    mdl.n_ce = n_ce_for(s, mi, m);
+    mlmc_level_sums sums;
+    std::memset(&sums, 0, sizeof sums);
+    const int maxb = s->opts.max_batch;
+    if (hipMemcpyAsync(w.d_ids, w.h_ids, sizeof(uint32_t) * wb, hipMemcpyHostToDevice,
+                       w.stream) != hipSuccess)
+      return;
+    (void)mlmc_level_run_ids(w.ctx, &mdl, rq.level, m, w.d_ids, wb, s->opts.cgv, &s->solvers[mi],
+                             &sums, w.d_out, w.d_out + maxb, w.d_out + 2 * maxb, w.d_flags,
+                             w.d_flags + maxb);
+  }
+  (void)hipStreamSynchronize(w.stream);
+}
+
 void worker_loop(mlmc_server* s, int wi) {
   Worker& w = s->workers[wi];
   (void)hipSetDevice(s->opts.device);
   const int maxb = s->opts.max_batch;
   std::vector<Pending> batch;
   batch.reserve(maxb);
+  warm_up(s, w);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    --s->warming;
+  }
+  s->cv.notify_all();
   for (;;) {
     uint64_t bytes = 0;
     bool is_long = false;
@@ -330,8 +366,13 @@ mlmc_status mlmc_serve_start_models(const mlmc_model* models, const mlmc_solver_
       return MLMC_ENOMEM;
     }
   }
+  s->warming = opts->n_workers;
   for (int wi = 0; wi < opts->n_workers; ++wi)
     s->workers[wi].thread = std::thread(worker_loop, s, wi);
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv.wait(lk, [s] { return s->warming == 0; });
+  }
   *out = s;
   return MLMC_OK;
 }
