@@ -290,9 +290,9 @@ def copy_calibration():
 def path_variants(lib, torch, wl, ctx, opts, args):
     """Other forms of the same step, timed over args.steps steps each after the
     main measurement (not part of `value`):
-    * all levels in one call (mlmc_run_levels: one solve per distinct grid, level
-      l's fine samples merged with level l+1's companions), FP64, with eager
-      launches and with the PCG iterations replayed from captured HIP graphs;
+    * all levels in one call (mlmc_run_levels: each level's pipeline on its own
+      stream, concurrently), FP64, with eager launches and with the PCG
+      iterations replayed from captured HIP graphs;
     * the per-level step with graph-replayed iterations;
     * the per-level step with the multigrid hierarchy stored in FP32 inside the FP64
       flexible CG, with the largest relative QoI difference to the FP64 solve of
@@ -386,7 +386,8 @@ def other_configs(lib, torch, steps):
     pass (not part of `value`):
     * Coarse Grid Variates on the piecewise constant model, levels 64^2..512^2
       (4096/1024/256/64 samples, 2^d = 4 sub-lattice companions per fine sample),
-      all levels in one call (mlmc_run_levels) and level by level; FP64;
+      all levels in one call (mlmc_run_levels, levels concurrently) and level by
+      level; FP64;
     * the high-contrast field on 1024^2 (256 samples) with the multigrid in FP64,
       FP32 and bfloat16 inside the FP64 CG, with the largest relative QoI
       difference of each reduced precision to the FP64 solve of the same samples;

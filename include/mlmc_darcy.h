@@ -173,6 +173,11 @@ typedef struct mlmc_solver_opts {
                             on-chip 64 x 64 path and the 3-D solver start from
                             zero).  The stopping rule is ||r||/||b|| < tol either
                             way (||b|| = ||r_0|| for the zero guess); default 0 */
+  int32_t tile_shape;   /* tile kernels of the 2-D multigrid: 0 the default tile
+                           shapes, 1 an alternative set (other tile sizes and
+                           workgroup sizes) for the autotuner to try; the same
+                           arithmetic per cell (the r^T z partial sums add the
+                           tiles in another order); default 0                 */
 } mlmc_solver_opts;
 
 /* Per-level sums of the estimator (host struct; accumulates across calls). */
@@ -361,12 +366,14 @@ mlmc_status mlmc_level_run_ids(mlmc_ctx* ctx, const mlmc_model* model, int level
 /* Every level of the estimator in one call: level l has n[l] samples starting
  * at first_sample[l] on the m_fine[l] grid (embedding size n_ce[l] for
  * correlated fields; n_ce may be NULL for piecewise constant models) and
- * solver options opts[l].  Samples that share a grid -- the fine samples of
- * one level and the coarse companions of the next finer level -- are solved in
- * one batch with the options of the level whose fine grid it is, so the
- * estimator takes one multigrid-PCG solve per distinct grid size.  Results
- * are those of mlmc_level_run for each level (same samples, same numbers).
- * All inputs host; sums[n_levels] (host) accumulate.  Synchronises. */
+ * solver options opts[l].  The levels are independent (eq. (3.6)), so each
+ * level's pipeline -- sampling, coarse companions, fine solve, QoI, sums --
+ * runs concurrently with the others on a stream of its own (the context keeps
+ * one internal context, stream and workspace set per level for later calls),
+ * starting after the work already enqueued on the context's stream.  Results
+ * are those of mlmc_level_run for each level (same samples, bitwise the same
+ * numbers).  All inputs host; sums[n_levels] (host) accumulate.  Synchronises.
+ * Kernel timing (mlmc_profile_enable) does not record these launches. */
 mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels,
                             const int* m_fine, const int* n_ce, const uint64_t* first_sample,
                             const int* n, int cgv, const mlmc_solver_opts* opts,

@@ -57,7 +57,7 @@ class mlmc_solver_opts(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("cycle_max", ctypes.c_int32), ("gamma", ctypes.c_int32),
                 ("gamma_levels", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("initial_guess", ctypes.c_int32)]
+                ("initial_guess", ctypes.c_int32), ("tile_shape", ctypes.c_int32)]
 
 
 class mlmc_level_sums(ctypes.Structure):

@@ -4,7 +4,8 @@ For each fine grid size of a workload it times ``mlmc_level_run`` on a
 calibration batch drawn from the workload itself, for every combination of
 the tunable solver options (multigrid storage precision, coarse-grid
 correction scaling omega, V- or W-cycle and the number of W levels, coarsest
-grid size, host convergence-check interval, on-chip cycle threshold).  A combination is admissible only if every QoI of the calibration
+grid size, host convergence-check interval, on-chip cycle threshold, tile
+shapes of the multigrid kernels).  A combination is admissible only if every QoI of the calibration
 batch stays within ``qoi_rtol`` (default 1e-10) of the FP64 default
 solver's QoI for the same samples; the fastest admissible one is kept.
 
@@ -26,6 +27,7 @@ DEFAULT_SPACE = {
     "coarse_max": [2, 4, 8],
     "check_every": [4, 8],
     "cycle_max": [16, 32],
+    "tile_shape": [0, 1],
 }
 
 

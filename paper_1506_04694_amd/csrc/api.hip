@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -76,6 +77,9 @@ struct mlmc_ctx {
   char* arena = nullptr;
   size_t arena_bytes = 0, arena_used = 0;
   std::map<std::string, std::pair<size_t, size_t>> arena_names;  // name -> (offset, bytes)
+  // mlmc_run_levels: one sub-context per level (own stream, own workspaces)
+  std::vector<mlmc_ctx*> subs;
+  bool owns_stream = false;
 };
 
 namespace {
@@ -334,6 +338,8 @@ mlmc_status check_opts(mlmc_ctx* ctx, const mlmc_solver_opts* o) {
   if (o->graph != 0 && o->graph != 1) return fail(ctx, MLMC_EINVAL, "graph must be 0 or 1");
   if (o->initial_guess != 0 && o->initial_guess != 1)
     return fail(ctx, MLMC_EINVAL, "initial_guess must be 0 or 1");
+  if (o->tile_shape != 0 && o->tile_shape != 1)
+    return fail(ctx, MLMC_EINVAL, "tile_shape must be 0 or 1");
   if (o->variant < 0 || o->variant > 2) return fail(ctx, MLMC_EINVAL, "variant must be 0, 1 or 2");
   return MLMC_OK;
 }
@@ -431,6 +437,8 @@ mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx) {
   }
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  for (mlmc_ctx* sub : ctx->subs) (void)mlmc_ctx_destroy(sub);
+  if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return MLMC_OK;
 }
@@ -457,6 +465,7 @@ mlmc_status mlmc_solver_opts_default(mlmc_solver_opts* o) {
   o->gamma_levels = 2;
   o->graph = 0;
   o->initial_guess = 0;
+  o->tile_shape = 0;
   return MLMC_OK;
 }
 
@@ -944,7 +953,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   TRY(ws(ctx, "s_p", batch * n, &pv));
   TRY(ws(ctx, "s_q", batch * n, &q));
   const int parts_max =
-      std::max({bps, mg_rz_parts(m % 2 == 0 ? m : 2, prec), m % 64 == 0 ? cg_dir_parts(m) : 1});
+      std::max({bps, mg_rz_parts(m % 2 == 0 ? m : 2, prec, opts->tile_shape), m % 64 == 0 ? cg_dir_parts(m) : 1});
   TRY(ws(ctx, "s_partial", (size_t)batch * parts_max, &partial));
   if (flexible) TRY(ws(ctx, "s_partial2", (size_t)batch * bps, &partial2));
   zl[0] = z;
@@ -1107,7 +1116,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   };
   // z = M r, and the partials of r^T z: rz_parts per sample in `partial`
   int rz_parts = bps;
-  if (fused) rz_parts = l0 == 0 ? 1 : mg_rz_parts(ms[0], prec);
+  if (fused) rz_parts = l0 == 0 ? 1 : mg_rz_parts(ms[0], prec, opts->tile_shape);
   // Fused gamma-cycle: on a tiled level l, the down kernel pre-smooths and
   // restricts; after the first coarse visit the mid kernel adds the correction,
   // post- and pre-smooths and restricts again; the up kernel adds the last
@@ -1151,7 +1160,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     const double rb = l == 0 ? 8.0 : ebd;  // r (FP64 on the finest level)
     // T 2 words, r, z_pre write, coarse r write (1/4 word)
     timed(ctx, "k_mg_down", cells * (ebd * 3.25 + rb), [&] {
-      launch_mg_down(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], rs[l + 1],
+      launch_mg_down(st, prec, opts->tile_shape, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], rs[l + 1],
                      S.active);
     }, l);
     fcycle(l + 1);
@@ -1159,7 +1168,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     if (visits(l) == 2) {
       // T 2 words, r, z_pre, coarse z (1/4), z write, coarse r write (1/4)
       timed(ctx, "k_mg_mid", cells * (ebd * 4.5 + rb), [&] {
-        launch_mg_mid(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], zmid[l],
+        launch_mg_mid(st, prec, opts->tile_shape, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], zmid[l],
                       zs[l + 1], omega, rs[l + 1], S.active);
       }, l);
       fcycle(l + 1);
@@ -1167,7 +1176,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     }
     // T 2 words, r and z (FP64 on the finest level), z_in, coarse z (1/4 word)
     timed(ctx, "k_mg_up", cells * (ebd * 3.25 + (l == 0 ? 16.0 : 2.0 * ebd)), [&] {
-      launch_mg_up(st, prec, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zin, zs[l], zs[l + 1],
+      launch_mg_up(st, prec, opts->tile_shape, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zin, zs[l], zs[l + 1],
                    omega, S.active, l == 0 ? partial : nullptr);
     }, l);
   };
@@ -1509,177 +1518,50 @@ mlmc_status mlmc_run_levels(mlmc_ctx* ctx, const mlmc_model* model, int n_levels
       return fail(ctx, MLMC_EINVAL, "bad level size or sample count");
   }
   (void)hipSetDevice(ctx->device);
-  if (model->dim == 3) {  // 3-D: one level run after another
-    for (int l = 0; l < n_levels; ++l) {
+  // One sub-context per level, each with its own stream and workspaces (kept
+  // for later calls), so the levels' pipelines -- sampling, companion solves,
+  // fine solve, QoI, reduction -- run concurrently: one level's latency-bound
+  // coarse-grid and on-chip launches overlap another's bandwidth-bound
+  // fine-grid launches.  Each level runs exactly mlmc_level_run's steps, so its
+  // sums are bitwise those of a level run over the same samples.
+  while ((int)ctx->subs.size() < n_levels) {
+    hipStream_t sst = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking));
+    mlmc_ctx* sub = nullptr;
+    const mlmc_status rc = mlmc_ctx_create(ctx->device, sst, &sub);
+    if (rc != MLMC_OK) {
+      (void)hipStreamDestroy(sst);
+      return fail(ctx, rc, "mlmc_run_levels: could not create a level context");
+    }
+    sub->owns_stream = true;
+    ctx->subs.push_back(sub);
+  }
+  // the levels start after the work already on the caller's stream
+  hipEvent_t start = pool_event(ctx);
+  HIP_TRY(hipEventRecord(start, ctx->stream));
+  for (int l = 0; l < n_levels; ++l) HIP_TRY(hipStreamWaitEvent(ctx->subs[l]->stream, start, 0));
+  std::vector<mlmc_status> rc(n_levels, MLMC_OK);
+  std::vector<std::thread> th;
+  th.reserve(n_levels);
+  for (int l = 0; l < n_levels; ++l) {
+    th.emplace_back([&, l] {
       mlmc_model ml = *model;
       if (n_ce) ml.n_ce = n_ce[l];
-      TRY(level_run_impl(ctx, &ml, l, m_fine[l], first_sample[l], nullptr, n[l], cgv, &opts[l],
-                         &sums[l], nullptr, nullptr, nullptr, nullptr, nullptr));
-    }
-    return MLMC_OK;
+      rc[l] = level_run_impl(ctx->subs[l], &ml, l, m_fine[l], first_sample[l], nullptr, n[l], cgv,
+                             &opts[l], &sums[l], nullptr, nullptr, nullptr, nullptr, nullptr);
+    });
   }
-  hipStream_t st = ctx->stream;
-  const int ncomp = cgv ? 4 : 1;
-
-  // Grid groups: fine samples of level l (grid m_l) and companions of level
-  // l' >= 1 (grid m_l' / 2); group order = first appearance, fine before
-  // companion, so level l's fine samples precede level l+1's companions.
-  struct Part {
-    int level, role;  // role 0 fine, 1 companions
-    long long off;    // first sample of the part within its group
-    long long count;
-  };
-  struct Group {
-    int m;
-    int opts_level;
-    long long count = 0;
-    std::vector<Part> parts;
-  };
-  std::vector<Group> groups;
-  auto group_of = [&](int m, int lvl) -> Group& {
-    for (auto& g : groups)
-      if (g.m == m) return g;
-    groups.push_back(Group{});
-    groups.back().m = m;
-    groups.back().opts_level = lvl;
-    return groups.back();
-  };
-  for (int l = 0; l < n_levels; ++l) {
-    Group& g = group_of(m_fine[l], l);
-    g.parts.push_back(Part{l, 0, g.count, n[l]});
-    g.count += n[l];
-    if (l > 0) {
-      Group& gc = group_of(m_fine[l] / 2, l);
-      gc.parts.push_back(Part{l, 1, gc.count, (long long)n[l] * ncomp});
-      gc.count += (long long)n[l] * ncomp;
-    }
-  }
-  // per group: k, T, tb, b, p, q, status, iters, relres
-  struct GroupBuf {
-    double *k, *T, *tb, *b, *p, *q, *rr;
-    int32_t *stt, *it;
-  };
-  std::vector<GroupBuf> gb(groups.size());
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const long long B = std::max<long long>(groups[gi].count, 1);
-    const long long cells = (long long)groups[gi].m * groups[gi].m;
-    const std::string tag = "rl" + std::to_string(gi) + "_";
-    TRY(ws(ctx, tag + "k", B * cells, &gb[gi].k));
-    TRY(ws(ctx, tag + "T", B * 2 * cells, &gb[gi].T));
-    TRY(ws(ctx, tag + "tb", (size_t)B * 2 * groups[gi].m, &gb[gi].tb));
-    TRY(ws(ctx, tag + "b", B * cells, &gb[gi].b));
-    TRY(ws(ctx, tag + "p", B * cells, &gb[gi].p));
-    TRY(ws(ctx, tag + "q", B, &gb[gi].q));
-    TRY(ws(ctx, tag + "rr", B, &gb[gi].rr));
-    TRY(ws(ctx, tag + "st", B, &gb[gi].stt));
-    TRY(ws(ctx, tag + "it", B, &gb[gi].it));
-  }
-  auto find = [&](int m, int level, int role, size_t* gi_out) -> const Part* {
-    for (size_t gi = 0; gi < groups.size(); ++gi)
-      if (groups[gi].m == m)
-        for (auto& pt : groups[gi].parts)
-          if (pt.level == level && pt.role == role) {
-            *gi_out = gi;
-            return &pt;
-          }
-    return nullptr;
-  };
-  // sample every level straight into its group slots (plain companions too)
-  for (int l = 0; l < n_levels; ++l) {
-    if (n[l] == 0) continue;
-    size_t gf = 0, gcp = 0;
-    const Part* pf = find(m_fine[l], l, 0, &gf);
-    const Part* pc = l > 0 ? find(m_fine[l] / 2, l, 1, &gcp) : nullptr;
-    const long long cf = (long long)m_fine[l] * m_fine[l];
-    double* kf = gb[gf].k + pf->off * cf;
-    double* kc = nullptr;
-    if (pc) kc = gb[gcp].k + pc->off * (long long)(m_fine[l] / 2) * (m_fine[l] / 2);
-    mlmc_model mdl = *model;
-    mdl.n_ce = n_ce ? n_ce[l] : model->n_ce;
-    TRY(sample_field_impl(ctx, &mdl, m_fine[l], l, first_sample[l], nullptr, n[l], kf,
-                          (pc && !cgv) ? kc : nullptr));
-    if (pc && cgv) TRY(mlmc_cgv_extract(ctx, 2, m_fine[l], n[l], kf, kc));
-  }
-  // one assemble + solve + QoI per grid, smallest grid first: as in
-  // mlmc_level_run, the fine samples of a level l >= 1 start from the
-  // solutions of their first companions (solved with grid m_l / 2, earlier),
-  // the other samples from zero, which gives the same iterates as a solve
-  // without a guess
-  std::vector<size_t> order(groups.size());
-  for (size_t gi = 0; gi < groups.size(); ++gi) order[gi] = gi;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](size_t a, size_t b2) { return groups[a].m < groups[b2].m; });
-  for (size_t gi : order) {
-    const Group& g = groups[gi];
-    if (g.count == 0) continue;
-    TRY(mlmc_assemble_problem(ctx, model->problem, 2, g.m, (int)g.count, gb[gi].k, gb[gi].T,
-                              gb[gi].tb, gb[gi].b));
-    mlmc_solver_opts o = opts[g.opts_level];
-    o.initial_guess = 0;
-    const long long cells = (long long)g.m * g.m;
-    for (const Part& pt : g.parts) {
-      size_t gcp = 0;
-      const Part* pc = (pt.role == 0 && pt.level > 0 && pt.count > 0 && g.m % 2 == 0)
-                           ? find(g.m / 2, pt.level, 1, &gcp)
-                           : nullptr;
-      if (!pc) continue;
-      if (!o.initial_guess)
-        HIP_TRY(hipMemsetAsync(gb[gi].p, 0, sizeof(double) * g.count * cells, st));
-      o.initial_guess = 1;
-      launch_inject(st, g.m, (int)pt.count, ncomp, gb[gcp].p + pc->off * (cells / 4),
-                    gb[gi].p + pt.off * cells);
-    }
-    TRY(mlmc_solve(ctx, 2, g.m, (int)g.count, gb[gi].T, gb[gi].tb, gb[gi].b, gb[gi].p, &o,
-                   gb[gi].stt, gb[gi].it, gb[gi].rr));
-    TRY(model_qoi(ctx, model, 2, g.m, (int)g.count, gb[gi].k, gb[gi].p, gb[gi].q));
-  }
-  // per level: Y, failures, sums
-  double *yv, *qcv, *out;
-  int32_t* failed;
-  long long nmax = 1;
-  for (int l = 0; l < n_levels; ++l) nmax = std::max<long long>(nmax, n[l]);
-  TRY(ws(ctx, "rlv_y", nmax, &yv));
-  TRY(ws(ctx, "rlv_qc", nmax, &qcv));
-  TRY(ws(ctx, "rlv_failed", nmax, &failed));
-  TRY(ws(ctx, "rlv_out", 8 * n_levels, &out));
-  for (int l = 0; l < n_levels; ++l) {
-    if (n[l] == 0) continue;
-    size_t gf = 0, gcp = 0;
-    const Part* pf = find(m_fine[l], l, 0, &gf);
-    const Part* pc = l > 0 ? find(m_fine[l] / 2, l, 1, &gcp) : nullptr;
-    const double* qf = gb[gf].q + pf->off;
-    const int32_t* stf = gb[gf].stt + pf->off;
-    const int32_t* itf = gb[gf].it + pf->off;
-    const double* qc = nullptr;
-    const int32_t *stc = nullptr, *itc = nullptr;
-    if (pc) {
-      launch_cgv_average(st, n[l], ncomp, gb[gcp].q + pc->off, qcv);
-      qc = qcv;
-      stc = gb[gcp].stt + pc->off;
-      itc = gb[gcp].it + pc->off;
-    }
-    launch_y_and_fail(st, n[l], qf, qc, stf, stc, pc ? ncomp : 0, yv, failed);
-    launch_level_reduce(st, n[l], yv, qf, qc, failed, itf, itc, pc ? ncomp : 0, out + 8 * l);
-  }
-  CHECK_LAUNCH();
-  std::vector<double> h(8 * n_levels);
-  HIP_TRY(hipMemcpyAsync(h.data(), out, sizeof(double) * 8 * n_levels, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  bool any_failed = false;
-  for (int l = 0; l < n_levels; ++l) {
-    if (n[l] == 0) continue;
-    const double* hl = h.data() + 8 * l;
-    sums[l].n += n[l];
-    sums[l].sum_y += hl[0];
-    sums[l].sum_y2 += hl[1];
-    sums[l].sum_qf += hl[2];
-    sums[l].sum_qc += hl[3];
-    sums[l].n_failed += (int64_t)llround(hl[4]);
-    sums[l].iters_fine += (int64_t)llround(hl[5]);
-    sums[l].iters_coarse += (int64_t)llround(hl[6]);
-    any_failed |= hl[4] > 0.5;
-  }
-  if (any_failed) return fail(ctx, MLMC_ENOCONV, "some solves did not reach the tolerance");
+  for (auto& t : th) t.join();
+  ctx->event_pool.push_back(start);
+  // level runs synchronise their streams before returning; report the first
+  // error, a non-converged solve only when nothing else failed
+  int worst = -1;
+  for (int l = 0; l < n_levels; ++l)
+    if (rc[l] != MLMC_OK && (worst < 0 || (rc[worst] == MLMC_ENOCONV && rc[l] != MLMC_ENOCONV)))
+      worst = l;
+  if (worst >= 0)
+    return fail(ctx, rc[worst],
+                "level " + std::to_string(worst) + ": " + mlmc_last_error(ctx->subs[worst]));
   return MLMC_OK;
 }
 

@@ -97,17 +97,19 @@ struct CoarseDesc {
 // prec: MLMC_PREC_* storage of the hierarchy (T, tb, z_pre, z and r below the
 // finest level).  top: the level is the finest one, whose r and z are FP64.
 // With rz_partial != NULL (top only) the up kernel writes r^T z per tile:
-// rz_partial[s * mg_rz_parts(m, prec) + tile]; the coarse cycle per sample.
-int mg_rz_parts(int m, int prec);
+// rz_partial[s * mg_rz_parts(m, prec, shape) + tile]; the coarse cycle per
+// sample.  shape: mlmc_solver_opts.tile_shape (0 default tiles, 1 alternative).
+int mg_rz_parts(int m, int prec, int shape);
 size_t prec_bytes(int prec);
-void launch_mg_down(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
-                    const void* tb, const void* r, void* z, void* rc, const int32_t* active);
-void launch_mg_up(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+void launch_mg_down(hipStream_t st, int prec, int shape, bool top, int m, int batch,
+                    const void* T, const void* tb, const void* r, void* z, void* rc,
+                    const int32_t* active);
+void launch_mg_up(hipStream_t st, int prec, int shape, bool top, int m, int batch, const void* T,
                   const void* tb, const void* r, const void* zpre, void* z, const void* zc,
                   double omega, const int32_t* active, double* rz_partial);
 // Second coarse correction of a W-cycle level: z = zpre + omega P zc,
 // black-red-black sweeps, z and the restricted residual rc.
-void launch_mg_mid(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+void launch_mg_mid(hipStream_t st, int prec, int shape, bool top, int m, int batch, const void* T,
                    const void* tb, const void* r, const void* zpre, void* z, const void* zc,
                    double omega, void* rc, const int32_t* active);
 size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev);

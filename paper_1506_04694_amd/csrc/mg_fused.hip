@@ -1425,10 +1425,14 @@ static bool fixed_tile(int m) { return m % kTileX == 0 && m % kTileY == 0; }
 // where 128 divides m, else 64 x 16 on 384; FP32 and bfloat16: down and up
 // 64 x 32 on 640 threads, mid 64 x 64 on 1024).  Every shape divides each m
 // that is a multiple of 64 (fixed_tile), except up's 128 x 16.
+// shape = 1 selects an alternative set for the autotuner to try (FP64: down
+// and up 64 x 16 on 384 threads, mid 64 x 64 on 1024; FP32 and bfloat16: down
+// and up 64 x 16 on 704, mid 64 x 32 on 768).
 static bool up_wide(int m) { return m % 128 == 0; }
 
-int mg_rz_parts(int m, int prec) {
+int mg_rz_parts(int m, int prec, int shape) {
   if (fixed_tile(m)) {
+    if (shape == 1) return (m / 64) * (m / 16);
     if (prec == MLMC_PREC_FP64) return up_wide(m) ? (m / 128) * (m / 16) : (m / 64) * (m / 16);
     return (m / 64) * (m / 32);
   }
@@ -1468,11 +1472,15 @@ static void mid_p(hipStream_t st, int m, int batch, const void* T, const void* t
 }
 
 template <class S, bool TOP>
-static void down_impl(hipStream_t st, int m, int batch, const void* T, const void* tb,
+static void down_impl(int shape, hipStream_t st, int m, int batch, const void* T, const void* tb,
                       const void* r, void* z, void* rc, const int32_t* active) {
   using R = VecT<S, TOP>;
   if (fixed_tile(m)) {
-    if constexpr (std::is_same<S, double>::value)
+    if (shape == 1) {
+      if constexpr (std::is_same<S, double>::value)
+        down_p<64, 16, 384, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
+      else down_p<64, 16, 704, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
+    } else if constexpr (std::is_same<S, double>::value)
       down_p<64, 32, 1024, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
     else down_p<64, 32, 640, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
     return;
@@ -1486,12 +1494,16 @@ static void down_impl(hipStream_t st, int m, int batch, const void* T, const voi
 }
 
 template <class S, bool TOP>
-static void up_impl(hipStream_t st, int m, int batch, const void* T, const void* tb,
+static void up_impl(int shape, hipStream_t st, int m, int batch, const void* T, const void* tb,
                     const void* r, const void* zpre, void* z, const void* zc, double omega,
                     const int32_t* active, double* rz_partial) {
   using R = VecT<S, TOP>;
   if (fixed_tile(m)) {
-    if constexpr (!std::is_same<S, double>::value)
+    if (shape == 1) {
+      if constexpr (std::is_same<S, double>::value)
+        up_p<64, 16, 384, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+      else up_p<64, 16, 704, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+    } else if constexpr (!std::is_same<S, double>::value)
       up_p<64, 32, 640, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
     else if (up_wide(m))
       up_p<128, 16, 640, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
@@ -1507,12 +1519,16 @@ static void up_impl(hipStream_t st, int m, int batch, const void* T, const void*
 }
 
 template <class S, bool TOP>
-static void mid_impl(hipStream_t st, int m, int batch, const void* T, const void* tb, const void* r,
-                     const void* zpre, void* z, const void* zc, double omega, void* rc,
-                     const int32_t* active) {
+static void mid_impl(int shape, hipStream_t st, int m, int batch, const void* T, const void* tb,
+                     const void* r, const void* zpre, void* z, const void* zc, double omega,
+                     void* rc, const int32_t* active) {
   using R = VecT<S, TOP>;
   if (fixed_tile(m)) {
-    if constexpr (std::is_same<S, double>::value)
+    if (shape == 1) {
+      if constexpr (std::is_same<S, double>::value)
+        mid_p<64, 64, 1024, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+      else mid_p<64, 32, 768, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+    } else if constexpr (std::is_same<S, double>::value)
       mid_p<64, 32, 768, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
     else mid_p<64, 64, 1024, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
     return;
@@ -1527,34 +1543,36 @@ static void mid_impl(hipStream_t st, int m, int batch, const void* T, const void
 }
 
 template <class S>
-static void mid_any(bool top, hipStream_t st, int m, int batch, const void* T, const void* tb,
-                    const void* r, const void* zpre, void* z, const void* zc, double omega,
-                    void* rc, const int32_t* active) {
-  if (top) mid_impl<S, true>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
-  else mid_impl<S, false>(st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+static void mid_any(int shape, bool top, hipStream_t st, int m, int batch, const void* T,
+                    const void* tb, const void* r, const void* zpre, void* z, const void* zc,
+                    double omega, void* rc, const int32_t* active) {
+  if (top) mid_impl<S, true>(shape, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+  else mid_impl<S, false>(shape, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
 }
 
-void launch_mg_mid(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+void launch_mg_mid(hipStream_t st, int prec, int shape, bool top, int m, int batch, const void* T,
                    const void* tb, const void* r, const void* zpre, void* z, const void* zc,
                    double omega, void* rc, const int32_t* active) {
-  if (prec == MLMC_PREC_FP64) mid_any<double>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
-  else if (prec == MLMC_PREC_FP32) mid_any<float>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
-  else mid_any<bf16_t>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+  if (prec == MLMC_PREC_FP64)
+    mid_any<double>(shape, top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+  else if (prec == MLMC_PREC_FP32)
+    mid_any<float>(shape, top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
+  else mid_any<bf16_t>(shape, top, st, m, batch, T, tb, r, zpre, z, zc, omega, rc, active);
 }
 
 template <class S>
-static void down_any(bool top, hipStream_t st, int m, int batch, const void* T, const void* tb,
-                     const void* r, void* z, void* rc, const int32_t* active) {
-  if (top) down_impl<S, true>(st, m, batch, T, tb, r, z, rc, active);
-  else down_impl<S, false>(st, m, batch, T, tb, r, z, rc, active);
+static void down_any(int shape, bool top, hipStream_t st, int m, int batch, const void* T,
+                     const void* tb, const void* r, void* z, void* rc, const int32_t* active) {
+  if (top) down_impl<S, true>(shape, st, m, batch, T, tb, r, z, rc, active);
+  else down_impl<S, false>(shape, st, m, batch, T, tb, r, z, rc, active);
 }
 
 template <class S>
-static void up_any(bool top, hipStream_t st, int m, int batch, const void* T, const void* tb,
-                   const void* r, const void* zpre, void* z, const void* zc, double omega,
-                   const int32_t* active, double* rz_partial) {
-  if (top) up_impl<S, true>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
-  else up_impl<S, false>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+static void up_any(int shape, bool top, hipStream_t st, int m, int batch, const void* T,
+                   const void* tb, const void* r, const void* zpre, void* z, const void* zc,
+                   double omega, const int32_t* active, double* rz_partial) {
+  if (top) up_impl<S, true>(shape, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+  else up_impl<S, false>(shape, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
 }
 
 template <class S, bool TOP, int NL, bool W0>
@@ -1624,21 +1642,22 @@ static void convert_any(hipStream_t st, long long count, const double* x, void* 
                      (S*)y);
 }
 
-void launch_mg_down(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
-                    const void* tb, const void* r, void* z, void* rc, const int32_t* active) {
-  if (prec == MLMC_PREC_FP64) down_any<double>(top, st, m, batch, T, tb, r, z, rc, active);
-  else if (prec == MLMC_PREC_FP32) down_any<float>(top, st, m, batch, T, tb, r, z, rc, active);
-  else down_any<bf16_t>(top, st, m, batch, T, tb, r, z, rc, active);
+void launch_mg_down(hipStream_t st, int prec, int shape, bool top, int m, int batch,
+                    const void* T, const void* tb, const void* r, void* z, void* rc,
+                    const int32_t* active) {
+  if (prec == MLMC_PREC_FP64) down_any<double>(shape, top, st, m, batch, T, tb, r, z, rc, active);
+  else if (prec == MLMC_PREC_FP32) down_any<float>(shape, top, st, m, batch, T, tb, r, z, rc, active);
+  else down_any<bf16_t>(shape, top, st, m, batch, T, tb, r, z, rc, active);
 }
 
-void launch_mg_up(hipStream_t st, int prec, bool top, int m, int batch, const void* T,
+void launch_mg_up(hipStream_t st, int prec, int shape, bool top, int m, int batch, const void* T,
                   const void* tb, const void* r, const void* zpre, void* z, const void* zc,
                   double omega, const int32_t* active, double* rz_partial) {
   if (prec == MLMC_PREC_FP64)
-    up_any<double>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+    up_any<double>(shape, top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
   else if (prec == MLMC_PREC_FP32)
-    up_any<float>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
-  else up_any<bf16_t>(top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+    up_any<float>(shape, top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+  else up_any<bf16_t>(shape, top, st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
 }
 
 size_t coarse_cycle_lds_bytes(const CoarseDesc& d, int nlev) {

@@ -19,7 +19,7 @@ def lib():
     return lib
 
 
-@pytest.mark.parametrize("model,m", [("ce2", 64), ("tilted3", 16)])
+@pytest.mark.parametrize("model,m", [("ce2", 64), ("ce2", 128), ("tilted3", 16)])
 def test_tune_level_small_space(lib, model, m):
     from paper_1506_04694_amd import autotune
     mdl = {"ce2": W.CE2, "tilted3": W.TILTED3}[model]
@@ -28,6 +28,8 @@ def test_tune_level_small_space(lib, model, m):
     try:
         space = {"precision": [lib.MLMC_PREC_FP64, lib.MLMC_PREC_FP32, lib.MLMC_PREC_BF16],
                  "gamma_levels": [2, 3]}
+        if m == 128:   # tile shapes instead of W depth on a tiled grid
+            space = {"precision": space["precision"], "tile_shape": [0, 1]}
         res = autotune.tune_level(ctx, mdl, 1, m, 8, space=space, reps=1)
     finally:
         lib.mlmc_ctx_destroy(ctx)

@@ -500,6 +500,27 @@ def test_high_contrast_1024_all_precisions(lib, ctx):
             assert abs(out[prec][s] - row["Q_f"]) <= QTOL * row["Q_f"], (s, prec, out[prec][s])
 
 
+@pytest.mark.parametrize("m,prec,variant", [(64, 0, 2), (128, 0, 0), (192, 0, 0), (256, 0, 0),
+                                             (128, 1, 0), (256, 1, 0), (128, 2, 0)])
+def test_tile_shapes_agree(lib, ctx, m, prec, variant):
+    """The alternative tile shapes of the multigrid kernels (tile_shape = 1) do
+    the same arithmetic per cell: same iterations (+-1: the r^T z tile sums add
+    in another order) and QoIs to 1e-12 of the default shapes, and the oracle's
+    QoI to 1e-10.  m = 192 takes the 64-wide fallback of the default up tile."""
+    print("tile shapes m=%d prec=%d variant=%d" % (m, prec, variant), flush=True)
+    rng = np.random.default_rng(1300 + m + prec)
+    kh = np.exp(1.4 * rng.standard_normal((3, m, m)))
+    a = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=prec, variant=variant))
+    b = solve_batch(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=prec, variant=variant,
+                                                             tile_shape=1))
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+    assert np.all(np.abs(a["iters"] - b["iters"]) <= 1), (a["iters"], b["iters"])
+    np.testing.assert_allclose(b["q_out"], a["q_out"], rtol=1e-12, atol=0)
+    A, bb = ofv.assemble(kh[0])
+    q = oqoi.outflow(kh[0], osolve.direct_solve(A, bb))
+    assert abs(b["q_out"][0] - q) <= QTOL * q
+
+
 def test_mixed_precision_requires_fused(lib, ctx):
     kh = np.ones((1, 16, 16))
     with pytest.raises(lib.MlmcError):
@@ -509,7 +530,8 @@ def test_mixed_precision_requires_fused(lib, ctx):
 # ------------------------------------------------------------------ all levels in one call
 @pytest.mark.parametrize("cgv", [False, True])
 def test_run_levels_matches_level_runs(lib, ctx, cgv):
-    """Merging level l's fine samples with level l+1's companions into one solve per
+    """Running the levels concurrently in one call (a pipeline per level on its own
+    stream) does not change any sample's numbers; formerly: merging level l's fine samples with level l+1's companions into one solve per
     grid does not change any sample's numbers, so the level sums are identical."""
     model, ms, ns = W.CE2, [32, 64, 128], [48, 24, 8]
     per = []
