@@ -381,6 +381,48 @@ def cgv_variance(lib, torch, ctx, opts):
     return out
 
 
+def rates_vs_reference(lib, torch, ctx, opts):
+    """Section 3.4's convergence observations from reference solutions: for the
+    paper's three piecewise constant layers (the sample -- two random lines and
+    three log-normal constants -- does not depend on the grid, so each sample is
+    solved on every grid and on the reference grid h* = 1/512 in 2-D, 1/128 in
+    3-D), the weak error |E[Q_h - Q_h*]| per grid from the paired differences,
+    its standard error, the least squares rate alpha_ref, and beside it the rate
+    alpha_Y of |E[Q_h - Q_2h]| (the MLMC differences of the same samples), for
+    the outflow (Model Problem 2) and the mean pressure (Model Problem 1)."""
+    import numpy as np
+    out = {}
+    for key, model, grids, ref, n in W.RATES_REFERENCE:
+        q = {}
+        t0 = time.perf_counter()
+        for m in grids + [ref]:
+            qt = torch.empty(n, dtype=torch.float64, device="cuda")
+            lib.mlmc_level_run(ctx, model, 0, m, 0, n, False, opts, q_f=qt)
+            q[m] = qt.cpu().numpy()
+        rows = []
+        for m in grids:
+            d = q[m] - q[ref]
+            row = {"h": 1.0 / m, "m": m, "weak_error": float(abs(d.mean())),
+                   "std_error": float(d.std(ddof=1) / math.sqrt(n))}
+            if m // 2 in q:
+                y = q[m] - q[m // 2]
+                row["mean_y"] = float(y.mean())
+                row["var_y"] = float(y.var(ddof=1))
+            rows.append(row)
+        h = np.array([r["h"] for r in rows])
+        e = np.array([r["weak_error"] for r in rows])
+        alpha_ref = float(np.polyfit(np.log2(h), np.log2(e), 1)[0])
+        hy = np.array([r["h"] for r in rows if "mean_y" in r])
+        ey = np.abs(np.array([r["mean_y"] for r in rows if "mean_y" in r]))
+        alpha_y = float(np.polyfit(np.log2(hy), np.log2(ey), 1)[0]) if len(hy) >= 2 else None
+        vy = np.array([r["var_y"] for r in rows if "var_y" in r])
+        beta = float(np.polyfit(np.log2(hy), np.log2(vy), 1)[0]) if len(hy) >= 2 else None
+        out[key] = {"dim": int(model.dim), "problem": int(model.problem), "reference_m": ref,
+                    "samples": n, "grids": rows, "alpha_ref": alpha_ref, "alpha_y": alpha_y,
+                    "beta": beta, "seconds": time.perf_counter() - t0}
+    return out
+
+
 def other_configs(lib, torch, steps):
     """The other batched workloads, each timed over `steps` passes after one warm-up
     pass (not part of `value`):
@@ -395,7 +437,8 @@ def other_configs(lib, torch, steps):
     * Model Problem 1 on the bench workload's levels, level by level;
     * Section 3.4's three-layer correlated model (per-layer correlation lengths),
       both model problems, all levels in one call;
-    * adaptive MLMC to a root mean square error (Section 3.2), plain and CGV."""
+    * adaptive MLMC to a root mean square error (Section 3.2), plain and CGV;
+    * weak-error rates against reference solutions (rates_vs_reference)."""
     ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
     opts = lib.mlmc_solver_opts_default()
 
@@ -531,6 +574,7 @@ def other_configs(lib, torch, steps):
                          "alpha": r.alpha, "beta": r.beta, "gamma": r.gamma}
         out["adaptive"] = {"model": "layered CE (bench model)", "eps": W.ADAPTIVE_EPS,
                            "runs": ada}
+        out["rates_vs_reference"] = rates_vs_reference(lib, torch, ctx, opts)
     finally:
         lib.mlmc_ctx_destroy(ctx)
     return out

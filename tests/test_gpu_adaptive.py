@@ -87,3 +87,31 @@ def test_adaptive_refuses_bad_hierarchy(lib, ctx):
     opts = lib.mlmc_adaptive_opts_default()
     with pytest.raises(lib.MlmcError):
         lib.mlmc_adaptive(ctx, W.PC2, [8, 12, 24], opts, lib.mlmc_solver_opts_default())
+
+
+@pytest.mark.parametrize("key", ["2d_mp2", "2d_mp1", "3d_mp2"])
+def test_reference_solution_rates_inputs(lib, ctx, key):
+    """The reference-solution rates of the bench (Section 3.4) solve the same
+    sample on every grid: for the paper's three piecewise constant layers the
+    level-0 stream fixes the lines and the constants independently of the grid.
+    Samples 0-2 on each grid (and on the 3-D reference grid's half) equal the
+    oracle's exact discrete QoI of that sample on that grid (1e-10), and the
+    paired weak errors against the reference grid shrink as h does."""
+    spec = {k: (mdl, grids, ref, n) for k, mdl, grids, ref, n in W.RATES_REFERENCE}
+    mdl, grids, ref, _ = spec[key]
+    n = 16
+    opts = lib.mlmc_solver_opts_default()
+    q = {}
+    for m in grids + [ref]:
+        print("reference rates %s m=%d" % (key, m), flush=True)
+        qt = torch.empty(n, dtype=torch.float64, device="cuda")
+        sums = lib.mlmc_level_run(ctx, mdl, 0, m, 0, n, False, opts, q_f=qt)
+        assert sums.n_failed == 0
+        q[m] = qt.cpu().numpy()
+    check = [g for g in grids if g <= (32 if mdl.dim == 3 else 256)][:3]
+    for m in check:
+        for s in range(3):
+            ref_q = omlmc.level_sample(mdl, 0, s, m)["Q_f"]
+            assert abs(q[m][s] - ref_q) <= 1e-10 * abs(ref_q), (m, s, q[m][s], ref_q)
+    err = [abs(np.mean(q[m] - q[ref])) for m in grids]
+    assert err[-1] < err[0], err

@@ -128,6 +128,17 @@ ADAPTIVE_LEVELS = [16, 32, 64, 128, 256, 512]
 MP1_PAPER3 = Model(interface_kind=PAPER_TWO_LINES, n_layers=3, field_kind=PIECEWISE_CONSTANT,
                    mu=(0.0, 0.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0), seed=0, problem=1)
 
+# Weak errors against reference solutions (Section 3.4: h* = 1/512 in 2-D,
+# 1/128 in 3-D) on the paper's three piecewise constant layers between two
+# random lines (extruded along x3 in 3-D): the same sample on every grid, both
+# model problems; (key, model, grids, reference grid, samples).
+RATES_REFERENCE = [
+    ("2d_mp2", MP1_PAPER3.with_(problem=0), [16, 32, 64, 128, 256], 512, 1024),
+    ("2d_mp1", MP1_PAPER3, [16, 32, 64, 128, 256], 512, 1024),
+    ("3d_mp2", MP1_PAPER3.with_(problem=0, dim=3), [8, 16, 32, 64], 128, 128),
+    ("3d_mp1", MP1_PAPER3.with_(dim=3), [8, 16, 32, 64], 128, 128),
+]
+
 # The variance experiment of Section 4.2: V[Y_l] of the plain and the CGV
 # estimator on the stationary 1-norm field, fine grids h_l = 1/8 .. 1/256 in
 # 2-D and 1/8 .. 1/64 in 3-D; (fine grid m_l, samples).
