@@ -423,6 +423,49 @@ def rates_vs_reference(lib, torch, ctx, opts):
     return out
 
 
+def served_3d(lib, torch, ctx, steps):
+    """Level runs of the served 3-D model (tilted plane, two correlated layers,
+    2-norm covariance; 32^3, 64^3, 128^3 with 64/16/4 samples, fine solve plus
+    plain coarse companion): per level the median over `steps` calls after one
+    warm-up, with the FP32 hierarchy (and the level's tuned W depth) and with
+    the FP64 one, the mean fine PCG iterations, and the time of the field
+    sampler alone (circulant embedding, n_ce^3 points per sample) for the same
+    samples."""
+    wl = W.SERVED_3D
+    out = []
+    for level, (m, n) in enumerate(zip(wl.m_levels, wl.n_samples)):
+        row = {"level": level, "m": m, "samples": n, "n_ce": wl.model.n_ce[m]}
+        for name, prec in (("f32", lib.MLMC_PREC_FP32), ("f64", lib.MLMC_PREC_FP64)):
+            o = lib.mlmc_solver_opts_default(precision=prec)
+            for key, v in W.SERVED_3D_LEVEL_OPTS[level].items():
+                setattr(o, key, v)
+            ts, its = [], 0
+            for k in range(steps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = lib.mlmc_level_run(ctx, wl.model, level, m, k * n, n, False, o)
+                torch.cuda.synchronize()
+                if k > 0:
+                    ts.append(time.perf_counter() - t0)
+                    its += s.iters_fine
+            row[name] = {"ms": 1e3 * sorted(ts)[len(ts) // 2],
+                         "mean_iters_fine": its / (steps * n),
+                         "opts": dict(W.SERVED_3D_LEVEL_OPTS[level])}
+        k = torch.empty(n, m, m, m, dtype=torch.float64, device="cuda")
+        kc = torch.empty(n, m // 2, m // 2, m // 2, dtype=torch.float64, device="cuda")
+        ts = []
+        for j in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lib.mlmc_sample_field(ctx, wl.model, m, level, j * n, n, k, kc)
+            torch.cuda.synchronize()
+            if j > 0:
+                ts.append(time.perf_counter() - t0)
+        row["sampler_ms"] = 1e3 * sorted(ts)[len(ts) // 2]
+        out.append(row)
+    return {"workload": wl.name, "per_level": out}
+
+
 def other_configs(lib, torch, steps):
     """The other batched workloads, each timed over `steps` passes after one warm-up
     pass (not part of `value`):
@@ -438,6 +481,7 @@ def other_configs(lib, torch, steps):
     * Section 3.4's three-layer correlated model (per-layer correlation lengths),
       both model problems, all levels in one call;
     * adaptive MLMC to a root mean square error (Section 3.2), plain and CGV;
+    * the served 3-D model's level runs (served_3d);
     * weak-error rates against reference solutions (rates_vs_reference)."""
     ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
     opts = lib.mlmc_solver_opts_default()
@@ -574,6 +618,7 @@ def other_configs(lib, torch, steps):
                          "alpha": r.alpha, "beta": r.beta, "gamma": r.gamma}
         out["adaptive"] = {"model": "layered CE (bench model)", "eps": W.ADAPTIVE_EPS,
                            "runs": ada}
+        out["served_3d"] = served_3d(lib, torch, ctx, steps)
         out["rates_vs_reference"] = rates_vs_reference(lib, torch, ctx, opts)
     finally:
         lib.mlmc_ctx_destroy(ctx)

@@ -232,7 +232,7 @@ mlmc_status mlmc_ce_min_embedding(mlmc_ctx* ctx, const mlmc_model* model, int m,
  *            layers keep their value; correlated layers take the Gaussian
  *            value of fine cell (2I, 2J) (3-D: (2I, 2J, 2L)).
  * Correlated fields need model->n_ce valid for m (else MLMC_EEMBED; 3-D
- * embeddings are limited to n_ce <= 512, else MLMC_EINVAL); the embedding
+ * embeddings are limited to n_ce <= 1024, else MLMC_EINVAL); the embedding
  * eigenvalues are computed once per (d, m, n_ce, sigma2, lambda, r) and cached
  * in the context. */
 mlmc_status mlmc_sample_field(mlmc_ctx* ctx, const mlmc_model* model, int m, int level,

@@ -822,8 +822,11 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
       launch_resid_restrict3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], rh[l + 1],
                                S.active);
       cycle(l + 1);
-      launch_prolong3_p(st, f32, top, ml, batch, zh[l + 1], zh[l], omega, S.active);
-      for (int it = 0; it < nu; ++it) {
+      // the prolongation rides on the first (black) half-sweep of post-smoothing
+      launch_prolong_black3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], zh[l + 1],
+                              omega, S.active);
+      sweep(0, 0);
+      for (int it = 1; it < nu; ++it) {
         sweep(1, 0);
         sweep(0, 0);
       }

@@ -294,17 +294,76 @@ static void rbgs3_t(hipStream_t st, int m, int batch, const void* T, const void*
                      (const S*)T, (const S*)tb, (V*)z, (const V*)r, active, color, zero_init, cd);
 }
 
-void launch_rbgs3(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
-                  const double* r, const int32_t* active, int color, int zero_init) {
-  rbgs3_t<double, double>(st, m, batch, T, tb, z, r, active, color, zero_init);
-}
-
 void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
                     const void* tb, void* z, const void* r, const int32_t* active, int color,
                     int zero_init) {
   if (!f32) rbgs3_t<double, double>(st, m, batch, T, tb, z, r, active, color, zero_init);
   else if (top) rbgs3_t<float, double>(st, m, batch, T, tb, z, r, active, color, zero_init);
   else rbgs3_t<float, float>(st, m, batch, T, tb, z, r, active, color, zero_init);
+}
+
+// Prolongation fused into the first half-sweep of post-smoothing.  After
+// z += omega P zc the black half-sweep replaces every black value, and the red
+// half-sweep after it replaces every red one, so the prolonged values are
+// only ever read as the black cells' red neighbours: the kernel updates the
+// black cells (one thread each) from neighbours z_n + omega zc(parent of n),
+// formed as the prolongation forms them (in V), and writes nothing else: the
+// arithmetic of a separate prolongation pass followed by k_rbgs3 on the black
+// cells.
+template <class S, class V>
+__global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T,
+                                 const S* __restrict__ tb, V* __restrict__ z,
+                                 const V* __restrict__ r, const S* __restrict__ zc,
+                                 double omega, const int32_t* __restrict__ active, CellDiv cd) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int half = m / 2;
+  const long long per = (long long)m * m * half;
+  int h, j, l;
+  const long long s = split_cell(g, per, cd, h, j, l);
+  if (!active[s]) return;
+  const int i = 2 * h + ((j + l + 1) & 1);
+  const long long n = (long long)m * m * m;
+  const int mc = m / 2;
+  const Faces3T<S> f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
+  V* zs = z + s * n;
+  const S* zcs = zc + s * (long long)mc * mc * mc;
+  const V w = (V)omega;
+  auto pz = [&](long long c, int ii, int jj, int ll) -> S {
+    return (S)(zs[c] + w * (V)zcs[((long long)(ll / 2) * mc + jj / 2) * mc + ii / 2]);
+  };
+  const long long c = ((long long)l * m + j) * m + i;
+  const long long mm = (long long)m * m;
+  S o = S(0);
+  if (i < m - 1) o += f.te * pz(c + 1, i + 1, j, l);
+  if (i > 0) o += f.tw * pz(c - 1, i - 1, j, l);
+  if (j < m - 1) o += f.tn * pz(c + m, i, j + 1, l);
+  if (j > 0) o += f.ts * pz(c - m, i, j - 1, l);
+  if (l < m - 1) o += f.tu * pz(c + mm, i, j, l + 1);
+  if (l > 0) o += f.td * pz(c - mm, i, j, l - 1);
+  const S rv = (S)r[s * n + c];
+  zs[c] = (V)((rv + o) / diag3(f));
+}
+
+template <class S, class V>
+static void prolong_black3_t(hipStream_t st, int m, int batch, const void* T, const void* tb,
+                             void* z, const void* r, const void* zc, double omega,
+                             const int32_t* active) {
+  const long long total = (long long)batch * m * m * (m / 2);
+  CellDiv cd = make_celldiv(total, (long long)m * m * (m / 2), m);
+  cd.mm = make_fastdiv((uint32_t)m * (uint32_t)(m / 2));
+  cd.m = make_fastdiv((uint32_t)(m / 2));
+  hipLaunchKernelGGL((k_prolong_black3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m,
+                     total, (const S*)T, (const S*)tb, (V*)z, (const V*)r, (const S*)zc, omega,
+                     active, cd);
+}
+
+void launch_prolong_black3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
+                             const void* tb, void* z, const void* r, const void* zc,
+                             double omega, const int32_t* active) {
+  if (!f32) prolong_black3_t<double, double>(st, m, batch, T, tb, z, r, zc, omega, active);
+  else if (top) prolong_black3_t<float, double>(st, m, batch, T, tb, z, r, zc, omega, active);
+  else prolong_black3_t<float, float>(st, m, batch, T, tb, z, r, zc, omega, active);
 }
 
 // rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z); rc in S.
@@ -349,56 +408,12 @@ static void resid_restrict3_t(hipStream_t st, int m, int batch, const void* T, c
                      cd);
 }
 
-void launch_resid_restrict3(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                            const double* z, const double* r, double* rc,
-                            const int32_t* active) {
-  resid_restrict3_t<double, double>(st, m, batch, T, tb, z, r, rc, active);
-}
-
 void launch_resid_restrict3_p(hipStream_t st, bool f32, bool top, int m, int batch,
                               const void* T, const void* tb, const void* z, const void* r,
                               void* rc, const int32_t* active) {
   if (!f32) resid_restrict3_t<double, double>(st, m, batch, T, tb, z, r, rc, active);
   else if (top) resid_restrict3_t<float, double>(st, m, batch, T, tb, z, r, rc, active);
   else resid_restrict3_t<float, float>(st, m, batch, T, tb, z, r, rc, active);
-}
-
-// z += omega * (coarse correction of the cell's 2 x 2 x 2 block); zc in S,
-// z in V (the addition is done in V).
-template <class S, class V>
-__global__ void k_prolong3(int m, long long total, const S* __restrict__ zc,
-                           V* __restrict__ z, double omega,
-                           const int32_t* __restrict__ active, CellDiv cd) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const long long n = (long long)m * m * m;
-  int i, j, l;
-  const long long s = split_cell(g, n, cd, i, j, l);
-  if (!active[s]) return;
-  const int mc = m / 2;
-  z[g] += (V)omega *
-          (V)zc[s * (long long)mc * mc * mc + ((long long)(l / 2) * mc + j / 2) * mc + i / 2];
-}
-
-template <class S, class V>
-static void prolong3_t(hipStream_t st, int m, int batch, const void* zc, void* z, double omega,
-                       const int32_t* active) {
-  const long long total = (long long)batch * m * m * m;
-  const CellDiv cd = make_celldiv(total, (long long)m * m * m, m);
-  hipLaunchKernelGGL((k_prolong3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total,
-                     (const S*)zc, (V*)z, omega, active, cd);
-}
-
-void launch_prolong3(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
-                     const int32_t* active) {
-  prolong3_t<double, double>(st, m, batch, zc, z, omega, active);
-}
-
-void launch_prolong3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* zc,
-                       void* z, double omega, const int32_t* active) {
-  if (!f32) prolong3_t<double, double>(st, m, batch, zc, z, omega, active);
-  else if (top) prolong3_t<float, double>(st, m, batch, zc, z, omega, active);
-  else prolong3_t<float, float>(st, m, batch, zc, z, omega, active);
 }
 
 // z = A^-1 r on the coarsest grid for vectors of a reduced-precision
@@ -832,9 +847,12 @@ void launch_ce_sqrt3(hipStream_t st, const double2* lam, int n, double* sq) {
 // Pass A: L consecutive noise rows r = k3 n + k2 (lines along x1) of one
 // sample: xi(k1) = (z0, z1) of Philox block (r/2) n + k1 for even r, (z2, z3)
 // for odd r; scaled by sqrt(Lambda / n^3); FFT along x1; the first m outputs
-// to u1[s][r][j1].
-template <int C>
-__global__ void __launch_bounds__(kBlock)
+// to u1[s][r][j1].  P: L is even (so r0 is), and a thread draws one block for
+// the row pair (r, r + 1) and fills both lines; otherwise each row draws its
+// own block and keeps half of it.  C = 0: one line per workgroup, fft_line
+// (T = kBlock); otherwise fft_lines<C, T>.
+template <int C, int T, bool P>
+__global__ void __launch_bounds__(T)
 k_ce3_pass_a(uint64_t seed, uint32_t tag, uint32_t level, uint64_t first,
              const uint32_t* __restrict__ ids,
              int m, const double* __restrict__ sq, const double2* __restrict__ tw, FftPlan pl,
@@ -849,30 +867,62 @@ k_ce3_pass_a(uint64_t seed, uint32_t tag, uint32_t level, uint64_t first,
   const int lines = min(L, rows - r0);
   const uint32_t sample = ids ? ids[s] : (uint32_t)(first + (uint64_t)s);
   const float inv_n = 1.0f / (float)n;
-  for (int t = threadIdx.x; t < L * n; t += kBlock) {
-    const int q = div_small(t, inv_n);
-    const int k1 = t - q * n;
-    if (q >= lines) {
-      sre[t] = 0.0;
-      sim[t] = 0.0;
-      continue;
+  if constexpr (P) {
+    for (int t = threadIdx.x; t < (L / 2) * n; t += T) {
+      const int pp = div_small(t, inv_n);
+      const int k1 = t - pp * n;
+      const int q = 2 * pp;
+      double zr = 0.0, zi = 0.0, wr = 0.0, wi = 0.0;
+      if (q < lines) {
+        const int r = r0 + q;
+        const U4 bk = stream_block(seed, (uint32_t)(r / 2) * (uint32_t)n + (uint32_t)k1, sample,
+                                   level, tag);
+        box_muller(to_uniform(bk.x), to_uniform(bk.y), zr, zi);
+        const double a = sq[(long long)r * n + k1];
+        zr *= a;
+        zi *= a;
+        if (q + 1 < lines) {
+          box_muller(to_uniform(bk.z), to_uniform(bk.w), wr, wi);
+          const double a1 = sq[(long long)(r + 1) * n + k1];
+          wr *= a1;
+          wi *= a1;
+        }
+      }
+      sre[q * n + k1] = zr;
+      sim[q * n + k1] = zi;
+      sre[(q + 1) * n + k1] = wr;
+      sim[(q + 1) * n + k1] = wi;
     }
-    const int r = r0 + q;
-    const U4 bk = stream_block(seed, (uint32_t)(r / 2) * (uint32_t)n + (uint32_t)k1, sample, level,
-                               tag);
-    double zr, zi;
-    if ((r & 1) == 0) box_muller(to_uniform(bk.x), to_uniform(bk.y), zr, zi);
-    else box_muller(to_uniform(bk.z), to_uniform(bk.w), zr, zi);
-    const double a = sq[(long long)r * n + k1];
-    sre[t] = a * zr;
-    sim[t] = a * zi;
+  } else {
+    for (int t = threadIdx.x; t < L * n; t += T) {
+      const int q = div_small(t, inv_n);
+      const int k1 = t - q * n;
+      if (q >= lines) {
+        sre[t] = 0.0;
+        sim[t] = 0.0;
+        continue;
+      }
+      const int r = r0 + q;
+      const U4 bk = stream_block(seed, (uint32_t)(r / 2) * (uint32_t)n + (uint32_t)k1, sample,
+                                 level, tag);
+      double zr, zi;
+      if ((r & 1) == 0) box_muller(to_uniform(bk.x), to_uniform(bk.y), zr, zi);
+      else box_muller(to_uniform(bk.z), to_uniform(bk.w), zr, zi);
+      const double a = sq[(long long)r * n + k1];
+      sre[t] = a * zr;
+      sim[t] = a * zi;
+    }
   }
   __syncthreads();
-  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
-  else fft_lines<C, kBlock>(sre, sim, tw, pl, L);
+  if constexpr (C == 0) {
+    static_assert(T == kBlock, "fft_line runs on kBlock threads");
+    fft_line(sre, sim, tw, pl);
+  } else {
+    fft_lines<C, T>(sre, sim, tw, pl, L);
+  }
   double2* out = u1 + ((long long)s * rows + r0) * m;
   const float inv_m = 1.0f / (float)m;
-  for (int t = threadIdx.x; t < lines * m; t += kBlock) {
+  for (int t = threadIdx.x; t < lines * m; t += T) {
     const int q = div_small(t, inv_m);
     const int j1 = t - q * m;
     out[t] = make_double2(sre[q * n + j1], sim[q * n + j1]);
@@ -880,9 +930,11 @@ k_ce3_pass_a(uint64_t seed, uint32_t tag, uint32_t level, uint64_t first,
 }
 
 // Pass B: lines along x2 for fixed (k3, j1), L consecutive j1 of one sample:
-// u1[s][k3 n + k2][j1] -> FFT over k2 -> u2[s][k3][j2][j1], j2 < m.
-template <int C>
-__global__ void __launch_bounds__(kBlock)
+// u1[s][k3 n + k2][j1] -> FFT over k2 -> u2[s][k3][j2][j1], j2 < m.  The L
+// lines of a workgroup are adjacent in memory, so its reads are runs of
+// 16 L bytes.
+template <int C, int T>
+__global__ void __launch_bounds__(T)
 k_ce3_pass_b(int m, const double2* __restrict__ u1, const double2* __restrict__ tw, FftPlan pl,
              int L, int groups, double2* __restrict__ u2) {
   extern __shared__ double lds[];
@@ -896,17 +948,21 @@ k_ce3_pass_b(int m, const double2* __restrict__ u1, const double2* __restrict__ 
   const int j1_0 = (rem - k3 * per_k3) * L;
   const int lines = min(L, m - j1_0);
   const double2* in = u1 + ((long long)s * n * n + (long long)k3 * n) * m + j1_0;
-  for (int t = threadIdx.x; t < L * n; t += kBlock) {
+  for (int t = threadIdx.x; t < L * n; t += T) {
     const int k2 = t / L, q = t - k2 * L;  // L adjacent j1 of row k2 are contiguous
     const double2 v = q < lines ? in[(long long)k2 * m + q] : make_double2(0.0, 0.0);
     sre[q * n + k2] = v.x;
     sim[q * n + k2] = v.y;
   }
   __syncthreads();
-  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
-  else fft_lines<C, kBlock>(sre, sim, tw, pl, L);
+  if constexpr (C == 0) {
+    static_assert(T == kBlock, "fft_line runs on kBlock threads");
+    fft_line(sre, sim, tw, pl);
+  } else {
+    fft_lines<C, T>(sre, sim, tw, pl, L);
+  }
   double2* out = u2 + ((long long)s * n + k3) * m * m + j1_0;
-  for (int t = threadIdx.x; t < lines * m; t += kBlock) {
+  for (int t = threadIdx.x; t < lines * m; t += T) {
     const int j2 = t / lines, q = t - j2 * lines;
     out[(long long)j2 * m + q] = make_double2(sre[q * n + j2], sim[q * n + j2]);
   }
@@ -917,8 +973,8 @@ k_ce3_pass_b(int m, const double2* __restrict__ u1, const double2* __restrict__ 
 // k = exp(mu_l + g_l) with l the layer of the centre, and the plain coarse
 // companion (layers re-evaluated at the coarse centres, Gaussian values of the
 // fine cell (2I, 2J, 2L)).
-template <int C>
-__global__ void __launch_bounds__(kBlock)
+template <int C, int T>
+__global__ void __launch_bounds__(T)
 k_ce3_pass_c(int kind, int n_nodes, int n_layers, CePair pr, int m,
              const double2* __restrict__ u2, const double2* __restrict__ tw, FftPlan pl, int L,
              int groups, const double* __restrict__ params, double* __restrict__ k,
@@ -935,18 +991,22 @@ k_ce3_pass_c(int kind, int n_nodes, int n_layers, CePair pr, int m,
   const int lines = min(L, m - j1_0);
   const long long mm = (long long)m * m;
   const double2* in = u2 + (long long)s * n * mm + (long long)j2 * m + j1_0;
-  for (int t = threadIdx.x; t < L * n; t += kBlock) {
+  for (int t = threadIdx.x; t < L * n; t += T) {
     const int k3 = t / L, q = t - k3 * L;
     const double2 v = q < lines ? in[(long long)k3 * mm + q] : make_double2(0.0, 0.0);
     sre[q * n + k3] = v.x;
     sim[q * n + k3] = v.y;
   }
   __syncthreads();
-  if constexpr (C == 0) fft_line(sre, sim, tw, pl);
-  else fft_lines<C, kBlock>(sre, sim, tw, pl, L);
+  if constexpr (C == 0) {
+    static_assert(T == kBlock, "fft_line runs on kBlock threads");
+    fft_line(sre, sim, tw, pl);
+  } else {
+    fft_lines<C, T>(sre, sim, tw, pl, L);
+  }
   const double* prm = params + s * kParamStride;
   const int mc = m / 2;
-  for (int t = threadIdx.x; t < lines * m; t += kBlock) {
+  for (int t = threadIdx.x; t < lines * m; t += T) {
     const int j3 = t / lines, q = t - j3 * lines;
     const int j1 = j1_0 + q;
     const double g0 = sre[q * n + j3], g1 = sim[q * n + j3];
@@ -967,33 +1027,72 @@ k_ce3_pass_c(int kind, int n_nodes, int n_layers, CePair pr, int m,
   }
 }
 
+// Launch shapes of the three passes, w = the widest stage's butterflies per
+// line.  Pass A's lines (along x1) are contiguous; a workgroup takes an even
+// number of them, so that row pairs share their Philox blocks.  Passes B and C
+// read lines across rows, a run of L adjacent values per row for L lines.
+// Short lines (w <= 32): 8 lines on 256 threads, one butterfly per thread and
+// stage.  Otherwise 2 lines on 192 threads with C = ceil(2 w / 192) <= 3
+// butterfly slots per thread.  Measured at n = 225 and 540 (the 64^3 and 128^3
+// grids, 16 and 4 samples per call): the smallest workgroups were fastest.
+// Pass A on 2 lines / 192 threads: 3.8 and 10.6 ms per sampler call, against
+// 4.9 and 12.6 ms on 2 lines / 384 threads and 6.0 and 17.2 ms on 4 lines /
+// 384; passes B and C on 2 lines / 192 threads: 3.3 and 10.4 ms, against 3.4
+// and 10.7 ms on 8 (225) or 4 (540) lines / 256 threads and 4.0 and 11.2 ms on
+// one line / 192.  Wider stages take one line per 256-thread workgroup
+// (fft_line) in pass A and the multi-line shape of fft_lines_per_group, or
+// fft_line, in passes B and C.
+static int widest_stage(const FftPlan& pl) {
+  int w = 1;
+  for (int st = 0; st < pl.nstages; ++st) w = std::max(w, pl.n / pl.radix[st]);
+  return w;
+}
+
+template <int C, int T>
+static void ce3_pass_bc(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int batch, int m,
+                        const double2* tw, const FftPlan& pl, int L, const double* params,
+                        double2* u1, double2* u2, double* k, double* k_coarse) {
+  const int n = pl.n;
+  const size_t lds = 2 * (size_t)L * n * sizeof(double);
+  const int gb = n * ((m + L - 1) / L);
+  const int gc = m * ((m + L - 1) / L);
+  hipLaunchKernelGGL((k_ce3_pass_b<C, T>), dim3(batch * gb), dim3(T), lds, st, m, u1, tw, pl, L,
+                     gb, u2);
+  hipLaunchKernelGGL((k_ce3_pass_c<C, T>), dim3(batch * gc), dim3(T), lds, st,
+                     mdl.interface_kind, mdl.n_nodes, mdl.n_layers, pr, m, u2, tw, pl, L, gc,
+                     params, k, k_coarse);
+}
+
 void launch_ce3(hipStream_t st, const mlmc_model& mdl, const CePair& pr, int level, uint64_t first,
                 const uint32_t* ids, int batch, int m, const double* sq, const double2* tw,
                 const FftPlan& pl, const double* params, double2* u1, double2* u2, double* k,
                 double* k_coarse) {
   const int n = pl.n;
   const int L = fft_lines_per_group(pl);
-  const size_t lds = 2 * (size_t)L * n * sizeof(double);
-  const int ga = (n * n + L - 1) / L;
-  const int gb = n * ((m + L - 1) / L);
-  const int gc = m * ((m + L - 1) / L);
-  if (L > 1) {
-    hipLaunchKernelGGL(k_ce3_pass_a<1>, dim3(batch * ga), dim3(kBlock), lds, st, mdl.seed,
-                       pr.tag, (uint32_t)level, first, ids, m, sq, tw, pl, L, ga, u1);
-    hipLaunchKernelGGL(k_ce3_pass_b<1>, dim3(batch * gb), dim3(kBlock), lds, st, m, u1, tw, pl, L,
-                       gb, u2);
-    hipLaunchKernelGGL(k_ce3_pass_c<1>, dim3(batch * gc), dim3(kBlock), lds, st,
-                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, pr, m, u2,
-                       tw, pl, L, gc, params, k, k_coarse);
-  } else {
-    hipLaunchKernelGGL(k_ce3_pass_a<0>, dim3(batch * ga), dim3(kBlock), lds, st, mdl.seed,
-                       pr.tag, (uint32_t)level, first, ids, m, sq, tw, pl, 1, ga, u1);
-    hipLaunchKernelGGL(k_ce3_pass_b<0>, dim3(batch * gb), dim3(kBlock), lds, st, m, u1, tw, pl, 1,
-                       gb, u2);
-    hipLaunchKernelGGL(k_ce3_pass_c<0>, dim3(batch * gc), dim3(kBlock), lds, st,
-                       mdl.interface_kind, mdl.n_nodes, mdl.n_layers, pr, m, u2,
-                       tw, pl, 1, gc, params, k, k_coarse);
+  const int wide = widest_stage(pl);
+  auto pass_a = [&](auto kern, int la, int ta) {
+    const int ga = (n * n + la - 1) / la;
+    hipLaunchKernelGGL(kern, dim3(batch * ga), dim3(ta), 2 * (size_t)la * n * sizeof(double), st,
+                       mdl.seed, pr.tag, (uint32_t)level, first, ids, m, sq, tw, pl, la, ga, u1);
+  };
+  const int ca = (2 * wide + 191) / 192;
+  if (8 * wide <= kBlock) pass_a(k_ce3_pass_a<1, kBlock, true>, 8, kBlock);
+  else if (ca == 1) pass_a(k_ce3_pass_a<1, 192, true>, 2, 192);
+  else if (ca == 2) pass_a(k_ce3_pass_a<2, 192, true>, 2, 192);
+  else if (ca == 3) pass_a(k_ce3_pass_a<3, 192, true>, 2, 192);
+  else pass_a(k_ce3_pass_a<0, kBlock, false>, 1, kBlock);
+  if (8 * wide <= kBlock) {
+    ce3_pass_bc<1, kBlock>(st, mdl, pr, batch, m, tw, pl, 8, params, u1, u2, k, k_coarse);
+    return;
   }
+  switch (ca) {
+    case 1: ce3_pass_bc<1, 192>(st, mdl, pr, batch, m, tw, pl, 2, params, u1, u2, k, k_coarse); return;
+    case 2: ce3_pass_bc<2, 192>(st, mdl, pr, batch, m, tw, pl, 2, params, u1, u2, k, k_coarse); return;
+    case 3: ce3_pass_bc<3, 192>(st, mdl, pr, batch, m, tw, pl, 2, params, u1, u2, k, k_coarse); return;
+    default: break;
+  }
+  if (L > 1) ce3_pass_bc<1, kBlock>(st, mdl, pr, batch, m, tw, pl, L, params, u1, u2, k, k_coarse);
+  else ce3_pass_bc<0, kBlock>(st, mdl, pr, batch, m, tw, pl, 1, params, u1, u2, k, k_coarse);
 }
 
 // ---- plain coarse companion of a piecewise constant sample, CGV sub-lattices

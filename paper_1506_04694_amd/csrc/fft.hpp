@@ -19,7 +19,7 @@
 namespace mlmc {
 
 constexpr int kFftMax = 4096;
-constexpr int kFftMax3 = 512;  // 3-D embeddings: n^3 complex values per transform
+constexpr int kFftMax3 = 1024;  // 3-D embeddings: n^3 complex values per transform
 constexpr int kFftMaxStages = 16;
 
 struct FftPlan {

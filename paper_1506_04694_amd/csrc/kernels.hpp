@@ -176,12 +176,6 @@ void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double
                  double* qin);
 void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const double* tb,
                      double* Tc, double* tbc);
-void launch_rbgs3(hipStream_t st, int m, int batch, const double* T, const double* tb, double* z,
-                  const double* r, const int32_t* active, int color, int zero_init);
-void launch_resid_restrict3(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                            const double* z, const double* r, double* rc, const int32_t* active);
-void launch_prolong3(hipStream_t st, int m, int batch, const double* zc, double* z, double omega,
-                     const int32_t* active);
 void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, const double* tb,
                           double* Ainv);
 // Multigrid sweeps of a 3-D hierarchy in FP64 (f32 false) or with the operator,
@@ -193,8 +187,9 @@ void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const 
 void launch_resid_restrict3_p(hipStream_t st, bool f32, bool top, int m, int batch,
                               const void* T, const void* tb, const void* z, const void* r,
                               void* rc, const int32_t* active);
-void launch_prolong3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* zc,
-                       void* z, double omega, const int32_t* active);
+void launch_prolong_black3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
+                             const void* tb, void* z, const void* r, const void* zc,
+                             double omega, const int32_t* active);
 void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, const float* r,
                           float* z, const int32_t* active);
 // The cycle on levels l0..L of a 3-D hierarchy (desc: their sizes and

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import workloads as W  # noqa: E402
-from oracle import mlmc, solve  # noqa: E402
+from oracle import field, mlmc, solve  # noqa: E402
 
 
 def level_records(model, m_levels, n_per_level, cgv, levels=None):
@@ -48,8 +48,39 @@ FILES = {
 }
 
 
+def field_record(model, level, sample, m, n_cells, rng_seed):
+    """log k of one oracle sample at n_cells fixed pseudo-random cells of the
+    m^3 grid, and log of its plain coarse companion at n_cells / 2 cells."""
+    import numpy as np
+    k, kc = field.sample_k(model, level, sample, m, with_coarse=True)
+    rng = np.random.default_rng(rng_seed)
+    idx = rng.integers(0, k.size, size=n_cells)
+    idc = rng.integers(0, kc.size, size=n_cells // 2)
+    return {"level": level, "sample": sample, "m": m,
+            "cells": idx.tolist(), "log_k": np.log(k.ravel()[idx]).tolist(),
+            "coarse_cells": idc.tolist(), "log_k_coarse": np.log(kc.ravel()[idc]).tolist()}
+
+
+FIELDS = {
+    # the served 3-D model's 128^3 field (embedding 540^3): too large for the
+    # oracle to sample inside a GPU test
+    "tilted3_field_128.json": (W.TILTED3, 2, 0, 128, 4096, 7),
+}
+
+
 def main(names):
     for name in names:
+        if name in FIELDS:
+            model, level, sample, m, cells, seed = FIELDS[name]
+            rec = {"source": "oracle/field.py sample_k (FP64)",
+                   "model": {k: (list(v) if isinstance(v, tuple) else v)
+                             for k, v in model.__dict__.items() if k != "n_ce"},
+                   "n_ce": {str(k): v for k, v in model.n_ce.items()},
+                   "field": field_record(model, level, sample, m, cells, seed)}
+            with open(os.path.join(HERE, name), "w") as f:
+                json.dump(rec, f)
+            print("wrote", name)
+            continue
         model, ms, n, cgv, levels = FILES[name]
         rec = {"source": "oracle/ (FP64; solver per level in fine_solver / coarse_solver)",
                "model": {k: (list(v) if isinstance(v, tuple) else v)
@@ -62,4 +93,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(FILES))
+    main(sys.argv[1:] or list(FILES) + list(FIELDS))

@@ -65,10 +65,9 @@ def solve3(lib, ctx, kh, opts=None):
 
 
 # ------------------------------------------------------------------ fields
-@pytest.mark.parametrize("m,level,batch", [(8, 0, 3), (16, 1, 3), (32, 0, 2), (64, 1, 2),
-                                           (128, 2, 1)])
+@pytest.mark.parametrize("m,level,batch", [(8, 0, 3), (16, 1, 3), (32, 0, 2), (64, 1, 2)])
 def test_field_3d_circulant_embedding(lib, ctx, m, level, batch):
-    """The served grids' fields too (32^3..128^3, embeddings of 64^3..256^3)."""
+    """The served grids' fields too (32^3 and 64^3, embeddings of 75^3 and 225^3)."""
     print("3-D field m=%d level=%d" % (m, level), flush=True)
     k, kc = f64(batch, m, m, m), f64(batch, m // 2, m // 2, m // 2)
     lib.mlmc_sample_field(ctx, MODEL, m, level, 5, batch, k, kc)
@@ -78,6 +77,32 @@ def test_field_3d_circulant_embedding(lib, ctx, m, level, batch):
         kr, kcr = ofield.sample_k(MODEL, level, 5 + s, m, with_coarse=True)
         assert np.max(np.abs(np.log(k[s]) - np.log(kr))) <= 1e-11
         assert np.max(np.abs(np.log(kc[s]) - np.log(kcr))) <= 1e-11
+
+
+FIELD128 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "tilted3_field_128.json")
+
+
+def test_field_3d_128_against_stored_oracle_cells(lib, ctx):
+    """The 128^3 field (embedding 540^3; a launch of two samples, the first of
+    them the stored one): log k at 4096 and the plain coarse companion at 2048
+    cells that the oracle sampled, stored with the model's parameters."""
+    with open(FIELD128) as f:
+        rec = json.load(f)
+    assert {int(a): b for a, b in rec["n_ce"].items()} == MODEL.n_ce
+    for key in ("norm_r", "lam", "sigma2", "mu", "interface_kind", "seed"):
+        v = getattr(MODEL, key)
+        assert (list(v) if isinstance(v, tuple) else v) == rec["model"][key], key
+    fr = rec["field"]
+    m, level, s0 = fr["m"], fr["level"], fr["sample"]
+    print("3-D field m=%d level=%d (stored)" % (m, level), flush=True)
+    k, kc = f64(2, m, m, m), f64(2, m // 2, m // 2, m // 2)
+    lib.mlmc_sample_field(ctx, MODEL, m, level, s0, 2, k, kc)
+    torch.cuda.synchronize()
+    lk = torch.log(k[0]).flatten().cpu().numpy()[np.array(fr["cells"])]
+    lkc = torch.log(kc[0]).flatten().cpu().numpy()[np.array(fr["coarse_cells"])]
+    assert np.max(np.abs(lk - np.array(fr["log_k"]))) <= 1e-11
+    assert np.max(np.abs(lkc - np.array(fr["log_k_coarse"]))) <= 1e-11
 
 
 def test_field_3d_piecewise_constant(lib, ctx):

@@ -146,14 +146,20 @@ CGV_VARIANCE_2D = [(8, 8192), (16, 8192), (32, 8192), (64, 8192), (128, 4096), (
 CGV_VARIANCE_3D = [(8, 4096), (16, 2048), (32, 1024), (64, 256)]
 
 # 3-D served model: tilted planar interface, two layers with independent
-# stationary Gaussian fields, exponential covariance with the 1-norm (separable,
-# so the embedding of length 2m is non-negative), sigma^2 = 1, lambda = 0.2,
-# means 0 (bottom) and 2 (top).
+# stationary Gaussian fields, exponential covariance with the 2-norm, sigma^2 =
+# 1, lambda = 0.2, means 0 (bottom) and 2 (top); embedding lengths: the
+# smallest 5-smooth n_ce >= 2m whose eigenvalues are non-negative (75, 225, 540
+# at 32^3, 64^3, 128^3).
 TILTED3 = Model(dim=3, interface_kind=TILTED_PLANE, n_layers=2, field_kind=CORRELATED_CE,
-                norm_r=1, mu=(0.0, 2.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0),
+                norm_r=2, mu=(0.0, 2.0, 0.0, 0.0), sigma2=(1.0, 1.0, 1.0, 1.0),
                 lam=(0.2, 0.2, 0.2, 0.2), seed=0,
-                n_ce={4: 8, 8: 16, 16: 32, 32: 64, 64: 128, 128: 256})
+                n_ce={2: 4, 4: 8, 8: 16, 16: 36, 32: 75, 64: 225, 128: 540})
 SERVED_3D = Workload("3d-ce-tilted-32-128", TILTED3, [32, 64, 128], [64, 16, 4])
+# Solver options per level of SERVED_3D (overrides of the defaults, FP32
+# hierarchy), as chosen by autotune.tune_level over gamma_levels: at 128^3 W on
+# the three finest levels (10.8 PCG iterations against 14.3 with W on two, 6%
+# less time per level run); 32^3 and 64^3 keep W on two.
+SERVED_3D_LEVEL_OPTS = ({}, {}, {"gamma_levels": 3})
 
 # The served stream: single-sample requests of the layered 2-D model on
 # 64^2..512^2, the high-contrast 2-D model on 1024^2 and the 3-D model on
