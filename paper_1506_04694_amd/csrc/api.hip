@@ -667,8 +667,13 @@ mlmc_status mlmc_qoi_outflow(mlmc_ctx* ctx, int dim, int m, int batch, const dou
     return fail(ctx, MLMC_EINVAL, "bad arguments to mlmc_qoi_outflow");
   if (batch == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
-  if (dim == 3) launch_qoi3(ctx->stream, m, batch, k, p, q_out, q_in);
-  else launch_qoi(ctx->stream, m, batch, k, p, q_out, q_in);
+  if (dim == 3) {
+    double* part = nullptr;
+    TRY(ws(ctx, "qoi3_parts", qoi3_parts_size(batch), &part));
+    launch_qoi3(ctx->stream, m, batch, k, p, part, q_out, q_in);
+  } else {
+    launch_qoi(ctx->stream, m, batch, k, p, q_out, q_in);
+  }
   CHECK_LAUNCH();
   return MLMC_OK;
 }
@@ -814,9 +819,13 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
       sweep(1, 0);
     }
     for (int visit = 0; visit < visits(l); ++visit) {
+      // a later visit's pre-smoothing starts with the red half-sweep that
+      // ended the post-smoothing before it: the red values depend only on the
+      // (unchanged) black ones, so it would rewrite them bit for bit, and is
+      // skipped
       if (visit > 0)
         for (int it = 0; it < nu; ++it) {
-          sweep(0, 0);
+          if (it > 0) sweep(0, 0);
           sweep(1, 0);
         }
       launch_resid_restrict3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], rh[l + 1],

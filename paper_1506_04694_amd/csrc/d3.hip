@@ -183,20 +183,45 @@ void launch_assemble3(hipStream_t st, int problem, int m, int batch, const doubl
 // ------------------------------------------------------------------ QoI
 // Q_out = sum over the x1 = 1 faces of 2 k h p, Q_in = sum over x1 = 0 of
 // 2 k h (1 - p); one wave per sample, fixed-order sums.
-__global__ void k_qoi3(int m, int batch, const double* __restrict__ k, const double* __restrict__ p,
-                       double* __restrict__ qout, double* __restrict__ qin) {
-  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  if (wave >= batch) return;
+// Outflow (and inflow) of each sample in two steps: kQoi3Parts workgroups per
+// sample sum fixed, contiguous ranges of the m^2 boundary rows (q = l m + j)
+// into partials; one wave per sample adds its partials in order.  The sums do
+// not depend on the launch's timing.
+constexpr int kQoi3Parts = 32;
+__global__ void k_qoi3_parts(int m, int batch, const double* __restrict__ k,
+                             const double* __restrict__ p, double* __restrict__ part) {
+  const int s = blockIdx.x / kQoi3Parts;
+  const int g = blockIdx.x - s * kQoi3Parts;
+  if (s >= batch) return;
   const long long n = (long long)m * m * m;
-  const long long base = wave * n;
+  const long long base = (long long)s * n;
   const double h = 1.0 / (double)m;
+  const int rows = m * m;
+  const int per = (rows + kQoi3Parts - 1) / kQoi3Parts;
+  const int q0 = g * per, q1 = min(rows, q0 + per);
   double so = 0.0, si = 0.0;
-  for (int q = lane; q < m * m; q += kWave) {
-    const long long row = base + (long long)q * m;  // q = l m + j
+  for (int q = q0 + threadIdx.x; q < q1; q += kBlock) {
+    const long long row = base + (long long)q * m;
     so += 2.0 * k[row + m - 1] * h * p[row + m - 1];
     si += 2.0 * k[row] * h * (1.0 - p[row]);
   }
+  __shared__ double sho[kBlock / kWave], shi[kBlock / kWave];
+  so = block_sum(so, sho);
+  si = block_sum(si, shi);
+  if (threadIdx.x == 0) {
+    part[2 * (long long)blockIdx.x] = so;
+    part[2 * (long long)blockIdx.x + 1] = si;
+  }
+}
+
+__global__ void k_qoi3_final(int batch, const double* __restrict__ part, double* __restrict__ qout,
+                             double* __restrict__ qin) {
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (wave >= batch) return;
+  const double* ps = part + 2 * wave * kQoi3Parts;
+  double so = lane < kQoi3Parts ? ps[2 * lane] : 0.0;
+  double si = lane < kQoi3Parts ? ps[2 * lane + 1] : 0.0;
   so = wave_sum(so);
   si = wave_sum(si);
   if (lane == 0) {
@@ -205,11 +230,15 @@ __global__ void k_qoi3(int m, int batch, const double* __restrict__ k, const dou
   }
 }
 
-void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double* p, double* qout,
-                 double* qin) {
+size_t qoi3_parts_size(int batch) { return (size_t)batch * kQoi3Parts * 2; }
+
+void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double* p, double* part,
+                 double* qout, double* qin) {
+  hipLaunchKernelGGL(k_qoi3_parts, dim3(batch * kQoi3Parts), dim3(kBlock), 0, st, m, batch, k, p,
+                     part);
   const long long threads = (long long)batch * kWave;
-  hipLaunchKernelGGL(k_qoi3, dim3(blocks_for(threads)), dim3(kBlock), 0, st, m, batch, k, p, qout,
-                     qin);
+  hipLaunchKernelGGL(k_qoi3_final, dim3(blocks_for(threads)), dim3(kBlock), 0, st, batch, part,
+                     qout, qin);
 }
 
 // ------------------------------------------------------------------ hierarchy
@@ -664,14 +693,17 @@ void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nle
 
 // ------------------------------------------------------------------ coarsest grid
 // Explicit inverse of each sample's coarsest matrix (n = m^3 <= 64) by
-// Gauss-Jordan elimination without pivoting (SPD), as in 2-D.
-// 256 threads per sample: each elimination step updates n^2 <= 4096 entries.
+// Gauss-Jordan elimination without pivoting (SPD), as in 2-D.  256 threads
+// per sample; thread t holds column j = t mod n of the rows t / n + q P
+// (P = 256 / n rows per pass, at most 16 entries) in registers.  Step k
+// publishes column k and the scaled pivot row in LDS, then every thread
+// updates its entries: no index division inside the elimination.
 constexpr int kDenseThreads3 = 256;
 __global__ void __launch_bounds__(kDenseThreads3)
 k_dense_factor3(int m, int batch, const double* __restrict__ T, const double* __restrict__ tb,
                 double* __restrict__ Ainv) {
   __shared__ double A[64 * 64];
-  __shared__ double col[64];
+  __shared__ double col[64], prow[64];
   const int s = blockIdx.x;
   if (s >= batch) return;
   const int n = m * m * m, mm = m * m;
@@ -689,21 +721,52 @@ k_dense_factor3(int m, int batch, const double* __restrict__ T, const double* __
     if (l < m - 1) A[c * n + c + mm] = A[(c + mm) * n + c] = -f.tu;
   }
   __syncthreads();
+  constexpr int kMaxRows = 16;
+  const int P = kDenseThreads3 / n;                   // rows per pass (n <= 64: P >= 4)
+  const int t = threadIdx.x;
+  const bool on = t < P * n;
+  const int j = on ? t % n : 0, i0 = on ? t / n : 0;
+  double a[kMaxRows];
+#pragma unroll
+  for (int q = 0; q < kMaxRows; ++q) {
+    const int i = i0 + q * P;
+    a[q] = (on && i < n) ? A[i * n + j] : 0.0;
+  }
   for (int k = 0; k < n; ++k) {
-    for (int i = threadIdx.x; i < n; i += kDenseThreads3) col[i] = A[i * n + k];
+    // column k of the current matrix
+    if (on && j == k) {
+#pragma unroll
+      for (int q = 0; q < kMaxRows; ++q)
+        if (i0 + q * P < n) col[i0 + q * P] = a[q];
+    }
     __syncthreads();
     const double piv = col[k];
-    for (int j = threadIdx.x; j < n; j += kDenseThreads3)
-      A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) / piv;
+    // row k divided by the pivot (its column-k entry becomes 1 / piv)
+    if (on && i0 == k % P) {
+      const int q = k / P;
+#pragma unroll
+      for (int qq = 0; qq < kMaxRows; ++qq)
+        if (qq == q) prow[j] = (j == k ? 1.0 : a[qq]) / piv;
+    }
     __syncthreads();
-    for (int q = threadIdx.x; q < n * n; q += kDenseThreads3) {
-      const int i = q / n, j = q - i * n;
-      if (i != k) A[q] = (j == k ? 0.0 : A[q]) - col[i] * A[k * n + j];
+    if (on) {
+      const double pk = prow[j];
+#pragma unroll
+      for (int q = 0; q < kMaxRows; ++q) {
+        const int i = i0 + q * P;
+        if (i < n) a[q] = i == k ? pk : (j == k ? 0.0 : a[q]) - col[i] * pk;
+      }
     }
     __syncthreads();
   }
   double* X = Ainv + (long long)s * n * n;
-  for (int q = threadIdx.x; q < n * n; q += kDenseThreads3) X[q] = A[q];
+  if (on) {
+#pragma unroll
+    for (int q = 0; q < kMaxRows; ++q) {
+      const int i = i0 + q * P;
+      if (i < n) X[i * n + j] = a[q];
+    }
+  }
 }
 
 void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, const double* tb,

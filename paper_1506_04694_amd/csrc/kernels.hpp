@@ -172,8 +172,9 @@ inline int blocks_per_sample(long long n) { return (int)((n + kCellsPerBlock - 1
 // bottom faces), k, b, x [s][m^3] with x1 fastest.
 void launch_assemble3(hipStream_t st, int problem, int m, int batch, const double* k, double* T,
                       double* tb, double* b);
-void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double* p, double* qout,
-                 double* qin);
+size_t qoi3_parts_size(int batch);  // doubles of the partials buffer
+void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double* p, double* part,
+                 double* qout, double* qin);
 void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const double* tb,
                      double* Tc, double* tbc);
 void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, const double* tb,
