@@ -79,6 +79,8 @@ struct mlmc_ctx {
   std::map<std::string, std::pair<size_t, size_t>> arena_names;  // name -> (offset, bytes)
   // mlmc_run_levels: one sub-context per level (own stream, own workspaces)
   std::vector<mlmc_ctx*> subs;
+  // 3-D level runs: sub-context the coarse companions are solved on
+  mlmc_ctx* comp = nullptr;
   bool owns_stream = false;
 };
 
@@ -107,6 +109,13 @@ mlmc_status fail(mlmc_ctx* ctx, mlmc_status code, const std::string& msg) {
     hipError_t e_ = hipGetLastError();                                                 \
     if (e_ != hipSuccess)                                                              \
       return fail(ctx, MLMC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHECK_LAUNCH_CTX(c)                                                            \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess)                                                              \
+      return fail((c), MLMC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
   } while (0)
 
 // Grow-only named device workspace.
@@ -438,6 +447,7 @@ mlmc_status mlmc_ctx_destroy(mlmc_ctx* ctx) {
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   for (mlmc_ctx* sub : ctx->subs) (void)mlmc_ctx_destroy(sub);
+  if (ctx->comp) (void)mlmc_ctx_destroy(ctx->comp);
   if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return MLMC_OK;
@@ -760,18 +770,6 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   TRY(ws(ctx, "s3_count", 1, &S.count));
   int32_t* carried = nullptr;  // iterations of a W pass whose sample restarts with V
   if (opts->gamma == 2) TRY(ws(ctx, "s3_carried", batch, &carried));
-  // every workspace is in hand: the hierarchy's set-up launches
-  for (int l = 1; l <= L; ++l)
-    launch_coarsen3(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tw[l], tbw[l]);
-  launch_dense_factor3(st, ms[L], batch, Tl[L], tbl[L], Ainv);
-  if (f32)
-    for (int l = 0; l <= L; ++l) {
-      const long long nl = (long long)ms[l] * ms[l] * ms[l];
-      const long long fl = (long long)ms[l] * ms[l];
-      launch_convert(st, MLMC_PREC_FP32, batch * 3 * nl, Tl[l], const_cast<void*>(Th[l]));
-      launch_convert(st, MLMC_PREC_FP32, batch * 3 * fl, tbl[l], const_cast<void*>(tbh[l]));
-    }
-  CHECK_LAUNCH();
   const int nu = opts->nu1;
   const double omega = opts->omega;
   int cur_gamma = opts->gamma;
@@ -788,19 +786,37 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
         l0 = l;
         break;
       }
-  if (l0 >= 0)
+  void* cimg = nullptr;  // padded operator image of the in-LDS levels
+  if (l0 >= 0) {
     for (int q2 = 0; l0 + q2 <= L; ++q2) {
       cdesc.m[q2] = ms[l0 + q2];
       cdesc.T[q2] = Th[l0 + q2];
       cdesc.tb[q2] = tbh[l0 + q2];
     }
+    const size_t words = (size_t)coarse3_image_words(L - l0 + 1, cdesc.m);
+    TRY(ws_get(ctx, "s3_cimg", (size_t)batch * words * (f32 ? sizeof(float) : sizeof(double)),
+               &cimg));
+  }
+  // every workspace is in hand: the hierarchy's set-up launches
+  for (int l = 1; l <= L; ++l)
+    launch_coarsen3(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tw[l], tbw[l]);
+  launch_dense_factor3(st, ms[L], batch, Tl[L], tbl[L], Ainv);
+  if (f32)
+    for (int l = 0; l <= L; ++l) {
+      const long long nl = (long long)ms[l] * ms[l] * ms[l];
+      const long long fl = (long long)ms[l] * ms[l];
+      launch_convert(st, MLMC_PREC_FP32, batch * 3 * nl, Tl[l], const_cast<void*>(Th[l]));
+      launch_convert(st, MLMC_PREC_FP32, batch * 3 * fl, tbl[l], const_cast<void*>(tbh[l]));
+    }
+  if (l0 >= 0) launch_coarse3_image(st, f32, batch, L - l0 + 1, cdesc, cimg);
+  CHECK_LAUNCH();
   std::function<void(int)> cycle = [&](int l) {
     if (l == l0) {
       unsigned wmask = 0;
       for (int q2 = 0; l0 + q2 < L; ++q2)
         if (visits(l0 + q2) == 2) wmask |= 1u << q2;
-      launch_coarse3_cycle(st, f32, l0 == 0, batch, L - l0 + 1, cdesc, rh[l0], zh[l0], Ainv, omega,
-                           wmask, S.active);
+      launch_coarse3_cycle(st, f32, l0 == 0, batch, L - l0 + 1, cdesc, cimg, rh[l0], zh[l0], Ainv,
+                           omega, wmask, S.active);
       return;
     }
     if (l == L) {
@@ -1440,17 +1456,26 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
                         (ncomp == 1) ? kc : nullptr));
   if (ncomp > 1) TRY(mlmc_cgv_extract(ctx, d, m, n, k, kc));
 
-  // The companions are solved first: in 2-D the fine solve then starts from
-  // the solution of each sample's first companion, injected to the fine cells
-  // (about one CG iteration fewer; same stopping rule ||r||/||b|| < tol).
+  // In 2-D the companions are solved first and the fine solve starts from the
+  // solution of each sample's first companion, injected to the fine cells
+  // (about one CG iteration fewer; same stopping rule ||r||/||b|| < tol).  In
+  // 3-D the fine solve starts from zero, so the companions (assembly, solve,
+  // QoI) run beside it on a sub-context of their own (own stream, workspaces
+  // and host thread): the coarse grid's latency-bound launches fill the
+  // device while the fine grid's run.  The kernels and their inputs are the
+  // same either way, so are the results, bit for bit.
   mlmc_solver_opts zero_guess = *opts;
   zero_guess.initial_guess = 0;
   double* qcv = nullptr;
   double* pc = nullptr;
   int32_t *stc = nullptr, *itc = nullptr;
+  const bool beside = d == 3 && ncomp > 0;
+  std::thread comp_thread;
+  mlmc_status comp_rc = MLMC_OK;
+  hipEvent_t comp_start = nullptr, comp_done = nullptr;
   if (ncomp > 0) {
     const int nb = n * ncomp;
-    double *Tc, *tbc, *bc, *qcomp;
+    double *Tc, *tbc, *bc, *qcomp, *relres_c;
     TRY(ws(ctx, "lr_Tc", (size_t)nb * d * ncl, &Tc));
     TRY(ws(ctx, "lr_tbc", (size_t)nb * d * cface, &tbc));
     TRY(ws(ctx, "lr_bc", (size_t)nb * ncl, &bc));
@@ -1459,11 +1484,56 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
     TRY(ws(ctx, "lr_qc", n, &qcv));
     TRY(ws(ctx, "lr_stc", nb, &stc));
     TRY(ws(ctx, "lr_itc", nb, &itc));
-    TRY(mlmc_assemble_problem(ctx, model->problem, d, mc, nb, kc, Tc, tbc, bc));
-    TRY(mlmc_solve(ctx, d, mc, nb, Tc, tbc, bc, pc, &zero_guess, stc, itc, relres));
-    TRY(model_qoi(ctx, model, d, mc, nb, kc, pc, qcomp));
-    launch_cgv_average(st, n, ncomp, qcomp, qcv);
+    TRY(ws(ctx, "lr_relres_c", nb, &relres_c));
+    auto companions = [=, &zero_guess](mlmc_ctx* cc) -> mlmc_status {
+      TRY(mlmc_assemble_problem(cc, model->problem, d, mc, nb, kc, Tc, tbc, bc));
+      TRY(mlmc_solve(cc, d, mc, nb, Tc, tbc, bc, pc, &zero_guess, stc, itc, relres_c));
+      TRY(model_qoi(cc, model, d, mc, nb, kc, pc, qcomp));
+      launch_cgv_average(cc->stream, n, ncomp, qcomp, qcv);
+      CHECK_LAUNCH_CTX(cc);
+      return MLMC_OK;
+    };
+    if (beside) {
+      if (!ctx->comp) {
+        hipStream_t cst = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&cst, hipStreamNonBlocking));
+        const mlmc_status rc = mlmc_ctx_create(ctx->device, cst, &ctx->comp);
+        if (rc != MLMC_OK) {
+          (void)hipStreamDestroy(cst);
+          return fail(ctx, rc, "could not create the companion context");
+        }
+        ctx->comp->owns_stream = true;
+      }
+      mlmc_ctx* cc = ctx->comp;
+      comp_start = pool_event(ctx);
+      comp_done = pool_event(ctx);
+      HIP_TRY(hipEventRecord(comp_start, st));  // k and the companions' k are sampled
+      HIP_TRY(hipStreamWaitEvent(cc->stream, comp_start, 0));
+      mlmc_status* rc_out = &comp_rc;
+      const hipEvent_t done = comp_done;
+      comp_thread = std::thread([companions, cc, rc_out, done] {
+        (void)hipSetDevice(cc->device);
+        mlmc_status rc = companions(cc);
+        if (rc == MLMC_OK && hipEventRecord(done, cc->stream) != hipSuccess)
+          rc = fail(cc, MLMC_EDEVICE, "hipEventRecord failed");
+        *rc_out = rc;
+      });
+    } else {
+      TRY(companions(ctx));
+    }
   }
+  // joins the companion thread on every path out of here, then returns the
+  // events to the pool
+  struct Joiner {
+    std::thread& t;
+    mlmc_ctx* ctx;
+    hipEvent_t a, b;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+      if (a) ctx->event_pool.push_back(a);
+      if (b) ctx->event_pool.push_back(b);
+    }
+  } joiner{comp_thread, ctx, comp_start, comp_done};
   TRY(mlmc_assemble_problem(ctx, model->problem, d, m, n, k, T, tb, b));
   mlmc_solver_opts fine = zero_guess;
   if (d == 2 && ncomp > 0) {
@@ -1472,6 +1542,12 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
   }
   TRY(mlmc_solve(ctx, d, m, n, T, tb, b, p, &fine, stf, itf, relres));
   TRY(model_qoi(ctx, model, d, m, n, k, p, qf));
+  if (beside) {
+    comp_thread.join();
+    if (comp_rc != MLMC_OK)
+      return fail(ctx, comp_rc, std::string("companion solves: ") + mlmc_last_error(ctx->comp));
+    HIP_TRY(hipStreamWaitEvent(st, comp_done, 0));
+  }
   launch_y_and_fail(st, n, qf, qcv, stf, stc, ncomp, yv, failed);
   launch_level_reduce(st, n, yv, qf, qcv, failed, itf, itc, ncomp, out);
   if (q_f) HIP_TRY(hipMemcpyAsync(q_f, qf, sizeof(double) * n, hipMemcpyDeviceToDevice, st));

@@ -533,11 +533,63 @@ __device__ void c3_sweep(E* a, int m, int P, int color, bool zero) {
   __syncthreads();
 }
 
+// Padded operator image of the in-LDS levels, built once per solve: per
+// sample and level q the arrays te, tn, tu of the kernel's LDS layout ((m + 2)^3
+// words each, boundary faces on the ring, zeros elsewhere), so that each cycle
+// launch copies them linearly instead of gathering from the hierarchy.
+int coarse3_image_words(int nlev, const int* ms) {
+  int w = 0;
+  for (int q = 0; q < nlev; ++q) w += 3 * (ms[q] + 2) * (ms[q] + 2) * (ms[q] + 2);
+  return w;
+}
+
+template <class S, class E>
+__global__ void k_coarse3_image(int nlev, CoarseDesc desc, long long total, int words,
+                                E* __restrict__ img) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long s = g / words;
+  int w = (int)(g - s * words);
+  int q = 0, P = desc.m[0] + 2;
+  while (w >= 3 * P * P * P) {
+    w -= 3 * P * P * P;
+    ++q;
+    P = desc.m[q] + 2;
+  }
+  const int m = desc.m[q], PPP = P * P * P, mm = m * m;
+  const int arr = w / PPP, f = w - arr * PPP;
+  const int row = f / P, lp = row / P;  // row = (l + 1) P + (j + 1)
+  const int i = f - row * P - 1, j = row - lp * P - 1, l = lp - 1;
+  const bool ii = i >= 0 && i < m, jj = j >= 0 && j < m, ll = l >= 0 && l < m;
+  const long long n = (long long)mm * m;
+  const long long c = ((long long)l * m + j) * m + i;
+  const S* Ts = static_cast<const S*>(desc.T[q]) + s * 3 * n;
+  const S* tbs = static_cast<const S*>(desc.tb[q]) + s * 3 * mm;
+  E v = E(0);
+  if (arr == 0 && jj && ll) v = i == -1 ? (E)tbs[l * m + j] : (ii ? (E)Ts[c] : E(0));
+  if (arr == 1 && ii && ll) v = j == -1 ? (E)tbs[mm + l * m + i] : (jj ? (E)Ts[n + c] : E(0));
+  if (arr == 2 && ii && jj) v = l == -1 ? (E)tbs[2 * mm + j * m + i] : (ll ? (E)Ts[2 * n + c] : E(0));
+  img[g] = v;
+}
+
+void launch_coarse3_image(hipStream_t st, bool f32, int batch, int nlev, const CoarseDesc& desc,
+                          void* img) {
+  const int words = coarse3_image_words(nlev, desc.m);
+  const long long total = (long long)batch * words;
+  if (f32)
+    hipLaunchKernelGGL((k_coarse3_image<float, float>), dim3(blocks_for(total)), dim3(kBlock), 0,
+                       st, nlev, desc, total, words, (float*)img);
+  else
+    hipLaunchKernelGGL((k_coarse3_image<double, double>), dim3(blocks_for(total)), dim3(kBlock),
+                       0, st, nlev, desc, total, words, (double*)img);
+}
+
 // S: storage type of the hierarchy; V: type of the first level's r and z;
 // E: LDS and arithmetic type.
 template <class S, class V, class E>
 __global__ void __launch_bounds__(Lds3Cfg<E>::kThreads)
-k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restrict__ z0,
+k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_words,
+                const V* __restrict__ r0, V* __restrict__ z0,
                 const double* __restrict__ Ainv, double omega, unsigned wmask,
                 const int32_t* __restrict__ active) {
   constexpr int NT = Lds3Cfg<E>::kThreads;
@@ -553,27 +605,26 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
     off += 5 * lv[q].P * lv[q].P * lv[q].P;
   }
   E* vec = lds + off;  // coarsest right-hand side
+  // operators from the image (linear copy), r and z zero, r of the first level
+  // from r0
+  const E* im = img + (long long)s * img_words;
   for (int q = 0; q < nlev; ++q) {
-    const int m = lv[q].m, P = lv[q].P, PPP = P * P * P, mm = m * m;
+    const int P = lv[q].P, PPP = P * P * P;
     E* a = lds + lv[q].off;
-    const long long n = (long long)mm * m;
-    const S* Ts = static_cast<const S*>(desc.T[q]) + (long long)s * 3 * n;
-    const S* tbs = static_cast<const S*>(desc.tb[q]) + (long long)s * 3 * mm;
-    const float inv_P = 1.0f / (float)P;
-    for (int f = threadIdx.x; f < PPP; f += NT) {
-      const int row = div_small(f, inv_P), lp = div_small(row, inv_P);  // row = (l+1) P + (j+1)
-      const int i = f - row * P - 1, j = row - lp * P - 1, l = lp - 1;
-      const bool ii = i >= 0 && i < m, jj = j >= 0 && j < m, ll = l >= 0 && l < m;
-      const long long c = ((long long)l * m + j) * m + i;
-      E te = E(0), tn = E(0), tu = E(0);
-      if (jj && ll) te = i == -1 ? (E)tbs[l * m + j] : (ii ? (E)Ts[c] : E(0));
-      if (ii && ll) tn = j == -1 ? (E)tbs[mm + l * m + i] : (jj ? (E)Ts[n + c] : E(0));
-      if (ii && jj) tu = l == -1 ? (E)tbs[2 * mm + j * m + i] : (ll ? (E)Ts[2 * n + c] : E(0));
-      a[f] = te;
-      a[PPP + f] = tn;
-      a[2 * PPP + f] = tu;
-      a[3 * PPP + f] = (q == 0 && ii && jj && ll) ? (E)r0[(long long)s * n + c] : E(0);
-      a[4 * PPP + f] = E(0);
+    for (int w = threadIdx.x; w < 3 * PPP; w += NT) a[w] = im[w];
+    for (int w = threadIdx.x; w < 2 * PPP; w += NT) a[3 * PPP + w] = E(0);
+    im += 3 * PPP;
+  }
+  __syncthreads();
+  {
+    const int m = lv[0].m, P = lv[0].P, PPP = P * P * P;
+    E* rr = lds + lv[0].off + 3 * PPP;
+    const long long n = (long long)m * m * m;
+    const float inv_m = 1.0f / (float)m;
+    for (int c = threadIdx.x; c < n; c += NT) {
+      const int row = div_small(c, inv_m), i = c - row * m;  // row = l m + j
+      const int l = div_small(row, inv_m), j = row - l * m;
+      rr[pidx3(P, i, j, l)] = (E)r0[(long long)s * n + c];
     }
   }
   __syncthreads();
@@ -675,20 +726,22 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const V* __restrict__ r0, V* __restri
 int coarse3_max_side(bool f32) { return f32 ? Lds3Cfg<float>::kMax : Lds3Cfg<double>::kMax; }
 
 void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nlev,
-                          const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
-                          double omega, unsigned wmask, const int32_t* active) {
+                          const CoarseDesc& desc, const void* img, const void* r0, void* z0,
+                          const double* Ainv, double omega, unsigned wmask,
+                          const int32_t* active) {
+  const int words = coarse3_image_words(nlev, desc.m);
   if (!f32)
     hipLaunchKernelGGL((k_coarse3_cycle<double, double, double>), dim3(batch),
-                       dim3(Lds3Cfg<double>::kThreads), 0, st, nlev, desc, (const double*)r0,
-                       (double*)z0, Ainv, omega, wmask, active);
+                       dim3(Lds3Cfg<double>::kThreads), 0, st, nlev, desc, (const double*)img,
+                       words, (const double*)r0, (double*)z0, Ainv, omega, wmask, active);
   else if (top)
     hipLaunchKernelGGL((k_coarse3_cycle<float, double, float>), dim3(batch),
-                       dim3(Lds3Cfg<float>::kThreads), 0, st, nlev, desc, (const double*)r0,
-                       (double*)z0, Ainv, omega, wmask, active);
+                       dim3(Lds3Cfg<float>::kThreads), 0, st, nlev, desc, (const float*)img,
+                       words, (const double*)r0, (double*)z0, Ainv, omega, wmask, active);
   else
     hipLaunchKernelGGL((k_coarse3_cycle<float, float, float>), dim3(batch),
-                       dim3(Lds3Cfg<float>::kThreads), 0, st, nlev, desc, (const float*)r0,
-                       (float*)z0, Ainv, omega, wmask, active);
+                       dim3(Lds3Cfg<float>::kThreads), 0, st, nlev, desc, (const float*)img,
+                       words, (const float*)r0, (float*)z0, Ainv, omega, wmask, active);
 }
 
 // ------------------------------------------------------------------ coarsest grid

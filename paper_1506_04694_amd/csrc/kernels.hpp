@@ -198,9 +198,13 @@ void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, 
 // workgroup per sample; wmask bit q: level l0 + q takes two coarse visits.
 // r0, z0: the vectors of level l0.
 int coarse3_max_side(bool f32);
+int coarse3_image_words(int nlev, const int* ms);  // words per sample
+void launch_coarse3_image(hipStream_t st, bool f32, int batch, int nlev, const CoarseDesc& desc,
+                          void* img);
 void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nlev,
-                          const CoarseDesc& desc, const void* r0, void* z0, const double* Ainv,
-                          double omega, unsigned wmask, const int32_t* active);
+                          const CoarseDesc& desc, const void* img, const void* r0, void* z0,
+                          const double* Ainv, double omega, unsigned wmask,
+                          const int32_t* active);
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                       const double* p, double* q, double* partial, int bps, const int32_t* active);
 void launch_true_residual3(hipStream_t st, int m, int batch, const double* T, const double* tb,
