@@ -57,6 +57,8 @@ def parse():
                     help="run the levels of a step at once (own streams and host threads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--served-3d-only", action="store_true",
+                    help="only time the served 3-D model's level runs (served_3d) and print them")
     return ap.parse_args()
 
 
@@ -463,7 +465,29 @@ def served_3d(lib, torch, ctx, steps):
                 ts.append(time.perf_counter() - t0)
         row["sampler_ms"] = 1e3 * sorted(ts)[len(ts) // 2]
         out.append(row)
-    return {"workload": wl.name, "per_level": out}
+    # roofline of the fine grid's red-black half-sweep (the 3-D path's largest
+    # kernel by time) in one more 128^3 level run, FP32 hierarchy: algorithmic
+    # bytes (every face, r of the swept colour, z of both colours once, scaled
+    # by the share of samples still iterating) over its event-timed launches
+    level = len(wl.m_levels) - 1
+    m, n = wl.m_levels[level], wl.n_samples[level]
+    o = lib.mlmc_solver_opts_default(precision=lib.MLMC_PREC_FP32)
+    for key, v in W.SERVED_3D_LEVEL_OPTS[level].items():
+        setattr(o, key, v)
+    lib.mlmc_profile_enable(ctx, "k_rbgs3@0")
+    lib.mlmc_level_run(ctx, wl.model, level, m, 0, n, False, o)
+    torch.cuda.synchronize()
+    pr = lib.mlmc_profile_read(ctx)
+    lib.mlmc_profile_enable(ctx, None)
+    roof = None
+    if pr["launches"] > 0 and pr["total_ms"] > 0:
+        ach = pr["algorithmic_bytes"] / (pr["total_ms"] * 1e-3) / 1e9
+        roof = {"kernel": "k_rbgs3@0", "grid": "%d^3 x %d, FP32 hierarchy" % (m, n),
+                "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "launches": pr["launches"],
+                "avg_launch_ms": pr["total_ms"] / pr["launches"],
+                "algorithmic_bytes_per_launch": pr["algorithmic_bytes"] / pr["launches"]}
+    return {"workload": wl.name, "per_level": out, "roofline": roof}
 
 
 def other_configs(lib, torch, steps):
@@ -629,6 +653,16 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return 0
+    if args.served_3d_only:
+        import torch
+
+        import paper_1506_04694_amd as lib
+        ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
+        try:
+            print(json.dumps({"served_3d": served_3d(lib, torch, ctx, args.steps)}), flush=True)
+        finally:
+            lib.mlmc_ctx_destroy(ctx)
         return 0
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the sample-parallel path on a single "

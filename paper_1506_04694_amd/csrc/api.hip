@@ -212,6 +212,27 @@ void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch, int level 
   }
 }
 
+// Profiled launches of a PCG pass: the work of iteration it is done for the
+// samples with iters >= it (converged or failed samples skip their work), so
+// each launch's algorithmic bytes are scaled by that share of the batch.
+mlmc_status scale_prof_by_active(mlmc_ctx* ctx, size_t prof_begin, const int32_t* iters,
+                                 int batch) {
+  if (ctx->prof.size() <= prof_begin) return MLMC_OK;
+  std::vector<int32_t> hi(batch);
+  HIP_TRY(hipMemcpyAsync(hi.data(), iters, batch * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  std::sort(hi.begin(), hi.end());
+  for (size_t e = prof_begin; e < ctx->prof.size(); ++e) {
+    ProfEvent& pe = ctx->prof[e];
+    if (pe.iter <= 0) continue;
+    const long long active = hi.end() - std::lower_bound(hi.begin(), hi.end(), pe.iter);
+    pe.bytes *= (double)active / batch;
+    pe.iter = 0;
+  }
+  return MLMC_OK;
+}
+
 bool five_smooth(int n) {
   if (n < 1) return false;
   for (int p : {2, 3, 5})
@@ -827,8 +848,16 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     }
     const int ml = ms[l];
     const bool top = l == 0;
+    // algorithmic bytes of a half-sweep per cell: every face once (3 S), r of
+    // the swept colour, the other colour's z read and the swept colour's z
+    // written (V each, half the cells); from zero no z is read
+    const double cells = (double)batch * ml * ml * ml;
+    const double sb = f32 ? 4.0 : 8.0, vb = (top || !f32) ? 8.0 : 4.0;
     auto sweep = [&](int color, int zero) {
-      launch_rbgs3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], S.active, color, zero);
+      timed(ctx, "k_rbgs3", cells * (3.0 * sb + (zero ? 1.0 : 1.5) * vb), [&] {
+        launch_rbgs3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], S.active, color,
+                       zero);
+      }, l);
     };
     for (int it = 0; it < nu; ++it) {
       sweep(0, it == 0);
@@ -866,6 +895,7 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   auto pcg_pass = [&](bool restart) -> mlmc_status {
     launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
     launch_sc_init(st, batch, partial, bps, S, status, iters, relres, restart ? 1 : 0);
+    ctx->prof_iter = restart ? 0 : 1;
     precond();
     launch_sc_rho(st, batch, partial, bps, S, status, 1, nullptr, 0);
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
@@ -883,20 +913,27 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
         HIP_TRY(hipStreamSynchronize(st));
         if (*hcount == 0) break;
       }
+      ctx->prof_iter = restart ? 0 : it + 1;
       precond();
       launch_sc_rho(st, batch, partial, bps, S, status, 0, partial2, f32 ? bps : 0);
       launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 0);
     }
     return MLMC_OK;
   };
+  const size_t prof_begin = ctx->prof.size();
   TRY(pcg_pass(false));
+  ctx->prof_iter = 0;
+  TRY(scale_prof_by_active(ctx, prof_begin, iters, batch));
   if (cur_gamma == 2) {  // V-cycle restart where the W preconditioner broke down
     launch_sc_restart(st, batch, S, status, iters, carried);
     HIP_TRY(hipMemcpyAsync(hcount, S.count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (*hcount > 0) {
       cur_gamma = 1;
-      TRY(pcg_pass(true));
+      ctx->prof_scale = (double)*hcount / batch;
+      const mlmc_status rc = pcg_pass(true);
+      ctx->prof_scale = 1.0;
+      TRY(rc);
       launch_iters_add(st, batch, iters, carried);
     }
   }
@@ -1350,21 +1387,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
   const size_t prof_begin = ctx->prof.size();
   TRY(pcg_pass(false));
   ctx->prof_iter = 0;
-  // profiled launches: the work of iteration it is done for the samples with
-  // iters >= it (converged or failed samples skip their tiles)
-  if (ctx->prof.size() > prof_begin) {
-    std::vector<int32_t> hi(batch);
-    HIP_TRY(hipMemcpyAsync(hi.data(), iters, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    std::sort(hi.begin(), hi.end());
-    for (size_t e = prof_begin; e < ctx->prof.size(); ++e) {
-      ProfEvent& pe = ctx->prof[e];
-      if (pe.iter <= 0) continue;
-      const long long active = hi.end() - std::lower_bound(hi.begin(), hi.end(), pe.iter);
-      pe.bytes *= (double)active / batch;
-      pe.iter = 0;
-    }
-  }
+  TRY(scale_prof_by_active(ctx, prof_begin, iters, batch));
   // The W-cycle preconditioner is symmetric but, with over-corrected coarse
   // steps, not positive definite for every operator (two coarse visits act as
   // 2B - BAB, indefinite once B A has an eigenvalue above 2); a sample whose
