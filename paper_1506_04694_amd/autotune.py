@@ -3,9 +3,9 @@
 For each fine grid size of a workload it times ``mlmc_level_run`` on a
 calibration batch drawn from the workload itself, for every combination of
 the tunable solver options (multigrid storage precision, coarse-grid
-correction scaling omega, V- or W-cycle and the number of W levels, coarsest
-grid size, host convergence-check interval, on-chip cycle threshold, tile
-shapes of the multigrid kernels).  A combination is admissible only if every QoI of the calibration
+correction scaling omega, V- or W-cycle and the number of W levels, smoothing
+sweeps nu = nu1 = nu2, coarsest grid size, host convergence-check interval,
+on-chip cycle threshold, tile shapes of the multigrid kernels).  A combination is admissible only if every QoI of the calibration
 batch stays within ``qoi_rtol`` (default 1e-10) of the FP64 default
 solver's QoI for the same samples; the fastest admissible one is kept.
 
@@ -24,11 +24,21 @@ DEFAULT_SPACE = {
     "omega": [1.8, 1.9, 2.0],
     "gamma": [1, 2],
     "gamma_levels": [2, 3],
+    "nu": [1, 2],
     "coarse_max": [2, 4, 8],
     "check_every": [4, 8],
     "cycle_max": [16, 32],
     "tile_shape": [0, 1],
 }
+
+
+def make_opts(**kw):
+    """mlmc_solver_opts from a point of the search space; "nu" sets the
+    symmetric pair nu1 = nu2 (pre- and post-smoothing sweeps)."""
+    kw = dict(kw)
+    if "nu" in kw:
+        kw["nu1"] = kw["nu2"] = kw.pop("nu")
+    return lib.mlmc_solver_opts_default(**kw)
 
 
 def _time_level(ctx, model, level, m, n, opts, first, reps):
@@ -57,7 +67,7 @@ def tune_level(ctx, model, level, m, n, space=None, qoi_rtol=1e-10, reps=2, firs
     keys = list(space)
     for combo in itertools.product(*(space[k] for k in keys)):
         kw = dict(zip(keys, combo))
-        opts = lib.mlmc_solver_opts_default(**kw)
+        opts = make_opts(**kw)
         try:
             t, qf, qc, sums = _time_level(ctx, model, level, m, n, opts, first, reps)
         except lib.MlmcError as e:
@@ -106,4 +116,4 @@ def best_opts(tuned, m):
     res = tuned.get(m) or tuned.get(str(m))
     if not res or not res.get("best"):
         return lib.mlmc_solver_opts_default()
-    return lib.mlmc_solver_opts_default(**res["best"]["opts"])
+    return make_opts(**res["best"]["opts"])

@@ -132,3 +132,13 @@ def test_product_path_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower() or f == "__init__.py" and \
                     "import oracle" not in text, f
+
+
+def test_autotune_space_point_to_opts(lib):
+    """The autotuner's "nu" sets the symmetric pair nu1 = nu2; other keys are
+    solver option fields (host-only: no device work)."""
+    from paper_1506_04694_amd import autotune
+    o = autotune.make_opts(nu=2, gamma_levels=3, precision=lib.MLMC_PREC_FP32)
+    assert o.nu1 == 2 and o.nu2 == 2 and o.gamma_levels == 3
+    assert o.precision == lib.MLMC_PREC_FP32
+    assert set(autotune.DEFAULT_SPACE) >= {"nu", "coarse_max", "tile_shape", "gamma_levels"}

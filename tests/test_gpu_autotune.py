@@ -44,3 +44,21 @@ def test_tune_level_small_space(lib, model, m):
         # bfloat16 hierarchies are 2-D only: recorded as errors
         assert all("error" in t for t in res["trials"]
                    if t["opts"]["precision"] == lib.MLMC_PREC_BF16)
+
+
+def test_tune_level_smoothing_sweeps(lib):
+    """nu = 1 (fused tile kernels) and nu = 2 (per-sweep cycle) both reach the
+    FP64 default's QoIs; the tuner keeps the faster admissible one."""
+    from paper_1506_04694_amd import autotune
+    print("autotune nu m=128", flush=True)
+    ctx = lib.mlmc_ctx_create(0, torch.cuda.current_stream(0))
+    try:
+        res = autotune.tune_level(ctx, W.CE2, 1, 128, 8, space={"nu": [1, 2]}, reps=1)
+    finally:
+        lib.mlmc_ctx_destroy(ctx)
+    assert [t["opts"]["nu"] for t in res["trials"]] == [1, 2]
+    assert all(t.get("admissible") for t in res["trials"]), res["trials"]
+    assert all(t["max_qoi_rel_dev"] <= 1e-10 for t in res["trials"])
+    assert res["best"]["seconds"] == min(t["seconds"] for t in res["trials"])
+    o = autotune.best_opts({128: res}, 128)
+    assert o.nu1 == o.nu2 == res["best"]["opts"]["nu"]
