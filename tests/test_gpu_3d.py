@@ -359,6 +359,25 @@ def test_in_lds_cycle_equals_per_sweep_cycle(lib, ctx, m, gamma, gamma_levels):
     np.testing.assert_allclose(lds["q_out"], per["q_out"], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("m,prec", [(16, "f64"), (32, "f32"), (64, "f32"), (64, "f64"),
+                                    (128, "f64"), (128, "f32")])
+def test_default_cycle_equals_per_sweep_cycle_large(lib, ctx, m, prec):
+    """The default cycle (small levels in the in-LDS kernel) against variant 1
+    (one launch per half-sweep on every level) up to 128^3, with both
+    hierarchies and W on every level: the same iteration counts and, to
+    rounding, the same QoIs and pressures."""
+    print("3-D default vs per-sweep m=%d %s" % (m, prec), flush=True)
+    rng = np.random.default_rng(1300 + m)
+    kh = np.exp(1.5 * rng.standard_normal((3, m, m, m)))
+    p = lib.MLMC_PREC_FP32 if prec == "f32" else lib.MLMC_PREC_FP64
+    a = solve3(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=p, gamma_levels=0))
+    b = solve3(lib, ctx, kh, lib.mlmc_solver_opts_default(precision=p, gamma_levels=0, variant=1))
+    assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    np.testing.assert_allclose(a["q_out"], b["q_out"], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(a["p"], b["p"], rtol=0, atol=1e-12)
+
+
 def test_serve_3d(lib, ctx):
     grids = [16, 32]
     opts = lib.serve_opts_for(MODEL, grids, n_workers=2, max_batch=8)
