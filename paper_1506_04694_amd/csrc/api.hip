@@ -254,6 +254,14 @@ FftPlan make_plan(int n) {
   while (r % 3 == 0) push(3);
   while (r % 4 == 0) push(4);
   while (r % 2 == 0) push(2);
+  // the FP32 reciprocals div_small multiplies by, correctly rounded as the
+  // device's FP32 division rounds them
+  int ns = 1;
+  for (int st = 0; st < pl.nstages; ++st) {
+    pl.inv_nb[st] = 1.0f / (float)(n / pl.radix[st]);
+    pl.inv_ns[st] = 1.0f / (float)ns;
+    ns *= pl.radix[st];
+  }
   return pl;
 }
 

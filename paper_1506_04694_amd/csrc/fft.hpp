@@ -26,6 +26,10 @@ struct FftPlan {
   int n;
   int nstages;
   int radix[kFftMaxStages];
+  // per stage: 1 / (butterflies per line) and 1 / (span before the stage),
+  // rounded once to FP32 on the host (the divisors of div_small)
+  float inv_nb[kFftMaxStages];
+  float inv_ns[kFftMaxStages];
 };
 
 template <int R>
@@ -87,13 +91,13 @@ __device__ __forceinline__ int div_small(int a, float inv_d) {
 
 template <int R>
 __device__ __forceinline__ void fft_stage_one(double* __restrict__ sre, double* __restrict__ sim,
-                                          const double2* __restrict__ tw, int n, int ns) {
+                                          const double2* __restrict__ tw, int n, int ns,
+                                          float inv_ns) {
   constexpr int kMaxC = (kFftMax / R + kBlock - 1) / kBlock;
   const int nb = n / R;
   const int step = n / (ns * R);
-  // butterfly j splits as j = jq ns + kk (one FP32 multiply instead of an
-  // integer division per butterfly)
-  const float inv_ns = 1.0f / (float)ns;
+  // butterfly j splits as j = jq ns + kk (one FP32 multiply by the plan's
+  // 1 / ns instead of an integer division per butterfly)
   double vr[kMaxC][R], vi[kMaxC][R];
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c) {
@@ -142,10 +146,11 @@ __device__ __forceinline__ void fft_line(double* sre, double* sim, const double2
   int ns = 1;
   for (int st = 0; st < pl.nstages; ++st) {
     const int R = pl.radix[st];
-    if (R == 4) fft_stage_one<4>(sre, sim, tw, pl.n, ns);
-    else if (R == 2) fft_stage_one<2>(sre, sim, tw, pl.n, ns);
-    else if (R == 3) fft_stage_one<3>(sre, sim, tw, pl.n, ns);
-    else fft_stage_one<5>(sre, sim, tw, pl.n, ns);
+    const float ins = pl.inv_ns[st];
+    if (R == 4) fft_stage_one<4>(sre, sim, tw, pl.n, ns, ins);
+    else if (R == 2) fft_stage_one<2>(sre, sim, tw, pl.n, ns, ins);
+    else if (R == 3) fft_stage_one<3>(sre, sim, tw, pl.n, ns, ins);
+    else fft_stage_one<5>(sre, sim, tw, pl.n, ns, ins);
     ns *= R;
   }
 }
@@ -155,11 +160,11 @@ __device__ __forceinline__ void fft_line(double* sre, double* sim, const double2
 // T threads) a thread takes.
 template <int R, int C, int T>
 __device__ __forceinline__ void fft_stage(double* __restrict__ sre, double* __restrict__ sim,
-                                          const double2* __restrict__ tw, int n, int ns, int L) {
+                                          const double2* __restrict__ tw, int n, int ns, int L,
+                                          float inv_nb, float inv_ns) {
   const int nb = n / R;
   const int step = n / (ns * R);
   const int total = L * nb;
-  const float inv_nb = 1.0f / (float)nb, inv_ns = 1.0f / (float)ns;
   double vr[C][R], vi[C][R];
   int base[C];
 #pragma unroll
@@ -212,10 +217,11 @@ __device__ __forceinline__ void fft_lines(double* sre, double* sim, const double
   int ns = 1;
   for (int st = 0; st < pl.nstages; ++st) {
     const int R = pl.radix[st];
-    if (R == 4) fft_stage<4, C, T>(sre, sim, tw, pl.n, ns, L);
-    else if (R == 2) fft_stage<2, C, T>(sre, sim, tw, pl.n, ns, L);
-    else if (R == 3) fft_stage<3, C, T>(sre, sim, tw, pl.n, ns, L);
-    else fft_stage<5, C, T>(sre, sim, tw, pl.n, ns, L);
+    const float inb = pl.inv_nb[st], ins = pl.inv_ns[st];
+    if (R == 4) fft_stage<4, C, T>(sre, sim, tw, pl.n, ns, L, inb, ins);
+    else if (R == 2) fft_stage<2, C, T>(sre, sim, tw, pl.n, ns, L, inb, ins);
+    else if (R == 3) fft_stage<3, C, T>(sre, sim, tw, pl.n, ns, L, inb, ins);
+    else fft_stage<5, C, T>(sre, sim, tw, pl.n, ns, L, inb, ins);
     ns *= R;
   }
 }
