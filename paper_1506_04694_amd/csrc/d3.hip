@@ -397,7 +397,7 @@ void launch_prolong_black3_p(hipStream_t st, bool f32, bool top, int m, int batc
 
 // rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z); rc in S.
 template <class S, class V>
-__global__ void k_resid_restrict3(int m, long long total, const S* __restrict__ T,
+__global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long total, const S* __restrict__ T,
                                   const S* __restrict__ tb, const V* __restrict__ z,
                                   const V* __restrict__ r, S* __restrict__ rc,
                                   const int32_t* __restrict__ active, CellDiv cd) {
@@ -496,6 +496,7 @@ struct Lds3Cfg<float> {
 
 struct Lds3Level {
   int m, P, off;  // size, padded pitch (m + 2), offset of the level's arrays
+  float inv_m, inv_half;  // 1 / m and 1 / max(m / 2, 1), the divisors of div_small
 };
 
 __device__ __forceinline__ int pidx3(int P, int i, int j, int l) {
@@ -504,7 +505,8 @@ __device__ __forceinline__ int pidx3(int P, int i, int j, int l) {
 
 // arrays of a level: te, tn, tu, r, z, each P^3 words
 template <class E, int NT>
-__device__ void c3_sweep(E* a, int m, int P, int color, bool zero) {
+__device__ void c3_sweep(E* a, const Lds3Level& lq, int color, bool zero) {
+  const int m = lq.m, P = lq.P;
   const int PPP = P * P * P, PP = P * P;
   E* te = a;
   E* tn = a + PPP;
@@ -514,10 +516,9 @@ __device__ void c3_sweep(E* a, int m, int P, int color, bool zero) {
   const int half = m / 2 > 0 ? m / 2 : 1;
   const int cnt = m * m * half;
   // quotients through one FP32 multiply (exact for these small operands)
-  const float inv_half = 1.0f / (float)half, inv_m = 1.0f / (float)m;
   for (int c = threadIdx.x; c < cnt; c += NT) {
-    const int row = div_small(c, inv_half);  // row = l m + j
-    const int l = div_small(row, inv_m), j = row - l * m;
+    const int row = div_small(c, lq.inv_half);  // row = l m + j
+    const int l = div_small(row, lq.inv_m), j = row - l * m;
     const int i = 2 * (c - row * half) + ((j + l + color) & 1);
     if (i >= m) continue;
     const int f = pidx3(P, i, j, l);
@@ -596,14 +597,17 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
   __shared__ E lds[Lds3Cfg<E>::kWords];
   const int s = blockIdx.x;
   if (!active[s]) return;
-  Lds3Level lv[kMaxCoarseLevels];
+  // the level table in LDS: the loops below index it by the running level, a
+  // per-thread array would live in scratch memory
+  __shared__ Lds3Level lv[kMaxCoarseLevels];
   int off = 0;
   for (int q = 0; q < nlev; ++q) {
-    lv[q].m = desc.m[q];
-    lv[q].P = desc.m[q] + 2;
-    lv[q].off = off;
-    off += 5 * lv[q].P * lv[q].P * lv[q].P;
+    const int mq = desc.m[q], P = mq + 2;
+    if (threadIdx.x == 0)
+      lv[q] = Lds3Level{mq, P, off, 1.0f / (float)mq, 1.0f / (float)(mq / 2 > 0 ? mq / 2 : 1)};
+    off += 5 * P * P * P;
   }
+  __syncthreads();
   E* vec = lds + off;  // coarsest right-hand side
   // operators from the image (linear copy), r and z zero, r of the first level
   // from r0
@@ -620,7 +624,7 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
     const int m = lv[0].m, P = lv[0].P, PPP = P * P * P;
     E* rr = lds + lv[0].off + 3 * PPP;
     const long long n = (long long)m * m * m;
-    const float inv_m = 1.0f / (float)m;
+    const float inv_m = lv[0].inv_m;
     for (int c = threadIdx.x; c < n; c += NT) {
       const int row = div_small(c, inv_m), i = c - row * m;  // row = l m + j
       const int l = div_small(row, inv_m), j = row - l * m;
@@ -666,21 +670,21 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
       continue;
     }
     if (descending) {
-      c3_sweep<E, NT>(a, m, P, 0, true);
-      c3_sweep<E, NT>(a, m, P, 1, false);
+      c3_sweep<E, NT>(a, lv[q], 0, true);
+      c3_sweep<E, NT>(a, lv[q], 1, false);
     } else {
       const int Pc = lv[q + 1].P, PPPc = Pc * Pc * Pc;
       const E* zc = lds + lv[q + 1].off + 4 * PPPc;
       const E om = (E)omega;
-      const float inv_m = 1.0f / (float)m;
+      const float inv_m = lv[q].inv_m;
       for (int c = threadIdx.x; c < m * m * m; c += NT) {
         const int row = div_small(c, inv_m), i = c - row * m;  // row = l m + j
         const int l = div_small(row, inv_m), j = row - l * m;
         zz[pidx3(P, i, j, l)] += om * zc[pidx3(Pc, i / 2, j / 2, l / 2)];
       }
       __syncthreads();
-      c3_sweep<E, NT>(a, m, P, 1, false);
-      c3_sweep<E, NT>(a, m, P, 0, false);
+      c3_sweep<E, NT>(a, lv[q], 1, false);
+      c3_sweep<E, NT>(a, lv[q], 0, false);
       if (!(wmask >> q & 1u) || (once >> q & 1u)) {
         once &= ~(1u << q);
         if (q == 0) break;
@@ -688,14 +692,14 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
         continue;
       }
       once |= 1u << q;
-      c3_sweep<E, NT>(a, m, P, 1, false);
+      c3_sweep<E, NT>(a, lv[q], 1, false);
     }
     // residual, restricted to the next level (sum over the 2 x 2 x 2 block)
     const int mc = lv[q + 1].m, Pc = lv[q + 1].P, PPPc = Pc * Pc * Pc;
     E* rc = lds + lv[q + 1].off + 3 * PPPc;
     // one fine cell per lane, t = 8 c + (aa + 2 bb + 4 cc), summed over the
     // 8-lane group of coarse cell c (groups never straddle the loop bound)
-    const float inv_mc = 1.0f / (float)mc;
+    const float inv_mc = lv[q + 1].inv_m;
     for (int t = threadIdx.x; t < 8 * mc * mc * mc; t += NT) {
       const int c = t >> 3, k = t & 7;
       const int row = div_small(c, inv_mc), I = c - row * mc;  // row = L mc + J

@@ -951,14 +951,16 @@ k_mg_coarse_cycle(int nlev, CoarseDesc desc, const VecT<S, TOP>* __restrict__ r0
   extern __shared__ double lds[];
   const int s = blockIdx.x;
   if (!active[s]) return;
-  CoarseLevel lv[kMaxCoarseLevels];
+  // the level table in LDS: the cycle indexes it by the running level, a
+  // per-thread array would live in scratch memory
+  __shared__ CoarseLevel lv[kMaxCoarseLevels];
   int off = 0;
   for (int l = 0; l < nlev; ++l) {
-    lv[l].m = desc.m[l];
-    lv[l].P = desc.m[l] + 2;
-    lv[l].off = off;
-    off += 4 * lv[l].P * lv[l].P;
+    const int P = desc.m[l] + 2;
+    if (threadIdx.x == 0) lv[l] = CoarseLevel{desc.m[l], P, off};
+    off += 4 * P * P;
   }
+  __syncthreads();
   double* vec = lds + off;  // coarsest right-hand side (n_c doubles)
   for (int l = 0; l < nlev; ++l) {
     const int m = lv[l].m, P = lv[l].P, PP = P * P;
