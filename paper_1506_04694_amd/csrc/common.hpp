@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/mlmc_darcy.h"
+#include "unitmath.hpp"
 
 namespace mlmc {
 
@@ -62,12 +63,13 @@ __device__ __forceinline__ double to_uniform(uint32_t x) {
 }
 
 // Box-Muller: two standard normals from two uniforms.  cos and sin of 2 pi u1
-// come from sincospi(2 u1), whose argument is exact (no rounding of 2 pi u1
-// and no range reduction by pi).
+// come from sin/cos of pi (2 u1), whose argument is exact (no rounding of
+// 2 pi u1); the logarithm and the sine/cosine are the short forms for these
+// argument ranges (unitmath.hpp), a few ulps from the exact values.
 __device__ __forceinline__ void box_muller(double u0, double u1, double& z0, double& z1) {
-  const double r = sqrt(-2.0 * log(u0));
+  const double r = sqrt(-2.0 * log_unit(u0));
   double s, c;
-  sincospi(2.0 * u1, &s, &c);
+  sincospi_unit(2.0 * u1, &s, &c);
   z0 = r * c;
   z1 = r * s;
 }
