@@ -774,6 +774,30 @@ def main():
             for key in prof_all:
                 prof_all[key] += pr[key]
             lib.mlmc_profile_enable(c, None)
+    # the same kernel split by launch size, one more step each: the level runs'
+    # 2^24-cell fine solves (working set per launch larger than the 256 MB
+    # Infinity Cache) apart from the 2^22-cell companions
+    by_size = None
+    if args.kernel == DOMINANT:
+        by_size = {}
+        for cells in (1 << 24, 1 << 22):
+            label = "%s#%d" % (args.kernel, cells)
+            for c in lctx:
+                lib.mlmc_profile_enable(c, label)
+            step(args.warmup + args.steps + 1, False)
+            torch.cuda.synchronize()
+            pb = {"launches": 0, "total_ms": 0.0, "algorithmic_bytes": 0.0}
+            for c in lctx:
+                pr = lib.mlmc_profile_read(c)
+                for key in pb:
+                    pb[key] += pr[key]
+                lib.mlmc_profile_enable(c, None)
+            if pb["launches"] and pb["total_ms"] > 0:
+                ach = pb["algorithmic_bytes"] / (pb["total_ms"] * 1e-3) / 1e9
+                by_size[str(cells)] = {
+                    "label": label, "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "launches": pb["launches"], "avg_launch_ms": pb["total_ms"] / pb["launches"],
+                    "algorithmic_bytes_per_launch": pb["algorithmic_bytes"] / pb["launches"]}
     est = lib.mlmc_estimate(sums)
     single = per_sample_baseline() if not args.no_per_sample else None
     variants = None if args.no_variants else path_variants(lib, torch, wl, ctx, opts, args)
@@ -826,6 +850,8 @@ def main():
                 "traffic": measured_traffic(args.kernel), "launches": prof["launches"],
                 "avg_launch_ms": avg_ms,
                 "algorithmic_bytes_per_launch": prof["algorithmic_bytes"] / prof["launches"]}
+        if by_size:
+            roof["by_launch_cells"] = by_size
         if prof_all and prof_all["launches"] > 0:
             ach = prof_all["algorithmic_bytes"] / (prof_all["total_ms"] * 1e-3) / 1e9
             roof["all_levels"] = {

@@ -456,7 +456,9 @@ mlmc_status mlmc_adaptive(mlmc_ctx* ctx, const mlmc_model* model, int max_levels
  * The tiled multigrid kernels (k_mg_down, k_mg_mid, k_mg_up) also answer to
  * "<name>@<level>", which times the launches on that level of each solve only
  * (level 0 = the finest grid, the kernel instantiation that works on FP64
- * residuals). */
+ * residuals), and to "<name>@<level>#<cells>", the launches on that level
+ * whose batch holds that many cells (batch x m x m; e.g. the 2^24-cell fine
+ * solves of a level run apart from its 2^22-cell companions). */
 mlmc_status mlmc_profile_enable(mlmc_ctx* ctx, const char* kernel_name);
 mlmc_status mlmc_profile_read(mlmc_ctx* ctx, int64_t* launches, double* total_ms,
                               double* algorithmic_bytes);

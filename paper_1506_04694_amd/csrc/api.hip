@@ -192,14 +192,23 @@ hipEvent_t pool_event(mlmc_ctx* ctx) {
 // selects that level's launches only (level 0: the finest grid of a solve,
 // a kernel instantiation of its own).
 template <class F>
-void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch, int level = -1) {
+void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch, int level = -1,
+           long long cells = -1) {
   bool hit = false;
   if (!ctx->prof_name.empty()) {
-    const std::string& p = ctx->prof_name;
+    // "<name>", "<name>@<level>" or "<name>@<level>#<cells of the launch's batch>"
+    std::string p = ctx->prof_name;
+    const size_t hash = p.find('#');
+    bool grid_ok = true;
+    if (hash != std::string::npos) {
+      grid_ok = cells >= 0 && std::to_string(cells) == p.substr(hash + 1);
+      p = p.substr(0, hash);
+    }
     const size_t at = p.find('@');
-    hit = at == std::string::npos ? p == name
-                                  : (p.compare(0, at, name) == 0 && std::strlen(name) == at &&
-                                     level >= 0 && std::to_string(level) == p.substr(at + 1));
+    hit = grid_ok && (at == std::string::npos
+                          ? p == name
+                          : (p.compare(0, at, name) == 0 && std::strlen(name) == at &&
+                             level >= 0 && std::to_string(level) == p.substr(at + 1)));
   }
   if (hit) {
     ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes * ctx->prof_scale, ctx->prof_iter};
@@ -1235,7 +1244,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     timed(ctx, "k_mg_down", cells * (ebd * 3.25 + rb), [&] {
       launch_mg_down(st, prec, opts->tile_shape, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], rs[l + 1],
                      S.active);
-    }, l);
+    }, l, (long long)batch * ms[l] * ms[l]);
     fcycle(l + 1);
     const void* zin = zpre[l];
     if (visits(l) == 2) {
@@ -1243,7 +1252,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       timed(ctx, "k_mg_mid", cells * (ebd * 4.5 + rb), [&] {
         launch_mg_mid(st, prec, opts->tile_shape, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zpre[l], zmid[l],
                       zs[l + 1], omega, rs[l + 1], S.active);
-      }, l);
+      }, l, (long long)batch * ms[l] * ms[l]);
       fcycle(l + 1);
       zin = zmid[l];
     }
@@ -1251,7 +1260,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
     timed(ctx, "k_mg_up", cells * (ebd * 3.25 + (l == 0 ? 16.0 : 2.0 * ebd)), [&] {
       launch_mg_up(st, prec, opts->tile_shape, l == 0, ms[l], batch, Ts[l], tbs[l], rs[l], zin, zs[l], zs[l + 1],
                    omega, S.active, l == 0 ? partial : nullptr);
-    }, l);
+    }, l, (long long)batch * ms[l] * ms[l]);
   };
   auto vcycle = [&]() {
     if (!fused) {
