@@ -156,10 +156,11 @@ TILTED3 = Model(dim=3, interface_kind=TILTED_PLANE, n_layers=2, field_kind=CORRE
                 n_ce={2: 4, 4: 8, 8: 16, 16: 36, 32: 75, 64: 225, 128: 540})
 SERVED_3D = Workload("3d-ce-tilted-32-128", TILTED3, [32, 64, 128], [64, 16, 4])
 # Solver options per level of SERVED_3D (overrides of the defaults, FP32
-# hierarchy), as chosen by autotune.tune_level over gamma_levels: at 128^3 W on
-# the three finest levels (10.8 PCG iterations against 14.3 with W on two, 6%
-# less time per level run); 32^3 and 64^3 keep W on two.
-SERVED_3D_LEVEL_OPTS = ({}, {}, {"gamma_levels": 3})
+# hierarchy), as chosen by autotune.tune_level over omega in 1.6..2.0 and W on
+# two or three levels: at 64^3 and 128^3 omega = 1.8 with W on two levels (at
+# 128^3 11.5 PCG iterations and 25.0 ms per level run, against 10.8 and 26.0 ms
+# for the next best, omega = 1.9 with W on three); 32^3 keeps the defaults.
+SERVED_3D_LEVEL_OPTS = ({}, {"omega": 1.8}, {"omega": 1.8})
 
 # The served stream: single-sample requests of the layered 2-D model on
 # 64^2..512^2, the high-contrast 2-D model on 1024^2 and the 3-D model on
