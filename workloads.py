@@ -79,7 +79,11 @@ LAYERED_CE = Workload("2d-ce-8node-64-512", CE2, [64, 128, 256, 512], [4096, 102
 # autotune.tune_level over omega, gamma_levels and check_every in FP64: the 64^2
 # level, solved whole on chip, is fastest with W on its finest grid only (about
 # 10% fewer ms per level run than W on two grids, 10.3 against 8.6 iterations);
-# the larger grids keep the defaults.
+# the larger grids keep the defaults.  (Re-tuned over omega 1.8..2.0 as well:
+# omega = 2.0 looked 1.5-2% faster on a calibration batch at 64^2 and 512^2, but
+# on the bench's own samples it gained nothing at 64^2 and made the 512^2 level
+# 25% slower, its W-cycle preconditioner breaking down into V restarts more
+# often; not kept.)
 LAYERED_CE_LEVEL_OPTS = ({"gamma_levels": 1}, {}, {}, {})
 
 # The same piecewise constant model on 64^2..512^2 with Coarse Grid Variates.
