@@ -12,9 +12,11 @@
 // times the harmonic mean; a Dirichlet face T = 2 k_P h (half-cell distance).
 //
 // The multigrid is the same as in 2-D with 2 x 2 x 2 aggregation (the
-// Galerkin coarse face is the sum of the four fine faces it covers), one
-// launch per colour sweep, restriction and prolongation, and the dense
-// inverse on the coarsest grid (<= 4^3 unknowns).
+// Galerkin coarse face is the sum of the four fine faces it covers): on the
+// larger grids one launch per colour half-sweep, one for residual and
+// restriction, and the prolongation folded into the next black half-sweep;
+// the levels from side 8 (FP64) or 16 (FP32) down in one in-LDS launch per
+// visit; the dense inverse on the coarsest grid (<= 4^3 unknowns).
 #include <cfloat>
 
 #include "common.hpp"

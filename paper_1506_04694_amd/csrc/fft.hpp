@@ -1,5 +1,5 @@
 // LDS-resident mixed-radix (2, 3, 4, 5) complex FP64 FFT for lines of length
-// n <= kFftMax, one or several lines per 256-thread workgroup.
+// n <= kFftMax, one or several lines per workgroup.
 //
 // Stockham autosort formulation (natural-order input and output): at a stage
 // of radix R with span Ns (product of the radices already applied), butterfly
