@@ -191,6 +191,17 @@ hipEvent_t pool_event(mlmc_ctx* ctx) {
 // of a multigrid level pass `level`; the profiled name "<name>@<level>" then
 // selects that level's launches only (level 0: the finest grid of a solve,
 // a kernel instantiation of its own).
+thread_local ArmedEvents t_armed;
+
+// Kernels whose launches go through launch_k, timed by their own dispatch
+// (the others are bracketed by events recorded on the stream around them).
+bool stamped_by_launch(const char* name) {
+  for (const char* k : {"k_mg_down", "k_mg_mid", "k_mg_up", "k_cg_direction_t", "k_axpy_dot",
+                        "k_rbgs3"})
+    if (std::strcmp(name, k) == 0) return true;
+  return false;
+}
+
 template <class F>
 void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch, int level = -1,
            long long cells = -1) {
@@ -212,9 +223,22 @@ void timed(mlmc_ctx* ctx, const char* name, double bytes, F&& launch, int level 
   }
   if (hit) {
     ProfEvent pe{pool_event(ctx), pool_event(ctx), bytes * ctx->prof_scale, ctx->prof_iter};
-    (void)hipEventRecord(pe.a, ctx->stream);
-    launch();
-    (void)hipEventRecord(pe.b, ctx->stream);
+    if (stamped_by_launch(name)) {
+      // the kernel's own launch stamps the events with its dispatch's start
+      // and end (launch_k)
+      armed_events() = ArmedEvents{pe.a, pe.b};
+      launch();
+      if (armed_events().start != nullptr) {  // not issued through launch_k
+        armed_events() = ArmedEvents{};
+        ctx->event_pool.push_back(pe.a);
+        ctx->event_pool.push_back(pe.b);
+        return;
+      }
+    } else {
+      (void)hipEventRecord(pe.a, ctx->stream);
+      launch();
+      (void)hipEventRecord(pe.b, ctx->stream);
+    }
     ctx->prof.push_back(pe);
   } else {
     launch();
@@ -437,6 +461,9 @@ namespace mlmc {
 mlmc_status set_error(mlmc_ctx* ctx, mlmc_status code, const char* msg) {
   return fail(ctx, code, msg);
 }
+
+// This host thread's event pair for the next launch_k (kernels.hpp).
+ArmedEvents& armed_events() { return t_armed; }
 }  // namespace mlmc
 
 extern "C" {

@@ -321,7 +321,7 @@ static void rbgs3_t(hipStream_t st, int m, int batch, const void* T, const void*
   CellDiv cd = make_celldiv(total, (long long)m * m * (m / 2), m);
   cd.mm = make_fastdiv((uint32_t)m * (uint32_t)(m / 2));
   cd.m = make_fastdiv((uint32_t)(m / 2));
-  hipLaunchKernelGGL((k_rbgs3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total,
+  launch_k((k_rbgs3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total,
                      (const S*)T, (const S*)tb, (V*)z, (const V*)r, active, color, zero_init, cd);
 }
 

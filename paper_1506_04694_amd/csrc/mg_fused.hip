@@ -1448,7 +1448,7 @@ template <int TX, int TY, int NT, class S, bool TOP>
 static void down_p(hipStream_t st, int m, int batch, const void* T, const void* tb, const void* r,
                    void* z, void* rc, const int32_t* active) {
   using R = VecT<S, TOP>;
-  hipLaunchKernelGGL((k_mg_down_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)),
+  launch_k((k_mg_down_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)),
                      dim3(NT), 0, st, m, (const S*)T, (const S*)tb, (const R*)r, (S*)z, (S*)rc,
                      active);
 }
@@ -1458,7 +1458,7 @@ static void up_p(hipStream_t st, int m, int batch, const void* T, const void* tb
                  const void* zpre, void* z, const void* zc, double omega, const int32_t* active,
                  double* rz_partial) {
   using R = VecT<S, TOP>;
-  hipLaunchKernelGGL((k_mg_up_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)), dim3(NT),
+  launch_k((k_mg_up_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)), dim3(NT),
                      0, st, m, (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (R*)z,
                      (const S*)zc, omega, active, rz_partial);
 }
@@ -1468,7 +1468,7 @@ static void mid_p(hipStream_t st, int m, int batch, const void* T, const void* t
                   const void* zpre, void* z, const void* zc, double omega, void* rc,
                   const int32_t* active) {
   using R = VecT<S, TOP>;
-  hipLaunchKernelGGL((k_mg_mid_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)),
+  launch_k((k_mg_mid_p<TX, TY, NT, S, TOP>), dim3(batch * (m / TX) * (m / TY)),
                      dim3(NT), 0, st, m, (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre,
                      (S*)z, (const S*)zc, omega, (S*)rc, active);
 }
@@ -1490,7 +1490,7 @@ static void down_impl(int shape, hipStream_t st, int m, int batch, const void* T
   using C = typename Prec<S>::C;
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
   const int tps = (m / tx) * (m / ty);
-  hipLaunchKernelGGL((k_mg_down<S, TOP>), dim3(batch * tps), dim3(kBlock), frame_bytes<C>(tx, ty),
+  launch_k((k_mg_down<S, TOP>), dim3(batch * tps), dim3(kBlock), frame_bytes<C>(tx, ty),
                      st, m, tx, ty, tps, (const S*)T, (const S*)tb, (const R*)r, (S*)z, (S*)rc,
                      active);
 }
@@ -1515,7 +1515,7 @@ static void up_impl(int shape, hipStream_t st, int m, int batch, const void* T, 
   using C = typename Prec<S>::C;
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
   const int tps = (m / tx) * (m / ty);
-  hipLaunchKernelGGL((k_mg_up<S, TOP>), dim3(batch * tps), dim3(kBlock), frame_bytes<C>(tx, ty), st,
+  launch_k((k_mg_up<S, TOP>), dim3(batch * tps), dim3(kBlock), frame_bytes<C>(tx, ty), st,
                      m, tx, ty, tps, (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (R*)z,
                      (const S*)zc, omega, active, rz_partial);
 }
@@ -1539,7 +1539,7 @@ static void mid_impl(int shape, hipStream_t st, int m, int batch, const void* T,
   const int tx = tile_dim(m, kTileX), ty = tile_dim(m, kTileY);
   const int tps = (m / tx) * (m / ty);
   const size_t lds = (size_t)4 * (tx + 8) * (ty + 8) * sizeof(C);
-  hipLaunchKernelGGL((k_mg_mid<S, TOP>), dim3(batch * tps), dim3(kBlock), lds, st, m, tx, ty, tps,
+  launch_k((k_mg_mid<S, TOP>), dim3(batch * tps), dim3(kBlock), lds, st, m, tx, ty, tps,
                      (const S*)T, (const S*)tb, (const R*)r, (const S*)zpre, (S*)z, (const S*)zc,
                      omega, (S*)rc, active);
 }
@@ -1693,7 +1693,7 @@ void launch_cg_direction(hipStream_t st, int m, int batch, const double* T, cons
                          const double* z, const double* pold, double* pnew, double* q,
                          const double* beta, int first, double* partial, const int32_t* active) {
   const int nb = batch * (m / kTileX) * (m / kTileY);
-  hipLaunchKernelGGL((k_cg_direction_t<kTileX, kTileY>), dim3(nb), dim3(kMgThreads), 0, st, m, T,
+  launch_k((k_cg_direction_t<kTileX, kTileY>), dim3(nb), dim3(kMgThreads), 0, st, m, T,
                      tb, z, pold, pnew, q, beta, first, partial, active);
 }
 

@@ -420,7 +420,7 @@ k_axpy_dot(int n, double* __restrict__ x, double* __restrict__ r, const double* 
 void launch_axpy_dot(hipStream_t st, int n, int batch, double* x, double* r, const double* p,
                      const double* q, const double* alpha, double* partial, int bps,
                      const int32_t* active, const double* zold, double* partial2) {
-  hipLaunchKernelGGL(k_axpy_dot, dim3(batch * bps), dim3(kBlock), 0, st, n, x, r, p, q, alpha,
+  launch_k(k_axpy_dot, dim3(batch * bps), dim3(kBlock), 0, st, n, x, r, p, q, alpha,
                      partial, bps, active, zold, partial2);
 }
 
