@@ -1423,7 +1423,7 @@ static bool fixed_tile(int m) { return m % kTileX == 0 && m % kTileY == 0; }
 
 // Tile shapes of the colour-split kernels: the fastest of the shapes measured
 // per kernel and hierarchy precision on the 512 x 512 level with 64 samples
-// (FP64: down 64 x 32 on 1024 threads, mid 64 x 32 on 768, up 128 x 16 on 640
+// (FP64: down 64 x 32 on 768 threads, mid 64 x 32 on 768, up 128 x 16 on 768
 // where 128 divides m, else 64 x 16 on 384; FP32 and bfloat16: down and up
 // 64 x 32 on 640 threads, mid 64 x 64 on 1024).  Every shape divides each m
 // that is a multiple of 64 (fixed_tile), except up's 128 x 16.
@@ -1483,7 +1483,7 @@ static void down_impl(int shape, hipStream_t st, int m, int batch, const void* T
         down_p<64, 16, 384, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
       else down_p<64, 16, 704, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
     } else if constexpr (std::is_same<S, double>::value)
-      down_p<64, 32, 1024, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
+      down_p<64, 32, 768, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
     else down_p<64, 32, 640, S, TOP>(st, m, batch, T, tb, r, z, rc, active);
     return;
   }
@@ -1508,7 +1508,7 @@ static void up_impl(int shape, hipStream_t st, int m, int batch, const void* T, 
     } else if constexpr (!std::is_same<S, double>::value)
       up_p<64, 32, 640, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
     else if (up_wide(m))
-      up_p<128, 16, 640, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
+      up_p<128, 16, 768, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
     else up_p<64, 16, 384, S, TOP>(st, m, batch, T, tb, r, zpre, z, zc, omega, active, rz_partial);
     return;
   }
