@@ -4,7 +4,7 @@
 // is a short range reduction plus one polynomial, about a third of the
 // general library functions' instructions.  Both are built from the
 // mathematics, with errors of a few units in the last place (checked against
-// 200-digit references by the CPU tests):
+// 60-digit references by the CPU tests):
 //
 //  * log_unit: u = m 2^e with m in [sqrt(1/2), sqrt(2)); with f = m - 1 and
 //    s = f / (2 + f), log m = 2 atanh s = 2 s (1 + s^2/3 + s^4/5 + ...);
