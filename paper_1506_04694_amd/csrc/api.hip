@@ -851,6 +851,12 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
         l0 = l;
         break;
       }
+  // the levels above the in-LDS (or else the dense coarsest) one are swept per
+  // launch and keep their z and r in colour-split order; so does the CG when
+  // the finest level is one of them (its x is put back in natural order at
+  // the end)
+  const int lsplit = l0 >= 0 ? l0 : L;
+  auto split = [&](int l) { return l < lsplit; };
   void* cimg = nullptr;  // padded operator image of the in-LDS levels
   if (l0 >= 0) {
     for (int q2 = 0; l0 + q2 <= L; ++q2) {
@@ -918,11 +924,11 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
           sweep(1, 0);
         }
       launch_resid_restrict3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], rh[l + 1],
-                               S.active);
+                               S.active, split(l + 1));
       cycle(l + 1);
       // the prolongation rides on the first (black) half-sweep of post-smoothing
       launch_prolong_black3_p(st, f32, top, ml, batch, Th[l], tbh[l], zh[l], rh[l], zh[l + 1],
-                              omega, S.active);
+                              omega, S.active, split(l + 1));
       sweep(0, 0);
       for (int it = 1; it < nu; ++it) {
         sweep(1, 0);
@@ -937,7 +943,10 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   int32_t* hcount = static_cast<int32_t*>(ctx->host_pinned);
   const int check = opts->check_every > 0 ? opts->check_every : 1;
   auto pcg_pass = [&](bool restart) -> mlmc_status {
-    launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
+    if (split(0))
+      launch_pcg_init3_split(st, m, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
+    else
+      launch_pcg_init(st, (int)n, batch, b, p, r, partial, bps, restart ? S.active : nullptr);
     launch_sc_init(st, batch, partial, bps, S, status, iters, relres, restart ? 1 : 0);
     ctx->prof_iter = restart ? 0 : 1;
     precond();
@@ -945,7 +954,7 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
     CHECK_LAUNCH();
     for (int it = 1;; ++it) {
-      launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active);
+      launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active, split(0));
       launch_sc_alpha(st, batch, partial, bps, S, status);
       // flexible form with a reduced-precision cycle: also r_new . z_old
       launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,
@@ -980,6 +989,10 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
       TRY(rc);
       launch_iters_add(st, batch, iters, carried);
     }
+  }
+  if (split(0)) {  // x back to natural order, through z
+    launch_from_split3(st, m, batch, p, z);
+    HIP_TRY(hipMemcpyAsync(p, z, (size_t)batch * n * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
   launch_true_residual3(st, m, batch, T, tb, b, p, partial, bps);
   launch_sc_final(st, batch, partial, bps, S, relres);

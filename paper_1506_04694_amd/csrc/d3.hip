@@ -17,9 +17,15 @@
 // restriction, and the prolongation folded into the next black half-sweep;
 // the levels from side 8 (FP64) or 16 (FP32) down in one in-LDS launch per
 // visit; the dense inverse on the coarsest grid (<= 4^3 unknowns).
+//
+// The vectors (z, r and, on the finest level, the CG's x, r, p, q) of every
+// level swept by the per-sweep kernels are stored in colour-split order
+// (cs3.hpp); the faces, k, b and the solution handed back stay in the natural
+// order, and so do the in-LDS and the dense coarsest levels.
 #include <cfloat>
 
 #include "common.hpp"
+#include "cs3.hpp"
 #include "fft.hpp"
 #include "kernels.hpp"
 
@@ -64,6 +70,23 @@ __device__ __forceinline__ S nsum3(const X* __restrict__ x, int m, int i, int j,
   if (j > 0) o += f.ts * (S)x[c - m];
   if (l < m - 1) o += f.tu * (S)x[c + mm];
   if (l > 0) o += f.td * (S)x[c - mm];
+  return o;
+}
+
+// The same sum, in the same order, over a level vector xs (one sample) in
+// colour-split order.
+template <class S, class X>
+__device__ __forceinline__ S nsum3_cs(const X* __restrict__ xs, int m, int i, int j, int l,
+                                      const Faces3T<S>& f) {
+  const Cs3Nb nb = cs3_neighbours(m, i, j, l);
+  const X* xo = xs + nb.other;
+  S o = S(0);
+  if (i < m - 1) o += f.te * (S)xo[nb.de];
+  if (i > 0) o += f.tw * (S)xo[nb.dw];
+  if (j < m - 1) o += f.tn * (S)xo[nb.dn];
+  if (j > 0) o += f.ts * (S)xo[nb.ds];
+  if (l < m - 1) o += f.tu * (S)xo[nb.du];
+  if (l > 0) o += f.td * (S)xo[nb.dd];
   return o;
 }
 
@@ -287,7 +310,9 @@ void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const do
 }
 
 // ------------------------------------------------------------------ smoother
-// One thread per cell of the colour ((i + j + l) % 2 == color); m even.
+// One thread per cell of the colour ((i + j + l) % 2 == color); m even; z and
+// r in colour-split order, so thread g of sample s reads r and writes z at
+// color m^3/2 + (g - s m^3/2).
 // S: operator storage and arithmetic type; V: type of the level's z and r
 // (double on the finest level, whose z and r are the CG's).
 template <class S, class V>
@@ -308,9 +333,9 @@ __global__ void k_rbgs3(int m, long long total, const S* __restrict__ T,
   const long long n = (long long)m * m * m;
   const Faces3T<S> f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
   V* zs = z + s * n;
-  const long long c = ((long long)l * m + j) * m + i;
-  const S rv = (S)r[s * n + c];
-  zs[c] = (V)(zero_init ? rv / diag3(f) : (rv + nsum3(zs, m, i, j, l, f)) / diag3(f));
+  const long long e = (long long)color * per + (g - s * per);
+  const S rv = (S)r[s * n + e];
+  zs[e] = (V)(zero_init ? rv / diag3(f) : (rv + nsum3_cs(zs, m, i, j, l, f)) / diag3(f));
 }
 
 template <class S, class V>
@@ -340,12 +365,14 @@ void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const 
 // black cells (one thread each) from neighbours z_n + omega zc(parent of n),
 // formed as the prolongation forms them (in V), and writes nothing else: the
 // arithmetic of a separate prolongation pass followed by k_rbgs3 on the black
-// cells.
+// cells.  z and r in colour-split order; zc in colour-split order when csc is
+// set (the coarse level is swept per launch too), else natural.
 template <class S, class V>
 __global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T,
                                  const S* __restrict__ tb, V* __restrict__ z,
                                  const V* __restrict__ r, const S* __restrict__ zc,
-                                 double omega, const int32_t* __restrict__ active, CellDiv cd) {
+                                 double omega, const int32_t* __restrict__ active, int csc,
+                                 CellDiv cd) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int half = m / 2;
@@ -360,49 +387,59 @@ __global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T
   V* zs = z + s * n;
   const S* zcs = zc + s * (long long)mc * mc * mc;
   const V w = (V)omega;
-  auto pz = [&](long long c, int ii, int jj, int ll) -> S {
-    return (S)(zs[c] + w * (V)zcs[((long long)(ll / 2) * mc + jj / 2) * mc + ii / 2]);
+  // the red neighbour at offset d of the red row entry, prolonged from the
+  // coarse cell holding fine cell (ii, jj, ll)
+  const Cs3Nb nb = cs3_neighbours(m, i, j, l);
+  const V* zo = zs + nb.other;
+  auto pz = [&](int d, int ii, int jj, int ll) -> S {
+    const int I = ii >> 1, J = jj >> 1, L = ll >> 1;
+    const long long ci = csc ? cs3_index(mc, I, J, L) : ((long long)L * mc + J) * mc + I;
+    return (S)(zo[d] + w * (V)zcs[ci]);
   };
-  const long long c = ((long long)l * m + j) * m + i;
-  const long long mm = (long long)m * m;
   S o = S(0);
-  if (i < m - 1) o += f.te * pz(c + 1, i + 1, j, l);
-  if (i > 0) o += f.tw * pz(c - 1, i - 1, j, l);
-  if (j < m - 1) o += f.tn * pz(c + m, i, j + 1, l);
-  if (j > 0) o += f.ts * pz(c - m, i, j - 1, l);
-  if (l < m - 1) o += f.tu * pz(c + mm, i, j, l + 1);
-  if (l > 0) o += f.td * pz(c - mm, i, j, l - 1);
-  const S rv = (S)r[s * n + c];
-  zs[c] = (V)((rv + o) / diag3(f));
+  if (i < m - 1) o += f.te * pz(nb.de, i + 1, j, l);
+  if (i > 0) o += f.tw * pz(nb.dw, i - 1, j, l);
+  if (j < m - 1) o += f.tn * pz(nb.dn, i, j + 1, l);
+  if (j > 0) o += f.ts * pz(nb.ds, i, j - 1, l);
+  if (l < m - 1) o += f.tu * pz(nb.du, i, j, l + 1);
+  if (l > 0) o += f.td * pz(nb.dd, i, j, l - 1);
+  const long long e = per + (g - s * per);  // black block
+  const S rv = (S)r[s * n + e];
+  zs[e] = (V)((rv + o) / diag3(f));
 }
 
 template <class S, class V>
 static void prolong_black3_t(hipStream_t st, int m, int batch, const void* T, const void* tb,
                              void* z, const void* r, const void* zc, double omega,
-                             const int32_t* active) {
+                             const int32_t* active, int csc) {
   const long long total = (long long)batch * m * m * (m / 2);
   CellDiv cd = make_celldiv(total, (long long)m * m * (m / 2), m);
   cd.mm = make_fastdiv((uint32_t)m * (uint32_t)(m / 2));
   cd.m = make_fastdiv((uint32_t)(m / 2));
   hipLaunchKernelGGL((k_prolong_black3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m,
                      total, (const S*)T, (const S*)tb, (V*)z, (const V*)r, (const S*)zc, omega,
-                     active, cd);
+                     active, csc, cd);
 }
 
 void launch_prolong_black3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
                              const void* tb, void* z, const void* r, const void* zc,
-                             double omega, const int32_t* active) {
-  if (!f32) prolong_black3_t<double, double>(st, m, batch, T, tb, z, r, zc, omega, active);
-  else if (top) prolong_black3_t<float, double>(st, m, batch, T, tb, z, r, zc, omega, active);
-  else prolong_black3_t<float, float>(st, m, batch, T, tb, z, r, zc, omega, active);
+                             double omega, const int32_t* active, bool coarse_split) {
+  const int csc = coarse_split ? 1 : 0;
+  if (!f32) prolong_black3_t<double, double>(st, m, batch, T, tb, z, r, zc, omega, active, csc);
+  else if (top)
+    prolong_black3_t<float, double>(st, m, batch, T, tb, z, r, zc, omega, active, csc);
+  else prolong_black3_t<float, float>(st, m, batch, T, tb, z, r, zc, omega, active, csc);
 }
 
 // rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z); rc in S.
+// z and r in colour-split order (one thread per coarse cell, taken in natural
+// order: the fine cells 2I and 2I + 1 of a row sit at I in the red and the
+// black row); rc in colour-split order when csc is set, else natural.
 template <class S, class V>
 __global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long total, const S* __restrict__ T,
                                   const S* __restrict__ tb, const V* __restrict__ z,
                                   const V* __restrict__ r, S* __restrict__ rc,
-                                  const int32_t* __restrict__ active, CellDiv cd) {
+                                  const int32_t* __restrict__ active, int csc, CellDiv cd) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int mc = m / 2;
@@ -423,28 +460,30 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long tot
       for (int a = 0; a < 2; ++a) {
         const int i = 2 * I + a, j = 2 * J + bb, l = 2 * L + cc;
         const Faces3T<S> f = load_faces3(Ts, tbs, m, i, j, l);
-        const long long c = ((long long)l * m + j) * m + i;
-        acc += (S)rs[c] - (diag3(f) * (S)zs[c] - nsum3(zs, m, i, j, l, f));
+        const long long e = cs3_index(m, i, j, l);
+        acc += (S)rs[e] - (diag3(f) * (S)zs[e] - nsum3_cs(zs, m, i, j, l, f));
       }
-  rc[g] = acc;
+  rc[csc ? s * nc + cs3_index(mc, I, J, L) : g] = acc;
 }
 
 template <class S, class V>
 static void resid_restrict3_t(hipStream_t st, int m, int batch, const void* T, const void* tb,
-                              const void* z, const void* r, void* rc, const int32_t* active) {
+                              const void* z, const void* r, void* rc, const int32_t* active,
+                              int csc) {
   const long long total = (long long)batch * (m / 2) * (m / 2) * (m / 2);
   const CellDiv cd = make_celldiv(total, (long long)(m / 2) * (m / 2) * (m / 2), m / 2);
   hipLaunchKernelGGL((k_resid_restrict3<S, V>), dim3(blocks_for(total)), dim3(kBlock), 0, st, m,
                      total, (const S*)T, (const S*)tb, (const V*)z, (const V*)r, (S*)rc, active,
-                     cd);
+                     csc, cd);
 }
 
 void launch_resid_restrict3_p(hipStream_t st, bool f32, bool top, int m, int batch,
                               const void* T, const void* tb, const void* z, const void* r,
-                              void* rc, const int32_t* active) {
-  if (!f32) resid_restrict3_t<double, double>(st, m, batch, T, tb, z, r, rc, active);
-  else if (top) resid_restrict3_t<float, double>(st, m, batch, T, tb, z, r, rc, active);
-  else resid_restrict3_t<float, float>(st, m, batch, T, tb, z, r, rc, active);
+                              void* rc, const int32_t* active, bool coarse_split) {
+  const int csc = coarse_split ? 1 : 0;
+  if (!f32) resid_restrict3_t<double, double>(st, m, batch, T, tb, z, r, rc, active, csc);
+  else if (top) resid_restrict3_t<float, double>(st, m, batch, T, tb, z, r, rc, active, csc);
+  else resid_restrict3_t<float, float>(st, m, batch, T, tb, z, r, rc, active, csc);
 }
 
 // z = A^-1 r on the coarsest grid for vectors of a reduced-precision
@@ -835,7 +874,9 @@ void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, con
 }
 
 // ------------------------------------------------------------------ PCG stencil kernels
-// Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c.
+// Block b of sample s (blockIdx.x = s * bps + b) owns entries b*1024 + t + 256 c
+// of the sample's vectors, in colour-split order when CS is set.
+template <bool CS>
 __global__ void __launch_bounds__(kBlock)
 k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
             const double* __restrict__ p, double* __restrict__ q, double* __restrict__ partial,
@@ -854,9 +895,11 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
     const long long cell = (long long)blk * kCellsPerBlock + threadIdx.x + c * kBlock;
     if (cell < n) {
       int i, j, l;
-      cell_of(cell, m, i, j, l);
+      if (CS) cs3_cell(m, cell, i, j, l);
+      else cell_of(cell, m, i, j, l);
       const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
-      const double v = diag3(f) * ps[cell] - nsum3(ps, m, i, j, l, f);
+      const double v =
+          diag3(f) * ps[cell] - (CS ? nsum3_cs(ps, m, i, j, l, f) : nsum3(ps, m, i, j, l, f));
       q[s * n + cell] = v;
       acc += ps[cell] * v;
     }
@@ -867,9 +910,66 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
 
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                       const double* p, double* q, double* partial, int bps,
-                      const int32_t* active) {
-  hipLaunchKernelGGL(k_spmv3_dot, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q, partial,
-                     bps, active);
+                      const int32_t* active, bool split) {
+  if (split)
+    hipLaunchKernelGGL(k_spmv3_dot<true>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
+                       partial, bps, active);
+  else
+    hipLaunchKernelGGL(k_spmv3_dot<false>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p,
+                       q, partial, bps, active);
+}
+
+// x = 0 and r = b with r in colour-split order (b natural), and the partial
+// sums of b^2 per block, as k_pcg_init does in the natural order (only: the
+// samples to start, or null for all).
+__global__ void __launch_bounds__(kBlock)
+k_pcg_init3_split(int m, const double* __restrict__ b, double* __restrict__ x,
+                  double* __restrict__ r, double* __restrict__ partial, int bps,
+                  const int32_t* __restrict__ only) {
+  __shared__ double sh[kBlock / kWave];
+  const long long s = blockIdx.x / bps;
+  const int blk = blockIdx.x - (int)(s * bps);
+  if (only && !only[s]) return;
+  const long long n = (long long)m * m * m;
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCellsPerThread; ++c) {
+    const long long e = (long long)blk * kCellsPerBlock + threadIdx.x + c * kBlock;
+    if (e < n) {
+      int i, j, l;
+      cs3_cell(m, e, i, j, l);
+      const double v = b[s * n + ((long long)l * m + j) * m + i];
+      x[s * n + e] = 0.0;
+      r[s * n + e] = v;
+      acc += v * v;
+    }
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_pcg_init3_split(hipStream_t st, int m, int batch, const double* b, double* x,
+                            double* r, double* partial, int bps, const int32_t* only) {
+  hipLaunchKernelGGL(k_pcg_init3_split, dim3(batch * bps), dim3(kBlock), 0, st, m, b, x, r,
+                     partial, bps, only);
+}
+
+// out (natural order) = in (colour-split order), one thread per cell.
+__global__ void k_from_split3(int m, long long total, const double* __restrict__ in,
+                              double* __restrict__ out, CellDiv cd) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long n = (long long)m * m * m;
+  int i, j, l;
+  const long long s = split_cell(g, n, cd, i, j, l);
+  out[g] = in[s * n + cs3_index(m, i, j, l)];
+}
+
+void launch_from_split3(hipStream_t st, int m, int batch, const double* in, double* out) {
+  const long long n = (long long)m * m * m, total = (long long)batch * n;
+  const CellDiv cd = make_celldiv(total, n, m);
+  hipLaunchKernelGGL(k_from_split3, dim3(blocks_for(total)), dim3(kBlock), 0, st, m, total, in,
+                     out, cd);
 }
 
 __global__ void __launch_bounds__(kBlock)

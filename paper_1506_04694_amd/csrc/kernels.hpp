@@ -203,16 +203,18 @@ void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, con
                           double* Ainv);
 // Multigrid sweeps of a 3-D hierarchy in FP64 (f32 false) or with the operator,
 // z and r stored and computed in float (f32 true); on the finest level (top)
-// z and r are the CG's FP64 vectors in either case.
+// z and r are the CG's FP64 vectors in either case.  The swept level's z and
+// r are in colour-split order (cs3.hpp); coarse_split: so is the next coarser
+// level's (else natural: the in-LDS or dense coarsest levels).
 void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
                     const void* tb, void* z, const void* r, const int32_t* active, int color,
                     int zero_init);
 void launch_resid_restrict3_p(hipStream_t st, bool f32, bool top, int m, int batch,
                               const void* T, const void* tb, const void* z, const void* r,
-                              void* rc, const int32_t* active);
+                              void* rc, const int32_t* active, bool coarse_split);
 void launch_prolong_black3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
                              const void* tb, void* z, const void* r, const void* zc,
-                             double omega, const int32_t* active);
+                             double omega, const int32_t* active, bool coarse_split);
 void launch_dense_apply3f(hipStream_t st, int n, int batch, const double* Ainv, const float* r,
                           float* z, const int32_t* active);
 // The cycle on levels l0..L of a 3-D hierarchy (desc: their sizes and
@@ -227,8 +229,15 @@ void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nle
                           const CoarseDesc& desc, const void* img, const void* r0, void* z0,
                           const double* Ainv, double omega, unsigned wmask,
                           const int32_t* active);
+// q = A p and partial sums of p . q; p, q in colour-split order when split.
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
-                      const double* p, double* q, double* partial, int bps, const int32_t* active);
+                      const double* p, double* q, double* partial, int bps, const int32_t* active,
+                      bool split);
+// k_pcg_init with r in colour-split order (b natural).
+void launch_pcg_init3_split(hipStream_t st, int m, int batch, const double* b, double* x,
+                            double* r, double* partial, int bps, const int32_t* only);
+// out (natural order) = in (colour-split order).
+void launch_from_split3(hipStream_t st, int m, int batch, const double* in, double* out);
 void launch_true_residual3(hipStream_t st, int m, int batch, const double* T, const double* tb,
                            const double* b, const double* x, double* partial, int bps);
 void launch_field_pc3(hipStream_t st, const mlmc_model& mdl, int m, int batch,
