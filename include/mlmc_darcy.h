@@ -310,7 +310,7 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
  * made.  Limits and behaviour:
  *   - the solve's workspaces must fit in the 64 MiB array (about 2500 samples
  *     of 64 x 64, 57 of 128 x 128, 14 of 256 x 256 with the FP64 defaults;
- *     3-D: 51 of 32^3); a larger batch is refused with MLMC_EINVAL and a
+ *     3-D: 30 of 32^3); a larger batch is refused with MLMC_EINVAL and a
  *     message naming the workspace that did not fit, before any work is
  *     enqueued;
  *   - opts->graph must be 0 (MLMC_EINVAL otherwise); kernel timing

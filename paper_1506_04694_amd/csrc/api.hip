@@ -798,7 +798,24 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   const int nc = ms[L] * ms[L] * ms[L];
   double* Ainv = nullptr;
   TRY(ws(ctx, "s3_ainv", (size_t)batch * nc * nc, &Ainv));
+  const int nu = opts->nu1;
+  // levels from the first one of side <= 8 (FP64) or 16 (FP32) down run in one
+  // in-LDS kernel (nu = 1; variant 1 keeps the per-sweep launches on every level)
+  int l0 = -1;
+  if (nu == 1 && opts->variant != 1)
+    for (int l = 0; l < L; ++l)
+      if (ms[l] <= coarse3_max_side(f32)) {
+        l0 = l;
+        break;
+      }
+  // the levels above the in-LDS (or else the dense coarsest) one are swept per
+  // launch and keep their faces, z and r in colour-split order; so does the CG
+  // when the finest level is one of them (its x is put back in natural order
+  // at the end)
+  const int lsplit = l0 >= 0 ? l0 : L;
+  auto split = [&](int l) { return l < lsplit; };
   // the operators and vectors the cycle works on, in the hierarchy's type
+  // (the faces of a split level: a colour-split copy)
   std::vector<const void*> Th(L + 1), tbh(L + 1);
   std::vector<void*> zh(L + 1), rh(L + 1);
   for (int l = 0; l <= L; ++l) {
@@ -806,6 +823,11 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     const long long fl = (long long)ms[l] * ms[l];
     if (!f32) {
       Th[l] = Tl[l];
+      if (split(l)) {
+        double* Tcs = nullptr;
+        TRY(ws(ctx, lv("s3_Tcs", l), batch * 3 * nl, &Tcs));
+        Th[l] = Tcs;
+      }
       tbh[l] = tbl[l];
       zh[l] = zl[l];
       rh[l] = rl[l];
@@ -835,28 +857,12 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   TRY(ws(ctx, "s3_count", 1, &S.count));
   int32_t* carried = nullptr;  // iterations of a W pass whose sample restarts with V
   if (opts->gamma == 2) TRY(ws(ctx, "s3_carried", batch, &carried));
-  const int nu = opts->nu1;
   const double omega = opts->omega;
   int cur_gamma = opts->gamma;
   auto visits = [&](int l) {
     return (opts->gamma_levels == 0 || l < opts->gamma_levels) ? cur_gamma : 1;
   };
-  // levels from the first one of side <= 8 (FP64) or 16 (FP32) down run in one
-  // in-LDS kernel (nu = 1; variant 1 keeps the per-sweep launches on every level)
-  int l0 = -1;
   CoarseDesc cdesc{};
-  if (nu == 1 && opts->variant != 1)
-    for (int l = 0; l < L; ++l)
-      if (ms[l] <= coarse3_max_side(f32)) {
-        l0 = l;
-        break;
-      }
-  // the levels above the in-LDS (or else the dense coarsest) one are swept per
-  // launch and keep their z and r in colour-split order; so does the CG when
-  // the finest level is one of them (its x is put back in natural order at
-  // the end)
-  const int lsplit = l0 >= 0 ? l0 : L;
-  auto split = [&](int l) { return l < lsplit; };
   void* cimg = nullptr;  // padded operator image of the in-LDS levels
   if (l0 >= 0) {
     for (int q2 = 0; l0 + q2 <= L; ++q2) {
@@ -872,13 +878,15 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
   for (int l = 1; l <= L; ++l)
     launch_coarsen3(st, ms[l - 1], batch, Tl[l - 1], tbl[l - 1], Tw[l], tbw[l]);
   launch_dense_factor3(st, ms[L], batch, Tl[L], tbl[L], Ainv);
-  if (f32)
-    for (int l = 0; l <= L; ++l) {
-      const long long nl = (long long)ms[l] * ms[l] * ms[l];
-      const long long fl = (long long)ms[l] * ms[l];
+  for (int l = 0; l <= L; ++l) {
+    const long long nl = (long long)ms[l] * ms[l] * ms[l];
+    const long long fl = (long long)ms[l] * ms[l];
+    if (split(l)) launch_faces_split3(st, f32, ms[l], batch, Tl[l], const_cast<void*>(Th[l]));
+    else if (f32)
       launch_convert(st, MLMC_PREC_FP32, batch * 3 * nl, Tl[l], const_cast<void*>(Th[l]));
+    if (f32)
       launch_convert(st, MLMC_PREC_FP32, batch * 3 * fl, tbl[l], const_cast<void*>(tbh[l]));
-    }
+  }
   if (l0 >= 0) launch_coarse3_image(st, f32, batch, L - l0 + 1, cdesc, cimg);
   CHECK_LAUNCH();
   std::function<void(int)> cycle = [&](int l) {
@@ -954,7 +962,11 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
     CHECK_LAUNCH();
     for (int it = 1;; ++it) {
-      launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active, split(0));
+      // the FP64 hierarchy's colour-split copy of the finest faces serves the
+      // operator too
+      if (split(0) && !f32)
+        launch_spmv3_dot(st, m, batch, (const double*)Th[0], tb, pv, q, partial, bps, S.active, 2);
+      else launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active, split(0) ? 1 : 0);
       launch_sc_alpha(st, batch, partial, bps, S, status);
       // flexible form with a reduced-precision cycle: also r_new . z_old
       launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,

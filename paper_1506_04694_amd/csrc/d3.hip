@@ -18,9 +18,10 @@
 // the levels from side 8 (FP64) or 16 (FP32) down in one in-LDS launch per
 // visit; the dense inverse on the coarsest grid (<= 4^3 unknowns).
 //
-// The vectors (z, r and, on the finest level, the CG's x, r, p, q) of every
-// level swept by the per-sweep kernels are stored in colour-split order
-// (cs3.hpp); the faces, k, b and the solution handed back stay in the natural
+// The vectors (z, r and, on the finest level, the CG's x, r, p, q) and the
+// faces T of every level swept by the per-sweep kernels are stored in
+// colour-split order (cs3.hpp), the faces as a copy in the hierarchy's type;
+// k, b, the caller's T and the solution handed back stay in the natural
 // order, and so do the in-LDS and the dense coarsest levels.
 #include <cfloat>
 
@@ -53,6 +54,26 @@ __device__ __forceinline__ Faces3T<S> load_faces3(const S* __restrict__ Ts,
   f.ts = j > 0 ? Ts[n + c - m] : tbs[mm + l * m + i];
   f.tu = Ts[2 * n + c];
   f.td = l > 0 ? Ts[2 * n + c - mm] : tbs[2 * mm + j * m + i];
+  return f;
+}
+
+// The same faces from face arrays in colour-split order (T[a] entry of a cell
+// at its colour-split index): the east, north and up faces at the cell's own
+// index `own`, the west, south and down ones at its neighbours' (nb).
+template <class S>
+__device__ __forceinline__ Faces3T<S> load_faces3_cs(const S* __restrict__ Ts,
+                                                     const S* __restrict__ tbs, int m, int i,
+                                                     int j, int l, long long own,
+                                                     const Cs3Nb& nb) {
+  const long long n = (long long)m * m * m;
+  const int mm = m * m;
+  Faces3T<S> f;
+  f.te = Ts[own];
+  f.tw = i > 0 ? Ts[nb.other + nb.dw] : tbs[l * m + j];
+  f.tn = Ts[n + own];
+  f.ts = j > 0 ? Ts[n + nb.other + nb.ds] : tbs[mm + l * m + i];
+  f.tu = Ts[2 * n + own];
+  f.td = l > 0 ? Ts[2 * n + nb.other + nb.dd] : tbs[2 * mm + j * m + i];
   return f;
 }
 
@@ -310,9 +331,9 @@ void launch_coarsen3(hipStream_t st, int m, int batch, const double* T, const do
 }
 
 // ------------------------------------------------------------------ smoother
-// One thread per cell of the colour ((i + j + l) % 2 == color); m even; z and
-// r in colour-split order, so thread g of sample s reads r and writes z at
-// color m^3/2 + (g - s m^3/2).
+// One thread per cell of the colour ((i + j + l) % 2 == color); m even; T, z
+// and r in colour-split order, so thread g of sample s reads r and writes z
+// at color m^3/2 + (g - s m^3/2).
 // S: operator storage and arithmetic type; V: type of the level's z and r
 // (double on the finest level, whose z and r are the CG's).
 template <class S, class V>
@@ -331,9 +352,10 @@ __global__ void k_rbgs3(int m, long long total, const S* __restrict__ T,
   if (!active[s]) return;
   const int i = 2 * h + ((j + l + color) & 1);
   const long long n = (long long)m * m * m;
-  const Faces3T<S> f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
   V* zs = z + s * n;
   const long long e = (long long)color * per + (g - s * per);
+  const Faces3T<S> f = load_faces3_cs(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l, e,
+                                      cs3_neighbours(m, i, j, l));
   const S rv = (S)r[s * n + e];
   zs[e] = (V)(zero_init ? rv / diag3(f) : (rv + nsum3_cs(zs, m, i, j, l, f)) / diag3(f));
 }
@@ -365,8 +387,8 @@ void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const 
 // black cells (one thread each) from neighbours z_n + omega zc(parent of n),
 // formed as the prolongation forms them (in V), and writes nothing else: the
 // arithmetic of a separate prolongation pass followed by k_rbgs3 on the black
-// cells.  z and r in colour-split order; zc in colour-split order when csc is
-// set (the coarse level is swept per launch too), else natural.
+// cells.  T, z and r in colour-split order; zc in colour-split order when csc
+// is set (the coarse level is swept per launch too), else natural.
 template <class S, class V>
 __global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T,
                                  const S* __restrict__ tb, V* __restrict__ z,
@@ -383,13 +405,14 @@ __global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T
   const int i = 2 * h + ((j + l + 1) & 1);
   const long long n = (long long)m * m * m;
   const int mc = m / 2;
-  const Faces3T<S> f = load_faces3(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l);
+  const long long e = per + (g - s * per);  // black block
+  const Cs3Nb nb = cs3_neighbours(m, i, j, l);
+  const Faces3T<S> f = load_faces3_cs(T + s * 3 * n, tb + s * 3 * m * m, m, i, j, l, e, nb);
   V* zs = z + s * n;
   const S* zcs = zc + s * (long long)mc * mc * mc;
   const V w = (V)omega;
   // the red neighbour at offset d of the red row entry, prolonged from the
   // coarse cell holding fine cell (ii, jj, ll)
-  const Cs3Nb nb = cs3_neighbours(m, i, j, l);
   const V* zo = zs + nb.other;
   auto pz = [&](int d, int ii, int jj, int ll) -> S {
     const int I = ii >> 1, J = jj >> 1, L = ll >> 1;
@@ -403,7 +426,6 @@ __global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T
   if (j > 0) o += f.ts * pz(nb.ds, i, j - 1, l);
   if (l < m - 1) o += f.tu * pz(nb.du, i, j, l + 1);
   if (l > 0) o += f.td * pz(nb.dd, i, j, l - 1);
-  const long long e = per + (g - s * per);  // black block
   const S rv = (S)r[s * n + e];
   zs[e] = (V)((rv + o) / diag3(f));
 }
@@ -432,7 +454,7 @@ void launch_prolong_black3_p(hipStream_t st, bool f32, bool top, int m, int batc
 }
 
 // rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z); rc in S.
-// z and r in colour-split order (one thread per coarse cell, taken in natural
+// T, z and r in colour-split order (one thread per coarse cell, taken in natural
 // order: the fine cells 2I and 2I + 1 of a row sit at I in the red and the
 // black row); rc in colour-split order when csc is set, else natural.
 template <class S, class V>
@@ -459,8 +481,8 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long tot
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int i = 2 * I + a, j = 2 * J + bb, l = 2 * L + cc;
-        const Faces3T<S> f = load_faces3(Ts, tbs, m, i, j, l);
         const long long e = cs3_index(m, i, j, l);
+        const Faces3T<S> f = load_faces3_cs(Ts, tbs, m, i, j, l, e, cs3_neighbours(m, i, j, l));
         acc += (S)rs[e] - (diag3(f) * (S)zs[e] - nsum3_cs(zs, m, i, j, l, f));
       }
   rc[csc ? s * nc + cs3_index(mc, I, J, L) : g] = acc;
@@ -875,8 +897,9 @@ void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, con
 
 // ------------------------------------------------------------------ PCG stencil kernels
 // Block b of sample s (blockIdx.x = s * bps + b) owns entries b*1024 + t + 256 c
-// of the sample's vectors, in colour-split order when CS is set.
-template <bool CS>
+// of the sample's vectors, in colour-split order when CS > 0; the faces T in
+// colour-split order too when CS = 2.
+template <int CS>
 __global__ void __launch_bounds__(kBlock)
 k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
             const double* __restrict__ p, double* __restrict__ q, double* __restrict__ partial,
@@ -897,7 +920,8 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
       int i, j, l;
       if (CS) cs3_cell(m, cell, i, j, l);
       else cell_of(cell, m, i, j, l);
-      const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
+      const Faces3 f = CS == 2 ? load_faces3_cs(Ts, tbs, m, i, j, l, cell, cs3_neighbours(m, i, j, l))
+                               : load_faces3(Ts, tbs, m, i, j, l);
       const double v =
           diag3(f) * ps[cell] - (CS ? nsum3_cs(ps, m, i, j, l, f) : nsum3(ps, m, i, j, l, f));
       q[s * n + cell] = v;
@@ -910,13 +934,41 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
 
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                       const double* p, double* q, double* partial, int bps,
-                      const int32_t* active, bool split) {
-  if (split)
-    hipLaunchKernelGGL(k_spmv3_dot<true>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
+                      const int32_t* active, int split) {
+  if (split == 2)
+    hipLaunchKernelGGL(k_spmv3_dot<2>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
+                       partial, bps, active);
+  else if (split == 1)
+    hipLaunchKernelGGL(k_spmv3_dot<1>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
                        partial, bps, active);
   else
-    hipLaunchKernelGGL(k_spmv3_dot<false>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p,
-                       q, partial, bps, active);
+    hipLaunchKernelGGL(k_spmv3_dot<0>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
+                       partial, bps, active);
+}
+
+// Ts (colour-split order, type S) = T (natural order, FP64), the three face
+// arrays of each sample; one thread per destination entry.
+template <class S>
+__global__ void k_faces_split3(int m, long long total, const double* __restrict__ T,
+                               S* __restrict__ Ts) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const long long n = (long long)m * m * m;
+  const long long a = g / n;  // sample * 3 + face array
+  const long long e = g - a * n;
+  int i, j, l;
+  cs3_cell(m, e, i, j, l);
+  Ts[g] = (S)T[a * n + ((long long)l * m + j) * m + i];
+}
+
+void launch_faces_split3(hipStream_t st, bool f32, int m, int batch, const double* T, void* Ts) {
+  const long long total = (long long)batch * 3 * m * m * m;
+  if (f32)
+    hipLaunchKernelGGL(k_faces_split3<float>, dim3(blocks_for(total)), dim3(kBlock), 0, st, m,
+                       total, T, (float*)Ts);
+  else
+    hipLaunchKernelGGL(k_faces_split3<double>, dim3(blocks_for(total)), dim3(kBlock), 0, st, m,
+                       total, T, (double*)Ts);
 }
 
 // x = 0 and r = b with r in colour-split order (b natural), and the partial

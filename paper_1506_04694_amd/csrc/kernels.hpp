@@ -203,9 +203,9 @@ void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, con
                           double* Ainv);
 // Multigrid sweeps of a 3-D hierarchy in FP64 (f32 false) or with the operator,
 // z and r stored and computed in float (f32 true); on the finest level (top)
-// z and r are the CG's FP64 vectors in either case.  The swept level's z and
-// r are in colour-split order (cs3.hpp); coarse_split: so is the next coarser
-// level's (else natural: the in-LDS or dense coarsest levels).
+// z and r are the CG's FP64 vectors in either case.  The swept level's T, z
+// and r are in colour-split order (cs3.hpp); coarse_split: so are the next
+// coarser level's z and r (else natural: the in-LDS or dense coarsest levels).
 void launch_rbgs3_p(hipStream_t st, bool f32, bool top, int m, int batch, const void* T,
                     const void* tb, void* z, const void* r, const int32_t* active, int color,
                     int zero_init);
@@ -229,10 +229,13 @@ void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nle
                           const CoarseDesc& desc, const void* img, const void* r0, void* z0,
                           const double* Ainv, double omega, unsigned wmask,
                           const int32_t* active);
-// q = A p and partial sums of p . q; p, q in colour-split order when split.
+// q = A p and partial sums of p . q; p, q in colour-split order when split > 0,
+// and T too when split == 2.
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                       const double* p, double* q, double* partial, int bps, const int32_t* active,
-                      bool split);
+                      int split);
+// Ts (colour-split order; float when f32, else double) = T (natural, FP64).
+void launch_faces_split3(hipStream_t st, bool f32, int m, int batch, const double* T, void* Ts);
 // k_pcg_init with r in colour-split order (b natural).
 void launch_pcg_init3_split(hipStream_t st, int m, int batch, const double* b, double* x,
                             double* r, double* partial, int bps, const int32_t* only);

@@ -97,16 +97,18 @@ int n_ce_for(const mlmc_server* s, int model, int m) {
 }
 
 // Device bytes of one request's share of a batch: k, T (d), b, p, r, z, p, q,
-// z_pre and the multigrid hierarchy (about 1/3 of a level per array), plus the
-// companions on the coarse grid (1 plain, 2^d with CGV), all FP64, and the
-// circulant-embedding scratch (2-D: n m; 3-D: n^2 m + n m^2 complex values).
+// z_pre and the multigrid hierarchy (about 1/3 of a level per array; in 3-D
+// also the colour-split copy of the swept levels' faces, 8/7 of the finest
+// level's), plus the companions on the coarse grid (1 plain, 2^d with CGV), all
+// FP64, and the circulant-embedding scratch (2-D: n m; 3-D: n^2 m + n m^2
+// complex values).
 uint64_t request_bytes(const mlmc_server* s, const mlmc_request& r) {
   const mlmc_model& mdl = s->models[r.model];
   const int d = mdl.dim;
   const double m = (double)r.m_fine;
   const double cells = d == 3 ? m * m * m : m * m;
   const double ncomp = r.level == 0 ? 0.0 : (s->opts.cgv ? (double)(1 << d) : 1.0);
-  const double per_cell = 8.0 * (10.0 + (d + 2) * 4.0 / 3.0);
+  const double per_cell = 8.0 * (10.0 + (d + 2) * 4.0 / 3.0 + (d == 3 ? 3.0 * 8.0 / 7.0 : 0.0));
   double ce = 0.0;
   const double nce = (double)n_ce_for(s, r.model, r.m_fine);
   if (mdl.field_kind == MLMC_FIELD_CORRELATED)
