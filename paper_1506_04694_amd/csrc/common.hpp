@@ -15,6 +15,15 @@ constexpr int kCellsPerThread = 4;   // cells per thread in per-sample vector ke
 constexpr int kCellsPerBlock = kBlock * kCellsPerThread;
 constexpr int kWave = 64;
 
+// XCD-aware block order: hardware dispatches consecutive workgroup ids round
+// robin over the 8 XCDs; give XCD x a contiguous range of logical ids (a
+// bijection of [0, nblocks)), so that neighbouring blocks share its L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int x = bid & 7, q = bid >> 3;
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
 // bfloat16 storage (the upper half of an FP32 value); arithmetic is done in FP32.
 struct bf16_t {
   uint16_t bits;

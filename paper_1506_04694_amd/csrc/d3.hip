@@ -341,7 +341,8 @@ __global__ void k_rbgs3(int m, long long total, const S* __restrict__ T,
                         const S* __restrict__ tb, V* __restrict__ z,
                         const V* __restrict__ r, const int32_t* __restrict__ active,
                         int color, int zero_init, CellDiv cd) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // rows of a sample that share z and face lines run on one XCD
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int half = m / 2;
   const long long per = (long long)m * m * half;
@@ -395,7 +396,8 @@ __global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T
                                  const V* __restrict__ r, const S* __restrict__ zc,
                                  double omega, const int32_t* __restrict__ active, int csc,
                                  CellDiv cd) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // rows of a sample that share z and face lines run on one XCD
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int half = m / 2;
   const long long per = (long long)m * m * half;
@@ -462,7 +464,8 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long tot
                                   const S* __restrict__ tb, const V* __restrict__ z,
                                   const V* __restrict__ r, S* __restrict__ rc,
                                   const int32_t* __restrict__ active, int csc, CellDiv cd) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // rows of a sample that share z and face lines run on one XCD
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int mc = m / 2;
   const long long nc = (long long)mc * mc * mc, n = (long long)m * m * m;

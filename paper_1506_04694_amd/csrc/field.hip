@@ -31,14 +31,6 @@
 
 namespace mlmc {
 
-// XCD-aware block order: hardware dispatches consecutive workgroup ids round
-// robin over the 8 XCDs; give XCD x a contiguous range of logical ids.
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  const int x = bid & 7, q = bid >> 3;
-  const int per = nblocks >> 3, rem = nblocks & 7;
-  return x * per + (x < rem ? x : rem) + q;
-}
-
 // ------------------------------------------------------------ per-sample parameters
 __global__ void k_sample_params(mlmc_model mdl, uint32_t level, uint64_t first,
                                 const uint32_t* __restrict__ ids, int batch,
