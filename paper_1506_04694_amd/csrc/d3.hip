@@ -676,12 +676,27 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
   __syncthreads();
   E* vec = lds + off;  // coarsest right-hand side
   // operators from the image (linear copy), r and z zero, r of the first level
-  // from r0
+  // from r0.  Each thread issues its global loads in groups of kCopyU before
+  // storing any of them, so a group costs one memory latency instead of one
+  // per word (one workgroup per CU: nothing else hides that latency).
+  constexpr int kCopyU = 8;
   const E* im = img + (long long)s * img_words;
   for (int q = 0; q < nlev; ++q) {
     const int P = lv[q].P, PPP = P * P * P;
     E* a = lds + lv[q].off;
-    for (int w = threadIdx.x; w < 3 * PPP; w += NT) a[w] = im[w];
+    for (int w0 = threadIdx.x; w0 < 3 * PPP; w0 += kCopyU * NT) {
+      E v[kCopyU];
+#pragma unroll
+      for (int u = 0; u < kCopyU; ++u) {
+        const int w = w0 + u * NT;
+        v[u] = w < 3 * PPP ? im[w] : E(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kCopyU; ++u) {
+        const int w = w0 + u * NT;
+        if (w < 3 * PPP) a[w] = v[u];
+      }
+    }
     for (int w = threadIdx.x; w < 2 * PPP; w += NT) a[3 * PPP + w] = E(0);
     im += 3 * PPP;
   }
@@ -689,12 +704,24 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
   {
     const int m = lv[0].m, P = lv[0].P, PPP = P * P * P;
     E* rr = lds + lv[0].off + 3 * PPP;
-    const long long n = (long long)m * m * m;
+    const int n = m * m * m;
     const float inv_m = lv[0].inv_m;
-    for (int c = threadIdx.x; c < n; c += NT) {
-      const int row = div_small(c, inv_m), i = c - row * m;  // row = l m + j
-      const int l = div_small(row, inv_m), j = row - l * m;
-      rr[pidx3(P, i, j, l)] = (E)r0[(long long)s * n + c];
+    for (int c0 = threadIdx.x; c0 < n; c0 += kCopyU * NT) {
+      V v[kCopyU];
+#pragma unroll
+      for (int u = 0; u < kCopyU; ++u) {
+        const int c = c0 + u * NT;
+        v[u] = c < n ? r0[(long long)s * n + c] : V(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kCopyU; ++u) {
+        const int c = c0 + u * NT;
+        if (c < n) {
+          const int row = div_small(c, inv_m), i = c - row * m;  // row = l m + j
+          const int l = div_small(row, inv_m), j = row - l * m;
+          rr[pidx3(P, i, j, l)] = (E)v[u];
+        }
+      }
     }
   }
   __syncthreads();
@@ -718,11 +745,18 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
       __syncthreads();
       // row c of the inverse by the 16 lanes t = 16 c + k (entries k, k + 16, ...),
       // summed over the lane group; groups never straddle the loop bound
+      // (nc <= 64: at most four entries per lane, loaded before the sum)
       const double* A = Ainv + (long long)s * nc * nc;
       for (int t = threadIdx.x; t < 16 * nc; t += NT) {
         const int c = t >> 4, k = t & 15;
+        double av[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          av[u] = k + 16 * u < nc ? A[(long long)c * nc + k + 16 * u] : 0.0;
         double acc = 0.0;
-        for (int p2 = k; p2 < nc; p2 += 16) acc += A[(long long)c * nc + p2] * (double)vec[p2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k + 16 * u < nc) acc += av[u] * (double)vec[k + 16 * u];
         acc += __shfl_xor(acc, 8, 16);
         acc += __shfl_xor(acc, 4, 16);
         acc += __shfl_xor(acc, 2, 16);
@@ -908,8 +942,10 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
             const double* __restrict__ p, double* __restrict__ q, double* __restrict__ partial,
             int bps, const int32_t* __restrict__ active) {
   __shared__ double sh[kBlock / kWave];
-  const long long s = blockIdx.x / bps;
-  const int blk = blockIdx.x - (int)(s * bps);
+  // blocks of neighbouring rows and planes run on one XCD
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long s = lb / bps;
+  const int blk = lb - (int)(s * bps);
   if (!active[s]) return;
   const long long n = (long long)m * m * m;
   const double* Ts = T + s * 3 * n;
@@ -932,7 +968,7 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lb] = t;
 }
 
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
@@ -982,8 +1018,10 @@ k_pcg_init3_split(int m, const double* __restrict__ b, double* __restrict__ x,
                   double* __restrict__ r, double* __restrict__ partial, int bps,
                   const int32_t* __restrict__ only) {
   __shared__ double sh[kBlock / kWave];
-  const long long s = blockIdx.x / bps;
-  const int blk = blockIdx.x - (int)(s * bps);
+  // blocks of neighbouring rows and planes run on one XCD
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long s = lb / bps;
+  const int blk = lb - (int)(s * bps);
   if (only && !only[s]) return;
   const long long n = (long long)m * m * m;
   double acc = 0.0;
@@ -1000,7 +1038,7 @@ k_pcg_init3_split(int m, const double* __restrict__ b, double* __restrict__ x,
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lb] = t;
 }
 
 void launch_pcg_init3_split(hipStream_t st, int m, int batch, const double* b, double* x,
@@ -1032,8 +1070,10 @@ k_true_residual3(int m, const double* __restrict__ T, const double* __restrict__
                  const double* __restrict__ b, const double* __restrict__ x,
                  double* __restrict__ partial, int bps) {
   __shared__ double sh[kBlock / kWave];
-  const long long s = blockIdx.x / bps;
-  const int blk = blockIdx.x - (int)(s * bps);
+  // blocks of neighbouring rows and planes run on one XCD
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long s = lb / bps;
+  const int blk = lb - (int)(s * bps);
   const long long n = (long long)m * m * m;
   const double* Ts = T + s * 3 * n;
   const double* tbs = tb + s * 3 * m * m;
@@ -1051,7 +1091,7 @@ k_true_residual3(int m, const double* __restrict__ T, const double* __restrict__
     }
   }
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[lb] = t;
 }
 
 void launch_true_residual3(hipStream_t st, int m, int batch, const double* T, const double* tb,

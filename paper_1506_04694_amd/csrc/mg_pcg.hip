@@ -517,7 +517,19 @@ __device__ __forceinline__ double sum_partials_t(const double* __restrict__ part
                                                  int s, int lane) {
   double acc = 0.0;
   if (WIDE) {
-    for (int q = lane; q < bps; q += kWave) acc += partial[(long long)s * bps + q];
+    // lane k adds entries k, k + 64, ... in that order; the loads of a group
+    // of eight are issued before its adds, so a group costs one memory
+    // latency (thousands of partials per sample on the large 3-D grids)
+    constexpr int kU = 8;
+    const double* ps = partial + (long long)s * bps;
+    for (int q0 = lane; q0 < bps; q0 += kU * kWave) {
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) v[u] = q0 + u * kWave < bps ? ps[q0 + u * kWave] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (q0 + u * kWave < bps) acc += v[u];
+    }
     return wave_sum(acc);
   }
   for (int q = 0; q < bps; ++q) acc += partial[(long long)s * bps + q];
