@@ -458,7 +458,11 @@ void launch_prolong_black3_p(hipStream_t st, bool f32, bool top, int m, int batc
 // rc(I, J, L) = sum over the 2 x 2 x 2 fine cells of (r - A z); rc in S.
 // T, z and r in colour-split order (one thread per coarse cell, taken in natural
 // order: the fine cells 2I and 2I + 1 of a row sit at I in the red and the
-// black row); rc in colour-split order when csc is set, else natural.
+// black row); rc in colour-split order when csc is set, else natural.  Each
+// value the eight residuals use is loaded once: z and the faces of the block's
+// four rows, z of the eight rows beside it in x2 and x3, the faces below and
+// south of it, and z and the east face west of it; the sums are those of
+// nsum3_cs and diag3, term by term.
 template <class S, class V>
 __global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long total, const S* __restrict__ T,
                                   const S* __restrict__ tb, const V* __restrict__ z,
@@ -467,15 +471,59 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long tot
   // rows of a sample that share z and face lines run on one XCD
   const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
-  const int mc = m / 2;
+  const int mc = m / 2, half = m / 2;
   const long long nc = (long long)mc * mc * mc, n = (long long)m * m * m;
   int I, J, L;
   const long long s = split_cell(g, nc, cd, I, J, L);
   if (!active[s]) return;
-  const S* Ts = T + s * 3 * n;
+  const S* Te = T + s * 3 * n;  // east, north and up faces
+  const S* Tn = Te + n;
+  const S* Tu = Tn + n;
   const S* tbs = tb + s * 3 * m * m;
   const V* zs = z + s * n;
   const V* rs = r + s * n;
+  const int nh = (int)(n / 2), mm = m * m;
+  // colour-split position of cell 2I + a of row (jj, ll); 2I - 1 sits one
+  // before that of 2I + 1, 2I + 2 one after that of 2I
+  auto pos = [&](int a, int jj, int ll) -> int {
+    return ((a + jj + ll) & 1) * nh + (ll * m + jj) * half + I;
+  };
+  const int j0 = 2 * J, l0 = 2 * L;
+  const bool hasW = I > 0, hasE = I < mc - 1, hasS = J > 0, hasN = J < mc - 1, hasD = L > 0,
+             hasU = L < mc - 1;
+  // rows by (dl, dj) = (ll - l0 + 1, jj - j0 + 1): the block's rows are 1..2 in
+  // both, the rows beside it 0 and 3 in one of them
+  V zv[4][4][2], rv[2][2][2], zw[2][2], ze[2][2];
+  S te[4][4][2], tn[4][4][2], tu[4][4][2], tew[2][2];
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const int jj = j0 + bb, ll = l0 + cc;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int q = pos(a, jj, ll);
+        zv[cc + 1][bb + 1][a] = zs[q];
+        rv[cc][bb][a] = rs[q];
+        te[cc + 1][bb + 1][a] = Te[q];
+        tn[cc + 1][bb + 1][a] = Tn[q];
+        tu[cc + 1][bb + 1][a] = Tu[q];
+      }
+      zw[cc][bb] = hasW ? zs[pos(1, jj, ll) - 1] : V(0);
+      tew[cc][bb] = hasW ? Te[pos(1, jj, ll) - 1] : S(0);
+      ze[cc][bb] = hasE ? zs[pos(0, jj, ll) + 1] : V(0);
+    }
+#pragma unroll
+  for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      zv[c2 + 1][0][a] = hasS ? zs[pos(a, j0 - 1, l0 + c2)] : V(0);
+      tn[c2 + 1][0][a] = hasS ? Tn[pos(a, j0 - 1, l0 + c2)] : S(0);
+      zv[c2 + 1][3][a] = hasN ? zs[pos(a, j0 + 2, l0 + c2)] : V(0);
+      zv[0][c2 + 1][a] = hasD ? zs[pos(a, j0 + c2, l0 - 1)] : V(0);
+      tu[0][c2 + 1][a] = hasD ? Tu[pos(a, j0 + c2, l0 - 1)] : S(0);
+      zv[3][c2 + 1][a] = hasU ? zs[pos(a, j0 + c2, l0 + 2)] : V(0);
+    }
   S acc = S(0);
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc)
@@ -483,10 +531,23 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict3(int m, long long tot
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const int i = 2 * I + a, j = 2 * J + bb, l = 2 * L + cc;
-        const long long e = cs3_index(m, i, j, l);
-        const Faces3T<S> f = load_faces3_cs(Ts, tbs, m, i, j, l, e, cs3_neighbours(m, i, j, l));
-        acc += (S)rs[e] - (diag3(f) * (S)zs[e] - nsum3_cs(zs, m, i, j, l, f));
+        const int dl = cc + 1, dj = bb + 1;
+        const int i = 2 * I + a, j = j0 + bb, l = l0 + cc;
+        Faces3T<S> f;
+        f.te = te[dl][dj][a];
+        f.tw = a == 1 ? te[dl][dj][0] : (hasW ? tew[cc][bb] : tbs[l * m + j]);
+        f.tn = tn[dl][dj][a];
+        f.ts = (bb == 1 || hasS) ? tn[dl][dj - 1][a] : tbs[mm + l * m + i];
+        f.tu = tu[dl][dj][a];
+        f.td = (cc == 1 || hasD) ? tu[dl - 1][dj][a] : tbs[2 * mm + j * m + i];
+        S o = S(0);
+        if (i < m - 1) o += f.te * (S)(a == 0 ? zv[dl][dj][1] : ze[cc][bb]);
+        if (i > 0) o += f.tw * (S)(a == 1 ? zv[dl][dj][0] : zw[cc][bb]);
+        if (j < m - 1) o += f.tn * (S)zv[dl][dj + 1][a];
+        if (j > 0) o += f.ts * (S)zv[dl][dj - 1][a];
+        if (l < m - 1) o += f.tu * (S)zv[dl + 1][dj][a];
+        if (l > 0) o += f.td * (S)zv[dl - 1][dj][a];
+        acc += (S)rv[cc][bb][a] - (diag3(f) * (S)zv[dl][dj][a] - o);
       }
   rc[csc ? s * nc + cs3_index(mc, I, J, L) : g] = acc;
 }
@@ -933,9 +994,10 @@ void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, con
 }
 
 // ------------------------------------------------------------------ PCG stencil kernels
-// Block b of sample s (blockIdx.x = s * bps + b) owns entries b*1024 + t + 256 c
-// of the sample's vectors, in colour-split order when CS > 0; the faces T in
-// colour-split order too when CS = 2.
+// Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c of
+// the sample: in natural order with natural faces (CS = 0: p, q natural; CS = 1:
+// p, q in colour-split order), or in colour-split order with the faces T in
+// that order too (CS = 2).
 template <int CS>
 __global__ void __launch_bounds__(kBlock)
 k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
@@ -957,14 +1019,21 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
     const long long cell = (long long)blk * kCellsPerBlock + threadIdx.x + c * kBlock;
     if (cell < n) {
       int i, j, l;
-      if (CS) cs3_cell(m, cell, i, j, l);
-      else cell_of(cell, m, i, j, l);
-      const Faces3 f = CS == 2 ? load_faces3_cs(Ts, tbs, m, i, j, l, cell, cs3_neighbours(m, i, j, l))
+      // entry e of p and q: with natural faces (CS < 2) the threads take the
+      // cells in natural order, so that the face loads stay contiguous
+      long long e = cell;
+      if (CS == 2) {
+        cs3_cell(m, cell, i, j, l);
+      } else {
+        cell_of(cell, m, i, j, l);
+        if (CS) e = cs3_index(m, i, j, l);
+      }
+      const Faces3 f = CS == 2 ? load_faces3_cs(Ts, tbs, m, i, j, l, e, cs3_neighbours(m, i, j, l))
                                : load_faces3(Ts, tbs, m, i, j, l);
       const double v =
-          diag3(f) * ps[cell] - (CS ? nsum3_cs(ps, m, i, j, l, f) : nsum3(ps, m, i, j, l, f));
-      q[s * n + cell] = v;
-      acc += ps[cell] * v;
+          diag3(f) * ps[e] - (CS ? nsum3_cs(ps, m, i, j, l, f) : nsum3(ps, m, i, j, l, f));
+      q[s * n + e] = v;
+      acc += ps[e] * v;
     }
   }
   const double t = block_sum(acc, sh);
