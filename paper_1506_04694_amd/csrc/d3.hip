@@ -612,13 +612,13 @@ struct Lds3Cfg;
 template <>
 struct Lds3Cfg<double> {
   static constexpr int kMax = 8, kThreads = 256;
-  // 5 (m + 2)^3 words for m = 8, 4, 2, 1 and the coarsest right-hand side
-  static constexpr int kWords = 5 * (1000 + 216 + 64 + 27) + 64;
+  // 5 (m + 2)^3 words for m = 8, 4, 2, 1
+  static constexpr int kWords = 5 * (1000 + 216 + 64 + 27);
 };
 template <>
 struct Lds3Cfg<float> {
   static constexpr int kMax = 16, kThreads = 1024;
-  static constexpr int kWords = 5 * (5832 + 1000 + 216 + 64 + 27) + 64;
+  static constexpr int kWords = 5 * (5832 + 1000 + 216 + 64 + 27);
 };
 
 struct Lds3Level {
@@ -727,24 +727,22 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
   // the level table in LDS: the loops below index it by the running level, a
   // per-thread array would live in scratch memory
   __shared__ Lds3Level lv[kMaxCoarseLevels];
-  int off = 0;
-  for (int q = 0; q < nlev; ++q) {
-    const int mq = desc.m[q], P = mq + 2;
-    if (threadIdx.x == 0)
-      lv[q] = Lds3Level{mq, P, off, 1.0f / (float)mq, 1.0f / (float)(mq / 2 > 0 ? mq / 2 : 1)};
-    off += 5 * P * P * P;
-  }
-  __syncthreads();
-  E* vec = lds + off;  // coarsest right-hand side
-  // operators from the image (linear copy), r and z zero, r of the first level
-  // from r0.  Each thread issues its global loads in groups of kCopyU before
-  // storing any of them, so a group costs one memory latency instead of one
-  // per word (one workgroup per CU: nothing else hides that latency).
+  // One phase before the cycle: the level table (thread 0), the operators from
+  // the image (linear copy), z zero (its frame is read as the boundary cells'
+  // neighbours), and r of the first level from r0.  The frame of r is never
+  // read, and the restriction writes the interior of a coarser level's r
+  // before it is read, so r is not cleared.  Each thread issues its global
+  // loads in groups of kCopyU before storing any of them, so a group costs one
+  // memory latency instead of one per word (one workgroup per CU: nothing else
+  // hides that latency).
   constexpr int kCopyU = 8;
   const E* im = img + (long long)s * img_words;
+  int off = 0;
   for (int q = 0; q < nlev; ++q) {
-    const int P = lv[q].P, PPP = P * P * P;
-    E* a = lds + lv[q].off;
+    const int mq = desc.m[q], P = mq + 2, PPP = P * P * P;
+    if (threadIdx.x == 0)
+      lv[q] = Lds3Level{mq, P, off, 1.0f / (float)mq, 1.0f / (float)(mq / 2 > 0 ? mq / 2 : 1)};
+    E* a = lds + off;
     for (int w0 = threadIdx.x; w0 < 3 * PPP; w0 += kCopyU * NT) {
       E v[kCopyU];
 #pragma unroll
@@ -758,15 +756,15 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
         if (w < 3 * PPP) a[w] = v[u];
       }
     }
-    for (int w = threadIdx.x; w < 2 * PPP; w += NT) a[3 * PPP + w] = E(0);
+    for (int w = threadIdx.x; w < PPP; w += NT) a[4 * PPP + w] = E(0);
     im += 3 * PPP;
+    off += 5 * PPP;
   }
-  __syncthreads();
   {
-    const int m = lv[0].m, P = lv[0].P, PPP = P * P * P;
-    E* rr = lds + lv[0].off + 3 * PPP;
+    const int m = desc.m[0], P = m + 2, PPP = P * P * P;
+    E* rr = lds + 3 * PPP;  // level 0 sits at offset 0
     const int n = m * m * m;
-    const float inv_m = lv[0].inv_m;
+    const float inv_m = 1.0f / (float)m;
     for (int c0 = threadIdx.x; c0 < n; c0 += kCopyU * NT) {
       V v[kCopyU];
 #pragma unroll
@@ -801,9 +799,6 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
     E* zz = a + 4 * PPP;
     if (q == nlev - 1) {
       const int nc = m * m * m;
-      for (int c = threadIdx.x; c < nc; c += NT)
-        vec[c] = rr[pidx3(P, c % m, (c / m) % m, c / (m * m))];
-      __syncthreads();
       // row c of the inverse by the 16 lanes t = 16 c + k (entries k, k + 16, ...),
       // summed over the lane group; groups never straddle the loop bound
       // (nc <= 64: at most four entries per lane, loaded before the sum)
@@ -816,8 +811,10 @@ k_coarse3_cycle(int nlev, CoarseDesc desc, const E* __restrict__ img, int img_wo
           av[u] = k + 16 * u < nc ? A[(long long)c * nc + k + 16 * u] : 0.0;
         double acc = 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k + 16 * u < nc) acc += av[u] * (double)vec[k + 16 * u];
+        for (int u = 0; u < 4; ++u) {
+          const int p2 = k + 16 * u;
+          if (p2 < nc) acc += av[u] * (double)rr[pidx3(P, p2 % m, (p2 / m) % m, p2 / (m * m))];
+        }
         acc += __shfl_xor(acc, 8, 16);
         acc += __shfl_xor(acc, 4, 16);
         acc += __shfl_xor(acc, 2, 16);
