@@ -1325,17 +1325,34 @@ k_ce3_pass_b(int m, const double2* __restrict__ u1, const double2* __restrict__ 
   double* sre = lds;
   double* sim = lds + L * n;
   const int per_k3 = (m + L - 1) / L;
-  const long long s = blockIdx.x / groups;
-  const int rem = blockIdx.x - (int)(s * groups);
+  // the workgroups of adjacent j1 read adjacent pieces of the same lines: one
+  // XCD (and its L2) takes a contiguous range of them
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const long long s = bid / groups;
+  const int rem = bid - (int)(s * groups);
   const int k3 = rem / per_k3;
   const int j1_0 = (rem - k3 * per_k3) * L;
   const int lines = min(L, m - j1_0);
   const double2* in = u1 + ((long long)s * n * n + (long long)k3 * n) * m + j1_0;
-  for (int t = threadIdx.x; t < L * n; t += T) {
-    const int k2 = t / L, q = t - k2 * L;  // L adjacent j1 of row k2 are contiguous
-    const double2 v = q < lines ? in[(long long)k2 * m + q] : make_double2(0.0, 0.0);
-    sre[q * n + k2] = v.x;
-    sim[q * n + k2] = v.y;
+  // loads in groups of kU issued before their stores
+  constexpr int kU = 8;
+  for (int t0 = threadIdx.x; t0 < L * n; t0 += kU * T) {
+    double2 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * T;
+      const int k2 = t / L, q = t - k2 * L;  // L adjacent j1 of row k2 are contiguous
+      v[u] = t < L * n && q < lines ? in[(long long)k2 * m + q] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * T;
+      const int k2 = t / L, q = t - k2 * L;
+      if (t < L * n) {
+        sre[q * n + k2] = v[u].x;
+        sim[q * n + k2] = v[u].y;
+      }
+    }
   }
   __syncthreads();
   if constexpr (C == 0) {
@@ -1367,18 +1384,35 @@ k_ce3_pass_c(int kind, int n_nodes, int n_layers, CePair pr, int m,
   double* sre = lds;
   double* sim = lds + L * n;
   const int per_j2 = (m + L - 1) / L;
-  const long long s = blockIdx.x / groups;
-  const int rem = blockIdx.x - (int)(s * groups);
+  // adjacent workgroups read adjacent pieces of the same lines: one XCD takes a
+  // contiguous range of them
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const long long s = bid / groups;
+  const int rem = bid - (int)(s * groups);
   const int j2 = rem / per_j2;
   const int j1_0 = (rem - j2 * per_j2) * L;
   const int lines = min(L, m - j1_0);
   const long long mm = (long long)m * m;
   const double2* in = u2 + (long long)s * n * mm + (long long)j2 * m + j1_0;
-  for (int t = threadIdx.x; t < L * n; t += T) {
-    const int k3 = t / L, q = t - k3 * L;
-    const double2 v = q < lines ? in[(long long)k3 * mm + q] : make_double2(0.0, 0.0);
-    sre[q * n + k3] = v.x;
-    sim[q * n + k3] = v.y;
+  // loads in groups of kU issued before their stores
+  constexpr int kU = 8;
+  for (int t0 = threadIdx.x; t0 < L * n; t0 += kU * T) {
+    double2 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * T;
+      const int k3 = t / L, q = t - k3 * L;
+      v[u] = t < L * n && q < lines ? in[(long long)k3 * mm + q] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * T;
+      const int k3 = t / L, q = t - k3 * L;
+      if (t < L * n) {
+        sre[q * n + k3] = v[u].x;
+        sim[q * n + k3] = v[u].y;
+      }
+    }
   }
   __syncthreads();
   if constexpr (C == 0) {

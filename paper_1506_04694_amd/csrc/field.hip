@@ -311,10 +311,23 @@ k_ce_pass_b(int kind, int n_nodes, int n_layers, CePair pr, int m,
   const int j2_0 = (blockIdx.x - s * groups) * L;
   const int lines = min(L, m - j2_0);
   const double2* in = uT + ((long long)s * m + j2_0) * n;
-  for (int q = threadIdx.x; q < L * n; q += T) {
-    const double2 v = q < lines * n ? in[q] : make_double2(0.0, 0.0);
-    sre[q] = v.x;
-    sim[q] = v.y;
+  // loads in groups of kU issued before their stores
+  constexpr int kU = 8;
+  for (int q0 = threadIdx.x; q0 < L * n; q0 += kU * T) {
+    double2 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = q0 + u * T;
+      v[u] = q < lines * n ? in[q] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = q0 + u * T;
+      if (q < L * n) {
+        sre[q] = v[u].x;
+        sim[q] = v[u].y;
+      }
+    }
   }
   __syncthreads();
   if constexpr (C == 0) fft_line(sre, sim, tw, pl);
