@@ -962,11 +962,9 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
     CHECK_LAUNCH();
     for (int it = 1;; ++it) {
-      // the FP64 hierarchy's colour-split copy of the finest faces serves the
-      // operator too
-      if (split(0) && !f32)
-        launch_spmv3_dot(st, m, batch, (const double*)Th[0], tb, pv, q, partial, bps, S.active, 2);
-      else launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active, split(0) ? 1 : 0);
+      // the natural faces with the cells in natural order: the colour-split
+      // copy, read in colour-split order, fetched every face line twice
+      launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active, split(0));
       launch_sc_alpha(st, batch, partial, bps, S, status);
       // flexible form with a reduced-precision cycle: also r_new . z_old
       launch_axpy_dot(st, (int)n, batch, p, r, pv, q, S.alpha, partial, bps, S.active,

@@ -992,10 +992,11 @@ void launch_dense_factor3(hipStream_t st, int m, int batch, const double* T, con
 
 // ------------------------------------------------------------------ PCG stencil kernels
 // Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c of
-// the sample: in natural order with natural faces (CS = 0: p, q natural; CS = 1:
-// p, q in colour-split order), or in colour-split order with the faces T in
-// that order too (CS = 2).
-template <int CS>
+// the sample in natural order, with the faces in natural order; p and q in
+// colour-split order when CS is set (each wave then reads and writes two
+// half-wave runs, one per colour, and every face line is used by both colours
+// at once).
+template <bool CS>
 __global__ void __launch_bounds__(kBlock)
 k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
             const double* __restrict__ p, double* __restrict__ q, double* __restrict__ partial,
@@ -1016,17 +1017,10 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
     const long long cell = (long long)blk * kCellsPerBlock + threadIdx.x + c * kBlock;
     if (cell < n) {
       int i, j, l;
-      // entry e of p and q: with natural faces (CS < 2) the threads take the
-      // cells in natural order, so that the face loads stay contiguous
-      long long e = cell;
-      if (CS == 2) {
-        cs3_cell(m, cell, i, j, l);
-      } else {
-        cell_of(cell, m, i, j, l);
-        if (CS) e = cs3_index(m, i, j, l);
-      }
-      const Faces3 f = CS == 2 ? load_faces3_cs(Ts, tbs, m, i, j, l, e, cs3_neighbours(m, i, j, l))
-                               : load_faces3(Ts, tbs, m, i, j, l);
+      // entry e of p and q
+      cell_of(cell, m, i, j, l);
+      const long long e = CS ? cs3_index(m, i, j, l) : cell;
+      const Faces3 f = load_faces3(Ts, tbs, m, i, j, l);
       const double v =
           diag3(f) * ps[e] - (CS ? nsum3_cs(ps, m, i, j, l, f) : nsum3(ps, m, i, j, l, f));
       q[s * n + e] = v;
@@ -1039,16 +1033,13 @@ k_spmv3_dot(int m, const double* __restrict__ T, const double* __restrict__ tb,
 
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                       const double* p, double* q, double* partial, int bps,
-                      const int32_t* active, int split) {
-  if (split == 2)
-    hipLaunchKernelGGL(k_spmv3_dot<2>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
-                       partial, bps, active);
-  else if (split == 1)
-    hipLaunchKernelGGL(k_spmv3_dot<1>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
+                      const int32_t* active, bool split) {
+  if (split)
+    hipLaunchKernelGGL(k_spmv3_dot<true>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
                        partial, bps, active);
   else
-    hipLaunchKernelGGL(k_spmv3_dot<0>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p, q,
-                       partial, bps, active);
+    hipLaunchKernelGGL(k_spmv3_dot<false>, dim3(batch * bps), dim3(kBlock), 0, st, m, T, tb, p,
+                       q, partial, bps, active);
 }
 
 // Ts (colour-split order, type S) = T (natural order, FP64), the three face

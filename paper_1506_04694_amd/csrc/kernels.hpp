@@ -229,11 +229,11 @@ void launch_coarse3_cycle(hipStream_t st, bool f32, bool top, int batch, int nle
                           const CoarseDesc& desc, const void* img, const void* r0, void* z0,
                           const double* Ainv, double omega, unsigned wmask,
                           const int32_t* active);
-// q = A p and partial sums of p . q; p, q in colour-split order when split > 0,
-// and T too when split == 2.
+// q = A p and partial sums of p . q (T natural); p, q in colour-split order
+// when split.
 void launch_spmv3_dot(hipStream_t st, int m, int batch, const double* T, const double* tb,
                       const double* p, double* q, double* partial, int bps, const int32_t* active,
-                      int split);
+                      bool split);
 // Ts (colour-split order; float when f32, else double) = T (natural, FP64).
 void launch_faces_split3(hipStream_t st, bool f32, int m, int batch, const double* T, void* Ts);
 // k_pcg_init with r in colour-split order (b natural).
