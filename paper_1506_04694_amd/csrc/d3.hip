@@ -194,7 +194,7 @@ __device__ __forceinline__ long long split_cell(long long g, long long per, cons
 __global__ void k_assemble3(int problem, int m, long long total, const double* __restrict__ k,
                             double* __restrict__ T, double* __restrict__ tb,
                             double* __restrict__ b) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const long long n = (long long)m * m * m;
   const int mm = m * m;
@@ -291,7 +291,7 @@ void launch_qoi3(hipStream_t st, int m, int batch, const double* k, const double
 __global__ void k_coarsen3(int m, long long total, const double* __restrict__ T,
                            const double* __restrict__ tb, double* __restrict__ Tc,
                            double* __restrict__ tbc) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int mc = m / 2;
   const long long nc = (long long)mc * mc * mc, n = (long long)m * m * m;

@@ -25,7 +25,8 @@ namespace mlmc {
 __global__ void k_assemble(int problem, int m, long long total, const double* __restrict__ k,
                            double* __restrict__ T, double* __restrict__ tb,
                            double* __restrict__ b) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // neighbouring rows (which read each other's k) on one XCD
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const long long n = (long long)m * m;
   const long long s = g / n;

@@ -64,7 +64,7 @@ __device__ __forceinline__ double apply_at(const double* __restrict__ x, int m, 
 __global__ void k_coarsen(int m, long long total, const double* __restrict__ T,
                           const double* __restrict__ tb, double* __restrict__ Tc,
                           double* __restrict__ tbc) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int mc = m / 2;
   const long long nc = (long long)mc * mc, n = (long long)m * m;
@@ -259,6 +259,8 @@ void launch_dense_apply(hipStream_t st, int m, int batch, const double* Ainv, co
 
 // ------------------------------------------------------------------ PCG vector kernels
 // Block b of sample s (blockIdx.x = s * bps + b) owns cells b*1024 + t + 256 c.
+// (Taken XCD by XCD instead, as the stencil kernels' blocks are, these mostly
+// streaming kernels made the bench step 1% slower.)
 #define PCG_PROLOGUE                                        \
   const int bps_ = bps;                                     \
   const int lbid = blockIdx.x;                              \
@@ -336,7 +338,7 @@ void launch_pcg_init_guess(hipStream_t st, int m, int batch, const double* T, co
 // fine cell takes the value of the coarse cell that contains it.
 __global__ void k_inject(int m, long long total, int ncomp, const double* __restrict__ xc,
                          double* __restrict__ x) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const long long n = (long long)m * m;
   const long long s = g / n;
