@@ -413,21 +413,34 @@ __global__ void k_prolong_black3(int m, long long total, const S* __restrict__ T
   V* zs = z + s * n;
   const S* zcs = zc + s * (long long)mc * mc * mc;
   const V w = (V)omega;
-  // the red neighbour at offset d of the red row entry, prolonged from the
-  // coarse cell holding fine cell (ii, jj, ll)
-  const V* zo = zs + nb.other;
-  auto pz = [&](int d, int ii, int jj, int ll) -> S {
-    const int I = ii >> 1, J = jj >> 1, L = ll >> 1;
-    const long long ci = csc ? cs3_index(mc, I, J, L) : ((long long)L * mc + J) * mc + I;
-    return (S)(zo[d] + w * (V)zcs[ci]);
+  // The six red neighbours lie in four coarse cells: the cell's own parent
+  // (I, J, L) and, along each axis, the parent one step towards the
+  // neighbour across the parent's face (I + dx with dx = +1 for odd i, -1 for
+  // even i; likewise in x2 and x3).  That parent exists exactly when that
+  // neighbour does.  Coarse indices in 32 bits (mc^3 < 2^31).
+  const int I = i >> 1, J = j >> 1, L = l >> 1;
+  const int dx = (i & 1) ? 1 : -1, dy = (j & 1) ? 1 : -1, dz = (l & 1) ? 1 : -1;
+  const int hc = mc / 2, nch = mc * mc * hc;
+  auto cidx = [&](int a, int b, int c) -> int {
+    return csc ? ((a + b + c) & 1) * nch + (c * mc + b) * hc + (a >> 1) : (c * mc + b) * mc + a;
   };
+  const S c0 = zcs[cidx(I, J, L)];
+  const bool hx = (unsigned)(I + dx) < (unsigned)mc, hy = (unsigned)(J + dy) < (unsigned)mc,
+             hz = (unsigned)(L + dz) < (unsigned)mc;
+  const S cx = hx ? zcs[cidx(I + dx, J, L)] : S(0);
+  const S cy = hy ? zcs[cidx(I, J + dy, L)] : S(0);
+  const S cz = hz ? zcs[cidx(I, J, L + dz)] : S(0);
+  // the red neighbour at offset d of the red row entry, prolonged from the
+  // coarse value zcv of the cell holding it
+  const V* zo = zs + nb.other;
+  auto pz = [&](int d, S zcv) -> S { return (S)(zo[d] + w * (V)zcv); };
   S o = S(0);
-  if (i < m - 1) o += f.te * pz(nb.de, i + 1, j, l);
-  if (i > 0) o += f.tw * pz(nb.dw, i - 1, j, l);
-  if (j < m - 1) o += f.tn * pz(nb.dn, i, j + 1, l);
-  if (j > 0) o += f.ts * pz(nb.ds, i, j - 1, l);
-  if (l < m - 1) o += f.tu * pz(nb.du, i, j, l + 1);
-  if (l > 0) o += f.td * pz(nb.dd, i, j, l - 1);
+  if (i < m - 1) o += f.te * pz(nb.de, (i & 1) ? cx : c0);
+  if (i > 0) o += f.tw * pz(nb.dw, (i & 1) ? c0 : cx);
+  if (j < m - 1) o += f.tn * pz(nb.dn, (j & 1) ? cy : c0);
+  if (j > 0) o += f.ts * pz(nb.ds, (j & 1) ? c0 : cy);
+  if (l < m - 1) o += f.tu * pz(nb.du, (l & 1) ? cz : c0);
+  if (l > 0) o += f.td * pz(nb.dd, (l & 1) ? c0 : cz);
   const S rv = (S)r[s * n + e];
   zs[e] = (V)((rv + o) / diag3(f));
 }
