@@ -798,6 +798,28 @@ def main():
                     "label": label, "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
                     "launches": pb["launches"], "avg_launch_ms": pb["total_ms"] / pb["launches"],
                     "algorithmic_bytes_per_launch": pb["algorithmic_bytes"] / pb["launches"]}
+    # the other finest-grid kernels of a PCG iteration (down, up, CG direction,
+    # axpy), one more step each, timed and credited like the dominant kernel
+    others = None
+    if args.kernel == DOMINANT:
+        others = {}
+        for label in ("k_mg_down@0", "k_mg_up@0", "k_cg_direction_t", "k_axpy_dot"):
+            for c in lctx:
+                lib.mlmc_profile_enable(c, label)
+            step(args.warmup + args.steps + 2, False)
+            torch.cuda.synchronize()
+            pb = {"launches": 0, "total_ms": 0.0, "algorithmic_bytes": 0.0}
+            for c in lctx:
+                pr = lib.mlmc_profile_read(c)
+                for key in pb:
+                    pb[key] += pr[key]
+                lib.mlmc_profile_enable(c, None)
+            if pb["launches"] and pb["total_ms"] > 0:
+                ach = pb["algorithmic_bytes"] / (pb["total_ms"] * 1e-3) / 1e9
+                others[label] = {
+                    "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "launches": pb["launches"], "avg_launch_ms": pb["total_ms"] / pb["launches"],
+                    "algorithmic_bytes_per_launch": pb["algorithmic_bytes"] / pb["launches"]}
     est = lib.mlmc_estimate(sums)
     single = per_sample_baseline() if not args.no_per_sample else None
     variants = None if args.no_variants else path_variants(lib, torch, wl, ctx, opts, args)
@@ -852,6 +874,8 @@ def main():
                 "algorithmic_bytes_per_launch": prof["algorithmic_bytes"] / prof["launches"]}
         if by_size:
             roof["by_launch_cells"] = by_size
+        if others:
+            roof["other_kernels"] = others
         if prof_all and prof_all["launches"] > 0:
             ach = prof_all["algorithmic_bytes"] / (prof_all["total_ms"] * 1e-3) / 1e9
             roof["all_levels"] = {
