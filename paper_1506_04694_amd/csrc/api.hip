@@ -66,6 +66,10 @@ struct mlmc_ctx {
   std::string prof_name;
   double prof_scale = 1.0;  // share of the batch a launch works on (restart passes)
   int prof_iter = 0;        // PCG iteration of the launches being enqueued (0: n/a)
+  // a solve ends with the true residual ||b - A x|| / ||b|| in relres; level
+  // runs, which keep no residuals, turn it off (relres then holds the CG's
+  // recursive residual at its last check)
+  bool true_residual = true;
   std::vector<ProfEvent> prof;
   std::vector<hipEvent_t> event_pool;
   uint64_t ws_gen = 0;             // bumped whenever a workspace is (re)allocated
@@ -1004,8 +1008,10 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     launch_from_split3(st, m, batch, p, z);
     HIP_TRY(hipMemcpyAsync(p, z, (size_t)batch * n * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  launch_true_residual3(st, m, batch, T, tb, b, p, partial, bps);
-  launch_sc_final(st, batch, partial, bps, S, relres);
+  if (ctx->true_residual) {
+    launch_true_residual3(st, m, batch, T, tb, b, p, partial, bps);
+    launch_sc_final(st, batch, partial, bps, S, relres);
+  }
   CHECK_LAUNCH();
   return MLMC_OK;
 }
@@ -1474,8 +1480,10 @@ mlmc_status mlmc_solve(mlmc_ctx* ctx, int dim, int m, int batch, const double* T
       launch_iters_add(st, batch, iters, carried);
     }
   }
-  launch_true_residual(st, m, batch, T, tb, b, p, partial, bps);
-  launch_sc_final(st, batch, partial, bps, S, relres);
+  if (ctx->true_residual) {
+    launch_true_residual(st, m, batch, T, tb, b, p, partial, bps);
+    launch_sc_final(st, batch, partial, bps, S, relres);
+  }
   CHECK_LAUNCH();
   return MLMC_OK;
 }
@@ -1504,6 +1512,15 @@ mlmc_status mlmc_solve_noalloc(mlmc_ctx* ctx, int dim, int m, int batch, const d
   return rc;
 }
 
+// Turns a context's end-of-solve true residual off for its lifetime (level
+// runs keep no residuals) and restores the setting on every return path.
+struct NoTrueResidual {
+  mlmc_ctx* c;
+  bool old;
+  explicit NoTrueResidual(mlmc_ctx* cc) : c(cc), old(cc->true_residual) { c->true_residual = false; }
+  ~NoTrueResidual() { c->true_residual = old; }
+};
+
 static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int level, int m_fine,
                                   uint64_t first_sample, const uint32_t* ids, int n, int cgv,
                                   const mlmc_solver_opts* opts, mlmc_level_sums* sums, double* q_f,
@@ -1517,6 +1534,7 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
   if (level > 0 && (m_fine % 2)) return fail(ctx, MLMC_EINVAL, "level >= 1 needs an even m_fine");
   if (n == 0) return MLMC_OK;
   (void)hipSetDevice(ctx->device);
+  const NoTrueResidual no_true_residual(ctx);
   hipStream_t st = ctx->stream;
   const int m = m_fine, mc = m / 2, d = model->dim;
   const long long nf = d == 3 ? (long long)m * m * m : (long long)m * m;
@@ -1576,6 +1594,7 @@ static mlmc_status level_run_impl(mlmc_ctx* ctx, const mlmc_model* model, int le
     TRY(ws(ctx, "lr_itc", nb, &itc));
     TRY(ws(ctx, "lr_relres_c", nb, &relres_c));
     auto companions = [=, &zero_guess](mlmc_ctx* cc) -> mlmc_status {
+      const NoTrueResidual no_true_residual_c(cc);
       TRY(mlmc_assemble_problem(cc, model->problem, d, mc, nb, kc, Tc, tbc, bc));
       TRY(mlmc_solve(cc, d, mc, nb, Tc, tbc, bc, pc, &zero_guess, stc, itc, relres_c));
       TRY(model_qoi(cc, model, d, mc, nb, kc, pc, qcomp));
