@@ -1,8 +1,9 @@
 """Degenerate calls through the C ABI on the GPU: empty batches leave their
 outputs untouched and return MLMC_OK on every entry point (2-D and 3-D), a
 level run of no samples adds nothing to the sums, all-levels runs accept
-levels without samples, and a server started and stopped without requests
-shuts down cleanly."""
+levels without samples, a server started and stopped without requests
+shuts down cleanly, and a solve after a level run (which skips the true
+residual) still reports it."""
 import numpy as np
 import pytest
 
@@ -72,3 +73,37 @@ def test_server_without_requests(lib):
     res, _ = lib.mlmc_serve_poll(srv)
     assert res == []
     lib.mlmc_serve_stop(srv)
+
+
+@pytest.mark.parametrize("d,m", [(2, 32), (2, 128), (3, 16)])
+def test_solve_reports_true_residual_after_level_run(lib, ctx, d, m):
+    """Level runs skip the end-of-solve true residual (their samples' status
+    comes from the recursive residual); a solve on the same context afterwards
+    still reports ||b - A x|| / ||b||, recomputed here with the oracle's matrix."""
+    from oracle import fv as ofv
+    print("true residual after a level run: d=%d m=%d" % (d, m), flush=True)
+    model = W.CE2 if d == 2 else W.TILTED3
+    lib.mlmc_level_run(ctx, model, 1, m, 0, 4, False, lib.mlmc_solver_opts_default())
+    rng = np.random.default_rng(50 + m)
+    batch = 2
+    kh = np.exp(rng.standard_normal((batch,) + (m,) * d))
+    k = torch.from_numpy(kh).to(DEV)
+    cells = m ** d
+    T = torch.empty((batch, d * cells), dtype=torch.float64, device=DEV)
+    tb = torch.empty((batch, d * m ** (d - 1)), dtype=torch.float64, device=DEV)
+    b = torch.empty((batch, cells), dtype=torch.float64, device=DEV)
+    p = torch.empty((batch, cells), dtype=torch.float64, device=DEV)
+    st = torch.empty((batch,), dtype=torch.int32, device=DEV)
+    it = torch.empty((batch,), dtype=torch.int32, device=DEV)
+    rr = torch.full((batch,), -1.0, dtype=torch.float64, device=DEV)
+    opts = lib.mlmc_solver_opts_default(tol=1e-6)   # loose: the true residual is well above 0
+    lib.mlmc_assemble(ctx, d, m, batch, k, T, tb, b)
+    lib.mlmc_solve(ctx, d, m, batch, T, tb, b, p, opts, st, it, rr)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    x = p.cpu().numpy()
+    for s in range(batch):
+        A, bb = ofv.assemble(kh[s])
+        want = np.linalg.norm(bb - A @ x[s].ravel()) / np.linalg.norm(bb)
+        got = rr[s].item()
+        assert want < 1e-6 and abs(got - want) <= 1e-6 * want + 1e-15, (s, got, want)
