@@ -966,8 +966,9 @@ static mlmc_status solve3_impl(mlmc_ctx* ctx, int m, int batch, const double* T,
     launch_pupdate(st, (int)n, batch, pv, z, S.beta, bps, S.active, 1);
     CHECK_LAUNCH();
     for (int it = 1;; ++it) {
-      // the natural faces with the cells in natural order: the colour-split
-      // copy, read in colour-split order, fetched every face line twice
+      // the operator reads the caller's faces with its cells taken in natural
+      // order (the colour-split face copy, read in colour-split order, fetched
+      // every face line twice)
       launch_spmv3_dot(st, m, batch, T, tb, pv, q, partial, bps, S.active, split(0));
       launch_sc_alpha(st, batch, partial, bps, S, status);
       // flexible form with a reduced-precision cycle: also r_new . z_old
